@@ -1,0 +1,99 @@
+/*
+ * CPU oracle for the object-centric census template-matching path.
+ *
+ * TEST INFRASTRUCTURE ONLY. Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library. It shares no source with
+ * the HIP library: its own types, its own loops, no common headers.
+ *
+ * Every function follows the paper's statement of the method step by step
+ * (Sec. 4.3 "Census-Based Template Matching" and Alg. 2), with the readings of
+ * silent points stated next to the code that takes them.
+ */
+#ifndef OCSR_ORACLE_H
+#define OCSR_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { ORC_MODE_TILED = 0, ORC_MODE_GRID = 1 };
+enum { ORC_AGG_SEGMENT_MEDIAN = 0, ORC_AGG_TRIMMED_MEDIAN = 1 };
+enum {
+  ORC_OK = 0, ORC_NOT_RANGED = 1, ORC_CLIPPED_EMPTY = 2, ORC_NO_ELIGIBLE_BLOCKS = 3,
+  ORC_NO_VALID_BLOCKS = 4, ORC_TOO_FEW_CONSISTENT = 5, ORC_NONPOSITIVE_DISPARITY = 6,
+  ORC_CAPACITY_OVERFLOW = 7
+};
+
+typedef struct { int32_t mode, bw, bh, n_side, dmin, dmax; } orc_path;
+
+typedef struct {
+  int32_t sx, sy;            /* census half-window of both levels */
+  int32_t close_scale;       /* s of the close level; the far level is s = 1 */
+  int32_t tau_s;             /* FAR iff max clipped side < tau_s (px) */
+  orc_path far_path, close_path;
+  int32_t lr_tol;            /* accept |d_b - d_f| <= lr_tol (level px) */
+  int32_t min_point_pct;     /* block eligible iff 100*points >= pct*nx*ny */
+  int32_t agg_mode;
+  float   tau_d;
+  int32_t n_min, trim_pct;
+  float   focal_px, baseline_m, d_eps;
+  int32_t max_blocks_per_box; /* boxes tiling into more blocks: CAPACITY_OVERFLOW */
+  int32_t cap_blocks;         /* total block capacity (prefix rule), <= 0: unlimited */
+} orc_params;
+
+typedef struct {
+  float   disparity, depth;
+  int32_t valid, reason, n_blocks, n_eligible, n_valid, n_used;
+} orc_box_result;
+
+typedef struct {
+  int32_t box, level_scale, u, v;
+  int32_t px0, py0, nx, ny;        /* level position of point 0 and point grid size */
+  uint64_t mask;
+  int32_t eligible, d_f, d_b, lr_ok;
+  float   d_sub;                   /* level px */
+  int32_t valid;
+  int32_t dlo, nd;                 /* level search range [dlo, dlo + nd) */
+} orc_block;
+
+/* Census of one level: out is [H/s][W/s] row-major, pitch W/s. Returns 0, or -1
+ * when the window does not fit in 64 bits or an argument is out of range. */
+int32_t orc_census(const uint8_t* img, int32_t W, int32_t H, int32_t pitch,
+                   int32_t sx, int32_t sy, int32_t s, int32_t sentinel, uint64_t* out);
+
+/* Per-box disparity and depth. L0/R0: level s = 1 descriptors [H][W];
+ * L1/R1: level s = close_scale descriptors [H/s][W/s] (may be NULL when no box
+ * is CLOSE). boxes: int32 [n][5] = x0, y0, x1, y1 (half-open, px), flags
+ * (bit 0: produce a range). Debug arrays may be NULL; when given, blocks[] has
+ * room for cap_dbg blocks and cost_f/cost_b for cap_dbg * cap_nd entries.
+ * Returns the total number of blocks tiled (>= 0) or -1 on bad arguments. */
+int32_t orc_match_boxes(const uint64_t* L0, const uint64_t* R0,
+                        const uint64_t* L1, const uint64_t* R1,
+                        int32_t W, int32_t H, const int32_t* boxes, int32_t n,
+                        const orc_params* p, orc_box_result* out,
+                        orc_block* blocks, uint16_t* cost_f, uint16_t* cost_b,
+                        int32_t cap_dbg, int32_t cap_nd, int32_t n_threads);
+
+/* Aggregation of one box and its depth. vals (n_valid values, sorted in place)
+ * are the full-res disparities of its valid blocks; n_blocks the blocks it was
+ * tiled into; r->n_eligible must be set by the caller. */
+void orc_aggregate(float* vals, int32_t n_valid, int32_t n_blocks, const orc_params* p,
+                   orc_box_result* r);
+
+/* Dense counterpart: per-pixel WTA over [dmin, dmax] of the (2r+1)^2 box sum
+ * of Hamming costs (clipped window), with a left/right check. disp: int16 [H][W],
+ * -1 where invalid. disp_r (nullable): right-view WTA. */
+int32_t orc_dense(const uint64_t* CL, const uint64_t* CR, int32_t W, int32_t H,
+                  int32_t dmin, int32_t dmax, int32_t radius, int32_t lr_tol,
+                  int16_t* disp, int16_t* disp_r, int32_t n_threads);
+
+/* Dense counterpart at n sampled pixels (xy: int32 [n][2]); out: int16 [n]. */
+int32_t orc_dense_at(const uint64_t* CL, const uint64_t* CR, int32_t W, int32_t H,
+                     int32_t dmin, int32_t dmax, int32_t radius, int32_t lr_tol,
+                     const int32_t* xy, int32_t n, int16_t* out, int32_t n_threads);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

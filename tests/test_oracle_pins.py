@@ -1,0 +1,345 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+No GPU. Each test names the passage or closed form it pins; none re-derives the
+oracle's own formula.
+"""
+import os
+
+import numpy as np
+import pytest
+from hypothesis import given, settings, strategies as st
+
+from oracle import micro
+from paper_2604_07980_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _read_fig3():
+    lines = [l.strip() for l in open(os.path.join(GOLDEN, "fig3_census.txt"))
+             if l.strip() and not l.startswith("#")]
+    i = lines.index("patch")
+    j = lines.index("bits")
+    patch = np.array([[int(v) for v in l.split()] for l in lines[i + 1:j]], dtype=np.uint8)
+    bits = [l.split() for l in lines[j + 1:j + 6]]
+    return patch, bits
+
+
+# ------------------------------------------------------------------------------------
+# census (Sec. 4.3.1)
+# ------------------------------------------------------------------------------------
+
+def test_fig3_worked_example(orc):
+    """Fig. 3: the printed code of the 5x5 patch, read in Alg. 1 order (x outer, y inner)."""
+    patch, bits = _read_fig3()
+    # every printed bit is the paper's comparison neighbour > centre
+    for r in range(5):
+        for c in range(5):
+            if (r, c) != (2, 2):
+                assert int(bits[r][c]) == int(patch[r, c] > patch[2, 2])
+    want = 1  # sentinel
+    for c in range(5):          # i = x offset (outer)
+        for r in range(5):      # j = y offset (inner)
+            want = (want << 1) | (0 if bits[r][c] == "." else int(bits[r][c]))
+    assert want == 0x2DF0F36
+    code = orc.census(patch, sx=2, sy=2, s=1, sentinel=1)
+    assert int(code[2, 2]) == want
+    assert bin(int(code[2, 2])).count("1") == 1 + 15   # 15 neighbours brighter than 55
+    code0 = orc.census(patch, sx=2, sy=2, s=1, sentinel=0)
+    assert int(code0[2, 2]) == want - (1 << 25)
+    # every other pixel's window leaves the patch: undefined
+    mask = np.ones((5, 5), bool)
+    mask[2, 2] = False
+    assert not code[mask].any()
+
+
+@pytest.mark.parametrize("i,j", [(-3, -4), (-3, 4), (0, 1), (2, -1), (3, 4), (1, 0)])
+def test_single_brighter_neighbour_bit_position(orc, i, j):
+    """Alg. 1 appends one bit per offset, x outer then y inner: exactly one bit is set,
+    at 62 - t where t = (i + 3) * 9 + (j + 4) is the offset's loop index (7x9 window)."""
+    img = np.full((20, 20), 100, np.uint8)
+    img[10 + j, 10 + i] = 101
+    code = int(orc.census(img, 3, 4, 1, 0)[10, 10])
+    t = (i + 3) * 9 + (j + 4)
+    assert code == 1 << (62 - t)
+
+
+@pytest.mark.parametrize("s", [1, 2, 3])
+def test_constant_image(orc, s):
+    """No neighbour exceeds the centre: without the sentinel every word is 0; with it the
+    defined words are exactly the sentinel bit (bit 63 for 7x9) and the border stays 0."""
+    img = np.full((50, 61), 77, np.uint8)
+    assert not orc.census(img, 3, 4, s, 0).any()
+    c = orc.census(img, 3, 4, s, 1)
+    Hs, Ws = 50 // s, 61 // s
+    inner = c[4:Hs - 4, 3:Ws - 3]
+    assert (inner == np.uint64(1 << 63)).all()
+    assert c.sum() == inner.sum()
+
+
+def test_monotone_invariance(orc):
+    """Census depends only on the order of intensities (Sec. 1.1 and 4.3.1): strictly
+    increasing maps leave it unchanged."""
+    rng = np.random.default_rng(7)
+    img = rng.integers(0, 120, size=(40, 52), dtype=np.uint8)
+    ref = orc.census(img, 3, 4, 1, 1)
+    assert (orc.census(img + 7, 3, 4, 1, 1) == ref).all()
+    assert (orc.census(img * 2, 3, 4, 1, 1) == ref).all()
+    lut = np.cumsum(rng.integers(1, 3, size=256)).clip(0, 255).astype(np.uint8)[:120]
+    assert np.all(np.diff(lut.astype(int)) > 0)
+    assert (orc.census(lut[img], 3, 4, 1, 1) == ref).all()
+
+
+def test_level_sampling(orc):
+    """Multi-resolution census by coordinate scaling: level s of I is the s = 1 census of
+    I sampled at (s x, s y)."""
+    rng = np.random.default_rng(3)
+    img = rng.integers(0, 256, size=(61, 83), dtype=np.uint8)
+    for s in (2, 3):
+        sub = np.ascontiguousarray(img[: (61 // s) * s: s, : (83 // s) * s: s])
+        assert (orc.census(img, 3, 4, s, 1) == orc.census(sub, 3, 4, 1, 1)).all()
+
+
+@pytest.mark.parametrize("shape", [(12, 16), (30, 40), (9, 7)])
+@pytest.mark.parametrize("win", [(3, 4), (2, 2), (4, 3), (1, 1), (0, 0)])
+@pytest.mark.parametrize("s", [1, 2])
+@pytest.mark.parametrize("sentinel", [0, 1])
+def test_census_vs_micro(orc, shape, win, s, sentinel):
+    rng = np.random.default_rng(hash((shape, win, s, sentinel)) % (1 << 32))
+    img = rng.integers(0, 256, size=shape, dtype=np.uint8)
+    a = orc.census(img, win[0], win[1], s, sentinel)
+    b = micro.census(img, win[0], win[1], s, sentinel)
+    assert (a == b).all()
+
+
+def test_census_window_too_wide(orc):
+    with pytest.raises(ValueError):
+        orc.census(np.zeros((20, 20), np.uint8), 4, 4, 1, 1)   # 81 bits
+
+
+# ------------------------------------------------------------------------------------
+# matching (Sec. 4.3.2 - 4.3.5)
+# ------------------------------------------------------------------------------------
+
+def _params(**kw):
+    p = synth.base_params()
+    p.update(kw)
+    return p
+
+
+def test_hamming_symmetric():
+    """popcount(a xor b) == popcount(b xor a), and the distance is a metric on words."""
+    rng = np.random.default_rng(0)
+    a, b, c = (rng.integers(0, 2**63, size=1000, dtype=np.uint64) for _ in range(3))
+    ab = np.bitwise_count(a ^ b)
+    assert (ab == np.bitwise_count(b ^ a)).all()
+    assert (np.bitwise_count(a ^ c) <= ab + np.bitwise_count(b ^ c)).all()
+
+
+def _shift_pair(k, H=120, W=200, seed=11):
+    """R(x, y) = L(x + k, y); the k exposed columns get independent noise."""
+    rng = np.random.default_rng(seed)
+    left = np.rint(synth.blurred_noise(rng, H, W)).astype(np.uint8)
+    right = np.empty_like(left)
+    right[:, :W - k] = left[:, k:]
+    right[:, W - k:] = rng.integers(0, 256, size=(H, k), dtype=np.uint8)
+    return left, right
+
+
+@pytest.mark.parametrize("k", [0, 1, 7, 19, 31])
+def test_integer_shift_far(orc, k):
+    """A pure integer shift: S_f(k) = 0, the zero is unique on the texture, so the WTA
+    disparity is exactly k and the backward search returns to k (Sec. 4.3.2-4.3.3)."""
+    left, right = _shift_pair(k)
+    p = _params(tau_s=1 << 30)
+    boxes = np.array([[60, 20, 140, 100, 1], [38, 10, 56, 40, 1]], np.int32)
+    _, (res, blk, cf, cb, n) = orc.run_scene(left, right, p, boxes, debug=True)
+    assert n > 0
+    el = blk["eligible"] == 1
+    assert el.all()
+    assert (blk["d_f"] == k).all() and (blk["d_b"] == k).all() and (blk["lr_ok"] == 1).all()
+    rows = np.arange(n)
+    kk = k - blk["dlo"]
+    assert (cf[rows, kk] == 0).all()
+    others = cf[:, :32].astype(int)
+    others[rows, kk] = 999
+    assert (others > 0).all()
+    if k == 0:
+        assert (res["reason"] == 6).all()      # zero disparity has no finite depth
+    else:
+        assert (res["valid"] == 1).all()
+        assert (np.abs(res["disparity"] - k) <= 0.5).all()
+
+
+def test_integer_shift_close(orc):
+    """At level s = 2 a full-res shift of 2k' is a level shift of k': close blocks
+    return d_f = k', and the box disparity is 2k' to within the parabola offset
+    (d_full = s d, Sec. 4.1)."""
+    kp = 13
+    left, right = _shift_pair(2 * kp, H=160, W=320)
+    p = _params(tau_s=64)
+    boxes = np.array([[120, 20, 260, 140, 1]], np.int32)
+    _, (res, blk, cf, cb, n) = orc.run_scene(left, right, p, boxes, debug=True)
+    assert (blk["level_scale"] == 2).all()
+    assert (blk["d_f"] == kp).all() and (blk["lr_ok"] == 1).all()
+    # the parabola moves each block by at most half a level pixel: one full-res pixel
+    assert res["valid"][0] == 1 and abs(res["disparity"][0] - 2 * kp) <= 1.0
+
+
+def _designed_level(costs, x0=40, y0=10, W=80, H=24):
+    """CL = 0 and CR words with chosen popcounts along row y0, so that a 1x1 block at
+    (x0, y0) has S_f(d) = costs[d]."""
+    L = np.zeros((H, W), np.uint64)
+    R = np.zeros((H, W), np.uint64)
+    for d, c in enumerate(costs):
+        R[y0, x0 - d] = np.uint64((1 << c) - 1) if c < 64 else np.uint64(2**64 - 1)
+    return L, R
+
+
+def _one_point(orc, costs, x0=40, y0=10):
+    L, R = _designed_level(costs, x0, y0)
+    H, W = L.shape
+    p = _params(tau_s=1 << 30, min_point_pct=0)
+    p["far"] = dict(mode=synth.MODE_TILED, bw=1, bh=1, n_side=1, dmin=0, dmax=len(costs) - 1)
+    boxes = np.array([[x0, y0, x0 + 1, y0 + 1, 1]], np.int32)
+    res, blk, cf, cb, n = orc.match_boxes(L, R, None, None, W, H, boxes, p, debug=True)
+    assert n == 1 and list(cf[0, :len(costs)]) == list(costs)
+    return blk[0]
+
+
+def test_subpixel_parabola_designed(orc):
+    """Sec. 4.3.2 parabola: the sub-pixel disparity is the vertex of the parabola through
+    (d_f - 1, a), (d_f, c), (d_f + 1, b); here (10, 2, 6) puts it at d_f + 1/6."""
+    costs = [40, 41, 30, 22, 10, 2, 6, 30, 35, 50]
+    b = _one_point(orc, costs)
+    assert b["d_f"] == 5
+    coef = np.polyfit([4.0, 5.0, 6.0], [10.0, 2.0, 6.0], 2)
+    vertex = -coef[1] / (2 * coef[0])
+    assert abs(vertex - (5 + 1 / 6)) < 1e-12
+    assert abs(float(b["d_sub"]) - vertex) < 1e-6
+
+
+def test_subpixel_symmetric_and_ends(orc):
+    b = _one_point(orc, [30, 20, 7, 3, 7, 25, 40])
+    assert b["d_f"] == 3 and b["d_sub"] == 3.0           # a == b: vertex at d_f
+    b = _one_point(orc, [1, 5, 9, 12, 14])
+    assert b["d_f"] == 0 and b["d_sub"] == 0.0           # range start: no parabola
+    b = _one_point(orc, [14, 12, 9, 5, 1])
+    assert b["d_f"] == 4 and b["d_sub"] == 4.0           # range end
+    b = _one_point(orc, [9, 4, 4, 9, 12])
+    assert b["d_f"] == 1                                 # tie: the smallest disparity
+
+
+@settings(max_examples=60, deadline=None)
+@given(st.lists(st.integers(0, 64), min_size=3, max_size=24))
+def test_subpixel_offset_bound(costs):
+    """With the smallest-index tie-break, an interior minimum has a > c and b >= c, so
+    the parabola offset lies in (-0.5, 0.5] (written here from the closed form)."""
+    from oracle import oracle as o
+    if not os.path.exists(o.LIB):
+        o.build()
+    b = _one_point(o, costs)
+    assert -0.5 <= float(b["d_sub"]) - b["d_f"] <= 0.5
+    assert b["d_f"] == int(np.argmin(costs))
+
+
+def test_backward_same_pairs_at_df(orc):
+    """At d' = d_f the backward search compares the same pairs as the forward winner, so
+    S_b(d_f) == S_f(d_f) (Hamming symmetry, Sec. 4.3.3)."""
+    sc = synth.scene_small(5, H=96, W=160, n_planes=4)
+    p = _params(tau_s=40)
+    p["far"].update(dmax=15, bw=4, bh=4)
+    p["close"].update(dmax=31, bw=4, bh=4)
+    _, (res, blk, cf, cb, n) = orc.run_scene(sc.left, sc.right, p, sc.boxes, debug=True)
+    el = np.nonzero(blk["eligible"])[0]
+    assert len(el) > 5
+    k = blk["d_f"][el] - blk["dlo"][el]
+    assert (cf[el, k] == cb[el, k]).all()
+
+
+def test_occluder_rule(orc):
+    """Sec. 4.3.5: points inside an overlapping box with a larger bottom y are excluded;
+    an overlapping box with a smaller bottom y excludes nothing; a box that is not
+    ranged still occludes."""
+    rng = np.random.default_rng(1)
+    img = rng.integers(0, 256, size=(80, 120), dtype=np.uint8)
+    p = _params(tau_s=1 << 30, min_point_pct=0)
+    p["far"] = dict(mode=synth.MODE_TILED, bw=8, bh=8, n_side=8, dmin=0, dmax=7)
+    target = [20, 20, 60, 60, 1]
+    lower = [40, 40, 90, 70, 0]     # bottom 70 > 60: occludes, not ranged itself
+    upper = [10, 5, 30, 30, 1]      # bottom 30 < 60: does not occlude the target
+    boxes = np.array([target, lower, upper], np.int32)
+    _, (res, blk, cf, cb, n) = orc.run_scene(img, img, p, boxes, debug=True)
+    for b in blk[blk["box"] == 0]:
+        for j in range(b["ny"]):
+            for i in range(b["nx"]):
+                x, y = b["px0"] + i, b["py0"] + j
+                hidden = 40 <= x < 90 and 40 <= y < 70
+                assert bool((int(b["mask"]) >> int(j * b["nx"] + i)) & 1) == (not hidden)
+    assert res["reason"][1] == 1                       # NOT_RANGED
+    # the upper box is occluded by the target (bottom 60 > 30) where they overlap
+    ub = blk[blk["box"] == 2]
+    assert any(int(b["mask"]) != (1 << int(b["nx"] * b["ny"])) - 1 for b in ub)
+
+
+# ------------------------------------------------------------------------------------
+# aggregation and depth (Sec. 4.3.4, Eq. 1)
+# ------------------------------------------------------------------------------------
+
+def test_segment_median_hand_lists(orc):
+    p = _params(agg_mode=synth.AGG_SEGMENT_MEDIAN, tau_d=1.0, n_min=3)
+    r = orc.aggregate([30.1, 10.0, 10.4, 30.0, 10.2], 5, p)
+    assert r["valid"] == 1 and r["disparity"] == np.float32(10.2) and r["n_used"] == 3
+    # two runs of equal length: the first (smallest) run wins
+    r = orc.aggregate([5.0, 5.5, 6.0, 20.0, 20.5, 21.0], 6, p)
+    assert r["disparity"] == np.float32(5.5)
+    # even-length run: mean of the two middle values
+    r = orc.aggregate([7.0, 7.5, 8.0, 8.5, 40.0], 5, p)
+    assert r["disparity"] == np.float32((np.float32(7.5) + np.float32(8.0)) * np.float32(0.5))
+    # a gap of exactly tau_d breaks the run ("below threshold")
+    r = orc.aggregate([1.0, 2.0, 3.0, 4.0], 4, p)
+    assert r["reason"] == 5 and r["n_used"] == 1
+    # longest run shorter than N_min
+    r = orc.aggregate([1.0, 1.5, 9.0, 9.2, 30.0], 5, p)
+    assert r["valid"] == 0 and r["reason"] == 5
+    # no valid blocks
+    r = orc.aggregate([], 5, p, n_eligible=3)
+    assert r["reason"] == 4
+    r = orc.aggregate([], 5, p, n_eligible=0)
+    assert r["reason"] == 3
+    # a single-block object takes its block value directly
+    r = orc.aggregate([2.75], 1, p)
+    assert r["valid"] == 1 and r["disparity"] == np.float32(2.75)
+
+
+@settings(max_examples=80, deadline=None)
+@given(st.lists(st.floats(0.5, 300.0, width=32), min_size=3, max_size=60),
+       st.integers(0, 45))
+def test_trimmed_median_is_median(vals, pct):
+    """A symmetric trim keeps the middle order statistics, so the trimmed median equals
+    the plain median of all valid values."""
+    from oracle import oracle as o
+    if not os.path.exists(o.LIB):
+        o.build()
+    p = _params(agg_mode=synth.AGG_TRIMMED_MEDIAN, trim_pct=pct, n_min=1)
+    r = o.aggregate(vals, len(vals) + 1, p)
+    v = np.sort(np.asarray(vals, np.float32))
+    m = len(v)
+    med = v[(m - 1) // 2] if m % 2 else np.float32((v[m // 2 - 1] + v[m // 2]) * np.float32(0.5))
+    assert r["valid"] == 1 and r["disparity"] == med
+
+
+def test_depth_paper_examples(orc):
+    """Eq. 1 on the paper's long-range examples: (f, b, d) = (2000 px, 0.30 m, 3.0 px) is
+    200 m exactly in fp32; (2000, 0.12, 1.2) is 200 m to fp32 rounding."""
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "depth_examples.txt"))
+            if l.strip() and not l.startswith("#")]
+    for f, b, d, z in rows:
+        p = _params(focal_px=float(f), baseline_m=float(b))
+        r = orc.aggregate([float(d)], 1, p)
+        assert r["valid"] == 1
+        assert abs(float(r["depth"]) - float(z)) <= 1e-6 * float(z)
+    r = orc.aggregate([3.0], 1, _params())
+    assert r["depth"] == np.float32(200.0)
+    r = orc.aggregate([0.0], 1, _params())
+    assert r["valid"] == 0 and r["reason"] == 6
