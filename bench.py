@@ -1,0 +1,172 @@
+#!/usr/bin/env python3
+"""Benchmark of the object-centric census template-matching path on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+
+Workload (one step = the whole path over one frame): the realistic 1920x1080 frame --
+census of both views at both levels, then per-box planning, forward/backward Hamming
+block search with WTA and parabola, L/R check, aggregation and depth, for 32 ranged
+boxes (19 far, 13 close) plus 32 occluder boxes. Inputs are resident in HBM before
+the timed region starts.
+
+Prints one JSON line: Gcost/s (one cost = one 64-bit Hamming term, forward or
+backward) over the timed steps, per-frame p50/p99 latency, the dominant kernel's
+roofline, and the CPU oracle's rate on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+METRIC = "box-block disparity evals/sec (Gcost/s) + per-frame p50/p99 latency, 1 MI355X"
+INT_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12      # int32 VALU lane-ops/s: CUs x lanes x clock
+HBM_PEAK_GBS = 8000.0
+CENSUS_OPS_PER_BIT = 2                        # compare + shift-in of one comparison bit
+MATCH_OPS_PER_COST = 4                        # 2 x v_xor_b32 + 2 x v_bcnt_u32_b32
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--warmup", type=int, default=30)
+    ap.add_argument("--latency-steps", type=int, default=1000)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def cpu_baseline(sc, params, costs_per_frame, seconds):
+    """The oracle as it stands, on the host cores, repeated on the same frame."""
+    from oracle import oracle as orc
+    if not os.path.exists(orc.LIB):
+        orc.build()
+    cores = len(os.sched_getaffinity(0))
+    reps = 0
+    t0 = time.perf_counter()
+    while True:
+        orc.run_scene(sc.left, sc.right, params, sc.boxes, threads=cores)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= seconds:
+            break
+    return {"value": costs_per_frame * reps / el / 1e9, "unit": "Gcost/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"{reps} repetitions of the realistic 1920x1080 frame (census of both views "
+                      f"at both levels + matching of 64 boxes), {el:.1f} s, OpenMP over rows/boxes",
+            "ms_per_frame": 1e3 * el / reps}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the path is per frame "
+              "and shards by frames, see DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2604_07980_amd import ocsr, synth
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    sc = synth.scene_realistic()
+    p = synth.params_for(2)
+    H, W = sc.left.shape
+    L = torch.from_numpy(sc.left).to(dev)
+    R = torch.from_numpy(sc.right).to(dev)
+    boxes = torch.from_numpy(sc.boxes).to(dev)
+    n = boxes.shape[0]
+    ws = ocsr.Workspace()
+    out = torch.empty((n, 8), dtype=torch.int32, device=dev)
+
+    # work of one frame, from the library's own block records (outside the timed region)
+    g = ocsr.census_many([L, R, L, R], [1, 1, p["close_scale"], p["close_scale"]])
+    _, extra = ocsr.match_boxes(*g, boxes, p, debug=True, cap_blocks=1 << 16)
+    nb, rec, _, _ = ocsr.debug_to_numpy(extra)
+    el = rec["eligible"] == 1
+    pts = np.array([bin(int(m)).count("1") for m in rec["mask"]])
+    costs = int((pts * rec["nd"] * el).sum()) * 2
+    evals = int((rec["nd"] * el).sum()) * 2
+    census_px = 2 * (W * H) + 2 * (W // 2) * (H // 2)
+    census_bits = (2 * p["sx"] + 1) * (2 * p["sy"] + 1)
+    del g, extra
+
+    def step():
+        ocsr.range_frame(L, R, boxes, p, workspace=ws, out=out)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    # timed region: K back-to-back frames, library kernel timing on
+    ocsr.reset_timing()
+    ocsr.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ocsr.set_timing(False)
+    ms_per_step = 1e3 * (t1 - t0) / args.steps
+    kern = {}
+    for name in ("census", "plan", "match", "aggregate"):
+        cnt, tot = ocsr.kernel_time(name)
+        kern[name] = {"launches": cnt, "avg_us": 1e3 * tot / max(cnt, 1)}
+
+    # per-frame latency: enqueue to result on the host, one frame at a time
+    lat = []
+    for _ in range(args.latency_steps):
+        a = time.perf_counter()
+        step()
+        torch.cuda.synchronize()
+        lat.append(1e3 * (time.perf_counter() - a))
+    lat = np.array(lat)
+
+    census_ops = census_px * census_bits * CENSUS_OPS_PER_BIT
+    match_ops = costs * MATCH_OPS_PER_COST
+    kern["census"]["tops"] = census_ops / (kern["census"]["avg_us"] * 1e-6) / 1e12
+    kern["match"]["tops"] = match_ops / (kern["match"]["avg_us"] * 1e-6) / 1e12
+    dom = max(("census", "match"), key=lambda k: kern[k]["avg_us"])
+    ach = kern[dom]["tops"]
+    roofline = {"kernel": dom, "bound": "alu", "achieved": round(ach, 3), "peak": round(INT_PEAK_TOPS, 2),
+                "unit": "TOP/s", "frac": round(ach / INT_PEAK_TOPS, 4), "traffic": None,
+                "ops_per_launch": census_ops if dom == "census" else match_ops}
+
+    res = {
+        "metric": METRIC,
+        "value": round(costs / (ms_per_step * 1e-3) / 1e9, 3),
+        "unit": "Gcost/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": "realistic_1080p: one 1920x1080 uint8 stereo pair, 32 ranged boxes "
+                               "(19 far 4x4 blocks d 0..31 at s=1, 13 close 8x8 blocks d 0..191 at "
+                               "s=2) + 32 occluder boxes, census 7x9, trimmed median",
+                   "costs_per_frame": costs, "block_evals_per_frame": evals,
+                   "blocks": int(nb), "census_level_px": census_px},
+        "block_evals_per_s": round(evals / (ms_per_step * 1e-3), 1),
+        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
+                       "p99": round(float(np.percentile(lat, 99)), 4),
+                       "frames": int(len(lat))},
+        "kernels": {k: {kk: (round(vv, 3) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+                    for k, v in kern.items()},
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(sc, p, costs, args.cpu_seconds)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,259 @@
+/*
+ * ocsr.h -- C ABI of the object-centric census stereo ranging library (gfx950).
+ *
+ * The library computes, on one MI355X GPU, the object-centric template-matching
+ * method of "Object-Centric Stereo Ranging for Autonomous Driving: From Dense
+ * Disparity to Census-Based Template Matching", Sec. 4.3:
+ *
+ *   census(image) -> 64-bit descriptors                  (Sec. 4.3.1, census eq., Alg. 1)
+ *   match_boxes(descL, descR, boxes, params) -> per box  (Sec. 4.3.2-4.3.6, Alg. 2)
+ *       far/close split, occlusion-aware block sampling, forward Hamming block
+ *       search with winner-take-all, parabola sub-pixel refinement, backward
+ *       verification, robust aggregation, depth Z = f b / d (Eq. 1).
+ *
+ * Conventions shared by every entry point:
+ *   - Pointers marked (dev) are device memory of the current HIP device, owned by
+ *     the caller; pointers marked (host) are host memory read during the call only.
+ *     The library never frees or keeps caller memory, and calls no hipMalloc on
+ *     the matching path: scratch space is the caller's workspace (ws, ws_bytes).
+ *   - Every call is asynchronous on `stream` (a hipStream_t; NULL = the default
+ *     stream). Outputs are valid once the caller synchronizes that stream.
+ *   - Disparity d >= 0 is the left-to-right shift: the right-image match of left
+ *     pixel (x, y) is (x - d, y). Images are rectified, so the vertical offset is 0.
+ *   - Return value: OCSR_OK (0) or a negative status. Arguments are validated before
+ *     anything is enqueued; on a negative status nothing was enqueued (except
+ *     OCSR_E_HIP, reported when a launch fails). ocsr_last_error() then returns a
+ *     message for the calling thread. No exception crosses the ABI; kernels never trap.
+ *   - Data-dependent outcomes (a box too small, no consistent block, ...) are not
+ *     errors: they are per-box reason codes (OCSR_REASON_*).
+ */
+#ifndef OCSR_H
+#define OCSR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define OCSR_ABI_VERSION 1
+
+/* status codes */
+#define OCSR_OK 0
+#define OCSR_E_INVALID (-1)      /* bad argument, nothing enqueued */
+#define OCSR_E_WORKSPACE (-2)    /* ws_bytes smaller than the matching *_workspace_bytes */
+#define OCSR_E_CAPACITY (-3)     /* a size beyond a documented limit */
+#define OCSR_E_HIP (-4)          /* a HIP runtime call failed */
+#define OCSR_E_UNSUPPORTED (-5)  /* e.g. a census window of more than 64 bits */
+
+/* per-box reason codes (ocsr_box_result.reason) */
+#define OCSR_REASON_OK 0
+#define OCSR_REASON_NOT_RANGED 1             /* flags bit 0 clear: the box only occludes */
+#define OCSR_REASON_CLIPPED_EMPTY 2          /* no area inside the image */
+#define OCSR_REASON_NO_ELIGIBLE_BLOCKS 3     /* no block with enough unoccluded points */
+#define OCSR_REASON_NO_VALID_BLOCKS 4        /* every block failed the L/R check */
+#define OCSR_REASON_TOO_FEW_CONSISTENT 5     /* aggregation kept fewer than n_min blocks */
+#define OCSR_REASON_NONPOSITIVE_DISPARITY 6  /* disparity <= d_eps: no finite depth */
+#define OCSR_REASON_CAPACITY_OVERFLOW 7      /* the box's blocks did not fit (see below) */
+
+#define OCSR_MODE_TILED 0   /* box cut into bw x bh blocks, every pixel a point */
+#define OCSR_MODE_GRID 1    /* whole box one block, n_side x n_side grid of points */
+
+#define OCSR_AGG_SEGMENT_MEDIAN 0  /* median of the longest run of gaps < tau_d (Sec. 4.3.4) */
+#define OCSR_AGG_TRIMMED_MEDIAN 1  /* median after a symmetric trim of trim_pct percent */
+
+#define OCSR_BOX_RANGE 1u   /* ocsr_box.flags: produce a range (else the box only occludes) */
+
+/* A box that tiles into more blocks than this is reported CAPACITY_OVERFLOW. */
+#define OCSR_MAX_BLOCKS_PER_BOX 16384
+/* Largest search range (level candidates) of one path. */
+#define OCSR_MAX_CANDIDATES 256
+
+typedef struct ocsr_ctx ocsr_ctx;
+
+/* Library ABI version (OCSR_ABI_VERSION of the build). */
+int32_t ocsr_abi_version(void);
+
+/* Message of the calling thread's last non-zero status ("" if none). The pointer
+ * stays valid until the thread's next library call. */
+const char* ocsr_last_error(void);
+
+/* Creates a context bound to HIP device `device` (it becomes current for the
+ * calling thread). The context holds launch-shape tables and timing state only.
+ * Returns OCSR_OK and *out, or a negative status. */
+int32_t ocsr_ctx_create(int32_t device, ocsr_ctx** out);
+void ocsr_ctx_destroy(ocsr_ctx* ctx);
+
+/* ------------------------------------------------------------------------------ */
+/* Census transform (Sec. 4.3.1, census equation; Alg. 1)                           */
+/* ------------------------------------------------------------------------------ */
+/* Window (2 sx + 1) wide and (2 sy + 1) tall, sx, sy >= 0. Level `scale` >= 1 samples
+ * the source at (scale x, scale y): the output has floor(W/scale) x floor(H/scale)
+ * words. Bit order is Alg. 1's: the word starts as the sentinel (1, or 0 when
+ * sentinel == 0), then for i = -sx..sx (outer), j = -sy..sy (inner) it shifts left by
+ * one and appends [I(x+i, y+j) > I(x, y)]. The centre term is included (always 0).
+ * A pixel whose window leaves the level image stores 0. Requires
+ * (2sx+1)(2sy+1) + (sentinel != 0) <= 64, else OCSR_E_UNSUPPORTED. */
+typedef struct {
+  int32_t sx, sy;
+  int32_t scale;
+  int32_t sentinel;
+} ocsr_census_params;
+
+/* img (dev): uint8 [H][pitch_bytes], W <= pitch_bytes. out (dev): uint64 rows of
+ * out_pitch_elems >= W/scale words, H/scale rows. */
+int32_t ocsr_census(ocsr_ctx* ctx, const uint8_t* img, int32_t width, int32_t height,
+                    int32_t pitch_bytes, const ocsr_census_params* params, uint64_t* out,
+                    int32_t out_pitch_elems, void* stream);
+
+/* Several census transforms in one launch (e.g. both views at both levels of a
+ * frame). jobs (host): n_jobs descriptions; every job uses params' window and
+ * sentinel and its own scale. n_jobs <= OCSR_MAX_CENSUS_JOBS. */
+#define OCSR_MAX_CENSUS_JOBS 64
+typedef struct {
+  const uint8_t* img;      /* dev, uint8 [height][pitch_bytes] */
+  uint64_t* out;           /* dev, uint64 [height/scale][out_pitch_elems] */
+  int32_t width, height, pitch_bytes, out_pitch_elems;
+  int32_t scale;
+  int32_t reserved;
+} ocsr_census_job;
+int32_t ocsr_census_many(ocsr_ctx* ctx, const ocsr_census_job* jobs, int32_t n_jobs,
+                         int32_t sx, int32_t sy, int32_t sentinel, void* stream);
+
+/* ------------------------------------------------------------------------------ */
+/* Object-centric matching (Sec. 4.3.2-4.3.6, Alg. 2)                               */
+/* ------------------------------------------------------------------------------ */
+/* Descriptors of one level: both views, same geometry. W, H are the level size
+ * (floor of the image size / scale); pitch_elems >= W. sx, sy: the census window the
+ * descriptors were made with (the matcher only uses pixels whose census is defined). */
+typedef struct {
+  const uint64_t* L;       /* dev */
+  const uint64_t* R;       /* dev */
+  int32_t width, height, pitch_elems;
+  int32_t scale;
+  int32_t sx, sy;
+} ocsr_level;
+
+/* Detection box in full-resolution pixels, half-open [x0, x1) x [y0, y1). */
+typedef struct {
+  int32_t x0, y0, x1, y1;
+  uint32_t flags;          /* OCSR_BOX_RANGE: produce a range; every box may occlude */
+} ocsr_box;
+
+/* One matching path (Sec. 4.3.4). Disparity range [dmin, dmax] in full-res px,
+ * 0 <= dmin <= dmax; a path on level s searches level disparities
+ * floor(dmin/s) .. floor(dmin/s) + ceil((dmax - dmin + 1)/s) - 1, at most
+ * OCSR_MAX_CANDIDATES of them. TILED: 1 <= bw * bh <= 64. GRID: 1 <= n_side <= 8. */
+typedef struct {
+  int32_t mode;
+  int32_t bw, bh;
+  int32_t n_side;
+  int32_t dmin, dmax;
+} ocsr_path;
+
+typedef struct {
+  uint32_t struct_size;    /* sizeof(ocsr_match_params) */
+  int32_t tau_s;           /* FAR iff max(clipped width, height) < tau_s (Sec. 4.3.4) */
+  ocsr_path far_path;      /* FAR boxes: level 0 (scale 1) */
+  ocsr_path close_path;    /* CLOSE boxes: level 1 (scale s, e.g. 2) */
+  int32_t lr_tol;          /* a block passes the L/R check iff |d_b - d_f| <= lr_tol */
+  int32_t min_point_pct;   /* block eligible iff points > 0 and 100 points >= pct nx ny */
+  int32_t agg_mode;        /* OCSR_AGG_* */
+  float tau_d;             /* segment gap threshold, full-res px */
+  int32_t n_min;           /* fewest blocks an aggregate may rest on */
+  int32_t trim_pct;        /* 0..49, TRIMMED_MEDIAN only */
+  float focal_px;          /* f */
+  float baseline_m;        /* b */
+  float d_eps;             /* disparity <= d_eps: NONPOSITIVE_DISPARITY */
+} ocsr_match_params;
+
+typedef struct {
+  float disparity;         /* full-res px (0 unless aggregation succeeded) */
+  float depth;             /* Z = f b / disparity, metres (0 unless valid) */
+  int32_t valid;           /* 1 iff reason == OCSR_REASON_OK */
+  int32_t reason;          /* OCSR_REASON_* */
+  int32_t n_blocks;        /* blocks the box was tiled into */
+  int32_t n_eligible;      /* blocks with enough unoccluded points */
+  int32_t n_valid;         /* eligible blocks that passed the L/R check */
+  int32_t n_used;          /* blocks the aggregate rests on */
+} ocsr_box_result;
+
+/* Per-block record of the debug output, blocks numbered box by box, then by block
+ * row and column (a box's blocks are contiguous). */
+typedef struct {
+  int32_t box, level_scale, u, v;
+  int32_t px0, py0, nx, ny;   /* level position of point 0; point grid nx x ny */
+  uint64_t mask;              /* bit j*nx+i: point (i, j) unoccluded */
+  int32_t eligible, d_f, d_b, lr_ok;
+  float d_sub;                /* sub-pixel forward disparity, level px */
+  int32_t valid;
+  int32_t dlo, nd;            /* level search range [dlo, dlo + nd) */
+} ocsr_block_record;
+
+/* Optional debug outputs of ocsr_match_boxes (any pointer may be NULL). Blocks
+ * numbered >= cap_blocks are not recorded; costs hold cap_nd entries per block. */
+typedef struct {
+  int32_t cap_blocks, cap_nd;
+  int32_t* n_blocks;              /* dev, 1 int: blocks numbered (incl. overflowed boxes) */
+  ocsr_block_record* blocks;      /* dev, [cap_blocks] */
+  uint16_t* cost_fwd;             /* dev, [cap_blocks][cap_nd]: S_f(dlo + k) */
+  uint16_t* cost_bwd;             /* dev, [cap_blocks][cap_nd]: S_b(dlo + k) */
+} ocsr_debug;
+
+/* Workspace of ocsr_match_boxes for up to n_boxes boxes and cap_blocks blocks in
+ * total. Blocks are numbered by a prefix over the boxes in order; a box whose
+ * range of numbers passes cap_blocks (and every box after it) is reported
+ * CAPACITY_OVERFLOW. cap_blocks <= 2^24. */
+size_t ocsr_match_workspace_bytes(int32_t n_boxes, int32_t cap_blocks);
+
+/* Matches every ranged box. lv0 (host struct, dev arrays): descriptors of level 0,
+ * scale 1, used by the FAR path. lv1: the level used by the CLOSE path (its scale
+ * is the close level's s); required -- a caller whose boxes are all FAR may pass
+ * lv0 again. boxes (dev): [n_boxes]. out (dev): [n_boxes]. ws (dev): at least
+ * ocsr_match_workspace_bytes(n_boxes, cap_blocks) bytes, 256-byte aligned; its
+ * contents on entry do not matter. dbg: NULL for no debug output. */
+int32_t ocsr_match_boxes(ocsr_ctx* ctx, const ocsr_level* lv0, const ocsr_level* lv1,
+                         const ocsr_box* boxes, int32_t n_boxes,
+                         const ocsr_match_params* params, int32_t cap_blocks,
+                         void* ws, size_t ws_bytes, ocsr_box_result* out,
+                         const ocsr_debug* dbg, void* stream);
+
+/* ------------------------------------------------------------------------------ */
+/* Whole frame: census of both views at both levels, then matching (Alg. 2)         */
+/* ------------------------------------------------------------------------------ */
+/* Census window and the close level's scale of a frame. */
+typedef struct {
+  int32_t sx, sy, sentinel;
+  int32_t close_scale;     /* >= 1 */
+} ocsr_frame_params;
+
+size_t ocsr_frame_workspace_bytes(int32_t width, int32_t height,
+                                  const ocsr_frame_params* fp, int32_t n_boxes,
+                                  int32_t cap_blocks);
+
+/* imgL, imgR (dev): uint8 [height][pitch_bytes]. The four descriptor images live in
+ * the workspace. Same outputs as ocsr_match_boxes. */
+int32_t ocsr_range_frame(ocsr_ctx* ctx, const uint8_t* imgL, const uint8_t* imgR,
+                         int32_t width, int32_t height, int32_t pitch_bytes,
+                         const ocsr_frame_params* fp, const ocsr_box* boxes,
+                         int32_t n_boxes, const ocsr_match_params* params,
+                         int32_t cap_blocks, void* ws, size_t ws_bytes,
+                         ocsr_box_result* out, void* stream);
+
+/* ------------------------------------------------------------------------------ */
+/* Timing                                                                           */
+/* ------------------------------------------------------------------------------ */
+/* When enabled, each kernel launch of the context is bracketed by HIP events on
+ * its stream; ocsr_ctx_kernel_time() then reports, per kernel name, the number of
+ * launches and their summed duration (ms) since the last reset. Reading
+ * synchronizes on the recorded events. */
+int32_t ocsr_ctx_set_timing(ocsr_ctx* ctx, int32_t enable);
+int32_t ocsr_ctx_kernel_time(ocsr_ctx* ctx, const char* kernel, int64_t* launches,
+                             double* total_ms);
+int32_t ocsr_ctx_reset_timing(ocsr_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* OCSR_H */

@@ -1,0 +1,414 @@
+// C ABI of libocsr: argument validation, workspace layout, launches and timing.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "ocsr_internal.hpp"
+
+using namespace ocsr;
+
+struct ocsr_ctx {
+  int device = 0;
+  int n_cu = 256;
+  bool timing = false;
+  struct Pending {
+    std::string name;
+    hipEvent_t start, stop;
+  };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> free_events;
+  std::map<std::string, std::pair<int64_t, double>> stats;
+  hipEvent_t open_start = nullptr;
+  std::mutex mu;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int32_t fail(int32_t code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+int32_t hip_fail(hipError_t e, const char* what) {
+  return fail(OCSR_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+hipEvent_t take_event(ocsr_ctx* c) {
+  if (!c->free_events.empty()) {
+    hipEvent_t e = c->free_events.back();
+    c->free_events.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+void timer_before(void* ctx, const char* name, hipStream_t s) {
+  (void)name;
+  ocsr_ctx* c = (ocsr_ctx*)ctx;
+  c->open_start = take_event(c);
+  if (c->open_start) hipEventRecord(c->open_start, s);
+}
+
+void timer_after(void* ctx, const char* name, hipStream_t s) {
+  ocsr_ctx* c = (ocsr_ctx*)ctx;
+  hipEvent_t stop = take_event(c);
+  if (!c->open_start || !stop) return;
+  hipEventRecord(stop, s);
+  c->pending.push_back({name, c->open_start, stop});
+  c->open_start = nullptr;
+}
+
+LaunchTimer make_timer(ocsr_ctx* c) { return LaunchTimer{c, timer_before, timer_after}; }
+
+int64_t cdiv64(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+int32_t check_census_window(int sx, int sy, int sentinel) {
+  if (sx < 0 || sy < 0 || sx > 32 || sy > 32)
+    return fail(OCSR_E_INVALID, "census window half-sizes must be in 0..32 (sx=%d sy=%d)", sx, sy);
+  const int bits = (2 * sx + 1) * (2 * sy + 1) + (sentinel ? 1 : 0);
+  if (bits > 64)
+    return fail(OCSR_E_UNSUPPORTED, "census window of %d bits does not fit 64 (sx=%d sy=%d)", bits, sx, sy);
+  return OCSR_OK;
+}
+
+int32_t check_job(const ocsr_census_job& j, int k) {
+  if (!j.img || !j.out) return fail(OCSR_E_INVALID, "census job %d: null image or output", k);
+  if (j.width <= 0 || j.height <= 0 || j.width > (1 << 16) || j.height > (1 << 16))
+    return fail(OCSR_E_INVALID, "census job %d: size %dx%d outside 1..65536", k, j.width, j.height);
+  if (j.pitch_bytes < j.width) return fail(OCSR_E_INVALID, "census job %d: pitch < width", k);
+  if (j.scale < 1 || j.scale > 16) return fail(OCSR_E_INVALID, "census job %d: scale %d outside 1..16", k, j.scale);
+  if (j.out_pitch_elems < j.width / j.scale)
+    return fail(OCSR_E_INVALID, "census job %d: output pitch %d < %d", k, j.out_pitch_elems, j.width / j.scale);
+  return OCSR_OK;
+}
+
+int32_t enqueue_census(ocsr_ctx* ctx, const ocsr_census_job* jobs, int n_jobs, int sx, int sy,
+                       int sentinel, hipStream_t stream) {
+  CensusJobsDev d;
+  memset(&d, 0, sizeof(d));
+  int64_t tiles = 0;
+  for (int k = 0; k < n_jobs; ++k) {
+    const ocsr_census_job& j = jobs[k];
+    const int Ws = j.width / j.scale, Hs = j.height / j.scale;
+    CensusJobDev& o = d.job[k];
+    o.img = j.img; o.out = j.out; o.W = j.width; o.H = j.height; o.pitch = j.pitch_bytes;
+    o.out_pitch = j.out_pitch_elems; o.scale = j.scale;
+    o.tiles_x = (int)cdiv64(Ws, kCensusTileX);
+    o.tile_begin = (int)tiles;
+    tiles += (int64_t)o.tiles_x * cdiv64(Hs, kCensusTileY);
+  }
+  d.n = n_jobs;
+  if (tiles > (1ll << 30)) return fail(OCSR_E_CAPACITY, "census: too many tiles");
+  LaunchTimer t = make_timer(ctx);
+  if (ctx->timing) t.before(ctx, "census", stream);
+  hipError_t e = launch_census(d, (int)tiles, sx, sy, sentinel, stream);
+  if (ctx->timing) t.after(ctx, "census", stream);
+  if (e != hipSuccess) return hip_fail(e, "census launch");
+  return OCSR_OK;
+}
+
+int32_t check_path(const ocsr_path& ph, const char* name, int scale, PathDev* out) {
+  if (ph.mode != OCSR_MODE_TILED && ph.mode != OCSR_MODE_GRID)
+    return fail(OCSR_E_INVALID, "%s path: unknown mode %d", name, ph.mode);
+  if (ph.mode == OCSR_MODE_TILED && (ph.bw < 1 || ph.bh < 1 || ph.bw * ph.bh > 64))
+    return fail(OCSR_E_INVALID, "%s path: TILED block %dx%d needs 1 <= bw*bh <= 64", name, ph.bw, ph.bh);
+  if (ph.mode == OCSR_MODE_GRID && (ph.n_side < 1 || ph.n_side > 8))
+    return fail(OCSR_E_INVALID, "%s path: GRID n_side %d outside 1..8", name, ph.n_side);
+  if (ph.dmin < 0 || ph.dmax < ph.dmin || ph.dmax > (1 << 20))
+    return fail(OCSR_E_INVALID, "%s path: disparity range [%d, %d] invalid", name, ph.dmin, ph.dmax);
+  const int64_t nd = cdiv64((int64_t)ph.dmax - ph.dmin + 1, scale);
+  if (nd > OCSR_MAX_CANDIDATES)
+    return fail(OCSR_E_CAPACITY, "%s path: %lld level candidates > %d", name, (long long)nd,
+                OCSR_MAX_CANDIDATES);
+  out->mode = ph.mode;
+  out->bw = ph.bw;
+  out->bh = ph.bh;
+  out->n_side = ph.n_side;
+  out->dlo = ph.dmin / scale;
+  out->nd = (int)nd;
+  return OCSR_OK;
+}
+
+int32_t check_level(const ocsr_level* lv, const char* name, LevelDev* out) {
+  if (!lv) return fail(OCSR_E_INVALID, "%s: null level", name);
+  if (!lv->L || !lv->R) return fail(OCSR_E_INVALID, "%s: null descriptor pointer", name);
+  if (lv->width <= 0 || lv->height <= 0 || lv->width > (1 << 16) || lv->height > (1 << 16))
+    return fail(OCSR_E_INVALID, "%s: size %dx%d outside 1..65536", name, lv->width, lv->height);
+  if (lv->pitch_elems < lv->width) return fail(OCSR_E_INVALID, "%s: pitch < width", name);
+  if (lv->scale < 1 || lv->scale > 16) return fail(OCSR_E_INVALID, "%s: scale %d outside 1..16", name, lv->scale);
+  if (lv->sx < 0 || lv->sy < 0) return fail(OCSR_E_INVALID, "%s: negative census window", name);
+  *out = LevelDev{lv->L, lv->R, lv->width, lv->height, lv->pitch_elems, lv->scale, lv->sx, lv->sy};
+  return OCSR_OK;
+}
+
+int32_t build_params(const ocsr_level* lv0, const ocsr_level* lv1, int n_boxes,
+                     const ocsr_match_params* p, int cap_blocks, MatchParamsDev* d) {
+  if (!p) return fail(OCSR_E_INVALID, "null params");
+  if (p->struct_size != sizeof(ocsr_match_params))
+    return fail(OCSR_E_INVALID, "params.struct_size %u != %zu", p->struct_size, sizeof(ocsr_match_params));
+  memset(d, 0, sizeof(*d));
+  int32_t rc;
+  if ((rc = check_level(lv0, "lv0", &d->lv[0])) != OCSR_OK) return rc;
+  if ((rc = check_level(lv1, "lv1", &d->lv[1])) != OCSR_OK) return rc;
+  if (lv0->scale != 1) return fail(OCSR_E_INVALID, "lv0 must have scale 1 (got %d)", lv0->scale);
+  if ((rc = check_path(p->far_path, "far", 1, &d->path[0])) != OCSR_OK) return rc;
+  if ((rc = check_path(p->close_path, "close", lv1->scale, &d->path[1])) != OCSR_OK) return rc;
+  if (p->lr_tol < 0) return fail(OCSR_E_INVALID, "lr_tol < 0");
+  if (p->min_point_pct < 0 || p->min_point_pct > 100) return fail(OCSR_E_INVALID, "min_point_pct outside 0..100");
+  if (p->agg_mode != OCSR_AGG_SEGMENT_MEDIAN && p->agg_mode != OCSR_AGG_TRIMMED_MEDIAN)
+    return fail(OCSR_E_INVALID, "unknown agg_mode %d", p->agg_mode);
+  if (p->trim_pct < 0 || p->trim_pct > 49) return fail(OCSR_E_INVALID, "trim_pct outside 0..49");
+  if (!(p->tau_d >= 0.0f) || !std::isfinite(p->tau_d)) return fail(OCSR_E_INVALID, "tau_d must be finite and >= 0");
+  if (!std::isfinite(p->focal_px) || !std::isfinite(p->baseline_m) || !std::isfinite(p->d_eps))
+    return fail(OCSR_E_INVALID, "focal, baseline and d_eps must be finite");
+  if (n_boxes < 0 || n_boxes > (1 << 20)) return fail(OCSR_E_INVALID, "n_boxes %d outside 0..2^20", n_boxes);
+  if (cap_blocks < 1 || cap_blocks > (1 << 24)) return fail(OCSR_E_INVALID, "cap_blocks %d outside 1..2^24", cap_blocks);
+  d->tau_s = p->tau_s;
+  d->lr_tol = p->lr_tol;
+  d->min_point_pct = p->min_point_pct;
+  d->agg_mode = p->agg_mode;
+  d->tau_d = p->tau_d;
+  d->n_min = p->n_min;
+  d->trim_pct = p->trim_pct;
+  const volatile float f = p->focal_px, b = p->baseline_m;
+  d->fb = f * b;
+  d->d_eps = p->d_eps;
+  d->cap_blocks = cap_blocks;
+  d->n_boxes = n_boxes;
+  return OCSR_OK;
+}
+
+int32_t enqueue_match(ocsr_ctx* ctx, const MatchParamsDev& d, const ocsr_box* boxes, void* ws,
+                      int cap_blocks, ocsr_box_result* out, const ocsr_debug* dbg,
+                      hipStream_t stream) {
+  MatchWs w = match_ws_carve(ws, d.n_boxes, cap_blocks);
+  DebugDev dd;
+  memset(&dd, 0, sizeof(dd));
+  if (dbg) {
+    dd.cap_blocks = dbg->cap_blocks;
+    dd.cap_nd = dbg->cap_nd;
+    dd.n_blocks = dbg->n_blocks;
+    dd.blocks = dbg->blocks;
+    dd.cost_fwd = dbg->cost_fwd;
+    dd.cost_bwd = dbg->cost_bwd;
+  }
+  const int n_wgs = std::max(1, std::min(cap_blocks, ctx->n_cu * 16));
+  LaunchTimer t = make_timer(ctx);
+  hipError_t e = launch_match(d, boxes, w, out, dd, n_wgs, stream, ctx->timing ? &t : nullptr);
+  if (e != hipSuccess) return hip_fail(e, "match launch");
+  if (dbg && dbg->n_blocks) {
+    e = hipMemcpyAsync(dbg->n_blocks, w.counters, sizeof(int32_t), hipMemcpyDeviceToDevice, stream);
+    if (e != hipSuccess) return hip_fail(e, "debug block count copy");
+  }
+  return OCSR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t ocsr_abi_version(void) { return OCSR_ABI_VERSION; }
+
+const char* ocsr_last_error(void) { return g_last_error.c_str(); }
+
+int32_t ocsr_ctx_create(int32_t device, ocsr_ctx** out) {
+  g_last_error.clear();
+  if (!out) return fail(OCSR_E_INVALID, "null output pointer");
+  *out = nullptr;
+  int n = 0;
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDeviceCount");
+  if (device < 0 || device >= n) return fail(OCSR_E_INVALID, "device %d outside 0..%d", device, n - 1);
+  e = hipSetDevice(device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  hipDeviceProp_t prop;
+  e = hipGetDeviceProperties(&prop, device);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(OCSR_E_UNSUPPORTED, "device %d is %s; this library is built for gfx950", device,
+                prop.gcnArchName);
+  ocsr_ctx* c = new (std::nothrow) ocsr_ctx();
+  if (!c) return fail(OCSR_E_INVALID, "out of host memory");
+  c->device = device;
+  c->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  *out = c;
+  return OCSR_OK;
+}
+
+void ocsr_ctx_destroy(ocsr_ctx* ctx) {
+  if (!ctx) return;
+  for (auto& p : ctx->pending) {
+    hipEventDestroy(p.start);
+    hipEventDestroy(p.stop);
+  }
+  for (auto e : ctx->free_events) hipEventDestroy(e);
+  delete ctx;
+}
+
+int32_t ocsr_census(ocsr_ctx* ctx, const uint8_t* img, int32_t width, int32_t height,
+                    int32_t pitch_bytes, const ocsr_census_params* params, uint64_t* out,
+                    int32_t out_pitch_elems, void* stream) {
+  g_last_error.clear();
+  if (!ctx || !params) return fail(OCSR_E_INVALID, "null context or params");
+  ocsr_census_job j;
+  j.img = img; j.out = out; j.width = width; j.height = height; j.pitch_bytes = pitch_bytes;
+  j.out_pitch_elems = out_pitch_elems; j.scale = params->scale; j.reserved = 0;
+  int32_t rc;
+  if ((rc = check_census_window(params->sx, params->sy, params->sentinel)) != OCSR_OK) return rc;
+  if ((rc = check_job(j, 0)) != OCSR_OK) return rc;
+  return enqueue_census(ctx, &j, 1, params->sx, params->sy, params->sentinel ? 1 : 0,
+                        (hipStream_t)stream);
+}
+
+int32_t ocsr_census_many(ocsr_ctx* ctx, const ocsr_census_job* jobs, int32_t n_jobs,
+                         int32_t sx, int32_t sy, int32_t sentinel, void* stream) {
+  g_last_error.clear();
+  if (!ctx || (!jobs && n_jobs > 0)) return fail(OCSR_E_INVALID, "null context or jobs");
+  if (n_jobs < 0 || n_jobs > OCSR_MAX_CENSUS_JOBS)
+    return fail(OCSR_E_INVALID, "n_jobs %d outside 0..%d", n_jobs, OCSR_MAX_CENSUS_JOBS);
+  int32_t rc;
+  if ((rc = check_census_window(sx, sy, sentinel)) != OCSR_OK) return rc;
+  for (int k = 0; k < n_jobs; ++k)
+    if ((rc = check_job(jobs[k], k)) != OCSR_OK) return rc;
+  if (n_jobs == 0) return OCSR_OK;
+  return enqueue_census(ctx, jobs, n_jobs, sx, sy, sentinel ? 1 : 0, (hipStream_t)stream);
+}
+
+size_t ocsr_match_workspace_bytes(int32_t n_boxes, int32_t cap_blocks) {
+  return match_ws_bytes(n_boxes, cap_blocks);
+}
+
+int32_t ocsr_match_boxes(ocsr_ctx* ctx, const ocsr_level* lv0, const ocsr_level* lv1,
+                         const ocsr_box* boxes, int32_t n_boxes, const ocsr_match_params* params,
+                         int32_t cap_blocks, void* ws, size_t ws_bytes, ocsr_box_result* out,
+                         const ocsr_debug* dbg, void* stream) {
+  g_last_error.clear();
+  if (!ctx) return fail(OCSR_E_INVALID, "null context");
+  MatchParamsDev d;
+  int32_t rc = build_params(lv0, lv1, n_boxes, params, cap_blocks, &d);
+  if (rc != OCSR_OK) return rc;
+  if (n_boxes == 0) return OCSR_OK;
+  if (!boxes || !out) return fail(OCSR_E_INVALID, "null boxes or output");
+  if (!ws || ((uintptr_t)ws & 255)) return fail(OCSR_E_INVALID, "workspace null or not 256-byte aligned");
+  const size_t need = match_ws_bytes(n_boxes, cap_blocks);
+  if (ws_bytes < need) return fail(OCSR_E_WORKSPACE, "workspace %zu bytes < %zu needed", ws_bytes, need);
+  if (dbg && (dbg->cap_blocks < 0 || dbg->cap_nd < 0))
+    return fail(OCSR_E_INVALID, "debug capacities must be >= 0");
+  return enqueue_match(ctx, d, boxes, ws, cap_blocks, out, dbg, (hipStream_t)stream);
+}
+
+static void frame_layout(int W, int H, int s, size_t* l0, size_t* l1) {
+  *l0 = ((size_t)W * H * 8 + 255) & ~(size_t)255;
+  *l1 = ((size_t)(W / s) * (H / s) * 8 + 255) & ~(size_t)255;
+}
+
+size_t ocsr_frame_workspace_bytes(int32_t width, int32_t height, const ocsr_frame_params* fp,
+                                  int32_t n_boxes, int32_t cap_blocks) {
+  if (!fp || width <= 0 || height <= 0 || fp->close_scale < 1) return 0;
+  size_t l0, l1;
+  frame_layout(width, height, fp->close_scale, &l0, &l1);
+  return 2 * l0 + 2 * l1 + match_ws_bytes(n_boxes, cap_blocks);
+}
+
+int32_t ocsr_range_frame(ocsr_ctx* ctx, const uint8_t* imgL, const uint8_t* imgR,
+                         int32_t width, int32_t height, int32_t pitch_bytes,
+                         const ocsr_frame_params* fp, const ocsr_box* boxes, int32_t n_boxes,
+                         const ocsr_match_params* params, int32_t cap_blocks, void* ws,
+                         size_t ws_bytes, ocsr_box_result* out, void* stream) {
+  g_last_error.clear();
+  if (!ctx || !fp) return fail(OCSR_E_INVALID, "null context or frame params");
+  if (fp->close_scale < 1 || fp->close_scale > 16) return fail(OCSR_E_INVALID, "close_scale outside 1..16");
+  int32_t rc;
+  if ((rc = check_census_window(fp->sx, fp->sy, fp->sentinel)) != OCSR_OK) return rc;
+  if (!ws || ((uintptr_t)ws & 255)) return fail(OCSR_E_INVALID, "workspace null or not 256-byte aligned");
+  const size_t need = ocsr_frame_workspace_bytes(width, height, fp, n_boxes, cap_blocks);
+  if (need == 0) return fail(OCSR_E_INVALID, "bad frame size");
+  if (ws_bytes < need) return fail(OCSR_E_WORKSPACE, "workspace %zu bytes < %zu needed", ws_bytes, need);
+  const int s = fp->close_scale;
+  size_t l0, l1;
+  frame_layout(width, height, s, &l0, &l1);
+  char* base = (char*)ws;
+  uint64_t* dL0 = (uint64_t*)base;
+  uint64_t* dR0 = (uint64_t*)(base + l0);
+  uint64_t* dL1 = (uint64_t*)(base + 2 * l0);
+  uint64_t* dR1 = (uint64_t*)(base + 2 * l0 + l1);
+  void* mws = base + 2 * l0 + 2 * l1;
+  ocsr_census_job jobs[4];
+  const uint8_t* imgs[4] = {imgL, imgR, imgL, imgR};
+  uint64_t* outs[4] = {dL0, dR0, dL1, dR1};
+  for (int k = 0; k < 4; ++k) {
+    const int sc = k < 2 ? 1 : s;
+    jobs[k].img = imgs[k]; jobs[k].out = outs[k]; jobs[k].width = width; jobs[k].height = height;
+    jobs[k].pitch_bytes = pitch_bytes; jobs[k].out_pitch_elems = width / sc; jobs[k].scale = sc;
+    jobs[k].reserved = 0;
+    if ((rc = check_job(jobs[k], k)) != OCSR_OK) return rc;
+  }
+  ocsr_level lv0 = {dL0, dR0, width, height, width, 1, fp->sx, fp->sy};
+  ocsr_level lv1 = {dL1, dR1, width / s, height / s, width / s, s, fp->sx, fp->sy};
+  MatchParamsDev d;
+  if ((rc = build_params(&lv0, &lv1, n_boxes, params, cap_blocks, &d)) != OCSR_OK) return rc;
+  if (n_boxes > 0 && (!boxes || !out)) return fail(OCSR_E_INVALID, "null boxes or output");
+  if ((rc = enqueue_census(ctx, jobs, 4, fp->sx, fp->sy, fp->sentinel ? 1 : 0, (hipStream_t)stream)) != OCSR_OK)
+    return rc;
+  if (n_boxes == 0) return OCSR_OK;
+  return enqueue_match(ctx, d, boxes, mws, cap_blocks, out, nullptr, (hipStream_t)stream);
+}
+
+int32_t ocsr_ctx_set_timing(ocsr_ctx* ctx, int32_t enable) {
+  g_last_error.clear();
+  if (!ctx) return fail(OCSR_E_INVALID, "null context");
+  ctx->timing = enable != 0;
+  return OCSR_OK;
+}
+
+static int32_t drain_pending(ocsr_ctx* ctx) {
+  for (auto& p : ctx->pending) {
+    hipError_t e = hipEventSynchronize(p.stop);
+    if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+    float ms = 0.0f;
+    e = hipEventElapsedTime(&ms, p.start, p.stop);
+    if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+    auto& st = ctx->stats[p.name];
+    st.first += 1;
+    st.second += ms;
+    ctx->free_events.push_back(p.start);
+    ctx->free_events.push_back(p.stop);
+  }
+  ctx->pending.clear();
+  return OCSR_OK;
+}
+
+int32_t ocsr_ctx_kernel_time(ocsr_ctx* ctx, const char* kernel, int64_t* launches, double* total_ms) {
+  g_last_error.clear();
+  if (!ctx || !kernel || !launches || !total_ms) return fail(OCSR_E_INVALID, "null argument");
+  int32_t rc = drain_pending(ctx);
+  if (rc != OCSR_OK) return rc;
+  auto it = ctx->stats.find(kernel);
+  *launches = it == ctx->stats.end() ? 0 : it->second.first;
+  *total_ms = it == ctx->stats.end() ? 0.0 : it->second.second;
+  return OCSR_OK;
+}
+
+int32_t ocsr_ctx_reset_timing(ocsr_ctx* ctx) {
+  g_last_error.clear();
+  if (!ctx) return fail(OCSR_E_INVALID, "null context");
+  int32_t rc = drain_pending(ctx);
+  ctx->stats.clear();
+  return rc;
+}
+
+}  // extern "C"

@@ -1,0 +1,361 @@
+"""Python binding of libocsr (the gfx950 HIP library), through its C ABI.
+
+Argument marshalling only: every step of the method runs in the library's
+kernels. PyTorch supplies device memory (tensors) and streams; the library is
+called on torch's current stream of the tensors' device. There is no fallback:
+if the built library is missing, load() raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import threading
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libocsr.so")
+
+OK = 0
+E_INVALID, E_WORKSPACE, E_CAPACITY, E_HIP, E_UNSUPPORTED = -1, -2, -3, -4, -5
+REASONS = ["OK", "NOT_RANGED", "CLIPPED_EMPTY", "NO_ELIGIBLE_BLOCKS", "NO_VALID_BLOCKS",
+           "TOO_FEW_CONSISTENT", "NONPOSITIVE_DISPARITY", "CAPACITY_OVERFLOW"]
+MODE_TILED, MODE_GRID = 0, 1
+AGG_SEGMENT_MEDIAN, AGG_TRIMMED_MEDIAN = 0, 1
+BOX_RANGE = 1
+MAX_BLOCKS_PER_BOX = 16384
+MAX_CANDIDATES = 256
+MAX_CENSUS_JOBS = 64
+DEFAULT_CAP_BLOCKS = 1 << 20
+
+EXPORTS = ["ocsr_abi_version", "ocsr_last_error", "ocsr_ctx_create", "ocsr_ctx_destroy",
+           "ocsr_census", "ocsr_census_many", "ocsr_match_workspace_bytes", "ocsr_match_boxes",
+           "ocsr_frame_workspace_bytes", "ocsr_range_frame", "ocsr_ctx_set_timing",
+           "ocsr_ctx_kernel_time", "ocsr_ctx_reset_timing"]
+
+
+class OcsrError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"ocsr status {code}: {msg}")
+        self.code = code
+
+
+# ---------------------------------------------------------------------------------
+# ABI structures (include/ocsr.h)
+# ---------------------------------------------------------------------------------
+class CensusParams(C.Structure):
+    _fields_ = [("sx", C.c_int32), ("sy", C.c_int32), ("scale", C.c_int32), ("sentinel", C.c_int32)]
+
+
+class CensusJob(C.Structure):
+    _fields_ = [("img", C.c_void_p), ("out", C.c_void_p), ("width", C.c_int32),
+                ("height", C.c_int32), ("pitch_bytes", C.c_int32), ("out_pitch_elems", C.c_int32),
+                ("scale", C.c_int32), ("reserved", C.c_int32)]
+
+
+class Level(C.Structure):
+    _fields_ = [("L", C.c_void_p), ("R", C.c_void_p), ("width", C.c_int32), ("height", C.c_int32),
+                ("pitch_elems", C.c_int32), ("scale", C.c_int32), ("sx", C.c_int32), ("sy", C.c_int32)]
+
+
+class Path(C.Structure):
+    _fields_ = [("mode", C.c_int32), ("bw", C.c_int32), ("bh", C.c_int32), ("n_side", C.c_int32),
+                ("dmin", C.c_int32), ("dmax", C.c_int32)]
+
+
+class MatchParams(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("tau_s", C.c_int32), ("far_path", Path),
+                ("close_path", Path), ("lr_tol", C.c_int32), ("min_point_pct", C.c_int32),
+                ("agg_mode", C.c_int32), ("tau_d", C.c_float), ("n_min", C.c_int32),
+                ("trim_pct", C.c_int32), ("focal_px", C.c_float), ("baseline_m", C.c_float),
+                ("d_eps", C.c_float)]
+
+
+class FrameParams(C.Structure):
+    _fields_ = [("sx", C.c_int32), ("sy", C.c_int32), ("sentinel", C.c_int32),
+                ("close_scale", C.c_int32)]
+
+
+class Debug(C.Structure):
+    _fields_ = [("cap_blocks", C.c_int32), ("cap_nd", C.c_int32), ("n_blocks", C.c_void_p),
+                ("blocks", C.c_void_p), ("cost_fwd", C.c_void_p), ("cost_bwd", C.c_void_p)]
+
+
+BOX_RESULT_DTYPE = np.dtype([("disparity", "<f4"), ("depth", "<f4"), ("valid", "<i4"),
+                             ("reason", "<i4"), ("n_blocks", "<i4"), ("n_eligible", "<i4"),
+                             ("n_valid", "<i4"), ("n_used", "<i4")])
+BLOCK_RECORD_DTYPE = np.dtype([("box", "<i4"), ("level_scale", "<i4"), ("u", "<i4"), ("v", "<i4"),
+                               ("px0", "<i4"), ("py0", "<i4"), ("nx", "<i4"), ("ny", "<i4"),
+                               ("mask", "<u8"), ("eligible", "<i4"), ("d_f", "<i4"),
+                               ("d_b", "<i4"), ("lr_ok", "<i4"), ("d_sub", "<f4"),
+                               ("valid", "<i4"), ("dlo", "<i4"), ("nd", "<i4")])
+assert BOX_RESULT_DTYPE.itemsize == 32 and BLOCK_RECORD_DTYPE.itemsize == 72
+
+_lib = None
+_lock = threading.Lock()
+_ctx: dict[int, C.c_void_p] = {}
+
+
+def load(path: str = LIB_PATH):
+    """Loads the built library (raises if it is not built)."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(path):
+            raise RuntimeError(f"libocsr is not built: {path} missing "
+                               "(run python -m paper_2604_07980_amd.build)")
+        L = C.CDLL(path)
+        vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+        L.ocsr_abi_version.restype = i32
+        L.ocsr_last_error.restype = C.c_char_p
+        L.ocsr_ctx_create.argtypes = [i32, C.POINTER(vp)]
+        L.ocsr_ctx_create.restype = i32
+        L.ocsr_ctx_destroy.argtypes = [vp]
+        L.ocsr_ctx_destroy.restype = None
+        L.ocsr_census.argtypes = [vp, vp, i32, i32, i32, C.POINTER(CensusParams), vp, i32, vp]
+        L.ocsr_census.restype = i32
+        L.ocsr_census_many.argtypes = [vp, C.POINTER(CensusJob), i32, i32, i32, i32, vp]
+        L.ocsr_census_many.restype = i32
+        L.ocsr_match_workspace_bytes.argtypes = [i32, i32]
+        L.ocsr_match_workspace_bytes.restype = C.c_size_t
+        L.ocsr_match_boxes.argtypes = [vp, C.POINTER(Level), C.POINTER(Level), vp, i32,
+                                       C.POINTER(MatchParams), i32, vp, C.c_size_t, vp,
+                                       C.POINTER(Debug), vp]
+        L.ocsr_match_boxes.restype = i32
+        L.ocsr_frame_workspace_bytes.argtypes = [i32, i32, C.POINTER(FrameParams), i32, i32]
+        L.ocsr_frame_workspace_bytes.restype = C.c_size_t
+        L.ocsr_range_frame.argtypes = [vp, vp, vp, i32, i32, i32, C.POINTER(FrameParams), vp, i32,
+                                       C.POINTER(MatchParams), i32, vp, C.c_size_t, vp, vp]
+        L.ocsr_range_frame.restype = i32
+        L.ocsr_ctx_set_timing.argtypes = [vp, i32]
+        L.ocsr_ctx_set_timing.restype = i32
+        L.ocsr_ctx_kernel_time.argtypes = [vp, C.c_char_p, C.POINTER(i64), C.POINTER(C.c_double)]
+        L.ocsr_ctx_kernel_time.restype = i32
+        L.ocsr_ctx_reset_timing.argtypes = [vp]
+        L.ocsr_ctx_reset_timing.restype = i32
+        _lib = L
+        return L
+
+
+def _check(rc: int):
+    if rc != OK:
+        raise OcsrError(rc, load().ocsr_last_error().decode())
+
+
+def context(device: int | None = None) -> C.c_void_p:
+    """The library context of a CUDA device (created once per device)."""
+    L = load()
+    if device is None:
+        device = torch.cuda.current_device()
+    with _lock:
+        if device not in _ctx:
+            h = C.c_void_p()
+            _check(L.ocsr_ctx_create(device, C.byref(h)))
+            _ctx[device] = h
+        return _ctx[device]
+
+
+def _stream(dev: torch.device) -> C.c_void_p:
+    return C.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+
+
+def _dptr(t: torch.Tensor) -> C.c_void_p:
+    return C.c_void_p(t.data_ptr())
+
+
+def _need_cuda(*ts):
+    for t in ts:
+        if not (isinstance(t, torch.Tensor) and t.is_cuda):
+            raise ValueError("expected CUDA tensors")
+
+
+# ---------------------------------------------------------------------------------
+# census
+# ---------------------------------------------------------------------------------
+def census(img: torch.Tensor, sx: int = 3, sy: int = 4, scale: int = 1, sentinel: int = 1,
+           out: torch.Tensor | None = None) -> torch.Tensor:
+    """Census descriptors of one uint8 image [H, W] (cuda) at level `scale`:
+    int64 [H // scale, W // scale] holding the uint64 codes' bits."""
+    _need_cuda(img)
+    if img.dtype != torch.uint8 or img.dim() != 2 or img.stride(1) != 1:
+        raise ValueError("img must be a row-contiguous uint8 [H, W] tensor")
+    H, W = img.shape
+    if out is None:
+        out = torch.empty((H // scale, W // scale), dtype=torch.int64, device=img.device)
+    p = CensusParams(sx, sy, scale, sentinel)
+    L = load()
+    _check(L.ocsr_census(context(img.device.index), _dptr(img), W, H, img.stride(0), C.byref(p),
+                         _dptr(out), out.stride(0), _stream(img.device)))
+    return out
+
+
+def census_many(imgs, scales, sx: int = 3, sy: int = 4, sentinel: int = 1, outs=None):
+    """Census of several images/levels in one launch; returns the list of outputs."""
+    if len(imgs) != len(scales) or len(imgs) > MAX_CENSUS_JOBS:
+        raise ValueError("bad job list")
+    _need_cuda(*imgs)
+    jobs = (CensusJob * max(1, len(imgs)))()
+    res = []
+    for k, (img, s) in enumerate(zip(imgs, scales)):
+        H, W = img.shape
+        o = outs[k] if outs is not None else torch.empty((H // s, W // s), dtype=torch.int64,
+                                                         device=img.device)
+        res.append(o)
+        jobs[k] = CensusJob(img.data_ptr(), o.data_ptr(), W, H, img.stride(0), o.stride(0), s, 0)
+    L = load()
+    _check(L.ocsr_census_many(context(imgs[0].device.index), jobs, len(imgs), sx, sy, sentinel,
+                              _stream(imgs[0].device)))
+    return res
+
+
+# ---------------------------------------------------------------------------------
+# matching
+# ---------------------------------------------------------------------------------
+def make_params(p: dict) -> MatchParams:
+    q = MatchParams()
+    q.struct_size = C.sizeof(MatchParams)
+    q.tau_s = int(min(p["tau_s"], 2**31 - 1))
+    for name, dst in (("far", q.far_path), ("close", q.close_path)):
+        src = p[name]
+        for f in ("mode", "bw", "bh", "n_side", "dmin", "dmax"):
+            setattr(dst, f, int(src[f]))
+    q.lr_tol, q.min_point_pct, q.agg_mode = p["lr_tol"], p["min_point_pct"], p["agg_mode"]
+    q.tau_d, q.n_min, q.trim_pct = p["tau_d"], p["n_min"], p["trim_pct"]
+    q.focal_px, q.baseline_m, q.d_eps = p["focal_px"], p["baseline_m"], p["d_eps"]
+    return q
+
+
+def results_to_numpy(res: torch.Tensor) -> np.ndarray:
+    """Device result tensor (int32 [N, 8]) -> numpy structured array."""
+    return res.cpu().numpy().view(BOX_RESULT_DTYPE).reshape(-1)
+
+
+def _level(L: torch.Tensor, R: torch.Tensor, scale: int, sx: int, sy: int) -> Level:
+    _need_cuda(L, R)
+    if L.shape != R.shape or L.dtype != torch.int64 or R.dtype != torch.int64:
+        raise ValueError("descriptor tensors must be int64 of equal shape")
+    if L.stride(0) != R.stride(0) or L.stride(1) != 1 or R.stride(1) != 1:
+        raise ValueError("descriptor tensors must share a row pitch and be row-contiguous")
+    H, W = L.shape
+    return Level(L.data_ptr(), R.data_ptr(), W, H, L.stride(0), scale, sx, sy)
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    ws = torch.empty(int(nbytes) + 256, dtype=torch.uint8, device=device)
+    off = (-ws.data_ptr()) % 256
+    return ws[off:off + int(nbytes)]
+
+
+class Workspace:
+    """A reusable device workspace (grows on demand)."""
+
+    def __init__(self):
+        self.buf = None
+
+    def get(self, nbytes: int, device) -> torch.Tensor:
+        if self.buf is None or self.buf.numel() < nbytes or self.buf.device != torch.device(device):
+            self.buf = _workspace(nbytes, device)
+        return self.buf
+
+
+def match_boxes(L0, R0, L1, R1, boxes: torch.Tensor, params: dict, close_scale: int | None = None,
+                cap_blocks: int = DEFAULT_CAP_BLOCKS, debug: bool = False, cap_nd: int = 256,
+                workspace: Workspace | None = None, out: torch.Tensor | None = None):
+    """Per-box disparity and depth from descriptors (int64 cuda tensors).
+
+    boxes: int32 [N, 5] cuda (x0, y0, x1, y1, flags). Returns the int32 [N, 8] result
+    tensor (see BOX_RESULT_DTYPE), plus (n_blocks, records, cost_fwd, cost_bwd)
+    device tensors when debug is set.
+    """
+    _need_cuda(boxes)
+    if boxes.dtype != torch.int32 or boxes.dim() != 2 or boxes.shape[1] != 5 or not boxes.is_contiguous():
+        raise ValueError("boxes must be a contiguous int32 [N, 5] tensor")
+    dev = boxes.device
+    sx, sy = params["sx"], params["sy"]
+    s = close_scale if close_scale is not None else params["close_scale"]
+    lv0 = _level(L0, R0, 1, sx, sy)
+    lv1 = _level(L1, R1, s, sx, sy) if L1 is not None else _level(L0, R0, 1, sx, sy)
+    n = boxes.shape[0]
+    L = load()
+    nbytes = L.ocsr_match_workspace_bytes(n, cap_blocks)
+    ws = (workspace or Workspace()).get(nbytes, dev)
+    if out is None:
+        out = torch.empty((n, 8), dtype=torch.int32, device=dev)
+    dbg = None
+    extra = None
+    if debug:
+        nb = torch.zeros(1, dtype=torch.int32, device=dev)
+        cap_dbg = cap_blocks
+        rec = torch.zeros((cap_dbg, BLOCK_RECORD_DTYPE.itemsize), dtype=torch.uint8, device=dev)
+        cf = torch.zeros((cap_dbg, cap_nd), dtype=torch.int16, device=dev)
+        cb = torch.zeros((cap_dbg, cap_nd), dtype=torch.int16, device=dev)
+        dbg = Debug(cap_dbg, cap_nd, nb.data_ptr(), rec.data_ptr(), cf.data_ptr(), cb.data_ptr())
+        extra = (nb, rec, cf, cb)
+    q = make_params(params)
+    _check(L.ocsr_match_boxes(context(dev.index), C.byref(lv0), C.byref(lv1), _dptr(boxes), n,
+                              C.byref(q), cap_blocks, _dptr(ws), ws.numel(), _dptr(out),
+                              C.byref(dbg) if dbg is not None else None, _stream(dev)))
+    if debug:
+        return out, extra
+    return out
+
+
+def debug_to_numpy(extra):
+    nb, rec, cf, cb = extra
+    n = int(nb.item())
+    n_rec = min(n, rec.shape[0])
+    recs = rec[:n_rec].cpu().numpy().view(BLOCK_RECORD_DTYPE).reshape(-1)
+    cfn = cf[:n_rec].cpu().numpy().view(np.uint16)
+    cbn = cb[:n_rec].cpu().numpy().view(np.uint16)
+    return n, recs, cfn, cbn
+
+
+def frame_workspace_bytes(W: int, H: int, params: dict, n_boxes: int,
+                          cap_blocks: int = DEFAULT_CAP_BLOCKS) -> int:
+    fp = FrameParams(params["sx"], params["sy"], params["sentinel"], params["close_scale"])
+    return int(load().ocsr_frame_workspace_bytes(W, H, C.byref(fp), n_boxes, cap_blocks))
+
+
+def range_frame(imgL: torch.Tensor, imgR: torch.Tensor, boxes: torch.Tensor, params: dict,
+                cap_blocks: int = DEFAULT_CAP_BLOCKS, workspace: Workspace | None = None,
+                out: torch.Tensor | None = None) -> torch.Tensor:
+    """Whole frame (census of both views at both levels, then matching)."""
+    _need_cuda(imgL, imgR, boxes)
+    if imgL.shape != imgR.shape or imgL.dtype != torch.uint8 or imgL.stride() != imgR.stride():
+        raise ValueError("images must be uint8 tensors of equal shape and pitch")
+    if boxes.dtype != torch.int32 or boxes.dim() != 2 or boxes.shape[1] != 5 or not boxes.is_contiguous():
+        raise ValueError("boxes must be a contiguous int32 [N, 5] tensor")
+    H, W = imgL.shape
+    dev = imgL.device
+    n = boxes.shape[0]
+    fp = FrameParams(params["sx"], params["sy"], params["sentinel"], params["close_scale"])
+    L = load()
+    nbytes = L.ocsr_frame_workspace_bytes(W, H, C.byref(fp), n, cap_blocks)
+    ws = (workspace or Workspace()).get(nbytes, dev)
+    if out is None:
+        out = torch.empty((n, 8), dtype=torch.int32, device=dev)
+    q = make_params(params)
+    _check(L.ocsr_range_frame(context(dev.index), _dptr(imgL), _dptr(imgR), W, H, imgL.stride(0),
+                              C.byref(fp), _dptr(boxes), n, C.byref(q), cap_blocks, _dptr(ws),
+                              ws.numel(), _dptr(out), _stream(dev)))
+    return out
+
+
+# ---------------------------------------------------------------------------------
+# timing
+# ---------------------------------------------------------------------------------
+def set_timing(enable: bool, device: int | None = None):
+    _check(load().ocsr_ctx_set_timing(context(device), 1 if enable else 0))
+
+
+def kernel_time(name: str, device: int | None = None) -> tuple[int, float]:
+    n = C.c_int64()
+    ms = C.c_double()
+    _check(load().ocsr_ctx_kernel_time(context(device), name.encode(), C.byref(n), C.byref(ms)))
+    return int(n.value), float(ms.value)
+
+
+def reset_timing(device: int | None = None):
+    _check(load().ocsr_ctx_reset_timing(context(device)))

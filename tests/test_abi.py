@@ -1,0 +1,71 @@
+"""Host-side checks of the C ABI: the built library loads and exports every function
+that include/*.h declares, and the binding's structures match the header's sizes.
+No GPU and no compute calls."""
+import ctypes as C
+import glob
+import os
+import re
+
+import pytest
+
+from paper_2604_07980_amd import ocsr
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        src = open(h).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        for m in re.finditer(r"\b(ocsr_[a-z0-9_]+)\s*\(", src):
+            names.add(m.group(1))
+    return names
+
+
+@pytest.fixture(scope="module")
+def built():
+    if not os.path.exists(ocsr.LIB_PATH):
+        from paper_2604_07980_amd import build
+        build.build()
+    return ocsr.load()
+
+
+def test_exports_every_declared_symbol(built):
+    declared = _declared_functions()
+    assert declared, "no declarations found"
+    missing = [n for n in sorted(declared) if not hasattr(built, n)]
+    assert not missing, missing
+    assert set(ocsr.EXPORTS) == declared
+
+
+def test_abi_version_and_host_only_calls(built):
+    assert built.ocsr_abi_version() == 1
+    assert built.ocsr_last_error() == b""
+    # workspace sizing is pure host arithmetic
+    a = built.ocsr_match_workspace_bytes(32, 1 << 16)
+    b = built.ocsr_match_workspace_bytes(64, 1 << 16)
+    assert 0 < a < b
+    fp = ocsr.FrameParams(3, 4, 1, 2)
+    f = built.ocsr_frame_workspace_bytes(1920, 1080, C.byref(fp), 32, 1 << 16)
+    assert f >= a + 2 * 1920 * 1080 * 8 + 2 * 960 * 540 * 8
+    assert built.ocsr_frame_workspace_bytes(0, 1080, C.byref(fp), 32, 1 << 16) == 0
+
+
+def test_struct_sizes_match_header():
+    assert C.sizeof(ocsr.MatchParams) == 4 + 4 + 2 * 24 + 3 * 4 + 4 + 2 * 4 + 3 * 4
+    assert C.sizeof(ocsr.Level) == 2 * 8 + 6 * 4
+    assert C.sizeof(ocsr.CensusJob) == 2 * 8 + 6 * 4
+    assert C.sizeof(ocsr.Debug) == 2 * 4 + 4 * 8
+    assert ocsr.BLOCK_RECORD_DTYPE.itemsize == 72
+
+
+def test_header_constants_match_binding():
+    src = open(os.path.join(ROOT, "include", "ocsr.h")).read()
+    def const(name):
+        return int(re.search(rf"#define {name} \(?(-?\d+)", src).group(1))
+    assert const("OCSR_MAX_BLOCKS_PER_BOX") == ocsr.MAX_BLOCKS_PER_BOX
+    assert const("OCSR_MAX_CANDIDATES") == ocsr.MAX_CANDIDATES
+    assert const("OCSR_MAX_CENSUS_JOBS") == ocsr.MAX_CENSUS_JOBS
+    for k, name in enumerate(ocsr.REASONS):
+        assert const(f"OCSR_REASON_{name}") == k

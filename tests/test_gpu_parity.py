@@ -1,0 +1,223 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle, on seeded inputs.
+
+Integer outputs (census words, block tables, masks, cost volumes, WTA indices,
+validity, reasons) must be bit-exact; sub-pixel disparity within 1e-4 px and depth
+within 1e-5 relative (fp32).
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_2604_07980_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+TOL_D = 1e-4
+TOL_Z = 1e-5
+
+
+def _u64(t: torch.Tensor) -> np.ndarray:
+    return t.cpu().numpy().view(np.uint64)
+
+
+def _cuda(a: np.ndarray) -> torch.Tensor:
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def assert_results_match(gpu: np.ndarray, orc: np.ndarray):
+    for f in ("valid", "reason", "n_blocks", "n_eligible", "n_valid", "n_used"):
+        assert (gpu[f] == orc[f]).all(), (f, np.nonzero(gpu[f] != orc[f])[0][:10],
+                                          gpu[f][gpu[f] != orc[f]][:10], orc[f][gpu[f] != orc[f]][:10])
+    assert np.all(np.abs(gpu["disparity"] - orc["disparity"]) <= TOL_D)
+    z_o = orc["depth"].astype(np.float64)
+    z_g = gpu["depth"].astype(np.float64)
+    assert np.all(np.abs(z_g - z_o) <= TOL_Z * np.maximum(np.abs(z_o), 1e-30))
+
+
+# ------------------------------------------------------------------------------------
+# census
+# ------------------------------------------------------------------------------------
+@pytest.mark.parametrize("shape", [(37, 53), (96, 130), (480, 640), (1080, 1920), (5, 5)])
+@pytest.mark.parametrize("win", [(3, 4), (2, 2), (4, 3), (1, 2)])
+@pytest.mark.parametrize("scale", [1, 2, 3])
+def test_census_parity(lib, orc, shape, win, scale):
+    rng = np.random.default_rng(hash((shape, win, scale)) % (1 << 32))
+    img = rng.integers(0, 256, size=shape, dtype=np.uint8)
+    if shape[0] >= 480:
+        img = np.rint(synth.blurred_noise(rng, *shape)).astype(np.uint8)
+    for sentinel in (0, 1):
+        want = orc.census(img, win[0], win[1], scale, sentinel)
+        got = _u64(lib.census(_cuda(img), win[0], win[1], scale, sentinel))
+        assert got.shape == want.shape
+        bad = np.argwhere(got != want)
+        assert bad.size == 0, bad[:10]
+
+
+def test_census_pitched_and_many(lib, orc):
+    rng = np.random.default_rng(4)
+    big = rng.integers(0, 256, size=(200, 333), dtype=np.uint8)
+    t = _cuda(big)[:, 10:310]             # pitched view: 300 wide, pitch 333
+    want = orc.census(np.ascontiguousarray(big[:, 10:310]), 3, 4, 1, 1)
+    assert (_u64(lib.census(t)) == want).all()
+    a = _cuda(rng.integers(0, 256, size=(120, 170), dtype=np.uint8))
+    b = _cuda(rng.integers(0, 256, size=(77, 64), dtype=np.uint8))
+    outs = lib.census_many([a, b, a, b], [1, 1, 2, 3])
+    for o, img, s in zip(outs, [a, b, a, b], [1, 1, 2, 3]):
+        assert (_u64(o) == orc.census(img.cpu().numpy(), 3, 4, s, 1)).all()
+
+
+def test_census_constant_image(lib):
+    img = torch.full((64, 100), 9, dtype=torch.uint8, device=DEV)
+    assert int(lib.census(img, sentinel=0).abs().sum()) == 0
+    c = _u64(lib.census(img, sentinel=1))
+    assert (c[4:-4, 3:-3] == np.uint64(1 << 63)).all()
+
+
+# ------------------------------------------------------------------------------------
+# matching, with debug records and cost volumes
+# ------------------------------------------------------------------------------------
+VARIANTS = {
+    "tiled_trim": dict(tau_s=40, far=dict(mode=0, bw=4, bh=4, n_side=8, dmin=0, dmax=15),
+                       close=dict(mode=0, bw=8, bh=8, n_side=8, dmin=0, dmax=31)),
+    "tiled_seg_lr0": dict(tau_s=40, agg_mode=0, lr_tol=0,
+                          far=dict(mode=0, bw=4, bh=2, n_side=8, dmin=2, dmax=13),
+                          close=dict(mode=0, bw=6, bh=5, n_side=8, dmin=3, dmax=28)),
+    "grid_far": dict(tau_s=50, agg_mode=0,
+                     far=dict(mode=1, bw=8, bh=8, n_side=8, dmin=0, dmax=15),
+                     close=dict(mode=0, bw=8, bh=8, n_side=8, dmin=0, dmax=31)),
+    "grid_both_s3": dict(tau_s=30, close_scale=3, min_point_pct=80,
+                         far=dict(mode=1, bw=8, bh=8, n_side=5, dmin=1, dmax=9),
+                         close=dict(mode=1, bw=8, bh=8, n_side=7, dmin=0, dmax=23)),
+    "wide_range": dict(tau_s=40, far=dict(mode=0, bw=8, bh=8, n_side=8, dmin=0, dmax=255),
+                       close=dict(mode=0, bw=8, bh=8, n_side=8, dmin=0, dmax=511)),
+    "win5x5": dict(sx=2, sy=2, tau_s=40, trim_pct=10, n_min=2,
+                   far=dict(mode=0, bw=3, bh=3, n_side=8, dmin=0, dmax=11),
+                   close=dict(mode=0, bw=4, bh=4, n_side=8, dmin=0, dmax=19)),
+}
+
+
+def _params(v):
+    p = synth.base_params()
+    p.update({k: (dict(val) if isinstance(val, dict) else val) for k, val in VARIANTS[v].items()})
+    return p
+
+
+def _gpu_levels(lib, left, right, p):
+    s = p["close_scale"]
+    L, R = _cuda(left), _cuda(right)
+    outs = lib.census_many([L, R, L, R], [1, 1, s, s], p["sx"], p["sy"], p["sentinel"])
+    return outs
+
+
+def _check_debug(lib, extra, blk, cf, cb, n):
+    n_g, rec, cfg, cbg = lib.debug_to_numpy(extra)
+    assert n_g == n
+    assert len(rec) == n
+    for f in ("box", "level_scale", "u", "v", "px0", "py0", "nx", "ny", "mask", "eligible",
+              "dlo", "nd"):
+        bad = np.nonzero(rec[f] != blk[f])[0]
+        assert bad.size == 0, (f, bad[:10], rec[f][bad[:5]], blk[f][bad[:5]])
+    el = blk["eligible"] == 1
+    for f in ("d_f", "d_b", "lr_ok", "valid"):
+        assert (rec[f][el] == blk[f][el]).all(), f
+    assert np.all(np.abs(rec["d_sub"][el] - blk["d_sub"][el]) <= TOL_D)
+    for k in np.nonzero(el)[0]:
+        nd = int(blk["nd"][k])
+        assert (cfg[k, :nd] == cf[k, :nd]).all(), ("fwd", k)
+        assert (cbg[k, :nd] == cb[k, :nd]).all(), ("bwd", k)
+
+
+@pytest.mark.parametrize("variant", list(VARIANTS))
+@pytest.mark.parametrize("seed", [1, 2, 3, 4])
+def test_match_parity_small(lib, orc, variant, seed):
+    p = _params(variant)
+    sc = synth.scene_small(1000 * seed + len(variant), H=120, W=200, n_planes=6)
+    (L0, R0, L1, R1), (res, blk, cf, cb, n) = orc.run_scene(sc.left, sc.right, p, sc.boxes,
+                                                            debug=True)
+    g = _gpu_levels(lib, sc.left, sc.right, p)
+    for a, b in zip(g, (L0, R0, L1, R1)):
+        assert (_u64(a) == b).all()
+    out, extra = lib.match_boxes(g[0], g[1], g[2], g[3], _cuda(sc.boxes), p, debug=True,
+                                 cap_blocks=max(n, 1) + 7)
+    assert_results_match(lib.results_to_numpy(out), res)
+    _check_debug(lib, extra, blk, cf, cb, n)
+
+
+def test_match_edge_cases(lib, orc):
+    sc = synth.scene_small(9, H=64, W=96, n_planes=2)
+    p = _params("tiled_trim")
+    boxes = np.array([[-30, -30, -1, -1, 1], [10, 10, 10, 40, 1], [90, 20, 140, 60, 1],
+                      [0, 0, 96, 64, 1], [20, 30, 23, 31, 1], [40, 20, 46, 60, 0],
+                      [5, 5, 12, 50, 1], [-5, -5, 200, 200, 1]], np.int32)
+    _, (res, blk, cf, cb, n) = orc.run_scene(sc.left, sc.right, p, boxes, debug=True)
+    g = _gpu_levels(lib, sc.left, sc.right, p)
+    out, extra = lib.match_boxes(*g, _cuda(boxes), p, debug=True, cap_blocks=4096)
+    assert_results_match(lib.results_to_numpy(out), res)
+    _check_debug(lib, extra, blk, cf, cb, n)
+
+
+def test_match_no_boxes(lib):
+    p = _params("tiled_trim")
+    img = torch.zeros((64, 96), dtype=torch.uint8, device=DEV)
+    g = lib.census_many([img, img, img, img], [1, 1, 2, 2])
+    out = lib.match_boxes(*g, torch.zeros((0, 5), dtype=torch.int32, device=DEV), p)
+    assert out.shape == (0, 8)
+
+
+def test_match_capacity(lib, orc):
+    sc = synth.scene_small(4, H=64, W=96, n_planes=3)
+    p = _params("tiled_trim")
+    boxes = np.array([[0, 34, 96, 64, 1], [10, 5, 30, 25, 1], [50, 5, 62, 17, 1]], np.int32)
+    _, (res0, *_r) = orc.run_scene(sc.left, sc.right, p, boxes)
+    nb = res0["n_blocks"]
+    g = _gpu_levels(lib, sc.left, sc.right, p)
+    for cap in (int(nb[0] + nb[1]), int(nb[0]) + 1, 1, int(nb.sum())):
+        _, (res, *_r) = orc.run_scene(sc.left, sc.right, p, boxes, cap_blocks=cap)
+        out = lib.match_boxes(*g, _cuda(boxes), p, cap_blocks=cap)
+        assert_results_match(lib.results_to_numpy(out), res)
+
+
+def test_match_many_boxes_occlusion(lib, orc):
+    """More boxes than a wave (the occluder scan loops over 64-box chunks)."""
+    rng = np.random.default_rng(8)
+    H, W = 240, 320
+    planes = synth.random_boxes(rng, H, W, 150, scale=0.25, tau_s=16)
+    left, right = synth.render_pair(rng, H, W, planes)
+    boxes = np.array([[q[0], q[1], q[2], q[3], 1] for q in planes], np.int32)
+    p = _params("tiled_trim")
+    p["min_point_pct"] = 30
+    _, (res, blk, cf, cb, n) = orc.run_scene(left, right, p, boxes, debug=True)
+    g = _gpu_levels(lib, left, right, p)
+    out, extra = lib.match_boxes(*g, _cuda(boxes), p, debug=True, cap_blocks=max(n, 1))
+    assert_results_match(lib.results_to_numpy(out), res)
+    _check_debug(lib, extra, blk, cf, cb, n)
+
+
+# ------------------------------------------------------------------------------------
+# the configured workloads, whole frame through ocsr_range_frame
+# ------------------------------------------------------------------------------------
+def _frame_parity(lib, orc, sc, p, debug_check=True):
+    (L0, R0, L1, R1), (res, blk, cf, cb, n) = orc.run_scene(sc.left, sc.right, p, sc.boxes,
+                                                            debug=debug_check)
+    out = lib.range_frame(_cuda(sc.left), _cuda(sc.right), _cuda(sc.boxes), p)
+    got = lib.results_to_numpy(out)
+    assert_results_match(got, res)
+    if debug_check:
+        g = _gpu_levels(lib, sc.left, sc.right, p)
+        out2, extra = lib.match_boxes(*g, _cuda(sc.boxes), p, debug=True, cap_blocks=max(n, 1))
+        assert_results_match(lib.results_to_numpy(out2), res)
+        _check_debug(lib, extra, blk, cf, cb, n)
+    return got
+
+
+def test_config1_tiny_frame(lib, orc):
+    sc = synth.scene_tiny()
+    got = _frame_parity(lib, orc, sc, synth.params_for(1))
+    assert got["valid"].sum() >= 3
+
+
+def test_config2_realistic_frame(lib, orc):
+    sc = synth.scene_realistic()
+    got = _frame_parity(lib, orc, sc, synth.params_for(2))
+    assert got["valid"][:32].sum() >= 20
