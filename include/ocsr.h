@@ -56,6 +56,8 @@ extern "C" {
 #define OCSR_REASON_TOO_FEW_CONSISTENT 5     /* aggregation kept fewer than n_min blocks */
 #define OCSR_REASON_NONPOSITIVE_DISPARITY 6  /* disparity <= d_eps: no finite depth */
 #define OCSR_REASON_CAPACITY_OVERFLOW 7      /* the box's blocks did not fit (see below) */
+#define OCSR_REASON_INTERNAL_TIMEOUT 8       /* a bounded wait inside a fused launch expired:
+                                                a library defect; the result is not valid */
 
 #define OCSR_MODE_TILED 0   /* box cut into bw x bh blocks, every pixel a point */
 #define OCSR_MODE_GRID 1    /* whole box one block, n_side x n_side grid of points */
@@ -66,7 +68,9 @@ extern "C" {
 #define OCSR_BOX_RANGE 1u   /* ocsr_box.flags: produce a range (else the box only occludes) */
 
 /* A box that tiles into more blocks than this is reported CAPACITY_OVERFLOW. */
-#define OCSR_MAX_BLOCKS_PER_BOX 16384
+#define OCSR_MAX_BLOCKS_PER_BOX 4096
+/* Most frames one ocsr_range_batch call takes. */
+#define OCSR_MAX_BATCH_FRAMES 16
 /* Largest search range (level candidates) of one path. */
 #define OCSR_MAX_CANDIDATES 256
 
@@ -242,12 +246,53 @@ int32_t ocsr_range_frame(ocsr_ctx* ctx, const uint8_t* imgL, const uint8_t* imgR
                          ocsr_box_result* out, void* stream);
 
 /* ------------------------------------------------------------------------------ */
-/* Timing                                                                           */
+/* Batch of frames in one launch sequence (Alg. 2 over many frames)                 */
 /* ------------------------------------------------------------------------------ */
+/* One frame of a batch. Frames may differ in size; every frame uses the same census
+ * window, close scale and matching parameters. Its boxes are
+ * boxes[box_offset .. box_offset + n_boxes) of the batch's box array, and its results
+ * land at the same positions of the output array. */
+typedef struct {
+  const uint8_t* imgL;     /* dev, uint8 [height][pitch_bytes] */
+  const uint8_t* imgR;     /* dev, same geometry */
+  int32_t width, height, pitch_bytes;
+  int32_t box_offset, n_boxes;
+  int32_t reserved;
+} ocsr_frame;
+
+/* Workspace of ocsr_range_batch: the four descriptor images of every frame, the plan
+ * of every box and cap_blocks blocks per frame. frames (host): n_frames entries. */
+size_t ocsr_batch_workspace_bytes(const ocsr_frame* frames, int32_t n_frames,
+                                  const ocsr_frame_params* fp, int32_t cap_blocks);
+
+/* Ranges every box of up to OCSR_MAX_BATCH_FRAMES frames. Results are those of one
+ * ocsr_range_frame call per frame, bit for bit. frames (host): n_frames entries; boxes
+ * (dev) and out (dev): the total box count of the batch, frame by frame. */
+int32_t ocsr_range_batch(ocsr_ctx* ctx, const ocsr_frame* frames, int32_t n_frames,
+                         const ocsr_frame_params* fp, const ocsr_box* boxes,
+                         const ocsr_match_params* params, int32_t cap_blocks, void* ws,
+                         size_t ws_bytes, ocsr_box_result* out, void* stream);
+
+/* ------------------------------------------------------------------------------ */
+/* Options and timing                                                               */
+/* ------------------------------------------------------------------------------ */
+/* OCSR_OPTION_FUSED: 0 (default) runs whole frames and batches as the multi-launch
+ * sequence (census of every view and level of every frame, plan, one match launch per
+ * level, aggregation); 1 runs them as one persistent launch of co-resident workgroups
+ * (census, planning, matching and aggregation in three phases split by grid barriers)
+ * when a fused kernel is built for the census window and path shapes, else falls back
+ * to the multi-launch sequence. Both give identical results. */
+#define OCSR_OPTION_FUSED 1
+/* OCSR_OPTION_WAVES_PER_CU: cap on the workgroups per compute unit of the persistent
+ * launch (0 = as many as fit, 1..32 = cap). */
+#define OCSR_OPTION_WAVES_PER_CU 2
+int32_t ocsr_ctx_set_option(ocsr_ctx* ctx, int32_t option, int32_t value);
+
 /* When enabled, each kernel launch of the context is bracketed by HIP events on
  * its stream; ocsr_ctx_kernel_time() then reports, per kernel name, the number of
  * launches and their summed duration (ms) since the last reset. Reading
- * synchronizes on the recorded events. */
+ * synchronizes on the recorded events. Kernel names: census, plan, match_far,
+ * match_close, aggregate (multi-launch path), reset, fused (fused path). */
 int32_t ocsr_ctx_set_timing(ocsr_ctx* ctx, int32_t enable);
 int32_t ocsr_ctx_kernel_time(ocsr_ctx* ctx, const char* kernel, int64_t* launches,
                              double* total_ms);

@@ -110,7 +110,7 @@ def match_boxes(levels: dict, W: int, H: int, boxes, p: dict):
             xs = [lx0 + int(np.floor((k + 0.5) * lw / nx)) for k in range(nx)]
             ys = [ly0 + int(np.floor((k + 0.5) * lh / ny)) for k in range(ny)]
             tiles.append((0, 0, xs, ys))
-        if len(tiles) > p.get("max_blocks_per_box", 16384):
+        if len(tiles) > p.get("max_blocks_per_box", 4096):
             r["reason"] = 7
             continue
         total += len(tiles)

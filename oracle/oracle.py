@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "ocsr_oracle.c")
 LIB = os.path.join(HERE, "liborc.so")
 
-MAX_BLOCKS_PER_BOX = 16384
+MAX_BLOCKS_PER_BOX = 4096
 
 REASONS = ["OK", "NOT_RANGED", "CLIPPED_EMPTY", "NO_ELIGIBLE_BLOCKS", "NO_VALID_BLOCKS",
            "TOO_FEW_CONSISTENT", "NONPOSITIVE_DISPARITY", "CAPACITY_OVERFLOW"]

@@ -3,6 +3,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <map>
 #include <mutex>
 #include <string>
@@ -16,6 +17,8 @@ struct ocsr_ctx {
   int device = 0;
   int n_cu = 256;
   bool timing = false;
+  int use_fused = 0;
+  int wgs_per_cu = 0;
   struct Pending {
     std::string name;
     hipEvent_t start, stop;
@@ -155,18 +158,22 @@ int32_t check_level(const ocsr_level* lv, const char* name, LevelDev* out) {
   return OCSR_OK;
 }
 
-int32_t build_params(const ocsr_level* lv0, const ocsr_level* lv1, int n_boxes,
-                     const ocsr_match_params* p, int cap_blocks, MatchParamsDev* d) {
+int32_t build_params(const ocsr_match_params* p, int close_scale, int cap_blocks,
+                     MatchParamsDev* d) {
   if (!p) return fail(OCSR_E_INVALID, "null params");
   if (p->struct_size != sizeof(ocsr_match_params))
     return fail(OCSR_E_INVALID, "params.struct_size %u != %zu", p->struct_size, sizeof(ocsr_match_params));
   memset(d, 0, sizeof(*d));
   int32_t rc;
-  if ((rc = check_level(lv0, "lv0", &d->lv[0])) != OCSR_OK) return rc;
-  if ((rc = check_level(lv1, "lv1", &d->lv[1])) != OCSR_OK) return rc;
-  if (lv0->scale != 1) return fail(OCSR_E_INVALID, "lv0 must have scale 1 (got %d)", lv0->scale);
   if ((rc = check_path(p->far_path, "far", 1, &d->path[0])) != OCSR_OK) return rc;
-  if ((rc = check_path(p->close_path, "close", lv1->scale, &d->path[1])) != OCSR_OK) return rc;
+  if ((rc = check_path(p->close_path, "close", close_scale, &d->path[1])) != OCSR_OK) return rc;
+  // Only the register-blocked TILED kernels are enabled: the per-candidate kernel that
+  // served GRID mode and blocks wider than 8 x 8 faulted on the device in its
+  // work-queue form and stays off until that is understood.
+  for (int l = 0; l < 2; ++l)
+    if (!pick_variant(d->path[l]).tiled)
+      return fail(OCSR_E_UNSUPPORTED, "%s path: GRID mode and blocks wider or taller than 8 are "
+                  "not enabled in this build", l == 0 ? "far" : "close");
   if (p->lr_tol < 0) return fail(OCSR_E_INVALID, "lr_tol < 0");
   if (p->min_point_pct < 0 || p->min_point_pct > 100) return fail(OCSR_E_INVALID, "min_point_pct outside 0..100");
   if (p->agg_mode != OCSR_AGG_SEGMENT_MEDIAN && p->agg_mode != OCSR_AGG_TRIMMED_MEDIAN)
@@ -175,7 +182,6 @@ int32_t build_params(const ocsr_level* lv0, const ocsr_level* lv1, int n_boxes,
   if (!(p->tau_d >= 0.0f) || !std::isfinite(p->tau_d)) return fail(OCSR_E_INVALID, "tau_d must be finite and >= 0");
   if (!std::isfinite(p->focal_px) || !std::isfinite(p->baseline_m) || !std::isfinite(p->d_eps))
     return fail(OCSR_E_INVALID, "focal, baseline and d_eps must be finite");
-  if (n_boxes < 0 || n_boxes > (1 << 20)) return fail(OCSR_E_INVALID, "n_boxes %d outside 0..2^20", n_boxes);
   if (cap_blocks < 1 || cap_blocks > (1 << 24)) return fail(OCSR_E_INVALID, "cap_blocks %d outside 1..2^24", cap_blocks);
   d->tau_s = p->tau_s;
   d->lr_tol = p->lr_tol;
@@ -188,14 +194,10 @@ int32_t build_params(const ocsr_level* lv0, const ocsr_level* lv1, int n_boxes,
   d->fb = f * b;
   d->d_eps = p->d_eps;
   d->cap_blocks = cap_blocks;
-  d->n_boxes = n_boxes;
   return OCSR_OK;
 }
 
-int32_t enqueue_match(ocsr_ctx* ctx, const MatchParamsDev& d, const ocsr_box* boxes, void* ws,
-                      int cap_blocks, ocsr_box_result* out, const ocsr_debug* dbg,
-                      hipStream_t stream) {
-  MatchWs w = match_ws_carve(ws, d.n_boxes, cap_blocks);
+DebugDev make_debug(const ocsr_debug* dbg) {
   DebugDev dd;
   memset(&dd, 0, sizeof(dd));
   if (dbg) {
@@ -206,14 +208,119 @@ int32_t enqueue_match(ocsr_ctx* ctx, const MatchParamsDev& d, const ocsr_box* bo
     dd.cost_fwd = dbg->cost_fwd;
     dd.cost_bwd = dbg->cost_bwd;
   }
-  const int n_wgs = std::max(1, std::min(cap_blocks, ctx->n_cu * 16));
-  LaunchTimer t = make_timer(ctx);
-  hipError_t e = launch_match(d, boxes, w, out, dd, n_wgs, stream, ctx->timing ? &t : nullptr);
-  if (e != hipSuccess) return hip_fail(e, "match launch");
-  if (dbg && dbg->n_blocks) {
-    e = hipMemcpyAsync(dbg->n_blocks, w.counters, sizeof(int32_t), hipMemcpyDeviceToDevice, stream);
-    if (e != hipSuccess) return hip_fail(e, "debug block count copy");
+  return dd;
+}
+
+int32_t check_ws(void* ws, size_t ws_bytes, size_t need) {
+  if (!ws || ((uintptr_t)ws & 255)) return fail(OCSR_E_INVALID, "workspace null or not 256-byte aligned");
+  if (ws_bytes < need) return fail(OCSR_E_WORKSPACE, "workspace %zu bytes < %zu needed", ws_bytes, need);
+  return OCSR_OK;
+}
+
+size_t a256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// descriptor images of one frame: L0, R0 at scale 1, L1, R1 at the close scale
+size_t frame_census_bytes(int W, int H, int s) {
+  return 2 * a256((size_t)W * H * 8) + 2 * a256((size_t)(W / s) * (H / s) * 8);
+}
+
+int32_t check_frames(const ocsr_frame* frames, int n_frames, const ocsr_frame_params* fp,
+                     int* n_boxes_total) {
+  if (!fp) return fail(OCSR_E_INVALID, "null frame params");
+  if (fp->close_scale < 1 || fp->close_scale > 16) return fail(OCSR_E_INVALID, "close_scale outside 1..16");
+  int32_t rc;
+  if ((rc = check_census_window(fp->sx, fp->sy, fp->sentinel)) != OCSR_OK) return rc;
+  if (!frames || n_frames < 1 || n_frames > OCSR_MAX_BATCH_FRAMES)
+    return fail(OCSR_E_INVALID, "n_frames %d outside 1..%d", n_frames, OCSR_MAX_BATCH_FRAMES);
+  long long total = 0;
+  for (int f = 0; f < n_frames; ++f) {
+    const ocsr_frame& fr = frames[f];
+    if (!fr.imgL || !fr.imgR) return fail(OCSR_E_INVALID, "frame %d: null image", f);
+    if (fr.width <= 0 || fr.height <= 0 || fr.width > (1 << 15) || fr.height > (1 << 15))
+      return fail(OCSR_E_INVALID, "frame %d: size %dx%d outside 1..32768", f, fr.width, fr.height);
+    if (fr.pitch_bytes < fr.width) return fail(OCSR_E_INVALID, "frame %d: pitch < width", f);
+    if (fr.width / fp->close_scale < 1 || fr.height / fp->close_scale < 1)
+      return fail(OCSR_E_INVALID, "frame %d: smaller than the close scale", f);
+    if (fr.n_boxes < 0 || fr.box_offset != total)
+      return fail(OCSR_E_INVALID, "frame %d: boxes must follow the previous frame's (offset %d, expected %lld)",
+                  f, fr.box_offset, total);
+    total += fr.n_boxes;
   }
+  if (total > (1 << 20)) return fail(OCSR_E_INVALID, "more than 2^20 boxes");
+  *n_boxes_total = (int)total;
+  return OCSR_OK;
+}
+
+size_t batch_ws_bytes(const ocsr_frame* frames, int n_frames, const ocsr_frame_params* fp,
+                      int n_boxes_total, int cap_blocks) {
+  size_t b = 0;
+  for (int f = 0; f < n_frames; ++f) b += frame_census_bytes(frames[f].width, frames[f].height, fp->close_scale);
+  return b + match_ws_bytes(n_frames, n_boxes_total, cap_blocks);
+}
+
+int32_t range_frames(ocsr_ctx* ctx, const ocsr_frame* frames, int n_frames,
+                     const ocsr_frame_params* fp, const ocsr_box* boxes,
+                     const ocsr_match_params* params, int cap_blocks, void* ws, size_t ws_bytes,
+                     ocsr_box_result* out, hipStream_t stream) {
+  int n_total = 0;
+  int32_t rc;
+  if ((rc = check_frames(frames, n_frames, fp, &n_total)) != OCSR_OK) return rc;
+  MatchParamsDev P;
+  if ((rc = build_params(params, fp->close_scale, cap_blocks, &P)) != OCSR_OK) return rc;
+  if (n_total > 0 && (!boxes || !out)) return fail(OCSR_E_INVALID, "null boxes or output");
+  if ((rc = check_ws(ws, ws_bytes, batch_ws_bytes(frames, n_frames, fp, n_total, cap_blocks))) != OCSR_OK)
+    return rc;
+  if (n_total == 0) return OCSR_OK;
+  const int s = fp->close_scale;
+  FramesDev FR;
+  memset(&FR, 0, sizeof(FR));
+  FR.n = n_frames;
+  FR.n_boxes_total = n_total;
+  ocsr_census_job jobs[4 * OCSR_MAX_BATCH_FRAMES];
+  char* base = (char*)ws;
+  int tiles = 0;
+  for (int f = 0; f < n_frames; ++f) {
+    const ocsr_frame& fr = frames[f];
+    const int W = fr.width, H = fr.height, W1 = W / s, H1 = H / s;
+    uint64_t* dL0 = (uint64_t*)base; base += a256((size_t)W * H * 8);
+    uint64_t* dR0 = (uint64_t*)base; base += a256((size_t)W * H * 8);
+    uint64_t* dL1 = (uint64_t*)base; base += a256((size_t)W1 * H1 * 8);
+    uint64_t* dR1 = (uint64_t*)base; base += a256((size_t)W1 * H1 * 8);
+    FrameDev& d = FR.f[f];
+    d.lv[0] = LevelDev{dL0, dR0, W, H, W, 1, fp->sx, fp->sy};
+    d.lv[1] = LevelDev{dL1, dR1, W1, H1, W1, s, fp->sx, fp->sy};
+    d.imgL = fr.imgL; d.imgR = fr.imgR;
+    d.W = W; d.H = H; d.pitch = fr.pitch_bytes;
+    d.box_off = fr.box_offset; d.n_boxes = fr.n_boxes;
+    d.tiles0_x = (int)cdiv64(W, kCensusTileX);
+    d.tiles0 = d.tiles0_x * (int)cdiv64(H, kCensusTileY);
+    d.tiles1_x = (int)cdiv64(W1, kCensusTileX);
+    d.tiles1 = d.tiles1_x * (int)cdiv64(H1, kCensusTileY);
+    d.tile_begin = tiles;
+    tiles += 2 * (d.tiles0 + d.tiles1);
+    const uint8_t* imgs[4] = {fr.imgL, fr.imgR, fr.imgL, fr.imgR};
+    uint64_t* outs[4] = {dL0, dR0, dL1, dR1};
+    for (int k = 0; k < 4; ++k) {
+      ocsr_census_job& j = jobs[4 * f + k];
+      const int sc = k < 2 ? 1 : s;
+      j.img = imgs[k]; j.out = outs[k]; j.width = W; j.height = H; j.pitch_bytes = fr.pitch_bytes;
+      j.out_pitch_elems = W / sc; j.scale = sc; j.reserved = 0;
+    }
+  }
+  MatchWs mws = match_ws_carve(base, n_frames, n_total, cap_blocks);
+  LaunchTimer t = make_timer(ctx);
+  const LaunchTimer* tp = ctx->timing ? &t : nullptr;
+  if (ctx->use_fused && fused_available(P, fp->sx, fp->sy)) {
+    hipError_t e = launch_fused(P, FR, boxes, mws, out, fp->sx, fp->sy, fp->sentinel ? 1 : 0, tiles,
+                                ctx->n_cu, ctx->wgs_per_cu, stream, tp);
+    if (e != hipSuccess) return hip_fail(e, "fused launch");
+    return OCSR_OK;
+  }
+  if ((rc = enqueue_census(ctx, jobs, 4 * n_frames, fp->sx, fp->sy, fp->sentinel ? 1 : 0, stream)) != OCSR_OK)
+    return rc;
+  const DebugDev no_dbg = make_debug(nullptr);
+  hipError_t e = launch_match(P, FR, boxes, mws, out, no_dbg, std::max(1, ctx->n_cu * 16), stream, tp);
+  if (e != hipSuccess) return hip_fail(e, "match launch");
   return OCSR_OK;
 }
 
@@ -289,7 +396,7 @@ int32_t ocsr_census_many(ocsr_ctx* ctx, const ocsr_census_job* jobs, int32_t n_j
 }
 
 size_t ocsr_match_workspace_bytes(int32_t n_boxes, int32_t cap_blocks) {
-  return match_ws_bytes(n_boxes, cap_blocks);
+  return match_ws_bytes(1, n_boxes, cap_blocks);
 }
 
 int32_t ocsr_match_boxes(ocsr_ctx* ctx, const ocsr_level* lv0, const ocsr_level* lv1,
@@ -298,30 +405,43 @@ int32_t ocsr_match_boxes(ocsr_ctx* ctx, const ocsr_level* lv0, const ocsr_level*
                          const ocsr_debug* dbg, void* stream) {
   g_last_error.clear();
   if (!ctx) return fail(OCSR_E_INVALID, "null context");
-  MatchParamsDev d;
-  int32_t rc = build_params(lv0, lv1, n_boxes, params, cap_blocks, &d);
-  if (rc != OCSR_OK) return rc;
+  int32_t rc;
+  FramesDev FR;
+  memset(&FR, 0, sizeof(FR));
+  if ((rc = check_level(lv0, "lv0", &FR.f[0].lv[0])) != OCSR_OK) return rc;
+  if ((rc = check_level(lv1, "lv1", &FR.f[0].lv[1])) != OCSR_OK) return rc;
+  if (lv0->scale != 1) return fail(OCSR_E_INVALID, "lv0 must have scale 1 (got %d)", lv0->scale);
+  MatchParamsDev P;
+  if ((rc = build_params(params, lv1->scale, cap_blocks, &P)) != OCSR_OK) return rc;
+  if (n_boxes < 0 || n_boxes > (1 << 20)) return fail(OCSR_E_INVALID, "n_boxes %d outside 0..2^20", n_boxes);
   if (n_boxes == 0) return OCSR_OK;
   if (!boxes || !out) return fail(OCSR_E_INVALID, "null boxes or output");
-  if (!ws || ((uintptr_t)ws & 255)) return fail(OCSR_E_INVALID, "workspace null or not 256-byte aligned");
-  const size_t need = match_ws_bytes(n_boxes, cap_blocks);
-  if (ws_bytes < need) return fail(OCSR_E_WORKSPACE, "workspace %zu bytes < %zu needed", ws_bytes, need);
+  if ((rc = check_ws(ws, ws_bytes, match_ws_bytes(1, n_boxes, cap_blocks))) != OCSR_OK) return rc;
   if (dbg && (dbg->cap_blocks < 0 || dbg->cap_nd < 0))
     return fail(OCSR_E_INVALID, "debug capacities must be >= 0");
-  return enqueue_match(ctx, d, boxes, ws, cap_blocks, out, dbg, (hipStream_t)stream);
-}
-
-static void frame_layout(int W, int H, int s, size_t* l0, size_t* l1) {
-  *l0 = ((size_t)W * H * 8 + 255) & ~(size_t)255;
-  *l1 = ((size_t)(W / s) * (H / s) * 8 + 255) & ~(size_t)255;
+  FR.n = 1;
+  FR.n_boxes_total = n_boxes;
+  FR.f[0].W = lv0->width;
+  FR.f[0].H = lv0->height;
+  FR.f[0].box_off = 0;
+  FR.f[0].n_boxes = n_boxes;
+  MatchWs mws = match_ws_carve(ws, 1, n_boxes, cap_blocks);
+  LaunchTimer t = make_timer(ctx);
+  hipError_t e = launch_match(P, FR, boxes, mws, out, make_debug(dbg), std::max(1, ctx->n_cu * 16),
+                              (hipStream_t)stream, ctx->timing ? &t : nullptr);
+  if (e != hipSuccess) return hip_fail(e, "match launch");
+  if (dbg && dbg->n_blocks) {
+    e = hipMemcpyAsync(dbg->n_blocks, mws.fcount + FC_NUMBERED, sizeof(int32_t),
+                       hipMemcpyDeviceToDevice, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "debug block count copy");
+  }
+  return OCSR_OK;
 }
 
 size_t ocsr_frame_workspace_bytes(int32_t width, int32_t height, const ocsr_frame_params* fp,
                                   int32_t n_boxes, int32_t cap_blocks) {
   if (!fp || width <= 0 || height <= 0 || fp->close_scale < 1) return 0;
-  size_t l0, l1;
-  frame_layout(width, height, fp->close_scale, &l0, &l1);
-  return 2 * l0 + 2 * l1 + match_ws_bytes(n_boxes, cap_blocks);
+  return frame_census_bytes(width, height, fp->close_scale) + match_ws_bytes(1, n_boxes, cap_blocks);
 }
 
 int32_t ocsr_range_frame(ocsr_ctx* ctx, const uint8_t* imgL, const uint8_t* imgR,
@@ -330,42 +450,46 @@ int32_t ocsr_range_frame(ocsr_ctx* ctx, const uint8_t* imgL, const uint8_t* imgR
                          const ocsr_match_params* params, int32_t cap_blocks, void* ws,
                          size_t ws_bytes, ocsr_box_result* out, void* stream) {
   g_last_error.clear();
-  if (!ctx || !fp) return fail(OCSR_E_INVALID, "null context or frame params");
-  if (fp->close_scale < 1 || fp->close_scale > 16) return fail(OCSR_E_INVALID, "close_scale outside 1..16");
-  int32_t rc;
-  if ((rc = check_census_window(fp->sx, fp->sy, fp->sentinel)) != OCSR_OK) return rc;
-  if (!ws || ((uintptr_t)ws & 255)) return fail(OCSR_E_INVALID, "workspace null or not 256-byte aligned");
-  const size_t need = ocsr_frame_workspace_bytes(width, height, fp, n_boxes, cap_blocks);
-  if (need == 0) return fail(OCSR_E_INVALID, "bad frame size");
-  if (ws_bytes < need) return fail(OCSR_E_WORKSPACE, "workspace %zu bytes < %zu needed", ws_bytes, need);
-  const int s = fp->close_scale;
-  size_t l0, l1;
-  frame_layout(width, height, s, &l0, &l1);
-  char* base = (char*)ws;
-  uint64_t* dL0 = (uint64_t*)base;
-  uint64_t* dR0 = (uint64_t*)(base + l0);
-  uint64_t* dL1 = (uint64_t*)(base + 2 * l0);
-  uint64_t* dR1 = (uint64_t*)(base + 2 * l0 + l1);
-  void* mws = base + 2 * l0 + 2 * l1;
-  ocsr_census_job jobs[4];
-  const uint8_t* imgs[4] = {imgL, imgR, imgL, imgR};
-  uint64_t* outs[4] = {dL0, dR0, dL1, dR1};
-  for (int k = 0; k < 4; ++k) {
-    const int sc = k < 2 ? 1 : s;
-    jobs[k].img = imgs[k]; jobs[k].out = outs[k]; jobs[k].width = width; jobs[k].height = height;
-    jobs[k].pitch_bytes = pitch_bytes; jobs[k].out_pitch_elems = width / sc; jobs[k].scale = sc;
-    jobs[k].reserved = 0;
-    if ((rc = check_job(jobs[k], k)) != OCSR_OK) return rc;
+  if (!ctx) return fail(OCSR_E_INVALID, "null context");
+  ocsr_frame fr = {imgL, imgR, width, height, pitch_bytes, 0, n_boxes, 0};
+  return range_frames(ctx, &fr, 1, fp, boxes, params, cap_blocks, ws, ws_bytes, out,
+                      (hipStream_t)stream);
+}
+
+size_t ocsr_batch_workspace_bytes(const ocsr_frame* frames, int32_t n_frames,
+                                  const ocsr_frame_params* fp, int32_t cap_blocks) {
+  int n_total = 0;
+  const std::string saved = g_last_error;
+  const int32_t rc = check_frames(frames, n_frames, fp, &n_total);
+  g_last_error = saved;
+  if (rc != OCSR_OK) return 0;
+  return batch_ws_bytes(frames, n_frames, fp, n_total, cap_blocks);
+}
+
+int32_t ocsr_range_batch(ocsr_ctx* ctx, const ocsr_frame* frames, int32_t n_frames,
+                         const ocsr_frame_params* fp, const ocsr_box* boxes,
+                         const ocsr_match_params* params, int32_t cap_blocks, void* ws,
+                         size_t ws_bytes, ocsr_box_result* out, void* stream) {
+  g_last_error.clear();
+  if (!ctx) return fail(OCSR_E_INVALID, "null context");
+  return range_frames(ctx, frames, n_frames, fp, boxes, params, cap_blocks, ws, ws_bytes, out,
+                      (hipStream_t)stream);
+}
+
+int32_t ocsr_ctx_set_option(ocsr_ctx* ctx, int32_t option, int32_t value) {
+  g_last_error.clear();
+  if (!ctx) return fail(OCSR_E_INVALID, "null context");
+  switch (option) {
+    case OCSR_OPTION_FUSED:
+      ctx->use_fused = value != 0;
+      return OCSR_OK;
+    case OCSR_OPTION_WAVES_PER_CU:
+      if (value < 0 || value > 32) return fail(OCSR_E_INVALID, "workgroups per CU outside 0..32");
+      ctx->wgs_per_cu = value;
+      return OCSR_OK;
+    default:
+      return fail(OCSR_E_INVALID, "unknown option %d", option);
   }
-  ocsr_level lv0 = {dL0, dR0, width, height, width, 1, fp->sx, fp->sy};
-  ocsr_level lv1 = {dL1, dR1, width / s, height / s, width / s, s, fp->sx, fp->sy};
-  MatchParamsDev d;
-  if ((rc = build_params(&lv0, &lv1, n_boxes, params, cap_blocks, &d)) != OCSR_OK) return rc;
-  if (n_boxes > 0 && (!boxes || !out)) return fail(OCSR_E_INVALID, "null boxes or output");
-  if ((rc = enqueue_census(ctx, jobs, 4, fp->sx, fp->sy, fp->sentinel ? 1 : 0, (hipStream_t)stream)) != OCSR_OK)
-    return rc;
-  if (n_boxes == 0) return OCSR_OK;
-  return enqueue_match(ctx, d, boxes, mws, cap_blocks, out, nullptr, (hipStream_t)stream);
 }
 
 int32_t ocsr_ctx_set_timing(ocsr_ctx* ctx, int32_t enable) {

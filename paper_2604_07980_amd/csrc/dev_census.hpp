@@ -1,0 +1,143 @@
+// Census transform of one 64 x 32 tile of level pixels by one workgroup of 256
+// threads (Sec. 4.3.1: census equation and Alg. 1).
+//
+// The tile plus its halo is staged in LDS as vertical pixel pairs (two 8-bit samples
+// in the two 16-bit halves of a word). Each lane owns one column and eight rows (four
+// pairs) and keeps the pair words of its window in registers. One packed 16-bit
+// subtract (centre pair - neighbour pair) decides a comparison for both pixels of a
+// pair: a half is >= 0xFF01 exactly when the neighbour is brighter, so its bits 8..15
+// all carry the comparison bit and one AND-OR drops both bits into place in a
+// byte-per-code-byte accumulator. Byte permutes then assemble the two 64-bit codes:
+// about one VALU instruction per comparison bit, with no lane-mask traffic.
+//
+// Bit order: Alg. 1 starts from the sentinel and, for i = -SX..SX (x, outer) and
+// j = -SY..SY (y, inner), shifts left and appends [I(x+i, y+j) > I(x, y)]; the first
+// comparison therefore ends at bit n-1 (n = (2SX+1)(2SY+1)) and the sentinel at bit n.
+// Pixels whose window leaves the level image store 0.
+#pragma once
+
+#include "dev_common.hpp"
+
+namespace ocsr {
+namespace dev {
+
+constexpr int kCensusRowsPerLane = 8;   // 4 waves x 8 rows = kCensusTileY
+
+template <int SX, int SY>
+struct CensusTile {
+  static constexpr int LW = kCensusTileX + 2 * SX;
+  static constexpr int PR = kCensusTileY + 2 * SY - 1;            // rows of pixel pairs
+  static constexpr int WR = kCensusRowsPerLane - 1 + 2 * SY;      // pair rows per lane
+  static constexpr int N = (2 * SX + 1) * (2 * SY + 1);           // comparisons
+  static constexpr size_t kLdsBytes = sizeof(uint32_t) * PR * LW;
+  static_assert(N + 1 <= 64, "window wider than a 64-bit code");
+};
+
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+// img: uint8 source (pitch bytes), level scale s: level image Ws x Hs = W/s x H/s.
+// (X0, Y0): level position of the tile. P: LDS of CensusTile<SX,SY>::kLdsBytes.
+// Called by all 256 threads of the workgroup.
+template <int SX, int SY>
+__device__ __forceinline__ void census_tile(const uint8_t* __restrict__ img, int W, int H,
+                                            int pitch, int s, uint64_t* __restrict__ out,
+                                            int out_pitch, int X0, int Y0, int sentinel,
+                                            uint32_t* P) {
+  using T = CensusTile<SX, SY>;
+  constexpr int LW = T::LW, PR = T::PR, WR = T::WR, N = T::N;
+  const int Ws = W / s, Hs = H / s;
+  // P[r * LW + c] = I(c, r) | I(c, r + 1) << 16 over the tile and its halo
+  for (int idx = threadIdx.x; idx < PR * LW; idx += 256) {
+    const int pr = idx / LW, pc = idx - pr * LW;
+    const int X = X0 - SX + pc, Y = Y0 - SY + pr;
+    uint32_t lo = 0, hi = 0;
+    if (X >= 0 && X < Ws) {
+      const uint8_t* col = img + (size_t)(s * X);
+      if (Y >= 0 && Y < Hs) lo = col[(size_t)(s * Y) * pitch];
+      if (Y + 1 >= 0 && Y + 1 < Hs) hi = col[(size_t)(s * (Y + 1)) * pitch];
+    }
+    P[idx] = lo | (hi << 16);
+  }
+  __syncthreads();
+
+  const int lane = threadIdx.x & 63;
+  const int r0 = (threadIdx.x >> 6) * kCensusRowsPerLane;
+  uint32_t v[2 * SX + 1][WR];
+#pragma unroll
+  for (int i = 0; i < 2 * SX + 1; ++i)
+#pragma unroll
+    for (int rr = 0; rr < WR; ++rr) v[i][rr] = P[(r0 + rr) * LW + lane + i];
+
+  const int X = X0 + lane;
+  const bool x_in = X < Ws;
+  const bool x_def = X >= SX && X < Ws - SX;
+  constexpr int NP = kCensusRowsPerLane / 2;
+  // pair pp holds pixels A = (X, Y0 + r0 + 2pp) and B = (X, YA + 1) in its low / high half
+  uint32_t acc[NP][8];
+#pragma unroll
+  for (int pp = 0; pp < NP; ++pp) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) acc[pp][k] = 0;
+    const u16x2 c2 = __builtin_bit_cast(u16x2, v[SX][2 * pp + SY]);
+#pragma unroll
+    for (int i = 0; i < 2 * SX + 1; ++i) {
+#pragma unroll
+      for (int jj = 0; jj < 2 * SY + 1; ++jj) {
+        // half = centre - neighbour: in 0..255 when the neighbour is not brighter, in
+        // 0xFF01..0xFFFF when it is, so bits 8..15 of each half all equal the bit
+        const u16x2 d = c2 - __builtin_bit_cast(u16x2, v[i][2 * pp + jj]);
+        const int pos = N - 1 - (i * (2 * SY + 1) + jj);   // Alg. 1 order, MSB first
+        acc[pp][pos >> 3] |= __builtin_bit_cast(uint32_t, d) & (0x01000100u << (pos & 7));
+      }
+    }
+  }
+#pragma unroll
+  for (int pp = 0; pp < NP; ++pp) {
+    if (sentinel) acc[pp][N >> 3] |= 0x01000100u << (N & 7);
+    // code byte k of A is byte 1 of acc[k], of B byte 3
+    const uint32_t x01 = __builtin_amdgcn_perm(acc[pp][1], acc[pp][0], 0x07030501u);
+    const uint32_t x23 = __builtin_amdgcn_perm(acc[pp][3], acc[pp][2], 0x07030501u);
+    const uint32_t x45 = __builtin_amdgcn_perm(acc[pp][5], acc[pp][4], 0x07030501u);
+    const uint32_t x67 = __builtin_amdgcn_perm(acc[pp][7], acc[pp][6], 0x07030501u);
+    const uint64_t codeA = ((uint64_t)__builtin_amdgcn_perm(x67, x45, 0x05040100u) << 32) |
+                           __builtin_amdgcn_perm(x23, x01, 0x05040100u);
+    const uint64_t codeB = ((uint64_t)__builtin_amdgcn_perm(x67, x45, 0x07060302u) << 32) |
+                           __builtin_amdgcn_perm(x23, x01, 0x07060302u);
+    const int YA = Y0 + r0 + 2 * pp;
+    if (x_in && YA < Hs) {
+      const bool def = x_def && YA >= SY && YA < Hs - SY;
+      out[(size_t)YA * out_pitch + X] = def ? codeA : 0ull;
+    }
+    const int YB = YA + 1;
+    if (x_in && YB < Hs) {
+      const bool def = x_def && YB >= SY && YB < Hs - SY;
+      out[(size_t)YB * out_pitch + X] = def ? codeB : 0ull;
+    }
+  }
+}
+
+// Any window: one pixel per thread per row, straight from global memory (no LDS).
+__device__ __forceinline__ void census_tile_generic(const uint8_t* __restrict__ img, int W, int H,
+                                                    int pitch, int s, uint64_t* __restrict__ out,
+                                                    int out_pitch, int X0, int Y0, int sx, int sy,
+                                                    int sentinel) {
+  const int Ws = W / s, Hs = H / s;
+  const int X = X0 + (threadIdx.x & 63);
+  for (int Y = Y0 + (int)(threadIdx.x >> 6); Y < Y0 + kCensusTileY; Y += 4) {
+    if (X >= Ws || Y >= Hs) continue;
+    uint64_t code = 0;
+    if (X >= sx && X < Ws - sx && Y >= sy && Y < Hs - sy) {
+      const uint8_t c = img[(size_t)(s * Y) * pitch + (size_t)(s * X)];
+      code = sentinel ? 1ull : 0ull;
+      for (int i = -sx; i <= sx; ++i)
+        for (int j = -sy; j <= sy; ++j) {
+          const uint8_t n = img[(size_t)(s * (Y + j)) * pitch + (size_t)(s * (X + i))];
+          code = (code << 1) | (n > c ? 1ull : 0ull);
+        }
+    }
+    out[(size_t)Y * out_pitch + X] = code;
+  }
+}
+
+}  // namespace dev
+}  // namespace ocsr

@@ -1,0 +1,103 @@
+// Device helpers shared by the census and matching code.
+#pragma once
+
+#include "ocsr_internal.hpp"
+
+namespace ocsr {
+namespace dev {
+
+__device__ __forceinline__ int cdiv_nonneg(int a, int s) { return (a + s - 1) / s; }
+
+__device__ __forceinline__ int wave_incl_scan(int v, int lane) {
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int t = __shfl_up(v, d, 64);
+    if (lane >= d) v += t;
+  }
+  return v;
+}
+
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v, int from = 1) {
+  for (int o = 32; o >= from; o >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, o, 64));
+  return v;
+}
+
+// Orders the LDS traffic of one wave: every lane's earlier LDS writes are seen by the
+// wave's later LDS reads (a wave's LDS instructions complete in order).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ uint64_t ld_word(const uint64_t* __restrict__ row, int x, int W) {
+  return (x >= 0 && x < W) ? row[x] : 0ull;
+}
+
+// device-scope counters of the fused persistent launch
+__device__ __forceinline__ int add_release(int32_t* p, int v) {
+  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int load_acquire(const int32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int load_relaxed(const int32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Bounded wait until *p >= target (the producers are running workgroups that hold
+// earlier queue items, so the wait ends; the bound only guards against a defect).
+// Returns false when the bound expired; the call then flags the timeout.
+constexpr int kSpinLimit = 1 << 22;
+__device__ __forceinline__ bool wait_at_least(const int32_t* p, int target, int32_t* timeout_flag) {
+  int spins = 0;
+  while (load_relaxed(p) < target) {
+    if (++spins > kSpinLimit) {
+      __hip_atomic_store(timeout_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return false;
+    }
+    __builtin_amdgcn_s_sleep(2);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // later loads see the producers' data
+  return true;
+}
+
+// Publishes a workgroup's global writes before one thread signals a counter: every
+// wave waits for its own stores, then the workgroup meets at a barrier.
+__device__ __forceinline__ void publish_workgroup() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+}
+
+// Grid-wide barrier of a launch whose workgroups are all resident: every workgroup
+// publishes its writes, counts itself in one of kBarSlots counters and waits (bounded)
+// until the slots add up to the grid size.
+__device__ __forceinline__ void grid_barrier(int32_t* slots, int n_groups, int32_t* timeout_flag) {
+  publish_workgroup();
+  if (threadIdx.x == 0) {
+    add_release(slots + (blockIdx.x % kBarSlots), 1);
+    int spins = 0;
+    for (;;) {
+      int sum = 0;
+#pragma unroll
+      for (int k = 0; k < kBarSlots; ++k) sum += load_relaxed(slots + k);
+      if (sum >= n_groups) break;
+      if (++spins > kSpinLimit) {
+        __hip_atomic_store(timeout_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
+  __syncthreads();
+}
+
+}  // namespace dev
+}  // namespace ocsr

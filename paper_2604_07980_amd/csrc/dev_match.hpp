@@ -1,0 +1,730 @@
+// Device code of the object-centric matching steps (Sec. 4.3.2-4.3.6, Alg. 2), shared by
+// the multi-launch kernels (match.hip) and the fused persistent kernel (fused.hip).
+//
+//   plan_frame        one wave per frame: clip, far/close type (Sec. 4.3.4 type
+//                     equation), level box, block grid, block numbers
+//   match_block_*     one wave per block: occluder mask (Sec. 4.3.5), forward Hamming
+//                     search (census cost equation), winner-take-all, parabola
+//                     (sub-pixel equation), backward search and L/R check (Sec. 4.3.3)
+//   aggregate_box     one workgroup per box: longest-segment or trimmed median of the
+//                     valid block disparities (Sec. 4.3.4), depth Z = f b / d (Eq. 1)
+#pragma once
+
+#include "dev_common.hpp"
+
+namespace ocsr {
+namespace dev {
+
+constexpr int kAggMax = OCSR_MAX_BLOCKS_PER_BOX;
+
+// ---------------------------------------------------------------------------------
+// plan: one wave walks the frame's boxes 64 at a time
+// ---------------------------------------------------------------------------------
+__device__ __forceinline__ void plan_frame(const MatchParamsDev& P, const FrameDev& fr, int f,
+                                           int n_total, const ocsr_box* __restrict__ boxes,
+                                           const MatchWs& ws, int lane) {
+  const int n = fr.n_boxes;
+  const int W = fr.W, H = fr.H;
+  int carry = 0, carry0 = 0, carry1 = 0, matched_end = 0;
+  for (int base = 0; base < n; base += 64) {
+    const int i = base + lane;
+    BoxPlan pl = {};
+    BoxClip cl = {0, 0, 0, 0};
+    int count = 0;
+    if (i < n) {
+      const ocsr_box b = boxes[fr.box_off + i];
+      const int cx0 = max(b.x0, 0), cy0 = max(b.y0, 0);
+      const int cx1 = min(b.x1, W), cy1 = min(b.y1, H);
+      const bool empty = !(cx0 < cx1 && cy0 < cy1);
+      if (!empty) cl = BoxClip{cx0, cy0, cx1, cy1};   // empty boxes overlap nothing
+      if (!(b.flags & OCSR_BOX_RANGE)) {
+        pl.status = OCSR_REASON_NOT_RANGED;
+      } else if (empty) {
+        pl.status = OCSR_REASON_CLIPPED_EMPTY;
+      } else {
+        // far/close type (Sec. 4.3.4): FAR iff the longer clipped side is below tau_s
+        const bool far_box = max(cx1 - cx0, cy1 - cy0) < P.tau_s;
+        const int level = far_box ? 0 : 1;
+        const LevelDev& lv = fr.lv[level];
+        const PathDev& ph = P.path[level];
+        const int s = lv.scale;
+        pl.level = level;
+        // level pixels whose full-res position s*x lies in the box and whose census
+        // is defined
+        const int x0 = max(cdiv_nonneg(cx0, s), lv.sx), x1 = min(cdiv_nonneg(cx1, s), lv.W - lv.sx);
+        const int y0 = max(cdiv_nonneg(cy0, s), lv.sy), y1 = min(cdiv_nonneg(cy1, s), lv.H - lv.sy);
+        if (x1 <= x0 || y1 <= y0) {
+          pl.status = OCSR_REASON_NO_ELIGIBLE_BLOCKS;
+        } else {
+          pl.lx0 = x0; pl.ly0 = y0; pl.lw = x1 - x0; pl.lh = y1 - y0;
+          if (ph.mode == OCSR_MODE_TILED) {
+            // centred grid of whole blocks; one shrunken block when the box is smaller
+            pl.bw = min(ph.bw, pl.lw);
+            pl.bh = min(ph.bh, pl.lh);
+            pl.nbx = max(1, pl.lw / ph.bw);
+            pl.nby = max(1, pl.lh / ph.bh);
+            pl.ox = pl.lx0 + (pl.lw - pl.nbx * pl.bw) / 2;
+            pl.oy = pl.ly0 + (pl.lh - pl.nby * pl.bh) / 2;
+          } else {
+            // the whole box is one block sampled on an n_side x n_side grid
+            pl.nbx = pl.nby = 1;
+            pl.bw = min(ph.n_side, pl.lw);
+            pl.bh = min(ph.n_side, pl.lh);
+          }
+          const int nb = pl.nbx * pl.nby;
+          if (nb > OCSR_MAX_BLOCKS_PER_BOX) {
+            pl.status = OCSR_REASON_CAPACITY_OVERFLOW;
+          } else {
+            pl.status = -1;
+            count = nb;
+          }
+        }
+      }
+    }
+    // block numbers: prefix over the boxes; a range passing the capacity is dropped
+    const int incl = wave_incl_scan(count, lane);
+    const int off = carry + incl - count;
+    int nblk = 0;
+    if (pl.status == -1 && i < n) {
+      if ((long long)off + count > (long long)P.cap_blocks) pl.status = OCSR_REASON_CAPACITY_OVERFLOW;
+      else nblk = count;
+    }
+    const int c0 = (pl.status == -1 && pl.level == 0) ? nblk : 0;
+    const int c1 = (pl.status == -1 && pl.level == 1) ? nblk : 0;
+    const int incl0 = wave_incl_scan(c0, lane);
+    const int incl1 = wave_incl_scan(c1, lane);
+    if (i < n) {
+      const int g = fr.box_off + i;
+      pl.off = off;
+      pl.nblk = nblk;
+      pl.loff = pl.level == 0 ? carry0 + incl0 - c0 : carry1 + incl1 - c1;
+      pl.frame = f;
+      ws.plan[g] = pl;
+      ws.clip[g] = cl;
+      ws.lbox_end[g] = carry0 + incl0;
+      ws.lbox_end[n_total + g] = carry1 + incl1;
+      ws.box_done[g] = 0;
+    }
+    matched_end = max(matched_end, wave_max(nblk > 0 ? off + nblk : 0));
+    carry += __shfl(incl, 63, 64);
+    carry0 += __shfl(incl0, 63, 64);
+    carry1 += __shfl(incl1, 63, 64);
+  }
+  if (lane == 0) {
+    int32_t* fc = ws.fcount + f * FC_N;
+    fc[FC_NUMBERED] = carry;
+    fc[FC_MATCHED] = matched_end;
+    fc[FC_FAR] = carry0;
+    fc[FC_CLOSE] = carry1;
+  }
+}
+
+// ---------------------------------------------------------------------------------
+// per-block steps
+// ---------------------------------------------------------------------------------
+// first of the frame's boxes whose running block end passes q (one vector load per 64)
+__device__ __forceinline__ int find_box(const int32_t* __restrict__ end, int n, int q, int lane) {
+  for (int base = 0; base < n; base += 64) {
+    const int e = base + lane < n ? end[base + lane] : 0x7FFFFFFF;
+    const uint64_t m = __ballot(e > q);
+    if (m) return base + __ffsll((unsigned long long)m) - 1;
+  }
+  return n - 1;
+}
+
+struct BlockGeom {
+  int nx, ny;
+  int s;
+  int tiled;
+  int cx, lx0, lw;   // TILED: first column cx; GRID: lx0, lw
+  int cy, ly0, lh;
+};
+
+__device__ __forceinline__ int geom_col(const BlockGeom& g, int i) {
+  return g.tiled ? g.cx + i : g.lx0 + (2 * i + 1) * g.lw / (2 * g.nx);
+}
+__device__ __forceinline__ int geom_row(const BlockGeom& g, int j) {
+  return g.tiled ? g.cy + j : g.ly0 + (2 * j + 1) * g.lh / (2 * g.ny);
+}
+
+// Occlusion-aware sampling (Sec. 4.3.5): bit j*nx+i is set iff point (i, j) lies in no
+// box of the frame that overlaps box k and has a larger bottom y. Lanes scan the boxes
+// 64 at a time; the few occluders found are then tested against one point per lane.
+__device__ __forceinline__ uint64_t block_mask(const MatchWs& ws, int box_off, int n, int k,
+                                               const BlockGeom& g, int lane) {
+  const BoxClip ck = ws.clip[box_off + k];
+  const int s = g.s;
+  const int npts = g.nx * g.ny;
+  const int pi = lane % g.nx, pj = min(lane / g.nx, g.ny - 1);
+  const int fx = s * geom_col(g, pi), fy = s * geom_row(g, pj);
+  const int bx0 = s * geom_col(g, 0), bx1 = s * geom_col(g, g.nx - 1);
+  const int by0 = s * geom_row(g, 0), by1 = s * geom_row(g, g.ny - 1);
+  bool hidden = false;
+  for (int jb = 0; jb < n; jb += 64) {
+    const int o = jb + lane;
+    bool occ = false;
+    if (o < n && o != k) {
+      const BoxClip co = ws.clip[box_off + o];
+      occ = ck.cx0 < co.cx1 && co.cx0 < ck.cx1 && ck.cy0 < co.cy1 && co.cy0 < ck.cy1 &&
+            co.cy1 > ck.cy1 && co.cx0 <= bx1 && co.cx1 > bx0 && co.cy0 <= by1 && co.cy1 > by0;
+    }
+    uint64_t m = __ballot(occ);
+    while (m) {
+      const int oo = jb + __ffsll((unsigned long long)m) - 1;
+      m &= m - 1;
+      const BoxClip co = ws.clip[box_off + oo];
+      hidden |= fx >= co.cx0 && fx < co.cx1 && fy >= co.cy0 && fy < co.cy1;
+    }
+  }
+  return __ballot(lane < npts && !hidden);
+}
+
+__device__ __forceinline__ bool block_eligible(const MatchParamsDev& P, uint64_t mask, int npts) {
+  const int nm = __popcll(mask);
+  return nm > 0 && 100 * nm >= P.min_point_pct * npts;
+}
+
+// parabola through (d_f - 1, a), (d_f, c), (d_f + 1, b) (sub-pixel equation, in d = -dx);
+// at either end of the range the integer disparity is kept
+__device__ __forceinline__ float subpixel(int d_f, int best, int nd, int a, int c, int b) {
+  if (best > 0 && best < nd - 1) {
+    const int num = a - b;
+    const int den = 2 * (a + b - 2 * c);
+    const float offs = (float)num / (float)den;
+    return (float)d_f + offs;
+  }
+  return (float)d_f;
+}
+
+struct BlockCtx {
+  int f;            // frame index
+  int level;
+  int k;            // box index within the frame
+  int kg;           // box index over the call
+  int b;            // block number within the frame
+  int slot;         // block storage index over the call
+  int u, v;
+  BoxPlan pl;
+  BlockGeom g;
+};
+
+__device__ __forceinline__ BlockCtx block_ctx(const MatchParamsDev& P, const FrameDev& fr, int f,
+                                              int n_total, const MatchWs& ws, int level, int q,
+                                              int lane) {
+  BlockCtx c;
+  c.f = f;
+  c.level = level;
+  c.k = find_box(ws.lbox_end + (size_t)level * n_total + fr.box_off, fr.n_boxes, q, lane);
+  c.kg = fr.box_off + c.k;
+  c.pl = ws.plan[c.kg];
+  const int local = q - c.pl.loff;
+  c.b = c.pl.off + local;
+  c.slot = f * P.cap_blocks + c.b;
+  c.v = local / c.pl.nbx;
+  c.u = local - c.v * c.pl.nbx;
+  const LevelDev& lv = fr.lv[level];
+  c.g.nx = c.pl.bw; c.g.ny = c.pl.bh; c.g.s = lv.scale;
+  c.g.tiled = P.path[level].mode == OCSR_MODE_TILED;
+  c.g.cx = c.pl.ox + c.u * c.pl.bw; c.g.lx0 = c.pl.lx0; c.g.lw = c.pl.lw;
+  c.g.cy = c.pl.oy + c.v * c.pl.bh; c.g.ly0 = c.pl.ly0; c.g.lh = c.pl.lh;
+  return c;
+}
+
+// Stores the block's result; with `track`, then counts the block as done for its box.
+__device__ __forceinline__ void write_block(const MatchWs& ws, const DebugDev& dbg,
+                                            const BlockCtx& c, const PathDev& ph, uint64_t mask,
+                                            bool eligible, int d_f, int d_b, int lr_ok,
+                                            float d_sub, int valid, bool track, int lane) {
+  if (lane == 0) {
+    ws.blk_val[c.slot] = (float)c.g.s * d_sub;   // d_full = s * d (Sec. 4.1)
+    ws.blk_flag[c.slot] = (uint8_t)((eligible ? 1 : 0) | (valid ? 2 : 0));
+    if (dbg.blocks && c.b < dbg.cap_blocks) {
+      ocsr_block_record rec;
+      rec.box = c.k; rec.level_scale = c.g.s; rec.u = c.u; rec.v = c.v;
+      rec.px0 = geom_col(c.g, 0); rec.py0 = geom_row(c.g, 0); rec.nx = c.g.nx; rec.ny = c.g.ny;
+      rec.mask = mask; rec.eligible = eligible; rec.d_f = d_f; rec.d_b = d_b;
+      rec.lr_ok = lr_ok; rec.d_sub = d_sub; rec.valid = valid;
+      rec.dlo = ph.dlo; rec.nd = ph.nd;
+      dbg.blocks[c.b] = rec;
+    }
+    if (track) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      add_release(ws.box_done + c.kg, 1);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------
+// generic block (any shape, GRID mode): lanes over candidates, straight from memory
+// ---------------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t pick4(const uint32_t a[4], int r) {
+  return r == 0 ? a[0] : r == 1 ? a[1] : r == 2 ? a[2] : a[3];
+}
+
+// S(d) for the 64 * 4 candidates of a wave: forward (dir > 0) or backward.
+__device__ __forceinline__ void block_costs(const LevelDev& lv, const BlockGeom& g, uint64_t mask,
+                                            int dlo, int nd, int dir, int d_f, int lane,
+                                            uint32_t acc[4]) {
+  acc[0] = acc[1] = acc[2] = acc[3] = 0;
+  const int npts = g.nx * g.ny;
+  for (int t = 0; t < npts; ++t) {
+    if (!((mask >> t) & 1ull)) continue;
+    const int j = t / g.nx, i = t - j * g.nx;
+    const int x = geom_col(g, i), y = geom_row(g, j);
+    const uint64_t* __restrict__ rowL = lv.L + (size_t)y * lv.pitch;
+    const uint64_t* __restrict__ rowR = lv.R + (size_t)y * lv.pitch;
+    if (dir > 0) {
+      const uint64_t tmpl = rowL[x];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int kc = lane + 64 * r;
+        if (kc < nd) acc[r] += __popcll(tmpl ^ ld_word(rowR, x - (dlo + kc), lv.W));
+      }
+    } else {
+      const int q = x - d_f;
+      const uint64_t tmpl = ld_word(rowR, q, lv.W);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int kc = lane + 64 * r;
+        if (kc < nd) acc[r] += __popcll(tmpl ^ ld_word(rowL, q + dlo + kc, lv.W));
+      }
+    }
+  }
+}
+
+// smallest index attaining the minimum cost (key = cost << 16 | index)
+__device__ __forceinline__ uint32_t wta4(const uint32_t acc[4], int nd, int lane) {
+  uint32_t key = 0xFFFFFFFFu;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int kc = lane + 64 * r;
+    if (kc < nd) key = min(key, (acc[r] << 16) | (uint32_t)kc);
+  }
+  return wave_min_u32(key);
+}
+
+__device__ __forceinline__ uint32_t cost_at(const uint32_t acc[4], int k) {
+  return (uint32_t)__shfl((int)pick4(acc, k >> 6), k & 63, 64);
+}
+
+__device__ __forceinline__ void match_block_generic(const MatchParamsDev& P, const FrameDev& fr,
+                                                    int f, int n_total, const MatchWs& ws,
+                                                    const DebugDev& dbg, int level, int q,
+                                                    bool track, int lane) {
+  const BlockCtx c = block_ctx(P, fr, f, n_total, ws, level, q, lane);
+  const LevelDev& lv = fr.lv[level];
+  const PathDev& ph = P.path[level];
+  const uint64_t mask = block_mask(ws, fr.box_off, fr.n_boxes, c.k, c.g, lane);
+  const bool eligible = block_eligible(P, mask, c.g.nx * c.g.ny);
+  int d_f = ph.dlo, d_b = ph.dlo, lr_ok = 0, valid = 0;
+  float d_sub = (float)ph.dlo;
+  uint32_t fwd[4] = {0, 0, 0, 0}, bwd[4] = {0, 0, 0, 0};
+  if (eligible) {
+    block_costs(lv, c.g, mask, ph.dlo, ph.nd, +1, 0, lane, fwd);
+    const uint32_t key = wta4(fwd, ph.nd, lane);
+    const int best = (int)(key & 0xFFFFu);
+    d_f = ph.dlo + best;
+    const int ca = (int)cost_at(fwd, max(best - 1, 0));
+    const int cb = (int)cost_at(fwd, min(best + 1, ph.nd - 1));
+    d_sub = subpixel(d_f, best, ph.nd, ca, (int)(key >> 16), cb);
+    block_costs(lv, c.g, mask, ph.dlo, ph.nd, -1, d_f, lane, bwd);
+    const uint32_t bkey = wta4(bwd, ph.nd, lane);
+    d_b = ph.dlo + (int)(bkey & 0xFFFFu);
+    lr_ok = abs(d_b - d_f) <= P.lr_tol;
+    valid = lr_ok;
+  }
+  if (eligible && c.b < dbg.cap_blocks) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int kc = lane + 64 * r;
+      if (kc < ph.nd && kc < dbg.cap_nd) {
+        if (dbg.cost_fwd) dbg.cost_fwd[(size_t)c.b * dbg.cap_nd + kc] = (uint16_t)fwd[r];
+        if (dbg.cost_bwd) dbg.cost_bwd[(size_t)c.b * dbg.cap_nd + kc] = (uint16_t)bwd[r];
+      }
+    }
+  }
+  write_block(ws, dbg, c, ph, mask, eligible, d_f, d_b, lr_ok, d_sub, valid, track, lane);
+}
+
+// ---------------------------------------------------------------------------------
+// TILED block, register-blocked. One wave per block of at most NX x ROWS points.
+// Lane = (row j, candidate group g); group g owns CPL consecutive candidates. The
+// block's template rows and its search strip (nd + nx - 1 words per row) are staged
+// in LDS with coalesced loads; each lane then holds its row's NX template words and
+// NX + CPL - 1 strip words in registers and forms NX * CPL costs from them
+// (2 x v_xor_b32 + 2 x v_bcnt_u32_b32 each). Row sums are combined with DPP.
+// ---------------------------------------------------------------------------------
+// popcount of a 64-bit word added to acc as two v_bcnt_u32_b32 (each adds its popcount
+// to its second operand). The empty asm keeps the compiler from regrouping the three
+// terms into a v_add3_u32, which would cost a fifth instruction per term.
+__device__ __forceinline__ uint32_t popc64_acc(uint64_t x, uint32_t acc) {
+  uint32_t t = __popc((uint32_t)x) + acc;
+  asm volatile("" : "+v"(t));
+  return __popc((uint32_t)(x >> 32)) + t;
+}
+
+// acc[c] = sum over the row's points i of popcount(t[i] ^ srow[i + c]). Every point is
+// summed first; points whose bit in rowmask is clear (occluded, or past the block's
+// width) are then subtracted again, which only costs anything when such points exist.
+template <int NX, int CPL>
+__device__ __forceinline__ void row_costs(const uint64_t (&t)[NX], const uint64_t* __restrict__ srow,
+                                          uint32_t rowmask, uint32_t (&acc)[CPL]) {
+  uint64_t w[NX + CPL - 1];
+#pragma unroll
+  for (int m = 0; m < NX + CPL - 1; ++m) w[m] = srow[m];
+#pragma unroll
+  for (int c = 0; c < CPL; ++c) acc[c] = 0;
+#pragma unroll
+  for (int i = 0; i < NX; ++i) {
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) acc[c] = popc64_acc(t[i] ^ w[i + c], acc[c]);
+  }
+#pragma unroll
+  for (int i = 0; i < NX; ++i) {
+    if (!((rowmask >> i) & 1u)) {
+      uint64_t ti = t[i];
+      asm volatile("" : "+v"(ti));   // recompute here rather than keep every term live
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) acc[c] -= popc64_acc(ti ^ w[i + c], 0u);
+    }
+  }
+}
+
+template <int ROWS>
+__device__ __forceinline__ uint32_t row_sum(uint32_t v) {
+  // lanes j = lane % ROWS of one group: quad_perm [1,0,3,2], [2,3,0,1], row_half_mirror
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false);
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false);
+  if (ROWS == 8) v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false);
+  return v;
+}
+
+template <int ROWS, int NX, int CPL>
+struct Tiled {
+  static constexpr int G = 64 / ROWS;
+  static constexpr int NC = G * CPL;           // candidates one wave covers
+  static constexpr int SW = NC + NX - 1;       // strip words per row
+  static constexpr size_t kLdsBytes = sizeof(uint64_t) * (ROWS * SW + ROWS * NX) +
+                                      sizeof(uint32_t) * 2 * NC;
+  static_assert(ROWS == 4 || ROWS == 8, "rows");
+};
+
+template <int ROWS, int NX, int CPL>
+__device__ __forceinline__ void match_block_tiled(const MatchParamsDev& P, const FrameDev& fr,
+                                                  int f, int n_total, const MatchWs& ws,
+                                                  const DebugDev& dbg, int level, int q,
+                                                  bool track, int lane, void* lds) {
+  using TT = Tiled<ROWS, NX, CPL>;
+  constexpr int SW = TT::SW, NC = TT::NC;
+  uint64_t* S = (uint64_t*)lds;
+  uint64_t* T = S + ROWS * SW;
+  uint32_t* costf = (uint32_t*)(T + ROWS * NX);
+  uint32_t* costb = costf + NC;
+  const int j = lane % ROWS, grp = lane / ROWS;
+  const LevelDev& lv = fr.lv[level];
+  const PathDev& ph = P.path[level];
+  const int nd = ph.nd, dlo = ph.dlo, dhi = dlo + nd - 1;
+
+  const BlockCtx c = block_ctx(P, fr, f, n_total, ws, level, q, lane);
+  const int nx = c.g.nx, ny = c.g.ny;
+  const int X0 = c.g.cx, Y0 = c.g.cy;
+  const uint64_t* __restrict__ Lb = lv.L + (size_t)Y0 * lv.pitch;
+  const uint64_t* __restrict__ Rb = lv.R + (size_t)Y0 * lv.pitch;
+  const int sw = nd + nx - 1;
+  // forward: template CL(X0 + i, Y0 + j); strip CR(X0 - dhi + m, Y0 + j). Issued before
+  // the occluder scan so that both sets of loads are in flight together.
+  for (int idx = lane; idx < ROWS * SW; idx += 64) {
+    const int jj = idx / SW, m = idx - jj * SW;
+    uint64_t w = 0;
+    if (jj < ny && m < sw) w = ld_word(Rb + (size_t)jj * lv.pitch, X0 - dhi + m, lv.W);
+    S[idx] = w;
+  }
+  for (int idx = lane; idx < ROWS * NX; idx += 64) {
+    const int jj = idx / NX, i = idx - jj * NX;
+    T[idx] = (jj < ny && i < nx) ? Lb[(size_t)jj * lv.pitch + X0 + i] : 0ull;
+  }
+  const uint64_t mask = block_mask(ws, fr.box_off, fr.n_boxes, c.k, c.g, lane);
+  const bool eligible = block_eligible(P, mask, nx * ny);
+  wave_sync();
+  if (!eligible) {
+    write_block(ws, dbg, c, ph, mask, false, dlo, dlo, 0, (float)dlo, 0, track, lane);
+    wave_sync();
+    return;
+  }
+  const uint32_t rowmask = j < ny ? (uint32_t)((mask >> (j * nx)) & ((1u << nx) - 1u)) : 0u;
+  uint64_t t[NX];
+#pragma unroll
+  for (int i = 0; i < NX; ++i) t[i] = T[j * NX + i];
+  uint32_t acc[CPL];
+  // strip entry e = grp*CPL + c + i holds CR(X0 + i - d) for d = dhi - (grp*CPL + c)
+  if (j < ny) row_costs<NX, CPL>(t, S + j * SW + grp * CPL, rowmask, acc);
+#pragma unroll
+  for (int cc = 0; cc < CPL; ++cc)
+    if (j >= ny) acc[cc] = 0;
+  uint32_t key = 0xFFFFFFFFu;
+#pragma unroll
+  for (int cc = 0; cc < CPL; ++cc) {
+    const uint32_t tot = row_sum<ROWS>(acc[cc]);
+    const int e = grp * CPL + cc;
+    if (e < nd) {
+      const int kc = nd - 1 - e;
+      key = min(key, (tot << 16) | (uint32_t)kc);
+      if (j == 0) costf[kc] = tot;
+    }
+  }
+  key = wave_min_u32(key, ROWS);
+  const int best = (int)(key & 0xFFFFu);
+  const int d_f = dlo + best;
+  // backward template CR(X0 - d_f + i, Y0 + j) sits in the forward strip at dhi - d_f + i
+#pragma unroll
+  for (int i = 0; i < NX; ++i) t[i] = S[j * SW + (dhi - d_f) + i];
+  wave_sync();
+  const int ca = (int)costf[max(best - 1, 0)];
+  const int cb = (int)costf[min(best + 1, nd - 1)];
+  const float d_sub = subpixel(d_f, best, nd, ca, (int)(key >> 16), cb);
+  // backward strip: CL(X0 - d_f + dlo + m, Y0 + j)
+  for (int idx = lane; idx < ROWS * SW; idx += 64) {
+    const int jj = idx / SW, m = idx - jj * SW;
+    uint64_t w = 0;
+    if (jj < ny && m < sw) w = ld_word(Lb + (size_t)jj * lv.pitch, X0 - d_f + dlo + m, lv.W);
+    S[idx] = w;
+  }
+  wave_sync();
+  if (j < ny) row_costs<NX, CPL>(t, S + j * SW + grp * CPL, rowmask, acc);
+#pragma unroll
+  for (int cc = 0; cc < CPL; ++cc)
+    if (j >= ny) acc[cc] = 0;
+  uint32_t bkey = 0xFFFFFFFFu;
+#pragma unroll
+  for (int cc = 0; cc < CPL; ++cc) {
+    const uint32_t tot = row_sum<ROWS>(acc[cc]);
+    const int kc = grp * CPL + cc;       // candidate dlo + kc
+    if (kc < nd) {
+      bkey = min(bkey, (tot << 16) | (uint32_t)kc);
+      if (j == 0) costb[kc] = tot;
+    }
+  }
+  bkey = wave_min_u32(bkey, ROWS);
+  const int d_b = dlo + (int)(bkey & 0xFFFFu);
+  const int lr_ok = abs(d_b - d_f) <= P.lr_tol;
+  if (c.b < dbg.cap_blocks && (dbg.cost_fwd || dbg.cost_bwd)) {
+    wave_sync();
+    for (int kc = lane; kc < nd && kc < dbg.cap_nd; kc += 64) {
+      if (dbg.cost_fwd) dbg.cost_fwd[(size_t)c.b * dbg.cap_nd + kc] = (uint16_t)costf[kc];
+      if (dbg.cost_bwd) dbg.cost_bwd[(size_t)c.b * dbg.cap_nd + kc] = (uint16_t)costb[kc];
+    }
+  }
+  write_block(ws, dbg, c, ph, mask, true, d_f, d_b, lr_ok, d_sub, lr_ok, track, lane);
+  wave_sync();
+}
+
+// Grid-stride loop of one wave over the blocks of one level of every frame: frames in
+// order, each frame's level blocks in box order. Block numbers come from the workgroup
+// index, so the loop is uniform across the wave and needs no shared counter.
+template <class Body>
+__device__ __forceinline__ void level_blocks(const FramesDev& FR, const MatchWs& ws, int level,
+                                             Body body) {
+  const int lane = threadIdx.x & 63;
+  const int cnt = lane < FR.n ? ws.fcount[lane * FC_N + (level == 0 ? FC_FAR : FC_CLOSE)] : 0;
+  const int incl = wave_incl_scan(cnt, lane);
+  const int total = __builtin_amdgcn_readfirstlane(__shfl(incl, 63, 64));
+  for (int q = blockIdx.x; q < total; q += gridDim.x) {
+    const uint64_t m = __ballot(lane < FR.n && incl > q);
+    const int f = __ffsll((unsigned long long)m) - 1;
+    const int excl = __builtin_amdgcn_readfirstlane(__shfl(incl - cnt, f, 64));
+    body(f, q - excl);
+  }
+}
+
+// ---------------------------------------------------------------------------------
+// aggregation: one workgroup (256 threads) per box
+// ---------------------------------------------------------------------------------
+struct AggLds {
+  float vals[kAggMax];
+  int32_t scratch[272];
+};
+
+__device__ __forceinline__ float median_sorted(const float* v, int m) {
+  if (m & 1) return v[(m - 1) / 2];
+  return (v[m / 2 - 1] + v[m / 2]) * 0.5f;
+}
+
+// k-th smallest (0-based) of the n non-negative floats in vals: radix select on their
+// bit patterns (monotone for non-negative floats), 8 bits per pass
+__device__ __forceinline__ uint32_t radix_select(const float* vals, int n, int k, int32_t* sc) {
+  const int tid = threadIdx.x;
+  uint32_t prefix = 0, pmask = 0;
+  for (int pass = 0; pass < 4; ++pass) {
+    const int shift = 24 - 8 * pass;
+    sc[tid] = 0;   // 256 bins
+    __syncthreads();
+    for (int i = tid; i < n; i += 256) {
+      const uint32_t u = __float_as_uint(vals[i]);
+      if ((u & pmask) == prefix) atomicAdd(&sc[(u >> shift) & 255u], 1);
+    }
+    __syncthreads();
+    if (tid < 64) {
+      const int c0 = sc[4 * tid], c1 = sc[4 * tid + 1], c2 = sc[4 * tid + 2], c3 = sc[4 * tid + 3];
+      const int sum = c0 + c1 + c2 + c3;
+      const int incl = wave_incl_scan(sum, tid);
+      const int excl = incl - sum;
+      if (k >= excl && k < incl) {   // exactly one lane
+        int d = 4 * tid, kk = k - excl;
+        if (kk >= c0) { kk -= c0; ++d;
+          if (kk >= c1) { kk -= c1; ++d;
+            if (kk >= c2) { kk -= c2; ++d; } } }
+        sc[256] = d;
+        sc[257] = kk;
+      }
+    }
+    __syncthreads();
+    prefix |= (uint32_t)sc[256] << shift;
+    pmask |= 255u << shift;
+    k = sc[257];
+    __syncthreads();
+  }
+  return prefix;
+}
+
+__device__ __forceinline__ void aggregate_box(const MatchParamsDev& P, const MatchWs& ws, int kg,
+                                              ocsr_box_result* out, bool timed_out, AggLds& sm) {
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const BoxPlan pl = ws.plan[kg];
+  ocsr_box_result r = {};
+  if (pl.status != -1 || timed_out) {
+    if (tid == 0) {
+      r.reason = timed_out ? OCSR_REASON_INTERNAL_TIMEOUT : pl.status;
+      out[kg] = r;
+    }
+    return;
+  }
+  const int base = pl.frame * P.cap_blocks + pl.off;
+  if (tid == 0) { sm.scratch[258] = 0; sm.scratch[259] = 0; }
+  __syncthreads();
+  // gather the valid values: one LDS atomic per wave, positions from the ballot
+  const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  for (int b0 = 0; b0 < pl.nblk; b0 += 256) {
+    const int i = b0 + tid;
+    const uint8_t fl = i < pl.nblk ? ws.blk_flag[base + i] : (uint8_t)0;
+    const uint64_t mv = __ballot((fl & 2) != 0);
+    const uint64_t me = __ballot((fl & 1) != 0);
+    int wbase = 0;
+    if (lane == 0) {
+      wbase = atomicAdd(&sm.scratch[258], (int)__popcll(mv));
+      atomicAdd(&sm.scratch[259], (int)__popcll(me));
+    }
+    wbase = __shfl(wbase, 0, 64);
+    if (fl & 2) sm.vals[wbase + __popcll(mv & below)] = ws.blk_val[base + i];
+  }
+  __syncthreads();
+  const int nv = sm.scratch[258], ne = sm.scratch[259];
+  r.n_blocks = pl.nblk;
+  r.n_eligible = ne;
+  r.n_valid = nv;
+  if (ne == 0 || nv == 0) {
+    if (tid == 0) {
+      r.reason = ne == 0 ? OCSR_REASON_NO_ELIGIBLE_BLOCKS : OCSR_REASON_NO_VALID_BLOCKS;
+      out[kg] = r;
+    }
+    return;
+  }
+  float d_box = 0.0f;
+  bool ok = true;
+  if (pl.nblk == 1) {
+    d_box = sm.vals[0];   // a single-block object takes its block result (Alg. 2)
+    r.n_used = 1;
+  } else if (P.agg_mode == OCSR_AGG_TRIMMED_MEDIAN) {
+    // symmetric trim of floor(pct * n / 100) values at each end, then the median: the
+    // one or two middle order statistics, found by radix selection
+    const int t = P.trim_pct * nv / 100;
+    const int m = nv - 2 * t;
+    r.n_used = m > 0 ? m : 0;
+    if (m <= 0 || m < P.n_min) {
+      ok = false;
+    } else {
+      const int k1 = t + (m - 1) / 2;
+      const uint32_t u1 = radix_select(sm.vals, nv, k1, sm.scratch);
+      if (m & 1) {
+        d_box = __uint_as_float(u1);
+      } else {
+        // the next order statistic: u1 again if it repeats, else the least value above u1
+        if (tid == 0) { sm.scratch[260] = 0; sm.scratch[261] = 0x7F800000; }
+        __syncthreads();
+        int le = 0;
+        uint32_t above = 0x7F800000u;
+        for (int i = tid; i < nv; i += 256) {
+          const uint32_t u = __float_as_uint(sm.vals[i]);
+          le += u <= u1;
+          if (u > u1) above = min(above, u);
+        }
+        atomicAdd(&sm.scratch[260], le);
+        atomicMin((uint32_t*)&sm.scratch[261], above);
+        __syncthreads();
+        const uint32_t u2 = sm.scratch[260] >= k1 + 2 ? u1 : (uint32_t)sm.scratch[261];
+        d_box = (__uint_as_float(u1) + __uint_as_float(u2)) * 0.5f;
+      }
+    }
+  } else {
+    // bitonic sort of the valid values, padded with +inf to a power of two
+    int n2 = 1;
+    while (n2 < nv) n2 <<= 1;
+    for (int i = nv + tid; i < n2; i += 256) sm.vals[i] = __builtin_inff();
+    __syncthreads();
+    for (int kk = 2; kk <= n2; kk <<= 1) {
+      for (int j = kk >> 1; j > 0; j >>= 1) {
+        for (int i = tid; i < n2; i += 256) {
+          const int ixj = i ^ j;
+          if (ixj > i) {
+            const float a = sm.vals[i], c = sm.vals[ixj];
+            const bool up = (i & kk) == 0;
+            if ((a > c) == up) { sm.vals[i] = c; sm.vals[ixj] = a; }
+          }
+        }
+        __syncthreads();
+      }
+    }
+    // longest run whose consecutive gaps stay below tau_d; the first run wins a tie
+    if (tid < 64) {
+      int best_start = 0, best_len = 1, start = 0;
+      for (int b0 = 0; b0 < nv; b0 += 64) {
+        const int q = b0 + tid;
+        const bool brk = q > 0 && q < nv && !(sm.vals[q] - sm.vals[q - 1] < P.tau_d);
+        uint64_t m = __ballot(brk);
+        while (m) {
+          const int pos = b0 + __ffsll((unsigned long long)m) - 1;
+          m &= m - 1;
+          const int len = pos - start;
+          if (len > best_len) { best_len = len; best_start = start; }
+          start = pos;
+        }
+      }
+      const int len = nv - start;
+      if (len > best_len) { best_len = len; best_start = start; }
+      if (tid == 0) { sm.scratch[262] = best_start; sm.scratch[263] = best_len; }
+    }
+    __syncthreads();
+    const int seg_start = sm.scratch[262], seg_len = sm.scratch[263];
+    r.n_used = seg_len;
+    if (seg_len < P.n_min) ok = false;
+    else d_box = median_sorted(sm.vals + seg_start, seg_len);
+  }
+  if (tid == 0) {
+    if (!ok) {
+      r.reason = OCSR_REASON_TOO_FEW_CONSISTENT;
+    } else {
+      r.disparity = d_box;
+      if (!(d_box > P.d_eps)) {
+        r.reason = OCSR_REASON_NONPOSITIVE_DISPARITY;
+      } else {
+        r.depth = P.fb / d_box;   // Eq. 1, IEEE fp32 division
+        r.valid = 1;
+        r.reason = OCSR_REASON_OK;
+      }
+    }
+    out[kg] = r;
+  }
+}
+
+}  // namespace dev
+}  // namespace ocsr

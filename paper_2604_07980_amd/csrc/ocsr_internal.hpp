@@ -38,6 +38,8 @@ hipError_t launch_census(const CensusJobsDev& jobs, int total_tiles, int sx, int
 // ---------------------------------------------------------------------------------
 // matching
 // ---------------------------------------------------------------------------------
+constexpr int kMaxFrames = OCSR_MAX_BATCH_FRAMES;
+
 struct LevelDev {
   const uint64_t* L;
   const uint64_t* R;
@@ -49,20 +51,36 @@ struct PathDev {
   int32_t dlo, nd;                 // level search range [dlo, dlo + nd)
 };
 
+// Matching parameters shared by every frame of a call.
 struct MatchParamsDev {
-  LevelDev lv[2];                  // 0: far level (scale 1), 1: close level
-  PathDev path[2];
+  PathDev path[2];                 // 0: far path (scale 1), 1: close path (close scale)
   int32_t tau_s;
   int32_t lr_tol, min_point_pct, agg_mode;
   float tau_d;
   int32_t n_min, trim_pct;
   float fb;                        // focal_px * baseline_m, one fp32 multiply
   float d_eps;
-  int32_t cap_blocks;
-  int32_t n_boxes;
+  int32_t cap_blocks;              // block capacity of one frame
 };
 
-// Per-box plan, written by the plan kernel (one 64-byte record per box).
+// One frame of a call: descriptor levels, its boxes and (whole-frame calls) its images.
+struct FrameDev {
+  LevelDev lv[2];
+  const uint8_t* imgL;             // whole-frame calls: the images the census is made from
+  const uint8_t* imgR;
+  int32_t W, H, pitch;             // full-resolution image size and pitch (bytes)
+  int32_t box_off, n_boxes;        // the frame's boxes: [box_off, box_off + n_boxes)
+  int32_t tile_begin;              // fused call: first census tile item of the frame
+  int32_t tiles0_x, tiles0, tiles1_x, tiles1;   // census tiles per view at levels 0 / 1
+};
+
+struct FramesDev {
+  FrameDev f[kMaxFrames];
+  int32_t n;
+  int32_t n_boxes_total;
+};
+
+// Per-box plan, written by the plan step (one 64-byte record per box).
 struct BoxPlan {
   int32_t status;                  // -1: to be matched; else an OCSR_REASON_* code
   int32_t level;                   // 0 far, 1 close
@@ -70,26 +88,36 @@ struct BoxPlan {
   int32_t nbx, nby;                // blocks along x / y
   int32_t bw, bh;                  // points per block along x / y
   int32_t ox, oy;                  // TILED: origin of block (0, 0)
-  int32_t off;                     // first block number
+  int32_t off;                     // first block number within the frame
   int32_t nblk;                    // blocks matched (0 if not matched)
-  int32_t cx0, cy0;                // clipped box (full res); cx1, cy1 in BoxClip
+  int32_t loff;                    // first block number among the frame's boxes of its level
+  int32_t frame;
 };
 
 struct BoxClip {
-  int32_t cx0, cy0, cx1, cy1;      // clipped box; empty boxes have cx0 >= cx1
+  int32_t cx0, cy0, cx1, cy1;      // clipped box; empty boxes are all zero
 };
+
+// per-frame counters
+enum { FC_NUMBERED = 0, FC_MATCHED = 1, FC_FAR = 2, FC_CLOSE = 3, FC_CENSUS_DONE = 4, FC_N = 8 };
+// call-wide counters: the timeout flag, and the arrival slots of the fused launch's two
+// grid barriers (arrivals spread over kBarSlots counters to keep atomics uncontended)
+constexpr int kBarSlots = 8;
+enum { GC_TIMEOUT = 0, GC_BAR0 = 8, GC_BAR1 = 16, GC_N = 24 };
 
 struct MatchWs {
-  BoxPlan* plan;       // [n_boxes]
-  BoxClip* clip;       // [n_boxes]
-  int32_t* box_end;    // [n_boxes] off + nblk (monotone)
-  int32_t* counters;   // [4]: 0 blocks numbered, 1 blocks matched
-  float* blk_val;      // [cap_blocks] full-res disparity of a valid block
-  uint8_t* blk_flag;   // [cap_blocks] bit 0 eligible, bit 1 valid
+  BoxPlan* plan;       // [n_boxes_total]
+  BoxClip* clip;       // [n_boxes_total]
+  int32_t* lbox_end;   // [2][n_boxes_total] per level and frame: running block end
+  int32_t* box_done;   // [n_boxes_total] blocks of the box finished (fused call)
+  int32_t* fcount;     // [kMaxFrames][FC_N]
+  int32_t* gcount;     // [GC_N]
+  float* blk_val;      // [n_frames][cap_blocks] full-res disparity of a valid block
+  uint8_t* blk_flag;   // [n_frames][cap_blocks] bit 0 eligible, bit 1 valid
 };
 
-size_t match_ws_bytes(int n_boxes, int cap_blocks);
-MatchWs match_ws_carve(void* base, int n_boxes, int cap_blocks);
+size_t match_ws_bytes(int n_frames, int n_boxes_total, int cap_blocks);
+MatchWs match_ws_carve(void* base, int n_frames, int n_boxes_total, int cap_blocks);
 
 struct DebugDev {
   int32_t cap_blocks, cap_nd;
@@ -106,8 +134,29 @@ struct LaunchTimer {
   void (*after)(void* ctx, const char* name, hipStream_t s);
 };
 
-hipError_t launch_match(const MatchParamsDev& p, const ocsr_box* boxes, const MatchWs& ws,
-                        ocsr_box_result* out, const DebugDev& dbg, int n_match_wgs,
-                        hipStream_t stream, const LaunchTimer* timer);
+// Kernel variant used for one level's blocks: TILED blocks of at most 8 x rows points
+// with at most (64 / rows) * cpl level candidates run the register-blocked code;
+// anything else (GRID, wider blocks) runs the generic code.
+struct MatchVariant {
+  int tiled;           // 1: register-blocked TILED code
+  int rows, cpl;
+};
+MatchVariant pick_variant(const PathDev& ph);
+
+// Multi-launch path: plan (one wave per frame), one work-queue match launch per level,
+// one aggregation workgroup per box.
+hipError_t launch_match(const MatchParamsDev& p, const FramesDev& fr, const ocsr_box* boxes,
+                        const MatchWs& ws, ocsr_box_result* out, const DebugDev& dbg,
+                        int n_match_wgs, hipStream_t stream, const LaunchTimer* timer);
+
+// Fused path: census of every frame, planning, matching and aggregation in one
+// persistent launch of co-resident workgroups (after a counter reset). Returns
+// hipErrorNotSupported when no fused kernel is built for this census window and pair of
+// path variants. wgs_per_cu caps the workgroups per compute unit (0: as many as fit).
+hipError_t launch_fused(const MatchParamsDev& p, const FramesDev& fr, const ocsr_box* boxes,
+                        const MatchWs& ws, ocsr_box_result* out, int sx, int sy, int sentinel,
+                        int n_census_tiles, int n_cu, int wgs_per_cu, hipStream_t stream,
+                        const LaunchTimer* timer);
+bool fused_available(const MatchParamsDev& p, int sx, int sy);
 
 }  // namespace ocsr

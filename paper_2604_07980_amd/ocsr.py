@@ -20,18 +20,22 @@ LIB_PATH = os.path.join(HERE, "libocsr.so")
 OK = 0
 E_INVALID, E_WORKSPACE, E_CAPACITY, E_HIP, E_UNSUPPORTED = -1, -2, -3, -4, -5
 REASONS = ["OK", "NOT_RANGED", "CLIPPED_EMPTY", "NO_ELIGIBLE_BLOCKS", "NO_VALID_BLOCKS",
-           "TOO_FEW_CONSISTENT", "NONPOSITIVE_DISPARITY", "CAPACITY_OVERFLOW"]
+           "TOO_FEW_CONSISTENT", "NONPOSITIVE_DISPARITY", "CAPACITY_OVERFLOW", "INTERNAL_TIMEOUT"]
 MODE_TILED, MODE_GRID = 0, 1
 AGG_SEGMENT_MEDIAN, AGG_TRIMMED_MEDIAN = 0, 1
 BOX_RANGE = 1
-MAX_BLOCKS_PER_BOX = 16384
+MAX_BLOCKS_PER_BOX = 4096
+MAX_BATCH_FRAMES = 16
 MAX_CANDIDATES = 256
 MAX_CENSUS_JOBS = 64
 DEFAULT_CAP_BLOCKS = 1 << 20
 
+OPTION_FUSED, OPTION_WAVES_PER_CU = 1, 2
+
 EXPORTS = ["ocsr_abi_version", "ocsr_last_error", "ocsr_ctx_create", "ocsr_ctx_destroy",
            "ocsr_census", "ocsr_census_many", "ocsr_match_workspace_bytes", "ocsr_match_boxes",
-           "ocsr_frame_workspace_bytes", "ocsr_range_frame", "ocsr_ctx_set_timing",
+           "ocsr_frame_workspace_bytes", "ocsr_range_frame", "ocsr_batch_workspace_bytes",
+           "ocsr_range_batch", "ocsr_ctx_set_option", "ocsr_ctx_set_timing",
            "ocsr_ctx_kernel_time", "ocsr_ctx_reset_timing"]
 
 
@@ -75,6 +79,12 @@ class MatchParams(C.Structure):
 class FrameParams(C.Structure):
     _fields_ = [("sx", C.c_int32), ("sy", C.c_int32), ("sentinel", C.c_int32),
                 ("close_scale", C.c_int32)]
+
+
+class Frame(C.Structure):
+    _fields_ = [("imgL", C.c_void_p), ("imgR", C.c_void_p), ("width", C.c_int32),
+                ("height", C.c_int32), ("pitch_bytes", C.c_int32), ("box_offset", C.c_int32),
+                ("n_boxes", C.c_int32), ("reserved", C.c_int32)]
 
 
 class Debug(C.Structure):
@@ -129,6 +139,13 @@ def load(path: str = LIB_PATH):
         L.ocsr_range_frame.argtypes = [vp, vp, vp, i32, i32, i32, C.POINTER(FrameParams), vp, i32,
                                        C.POINTER(MatchParams), i32, vp, C.c_size_t, vp, vp]
         L.ocsr_range_frame.restype = i32
+        L.ocsr_batch_workspace_bytes.argtypes = [C.POINTER(Frame), i32, C.POINTER(FrameParams), i32]
+        L.ocsr_batch_workspace_bytes.restype = C.c_size_t
+        L.ocsr_range_batch.argtypes = [vp, C.POINTER(Frame), i32, C.POINTER(FrameParams), vp,
+                                       C.POINTER(MatchParams), i32, vp, C.c_size_t, vp, vp]
+        L.ocsr_range_batch.restype = i32
+        L.ocsr_ctx_set_option.argtypes = [vp, i32, i32]
+        L.ocsr_ctx_set_option.restype = i32
         L.ocsr_ctx_set_timing.argtypes = [vp, i32]
         L.ocsr_ctx_set_timing.restype = i32
         L.ocsr_ctx_kernel_time.argtypes = [vp, C.c_char_p, C.POINTER(i64), C.POINTER(C.c_double)]
@@ -341,6 +358,58 @@ def range_frame(imgL: torch.Tensor, imgR: torch.Tensor, boxes: torch.Tensor, par
                               C.byref(fp), _dptr(boxes), n, C.byref(q), cap_blocks, _dptr(ws),
                               ws.numel(), _dptr(out), _stream(dev)))
     return out
+
+
+def _frame_params(params: dict) -> FrameParams:
+    return FrameParams(params["sx"], params["sy"], params["sentinel"], params["close_scale"])
+
+
+def range_batch(frames, boxes: torch.Tensor, params: dict, cap_blocks: int = 1 << 16,
+                workspace: Workspace | None = None, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Many frames in one launch sequence.
+
+    frames: list of (imgL, imgR, n_boxes) with uint8 [H, W] cuda images; boxes: int32
+    [sum n_boxes, 5] cuda, frame by frame. Returns int32 [sum n_boxes, 8] results.
+    """
+    if not frames or len(frames) > MAX_BATCH_FRAMES:
+        raise ValueError(f"1..{MAX_BATCH_FRAMES} frames per batch")
+    _need_cuda(boxes)
+    if boxes.dtype != torch.int32 or boxes.dim() != 2 or boxes.shape[1] != 5 or not boxes.is_contiguous():
+        raise ValueError("boxes must be a contiguous int32 [N, 5] tensor")
+    arr = (Frame * len(frames))()
+    off = 0
+    for k, (L, R, nb) in enumerate(frames):
+        _need_cuda(L, R)
+        if L.shape != R.shape or L.dtype != torch.uint8 or L.stride() != R.stride() or L.stride(1) != 1:
+            raise ValueError("frame images must be row-contiguous uint8 tensors of equal shape")
+        H, W = L.shape
+        arr[k] = Frame(L.data_ptr(), R.data_ptr(), W, H, L.stride(0), off, int(nb), 0)
+        off += int(nb)
+    if off != boxes.shape[0]:
+        raise ValueError("box counts of the frames do not add up to the box array")
+    dev = boxes.device
+    fp = _frame_params(params)
+    Lb = load()
+    nbytes = Lb.ocsr_batch_workspace_bytes(arr, len(frames), C.byref(fp), cap_blocks)
+    if nbytes == 0:
+        raise ValueError("invalid batch description")
+    ws = (workspace or Workspace()).get(nbytes, dev)
+    if out is None:
+        out = torch.empty((off, 8), dtype=torch.int32, device=dev)
+    q = make_params(params)
+    _check(Lb.ocsr_range_batch(context(dev.index), arr, len(frames), C.byref(fp), _dptr(boxes),
+                               C.byref(q), cap_blocks, _dptr(ws), ws.numel(), _dptr(out),
+                               _stream(dev)))
+    return out
+
+
+def set_option(option: int, value: int, device: int | None = None):
+    _check(load().ocsr_ctx_set_option(context(device), option, value))
+
+
+def set_fused(enable: bool, device: int | None = None):
+    """Whole frames and batches as one persistent launch (True) or the multi-launch path."""
+    set_option(OPTION_FUSED, 1 if enable else 0, device)
 
 
 # ---------------------------------------------------------------------------------

@@ -97,6 +97,13 @@ VARIANTS = {
 }
 
 
+# Variants whose blocks are not TILED (GRID mode): the kernel serving them is switched off
+# after a device memory fault in its work-queue form whose cause is not yet shown; the
+# library rejects them with OCSR_E_UNSUPPORTED (checked below without launching anything).
+NOT_ENABLED = {"grid_far", "grid_both_s3"}
+SKIP_REASON = "GRID-mode kernel disabled after an unexplained device fault (see DESIGN.md)"
+
+
 def _params(v):
     p = synth.base_params()
     p.update({k: (dict(val) if isinstance(val, dict) else val) for k, val in VARIANTS[v].items()})
@@ -131,6 +138,8 @@ def _check_debug(lib, extra, blk, cf, cb, n):
 @pytest.mark.parametrize("variant", list(VARIANTS))
 @pytest.mark.parametrize("seed", [1, 2, 3, 4])
 def test_match_parity_small(lib, orc, variant, seed):
+    if variant in NOT_ENABLED:
+        pytest.skip(SKIP_REASON)
     p = _params(variant)
     sc = synth.scene_small(1000 * seed + len(variant), H=120, W=200, n_planes=6)
     (L0, R0, L1, R1), (res, blk, cf, cb, n) = orc.run_scene(sc.left, sc.right, p, sc.boxes,
@@ -200,9 +209,18 @@ def test_match_many_boxes_occlusion(lib, orc):
 def _frame_parity(lib, orc, sc, p, debug_check=True):
     (L0, R0, L1, R1), (res, blk, cf, cb, n) = orc.run_scene(sc.left, sc.right, p, sc.boxes,
                                                             debug=debug_check)
-    out = lib.range_frame(_cuda(sc.left), _cuda(sc.right), _cuda(sc.boxes), p)
-    got = lib.results_to_numpy(out)
-    assert_results_match(got, res)
+    got = None
+    for fused in (True, False):
+        lib.set_fused(fused)
+        try:
+            out = lib.range_frame(_cuda(sc.left), _cuda(sc.right), _cuda(sc.boxes), p)
+            g = lib.results_to_numpy(out)
+        finally:
+            lib.set_fused(True)
+        assert_results_match(g, res)
+        if got is not None:
+            assert (g.view(np.int32) == got.view(np.int32)).all()   # both paths, bit for bit
+        got = g
     if debug_check:
         g = _gpu_levels(lib, sc.left, sc.right, p)
         out2, extra = lib.match_boxes(*g, _cuda(sc.boxes), p, debug=True, cap_blocks=max(n, 1))
@@ -221,3 +239,25 @@ def test_config2_realistic_frame(lib, orc):
     sc = synth.scene_realistic()
     got = _frame_parity(lib, orc, sc, synth.params_for(2))
     assert got["valid"][:32].sum() >= 20
+
+
+@pytest.mark.parametrize("variant", list(VARIANTS))
+def test_frame_paths_small(lib, orc, variant):
+    """Whole-frame entry point, fused and multi-launch, on the small-scene variants
+    (variants without a fused kernel take the multi-launch path both times)."""
+    if variant in NOT_ENABLED:
+        pytest.skip(SKIP_REASON)
+    p = _params(variant)
+    sc = synth.scene_small(77 + len(variant), H=120, W=200, n_planes=6)
+    _frame_parity(lib, orc, sc, p, debug_check=False)
+
+
+def test_grid_mode_rejected(lib):
+    """GRID-mode paths are refused before anything is enqueued."""
+    p = _params("grid_far")
+    img = torch.zeros((64, 96), dtype=torch.uint8, device=DEV)
+    g = lib.census_many([img, img, img, img], [1, 1, 2, 2])
+    boxes = torch.tensor([[10, 10, 30, 30, 1]], dtype=torch.int32, device=DEV)
+    with pytest.raises(lib.OcsrError) as e:
+        lib.match_boxes(*g, boxes, p)
+    assert e.value.code == lib.E_UNSUPPORTED
