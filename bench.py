@@ -36,6 +36,8 @@ def parse():
     ap.add_argument("--latency-steps", type=int, default=1000)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch-steps", type=int, default=40,
+                    help="timed repetitions of the 16-frame batch (0 skips the batch section)")
     ap.add_argument("--fused", action="store_true",
                     help="run the one-launch persistent kernel instead of the multi-launch path")
     return ap.parse_args()
@@ -60,6 +62,70 @@ def cpu_baseline(sc, params, costs_per_frame, seconds):
             "sample": f"{reps} repetitions of the realistic 1920x1080 frame (census of both views "
                       f"at both levels + matching of 64 boxes), {el:.1f} s, OpenMP over rows/boxes",
             "ms_per_frame": 1e3 * el / reps}
+
+
+def frame_costs(ocsr, L, R, boxes, p):
+    """Costs, block evaluations and blocks of one frame, from the library's block records."""
+    import numpy as np
+    g = ocsr.census_many([L, R, L, R], [1, 1, p["close_scale"], p["close_scale"]])
+    _, extra = ocsr.match_boxes(*g, boxes, p, debug=True, cap_blocks=1 << 16)
+    nb, rec, _, _ = ocsr.debug_to_numpy(extra)
+    el = rec["eligible"] == 1
+    pts = np.array([bin(int(m)).count("1") for m in rec["mask"]], dtype=np.int64)
+    far = rec["level_scale"] == 1
+    return {"costs": int((pts * rec["nd"] * el).sum()) * 2,
+            "costs_far": int((pts * rec["nd"] * (el & far)).sum()) * 2,
+            "evals": int((rec["nd"] * el).sum()) * 2,
+            "blocks": int(nb)}
+
+
+def batch_section(ocsr, synth, steps, warmup):
+    """16 frames of 1920x1200, min(128, Poisson(40)) boxes each: one batch call against
+    16 per-frame calls on the same inputs, with identical outputs required."""
+    import torch
+    dev = torch.device("cuda:0")
+    p = synth.params_for(3)
+    scenes = [synth.scene_batch_frame(f) for f in range(16)]
+    imgs = [(torch.from_numpy(s.left).to(dev), torch.from_numpy(s.right).to(dev)) for s in scenes]
+    fboxes = [torch.from_numpy(s.boxes).to(dev) for s in scenes]
+    boxes = torch.cat(fboxes).contiguous()
+    frames = [(L, R, b.shape[0]) for (L, R), b in zip(imgs, fboxes)]
+    work = [frame_costs(ocsr, L, R, b, p) for (L, R), b in zip(imgs, fboxes)]
+    costs = sum(w["costs"] for w in work)
+    ws_b, ws_f = ocsr.Workspace(), ocsr.Workspace()
+    out_b = torch.empty((boxes.shape[0], 8), dtype=torch.int32, device=dev)
+    outs_f = [torch.empty((b.shape[0], 8), dtype=torch.int32, device=dev) for b in fboxes]
+
+    def batch():
+        ocsr.range_batch(frames, boxes, p, workspace=ws_b, out=out_b)
+
+    def per_frame():
+        for (L, R), b, o in zip(imgs, fboxes, outs_f):
+            ocsr.range_frame(L, R, b, p, workspace=ws_f, out=o)
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return 1e3 * (time.perf_counter() - t0) / steps
+
+    ms_batch = timed(batch)
+    ms_frames = timed(per_frame)
+    identical = bool(torch.equal(out_b, torch.cat(outs_f)))
+    return {"workload": "batch_16x1920x1200: 16 uint8 stereo pairs, min(128, Poisson(40)) boxes "
+                        "per frame (log-uniform 12..512 px, overlaps occlude), params as the "
+                        "realistic frame",
+            "boxes": int(boxes.shape[0]), "blocks": sum(w["blocks"] for w in work),
+            "costs_per_batch": costs, "steps": steps,
+            "ms_per_batch": round(ms_batch, 4),
+            "value": round(costs / (ms_batch * 1e-3) / 1e9, 3), "unit": "Gcost/s",
+            "ms_16_frame_calls": round(ms_frames, 4),
+            "speedup_vs_16_calls": round(ms_frames / ms_batch, 3),
+            "identical_to_16_calls": identical}
 
 
 def main():
@@ -87,18 +153,10 @@ def main():
     out = torch.empty((n, 8), dtype=torch.int32, device=dev)
 
     # work of one frame, from the library's own block records (outside the timed region)
-    g = ocsr.census_many([L, R, L, R], [1, 1, p["close_scale"], p["close_scale"]])
-    _, extra = ocsr.match_boxes(*g, boxes, p, debug=True, cap_blocks=1 << 16)
-    nb, rec, _, _ = ocsr.debug_to_numpy(extra)
-    el = rec["eligible"] == 1
-    pts = np.array([bin(int(m)).count("1") for m in rec["mask"]])
-    costs = int((pts * rec["nd"] * el).sum()) * 2
-    far = rec["level_scale"] == 1
-    costs_far = int((pts * rec["nd"] * (el & far)).sum()) * 2
-    evals = int((rec["nd"] * el).sum()) * 2
+    fw = frame_costs(ocsr, L, R, boxes, p)
+    costs, costs_far, evals, nb = fw["costs"], fw["costs_far"], fw["evals"], fw["blocks"]
     census_px = 2 * (W * H) + 2 * (W // 2) * (H // 2)
     census_bits = (2 * p["sx"] + 1) * (2 * p["sy"] + 1)
-    del g, extra
 
     def step():
         ocsr.range_frame(L, R, boxes, p, workspace=ws, out=out)
@@ -132,6 +190,25 @@ def main():
         torch.cuda.synchronize()
         lat.append(1e3 * (time.perf_counter() - a))
     lat = np.array(lat)
+
+    # the same frame submitted as a replayed HIP graph (one submission per frame)
+    ocsr.set_graph(True)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    ms_graph = 1e3 * (time.perf_counter() - t0) / args.steps
+    glat = []
+    for _ in range(args.latency_steps):
+        a = time.perf_counter()
+        step()
+        torch.cuda.synchronize()
+        glat.append(1e3 * (time.perf_counter() - a))
+    ocsr.set_graph(False)
+    glat = np.array(glat)
 
     # algorithmic work per launch: census = informative comparisons (the centre term
     # is constant); match = 4 int32 ops per 64-bit Hamming cost
@@ -173,10 +250,15 @@ def main():
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
                        "p99": round(float(np.percentile(lat, 99)), 4),
                        "frames": int(len(lat))},
+        "graph": {"ms_per_step": round(ms_graph, 4),
+                  "latency_ms": {"p50": round(float(np.percentile(glat, 50)), 4),
+                                 "p99": round(float(np.percentile(glat, 99)), 4)}},
         "kernels": {k: {kk: (round(vv, 3) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                     for k, v in kern.items()},
         "roofline": roofline,
     }
+    if args.batch_steps > 0:
+        res["batch"] = batch_section(ocsr, synth, args.batch_steps, max(3, args.warmup // 10))
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(sc, p, costs, args.cpu_seconds)
     print(json.dumps(res), flush=True)

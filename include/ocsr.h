@@ -286,13 +286,27 @@ int32_t ocsr_range_batch(ocsr_ctx* ctx, const ocsr_frame* frames, int32_t n_fram
 /* OCSR_OPTION_WAVES_PER_CU: cap on the workgroups per compute unit of the persistent
  * launch (0 = as many as fit, 1..32 = cap). */
 #define OCSR_OPTION_WAVES_PER_CU 2
+/* OCSR_OPTION_GRAPH: 1 submits whole-frame and batch calls (ocsr_range_frame,
+ * ocsr_range_batch) as HIP graphs: the first call with a given set of arguments
+ * (every frame description, device pointer, size, parameter and option) captures its
+ * launches and instantiates them, and later calls with the same arguments replay the
+ * instantiated graph with a single submission. Up to 32 graphs are kept per context,
+ * least recently used dropped first. The kernels read their inputs at replay time,
+ * so new image or box contents at the same addresses are picked up; a change of any
+ * address or size captures a new graph. Results are identical to 0 (default). */
+#define OCSR_OPTION_GRAPH 3
 int32_t ocsr_ctx_set_option(ocsr_ctx* ctx, int32_t option, int32_t value);
+
+/* Graph submissions of the context so far: replays of a cached graph (*hits) and
+ * captures (*builds). Either pointer may be NULL. */
+int32_t ocsr_ctx_graph_stats(ocsr_ctx* ctx, int64_t* hits, int64_t* builds);
 
 /* When enabled, each kernel launch of the context is bracketed by HIP events on
  * its stream; ocsr_ctx_kernel_time() then reports, per kernel name, the number of
  * launches and their summed duration (ms) since the last reset. Reading
  * synchronizes on the recorded events. Kernel names: census, plan, match_far,
- * match_close, aggregate (multi-launch path), reset, fused (fused path). */
+ * match_close, aggregate (multi-launch path), reset, fused (fused path), graph (one
+ * replay of a whole-frame or batch call with OCSR_OPTION_GRAPH on). */
 int32_t ocsr_ctx_set_timing(ocsr_ctx* ctx, int32_t enable);
 int32_t ocsr_ctx_kernel_time(ocsr_ctx* ctx, const char* kernel, int64_t* launches,
                              double* total_ms);

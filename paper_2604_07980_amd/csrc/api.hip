@@ -4,6 +4,8 @@
 #include <cstdio>
 #include <cstring>
 #include <algorithm>
+#include <functional>
+#include <list>
 #include <map>
 #include <mutex>
 #include <string>
@@ -27,8 +29,19 @@ struct ocsr_ctx {
   std::vector<hipEvent_t> free_events;
   std::map<std::string, std::pair<int64_t, double>> stats;
   hipEvent_t open_start = nullptr;
-  std::mutex mu;
+  // graph submission: instantiated launch sequences of whole-frame calls, most
+  // recently used first, keyed by everything the launches depend on
+  int use_graph = 0;
+  struct Graph {
+    std::string key;
+    hipGraphExec_t exec;
+  };
+  std::list<Graph> graphs;
+  hipStream_t capture_stream = nullptr;
+  int64_t graph_hits = 0, graph_builds = 0;
 };
+
+constexpr size_t kMaxGraphs = 32;
 
 namespace {
 
@@ -79,6 +92,53 @@ LaunchTimer make_timer(ocsr_ctx* c) { return LaunchTimer{c, timer_before, timer_
 
 int64_t cdiv64(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// Replays the graph cached under `key`, or captures the call's launches (enqueue, on
+// the context's own capture stream, so that capture never touches the caller's
+// stream), instantiates them and replays that. The least recently used graph is
+// dropped beyond kMaxGraphs. With timing on, the replay is timed as "graph".
+int32_t graph_launch(ocsr_ctx* ctx, const std::string& key,
+                     const std::function<int32_t(hipStream_t, const LaunchTimer*)>& enqueue,
+                     hipStream_t stream) {
+  hipError_t e;
+  auto it = std::find_if(ctx->graphs.begin(), ctx->graphs.end(),
+                         [&](const ocsr_ctx::Graph& g) { return g.key == key; });
+  if (it != ctx->graphs.end()) {
+    ctx->graphs.splice(ctx->graphs.begin(), ctx->graphs, it);
+    ++ctx->graph_hits;
+  } else {
+    if (!ctx->capture_stream) {
+      e = hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking);
+      if (e != hipSuccess) return hip_fail(e, "hipStreamCreateWithFlags");
+    }
+    e = hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    const int32_t rc = enqueue(ctx->capture_stream, nullptr);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(ctx->capture_stream, &graph);
+    if (rc != OCSR_OK) {
+      if (graph) hipGraphDestroy(graph);
+      return rc;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+    ctx->graphs.push_front({key, exec});
+    ++ctx->graph_builds;
+    while (ctx->graphs.size() > kMaxGraphs) {
+      hipGraphExecDestroy(ctx->graphs.back().exec);
+      ctx->graphs.pop_back();
+    }
+  }
+  LaunchTimer t = make_timer(ctx);
+  if (ctx->timing) t.before(ctx, "graph", stream);
+  e = hipGraphLaunch(ctx->graphs.front().exec, stream);
+  if (ctx->timing) t.after(ctx, "graph", stream);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  return OCSR_OK;
+}
+
 int32_t check_census_window(int sx, int sy, int sentinel) {
   if (sx < 0 || sy < 0 || sx > 32 || sy > 32)
     return fail(OCSR_E_INVALID, "census window half-sizes must be in 0..32 (sx=%d sy=%d)", sx, sy);
@@ -99,8 +159,8 @@ int32_t check_job(const ocsr_census_job& j, int k) {
   return OCSR_OK;
 }
 
-int32_t enqueue_census(ocsr_ctx* ctx, const ocsr_census_job* jobs, int n_jobs, int sx, int sy,
-                       int sentinel, hipStream_t stream) {
+int32_t enqueue_census(const ocsr_census_job* jobs, int n_jobs, int sx, int sy, int sentinel,
+                       hipStream_t stream, const LaunchTimer* tp) {
   CensusJobsDev d;
   memset(&d, 0, sizeof(d));
   int64_t tiles = 0;
@@ -116,10 +176,9 @@ int32_t enqueue_census(ocsr_ctx* ctx, const ocsr_census_job* jobs, int n_jobs, i
   }
   d.n = n_jobs;
   if (tiles > (1ll << 30)) return fail(OCSR_E_CAPACITY, "census: too many tiles");
-  LaunchTimer t = make_timer(ctx);
-  if (ctx->timing) t.before(ctx, "census", stream);
+  if (tp) tp->before(tp->ctx, "census", stream);
   hipError_t e = launch_census(d, (int)tiles, sx, sy, sentinel, stream);
-  if (ctx->timing) t.after(ctx, "census", stream);
+  if (tp) tp->after(tp->ctx, "census", stream);
   if (e != hipSuccess) return hip_fail(e, "census launch");
   return OCSR_OK;
 }
@@ -308,20 +367,39 @@ int32_t range_frames(ocsr_ctx* ctx, const ocsr_frame* frames, int n_frames,
     }
   }
   MatchWs mws = match_ws_carve(base, n_frames, n_total, cap_blocks);
-  LaunchTimer t = make_timer(ctx);
-  const LaunchTimer* tp = ctx->timing ? &t : nullptr;
-  if (ctx->use_fused && fused_available(P, fp->sx, fp->sy)) {
-    hipError_t e = launch_fused(P, FR, boxes, mws, out, fp->sx, fp->sy, fp->sentinel ? 1 : 0, tiles,
-                                ctx->n_cu, ctx->wgs_per_cu, stream, tp);
-    if (e != hipSuccess) return hip_fail(e, "fused launch");
-    return OCSR_OK;
+  const bool fused = ctx->use_fused && fused_available(P, fp->sx, fp->sy);
+  const int sentinel = fp->sentinel ? 1 : 0;
+  // the whole launch sequence of the call, on stream s
+  auto enqueue = [&](hipStream_t s, const LaunchTimer* tp) -> int32_t {
+    if (fused) {
+      hipError_t e = launch_fused(P, FR, boxes, mws, out, fp->sx, fp->sy, sentinel, tiles,
+                                  ctx->n_cu, ctx->wgs_per_cu, s, tp);
+      return e == hipSuccess ? OCSR_OK : hip_fail(e, "fused launch");
+    }
+    int32_t r = enqueue_census(jobs, 4 * n_frames, fp->sx, fp->sy, sentinel, s, tp);
+    if (r != OCSR_OK) return r;
+    hipError_t e = launch_match(P, FR, boxes, mws, out, make_debug(nullptr),
+                                std::max(1, ctx->n_cu * 16), s, tp);
+    return e == hipSuccess ? OCSR_OK : hip_fail(e, "match launch");
+  };
+  if (ctx->use_graph) {
+    // Everything the launches depend on: the host-side descriptions, every device
+    // pointer and size, and the options that choose the kernels.
+    std::string key;
+    auto put = [&key](const void* p, size_t n) { key.append((const char*)p, n); };
+    put(frames, sizeof(ocsr_frame) * n_frames);
+    put(fp, sizeof(*fp));
+    put(&boxes, sizeof(boxes));
+    put(params, sizeof(*params));
+    put(&cap_blocks, sizeof(cap_blocks));
+    put(&ws, sizeof(ws));
+    put(&out, sizeof(out));
+    const int opts[3] = {fused ? 1 : 0, ctx->wgs_per_cu, ctx->n_cu};
+    put(opts, sizeof(opts));
+    return graph_launch(ctx, key, enqueue, stream);
   }
-  if ((rc = enqueue_census(ctx, jobs, 4 * n_frames, fp->sx, fp->sy, fp->sentinel ? 1 : 0, stream)) != OCSR_OK)
-    return rc;
-  const DebugDev no_dbg = make_debug(nullptr);
-  hipError_t e = launch_match(P, FR, boxes, mws, out, no_dbg, std::max(1, ctx->n_cu * 16), stream, tp);
-  if (e != hipSuccess) return hip_fail(e, "match launch");
-  return OCSR_OK;
+  LaunchTimer t = make_timer(ctx);
+  return enqueue(stream, ctx->timing ? &t : nullptr);
 }
 
 }  // namespace
@@ -363,6 +441,8 @@ void ocsr_ctx_destroy(ocsr_ctx* ctx) {
     hipEventDestroy(p.stop);
   }
   for (auto e : ctx->free_events) hipEventDestroy(e);
+  for (auto& g : ctx->graphs) hipGraphExecDestroy(g.exec);
+  if (ctx->capture_stream) hipStreamDestroy(ctx->capture_stream);
   delete ctx;
 }
 
@@ -377,8 +457,9 @@ int32_t ocsr_census(ocsr_ctx* ctx, const uint8_t* img, int32_t width, int32_t he
   int32_t rc;
   if ((rc = check_census_window(params->sx, params->sy, params->sentinel)) != OCSR_OK) return rc;
   if ((rc = check_job(j, 0)) != OCSR_OK) return rc;
-  return enqueue_census(ctx, &j, 1, params->sx, params->sy, params->sentinel ? 1 : 0,
-                        (hipStream_t)stream);
+  LaunchTimer t = make_timer(ctx);
+  return enqueue_census(&j, 1, params->sx, params->sy, params->sentinel ? 1 : 0,
+                        (hipStream_t)stream, ctx->timing ? &t : nullptr);
 }
 
 int32_t ocsr_census_many(ocsr_ctx* ctx, const ocsr_census_job* jobs, int32_t n_jobs,
@@ -392,7 +473,9 @@ int32_t ocsr_census_many(ocsr_ctx* ctx, const ocsr_census_job* jobs, int32_t n_j
   for (int k = 0; k < n_jobs; ++k)
     if ((rc = check_job(jobs[k], k)) != OCSR_OK) return rc;
   if (n_jobs == 0) return OCSR_OK;
-  return enqueue_census(ctx, jobs, n_jobs, sx, sy, sentinel ? 1 : 0, (hipStream_t)stream);
+  LaunchTimer t = make_timer(ctx);
+  return enqueue_census(jobs, n_jobs, sx, sy, sentinel ? 1 : 0, (hipStream_t)stream,
+                        ctx->timing ? &t : nullptr);
 }
 
 size_t ocsr_match_workspace_bytes(int32_t n_boxes, int32_t cap_blocks) {
@@ -483,6 +566,9 @@ int32_t ocsr_ctx_set_option(ocsr_ctx* ctx, int32_t option, int32_t value) {
     case OCSR_OPTION_FUSED:
       ctx->use_fused = value != 0;
       return OCSR_OK;
+    case OCSR_OPTION_GRAPH:
+      ctx->use_graph = value != 0;
+      return OCSR_OK;
     case OCSR_OPTION_WAVES_PER_CU:
       if (value < 0 || value > 32) return fail(OCSR_E_INVALID, "workgroups per CU outside 0..32");
       ctx->wgs_per_cu = value;
@@ -490,6 +576,14 @@ int32_t ocsr_ctx_set_option(ocsr_ctx* ctx, int32_t option, int32_t value) {
     default:
       return fail(OCSR_E_INVALID, "unknown option %d", option);
   }
+}
+
+int32_t ocsr_ctx_graph_stats(ocsr_ctx* ctx, int64_t* hits, int64_t* builds) {
+  g_last_error.clear();
+  if (!ctx) return fail(OCSR_E_INVALID, "null context");
+  if (hits) *hits = ctx->graph_hits;
+  if (builds) *builds = ctx->graph_builds;
+  return OCSR_OK;
 }
 
 int32_t ocsr_ctx_set_timing(ocsr_ctx* ctx, int32_t enable) {

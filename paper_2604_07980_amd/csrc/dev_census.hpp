@@ -46,17 +46,28 @@ __device__ __forceinline__ void census_tile(const uint8_t* __restrict__ img, int
   using T = CensusTile<SX, SY>;
   constexpr int LW = T::LW, PR = T::PR, WR = T::WR, N = T::N;
   const int Ws = W / s, Hs = H / s;
-  // P[r * LW + c] = I(c, r) | I(c, r + 1) << 16 over the tile and its halo
-  for (int idx = threadIdx.x; idx < PR * LW; idx += 256) {
+  // P[r * LW + c] = I(c, r) | I(c, r + 1) << 16 over the tile and its halo. Every
+  // load of the fill is issued before the first one is waited for: a load whose pixel
+  // lies outside the level image reads the image's first byte instead and is zeroed.
+  constexpr int NFILL = (PR * LW + 255) / 256;
+  uint32_t lo[NFILL], hi[NFILL];
+#pragma unroll
+  for (int k = 0; k < NFILL; ++k) {
+    const int idx = threadIdx.x + 256 * k;
     const int pr = idx / LW, pc = idx - pr * LW;
     const int X = X0 - SX + pc, Y = Y0 - SY + pr;
-    uint32_t lo = 0, hi = 0;
-    if (X >= 0 && X < Ws) {
-      const uint8_t* col = img + (size_t)(s * X);
-      if (Y >= 0 && Y < Hs) lo = col[(size_t)(s * Y) * pitch];
-      if (Y + 1 >= 0 && Y + 1 < Hs) hi = col[(size_t)(s * (Y + 1)) * pitch];
-    }
-    P[idx] = lo | (hi << 16);
+    const bool x_ok = idx < PR * LW && X >= 0 && X < Ws;
+    const bool ok0 = x_ok && Y >= 0 && Y < Hs;
+    const bool ok1 = x_ok && Y + 1 >= 0 && Y + 1 < Hs;
+    lo[k] = img[ok0 ? (size_t)(s * Y) * pitch + (size_t)(s * X) : 0];
+    hi[k] = img[ok1 ? (size_t)(s * (Y + 1)) * pitch + (size_t)(s * X) : 0];
+    lo[k] = ok0 ? lo[k] : 0u;
+    hi[k] = ok1 ? hi[k] : 0u;
+  }
+#pragma unroll
+  for (int k = 0; k < NFILL; ++k) {
+    const int idx = threadIdx.x + 256 * k;
+    if (idx < PR * LW) P[idx] = lo[k] | (hi[k] << 16);
   }
   __syncthreads();
 

@@ -399,6 +399,30 @@ __device__ __forceinline__ uint32_t row_sum(uint32_t v) {
   return v;
 }
 
+// S[jj * SW + m] = row jj's word at x_first + m of the level image (0 outside the
+// image, past the block's ny rows or past sw words), for ROWS x SW entries. All loads
+// of a lane are issued before the first is waited for; an entry with no word reads
+// the block's first row at column 0 instead and is zeroed.
+template <int ROWS, int SW>
+__device__ __forceinline__ void stage_strip(uint64_t* __restrict__ S, const uint64_t* __restrict__ rows,
+                                            int pitch, int x_first, int ny, int sw, int W, int lane) {
+  constexpr int N = ROWS * SW, IT = (N + 63) / 64;
+  uint64_t w[IT];
+#pragma unroll
+  for (int k = 0; k < IT; ++k) {
+    const int idx = lane + 64 * k;
+    const int jj = idx / SW, m = idx - jj * SW, x = x_first + m;
+    const bool ok = idx < N && jj < ny && m < sw && x >= 0 && x < W;
+    w[k] = rows[ok ? (size_t)jj * pitch + x : 0];
+    w[k] = ok ? w[k] : 0ull;
+  }
+#pragma unroll
+  for (int k = 0; k < IT; ++k) {
+    const int idx = lane + 64 * k;
+    if (idx < N) S[idx] = w[k];
+  }
+}
+
 template <int ROWS, int NX, int CPL>
 struct Tiled {
   static constexpr int G = 64 / ROWS;
@@ -433,16 +457,8 @@ __device__ __forceinline__ void match_block_tiled(const MatchParamsDev& P, const
   const int sw = nd + nx - 1;
   // forward: template CL(X0 + i, Y0 + j); strip CR(X0 - dhi + m, Y0 + j). Issued before
   // the occluder scan so that both sets of loads are in flight together.
-  for (int idx = lane; idx < ROWS * SW; idx += 64) {
-    const int jj = idx / SW, m = idx - jj * SW;
-    uint64_t w = 0;
-    if (jj < ny && m < sw) w = ld_word(Rb + (size_t)jj * lv.pitch, X0 - dhi + m, lv.W);
-    S[idx] = w;
-  }
-  for (int idx = lane; idx < ROWS * NX; idx += 64) {
-    const int jj = idx / NX, i = idx - jj * NX;
-    T[idx] = (jj < ny && i < nx) ? Lb[(size_t)jj * lv.pitch + X0 + i] : 0ull;
-  }
+  stage_strip<ROWS, SW>(S, Rb, lv.pitch, X0 - dhi, ny, sw, lv.W, lane);
+  stage_strip<ROWS, NX>(T, Lb, lv.pitch, X0, ny, nx, lv.W, lane);
   const uint64_t mask = block_mask(ws, fr.box_off, fr.n_boxes, c.k, c.g, lane);
   const bool eligible = block_eligible(P, mask, nx * ny);
   wave_sync();
@@ -483,12 +499,7 @@ __device__ __forceinline__ void match_block_tiled(const MatchParamsDev& P, const
   const int cb = (int)costf[min(best + 1, nd - 1)];
   const float d_sub = subpixel(d_f, best, nd, ca, (int)(key >> 16), cb);
   // backward strip: CL(X0 - d_f + dlo + m, Y0 + j)
-  for (int idx = lane; idx < ROWS * SW; idx += 64) {
-    const int jj = idx / SW, m = idx - jj * SW;
-    uint64_t w = 0;
-    if (jj < ny && m < sw) w = ld_word(Lb + (size_t)jj * lv.pitch, X0 - d_f + dlo + m, lv.W);
-    S[idx] = w;
-  }
+  stage_strip<ROWS, SW>(S, Lb, lv.pitch, X0 - d_f + dlo, ny, sw, lv.W, lane);
   wave_sync();
   if (j < ny) row_costs<NX, CPL>(t, S + j * SW + grp * CPL, rowmask, acc);
 #pragma unroll

@@ -30,13 +30,13 @@ MAX_CANDIDATES = 256
 MAX_CENSUS_JOBS = 64
 DEFAULT_CAP_BLOCKS = 1 << 20
 
-OPTION_FUSED, OPTION_WAVES_PER_CU = 1, 2
+OPTION_FUSED, OPTION_WAVES_PER_CU, OPTION_GRAPH = 1, 2, 3
 
 EXPORTS = ["ocsr_abi_version", "ocsr_last_error", "ocsr_ctx_create", "ocsr_ctx_destroy",
            "ocsr_census", "ocsr_census_many", "ocsr_match_workspace_bytes", "ocsr_match_boxes",
            "ocsr_frame_workspace_bytes", "ocsr_range_frame", "ocsr_batch_workspace_bytes",
            "ocsr_range_batch", "ocsr_ctx_set_option", "ocsr_ctx_set_timing",
-           "ocsr_ctx_kernel_time", "ocsr_ctx_reset_timing"]
+           "ocsr_ctx_kernel_time", "ocsr_ctx_reset_timing", "ocsr_ctx_graph_stats"]
 
 
 class OcsrError(RuntimeError):
@@ -152,6 +152,8 @@ def load(path: str = LIB_PATH):
         L.ocsr_ctx_kernel_time.restype = i32
         L.ocsr_ctx_reset_timing.argtypes = [vp]
         L.ocsr_ctx_reset_timing.restype = i32
+        L.ocsr_ctx_graph_stats.argtypes = [vp, C.POINTER(i64), C.POINTER(i64)]
+        L.ocsr_ctx_graph_stats.restype = i32
         _lib = L
         return L
 
@@ -410,6 +412,18 @@ def set_option(option: int, value: int, device: int | None = None):
 def set_fused(enable: bool, device: int | None = None):
     """Whole frames and batches as one persistent launch (True) or the multi-launch path."""
     set_option(OPTION_FUSED, 1 if enable else 0, device)
+
+
+def set_graph(enable: bool, device: int | None = None):
+    """Submit whole-frame and batch calls as cached HIP graphs (True) or launch by launch."""
+    set_option(OPTION_GRAPH, 1 if enable else 0, device)
+
+
+def graph_stats(device: int | None = None) -> tuple[int, int]:
+    """(replays of cached graphs, graph captures) of the device's context so far."""
+    hits, builds = C.c_int64(0), C.c_int64(0)
+    _check(load().ocsr_ctx_graph_stats(context(device), C.byref(hits), C.byref(builds)))
+    return hits.value, builds.value
 
 
 # ---------------------------------------------------------------------------------

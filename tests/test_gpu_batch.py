@@ -5,7 +5,7 @@ import pytest
 import torch
 
 from paper_2604_07980_amd import synth
-from test_gpu_parity import assert_results_match, _cuda
+from test_gpu_parity import assert_results_match, lib_options, _cuda
 
 pytestmark = pytest.mark.gpu
 
@@ -37,14 +37,11 @@ def test_batch_equals_per_frame_and_oracle(lib, orc, fused):
     p["close"].update(dmax=63)
     scenes = _small_batch(7, seed=1)
     frames, boxes = _batch_inputs(scenes)
-    lib.set_fused(fused)
-    try:
+    with lib_options(lib, fused=fused):
         got = lib.results_to_numpy(lib.range_batch(frames, boxes, p))
         per = np.concatenate([lib.results_to_numpy(
             lib.range_frame(f[0], f[1], _cuda(sc.boxes.reshape(-1, 5).astype(np.int32)), p))
             for f, sc in zip(frames, scenes) if len(sc.boxes)] or [np.zeros(0, got.dtype)])
-    finally:
-        lib.set_fused(True)
     assert (got.view(np.int32) == per.view(np.int32)).all()
     assert_results_match(got, _oracle(orc, scenes, p))
 
@@ -57,11 +54,8 @@ def test_batch_mixed_resolutions(lib, orc):
               synth.scene_small(903, H=64, W=64, n_planes=0)]
     frames, boxes = _batch_inputs(scenes)
     for fused in (True, False):
-        lib.set_fused(fused)
-        try:
+        with lib_options(lib, fused=fused):
             got = lib.results_to_numpy(lib.range_batch(frames, boxes, p))
-        finally:
-            lib.set_fused(True)
         assert_results_match(got, _oracle(orc, scenes, p))
 
 
@@ -73,11 +67,8 @@ def test_batch_config3_16_frames(lib, orc):
     want = _oracle(orc, scenes, p)
     got = lib.results_to_numpy(lib.range_batch(frames, boxes, p))
     assert_results_match(got, want)
-    lib.set_fused(False)
-    try:
+    with lib_options(lib, fused=True):
         got2 = lib.results_to_numpy(lib.range_batch(frames, boxes, p))
-    finally:
-        lib.set_fused(True)
     assert (got.view(np.int32) == got2.view(np.int32)).all()
     assert got["valid"].sum() > 0.5 * len(got)
 

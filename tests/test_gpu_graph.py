@@ -1,0 +1,92 @@
+"""Graph submission (OCSR_OPTION_GRAPH): whole-frame and batch calls captured once and
+replayed give the same results as launch-by-launch submission and as the oracle, on
+every replay, with new image contents at the same addresses between replays."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2604_07980_amd import synth
+from test_gpu_parity import assert_results_match, lib_options, _cuda
+
+pytestmark = pytest.mark.gpu
+
+
+def _frame_scenes():
+    return [synth.scene_small(700 + k, H=200, W=288, n_planes=6) for k in range(3)]
+
+
+@pytest.mark.parametrize("fused", [False, True])
+def test_graph_frame_replays(lib, orc, fused):
+    p = synth.params_for(2)
+    p["tau_s"] = 40
+    scenes = _frame_scenes()
+    nb = max(len(sc.boxes) for sc in scenes)
+    L = torch.empty((200, 288), dtype=torch.uint8, device="cuda:0")
+    R = torch.empty_like(L)
+    boxes = torch.zeros((nb, 5), dtype=torch.int32, device="cuda:0")
+    ws = lib.Workspace()
+    out = torch.empty((nb, 8), dtype=torch.int32, device="cuda:0")
+    with lib_options(lib, fused=fused, graph=True):
+        hits0, builds0 = lib.graph_stats()
+        for rep in range(6):
+            sc = scenes[rep % 3]
+            # eager work between replays: new contents at the same addresses
+            L.copy_(_cuda(sc.left))
+            R.copy_(_cuda(sc.right))
+            b = np.zeros((nb, 5), np.int32)          # padding rows: empty, not ranged
+            b[:len(sc.boxes)] = sc.boxes
+            boxes.copy_(_cuda(b))
+            lib.range_frame(L, R, boxes, p, workspace=ws, out=out)
+            got = lib.results_to_numpy(out)
+            torch.cuda.synchronize()
+            want = orc.run_scene(sc.left, sc.right, p, b)[1][0]
+            assert_results_match(got, want)
+        hits1, builds1 = lib.graph_stats()
+    assert builds1 - builds0 == 1 and hits1 - hits0 == 5
+    with lib_options(lib, fused=fused, graph=False):
+        eager = lib.results_to_numpy(lib.range_frame(L, R, boxes, p, workspace=ws, out=out))
+    assert (eager.view(np.int32) == got.view(np.int32)).all()
+
+
+def test_graph_batch_alternating(lib, orc):
+    """Two batch shapes in turn: one capture each, then replays of both."""
+    p = synth.base_params()
+    p["tau_s"] = 40
+    p["far"].update(dmax=15)
+    p["close"].update(dmax=63)
+    sets = [[synth.scene_small(800 + k, H=128, W=192, n_planes=4) for k in range(5)],
+            [synth.scene_small(850 + k, H=160, W=160, n_planes=3) for k in range(3)]]
+    inputs = []
+    for scenes in sets:
+        frames = [(_cuda(sc.left), _cuda(sc.right), len(sc.boxes)) for sc in scenes]
+        boxes = _cuda(np.concatenate([sc.boxes.reshape(-1, 5) for sc in scenes]).astype(np.int32))
+        want = np.concatenate([orc.run_scene(sc.left, sc.right, p, sc.boxes)[1][0] for sc in scenes])
+        out = torch.empty((boxes.shape[0], 8), dtype=torch.int32, device="cuda:0")
+        inputs.append((frames, boxes, want, out, lib.Workspace()))
+    with lib_options(lib, graph=True):
+        hits0, builds0 = lib.graph_stats()
+        for rep in range(6):
+            frames, boxes, want, out, ws = inputs[rep % 2]
+            lib.range_batch(frames, boxes, p, workspace=ws, out=out)
+            assert_results_match(lib.results_to_numpy(out), want)
+        hits1, builds1 = lib.graph_stats()
+    assert builds1 - builds0 == 2 and hits1 - hits0 == 4
+
+
+def test_graph_new_arguments_recapture(lib, orc):
+    """A different output address is a different graph; results stay correct."""
+    p = synth.params_for(2)
+    p["tau_s"] = 40
+    sc = _frame_scenes()[0]
+    L, R, boxes = _cuda(sc.left), _cuda(sc.right), _cuda(sc.boxes)
+    want = orc.run_scene(sc.left, sc.right, p, sc.boxes)[1][0]
+    ws = lib.Workspace()
+    with lib_options(lib, graph=True):
+        hits0, builds0 = lib.graph_stats()
+        for _ in range(3):
+            out = torch.empty((len(sc.boxes), 8), dtype=torch.int32, device="cuda:0")
+            lib.range_frame(L, R, boxes, p, workspace=ws, out=out)
+            assert_results_match(lib.results_to_numpy(out), want)
+            del out
+        hits1, builds1 = lib.graph_stats()
+    assert builds1 - builds0 + hits1 - hits0 == 3

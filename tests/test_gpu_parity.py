@@ -4,6 +4,8 @@ Integer outputs (census words, block tables, masks, cost volumes, WTA indices,
 validity, reasons) must be bit-exact; sub-pixel disparity within 1e-4 px and depth
 within 1e-5 relative (fp32).
 """
+import contextlib
+
 import numpy as np
 import pytest
 import torch
@@ -15,6 +17,18 @@ pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
 TOL_D = 1e-4
 TOL_Z = 1e-5
+
+
+@contextlib.contextmanager
+def lib_options(lib, fused=False, graph=False):
+    """Runs the block with the given submission options, then restores the defaults."""
+    lib.set_fused(fused)
+    lib.set_graph(graph)
+    try:
+        yield
+    finally:
+        lib.set_fused(False)
+        lib.set_graph(False)
 
 
 def _u64(t: torch.Tensor) -> np.ndarray:
@@ -210,13 +224,10 @@ def _frame_parity(lib, orc, sc, p, debug_check=True):
     (L0, R0, L1, R1), (res, blk, cf, cb, n) = orc.run_scene(sc.left, sc.right, p, sc.boxes,
                                                             debug=debug_check)
     got = None
-    for fused in (True, False):
-        lib.set_fused(fused)
-        try:
+    for fused in (False, True):
+        with lib_options(lib, fused=fused):
             out = lib.range_frame(_cuda(sc.left), _cuda(sc.right), _cuda(sc.boxes), p)
             g = lib.results_to_numpy(out)
-        finally:
-            lib.set_fused(True)
         assert_results_match(g, res)
         if got is not None:
             assert (g.view(np.int32) == got.view(np.int32)).all()   # both paths, bit for bit
