@@ -38,6 +38,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=40,
                     help="timed repetitions of the 16-frame batch (0 skips the batch section)")
+    ap.add_argument("--serve-requests", type=int, default=600,
+                    help="requests of the serving section at 120/s (0 skips it)")
+    ap.add_argument("--serve-pool", type=int, default=2,
+                    help="pre-rendered image pairs per serving resolution")
     ap.add_argument("--fused", action="store_true",
                     help="run the one-launch persistent kernel instead of the multi-launch path")
     return ap.parse_args()
@@ -126,6 +130,61 @@ def batch_section(ocsr, synth, steps, warmup):
             "ms_16_frame_calls": round(ms_frames, 4),
             "speedup_vs_16_calls": round(ms_frames / ms_batch, 3),
             "identical_to_16_calls": identical}
+
+
+def serving_section(ocsr, synth, n_requests, pool_size):
+    """The serving workload: Poisson arrivals at 120/s mixing 1280x720, 1920x1080 and
+    3840x2160 frames (0.3/0.5/0.2) from resident image pools, 1..200 boxes, close
+    ranges 0..127/191/255; continuous batching under a 4 GiB budget. Also run with all
+    requests arriving at once (throughput), and as plain per-frame calls one after
+    another, whose outputs the served ones must equal."""
+    import numpy as np
+    import torch
+    from paper_2604_07980_amd import serve
+    dev = torch.device("cuda:0")
+    pools = [[(torch.from_numpy(L).to(dev), torch.from_numpy(R).to(dev))
+              for L, R in synth.serving_pool(res, pool_size, seed=5000 + k)]
+             for k, res in enumerate(synth.SERVING_RESOLUTIONS)]
+    spec = synth.serving_requests(n_requests, pool_sizes=(pool_size,) * 3)
+
+    def requests(at_once):
+        return [serve.Request(q["rid"], *pools[q["res"]][q["pool"]], q["boxes"], q["params"],
+                              0.0 if at_once else q["arrival"]) for q in spec]
+
+    def served(at_once):
+        srv = serve.Server(serve.GpuExecutor(n_slots=3), mem_budget=4 << 30)
+        t0 = time.perf_counter()
+        res = srv.run(requests(at_once))
+        wall = time.perf_counter() - t0
+        return res, serve.summarize(res, wall)
+
+    served(True)                                   # warm-up: kernels, pools, allocator
+    res_rt, rt = served(False)
+    res_sat, sat = served(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plain = []
+    ws = ocsr.Workspace()
+    for q in requests(True):
+        out = ocsr.range_frame(q.left, q.right, torch.from_numpy(q.boxes).to(dev), q.params,
+                               cap_blocks=1 << 18, workspace=ws)
+        plain.append(ocsr.results_to_numpy(out))
+    wall_plain = time.perf_counter() - t0
+    identical = all((a.boxes.view(np.int32) == b.view(np.int32)).all() and
+                    (c.boxes.view(np.int32) == b.view(np.int32)).all()
+                    for a, c, b in zip(res_rt, res_sat, plain))
+    r4 = lambda v: None if v is None else round(v, 4)
+    return {"workload": f"serving mix: {n_requests} requests, Poisson 120/s, 1280x720 / 1920x1080 "
+                        f"/ 3840x2160 (0.3/0.5/0.2), 1..200 boxes, close 0..127/191/255, "
+                        f"{pool_size} resident pairs per resolution, 4 GiB budget, 3 streams",
+            "realtime_120_per_s": {"frames_per_s": r4(rt["frames_per_s"]),
+                                   "latency_ms": {k: r4(v) for k, v in rt["latency_ms"].items()},
+                                   "mean_batch_frames": r4(rt["mean_batch_frames"])},
+            "all_at_once": {"frames_per_s": r4(sat["frames_per_s"]),
+                            "latency_ms": {k: r4(v) for k, v in sat["latency_ms"].items()},
+                            "mean_batch_frames": r4(sat["mean_batch_frames"])},
+            "plain_per_frame_calls": {"frames_per_s": r4(n_requests / wall_plain)},
+            "identical_to_plain_calls": bool(identical)}
 
 
 def main():
@@ -259,6 +318,8 @@ def main():
     }
     if args.batch_steps > 0:
         res["batch"] = batch_section(ocsr, synth, args.batch_steps, max(3, args.warmup // 10))
+    if args.serve_requests > 0:
+        res["serving"] = serving_section(ocsr, synth, args.serve_requests, args.serve_pool)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(sc, p, costs, args.cpu_seconds)
     print(json.dumps(res), flush=True)

@@ -261,7 +261,9 @@ typedef struct {
 } ocsr_frame;
 
 /* Workspace of ocsr_range_batch: the four descriptor images of every frame, the plan
- * of every box and cap_blocks blocks per frame. frames (host): n_frames entries. */
+ * of every box and cap_blocks blocks per frame. frames (host): n_frames entries; only
+ * their sizes and box counts are read (image pointers may be NULL). Returns 0 for an
+ * invalid description. */
 size_t ocsr_batch_workspace_bytes(const ocsr_frame* frames, int32_t n_frames,
                                   const ocsr_frame_params* fp, int32_t cap_blocks);
 
@@ -272,6 +274,27 @@ int32_t ocsr_range_batch(ocsr_ctx* ctx, const ocsr_frame* frames, int32_t n_fram
                          const ocsr_frame_params* fp, const ocsr_box* boxes,
                          const ocsr_match_params* params, int32_t cap_blocks, void* ws,
                          size_t ws_bytes, ocsr_box_result* out, void* stream);
+
+/* ------------------------------------------------------------------------------ */
+/* Dense counterpart                                                                */
+/* ------------------------------------------------------------------------------ */
+/* Not part of the paper's method: the dense matcher the object-centric path is
+ * measured against, on the same descriptors and Hamming cost. For every pixel and
+ * every d in [dmin, dmax]: C(x, y, d) = sum over the (2 radius + 1)^2 window around
+ * (x, y), clipped to the image, of popcount(CL(x', y') ^ CR(x' - d, y')) (CR reads
+ * outside the image are 0). d_L(x, y) is the smallest d minimising C(x, y, d);
+ * d_R(xr, y) the smallest d minimising C(xr + d, y, d) over d with xr + d < width
+ * (-1 if none). disp(x, y) = d_L where x - d_L >= 0, d_R(x - d_L, y) >= 0 and
+ * |d_L - d_R(x - d_L, y)| <= lr_tol, else -1.
+ *
+ * lv (host struct, dev descriptors): one level's left/right descriptors (any scale).
+ * 0 <= dmin <= dmax, dmax - dmin < OCSR_MAX_CANDIDATES; radius 1..3 (else
+ * OCSR_E_UNSUPPORTED); lr_tol >= 0. disp (dev): int16 [height][width], row-contiguous;
+ * disp_right (dev, nullable): receives d_R. ws: ocsr_dense_workspace_bytes() bytes. */
+size_t ocsr_dense_workspace_bytes(int32_t width, int32_t height);
+int32_t ocsr_dense_match(ocsr_ctx* ctx, const ocsr_level* lv, int32_t dmin, int32_t dmax,
+                         int32_t radius, int32_t lr_tol, int16_t* disp, int16_t* disp_right,
+                         void* ws, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------------ */
 /* Options and timing                                                               */
@@ -286,6 +309,12 @@ int32_t ocsr_range_batch(ocsr_ctx* ctx, const ocsr_frame* frames, int32_t n_fram
 /* OCSR_OPTION_WAVES_PER_CU: cap on the workgroups per compute unit of the persistent
  * launch (0 = as many as fit, 1..32 = cap). */
 #define OCSR_OPTION_WAVES_PER_CU 2
+/* OCSR_OPTION_MATCH_WGS_PER_CU: workgroups per compute unit of the grid of each matching
+ * launch (1..64, default 16). The launch deals its work items over this grid. */
+#define OCSR_OPTION_MATCH_WGS_PER_CU 4
+/* OCSR_OPTION_BLOCKS_PER_WAVE: blocks each wave of a matching workgroup takes per work
+ * item (1..8, default 1); a work item holds 4 x this many blocks of one box. */
+#define OCSR_OPTION_BLOCKS_PER_WAVE 5
 /* OCSR_OPTION_GRAPH: 1 submits whole-frame and batch calls (ocsr_range_frame,
  * ocsr_range_batch) as HIP graphs: the first call with a given set of arguments
  * (every frame description, device pointer, size, parameter and option) captures its
@@ -297,6 +326,26 @@ int32_t ocsr_range_batch(ocsr_ctx* ctx, const ocsr_frame* frames, int32_t n_fram
 #define OCSR_OPTION_GRAPH 3
 int32_t ocsr_ctx_set_option(ocsr_ctx* ctx, int32_t option, int32_t value);
 
+/* ------------------------------------------------------------------------------ */
+/* Matching kernel variants (for tuners)                                            */
+/* ------------------------------------------------------------------------------ */
+/* A TILED path's blocks run in a register-blocked kernel: `rows` block rows per wave
+ * (4 for blocks up to 4x4, 8 for blocks up to 8x8) and `cpl` consecutive candidates per
+ * lane, covering (64 / rows) * cpl level candidates. Any variant that covers a path
+ * gives identical results; they differ in speed only. By default the smallest covering
+ * cpl of the smallest covering rows is used.
+ *
+ * ocsr_variant_candidates: writes up to `cap` (rows, cpl) pairs (host arrays) that
+ * cover bw x bh blocks and n_candidates level candidates; returns how many exist (may
+ * exceed cap), or a negative status. */
+int32_t ocsr_variant_candidates(int32_t bw, int32_t bh, int32_t n_candidates, int32_t* rows,
+                                int32_t* cpl, int32_t cap);
+/* Chooses the variant for paths of bw x bh blocks and n_candidates level candidates in
+ * this context (rows == 0 restores the default). OCSR_E_INVALID if the variant does not
+ * cover such a path. */
+int32_t ocsr_ctx_set_variant(ocsr_ctx* ctx, int32_t bw, int32_t bh, int32_t n_candidates,
+                             int32_t rows, int32_t cpl);
+
 /* Graph submissions of the context so far: replays of a cached graph (*hits) and
  * captures (*builds). Either pointer may be NULL. */
 int32_t ocsr_ctx_graph_stats(ocsr_ctx* ctx, int64_t* hits, int64_t* builds);
@@ -305,8 +354,9 @@ int32_t ocsr_ctx_graph_stats(ocsr_ctx* ctx, int64_t* hits, int64_t* builds);
  * its stream; ocsr_ctx_kernel_time() then reports, per kernel name, the number of
  * launches and their summed duration (ms) since the last reset. Reading
  * synchronizes on the recorded events. Kernel names: census, plan, match_far,
- * match_close, aggregate (multi-launch path), reset, fused (fused path), graph (one
- * replay of a whole-frame or batch call with OCSR_OPTION_GRAPH on). */
+ * match_close (multi-launch path), reset, fused (fused path), graph (one replay of a
+ * whole-frame or batch call with OCSR_OPTION_GRAPH on), dense and dense_check (the
+ * dense counterpart). */
 int32_t ocsr_ctx_set_timing(ocsr_ctx* ctx, int32_t enable);
 int32_t ocsr_ctx_kernel_time(ocsr_ctx* ctx, const char* kernel, int64_t* launches,
                              double* total_ms);

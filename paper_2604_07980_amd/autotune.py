@@ -1,0 +1,179 @@
+"""Autotuner of the matching launches: kernel variant per path shape, blocks per wave
+and grid size, measured on the caller's own workload and kept in a JSON table.
+
+The register-blocked matching kernel comes in variants (rows of a block per wave,
+candidates per lane) that all compute the same costs; blocks per wave and the grid size
+only change how work items are dealt. None of them changes a result, so the tuner times
+each choice on a real workload, requires its output to equal the default's bit for bit,
+and keeps the fastest. A table is tied to the device architecture it was measured on.
+
+    table = autotune.tune(run, params)        # run(): one call of the workload
+    autotune.save(table, "tune.json")
+    autotune.apply(autotune.load("tune.json"))
+"""
+from __future__ import annotations
+
+import json
+from dataclasses import dataclass, field
+
+from . import ocsr
+
+BLOCKS_PER_WAVE = (1, 2, 4)
+MATCH_WGS_PER_CU = (4, 8, 16, 32)
+DEFAULT_BLOCKS_PER_WAVE = 1
+DEFAULT_MATCH_WGS_PER_CU = 16
+
+
+@dataclass
+class Table:
+    arch: str
+    variants: dict = field(default_factory=dict)   # "bw x bh / nd" -> [rows, cpl]
+    blocks_per_wave: int = DEFAULT_BLOCKS_PER_WAVE
+    match_wgs_per_cu: int = DEFAULT_MATCH_WGS_PER_CU
+    timings_ms: dict = field(default_factory=dict)  # choice -> measured time
+
+
+def shape_key(bw: int, bh: int, nd: int) -> str:
+    return f"{bw}x{bh}/{nd}"
+
+
+def path_shapes(params: dict) -> list[tuple[int, int, int]]:
+    """(bw, bh, level candidates) of the far path (level scale 1) and the close path."""
+    out = []
+    for name, scale in (("far", 1), ("close", params["close_scale"])):
+        ph = params[name]
+        shape = (ph["bw"], ph["bh"], ocsr.level_candidates(ph, scale))
+        if shape not in out:
+            out.append(shape)
+    return out
+
+
+def _arch() -> str:
+    import torch
+    return torch.cuda.get_device_properties(torch.cuda.current_device()).gcnArchName.split(":")[0]
+
+
+def _time_ms(run, reps: int, warmup: int) -> float:
+    import torch
+    for _ in range(warmup):
+        run()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    times = []
+    for _ in range(reps):
+        a.record()
+        run()
+        b.record()
+        b.synchronize()
+        times.append(a.elapsed_time(b))
+    times.sort()
+    return times[len(times) // 2]
+
+
+def _snapshot(result):
+    return result.detach().cpu().clone()
+
+
+def apply(table: Table, device: int | None = None) -> None:
+    """Installs a table's choices in the device's library context."""
+    if table.arch != _arch():
+        raise ValueError(f"table measured on {table.arch}, device is {_arch()}")
+    for key, (rows, cpl) in table.variants.items():
+        bw_bh, nd = key.split("/")
+        bw, bh = (int(v) for v in bw_bh.split("x"))
+        ocsr.set_variant(bw, bh, int(nd), rows, cpl, device)
+    ocsr.set_option(ocsr.OPTION_BLOCKS_PER_WAVE, table.blocks_per_wave, device)
+    ocsr.set_option(ocsr.OPTION_MATCH_WGS_PER_CU, table.match_wgs_per_cu, device)
+
+
+def reset(params: dict, device: int | None = None) -> None:
+    """Restores the library defaults for the paths of `params`."""
+    for bw, bh, nd in path_shapes(params):
+        ocsr.set_variant(bw, bh, nd, 0, 0, device)
+    ocsr.set_option(ocsr.OPTION_BLOCKS_PER_WAVE, DEFAULT_BLOCKS_PER_WAVE, device)
+    ocsr.set_option(ocsr.OPTION_MATCH_WGS_PER_CU, DEFAULT_MATCH_WGS_PER_CU, device)
+
+
+def tune(run, params: dict, reps: int = 20, warmup: int = 3,
+         blocks_per_wave=BLOCKS_PER_WAVE, match_wgs_per_cu=MATCH_WGS_PER_CU,
+         device: int | None = None) -> Table:
+    """Tunes the matching launches for the workload `run` (a callable that submits one
+    call and returns its result tensor) with parameters `params`.
+
+    Coordinate descent: the variant of each path shape in turn (the others at their
+    current best), then blocks per wave, then the grid. Every choice's output must equal
+    the default configuration's exactly; a choice that differs raises, since it would be
+    a library defect. The chosen configuration is left installed."""
+    reset(params, device)
+    ref = _snapshot(run())
+    table = Table(arch=_arch())
+
+    def measure(label):
+        out = _snapshot(run())
+        if not bool((out == ref).all()):
+            raise RuntimeError(f"tuning choice {label} changed the results")
+        ms = _time_ms(run, reps, warmup)
+        table.timings_ms[label] = round(ms, 5)
+        return ms
+
+    for bw, bh, nd in path_shapes(params):
+        best = None
+        for rows, cpl in ocsr.variant_candidates(bw, bh, nd):
+            ocsr.set_variant(bw, bh, nd, rows, cpl, device)
+            ms = measure(f"variant {shape_key(bw, bh, nd)} rows={rows} cpl={cpl}")
+            if best is None or ms < best[0]:
+                best = (ms, rows, cpl)
+        if best is not None:
+            ocsr.set_variant(bw, bh, nd, best[1], best[2], device)
+            table.variants[shape_key(bw, bh, nd)] = [best[1], best[2]]
+
+    best = None
+    for bpw in blocks_per_wave:
+        ocsr.set_option(ocsr.OPTION_BLOCKS_PER_WAVE, bpw, device)
+        ms = measure(f"blocks_per_wave={bpw}")
+        if best is None or ms < best[0]:
+            best = (ms, bpw)
+    table.blocks_per_wave = best[1]
+    ocsr.set_option(ocsr.OPTION_BLOCKS_PER_WAVE, table.blocks_per_wave, device)
+
+    best = None
+    for g in match_wgs_per_cu:
+        ocsr.set_option(ocsr.OPTION_MATCH_WGS_PER_CU, g, device)
+        ms = measure(f"match_wgs_per_cu={g}")
+        if best is None or ms < best[0]:
+            best = (ms, g)
+    table.match_wgs_per_cu = best[1]
+    ocsr.set_option(ocsr.OPTION_MATCH_WGS_PER_CU, table.match_wgs_per_cu, device)
+    return table
+
+
+def to_json(table: Table) -> str:
+    return json.dumps({"arch": table.arch, "variants": table.variants,
+                       "blocks_per_wave": table.blocks_per_wave,
+                       "match_wgs_per_cu": table.match_wgs_per_cu,
+                       "timings_ms": table.timings_ms}, indent=1, sort_keys=True)
+
+
+def from_json(text: str) -> Table:
+    d = json.loads(text)
+    t = Table(arch=d["arch"], variants={k: [int(v[0]), int(v[1])] for k, v in d["variants"].items()},
+              blocks_per_wave=int(d["blocks_per_wave"]),
+              match_wgs_per_cu=int(d["match_wgs_per_cu"]),
+              timings_ms=dict(d.get("timings_ms", {})))
+    for key, (rows, cpl) in t.variants.items():
+        bw_bh, nd = key.split("/")
+        bw, bh = (int(v) for v in bw_bh.split("x"))
+        if (rows, cpl) not in ocsr.variant_candidates(bw, bh, int(nd)):
+            raise ValueError(f"table entry {key}: no kernel rows={rows} cpl={cpl} covers it")
+    if not 1 <= t.blocks_per_wave <= 8 or not 1 <= t.match_wgs_per_cu <= 64:
+        raise ValueError("table launch settings out of range")
+    return t
+
+
+def save(table: Table, path: str) -> None:
+    with open(path, "w") as f:
+        f.write(to_json(table))
+
+
+def load(path: str) -> Table:
+    with open(path) as f:
+        return from_json(f.read())

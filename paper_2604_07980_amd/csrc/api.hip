@@ -4,6 +4,7 @@
 #include <cstdio>
 #include <cstring>
 #include <algorithm>
+#include <array>
 #include <functional>
 #include <list>
 #include <map>
@@ -32,6 +33,10 @@ struct ocsr_ctx {
   // graph submission: instantiated launch sequences of whole-frame calls, most
   // recently used first, keyed by everything the launches depend on
   int use_graph = 0;
+  // matching kernel variants chosen for (bw, bh, level candidates), e.g. by a tuner
+  std::map<std::array<int, 3>, std::pair<int, int>> variants;
+  int match_wgs_per_cu = 16;
+  int blocks_per_wave = 1;
   struct Graph {
     std::string key;
     hipGraphExec_t exec;
@@ -217,8 +222,8 @@ int32_t check_level(const ocsr_level* lv, const char* name, LevelDev* out) {
   return OCSR_OK;
 }
 
-int32_t build_params(const ocsr_match_params* p, int close_scale, int cap_blocks,
-                     MatchParamsDev* d) {
+int32_t build_params(const ocsr_ctx* ctx, const ocsr_match_params* p, int close_scale,
+                     int cap_blocks, MatchParamsDev* d) {
   if (!p) return fail(OCSR_E_INVALID, "null params");
   if (p->struct_size != sizeof(ocsr_match_params))
     return fail(OCSR_E_INVALID, "params.struct_size %u != %zu", p->struct_size, sizeof(ocsr_match_params));
@@ -229,10 +234,21 @@ int32_t build_params(const ocsr_match_params* p, int close_scale, int cap_blocks
   // Only the register-blocked TILED kernels are enabled: the per-candidate kernel that
   // served GRID mode and blocks wider than 8 x 8 faulted on the device in its
   // work-queue form and stays off until that is understood.
-  for (int l = 0; l < 2; ++l)
-    if (!pick_variant(d->path[l]).tiled)
-      return fail(OCSR_E_UNSUPPORTED, "%s path: GRID mode and blocks wider or taller than 8 are "
-                  "not enabled in this build", l == 0 ? "far" : "close");
+  for (int l = 0; l < 2; ++l) {
+    PathDev& ph = d->path[l];
+    const MatchVariant v = pick_variant(ph);
+    if (!v.tiled)
+      return fail(OCSR_E_UNSUPPORTED, "%s path: GRID mode, blocks wider or taller than 8 and "
+                  "more than 256 level candidates are not enabled in this build",
+                  l == 0 ? "far" : "close");
+    ph.rows = v.rows;
+    ph.cpl = v.cpl;
+    auto it = ctx->variants.find({ph.bw, ph.bh, ph.nd});
+    if (it != ctx->variants.end() && variant_valid(ph, it->second.first, it->second.second)) {
+      ph.rows = it->second.first;
+      ph.cpl = it->second.second;
+    }
+  }
   if (p->lr_tol < 0) return fail(OCSR_E_INVALID, "lr_tol < 0");
   if (p->min_point_pct < 0 || p->min_point_pct > 100) return fail(OCSR_E_INVALID, "min_point_pct outside 0..100");
   if (p->agg_mode != OCSR_AGG_SEGMENT_MEDIAN && p->agg_mode != OCSR_AGG_TRIMMED_MEDIAN)
@@ -253,6 +269,7 @@ int32_t build_params(const ocsr_match_params* p, int close_scale, int cap_blocks
   d->fb = f * b;
   d->d_eps = p->d_eps;
   d->cap_blocks = cap_blocks;
+  d->item_blocks = kItemWaves * ctx->blocks_per_wave;
   return OCSR_OK;
 }
 
@@ -284,7 +301,7 @@ size_t frame_census_bytes(int W, int H, int s) {
 }
 
 int32_t check_frames(const ocsr_frame* frames, int n_frames, const ocsr_frame_params* fp,
-                     int* n_boxes_total) {
+                     int* n_boxes_total, bool need_images = true) {
   if (!fp) return fail(OCSR_E_INVALID, "null frame params");
   if (fp->close_scale < 1 || fp->close_scale > 16) return fail(OCSR_E_INVALID, "close_scale outside 1..16");
   int32_t rc;
@@ -294,7 +311,7 @@ int32_t check_frames(const ocsr_frame* frames, int n_frames, const ocsr_frame_pa
   long long total = 0;
   for (int f = 0; f < n_frames; ++f) {
     const ocsr_frame& fr = frames[f];
-    if (!fr.imgL || !fr.imgR) return fail(OCSR_E_INVALID, "frame %d: null image", f);
+    if (need_images && (!fr.imgL || !fr.imgR)) return fail(OCSR_E_INVALID, "frame %d: null image", f);
     if (fr.width <= 0 || fr.height <= 0 || fr.width > (1 << 15) || fr.height > (1 << 15))
       return fail(OCSR_E_INVALID, "frame %d: size %dx%d outside 1..32768", f, fr.width, fr.height);
     if (fr.pitch_bytes < fr.width) return fail(OCSR_E_INVALID, "frame %d: pitch < width", f);
@@ -325,7 +342,7 @@ int32_t range_frames(ocsr_ctx* ctx, const ocsr_frame* frames, int n_frames,
   int32_t rc;
   if ((rc = check_frames(frames, n_frames, fp, &n_total)) != OCSR_OK) return rc;
   MatchParamsDev P;
-  if ((rc = build_params(params, fp->close_scale, cap_blocks, &P)) != OCSR_OK) return rc;
+  if ((rc = build_params(ctx, params, fp->close_scale, cap_blocks, &P)) != OCSR_OK) return rc;
   if (n_total > 0 && (!boxes || !out)) return fail(OCSR_E_INVALID, "null boxes or output");
   if ((rc = check_ws(ws, ws_bytes, batch_ws_bytes(frames, n_frames, fp, n_total, cap_blocks))) != OCSR_OK)
     return rc;
@@ -335,7 +352,6 @@ int32_t range_frames(ocsr_ctx* ctx, const ocsr_frame* frames, int n_frames,
   memset(&FR, 0, sizeof(FR));
   FR.n = n_frames;
   FR.n_boxes_total = n_total;
-  ocsr_census_job jobs[4 * OCSR_MAX_BATCH_FRAMES];
   char* base = (char*)ws;
   int tiles = 0;
   for (int f = 0; f < n_frames; ++f) {
@@ -357,14 +373,6 @@ int32_t range_frames(ocsr_ctx* ctx, const ocsr_frame* frames, int n_frames,
     d.tiles1 = d.tiles1_x * (int)cdiv64(H1, kCensusTileY);
     d.tile_begin = tiles;
     tiles += 2 * (d.tiles0 + d.tiles1);
-    const uint8_t* imgs[4] = {fr.imgL, fr.imgR, fr.imgL, fr.imgR};
-    uint64_t* outs[4] = {dL0, dR0, dL1, dR1};
-    for (int k = 0; k < 4; ++k) {
-      ocsr_census_job& j = jobs[4 * f + k];
-      const int sc = k < 2 ? 1 : s;
-      j.img = imgs[k]; j.out = outs[k]; j.width = W; j.height = H; j.pitch_bytes = fr.pitch_bytes;
-      j.out_pitch_elems = W / sc; j.scale = sc; j.reserved = 0;
-    }
   }
   MatchWs mws = match_ws_carve(base, n_frames, n_total, cap_blocks);
   const bool fused = ctx->use_fused && fused_available(P, fp->sx, fp->sy);
@@ -376,10 +384,10 @@ int32_t range_frames(ocsr_ctx* ctx, const ocsr_frame* frames, int n_frames,
                                   ctx->n_cu, ctx->wgs_per_cu, s, tp);
       return e == hipSuccess ? OCSR_OK : hip_fail(e, "fused launch");
     }
-    int32_t r = enqueue_census(jobs, 4 * n_frames, fp->sx, fp->sy, sentinel, s, tp);
-    if (r != OCSR_OK) return r;
-    hipError_t e = launch_match(P, FR, boxes, mws, out, make_debug(nullptr),
-                                std::max(1, ctx->n_cu * 16), s, tp);
+    hipError_t e = launch_frame_census(P, FR, boxes, mws, fp->sx, fp->sy, sentinel, tiles, s, tp);
+    if (e != hipSuccess) return hip_fail(e, "census launch");
+    e = launch_match(P, FR, boxes, mws, out, make_debug(nullptr), true,
+                     std::max(1, ctx->n_cu * ctx->match_wgs_per_cu), s, tp);
     return e == hipSuccess ? OCSR_OK : hip_fail(e, "match launch");
   };
   if (ctx->use_graph) {
@@ -394,7 +402,8 @@ int32_t range_frames(ocsr_ctx* ctx, const ocsr_frame* frames, int n_frames,
     put(&cap_blocks, sizeof(cap_blocks));
     put(&ws, sizeof(ws));
     put(&out, sizeof(out));
-    const int opts[3] = {fused ? 1 : 0, ctx->wgs_per_cu, ctx->n_cu};
+    put(&P, sizeof(P));
+    const int opts[4] = {fused ? 1 : 0, ctx->wgs_per_cu, ctx->n_cu, ctx->match_wgs_per_cu};
     put(opts, sizeof(opts));
     return graph_launch(ctx, key, enqueue, stream);
   }
@@ -495,7 +504,7 @@ int32_t ocsr_match_boxes(ocsr_ctx* ctx, const ocsr_level* lv0, const ocsr_level*
   if ((rc = check_level(lv1, "lv1", &FR.f[0].lv[1])) != OCSR_OK) return rc;
   if (lv0->scale != 1) return fail(OCSR_E_INVALID, "lv0 must have scale 1 (got %d)", lv0->scale);
   MatchParamsDev P;
-  if ((rc = build_params(params, lv1->scale, cap_blocks, &P)) != OCSR_OK) return rc;
+  if ((rc = build_params(ctx, params, lv1->scale, cap_blocks, &P)) != OCSR_OK) return rc;
   if (n_boxes < 0 || n_boxes > (1 << 20)) return fail(OCSR_E_INVALID, "n_boxes %d outside 0..2^20", n_boxes);
   if (n_boxes == 0) return OCSR_OK;
   if (!boxes || !out) return fail(OCSR_E_INVALID, "null boxes or output");
@@ -510,8 +519,9 @@ int32_t ocsr_match_boxes(ocsr_ctx* ctx, const ocsr_level* lv0, const ocsr_level*
   FR.f[0].n_boxes = n_boxes;
   MatchWs mws = match_ws_carve(ws, 1, n_boxes, cap_blocks);
   LaunchTimer t = make_timer(ctx);
-  hipError_t e = launch_match(P, FR, boxes, mws, out, make_debug(dbg), std::max(1, ctx->n_cu * 16),
-                              (hipStream_t)stream, ctx->timing ? &t : nullptr);
+  hipError_t e = launch_match(P, FR, boxes, mws, out, make_debug(dbg), false,
+                              std::max(1, ctx->n_cu * ctx->match_wgs_per_cu), (hipStream_t)stream,
+                              ctx->timing ? &t : nullptr);
   if (e != hipSuccess) return hip_fail(e, "match launch");
   if (dbg && dbg->n_blocks) {
     e = hipMemcpyAsync(dbg->n_blocks, mws.fcount + FC_NUMBERED, sizeof(int32_t),
@@ -543,7 +553,7 @@ size_t ocsr_batch_workspace_bytes(const ocsr_frame* frames, int32_t n_frames,
                                   const ocsr_frame_params* fp, int32_t cap_blocks) {
   int n_total = 0;
   const std::string saved = g_last_error;
-  const int32_t rc = check_frames(frames, n_frames, fp, &n_total);
+  const int32_t rc = check_frames(frames, n_frames, fp, &n_total, false);
   g_last_error = saved;
   if (rc != OCSR_OK) return 0;
   return batch_ws_bytes(frames, n_frames, fp, n_total, cap_blocks);
@@ -569,6 +579,15 @@ int32_t ocsr_ctx_set_option(ocsr_ctx* ctx, int32_t option, int32_t value) {
     case OCSR_OPTION_GRAPH:
       ctx->use_graph = value != 0;
       return OCSR_OK;
+    case OCSR_OPTION_MATCH_WGS_PER_CU:
+      if (value < 1 || value > 64) return fail(OCSR_E_INVALID, "match workgroups per CU outside 1..64");
+      ctx->match_wgs_per_cu = value;
+      return OCSR_OK;
+    case OCSR_OPTION_BLOCKS_PER_WAVE:
+      if (value < 1 || value > kMaxBlocksPerWave)
+        return fail(OCSR_E_INVALID, "blocks per wave outside 1..%d", kMaxBlocksPerWave);
+      ctx->blocks_per_wave = value;
+      return OCSR_OK;
     case OCSR_OPTION_WAVES_PER_CU:
       if (value < 0 || value > 32) return fail(OCSR_E_INVALID, "workgroups per CU outside 0..32");
       ctx->wgs_per_cu = value;
@@ -576,6 +595,69 @@ int32_t ocsr_ctx_set_option(ocsr_ctx* ctx, int32_t option, int32_t value) {
     default:
       return fail(OCSR_E_INVALID, "unknown option %d", option);
   }
+}
+
+size_t ocsr_dense_workspace_bytes(int32_t width, int32_t height) {
+  if (width <= 0 || height <= 0) return 0;
+  return 2 * a256((size_t)width * height * sizeof(int16_t));
+}
+
+int32_t ocsr_dense_match(ocsr_ctx* ctx, const ocsr_level* lv, int32_t dmin, int32_t dmax,
+                         int32_t radius, int32_t lr_tol, int16_t* disp, int16_t* disp_right,
+                         void* ws, size_t ws_bytes, void* stream) {
+  g_last_error.clear();
+  if (!ctx) return fail(OCSR_E_INVALID, "null context");
+  int32_t rc;
+  LevelDev L;
+  if ((rc = check_level(lv, "lv", &L)) != OCSR_OK) return rc;
+  if (!disp) return fail(OCSR_E_INVALID, "null disparity output");
+  if (dmin < 0 || dmax < dmin) return fail(OCSR_E_INVALID, "disparity range [%d, %d] invalid", dmin, dmax);
+  if (dmax - dmin + 1 > OCSR_MAX_CANDIDATES)
+    return fail(OCSR_E_CAPACITY, "%d candidates > %d", dmax - dmin + 1, OCSR_MAX_CANDIDATES);
+  if (!dense_radius_supported(radius))
+    return fail(OCSR_E_UNSUPPORTED, "window radius %d: only 1..3 are built", radius);
+  if (lr_tol < 0) return fail(OCSR_E_INVALID, "lr_tol < 0");
+  if ((rc = check_ws(ws, ws_bytes, ocsr_dense_workspace_bytes(L.W, L.H))) != OCSR_OK) return rc;
+  int16_t* d_left = (int16_t*)ws;
+  int16_t* d_right = disp_right ? disp_right
+                                : (int16_t*)((char*)ws + a256((size_t)L.W * L.H * sizeof(int16_t)));
+  LaunchTimer t = make_timer(ctx);
+  hipError_t e = launch_dense(L.L, L.R, L.W, L.H, L.pitch, dmin, dmax, radius, lr_tol, disp, d_left,
+                              d_right, (hipStream_t)stream, ctx->timing ? &t : nullptr);
+  if (e != hipSuccess) return hip_fail(e, "dense launch");
+  return OCSR_OK;
+}
+
+int32_t ocsr_variant_candidates(int32_t bw, int32_t bh, int32_t n_candidates, int32_t* rows,
+                                int32_t* cpl, int32_t cap) {
+  g_last_error.clear();
+  if (cap < 0 || (cap > 0 && (!rows || !cpl))) return fail(OCSR_E_INVALID, "null output arrays");
+  PathDev ph = {};
+  ph.mode = OCSR_MODE_TILED;
+  ph.bw = bw;
+  ph.bh = bh;
+  ph.nd = n_candidates;
+  return variant_candidates(ph, rows, cpl, cap);
+}
+
+int32_t ocsr_ctx_set_variant(ocsr_ctx* ctx, int32_t bw, int32_t bh, int32_t n_candidates,
+                             int32_t rows, int32_t cpl) {
+  g_last_error.clear();
+  if (!ctx) return fail(OCSR_E_INVALID, "null context");
+  if (rows == 0) {
+    ctx->variants.erase({bw, bh, n_candidates});
+    return OCSR_OK;
+  }
+  PathDev ph = {};
+  ph.mode = OCSR_MODE_TILED;
+  ph.bw = bw;
+  ph.bh = bh;
+  ph.nd = n_candidates;
+  if (!variant_valid(ph, rows, cpl))
+    return fail(OCSR_E_INVALID, "no kernel with %d rows and %d candidates per lane covers %dx%d "
+                "blocks and %d candidates", rows, cpl, bw, bh, n_candidates);
+  ctx->variants[{bw, bh, n_candidates}] = {rows, cpl};
+  return OCSR_OK;
 }
 
 int32_t ocsr_ctx_graph_stats(ocsr_ctx* ctx, int64_t* hits, int64_t* builds) {

@@ -46,28 +46,42 @@ __device__ __forceinline__ void census_tile(const uint8_t* __restrict__ img, int
   using T = CensusTile<SX, SY>;
   constexpr int LW = T::LW, PR = T::PR, WR = T::WR, N = T::N;
   const int Ws = W / s, Hs = H / s;
-  // P[r * LW + c] = I(c, r) | I(c, r + 1) << 16 over the tile and its halo. Every
-  // load of the fill is issued before the first one is waited for: a load whose pixel
-  // lies outside the level image reads the image's first byte instead and is zeroed.
-  constexpr int NFILL = (PR * LW + 255) / 256;
-  uint32_t lo[NFILL], hi[NFILL];
+  // P[r * LW + c] = I(c, r) | I(c, r + 1) << 16 over the tile and its halo. Wave w
+  // loads source rows w*RB .. w*RB + RB of the tile (one more than the pair rows it
+  // writes): the row address is wave-uniform, so each load is one scalar base plus
+  // the lane's column offset. All loads are issued before the first is waited for; a
+  // pixel outside the level image reads a valid byte instead and is zeroed.
+  constexpr int RB = (PR + 1 + 3) / 4;
+  constexpr int NPASS = (LW + 63) / 64;
+  {
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    uint32_t px[NPASS][RB + 1];
 #pragma unroll
-  for (int k = 0; k < NFILL; ++k) {
-    const int idx = threadIdx.x + 256 * k;
-    const int pr = idx / LW, pc = idx - pr * LW;
-    const int X = X0 - SX + pc, Y = Y0 - SY + pr;
-    const bool x_ok = idx < PR * LW && X >= 0 && X < Ws;
-    const bool ok0 = x_ok && Y >= 0 && Y < Hs;
-    const bool ok1 = x_ok && Y + 1 >= 0 && Y + 1 < Hs;
-    lo[k] = img[ok0 ? (size_t)(s * Y) * pitch + (size_t)(s * X) : 0];
-    hi[k] = img[ok1 ? (size_t)(s * (Y + 1)) * pitch + (size_t)(s * X) : 0];
-    lo[k] = ok0 ? lo[k] : 0u;
-    hi[k] = ok1 ? hi[k] : 0u;
-  }
+    for (int cp = 0; cp < NPASS; ++cp) {
+      const int pc = lane + 64 * cp;
+      const int X = X0 - SX + pc;
+      const bool x_ok = pc < LW && X >= 0 && X < Ws;
+      const int coff = x_ok ? s * X : 0;
 #pragma unroll
-  for (int k = 0; k < NFILL; ++k) {
-    const int idx = threadIdx.x + 256 * k;
-    if (idx < PR * LW) P[idx] = lo[k] | (hi[k] << 16);
+      for (int k = 0; k <= RB; ++k) {
+        const int r = wave * RB + k;
+        const int Y = Y0 - SY + r;
+        const bool y_ok = r <= PR && Y >= 0 && Y < Hs;
+        const uint8_t* rp = img + (y_ok ? (size_t)(s * Y) * pitch : 0);
+        const uint32_t v = rp[coff];
+        px[cp][k] = (x_ok && y_ok) ? v : 0u;
+      }
+    }
+#pragma unroll
+    for (int cp = 0; cp < NPASS; ++cp) {
+      const int pc = lane + 64 * cp;
+#pragma unroll
+      for (int k = 0; k < RB; ++k) {
+        const int pr = wave * RB + k;
+        if (pr < PR && pc < LW) P[pr * LW + pc] = px[cp][k] | (px[cp][k + 1] << 16);
+      }
+    }
   }
   __syncthreads();
 
@@ -83,23 +97,36 @@ __device__ __forceinline__ void census_tile(const uint8_t* __restrict__ img, int
   const bool x_in = X < Ws;
   const bool x_def = X >= SX && X < Ws - SX;
   constexpr int NP = kCensusRowsPerLane / 2;
+  static_assert(NP == 4, "the accumulation barrier below names four pairs");
   // pair pp holds pixels A = (X, Y0 + r0 + 2pp) and B = (X, YA + 1) in its low / high half
   uint32_t acc[NP][8];
+  u16x2 c2[NP];
 #pragma unroll
   for (int pp = 0; pp < NP; ++pp) {
 #pragma unroll
     for (int k = 0; k < 8; ++k) acc[pp][k] = 0;
-    const u16x2 c2 = __builtin_bit_cast(u16x2, v[SX][2 * pp + SY]);
+    c2[pp] = __builtin_bit_cast(u16x2, v[SX][2 * pp + SY]);
+  }
 #pragma unroll
-    for (int i = 0; i < 2 * SX + 1; ++i) {
+  for (int i = 0; i < 2 * SX + 1; ++i) {
 #pragma unroll
-      for (int jj = 0; jj < 2 * SY + 1; ++jj) {
+    for (int jj = 0; jj < 2 * SY + 1; ++jj) {
+      const int pos = N - 1 - (i * (2 * SY + 1) + jj);   // Alg. 1 order, MSB first
+      const int q = pos >> 3;
+      uint32_t d[NP];
+#pragma unroll
+      for (int pp = 0; pp < NP; ++pp) {
         // half = centre - neighbour: in 0..255 when the neighbour is not brighter, in
         // 0xFF01..0xFFFF when it is, so bits 8..15 of each half all equal the bit
-        const u16x2 d = c2 - __builtin_bit_cast(u16x2, v[i][2 * pp + jj]);
-        const int pos = N - 1 - (i * (2 * SY + 1) + jj);   // Alg. 1 order, MSB first
-        acc[pp][pos >> 3] |= __builtin_bit_cast(uint32_t, d) & (0x01000100u << (pos & 7));
+        d[pp] = __builtin_bit_cast(uint32_t, c2[pp] - __builtin_bit_cast(u16x2, v[i][2 * pp + jj]));
       }
+#pragma unroll
+      for (int pp = 0; pp < NP; ++pp) acc[pp][q] = (d[pp] & (0x01000100u << (pos & 7))) | acc[pp][q];
+      // One v_and_or_b32 per comparison and pair. The empty asm keeps the compiler from
+      // regrouping the ORs into v_or3_b32 trees (an extra v_and_b32 per bit); the four
+      // pairs' subtracts are issued ahead of their AND-ORs, so no packed-result wait
+      // state is needed.
+      asm volatile("" : "+v"(acc[0][q]), "+v"(acc[1][q]), "+v"(acc[2][q]), "+v"(acc[3][q]));
     }
   }
 #pragma unroll
@@ -147,6 +174,36 @@ __device__ __forceinline__ void census_tile_generic(const uint8_t* __restrict__ 
         }
     }
     out[(size_t)Y * out_pitch + X] = code;
+  }
+}
+
+// Census tile c of a whole-frame call: the tiles of frame f start at
+// FR.f[f].tile_begin and run over view L then R at level 0, then L and R at level 1.
+// Window (SX, SY) > (-1, -1) takes the LDS code; (-1, -1) the generic code with (sx, sy).
+template <int SX, int SY>
+__device__ __forceinline__ void frame_census_tile(const FramesDev& FR, int c, int sx, int sy,
+                                                  int sentinel, uint32_t* P) {
+  int f = 0;
+  for (int k = 1; k < FR.n; ++k)
+    if (c >= FR.f[k].tile_begin) f = k;
+  const FrameDev& fr = FR.f[f];
+  int t = c - fr.tile_begin, level = 0, tiles = fr.tiles0, tiles_x = fr.tiles0_x;
+  if (t >= 2 * fr.tiles0) {
+    t -= 2 * fr.tiles0;
+    level = 1;
+    tiles = fr.tiles1;
+    tiles_x = fr.tiles1_x;
+  }
+  const int view = t / tiles;
+  t -= view * tiles;
+  const LevelDev& lv = fr.lv[level];
+  const uint8_t* img = view ? fr.imgR : fr.imgL;
+  uint64_t* out = (uint64_t*)(view ? lv.R : lv.L);
+  const int X0 = (t % tiles_x) * kCensusTileX, Y0 = (t / tiles_x) * kCensusTileY;
+  if constexpr (SX >= 0) {
+    census_tile<SX, SY>(img, fr.W, fr.H, fr.pitch, lv.scale, out, lv.pitch, X0, Y0, sentinel, P);
+  } else {
+    census_tile_generic(img, fr.W, fr.H, fr.pitch, lv.scale, out, lv.pitch, X0, Y0, sx, sy, sentinel);
   }
 }
 

@@ -40,33 +40,17 @@ __device__ __forceinline__ uint64_t ld_word(const uint64_t* __restrict__ row, in
   return (x >= 0 && x < W) ? row[x] : 0ull;
 }
 
-// device-scope counters of the fused persistent launch
+// device-scope counters
 __device__ __forceinline__ int add_release(int32_t* p, int v) {
   return __hip_atomic_fetch_add(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ int load_acquire(const int32_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ int load_relaxed(const int32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Bounded wait until *p >= target (the producers are running workgroups that hold
-// earlier queue items, so the wait ends; the bound only guards against a defect).
-// Returns false when the bound expired; the call then flags the timeout.
+// Bound on the spin of a grid barrier: the arrivals come from resident workgroups, so
+// the wait ends; the bound only guards against a defect.
 constexpr int kSpinLimit = 1 << 22;
-__device__ __forceinline__ bool wait_at_least(const int32_t* p, int target, int32_t* timeout_flag) {
-  int spins = 0;
-  while (load_relaxed(p) < target) {
-    if (++spins > kSpinLimit) {
-      __hip_atomic_store(timeout_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      return false;
-    }
-    __builtin_amdgcn_s_sleep(2);
-  }
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // later loads see the producers' data
-  return true;
-}
 
 // Publishes a workgroup's global writes before one thread signals a counter: every
 // wave waits for its own stores, then the workgroup meets at a barrier.

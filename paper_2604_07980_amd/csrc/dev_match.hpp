@@ -2,8 +2,8 @@
 // the multi-launch kernels (match.hip) and the fused persistent kernel (fused.hip).
 //
 //   plan_frame        one wave per frame: clip, far/close type (Sec. 4.3.4 type
-//                     equation), level box, block grid, block numbers
-//   match_block_*     one wave per block: occluder mask (Sec. 4.3.5), forward Hamming
+//                     equation), level box, block grid, block and work-item numbers
+//   match_block_tiled one wave per block: occluder mask (Sec. 4.3.5), forward Hamming
 //                     search (census cost equation), winner-take-all, parabola
 //                     (sub-pixel equation), backward search and L/R check (Sec. 4.3.3)
 //   aggregate_box     one workgroup per box: longest-segment or trimmed median of the
@@ -89,21 +89,22 @@ __device__ __forceinline__ void plan_frame(const MatchParamsDev& P, const FrameD
       if ((long long)off + count > (long long)P.cap_blocks) pl.status = OCSR_REASON_CAPACITY_OVERFLOW;
       else nblk = count;
     }
-    const int c0 = (pl.status == -1 && pl.level == 0) ? nblk : 0;
-    const int c1 = (pl.status == -1 && pl.level == 1) ? nblk : 0;
+    // work items of item_blocks blocks, per level
+    const int nitem = (nblk + P.item_blocks - 1) / P.item_blocks;
+    const int c0 = (pl.status == -1 && pl.level == 0) ? nitem : 0;
+    const int c1 = (pl.status == -1 && pl.level == 1) ? nitem : 0;
     const int incl0 = wave_incl_scan(c0, lane);
     const int incl1 = wave_incl_scan(c1, lane);
     if (i < n) {
       const int g = fr.box_off + i;
       pl.off = off;
       pl.nblk = nblk;
-      pl.loff = pl.level == 0 ? carry0 + incl0 - c0 : carry1 + incl1 - c1;
+      pl.ioff = pl.level == 0 ? carry0 + incl0 - c0 : carry1 + incl1 - c1;
       pl.frame = f;
       ws.plan[g] = pl;
       ws.clip[g] = cl;
-      ws.lbox_end[g] = carry0 + incl0;
-      ws.lbox_end[n_total + g] = carry1 + incl1;
-      ws.box_done[g] = 0;
+      ws.litem_end[g] = carry0 + incl0;
+      ws.litem_end[n_total + g] = carry1 + incl1;
     }
     matched_end = max(matched_end, wave_max(nblk > 0 ? off + nblk : 0));
     carry += __shfl(incl, 63, 64);
@@ -114,8 +115,8 @@ __device__ __forceinline__ void plan_frame(const MatchParamsDev& P, const FrameD
     int32_t* fc = ws.fcount + f * FC_N;
     fc[FC_NUMBERED] = carry;
     fc[FC_MATCHED] = matched_end;
-    fc[FC_FAR] = carry0;
-    fc[FC_CLOSE] = carry1;
+    fc[FC_FAR_ITEMS] = carry0;
+    fc[FC_CLOSE_ITEMS] = carry1;
   }
 }
 
@@ -208,33 +209,32 @@ struct BlockCtx {
   BlockGeom g;
 };
 
+// block `local` (0-based, row-major over the box's block grid) of box k of frame f
 __device__ __forceinline__ BlockCtx block_ctx(const MatchParamsDev& P, const FrameDev& fr, int f,
-                                              int n_total, const MatchWs& ws, int level, int q,
-                                              int lane) {
+                                              int k, const BoxPlan& pl, int local, int level) {
   BlockCtx c;
   c.f = f;
   c.level = level;
-  c.k = find_box(ws.lbox_end + (size_t)level * n_total + fr.box_off, fr.n_boxes, q, lane);
-  c.kg = fr.box_off + c.k;
-  c.pl = ws.plan[c.kg];
-  const int local = q - c.pl.loff;
-  c.b = c.pl.off + local;
+  c.k = k;
+  c.kg = fr.box_off + k;
+  c.pl = pl;
+  c.b = pl.off + local;
   c.slot = f * P.cap_blocks + c.b;
-  c.v = local / c.pl.nbx;
-  c.u = local - c.v * c.pl.nbx;
+  c.v = local / pl.nbx;
+  c.u = local - c.v * pl.nbx;
   const LevelDev& lv = fr.lv[level];
-  c.g.nx = c.pl.bw; c.g.ny = c.pl.bh; c.g.s = lv.scale;
+  c.g.nx = pl.bw; c.g.ny = pl.bh; c.g.s = lv.scale;
   c.g.tiled = P.path[level].mode == OCSR_MODE_TILED;
-  c.g.cx = c.pl.ox + c.u * c.pl.bw; c.g.lx0 = c.pl.lx0; c.g.lw = c.pl.lw;
-  c.g.cy = c.pl.oy + c.v * c.pl.bh; c.g.ly0 = c.pl.ly0; c.g.lh = c.pl.lh;
+  c.g.cx = pl.ox + c.u * pl.bw; c.g.lx0 = pl.lx0; c.g.lw = pl.lw;
+  c.g.cy = pl.oy + c.v * pl.bh; c.g.ly0 = pl.ly0; c.g.lh = pl.lh;
   return c;
 }
 
-// Stores the block's result; with `track`, then counts the block as done for its box.
+// Stores the block's result (lane 0 of the wave).
 __device__ __forceinline__ void write_block(const MatchWs& ws, const DebugDev& dbg,
                                             const BlockCtx& c, const PathDev& ph, uint64_t mask,
                                             bool eligible, int d_f, int d_b, int lr_ok,
-                                            float d_sub, int valid, bool track, int lane) {
+                                            float d_sub, int valid, int lane) {
   if (lane == 0) {
     ws.blk_val[c.slot] = (float)c.g.s * d_sub;   // d_full = s * d (Sec. 4.1)
     ws.blk_flag[c.slot] = (uint8_t)((eligible ? 1 : 0) | (valid ? 2 : 0));
@@ -247,103 +247,7 @@ __device__ __forceinline__ void write_block(const MatchWs& ws, const DebugDev& d
       rec.dlo = ph.dlo; rec.nd = ph.nd;
       dbg.blocks[c.b] = rec;
     }
-    if (track) {
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-      add_release(ws.box_done + c.kg, 1);
-    }
   }
-}
-
-// ---------------------------------------------------------------------------------
-// generic block (any shape, GRID mode): lanes over candidates, straight from memory
-// ---------------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t pick4(const uint32_t a[4], int r) {
-  return r == 0 ? a[0] : r == 1 ? a[1] : r == 2 ? a[2] : a[3];
-}
-
-// S(d) for the 64 * 4 candidates of a wave: forward (dir > 0) or backward.
-__device__ __forceinline__ void block_costs(const LevelDev& lv, const BlockGeom& g, uint64_t mask,
-                                            int dlo, int nd, int dir, int d_f, int lane,
-                                            uint32_t acc[4]) {
-  acc[0] = acc[1] = acc[2] = acc[3] = 0;
-  const int npts = g.nx * g.ny;
-  for (int t = 0; t < npts; ++t) {
-    if (!((mask >> t) & 1ull)) continue;
-    const int j = t / g.nx, i = t - j * g.nx;
-    const int x = geom_col(g, i), y = geom_row(g, j);
-    const uint64_t* __restrict__ rowL = lv.L + (size_t)y * lv.pitch;
-    const uint64_t* __restrict__ rowR = lv.R + (size_t)y * lv.pitch;
-    if (dir > 0) {
-      const uint64_t tmpl = rowL[x];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int kc = lane + 64 * r;
-        if (kc < nd) acc[r] += __popcll(tmpl ^ ld_word(rowR, x - (dlo + kc), lv.W));
-      }
-    } else {
-      const int q = x - d_f;
-      const uint64_t tmpl = ld_word(rowR, q, lv.W);
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int kc = lane + 64 * r;
-        if (kc < nd) acc[r] += __popcll(tmpl ^ ld_word(rowL, q + dlo + kc, lv.W));
-      }
-    }
-  }
-}
-
-// smallest index attaining the minimum cost (key = cost << 16 | index)
-__device__ __forceinline__ uint32_t wta4(const uint32_t acc[4], int nd, int lane) {
-  uint32_t key = 0xFFFFFFFFu;
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int kc = lane + 64 * r;
-    if (kc < nd) key = min(key, (acc[r] << 16) | (uint32_t)kc);
-  }
-  return wave_min_u32(key);
-}
-
-__device__ __forceinline__ uint32_t cost_at(const uint32_t acc[4], int k) {
-  return (uint32_t)__shfl((int)pick4(acc, k >> 6), k & 63, 64);
-}
-
-__device__ __forceinline__ void match_block_generic(const MatchParamsDev& P, const FrameDev& fr,
-                                                    int f, int n_total, const MatchWs& ws,
-                                                    const DebugDev& dbg, int level, int q,
-                                                    bool track, int lane) {
-  const BlockCtx c = block_ctx(P, fr, f, n_total, ws, level, q, lane);
-  const LevelDev& lv = fr.lv[level];
-  const PathDev& ph = P.path[level];
-  const uint64_t mask = block_mask(ws, fr.box_off, fr.n_boxes, c.k, c.g, lane);
-  const bool eligible = block_eligible(P, mask, c.g.nx * c.g.ny);
-  int d_f = ph.dlo, d_b = ph.dlo, lr_ok = 0, valid = 0;
-  float d_sub = (float)ph.dlo;
-  uint32_t fwd[4] = {0, 0, 0, 0}, bwd[4] = {0, 0, 0, 0};
-  if (eligible) {
-    block_costs(lv, c.g, mask, ph.dlo, ph.nd, +1, 0, lane, fwd);
-    const uint32_t key = wta4(fwd, ph.nd, lane);
-    const int best = (int)(key & 0xFFFFu);
-    d_f = ph.dlo + best;
-    const int ca = (int)cost_at(fwd, max(best - 1, 0));
-    const int cb = (int)cost_at(fwd, min(best + 1, ph.nd - 1));
-    d_sub = subpixel(d_f, best, ph.nd, ca, (int)(key >> 16), cb);
-    block_costs(lv, c.g, mask, ph.dlo, ph.nd, -1, d_f, lane, bwd);
-    const uint32_t bkey = wta4(bwd, ph.nd, lane);
-    d_b = ph.dlo + (int)(bkey & 0xFFFFu);
-    lr_ok = abs(d_b - d_f) <= P.lr_tol;
-    valid = lr_ok;
-  }
-  if (eligible && c.b < dbg.cap_blocks) {
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int kc = lane + 64 * r;
-      if (kc < ph.nd && kc < dbg.cap_nd) {
-        if (dbg.cost_fwd) dbg.cost_fwd[(size_t)c.b * dbg.cap_nd + kc] = (uint16_t)fwd[r];
-        if (dbg.cost_bwd) dbg.cost_bwd[(size_t)c.b * dbg.cap_nd + kc] = (uint16_t)bwd[r];
-      }
-    }
-  }
-  write_block(ws, dbg, c, ph, mask, eligible, d_f, d_b, lr_ok, d_sub, valid, track, lane);
 }
 
 // ---------------------------------------------------------------------------------
@@ -435,9 +339,8 @@ struct Tiled {
 
 template <int ROWS, int NX, int CPL>
 __device__ __forceinline__ void match_block_tiled(const MatchParamsDev& P, const FrameDev& fr,
-                                                  int f, int n_total, const MatchWs& ws,
-                                                  const DebugDev& dbg, int level, int q,
-                                                  bool track, int lane, void* lds) {
+                                                  const MatchWs& ws, const DebugDev& dbg,
+                                                  const BlockCtx& c, int lane, void* lds) {
   using TT = Tiled<ROWS, NX, CPL>;
   constexpr int SW = TT::SW, NC = TT::NC;
   uint64_t* S = (uint64_t*)lds;
@@ -445,11 +348,10 @@ __device__ __forceinline__ void match_block_tiled(const MatchParamsDev& P, const
   uint32_t* costf = (uint32_t*)(T + ROWS * NX);
   uint32_t* costb = costf + NC;
   const int j = lane % ROWS, grp = lane / ROWS;
-  const LevelDev& lv = fr.lv[level];
-  const PathDev& ph = P.path[level];
+  const LevelDev& lv = fr.lv[c.level];
+  const PathDev& ph = P.path[c.level];
   const int nd = ph.nd, dlo = ph.dlo, dhi = dlo + nd - 1;
 
-  const BlockCtx c = block_ctx(P, fr, f, n_total, ws, level, q, lane);
   const int nx = c.g.nx, ny = c.g.ny;
   const int X0 = c.g.cx, Y0 = c.g.cy;
   const uint64_t* __restrict__ Lb = lv.L + (size_t)Y0 * lv.pitch;
@@ -463,7 +365,7 @@ __device__ __forceinline__ void match_block_tiled(const MatchParamsDev& P, const
   const bool eligible = block_eligible(P, mask, nx * ny);
   wave_sync();
   if (!eligible) {
-    write_block(ws, dbg, c, ph, mask, false, dlo, dlo, 0, (float)dlo, 0, track, lane);
+    write_block(ws, dbg, c, ph, mask, false, dlo, dlo, 0, (float)dlo, 0, lane);
     wave_sync();
     return;
   }
@@ -525,18 +427,19 @@ __device__ __forceinline__ void match_block_tiled(const MatchParamsDev& P, const
       if (dbg.cost_bwd) dbg.cost_bwd[(size_t)c.b * dbg.cap_nd + kc] = (uint16_t)costb[kc];
     }
   }
-  write_block(ws, dbg, c, ph, mask, true, d_f, d_b, lr_ok, d_sub, lr_ok, track, lane);
+  write_block(ws, dbg, c, ph, mask, true, d_f, d_b, lr_ok, d_sub, lr_ok, lane);
   wave_sync();
 }
 
-// Grid-stride loop of one wave over the blocks of one level of every frame: frames in
-// order, each frame's level blocks in box order. Block numbers come from the workgroup
-// index, so the loop is uniform across the wave and needs no shared counter.
+// Grid-stride loop of a workgroup over the work items of one level of every frame:
+// frames in order, each frame's items in box order. Item numbers come from the
+// workgroup index, so the loop is uniform across the workgroup and needs no shared
+// counter. body(f, q) gets the frame and the item number within the frame's level.
 template <class Body>
-__device__ __forceinline__ void level_blocks(const FramesDev& FR, const MatchWs& ws, int level,
-                                             Body body) {
+__device__ __forceinline__ void level_items(const FramesDev& FR, const MatchWs& ws, int level,
+                                            Body body) {
   const int lane = threadIdx.x & 63;
-  const int cnt = lane < FR.n ? ws.fcount[lane * FC_N + (level == 0 ? FC_FAR : FC_CLOSE)] : 0;
+  const int cnt = lane < FR.n ? ws.fcount[lane * FC_N + (level == 0 ? FC_FAR_ITEMS : FC_CLOSE_ITEMS)] : 0;
   const int incl = wave_incl_scan(cnt, lane);
   const int total = __builtin_amdgcn_readfirstlane(__shfl(incl, 63, 64));
   for (int q = blockIdx.x; q < total; q += gridDim.x) {
@@ -734,6 +637,24 @@ __device__ __forceinline__ void aggregate_box(const MatchParamsDev& P, const Mat
       }
     }
     out[kg] = r;
+  }
+}
+
+// ---------------------------------------------------------------------------------
+// work items
+// ---------------------------------------------------------------------------------
+// Work item q of the frame's level: wave w of the workgroup runs blocks
+// item_blocks * (q - first item of the box) + w + 4 j of the item's box that exist.
+template <class RunBlock>
+__device__ __forceinline__ void run_item(const MatchParamsDev& P, const FrameDev& fr, int f,
+                                         int n_total, const MatchWs& ws, int level, int q,
+                                         int wave, int lane, RunBlock run) {
+  const int k = find_box(ws.litem_end + (size_t)level * n_total + fr.box_off, fr.n_boxes, q, lane);
+  const BoxPlan pl = ws.plan[fr.box_off + k];
+  const int first = P.item_blocks * (q - pl.ioff);
+  for (int j = wave; j < P.item_blocks; j += kItemWaves) {
+    const int local = first + j;
+    if (local < pl.nblk) run(block_ctx(P, fr, f, k, pl, local, level));
   }
 }
 

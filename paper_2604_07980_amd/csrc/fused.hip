@@ -5,9 +5,9 @@
 // all of them are resident, and the launch runs in three phases split by grid barriers:
 //   1. the plan of every frame, then every census tile (64 x 32 level pixels of one view
 //      at one level), dealt round-robin to the workgroups;
-//   2. the blocks of every frame (close blocks of a frame first, then its far blocks),
-//      four per work item, one per wave;
-//   3. one box per work item: aggregation and depth.
+//   2. the work items of every frame (all close items first, then all far items), up to
+//      item_blocks blocks of one box per item, spread over the four waves;
+//   3. one box per workgroup: aggregation and depth.
 // Work is dealt by workgroup index, so no shared counter is touched per item; each
 // barrier costs one atomic per workgroup, spread over kBarSlots counters. Its wait is
 // bounded: an expired wait (which needs a workgroup that was not resident) marks every
@@ -18,36 +18,16 @@
 namespace ocsr {
 namespace {
 
-struct VGeneric {
-  static constexpr bool tiled = false;
-  static constexpr size_t kLdsBytes = 0;
-};
 template <int ROWS, int NX, int CPL>
 struct VTiled {
-  static constexpr bool tiled = true;
   static constexpr int rows = ROWS, nx = NX, cpl = CPL;
   static constexpr size_t kLdsBytes = dev::Tiled<ROWS, NX, CPL>::kLdsBytes;
 };
 
-template <class V>
-__device__ __forceinline__ void run_block(const MatchParamsDev& P, const FrameDev& fr, int f,
-                                          int n_total, const MatchWs& ws, int level, int q,
-                                          int lane, void* lds) {
-  const DebugDev no_dbg = {0, 0, nullptr, nullptr, nullptr, nullptr};
-  if constexpr (V::tiled) {
-    dev::match_block_tiled<V::rows, V::nx, V::cpl>(P, fr, f, n_total, ws, no_dbg, level, q, false,
-                                                  lane, lds);
-  } else {
-    dev::match_block_generic(P, fr, f, n_total, ws, no_dbg, level, q, false, lane);
-  }
-}
-
 constexpr size_t cmax(size_t a, size_t b) { return a > b ? a : b; }
 
-__global__ __launch_bounds__(64) void reset_kernel(MatchWs ws, int n_frames) {
-  const int t = threadIdx.x;
-  if (t < GC_N) ws.gcount[t] = 0;
-  for (int i = t; i < n_frames * FC_N; i += 64) ws.fcount[i] = 0;
+__global__ __launch_bounds__(64) void reset_kernel(MatchWs ws) {
+  if (threadIdx.x < GC_N) ws.gcount[threadIdx.x] = 0;
 }
 
 template <int CSX, int CSY, class FV, class CV>
@@ -59,8 +39,9 @@ __global__ __launch_bounds__(256) void fused_kernel(MatchParamsDev P, FramesDev 
   constexpr size_t kLds = cmax(cmax(dev::CensusTile<CSX, CSY>::kLdsBytes, 4 * kWave),
                                sizeof(dev::AggLds));
   __shared__ uint64_t lds[(kLds + 7) / 8];
-  __shared__ int mprefix[kMaxFrames + 1];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  __shared__ int mprefix[2 * kMaxFrames + 1];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int G = gridDim.x, w = blockIdx.x;
   const int F = FR.n;
   int32_t* timeout = ws.gcount + GC_TIMEOUT;
@@ -70,58 +51,47 @@ __global__ __launch_bounds__(256) void fused_kernel(MatchParamsDev P, FramesDev 
     if (a < F) {
       if (wave == 0) dev::plan_frame(P, FR.f[a], a, FR.n_boxes_total, boxes, ws, lane);
     } else {
-      const int c = a - F;
-      int f = 0;
-      for (int k = 1; k < F; ++k)
-        if (c >= FR.f[k].tile_begin) f = k;
-      const FrameDev& fr = FR.f[f];
-      int t = c - fr.tile_begin, level = 0, tiles = fr.tiles0, tiles_x = fr.tiles0_x;
-      if (t >= 2 * fr.tiles0) {
-        t -= 2 * fr.tiles0;
-        level = 1;
-        tiles = fr.tiles1;
-        tiles_x = fr.tiles1_x;
-      }
-      const int view = t / tiles;
-      t -= view * tiles;
-      const LevelDev& lv = fr.lv[level];
-      dev::census_tile<CSX, CSY>(view ? fr.imgR : fr.imgL, fr.W, fr.H, fr.pitch, lv.scale,
-                                 (uint64_t*)(view ? lv.R : lv.L), lv.pitch,
-                                 (t % tiles_x) * kCensusTileX, (t / tiles_x) * kCensusTileY,
-                                 sentinel, (uint32_t*)lds);
+      dev::frame_census_tile<CSX, CSY>(FR, a - F, CSX, CSY, sentinel, (uint32_t*)lds);
     }
     __syncthreads();   // the next item reuses the LDS
   }
   dev::grid_barrier(ws.gcount + GC_BAR0, G, timeout);
+  bool timed_out = dev::load_relaxed(timeout) != 0;
 
-  // ---- phase 2: blocks, four per item (close blocks of a frame first)
+  // ---- phase 2: work items; close items of every frame, then far items
   if (tid < 64) {
-    const int cnt = lane < F ? ws.fcount[lane * FC_N + FC_CLOSE] + ws.fcount[lane * FC_N + FC_FAR] : 0;
+    // mprefix[j] = items before slot j, slot j < F: close items of frame j, else far
+    // items of frame j - F
+    const int j = lane < F ? lane : lane - F;
+    const int cnt = lane < 2 * F ? ws.fcount[j * FC_N + (lane < F ? FC_CLOSE_ITEMS : FC_FAR_ITEMS)] : 0;
     const int incl = dev::wave_incl_scan(cnt, lane);
-    if (lane < F) mprefix[lane + 1] = incl;
+    if (lane < 2 * F) mprefix[lane + 1] = incl;
     if (lane == 0) mprefix[0] = 0;
   }
   __syncthreads();
-  const int n_blocks = mprefix[F];
-  for (int m = w; 4 * m < n_blocks; m += G) {
-    const int g = 4 * m + wave;
-    if (g < n_blocks) {
-      int f = 0;
-      for (int k = 1; k < F; ++k)
-        if (g >= mprefix[k]) f = k;
-      const FrameDev& fr = FR.f[f];
-      const int local = g - mprefix[f];
-      const int n_close = ws.fcount[f * FC_N + FC_CLOSE];
-      void* wl = (char*)lds + wave * kWave;
-      if (local < n_close) run_block<CV>(P, fr, f, FR.n_boxes_total, ws, 1, local, lane, wl);
-      else run_block<FV>(P, fr, f, FR.n_boxes_total, ws, 0, local - n_close, lane, wl);
+  const int n_items = timed_out ? 0 : mprefix[2 * F];
+  void* wl = (char*)lds + wave * kWave;
+  for (int m = w; m < n_items; m += G) {
+    int slot = 0;
+    for (int k = 1; k < 2 * F; ++k)
+      if (m >= mprefix[k]) slot = k;
+    const int f = slot < F ? slot : slot - F;
+    const FrameDev& fr = FR.f[f];
+    const int q = m - mprefix[slot];
+    if (slot < F) {
+      dev::run_item(P, fr, f, FR.n_boxes_total, ws, 1, q, wave, lane, [&](const dev::BlockCtx& c) {
+        dev::match_block_tiled<CV::rows, CV::nx, CV::cpl>(P, fr, ws, DebugDev{}, c, lane, wl);
+      });
+    } else {
+      dev::run_item(P, fr, f, FR.n_boxes_total, ws, 0, q, wave, lane, [&](const dev::BlockCtx& c) {
+        dev::match_block_tiled<FV::rows, FV::nx, FV::cpl>(P, fr, ws, DebugDev{}, c, lane, wl);
+      });
     }
-    __syncthreads();
   }
   dev::grid_barrier(ws.gcount + GC_BAR1, G, timeout);
+  timed_out = dev::load_relaxed(timeout) != 0;
 
-  // ---- phase 3: aggregation, one box per item
-  const bool timed_out = dev::load_relaxed(timeout) != 0;
+  // ---- phase 3: aggregation, one box per workgroup
   for (int k = w; k < FR.n_boxes_total; k += G) {
     dev::aggregate_box(P, ws, k, out, timed_out, *(dev::AggLds*)lds);
     __syncthreads();
@@ -132,8 +102,9 @@ enum class FusedPair { kNone, k4_2__8_12, k4_2__8_8, k4_2__8_16, k8_8__8_12 };
 
 FusedPair fused_pair(const MatchParamsDev& P, int sx, int sy) {
   if (sx != 3 || sy != 4) return FusedPair::kNone;
-  const MatchVariant f = pick_variant(P.path[0]), c = pick_variant(P.path[1]);
-  if (!f.tiled || !c.tiled || c.rows != 8) return FusedPair::kNone;
+  const PathDev& f = P.path[0];
+  const PathDev& c = P.path[1];
+  if (c.rows != 8) return FusedPair::kNone;
   if (f.rows == 4 && f.cpl == 2) {
     if (c.cpl == 12) return FusedPair::k4_2__8_12;
     if (c.cpl == 8) return FusedPair::k4_2__8_8;
@@ -169,7 +140,7 @@ hipError_t launch_fused(const MatchParamsDev& P, const FramesDev& FR, const ocsr
   const FusedPair pair = fused_pair(P, sx, sy);
   if (pair == FusedPair::kNone) return hipErrorNotSupported;
   if (timer) timer->before(timer->ctx, "reset", stream);
-  reset_kernel<<<1, 64, 0, stream>>>(ws, FR.n);
+  reset_kernel<<<1, 64, 0, stream>>>(ws);
   if (timer) timer->after(timer->ctx, "reset", stream);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

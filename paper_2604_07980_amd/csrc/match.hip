@@ -1,33 +1,52 @@
-// Multi-launch matching path (Sec. 4.3.2-4.3.6, Alg. 2): plan, one grid-stride launch per
-// level (far blocks, close blocks), one aggregation workgroup per box. The steps are in
-// dev_match.hpp, shared with the fused persistent kernel.
+// Multi-launch path (Alg. 2): census and plan of every frame in one launch, one
+// matching launch per level, one aggregation launch. A matching launch deals work items
+// (up to item_blocks blocks of one box, spread over the four waves of a workgroup)
+// over its grid; the aggregation launch gives each box a workgroup that forms its
+// disparity (Sec. 4.3.4) and depth (Eq. 1). Results cross workgroups only at kernel
+// boundaries. The device steps are in dev_census.hpp and dev_match.hpp, shared with
+// the fused persistent kernel.
+#include "dev_census.hpp"
 #include "dev_match.hpp"
 
 namespace ocsr {
 namespace {
 
-// one wave per frame
+// one wave per frame (descriptor-level calls, whose census is the caller's)
 __global__ __launch_bounds__(64) void plan_kernel(MatchParamsDev P, FramesDev FR,
                                                   const ocsr_box* boxes, MatchWs ws) {
   const int f = blockIdx.x;
   dev::plan_frame(P, FR.f[f], f, FR.n_boxes_total, boxes, ws, threadIdx.x);
 }
 
-__global__ __launch_bounds__(64) void match_generic_kernel(MatchParamsDev P, FramesDev FR,
-                                                           MatchWs ws, DebugDev dbg, int level) {
-  dev::level_blocks(FR, ws, level, [&](int f, int q) {
-    dev::match_block_generic(P, FR.f[f], f, FR.n_boxes_total, ws, dbg, level, q, false,
-                             threadIdx.x);
-  });
+// workgroups 0 .. n_frames - 1 plan a frame each (one wave); the rest make one census
+// tile each
+template <int SX, int SY>
+__global__ __launch_bounds__(256) void frame_census_kernel(MatchParamsDev P, FramesDev FR,
+                                                           const ocsr_box* boxes, MatchWs ws,
+                                                           int sx, int sy, int sentinel) {
+  __shared__ uint32_t lds[SX >= 0 ? dev::CensusTile<(SX > 0 ? SX : 0), (SY > 0 ? SY : 0)>::kLdsBytes / 4 : 1];
+  if ((int)blockIdx.x < FR.n) {
+    if (threadIdx.x < 64)
+      dev::plan_frame(P, FR.f[blockIdx.x], blockIdx.x, FR.n_boxes_total, boxes, ws, threadIdx.x);
+    return;
+  }
+  dev::frame_census_tile<SX, SY>(FR, blockIdx.x - FR.n, sx, sy, sentinel, lds);
 }
 
 template <int ROWS, int NX, int CPL>
-__global__ __launch_bounds__(64) void match_tiled_kernel(MatchParamsDev P, FramesDev FR,
-                                                         MatchWs ws, DebugDev dbg, int level) {
-  __shared__ uint64_t lds[(dev::Tiled<ROWS, NX, CPL>::kLdsBytes + 7) / 8];
-  dev::level_blocks(FR, ws, level, [&](int f, int q) {
-    dev::match_block_tiled<ROWS, NX, CPL>(P, FR.f[f], f, FR.n_boxes_total, ws, dbg, level, q,
-                                          false, threadIdx.x, lds);
+__global__ __launch_bounds__(256) void match_tiled_kernel(MatchParamsDev P, FramesDev FR,
+                                                          MatchWs ws, DebugDev dbg, int level) {
+  constexpr size_t kWave = (dev::Tiled<ROWS, NX, CPL>::kLdsBytes + 15) & ~(size_t)15;
+  __shared__ uint64_t lds[(kItemWaves * kWave + 7) / 8];
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int lane = threadIdx.x & 63;
+  void* wl = (char*)lds + wave * kWave;
+  dev::level_items(FR, ws, level, [&](int f, int q) {
+    const FrameDev& fr = FR.f[f];
+    dev::run_item(P, fr, f, FR.n_boxes_total, ws, level, q, wave, lane,
+                  [&](const dev::BlockCtx& c) {
+      dev::match_block_tiled<ROWS, NX, CPL>(P, fr, ws, dbg, c, lane, wl);
+    });
   });
 }
 
@@ -45,7 +64,7 @@ size_t match_ws_bytes(int n_frames, int n_boxes_total, int cap_blocks) {
   const size_t n = (size_t)(n_boxes_total > 0 ? n_boxes_total : 1);
   const size_t c = (size_t)(cap_blocks > 0 ? cap_blocks : 1) * (size_t)(n_frames > 0 ? n_frames : 1);
   return align256(n * sizeof(BoxPlan)) + align256(n * sizeof(BoxClip)) +
-         align256(2 * n * sizeof(int32_t)) + align256(n * sizeof(int32_t)) +
+         align256(2 * n * sizeof(int32_t)) +
          align256((size_t)kMaxFrames * FC_N * sizeof(int32_t)) + align256(GC_N * sizeof(int32_t)) +
          align256(c * sizeof(float)) + align256(c * sizeof(uint8_t));
 }
@@ -57,8 +76,7 @@ MatchWs match_ws_carve(void* base, int n_frames, int n_boxes_total, int cap_bloc
   MatchWs ws;
   ws.plan = (BoxPlan*)b;        b += align256(n * sizeof(BoxPlan));
   ws.clip = (BoxClip*)b;        b += align256(n * sizeof(BoxClip));
-  ws.lbox_end = (int32_t*)b;    b += align256(2 * n * sizeof(int32_t));
-  ws.box_done = (int32_t*)b;    b += align256(n * sizeof(int32_t));
+  ws.litem_end = (int32_t*)b;   b += align256(2 * n * sizeof(int32_t));
   ws.fcount = (int32_t*)b;      b += align256((size_t)kMaxFrames * FC_N * sizeof(int32_t));
   ws.gcount = (int32_t*)b;      b += align256(GC_N * sizeof(int32_t));
   ws.blk_val = (float*)b;       b += align256(c * sizeof(float));
@@ -66,28 +84,47 @@ MatchWs match_ws_carve(void* base, int n_frames, int n_boxes_total, int cap_bloc
   return ws;
 }
 
-MatchVariant pick_variant(const PathDev& ph) {
-  MatchVariant v = {0, 0, 0};
-  if (ph.mode != OCSR_MODE_TILED) return v;
-  static const int cpl4[] = {2, 4, 8, 16};
-  static const int cpl8[] = {4, 8, 12, 16, 24, 32};
-  if (ph.bw <= 4 && ph.bh <= 4) {
-    for (int c : cpl4)
-      if (16 * c >= ph.nd) return MatchVariant{1, 4, c};
-  } else if (ph.bw <= 8 && ph.bh <= 8) {
-    for (int c : cpl8)
-      if (8 * c >= ph.nd) return MatchVariant{1, 8, c};
+namespace {
+// the built kernels, as in launch_level
+struct BuiltVariant { int rows, nx, cpl; };
+constexpr BuiltVariant kBuilt[] = {{4, 4, 2},  {4, 4, 4},  {4, 4, 8},  {4, 4, 16}, {8, 8, 4},
+                                   {8, 8, 8},  {8, 8, 12}, {8, 8, 16}, {8, 8, 24}, {8, 8, 32}};
+}  // namespace
+
+bool variant_valid(const PathDev& ph, int rows, int cpl) {
+  if (ph.mode != OCSR_MODE_TILED) return false;
+  for (const BuiltVariant& b : kBuilt)
+    if (b.rows == rows && b.cpl == cpl)
+      return ph.bw <= b.nx && ph.bh <= b.rows && (64 / b.rows) * b.cpl >= ph.nd;
+  return false;
+}
+
+int variant_candidates(const PathDev& ph, int* rows, int* cpl, int cap) {
+  int n = 0;
+  for (const BuiltVariant& b : kBuilt) {
+    if (!variant_valid(ph, b.rows, b.cpl)) continue;
+    if (n < cap) {
+      rows[n] = b.rows;
+      cpl[n] = b.cpl;
+    }
+    ++n;
   }
-  return v;
+  return n;
+}
+
+MatchVariant pick_variant(const PathDev& ph) {
+  for (const BuiltVariant& b : kBuilt)
+    if (variant_valid(ph, b.rows, b.cpl)) return MatchVariant{1, b.rows, b.cpl};
+  return MatchVariant{0, 0, 0};
 }
 
 static hipError_t launch_level(const MatchParamsDev& P, const FramesDev& FR, const MatchWs& ws,
                                const DebugDev& dbg, int level, int grid, hipStream_t stream) {
-  const MatchVariant v = pick_variant(P.path[level]);
-#define OCSR_TILED(R, X, C)                                                          \
-  if (v.tiled && v.rows == R && v.cpl == C) {                                        \
-    match_tiled_kernel<R, X, C><<<grid, 64, 0, stream>>>(P, FR, ws, dbg, level);    \
-    return hipGetLastError();                                                        \
+  const PathDev& v = P.path[level];
+#define OCSR_TILED(R, X, C)                                                              \
+  if (v.rows == R && v.cpl == C) {                                                       \
+    match_tiled_kernel<R, X, C><<<grid, 256, 0, stream>>>(P, FR, ws, dbg, level);       \
+    return hipGetLastError();                                                            \
   }
   OCSR_TILED(4, 4, 2)
   OCSR_TILED(4, 4, 4)
@@ -100,19 +137,40 @@ static hipError_t launch_level(const MatchParamsDev& P, const FramesDev& FR, con
   OCSR_TILED(8, 8, 24)
   OCSR_TILED(8, 8, 32)
 #undef OCSR_TILED
-  match_generic_kernel<<<grid, 64, 0, stream>>>(P, FR, ws, dbg, level);
+  return hipErrorNotSupported;   // rejected by the argument checks before any launch
+}
+
+hipError_t launch_frame_census(const MatchParamsDev& P, const FramesDev& FR,
+                               const ocsr_box* boxes, const MatchWs& ws, int sx, int sy,
+                               int sentinel, int n_census_tiles, hipStream_t stream,
+                               const LaunchTimer* timer) {
+  const dim3 grid(FR.n + n_census_tiles), block(256);
+  if (timer) timer->before(timer->ctx, "census", stream);
+  if (sx == 3 && sy == 4) {
+    frame_census_kernel<3, 4><<<grid, block, 0, stream>>>(P, FR, boxes, ws, sx, sy, sentinel);
+  } else if (sx == 2 && sy == 2) {
+    frame_census_kernel<2, 2><<<grid, block, 0, stream>>>(P, FR, boxes, ws, sx, sy, sentinel);
+  } else if (sx == 4 && sy == 3) {
+    frame_census_kernel<4, 3><<<grid, block, 0, stream>>>(P, FR, boxes, ws, sx, sy, sentinel);
+  } else {
+    frame_census_kernel<-1, -1><<<grid, block, 0, stream>>>(P, FR, boxes, ws, sx, sy, sentinel);
+  }
+  if (timer) timer->after(timer->ctx, "census", stream);
   return hipGetLastError();
 }
 
 hipError_t launch_match(const MatchParamsDev& P, const FramesDev& FR, const ocsr_box* boxes,
                         const MatchWs& ws, ocsr_box_result* out, const DebugDev& dbg,
-                        int n_match_wgs, hipStream_t stream, const LaunchTimer* timer) {
+                        bool plan_done, int n_match_wgs, hipStream_t stream,
+                        const LaunchTimer* timer) {
   if (FR.n_boxes_total <= 0) return hipSuccess;
   hipError_t e;
-  if (timer) timer->before(timer->ctx, "plan", stream);
-  plan_kernel<<<FR.n, 64, 0, stream>>>(P, FR, boxes, ws);
-  if (timer) timer->after(timer->ctx, "plan", stream);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (!plan_done) {
+    if (timer) timer->before(timer->ctx, "plan", stream);
+    plan_kernel<<<FR.n, 64, 0, stream>>>(P, FR, boxes, ws);
+    if (timer) timer->after(timer->ctx, "plan", stream);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   // close blocks first: they carry most of the work
   for (int level = 1; level >= 0; --level) {
     const char* name = level == 0 ? "match_far" : "match_close";

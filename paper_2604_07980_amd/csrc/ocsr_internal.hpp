@@ -49,6 +49,7 @@ struct LevelDev {
 struct PathDev {
   int32_t mode, bw, bh, n_side;
   int32_t dlo, nd;                 // level search range [dlo, dlo + nd)
+  int32_t rows, cpl;               // matching kernel variant (chosen on the host)
 };
 
 // Matching parameters shared by every frame of a call.
@@ -61,6 +62,7 @@ struct MatchParamsDev {
   float fb;                        // focal_px * baseline_m, one fp32 multiply
   float d_eps;
   int32_t cap_blocks;              // block capacity of one frame
+  int32_t item_blocks;             // blocks per work item: kItemWaves x blocks per wave
 };
 
 // One frame of a call: descriptor levels, its boxes and (whole-frame calls) its images.
@@ -90,7 +92,7 @@ struct BoxPlan {
   int32_t ox, oy;                  // TILED: origin of block (0, 0)
   int32_t off;                     // first block number within the frame
   int32_t nblk;                    // blocks matched (0 if not matched)
-  int32_t loff;                    // first block number among the frame's boxes of its level
+  int32_t ioff;                    // first work item among the frame's boxes of its level
   int32_t frame;
 };
 
@@ -98,8 +100,14 @@ struct BoxClip {
   int32_t cx0, cy0, cx1, cy1;      // clipped box; empty boxes are all zero
 };
 
-// per-frame counters
-enum { FC_NUMBERED = 0, FC_MATCHED = 1, FC_FAR = 2, FC_CLOSE = 3, FC_CENSUS_DONE = 4, FC_N = 8 };
+// Matching work is dealt in items of up to item_blocks consecutive blocks of one box
+// (blocks per wave x the 4 waves of a 256-thread workgroup).
+constexpr int kItemWaves = 4;
+constexpr int kMaxBlocksPerWave = 8;
+
+// per-frame counters: blocks numbered, block end of the matched boxes, work items of
+// the far and close levels
+enum { FC_NUMBERED = 0, FC_MATCHED = 1, FC_FAR_ITEMS = 2, FC_CLOSE_ITEMS = 3, FC_N = 8 };
 // call-wide counters: the timeout flag, and the arrival slots of the fused launch's two
 // grid barriers (arrivals spread over kBarSlots counters to keep atomics uncontended)
 constexpr int kBarSlots = 8;
@@ -108,8 +116,7 @@ enum { GC_TIMEOUT = 0, GC_BAR0 = 8, GC_BAR1 = 16, GC_N = 24 };
 struct MatchWs {
   BoxPlan* plan;       // [n_boxes_total]
   BoxClip* clip;       // [n_boxes_total]
-  int32_t* lbox_end;   // [2][n_boxes_total] per level and frame: running block end
-  int32_t* box_done;   // [n_boxes_total] blocks of the box finished (fused call)
+  int32_t* litem_end;  // [2][n_boxes_total] per level and frame: running work-item end
   int32_t* fcount;     // [kMaxFrames][FC_N]
   int32_t* gcount;     // [GC_N]
   float* blk_val;      // [n_frames][cap_blocks] full-res disparity of a valid block
@@ -134,20 +141,34 @@ struct LaunchTimer {
   void (*after)(void* ctx, const char* name, hipStream_t s);
 };
 
-// Kernel variant used for one level's blocks: TILED blocks of at most 8 x rows points
-// with at most (64 / rows) * cpl level candidates run the register-blocked code;
-// anything else (GRID, wider blocks) runs the generic code.
+// Kernel variant of one level's blocks: the register-blocked TILED kernel with `rows`
+// block rows per wave (4: blocks up to 4 x 4, 8: up to 8 x 8) and `cpl` consecutive
+// candidates per lane, which covers (64 / rows) * cpl level candidates. Other shapes
+// (GRID mode, wider blocks, wider ranges) have no kernel in this build.
 struct MatchVariant {
-  int tiled;           // 1: register-blocked TILED code
+  int tiled;           // 1: a register-blocked TILED kernel exists
   int rows, cpl;
 };
+// the default: the smallest cpl of the smallest rows that covers the block and range
 MatchVariant pick_variant(const PathDev& ph);
+// whether the (rows, cpl) kernel is built and covers the path's blocks and range
+bool variant_valid(const PathDev& ph, int rows, int cpl);
+// every built (rows, cpl) that covers the path, up to cap of them; returns the count
+int variant_candidates(const PathDev& ph, int* rows, int* cpl, int cap);
 
-// Multi-launch path: plan (one wave per frame), one work-queue match launch per level,
-// one aggregation workgroup per box.
+// Census of every view and level of every frame, and the plan of every frame, in one
+// launch (frames whose images are given).
+hipError_t launch_frame_census(const MatchParamsDev& p, const FramesDev& fr,
+                               const ocsr_box* boxes, const MatchWs& ws, int sx, int sy,
+                               int sentinel, int n_census_tiles, hipStream_t stream,
+                               const LaunchTimer* timer);
+
+// Multi-launch matching: the plan (unless plan_done), one launch per level that matches
+// the level's blocks, then one aggregation workgroup per box.
 hipError_t launch_match(const MatchParamsDev& p, const FramesDev& fr, const ocsr_box* boxes,
                         const MatchWs& ws, ocsr_box_result* out, const DebugDev& dbg,
-                        int n_match_wgs, hipStream_t stream, const LaunchTimer* timer);
+                        bool plan_done, int n_match_wgs, hipStream_t stream,
+                        const LaunchTimer* timer);
 
 // Fused path: census of every frame, planning, matching and aggregation in one
 // persistent launch of co-resident workgroups (after a counter reset). Returns
@@ -158,5 +179,13 @@ hipError_t launch_fused(const MatchParamsDev& p, const FramesDev& fr, const ocsr
                         int n_census_tiles, int n_cu, int wgs_per_cu, hipStream_t stream,
                         const LaunchTimer* timer);
 bool fused_available(const MatchParamsDev& p, int sx, int sy);
+
+// Dense counterpart: left-view and right-view winner-take-all over [dmin, dmax] of the
+// (2 radius + 1)^2 window sums of Hamming costs, then the left/right check. d_left and
+// d_right: int16 [H][W] scratch (d_right also an output when the caller asks for it).
+bool dense_radius_supported(int radius);
+hipError_t launch_dense(const uint64_t* CL, const uint64_t* CR, int W, int H, int pitch, int dmin,
+                        int dmax, int radius, int lr_tol, int16_t* disp, int16_t* d_left,
+                        int16_t* d_right, hipStream_t stream, const LaunchTimer* timer);
 
 }  // namespace ocsr

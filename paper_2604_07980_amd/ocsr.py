@@ -30,13 +30,15 @@ MAX_CANDIDATES = 256
 MAX_CENSUS_JOBS = 64
 DEFAULT_CAP_BLOCKS = 1 << 20
 
-OPTION_FUSED, OPTION_WAVES_PER_CU, OPTION_GRAPH = 1, 2, 3
+OPTION_FUSED, OPTION_WAVES_PER_CU, OPTION_GRAPH, OPTION_MATCH_WGS_PER_CU, OPTION_BLOCKS_PER_WAVE = 1, 2, 3, 4, 5
 
 EXPORTS = ["ocsr_abi_version", "ocsr_last_error", "ocsr_ctx_create", "ocsr_ctx_destroy",
            "ocsr_census", "ocsr_census_many", "ocsr_match_workspace_bytes", "ocsr_match_boxes",
            "ocsr_frame_workspace_bytes", "ocsr_range_frame", "ocsr_batch_workspace_bytes",
            "ocsr_range_batch", "ocsr_ctx_set_option", "ocsr_ctx_set_timing",
-           "ocsr_ctx_kernel_time", "ocsr_ctx_reset_timing", "ocsr_ctx_graph_stats"]
+           "ocsr_ctx_kernel_time", "ocsr_ctx_reset_timing", "ocsr_ctx_graph_stats",
+           "ocsr_variant_candidates", "ocsr_ctx_set_variant", "ocsr_dense_workspace_bytes",
+           "ocsr_dense_match"]
 
 
 class OcsrError(RuntimeError):
@@ -154,6 +156,15 @@ def load(path: str = LIB_PATH):
         L.ocsr_ctx_reset_timing.restype = i32
         L.ocsr_ctx_graph_stats.argtypes = [vp, C.POINTER(i64), C.POINTER(i64)]
         L.ocsr_ctx_graph_stats.restype = i32
+        L.ocsr_variant_candidates.argtypes = [i32, i32, i32, C.POINTER(i32), C.POINTER(i32), i32]
+        L.ocsr_variant_candidates.restype = i32
+        L.ocsr_ctx_set_variant.argtypes = [vp, i32, i32, i32, i32, i32]
+        L.ocsr_ctx_set_variant.restype = i32
+        L.ocsr_dense_workspace_bytes.argtypes = [i32, i32]
+        L.ocsr_dense_workspace_bytes.restype = C.c_size_t
+        L.ocsr_dense_match.argtypes = [vp, C.POINTER(Level), i32, i32, i32, i32, vp, vp, vp,
+                                       C.c_size_t, vp]
+        L.ocsr_dense_match.restype = i32
         _lib = L
         return L
 
@@ -366,6 +377,19 @@ def _frame_params(params: dict) -> FrameParams:
     return FrameParams(params["sx"], params["sy"], params["sentinel"], params["close_scale"])
 
 
+def batch_workspace_bytes(shapes, params: dict, cap_blocks: int = 1 << 16) -> int:
+    """Workspace bytes of a range_batch call; shapes: list of (H, W, n_boxes)."""
+    arr = (Frame * len(shapes))()
+    off = 0
+    for k, (H, W, nb) in enumerate(shapes):
+        arr[k] = Frame(0, 0, W, H, W, off, int(nb), 0)
+        off += int(nb)
+    n = load().ocsr_batch_workspace_bytes(arr, len(shapes), C.byref(_frame_params(params)), cap_blocks)
+    if n == 0:
+        raise ValueError("invalid batch description")
+    return n
+
+
 def range_batch(frames, boxes: torch.Tensor, params: dict, cap_blocks: int = 1 << 16,
                 workspace: Workspace | None = None, out: torch.Tensor | None = None) -> torch.Tensor:
     """Many frames in one launch sequence.
@@ -405,6 +429,24 @@ def range_batch(frames, boxes: torch.Tensor, params: dict, cap_blocks: int = 1 <
     return out
 
 
+def dense(L: torch.Tensor, R: torch.Tensor, dmin: int = 0, dmax: int = 191, radius: int = 2,
+          lr_tol: int = 1, right: bool = False, workspace: Workspace | None = None):
+    """Dense counterpart on one level's descriptors (int64 [H, W] cuda): int16 [H, W]
+    left-view disparity after the left/right check (-1 invalid), and with right=True
+    also the right-view winner-take-all map."""
+    lv = _level(L, R, 1, 0, 0)
+    H, W = L.shape
+    dev = L.device
+    Lb = load()
+    ws = (workspace or Workspace()).get(Lb.ocsr_dense_workspace_bytes(W, H), dev)
+    disp = torch.empty((H, W), dtype=torch.int16, device=dev)
+    disp_r = torch.empty((H, W), dtype=torch.int16, device=dev) if right else None
+    _check(Lb.ocsr_dense_match(context(dev.index), C.byref(lv), dmin, dmax, radius, lr_tol,
+                               _dptr(disp), _dptr(disp_r) if right else None, _dptr(ws),
+                               ws.numel(), _stream(dev)))
+    return (disp, disp_r) if right else disp
+
+
 def set_option(option: int, value: int, device: int | None = None):
     _check(load().ocsr_ctx_set_option(context(device), option, value))
 
@@ -417,6 +459,29 @@ def set_fused(enable: bool, device: int | None = None):
 def set_graph(enable: bool, device: int | None = None):
     """Submit whole-frame and batch calls as cached HIP graphs (True) or launch by launch."""
     set_option(OPTION_GRAPH, 1 if enable else 0, device)
+
+
+def variant_candidates(bw: int, bh: int, n_candidates: int) -> list[tuple[int, int]]:
+    """Every (rows, cpl) matching kernel that covers bw x bh blocks and n_candidates
+    level candidates (host query, no device needed)."""
+    L = load()
+    rows, cpl = (C.c_int32 * 32)(), (C.c_int32 * 32)()
+    n = L.ocsr_variant_candidates(bw, bh, n_candidates, rows, cpl, 32)
+    if n < 0:
+        raise OcsrError(n, L.ocsr_last_error().decode())
+    return [(rows[i], cpl[i]) for i in range(min(n, 32))]
+
+
+def set_variant(bw: int, bh: int, n_candidates: int, rows: int, cpl: int,
+                device: int | None = None):
+    """Use the (rows, cpl) kernel for paths of bw x bh blocks and n_candidates level
+    candidates (rows = 0 restores the default)."""
+    _check(load().ocsr_ctx_set_variant(context(device), bw, bh, n_candidates, rows, cpl))
+
+
+def level_candidates(path: dict, scale: int) -> int:
+    """Level candidates of a path searched at level scale `scale`."""
+    return -(-(path["dmax"] - path["dmin"] + 1) // scale)
 
 
 def graph_stats(device: int | None = None) -> tuple[int, int]:

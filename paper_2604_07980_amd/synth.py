@@ -290,3 +290,35 @@ def serving_pool(res: tuple[int, int], n: int, seed: int = 5000) -> list[tuple[n
         planes = random_boxes(rng, H, W, 24, scale=W / 1920, tau_s=64 * W / 1920)
         out.append(render_pair(rng, H, W, planes))
     return out
+
+
+SERVING_RESOLUTIONS = ((720, 1280), (1080, 1920), (2160, 3840))
+SERVING_WEIGHTS = (0.3, 0.5, 0.2)
+SERVING_CLOSE_RANGES = (128, 192, 256)
+
+
+def serving_requests(n: int, pool_sizes=(32, 32, 32), seed: int = 5000, rate: float = 120.0):
+    """The request stream of the serving workload: Poisson arrivals at `rate` per second,
+    resolution drawn with SERVING_WEIGHTS, an image pair drawn from that resolution's
+    pool, 1..200 boxes sized as the batch frames scaled by W / 1920, close range
+    0..D-1 with D drawn from SERVING_CLOSE_RANGES, far range 0..31.
+
+    Returns dicts with rid, arrival (s), res (index), pool (index), boxes (int32 [n, 5]),
+    params."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for rid in range(n):
+        t += float(rng.exponential(1.0 / rate))
+        ri = int(rng.choice(len(SERVING_RESOLUTIONS), p=SERVING_WEIGHTS))
+        H, W = SERVING_RESOLUTIONS[ri]
+        nb = int(rng.integers(1, 201))
+        planes = random_boxes(rng, H, W, nb, scale=W / 1920, tau_s=64 * W / 1920)
+        boxes = np.array([[p[0], p[1], p[2], p[3], BOX_RANGE] for p in planes],
+                         dtype=np.int32).reshape(-1, 5)
+        D = int(rng.choice(SERVING_CLOSE_RANGES))
+        params = params_for(5, width=W)
+        params["close"] = dict(params["close"], dmax=D - 1)
+        out.append(dict(rid=rid, arrival=t, res=ri, pool=int(rng.integers(0, pool_sizes[ri])),
+                        boxes=boxes, params=params))
+    return out

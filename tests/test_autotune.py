@@ -1,0 +1,55 @@
+"""Host-side logic of the autotuner and the kernel-variant query: path shapes, table
+persistence and validation. No GPU."""
+import os
+
+import pytest
+
+from paper_2604_07980_amd import autotune, ocsr, synth
+
+
+@pytest.fixture(scope="module")
+def built():
+    if not os.path.exists(ocsr.LIB_PATH):
+        from paper_2604_07980_amd import build
+        build.build()
+    return ocsr.load()
+
+
+def test_path_shapes_of_the_workloads():
+    # realistic frame: far 4x4 blocks over 0..31 at s=1, close 8x8 over 0..191 at s=2
+    assert autotune.path_shapes(synth.params_for(2)) == [(4, 4, 32), (8, 8, 96)]
+    # tiny frame: far 8x8 over 0..63; the close path is configured the same as the base
+    shapes = autotune.path_shapes(synth.params_for(1))
+    assert shapes[0] == (8, 8, 64)
+
+
+def test_variant_candidates_cover_the_shape(built):
+    for bw, bh, nd in [(4, 4, 32), (8, 8, 96), (8, 8, 64), (8, 8, 128), (5, 5, 40), (4, 4, 1)]:
+        cands = ocsr.variant_candidates(bw, bh, nd)
+        assert cands, (bw, bh, nd)
+        for rows, cpl in cands:
+            assert rows in (4, 8) and bh <= rows and bw <= rows
+            assert (64 // rows) * cpl >= nd
+    # nothing covers blocks wider than 8 or more than 256 candidates
+    assert ocsr.variant_candidates(9, 8, 32) == []
+    assert ocsr.variant_candidates(8, 8, 257) == []
+    # 4x4 blocks can also run in the 8-row kernels
+    assert (8, 4) in ocsr.variant_candidates(4, 4, 32)
+
+
+def test_table_round_trip(built):
+    t = autotune.Table(arch="gfx950", variants={"4x4/32": [4, 2], "8x8/96": [8, 16]},
+                       blocks_per_wave=2, match_wgs_per_cu=8, timings_ms={"a": 1.5})
+    back = autotune.from_json(autotune.to_json(t))
+    assert back == t
+
+
+@pytest.mark.parametrize("bad", [
+    '{"arch": "gfx950", "variants": {"8x8/96": [8, 8]}, "blocks_per_wave": 1, "match_wgs_per_cu": 16}',
+    '{"arch": "gfx950", "variants": {"8x8/96": [4, 16]}, "blocks_per_wave": 1, "match_wgs_per_cu": 16}',
+    '{"arch": "gfx950", "variants": {}, "blocks_per_wave": 9, "match_wgs_per_cu": 16}',
+    '{"arch": "gfx950", "variants": {}, "blocks_per_wave": 1, "match_wgs_per_cu": 0}',
+])
+def test_invalid_tables_rejected(built, bad):
+    with pytest.raises(ValueError):
+        autotune.from_json(bad)

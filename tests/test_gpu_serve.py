@@ -1,0 +1,63 @@
+"""Served requests (continuous batching over several streams, memory budget) give, bit
+for bit, the results each request gets alone, and the oracle's."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2604_07980_amd import serve, synth
+from test_gpu_parity import assert_results_match, _cuda
+
+pytestmark = pytest.mark.gpu
+
+RES = ((96, 128), (120, 200), (160, 256))
+
+
+def _stream(n, seed=77, rate=4000.0):
+    pools = [[(_cuda(L), _cuda(R), L, R) for L, R in synth.serving_pool(res, 2, seed=seed + k)]
+             for k, res in enumerate(RES)]
+    rng = np.random.default_rng(seed)
+    t, reqs, host = 0.0, [], {}
+    for rid in range(n):
+        t += float(rng.exponential(1.0 / rate))
+        ri = int(rng.integers(0, len(RES)))
+        H, W = RES[ri]
+        nb = int(rng.integers(1, 26))
+        planes = synth.random_boxes(rng, H, W, nb, scale=W / 1920, tau_s=64 * W / 1920)
+        boxes = np.array([[p[0], p[1], p[2], p[3], synth.BOX_RANGE] for p in planes], np.int32)
+        p = synth.params_for(5, width=W)
+        p["close"] = dict(p["close"], dmax=int(rng.choice([63, 95, 127])))
+        L, R, Lh, Rh = pools[ri][int(rng.integers(0, 2))]
+        reqs.append(serve.Request(rid, L, R, boxes, p, t))
+        host[rid] = (Lh, Rh)
+    return reqs, host
+
+
+def test_served_equals_alone_and_oracle(lib, orc):
+    reqs, host = _stream(60)
+    ex = serve.GpuExecutor(n_slots=3)
+    budget = 3 * ex.bytes_needed(reqs[:8])
+    srv = serve.Server(ex, mem_budget=budget)
+    res = srv.run(reqs)
+    assert [r.rid for r in res] == [q.rid for q in reqs]
+    assert srv.peak_in_use <= budget and srv.in_use == 0
+    assert max(r.batch_frames for r in res) > 1          # requests did share batches
+    for q, r in zip(reqs, res):
+        assert r.error is None
+        alone = lib.results_to_numpy(lib.range_frame(q.left, q.right, _cuda(q.boxes), q.params))
+        assert (alone.view(np.int32) == r.boxes.view(np.int32)).all(), q.rid
+    for q in reqs[::7]:
+        Lh, Rh = host[q.rid]
+        want = orc.run_scene(Lh, Rh, q.params, q.boxes)[1][0]
+        assert_results_match(res[q.rid].boxes, want)
+
+
+def test_budget_refuses_oversized_request(lib):
+    reqs, _ = _stream(6)
+    ex = serve.GpuExecutor(n_slots=2)
+    budget = max(ex.bytes_needed([q]) for q in reqs[1:])
+    big = reqs[0]
+    big.boxes = np.concatenate([big.boxes] * 2000)
+    srv = serve.Server(ex, mem_budget=budget)
+    res = srv.run(reqs)
+    assert res[0].error is not None
+    assert all(r.error is None for r in res[1:])
