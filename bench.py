@@ -42,6 +42,11 @@ def parse():
                     help="requests of the serving section at 120/s (0 skips it)")
     ap.add_argument("--serve-pool", type=int, default=2,
                     help="pre-rendered image pairs per serving resolution")
+    ap.add_argument("--dense-steps", type=int, default=20,
+                    help="timed repetitions of the dense counterpart (0 skips it)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
+                    help="only run a plain device-to-device copy of MB megabytes five times "
+                         "(the reference kernel that scales the HBM byte counters)")
     ap.add_argument("--fused", action="store_true",
                     help="run the one-launch persistent kernel instead of the multi-launch path")
     return ap.parse_args()
@@ -66,6 +71,22 @@ def cpu_baseline(sc, params, costs_per_frame, seconds):
             "sample": f"{reps} repetitions of the realistic 1920x1080 frame (census of both views "
                       f"at both levels + matching of 64 boxes), {el:.1f} s, OpenMP over rows/boxes",
             "ms_per_frame": 1e3 * el / reps}
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter measurement
+    (profiles/traffic.json), or None when there is none or the kernel's sources changed
+    since it was taken."""
+    from paper_2604_07980_amd import profiling
+    key = {"census": "census", "match": "match", "match_close": "match",
+           "match_far": "match", "aggregate": "aggregate"}.get(kernel)
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "traffic.json")
+    if key is None or not os.path.exists(path):
+        return None
+    entry = json.load(open(path)).get(key)
+    if not entry or entry.get("source_sha256") != profiling.source_hash(key):
+        return None
+    return round(entry["fetch_bytes"] + entry["write_bytes"])
 
 
 def frame_costs(ocsr, L, R, boxes, p):
@@ -130,6 +151,47 @@ def batch_section(ocsr, synth, steps, warmup):
             "ms_16_frame_calls": round(ms_frames, 4),
             "speedup_vs_16_calls": round(ms_frames / ms_batch, 3),
             "identical_to_16_calls": identical}
+
+
+def dense_section(ocsr, L, R, steps, sparse_ms):
+    """The dense counterpart on the same 1920x1080 pair: census of both views at full
+    resolution, then every pixel over d = 0..191 with 5x5 summed Hamming costs, WTA in
+    both views and the L/R check."""
+    import torch
+    W, H = L.shape[1], L.shape[0]
+    ws = ocsr.Workspace()
+
+    def run():
+        CL, CR = ocsr.census_many([L, R], [1, 1])
+        return ocsr.dense(CL, CR, 0, 191, 2, 1, workspace=ws)
+
+    for _ in range(3):
+        run()
+    torch.cuda.synchronize()
+    ocsr.reset_timing()
+    ocsr.set_timing(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        disp = run()
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / steps
+    ocsr.set_timing(False)
+    kern = {}
+    for name in ("census", "dense", "dense_check"):
+        cnt, tot = ocsr.kernel_time(name)
+        if cnt:
+            kern[name] = {"launches": cnt, "avg_us": round(1e3 * tot / cnt, 3)}
+    costs = W * H * 192
+    if "dense" in kern:
+        # 4 int32 ops per cost in each of the two views
+        kern["dense"]["tops"] = round(2 * 4 * costs / (kern["dense"]["avg_us"] * 1e-6) / 1e12, 3)
+    return {"workload": "dense_1080p: the realistic 1920x1080 pair, census 7x9 at s=1, "
+                        "d = 0..191, 5x5 window, WTA left and right, L/R <= 1",
+            "costs_per_frame": costs, "ms_per_frame": round(ms, 4),
+            "value": round(costs / (ms * 1e-3) / 1e9, 3), "unit": "Gcost/s",
+            "valid_fraction": round(float((disp >= 0).float().mean()), 4),
+            "ms_sparse_frame": round(sparse_ms, 4),
+            "dense_over_sparse_time": round(ms / sparse_ms, 2), "kernels": kern}
 
 
 def serving_section(ocsr, synth, n_requests, pool_size):
@@ -198,6 +260,19 @@ def main():
 
     from paper_2604_07980_amd import ocsr, synth
 
+    if args.copy_calibration > 0:
+        # a buffer well beyond the 256 MB last-level cache, so the copy's reads come from
+        # HBM; the source is filled first and not touched again before the copies
+        n = args.copy_calibration << 20
+        src = torch.ones(n, dtype=torch.uint8, device="cuda:0")
+        dst = torch.zeros_like(src)
+        torch.cuda.synchronize()
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": n, "copies": 5}), flush=True)
+        return
+
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     sc = synth.scene_realistic()
@@ -236,7 +311,8 @@ def main():
     ocsr.set_timing(False)
     ms_per_step = 1e3 * (t1 - t0) / args.steps
     kern = {}
-    for name in ("census", "plan", "match_far", "match_close", "aggregate", "reset", "fused"):
+    for name in ("census", "plan", "match", "match_far", "match_close", "aggregate", "reset",
+                 "fused", "graph"):
         cnt, tot = ocsr.kernel_time(name)
         if cnt:
             kern[name] = {"launches": cnt, "avg_us": 1e3 * tot / cnt}
@@ -274,8 +350,8 @@ def main():
     census_ops = census_px * (census_bits - 1) * CENSUS_OPS_PER_CMP
     far_ops = costs_far * MATCH_OPS_PER_COST
     close_ops = (costs - costs_far) * MATCH_OPS_PER_COST
-    work = {"census": census_ops, "match_far": far_ops, "match_close": close_ops,
-            "fused": census_ops + far_ops + close_ops}
+    work = {"census": census_ops, "match": far_ops + close_ops, "match_far": far_ops,
+            "match_close": close_ops, "fused": census_ops + far_ops + close_ops}
     for k, ops in work.items():
         if k in kern:
             kern[k]["tops"] = ops / (kern[k]["avg_us"] * 1e-6) / 1e12
@@ -283,8 +359,8 @@ def main():
     dom = max((k for k in work if k in kern), key=lambda k: kern[k]["avg_us"])
     ach = kern[dom]["tops"]
     roofline = {"kernel": dom, "bound": "alu", "achieved": round(ach, 3), "peak": round(INT_PEAK_TOPS, 2),
-                "unit": "TOP/s", "frac": round(ach / INT_PEAK_TOPS, 4), "traffic": None,
-                "ops_per_launch": work[dom]}
+                "unit": "TOP/s", "frac": round(ach / INT_PEAK_TOPS, 4),
+                "traffic": measured_traffic(dom), "ops_per_launch": work[dom]}
 
     res = {
         "metric": METRIC,
@@ -318,6 +394,8 @@ def main():
     }
     if args.batch_steps > 0:
         res["batch"] = batch_section(ocsr, synth, args.batch_steps, max(3, args.warmup // 10))
+    if args.dense_steps > 0:
+        res["dense"] = dense_section(ocsr, L, R, args.dense_steps, ms_per_step)
     if args.serve_requests > 0:
         res["serving"] = serving_section(ocsr, synth, args.serve_requests, args.serve_pool)
     if not args.no_cpu_baseline:

@@ -353,10 +353,12 @@ int32_t ocsr_ctx_graph_stats(ocsr_ctx* ctx, int64_t* hits, int64_t* builds);
 /* When enabled, each kernel launch of the context is bracketed by HIP events on
  * its stream; ocsr_ctx_kernel_time() then reports, per kernel name, the number of
  * launches and their summed duration (ms) since the last reset. Reading
- * synchronizes on the recorded events. Kernel names: census, plan, match_far,
- * match_close (multi-launch path), reset, fused (fused path), graph (one replay of a
- * whole-frame or batch call with OCSR_OPTION_GRAPH on), dense and dense_check (the
- * dense counterpart). */
+ * synchronizes on the recorded events. Kernel names: census (with the plan in
+ * whole-frame calls), plan (descriptor-level calls), match (both levels in one launch),
+ * match_close and match_far (one launch per level, when no kernel for the pair of
+ * variants is built), aggregate, reset and fused (the persistent launch), graph (one
+ * replay of a whole-frame or batch call with OCSR_OPTION_GRAPH on), dense and
+ * dense_check (the dense counterpart). */
 int32_t ocsr_ctx_set_timing(ocsr_ctx* ctx, int32_t enable);
 int32_t ocsr_ctx_kernel_time(ocsr_ctx* ctx, const char* kernel, int64_t* launches,
                              double* total_ms);

@@ -97,7 +97,7 @@ __device__ __forceinline__ void census_tile(const uint8_t* __restrict__ img, int
   const bool x_in = X < Ws;
   const bool x_def = X >= SX && X < Ws - SX;
   constexpr int NP = kCensusRowsPerLane / 2;
-  static_assert(NP == 4, "the accumulation barrier below names four pairs");
+  static_assert(NP == 2 || NP == 4, "the accumulation barrier below names two or four pairs");
   // pair pp holds pixels A = (X, Y0 + r0 + 2pp) and B = (X, YA + 1) in its low / high half
   uint32_t acc[NP][8];
   u16x2 c2[NP];
@@ -126,7 +126,10 @@ __device__ __forceinline__ void census_tile(const uint8_t* __restrict__ img, int
       // regrouping the ORs into v_or3_b32 trees (an extra v_and_b32 per bit); the four
       // pairs' subtracts are issued ahead of their AND-ORs, so no packed-result wait
       // state is needed.
-      asm volatile("" : "+v"(acc[0][q]), "+v"(acc[1][q]), "+v"(acc[2][q]), "+v"(acc[3][q]));
+      if constexpr (NP == 4)
+        asm volatile("" : "+v"(acc[0][q]), "+v"(acc[1][q]), "+v"(acc[2][q]), "+v"(acc[3][q]));
+      else
+        asm volatile("" : "+v"(acc[0][q]), "+v"(acc[1][q]));
     }
   }
 #pragma unroll

@@ -163,18 +163,18 @@ __device__ __forceinline__ uint64_t block_mask(const MatchWs& ws, int box_off, i
   bool hidden = false;
   for (int jb = 0; jb < n; jb += 64) {
     const int o = jb + lane;
-    bool occ = false;
-    if (o < n && o != k) {
-      const BoxClip co = ws.clip[box_off + o];
-      occ = ck.cx0 < co.cx1 && co.cx0 < ck.cx1 && ck.cy0 < co.cy1 && co.cy0 < ck.cy1 &&
-            co.cy1 > ck.cy1 && co.cx0 <= bx1 && co.cx1 > bx0 && co.cy0 <= by1 && co.cy1 > by0;
-    }
+    const BoxClip co = o < n ? ws.clip[box_off + o] : BoxClip{0, 0, 0, 0};
+    const bool occ = o < n && o != k && ck.cx0 < co.cx1 && co.cx0 < ck.cx1 && ck.cy0 < co.cy1 &&
+                     co.cy0 < ck.cy1 && co.cy1 > ck.cy1 && co.cx0 <= bx1 && co.cx1 > bx0 &&
+                     co.cy0 <= by1 && co.cy1 > by0;
     uint64_t m = __ballot(occ);
     while (m) {
-      const int oo = jb + __ffsll((unsigned long long)m) - 1;
+      // the occluder's box, read from the lane that loaded it
+      const int src = __ffsll((unsigned long long)m) - 1;
       m &= m - 1;
-      const BoxClip co = ws.clip[box_off + oo];
-      hidden |= fx >= co.cx0 && fx < co.cx1 && fy >= co.cy0 && fy < co.cy1;
+      const int x0 = __builtin_amdgcn_readlane(co.cx0, src), x1 = __builtin_amdgcn_readlane(co.cx1, src);
+      const int y0 = __builtin_amdgcn_readlane(co.cy0, src), y1 = __builtin_amdgcn_readlane(co.cy1, src);
+      hidden |= fx >= x0 && fx < x1 && fy >= y0 && fy < y1;
     }
   }
   return __ballot(lane < npts && !hidden);
@@ -516,20 +516,33 @@ __device__ __forceinline__ void aggregate_box(const MatchParamsDev& P, const Mat
   const int base = pl.frame * P.cap_blocks + pl.off;
   if (tid == 0) { sm.scratch[258] = 0; sm.scratch[259] = 0; }
   __syncthreads();
-  // gather the valid values: one LDS atomic per wave, positions from the ballot
+  // gather the valid values: one LDS atomic per wave, positions from the ballot. Flags
+  // and values of up to kGather blocks per thread are loaded before any is used.
+  constexpr int kGather = 4;
   const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-  for (int b0 = 0; b0 < pl.nblk; b0 += 256) {
-    const int i = b0 + tid;
-    const uint8_t fl = i < pl.nblk ? ws.blk_flag[base + i] : (uint8_t)0;
-    const uint64_t mv = __ballot((fl & 2) != 0);
-    const uint64_t me = __ballot((fl & 1) != 0);
-    int wbase = 0;
-    if (lane == 0) {
-      wbase = atomicAdd(&sm.scratch[258], (int)__popcll(mv));
-      atomicAdd(&sm.scratch[259], (int)__popcll(me));
+  for (int b0 = 0; b0 < pl.nblk; b0 += 256 * kGather) {
+    uint32_t fl[kGather];
+    float v[kGather];
+#pragma unroll
+    for (int u = 0; u < kGather; ++u) {
+      const int i = b0 + 256 * u + tid;
+      const int at = base + (i < pl.nblk ? i : 0);
+      fl[u] = ws.blk_flag[at];
+      v[u] = ws.blk_val[at];
+      fl[u] = i < pl.nblk ? fl[u] : 0u;
     }
-    wbase = __shfl(wbase, 0, 64);
-    if (fl & 2) sm.vals[wbase + __popcll(mv & below)] = ws.blk_val[base + i];
+#pragma unroll
+    for (int u = 0; u < kGather; ++u) {
+      const uint64_t mv = __ballot((fl[u] & 2) != 0);
+      const uint64_t me = __ballot((fl[u] & 1) != 0);
+      int wbase = 0;
+      if (lane == 0 && (mv | me)) {
+        wbase = atomicAdd(&sm.scratch[258], (int)__popcll(mv));
+        atomicAdd(&sm.scratch[259], (int)__popcll(me));
+      }
+      wbase = __shfl(wbase, 0, 64);
+      if (fl[u] & 2) sm.vals[wbase + __popcll(mv & below)] = v[u];
+    }
   }
   __syncthreads();
   const int nv = sm.scratch[258], ne = sm.scratch[259];

@@ -50,6 +50,50 @@ __global__ __launch_bounds__(256) void match_tiled_kernel(MatchParamsDev P, Fram
   });
 }
 
+// Both levels in one launch: work items of every frame's close level first, then of
+// every far level (FV / CV: the far and close kernel variants).
+template <int FR_, int FX, int FC, int CR_, int CX, int CC>
+__global__ __launch_bounds__(256) void match_pair_kernel(MatchParamsDev P, FramesDev FR,
+                                                         MatchWs ws, DebugDev dbg) {
+  constexpr size_t kF = (dev::Tiled<FR_, FX, FC>::kLdsBytes + 15) & ~(size_t)15;
+  constexpr size_t kC = (dev::Tiled<CR_, CX, CC>::kLdsBytes + 15) & ~(size_t)15;
+  constexpr size_t kWave = kF > kC ? kF : kC;
+  __shared__ uint64_t lds[(kItemWaves * kWave + 7) / 8];
+  __shared__ int prefix[2 * kMaxFrames + 1];
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int lane = threadIdx.x & 63;
+  const int F = FR.n;
+  if (threadIdx.x < 64) {
+    // prefix[j]: items before slot j; slot j < F is frame j's close level, else frame
+    // j - F's far level
+    const int j = lane < F ? lane : lane - F;
+    const int cnt = lane < 2 * F ? ws.fcount[j * FC_N + (lane < F ? FC_CLOSE_ITEMS : FC_FAR_ITEMS)] : 0;
+    const int incl = dev::wave_incl_scan(cnt, lane);
+    if (lane < 2 * F) prefix[lane + 1] = incl;
+    if (lane == 0) prefix[0] = 0;
+  }
+  __syncthreads();
+  void* wl = (char*)lds + wave * kWave;
+  const int total = prefix[2 * F];
+  for (int m = blockIdx.x; m < total; m += gridDim.x) {
+    int slot = 0;
+    for (int k = 1; k < 2 * F; ++k)
+      if (m >= prefix[k]) slot = k;
+    const int f = slot < F ? slot : slot - F;
+    const FrameDev& fr = FR.f[f];
+    const int q = m - prefix[slot];
+    if (slot < F) {
+      dev::run_item(P, fr, f, FR.n_boxes_total, ws, 1, q, wave, lane, [&](const dev::BlockCtx& c) {
+        dev::match_block_tiled<CR_, CX, CC>(P, fr, ws, dbg, c, lane, wl);
+      });
+    } else {
+      dev::run_item(P, fr, f, FR.n_boxes_total, ws, 0, q, wave, lane, [&](const dev::BlockCtx& c) {
+        dev::match_block_tiled<FR_, FX, FC>(P, fr, ws, dbg, c, lane, wl);
+      });
+    }
+  }
+}
+
 __global__ __launch_bounds__(256) void aggregate_kernel(MatchParamsDev P, MatchWs ws,
                                                         ocsr_box_result* out) {
   __shared__ dev::AggLds sm;
@@ -140,6 +184,28 @@ static hipError_t launch_level(const MatchParamsDev& P, const FramesDev& FR, con
   return hipErrorNotSupported;   // rejected by the argument checks before any launch
 }
 
+// One launch for both levels when a kernel for the pair of variants is built (with
+// launch == false: only whether it is built).
+static bool launch_pair(const MatchParamsDev& P, const FramesDev& FR, const MatchWs& ws,
+                        const DebugDev& dbg, int grid, hipStream_t stream, bool launch) {
+  const PathDev& f = P.path[0];
+  const PathDev& c = P.path[1];
+#define OCSR_PAIR(FRW, FXW, FCP, CRW, CXW, CCP)                                          \
+  if (f.rows == FRW && f.cpl == FCP && c.rows == CRW && c.cpl == CCP) {                 \
+    if (launch)                                                                          \
+      match_pair_kernel<FRW, FXW, FCP, CRW, CXW, CCP><<<grid, 256, 0, stream>>>(P, FR, ws, dbg); \
+    return true;                                                                         \
+  }
+  OCSR_PAIR(4, 4, 2, 8, 8, 8)
+  OCSR_PAIR(4, 4, 2, 8, 8, 12)
+  OCSR_PAIR(4, 4, 2, 8, 8, 16)
+  OCSR_PAIR(8, 8, 8, 8, 8, 8)
+  OCSR_PAIR(8, 8, 8, 8, 8, 12)
+  OCSR_PAIR(8, 8, 8, 8, 8, 16)
+#undef OCSR_PAIR
+  return false;
+}
+
 hipError_t launch_frame_census(const MatchParamsDev& P, const FramesDev& FR,
                                const ocsr_box* boxes, const MatchWs& ws, int sx, int sy,
                                int sentinel, int n_census_tiles, hipStream_t stream,
@@ -171,13 +237,20 @@ hipError_t launch_match(const MatchParamsDev& P, const FramesDev& FR, const ocsr
     if (timer) timer->after(timer->ctx, "plan", stream);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  // close blocks first: they carry most of the work
-  for (int level = 1; level >= 0; --level) {
-    const char* name = level == 0 ? "match_far" : "match_close";
-    if (timer) timer->before(timer->ctx, name, stream);
-    e = launch_level(P, FR, ws, dbg, level, n_match_wgs, stream);
-    if (timer) timer->after(timer->ctx, name, stream);
-    if (e != hipSuccess) return e;
+  if (launch_pair(P, FR, ws, dbg, n_match_wgs, stream, false)) {
+    if (timer) timer->before(timer->ctx, "match", stream);
+    launch_pair(P, FR, ws, dbg, n_match_wgs, stream, true);
+    if (timer) timer->after(timer->ctx, "match", stream);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  } else {
+    // close blocks first: they carry most of the work
+    for (int level = 1; level >= 0; --level) {
+      const char* name = level == 0 ? "match_far" : "match_close";
+      if (timer) timer->before(timer->ctx, name, stream);
+      e = launch_level(P, FR, ws, dbg, level, n_match_wgs, stream);
+      if (timer) timer->after(timer->ctx, name, stream);
+      if (e != hipSuccess) return e;
+    }
   }
   if (timer) timer->before(timer->ctx, "aggregate", stream);
   aggregate_kernel<<<FR.n_boxes_total, 256, 0, stream>>>(P, ws, out);

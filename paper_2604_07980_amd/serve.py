@@ -62,7 +62,8 @@ def params_key(p: dict) -> str:
 
 
 class RealClock:
-    """Wall clock; idle() yields the host thread briefly while the device works."""
+    """Wall clock; idle() yields the host thread while the device works (a timed sleep
+    would oversleep by tens of microseconds and add that to every result's latency)."""
 
     def __init__(self):
         self.t0 = time.perf_counter()
@@ -71,12 +72,15 @@ class RealClock:
         return time.perf_counter() - self.t0
 
     def wait_until(self, t: float) -> None:
+        # sleep most of the way, then yield until the time is reached
         dt = t - self.now()
-        if dt > 0:
-            time.sleep(dt)
+        if dt > 5e-4:
+            time.sleep(dt - 3e-4)
+        while self.now() < t:
+            time.sleep(0)
 
     def idle(self, executor) -> None:
-        time.sleep(20e-6)
+        time.sleep(0)
 
 
 @dataclass

@@ -263,6 +263,23 @@ def test_frame_paths_small(lib, orc, variant):
     _frame_parity(lib, orc, sc, p, debug_check=False)
 
 
+@pytest.mark.parametrize("shape", [(9, 7), (7, 9), (2, 2), (13, 17), (33, 65), (121, 3)])
+def test_frame_degenerate_images(lib, orc, shape):
+    """Images as small as or smaller than the census window, and one-block-wide boxes:
+    every box still gets the oracle's reason code."""
+    H, W = shape
+    rng = np.random.default_rng(H * 100 + W)
+    left = rng.integers(0, 256, size=(H, W), dtype=np.uint8)
+    right = np.roll(left, -1, axis=1)
+    boxes = np.array([[0, 0, W, H, 1], [-5, -5, W + 5, H + 5, 1], [W // 2, H // 2, W // 2 + 1, H // 2 + 1, 1],
+                      [1, 1, max(W - 1, 2), max(H - 1, 2), 0], [W, H, W + 3, H + 3, 1]], np.int32)
+    p = synth.params_for(2)
+    p["tau_s"] = 6
+    want = orc.run_scene(left, right, p, boxes)[1][0]
+    got = lib.results_to_numpy(lib.range_frame(_cuda(left), _cuda(right), _cuda(boxes), p))
+    assert_results_match(got, want)
+
+
 def test_grid_mode_rejected(lib):
     """GRID-mode paths are refused before anything is enqueued."""
     p = _params("grid_far")
