@@ -45,12 +45,23 @@ __device__ __forceinline__ void census_tile(const uint8_t* __restrict__ img, int
                                             uint32_t* P) {
   using T = CensusTile<SX, SY>;
   constexpr int LW = T::LW, PR = T::PR, WR = T::WR, N = T::N;
+  img = uniform(img);
+  out = uniform(out);
+  W = uniform(W);
+  H = uniform(H);
+  pitch = uniform(pitch);
+  s = uniform(s);
+  out_pitch = uniform(out_pitch);
+  X0 = uniform(X0);
+  Y0 = uniform(Y0);
   const int Ws = W / s, Hs = H / s;
   // P[r * LW + c] = I(c, r) | I(c, r + 1) << 16 over the tile and its halo. Wave w
   // loads source rows w*RB .. w*RB + RB of the tile (one more than the pair rows it
   // writes): the row address is wave-uniform, so each load is one scalar base plus
-  // the lane's column offset. All loads are issued before the first is waited for; a
-  // pixel outside the level image reads a valid byte instead and is zeroed.
+  // the lane's unsigned column offset. All loads are issued before the first is waited
+  // for. A position outside the level image reads some valid byte of the image instead:
+  // only pixels whose window leaves the image see such values, and their words are
+  // stored as 0 regardless.
   constexpr int RB = (PR + 1 + 3) / 4;
   constexpr int NPASS = (LW + 63) / 64;
   {
@@ -61,16 +72,13 @@ __device__ __forceinline__ void census_tile(const uint8_t* __restrict__ img, int
     for (int cp = 0; cp < NPASS; ++cp) {
       const int pc = lane + 64 * cp;
       const int X = X0 - SX + pc;
-      const bool x_ok = pc < LW && X >= 0 && X < Ws;
-      const int coff = x_ok ? s * X : 0;
+      const uint32_t coff = (uint32_t)(s * (X < 0 ? 0 : (X < Ws ? X : Ws - 1)));
 #pragma unroll
       for (int k = 0; k <= RB; ++k) {
-        const int r = wave * RB + k;
-        const int Y = Y0 - SY + r;
-        const bool y_ok = r <= PR && Y >= 0 && Y < Hs;
-        const uint8_t* rp = img + (y_ok ? (size_t)(s * Y) * pitch : 0);
-        const uint32_t v = rp[coff];
-        px[cp][k] = (x_ok && y_ok) ? v : 0u;
+        const int Y = Y0 - SY + wave * RB + k;
+        const int Yc = Y < 0 ? 0 : (Y < Hs ? Y : Hs - 1);
+        const uint8_t* rp = img + (size_t)(s * Yc) * pitch;
+        px[cp][k] = rp[coff];
       }
     }
 #pragma unroll
@@ -86,7 +94,7 @@ __device__ __forceinline__ void census_tile(const uint8_t* __restrict__ img, int
   __syncthreads();
 
   const int lane = threadIdx.x & 63;
-  const int r0 = (threadIdx.x >> 6) * kCensusRowsPerLane;
+  const int r0 = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) * kCensusRowsPerLane;
   uint32_t v[2 * SX + 1][WR];
 #pragma unroll
   for (int i = 0; i < 2 * SX + 1; ++i)
@@ -144,15 +152,17 @@ __device__ __forceinline__ void census_tile(const uint8_t* __restrict__ img, int
                            __builtin_amdgcn_perm(x23, x01, 0x05040100u);
     const uint64_t codeB = ((uint64_t)__builtin_amdgcn_perm(x67, x45, 0x07060302u) << 32) |
                            __builtin_amdgcn_perm(x23, x01, 0x07060302u);
+    // rows are wave-uniform: one scalar row address per store, the lane's column as an
+    // unsigned offset
     const int YA = Y0 + r0 + 2 * pp;
-    if (x_in && YA < Hs) {
-      const bool def = x_def && YA >= SY && YA < Hs - SY;
-      out[(size_t)YA * out_pitch + X] = def ? codeA : 0ull;
-    }
     const int YB = YA + 1;
-    if (x_in && YB < Hs) {
+    if (YA < Hs && x_in) {
+      const bool def = x_def && YA >= SY && YA < Hs - SY;
+      (out + (size_t)YA * out_pitch)[(uint32_t)X] = def ? codeA : 0ull;
+    }
+    if (YB < Hs && x_in) {
       const bool def = x_def && YB >= SY && YB < Hs - SY;
-      out[(size_t)YB * out_pitch + X] = def ? codeB : 0ull;
+      (out + (size_t)YB * out_pitch)[(uint32_t)X] = def ? codeB : 0ull;
     }
   }
 }

@@ -8,6 +8,20 @@ namespace dev {
 
 __device__ __forceinline__ int cdiv_nonneg(int a, int s) { return (a + s - 1) / s; }
 
+// A value the whole wave holds, moved to scalar registers (the compiler cannot always
+// tell that a value read through a uniformly computed index is uniform).
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+// A pointer to global memory that the whole wave holds (the result stays a global-memory
+// pointer, so accesses through it remain global rather than flat instructions).
+template <class T>
+__device__ __forceinline__ T* uniform(T* p) {
+  const uint64_t v = (uint64_t)(uintptr_t)p;
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+  typedef __attribute__((address_space(1))) T GlobalT;
+  return (T*)(GlobalT*)(uintptr_t)(((uint64_t)hi << 32) | lo);
+}
+
 __device__ __forceinline__ int wave_incl_scan(int v, int lane) {
 #pragma unroll
   for (int d = 1; d < 64; d <<= 1) {
