@@ -267,29 +267,36 @@ __device__ __forceinline__ uint32_t popc64_acc(uint64_t x, uint32_t acc) {
   return __popc((uint32_t)(x >> 32)) + t;
 }
 
-// acc[c] = sum over the row's points i of popcount(t[i] ^ srow[i + c]). Every point is
-// summed first; points whose bit in rowmask is clear (occluded, or past the block's
-// width) are then subtracted again, which only costs anything when such points exist.
+// acc[c] = sum over the row's unmasked points i of popcount(t[i] ^ srow[i + c]).
+// col_all / col_any (wave-uniform): the block columns whose point is unmasked in every
+// row / in some row. Columns masked in every row (occluded, or past the block's width)
+// are skipped. When every other column is unmasked in every row, a cost is 4 ops;
+// otherwise each difference is ANDed with the lane's own mask bit (6 ops).
 template <int NX, int CPL>
 __device__ __forceinline__ void row_costs(const uint64_t (&t)[NX], const uint64_t* __restrict__ srow,
-                                          uint32_t rowmask, uint32_t (&acc)[CPL]) {
+                                          uint32_t rowmask, uint32_t col_all, uint32_t col_any,
+                                          uint32_t (&acc)[CPL]) {
   uint64_t w[NX + CPL - 1];
 #pragma unroll
   for (int m = 0; m < NX + CPL - 1; ++m) w[m] = srow[m];
 #pragma unroll
   for (int c = 0; c < CPL; ++c) acc[c] = 0;
+  if (col_all == col_any) {
 #pragma unroll
-  for (int i = 0; i < NX; ++i) {
+    for (int i = 0; i < NX; ++i) {
+      if (col_all & (1u << i)) {
 #pragma unroll
-    for (int c = 0; c < CPL; ++c) acc[c] = popc64_acc(t[i] ^ w[i + c], acc[c]);
-  }
+        for (int c = 0; c < CPL; ++c) acc[c] = popc64_acc(t[i] ^ w[i + c], acc[c]);
+      }
+    }
+  } else {
 #pragma unroll
-  for (int i = 0; i < NX; ++i) {
-    if (!((rowmask >> i) & 1u)) {
-      uint64_t ti = t[i];
-      asm volatile("" : "+v"(ti));   // recompute here rather than keep every term live
+    for (int i = 0; i < NX; ++i) {
+      if (col_any & (1u << i)) {
+        const uint64_t keep = ((rowmask >> i) & 1u) ? ~0ull : 0ull;
 #pragma unroll
-      for (int c = 0; c < CPL; ++c) acc[c] -= popc64_acc(ti ^ w[i + c], 0u);
+        for (int c = 0; c < CPL; ++c) acc[c] = popc64_acc((t[i] ^ w[i + c]) & keep, acc[c]);
+      }
     }
   }
 }
@@ -370,12 +377,19 @@ __device__ __forceinline__ void match_block_tiled(const MatchParamsDev& P, const
     return;
   }
   const uint32_t rowmask = j < ny ? (uint32_t)((mask >> (j * nx)) & ((1u << nx) - 1u)) : 0u;
+  // columns unmasked in every row / in some row (the mask is wave-uniform)
+  uint32_t col_all = (1u << nx) - 1u, col_any = 0;
+  for (int jj = 0; jj < ny; ++jj) {
+    const uint32_t r = (uint32_t)((mask >> (jj * nx)) & ((1u << nx) - 1u));
+    col_all &= r;
+    col_any |= r;
+  }
   uint64_t t[NX];
 #pragma unroll
   for (int i = 0; i < NX; ++i) t[i] = T[j * NX + i];
   uint32_t acc[CPL];
   // strip entry e = grp*CPL + c + i holds CR(X0 + i - d) for d = dhi - (grp*CPL + c)
-  if (j < ny) row_costs<NX, CPL>(t, S + j * SW + grp * CPL, rowmask, acc);
+  if (j < ny) row_costs<NX, CPL>(t, S + j * SW + grp * CPL, rowmask, col_all, col_any, acc);
 #pragma unroll
   for (int cc = 0; cc < CPL; ++cc)
     if (j >= ny) acc[cc] = 0;
@@ -403,7 +417,7 @@ __device__ __forceinline__ void match_block_tiled(const MatchParamsDev& P, const
   // backward strip: CL(X0 - d_f + dlo + m, Y0 + j)
   stage_strip<ROWS, SW>(S, Lb, lv.pitch, X0 - d_f + dlo, ny, sw, lv.W, lane);
   wave_sync();
-  if (j < ny) row_costs<NX, CPL>(t, S + j * SW + grp * CPL, rowmask, acc);
+  if (j < ny) row_costs<NX, CPL>(t, S + j * SW + grp * CPL, rowmask, col_all, col_any, acc);
 #pragma unroll
   for (int cc = 0; cc < CPL; ++cc)
     if (j >= ny) acc[cc] = 0;

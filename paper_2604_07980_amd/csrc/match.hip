@@ -33,8 +33,15 @@ __global__ __launch_bounds__(256) void frame_census_kernel(MatchParamsDev P, Fra
   dev::frame_census_tile<SX, SY>(FR, blockIdx.x - FR.n, sx, sy, sentinel, lds);
 }
 
+// Waves per SIMD a single-level kernel is compiled for (as many as its registers allow
+// without spilling, checked in the built code).
+template <int ROWS, int CPL>
+constexpr int tiled_waves() {
+  return ROWS == 4 ? (CPL <= 4 ? 6 : CPL <= 8 ? 4 : 2) : (CPL <= 4 ? 5 : CPL <= 12 ? 3 : CPL <= 16 ? 2 : 1);
+}
+
 template <int ROWS, int NX, int CPL>
-__global__ __launch_bounds__(256) void match_tiled_kernel(MatchParamsDev P, FramesDev FR,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(tiled_waves<ROWS, CPL>()))) void match_tiled_kernel(MatchParamsDev P, FramesDev FR,
                                                           MatchWs ws, DebugDev dbg, int level) {
   constexpr size_t kWave = (dev::Tiled<ROWS, NX, CPL>::kLdsBytes + 15) & ~(size_t)15;
   __shared__ uint64_t lds[(kItemWaves * kWave + 7) / 8];
@@ -50,10 +57,17 @@ __global__ __launch_bounds__(256) void match_tiled_kernel(MatchParamsDev P, Fram
   });
 }
 
+// Waves per SIMD the paired kernel is compiled for: three where both variants fit in a
+// third of the register file without spilling (checked in the built code), else two.
+template <int FR_, int FC, int CC>
+constexpr int pair_waves() {
+  return ((FR_ == 4 && FC <= 2 && CC <= 12) || (FC <= 8 && CC <= 8)) ? 3 : 2;
+}
+
 // Both levels in one launch: work items of every frame's close level first, then of
 // every far level (FV / CV: the far and close kernel variants).
 template <int FR_, int FX, int FC, int CR_, int CX, int CC>
-__global__ __launch_bounds__(256) void match_pair_kernel(MatchParamsDev P, FramesDev FR,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(pair_waves<FR_, FC, CC>()))) void match_pair_kernel(MatchParamsDev P, FramesDev FR,
                                                          MatchWs ws, DebugDev dbg) {
   constexpr size_t kF = (dev::Tiled<FR_, FX, FC>::kLdsBytes + 15) & ~(size_t)15;
   constexpr size_t kC = (dev::Tiled<CR_, CX, CC>::kLdsBytes + 15) & ~(size_t)15;
@@ -199,6 +213,8 @@ static bool launch_pair(const MatchParamsDev& P, const FramesDev& FR, const Matc
   OCSR_PAIR(4, 4, 2, 8, 8, 8)
   OCSR_PAIR(4, 4, 2, 8, 8, 12)
   OCSR_PAIR(4, 4, 2, 8, 8, 16)
+  OCSR_PAIR(4, 4, 4, 8, 8, 8)
+  OCSR_PAIR(4, 4, 4, 8, 8, 12)
   OCSR_PAIR(8, 8, 8, 8, 8, 8)
   OCSR_PAIR(8, 8, 8, 8, 8, 12)
   OCSR_PAIR(8, 8, 8, 8, 8, 16)
