@@ -160,7 +160,9 @@ def batch_section(ocsr, synth, steps, warmup):
             kern[name] = {"launches": cnt, "avg_us": round(1e3 * tot / cnt, 3)}
     census_px = sum(2 * L.numel() + 2 * (L.shape[0] // p["close_scale"]) * (L.shape[1] // p["close_scale"])
                     for L, _ in imgs)
-    ops = {"census": census_px * 62, "match": costs * 4}
+    costs_far = sum(w["costs_far"] for w in work)
+    ops = {"census": census_px * 62, "match": costs * 4, "match_far": costs_far * 4,
+           "match_close": (costs - costs_far) * 4}
     for k, v in ops.items():
         if k in kern:
             kern[k]["tops"] = round(v / (kern[k]["avg_us"] * 1e-6) / 1e12, 3)
@@ -330,17 +332,25 @@ def main():
         step()
     torch.cuda.synchronize()
 
-    # timed region: K back-to-back frames, library kernel timing on
-    ocsr.reset_timing()
-    ocsr.set_timing(True)
+    # timed region: K back-to-back frames
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    ocsr.set_timing(False)
     ms_per_step = 1e3 * (t1 - t0) / args.steps
+
+    # the same K frames again with every kernel bracketed by HIP events on its stream
+    ocsr.reset_timing()
+    ocsr.set_timing(True)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    ms_per_step_events = 1e3 * (time.perf_counter() - t2) / args.steps
+    ocsr.set_timing(False)
     kern = {}
     for name in ("census", "plan", "match", "match_far", "match_close", "aggregate", "reset",
                  "fused", "graph"):
@@ -413,6 +423,7 @@ def main():
                    "block_evals_per_frame": evals,
                    "blocks": int(nb), "census_level_px": census_px},
         "block_evals_per_s": round(evals / (ms_per_step * 1e-3), 1),
+        "ms_per_step_with_kernel_events": round(ms_per_step_events, 4),
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
                        "p99": round(float(np.percentile(lat, 99)), 4),
                        "frames": int(len(lat))},

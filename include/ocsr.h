@@ -330,21 +330,23 @@ int32_t ocsr_ctx_set_option(ocsr_ctx* ctx, int32_t option, int32_t value);
 /* Matching kernel variants (for tuners)                                            */
 /* ------------------------------------------------------------------------------ */
 /* A TILED path's blocks run in a register-blocked kernel: `rows` block rows per wave
- * (4 for blocks up to 4x4, 8 for blocks up to 8x8) and `cpl` consecutive candidates per
- * lane, covering (64 / rows) * cpl level candidates. Any variant that covers a path
- * gives identical results; they differ in speed only. By default the smallest covering
- * cpl of the smallest covering rows is used.
+ * (4 for blocks up to 4x4, 8 for blocks up to 8x8), `cpl` consecutive candidates per
+ * lane and `passes` passes over the candidates, covering (64 / rows) * cpl * passes
+ * level candidates. Fewer candidates per lane need fewer registers, so more waves fit
+ * on a compute unit, at the price of more passes. Any variant that covers a path gives
+ * identical results; they differ in speed only. By default the first covering variant
+ * in the library's order is used (the fewest candidates per lane in one pass).
  *
- * ocsr_variant_candidates: writes up to `cap` (rows, cpl) pairs (host arrays) that
- * cover bw x bh blocks and n_candidates level candidates; returns how many exist (may
- * exceed cap), or a negative status. */
+ * ocsr_variant_candidates: writes up to `cap` (rows, cpl, passes) triples (host arrays)
+ * that cover bw x bh blocks and n_candidates level candidates; returns how many exist
+ * (may exceed cap), or a negative status. */
 int32_t ocsr_variant_candidates(int32_t bw, int32_t bh, int32_t n_candidates, int32_t* rows,
-                                int32_t* cpl, int32_t cap);
+                                int32_t* cpl, int32_t* passes, int32_t cap);
 /* Chooses the variant for paths of bw x bh blocks and n_candidates level candidates in
  * this context (rows == 0 restores the default). OCSR_E_INVALID if the variant does not
  * cover such a path. */
 int32_t ocsr_ctx_set_variant(ocsr_ctx* ctx, int32_t bw, int32_t bh, int32_t n_candidates,
-                             int32_t rows, int32_t cpl);
+                             int32_t rows, int32_t cpl, int32_t passes);
 
 /* Graph submissions of the context so far: replays of a cached graph (*hits) and
  * captures (*builds). Either pointer may be NULL. */

@@ -27,7 +27,7 @@ DEFAULT_MATCH_WGS_PER_CU = 16
 @dataclass
 class Table:
     arch: str
-    variants: dict = field(default_factory=dict)   # "bw x bh / nd" -> [rows, cpl]
+    variants: dict = field(default_factory=dict)   # "bw x bh / nd" -> [rows, cpl, passes]
     blocks_per_wave: int = DEFAULT_BLOCKS_PER_WAVE
     match_wgs_per_cu: int = DEFAULT_MATCH_WGS_PER_CU
     timings_ms: dict = field(default_factory=dict)  # choice -> measured time
@@ -77,10 +77,10 @@ def apply(table: Table, device: int | None = None) -> None:
     """Installs a table's choices in the device's library context."""
     if table.arch != _arch():
         raise ValueError(f"table measured on {table.arch}, device is {_arch()}")
-    for key, (rows, cpl) in table.variants.items():
+    for key, (rows, cpl, passes) in table.variants.items():
         bw_bh, nd = key.split("/")
         bw, bh = (int(v) for v in bw_bh.split("x"))
-        ocsr.set_variant(bw, bh, int(nd), rows, cpl, device)
+        ocsr.set_variant(bw, bh, int(nd), rows, cpl, passes, device)
     ocsr.set_option(ocsr.OPTION_BLOCKS_PER_WAVE, table.blocks_per_wave, device)
     ocsr.set_option(ocsr.OPTION_MATCH_WGS_PER_CU, table.match_wgs_per_cu, device)
 
@@ -88,7 +88,7 @@ def apply(table: Table, device: int | None = None) -> None:
 def reset(params: dict, device: int | None = None) -> None:
     """Restores the library defaults for the paths of `params`."""
     for bw, bh, nd in path_shapes(params):
-        ocsr.set_variant(bw, bh, nd, 0, 0, device)
+        ocsr.set_variant(bw, bh, nd, 0, 0, 0, device)
     ocsr.set_option(ocsr.OPTION_BLOCKS_PER_WAVE, DEFAULT_BLOCKS_PER_WAVE, device)
     ocsr.set_option(ocsr.OPTION_MATCH_WGS_PER_CU, DEFAULT_MATCH_WGS_PER_CU, device)
 
@@ -117,14 +117,14 @@ def tune(run, params: dict, reps: int = 20, warmup: int = 3,
 
     for bw, bh, nd in path_shapes(params):
         best = None
-        for rows, cpl in ocsr.variant_candidates(bw, bh, nd):
-            ocsr.set_variant(bw, bh, nd, rows, cpl, device)
-            ms = measure(f"variant {shape_key(bw, bh, nd)} rows={rows} cpl={cpl}")
+        for rows, cpl, passes in ocsr.variant_candidates(bw, bh, nd):
+            ocsr.set_variant(bw, bh, nd, rows, cpl, passes, device)
+            ms = measure(f"variant {shape_key(bw, bh, nd)} rows={rows} cpl={cpl} passes={passes}")
             if best is None or ms < best[0]:
-                best = (ms, rows, cpl)
+                best = (ms, rows, cpl, passes)
         if best is not None:
-            ocsr.set_variant(bw, bh, nd, best[1], best[2], device)
-            table.variants[shape_key(bw, bh, nd)] = [best[1], best[2]]
+            ocsr.set_variant(bw, bh, nd, best[1], best[2], best[3], device)
+            table.variants[shape_key(bw, bh, nd)] = [best[1], best[2], best[3]]
 
     best = None
     for bpw in blocks_per_wave:
@@ -155,15 +155,15 @@ def to_json(table: Table) -> str:
 
 def from_json(text: str) -> Table:
     d = json.loads(text)
-    t = Table(arch=d["arch"], variants={k: [int(v[0]), int(v[1])] for k, v in d["variants"].items()},
+    t = Table(arch=d["arch"], variants={k: [int(x) for x in v] for k, v in d["variants"].items()},
               blocks_per_wave=int(d["blocks_per_wave"]),
               match_wgs_per_cu=int(d["match_wgs_per_cu"]),
               timings_ms=dict(d.get("timings_ms", {})))
-    for key, (rows, cpl) in t.variants.items():
+    for key, v in t.variants.items():
         bw_bh, nd = key.split("/")
-        bw, bh = (int(v) for v in bw_bh.split("x"))
-        if (rows, cpl) not in ocsr.variant_candidates(bw, bh, int(nd)):
-            raise ValueError(f"table entry {key}: no kernel rows={rows} cpl={cpl} covers it")
+        bw, bh = (int(x) for x in bw_bh.split("x"))
+        if len(v) != 3 or tuple(v) not in ocsr.variant_candidates(bw, bh, int(nd)):
+            raise ValueError(f"table entry {key}: no kernel {v} (rows, cpl, passes) covers it")
     if not 1 <= t.blocks_per_wave <= 8 or not 1 <= t.match_wgs_per_cu <= 64:
         raise ValueError("table launch settings out of range")
     return t

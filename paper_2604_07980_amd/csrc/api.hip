@@ -34,7 +34,7 @@ struct ocsr_ctx {
   // recently used first, keyed by everything the launches depend on
   int use_graph = 0;
   // matching kernel variants chosen for (bw, bh, level candidates), e.g. by a tuner
-  std::map<std::array<int, 3>, std::pair<int, int>> variants;
+  std::map<std::array<int, 3>, std::array<int, 3>> variants;
   int match_wgs_per_cu = 16;
   int blocks_per_wave = 1;
   struct Graph {
@@ -243,10 +243,12 @@ int32_t build_params(const ocsr_ctx* ctx, const ocsr_match_params* p, int close_
                   l == 0 ? "far" : "close");
     ph.rows = v.rows;
     ph.cpl = v.cpl;
+    ph.passes = v.passes;
     auto it = ctx->variants.find({ph.bw, ph.bh, ph.nd});
-    if (it != ctx->variants.end() && variant_valid(ph, it->second.first, it->second.second)) {
-      ph.rows = it->second.first;
-      ph.cpl = it->second.second;
+    if (it != ctx->variants.end() && variant_valid(ph, it->second[0], it->second[1], it->second[2])) {
+      ph.rows = it->second[0];
+      ph.cpl = it->second[1];
+      ph.passes = it->second[2];
     }
   }
   if (p->lr_tol < 0) return fail(OCSR_E_INVALID, "lr_tol < 0");
@@ -629,19 +631,19 @@ int32_t ocsr_dense_match(ocsr_ctx* ctx, const ocsr_level* lv, int32_t dmin, int3
 }
 
 int32_t ocsr_variant_candidates(int32_t bw, int32_t bh, int32_t n_candidates, int32_t* rows,
-                                int32_t* cpl, int32_t cap) {
+                                int32_t* cpl, int32_t* passes, int32_t cap) {
   g_last_error.clear();
-  if (cap < 0 || (cap > 0 && (!rows || !cpl))) return fail(OCSR_E_INVALID, "null output arrays");
+  if (cap < 0 || (cap > 0 && (!rows || !cpl || !passes))) return fail(OCSR_E_INVALID, "null output arrays");
   PathDev ph = {};
   ph.mode = OCSR_MODE_TILED;
   ph.bw = bw;
   ph.bh = bh;
   ph.nd = n_candidates;
-  return variant_candidates(ph, rows, cpl, cap);
+  return variant_candidates(ph, rows, cpl, passes, cap);
 }
 
 int32_t ocsr_ctx_set_variant(ocsr_ctx* ctx, int32_t bw, int32_t bh, int32_t n_candidates,
-                             int32_t rows, int32_t cpl) {
+                             int32_t rows, int32_t cpl, int32_t passes) {
   g_last_error.clear();
   if (!ctx) return fail(OCSR_E_INVALID, "null context");
   if (rows == 0) {
@@ -653,10 +655,10 @@ int32_t ocsr_ctx_set_variant(ocsr_ctx* ctx, int32_t bw, int32_t bh, int32_t n_ca
   ph.bw = bw;
   ph.bh = bh;
   ph.nd = n_candidates;
-  if (!variant_valid(ph, rows, cpl))
-    return fail(OCSR_E_INVALID, "no kernel with %d rows and %d candidates per lane covers %dx%d "
-                "blocks and %d candidates", rows, cpl, bw, bh, n_candidates);
-  ctx->variants[{bw, bh, n_candidates}] = {rows, cpl};
+  if (!variant_valid(ph, rows, cpl, passes))
+    return fail(OCSR_E_INVALID, "no kernel with %d rows, %d candidates per lane and %d passes "
+                "covers %dx%d blocks and %d candidates", rows, cpl, passes, bw, bh, n_candidates);
+  ctx->variants[{bw, bh, n_candidates}] = {rows, cpl, passes};
   return OCSR_OK;
 }
 

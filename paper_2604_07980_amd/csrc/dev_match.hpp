@@ -334,21 +334,22 @@ __device__ __forceinline__ void stage_strip(uint64_t* __restrict__ S, const uint
   }
 }
 
-template <int ROWS, int NX, int CPL>
+template <int ROWS, int NX, int CPL, int PASSES = 1>
 struct Tiled {
   static constexpr int G = 64 / ROWS;
-  static constexpr int NC = G * CPL;           // candidates one wave covers
+  static constexpr int NC = G * CPL * PASSES;  // candidates one wave covers
   static constexpr int SW = NC + NX - 1;       // strip words per row
   static constexpr size_t kLdsBytes = sizeof(uint64_t) * (ROWS * SW + ROWS * NX) +
                                       sizeof(uint32_t) * 2 * NC;
   static_assert(ROWS == 4 || ROWS == 8, "rows");
 };
 
-template <int ROWS, int NX, int CPL>
+template <int ROWS, int NX, int CPL, int PASSES = 1>
 __device__ __forceinline__ void match_block_tiled(const MatchParamsDev& P, const FrameDev& fr,
                                                   const MatchWs& ws, const DebugDev& dbg,
                                                   const BlockCtx& c, int lane, void* lds) {
-  using TT = Tiled<ROWS, NX, CPL>;
+  using TT = Tiled<ROWS, NX, CPL, PASSES>;
+  constexpr int PC = TT::G * CPL;              // candidates of one pass
   constexpr int SW = TT::SW, NC = TT::NC;
   uint64_t* S = (uint64_t*)lds;
   uint64_t* T = S + ROWS * SW;
@@ -388,20 +389,24 @@ __device__ __forceinline__ void match_block_tiled(const MatchParamsDev& P, const
 #pragma unroll
   for (int i = 0; i < NX; ++i) t[i] = T[j * NX + i];
   uint32_t acc[CPL];
-  // strip entry e = grp*CPL + c + i holds CR(X0 + i - d) for d = dhi - (grp*CPL + c)
-  if (j < ny) row_costs<NX, CPL>(t, S + j * SW + grp * CPL, rowmask, col_all, col_any, acc);
-#pragma unroll
-  for (int cc = 0; cc < CPL; ++cc)
-    if (j >= ny) acc[cc] = 0;
   uint32_t key = 0xFFFFFFFFu;
+  // strip entry e + i (e = ps*PC + grp*CPL + c) holds CR(X0 + i - d) for d = dhi - e;
+  // the candidates are covered in PASSES passes of PC
+#pragma unroll 1
+  for (int ps = 0; ps < PASSES; ++ps) {
+    if (j < ny) row_costs<NX, CPL>(t, S + j * SW + ps * PC + grp * CPL, rowmask, col_all, col_any, acc);
 #pragma unroll
-  for (int cc = 0; cc < CPL; ++cc) {
-    const uint32_t tot = row_sum<ROWS>(acc[cc]);
-    const int e = grp * CPL + cc;
-    if (e < nd) {
-      const int kc = nd - 1 - e;
-      key = min(key, (tot << 16) | (uint32_t)kc);
-      if (j == 0) costf[kc] = tot;
+    for (int cc = 0; cc < CPL; ++cc)
+      if (j >= ny) acc[cc] = 0;
+#pragma unroll
+    for (int cc = 0; cc < CPL; ++cc) {
+      const uint32_t tot = row_sum<ROWS>(acc[cc]);
+      const int e = ps * PC + grp * CPL + cc;
+      if (e < nd) {
+        const int kc = nd - 1 - e;
+        key = min(key, (tot << 16) | (uint32_t)kc);
+        if (j == 0) costf[kc] = tot;
+      }
     }
   }
   key = wave_min_u32(key, ROWS);
@@ -417,18 +422,21 @@ __device__ __forceinline__ void match_block_tiled(const MatchParamsDev& P, const
   // backward strip: CL(X0 - d_f + dlo + m, Y0 + j)
   stage_strip<ROWS, SW>(S, Lb, lv.pitch, X0 - d_f + dlo, ny, sw, lv.W, lane);
   wave_sync();
-  if (j < ny) row_costs<NX, CPL>(t, S + j * SW + grp * CPL, rowmask, col_all, col_any, acc);
-#pragma unroll
-  for (int cc = 0; cc < CPL; ++cc)
-    if (j >= ny) acc[cc] = 0;
   uint32_t bkey = 0xFFFFFFFFu;
+#pragma unroll 1
+  for (int ps = 0; ps < PASSES; ++ps) {
+    if (j < ny) row_costs<NX, CPL>(t, S + j * SW + ps * PC + grp * CPL, rowmask, col_all, col_any, acc);
 #pragma unroll
-  for (int cc = 0; cc < CPL; ++cc) {
-    const uint32_t tot = row_sum<ROWS>(acc[cc]);
-    const int kc = grp * CPL + cc;       // candidate dlo + kc
-    if (kc < nd) {
-      bkey = min(bkey, (tot << 16) | (uint32_t)kc);
-      if (j == 0) costb[kc] = tot;
+    for (int cc = 0; cc < CPL; ++cc)
+      if (j >= ny) acc[cc] = 0;
+#pragma unroll
+    for (int cc = 0; cc < CPL; ++cc) {
+      const uint32_t tot = row_sum<ROWS>(acc[cc]);
+      const int kc = ps * PC + grp * CPL + cc;   // candidate dlo + kc
+      if (kc < nd) {
+        bkey = min(bkey, (tot << 16) | (uint32_t)kc);
+        if (j == 0) costb[kc] = tot;
+      }
     }
   }
   bkey = wave_min_u32(bkey, ROWS);

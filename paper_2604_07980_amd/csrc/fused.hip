@@ -104,7 +104,7 @@ FusedPair fused_pair(const MatchParamsDev& P, int sx, int sy) {
   if (sx != 3 || sy != 4) return FusedPair::kNone;
   const PathDev& f = P.path[0];
   const PathDev& c = P.path[1];
-  if (c.rows != 8) return FusedPair::kNone;
+  if (c.rows != 8 || f.passes != 1 || c.passes != 1) return FusedPair::kNone;
   if (f.rows == 4 && f.cpl == 2) {
     if (c.cpl == 12) return FusedPair::k4_2__8_12;
     if (c.cpl == 8) return FusedPair::k4_2__8_8;

@@ -40,10 +40,10 @@ constexpr int tiled_waves() {
   return ROWS == 4 ? (CPL <= 4 ? 6 : CPL <= 8 ? 4 : 2) : (CPL <= 4 ? 5 : CPL <= 12 ? 3 : CPL <= 16 ? 2 : 1);
 }
 
-template <int ROWS, int NX, int CPL>
+template <int ROWS, int NX, int CPL, int PASSES>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(tiled_waves<ROWS, CPL>()))) void match_tiled_kernel(MatchParamsDev P, FramesDev FR,
                                                           MatchWs ws, DebugDev dbg, int level) {
-  constexpr size_t kWave = (dev::Tiled<ROWS, NX, CPL>::kLdsBytes + 15) & ~(size_t)15;
+  constexpr size_t kWave = (dev::Tiled<ROWS, NX, CPL, PASSES>::kLdsBytes + 15) & ~(size_t)15;
   __shared__ uint64_t lds[(kItemWaves * kWave + 7) / 8];
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int lane = threadIdx.x & 63;
@@ -52,7 +52,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(tiled_waves
     const FrameDev& fr = FR.f[f];
     dev::run_item(P, fr, f, FR.n_boxes_total, ws, level, q, wave, lane,
                   [&](const dev::BlockCtx& c) {
-      dev::match_block_tiled<ROWS, NX, CPL>(P, fr, ws, dbg, c, lane, wl);
+      dev::match_block_tiled<ROWS, NX, CPL, PASSES>(P, fr, ws, dbg, c, lane, wl);
     });
   });
 }
@@ -143,27 +143,30 @@ MatchWs match_ws_carve(void* base, int n_frames, int n_boxes_total, int cap_bloc
 }
 
 namespace {
-// the built kernels, as in launch_level
-struct BuiltVariant { int rows, nx, cpl; };
-constexpr BuiltVariant kBuilt[] = {{4, 4, 2},  {4, 4, 4},  {4, 4, 8},  {4, 4, 16}, {8, 8, 4},
-                                   {8, 8, 8},  {8, 8, 12}, {8, 8, 16}, {8, 8, 24}, {8, 8, 32}};
+// the built kernels, as in launch_level, in order of preference for the default
+struct BuiltVariant { int rows, nx, cpl, passes; };
+constexpr BuiltVariant kBuilt[] = {
+    {4, 4, 2, 1},  {4, 4, 4, 1},  {4, 4, 8, 1},  {4, 4, 16, 1}, {8, 8, 4, 1},  {8, 8, 8, 1},
+    {8, 8, 12, 1}, {8, 8, 16, 1}, {8, 8, 24, 1}, {8, 8, 32, 1}, {8, 8, 4, 2},  {8, 8, 4, 3},
+    {8, 8, 4, 4},  {8, 8, 6, 2},  {8, 8, 8, 2},  {4, 4, 2, 2},  {4, 4, 4, 2}};
 }  // namespace
 
-bool variant_valid(const PathDev& ph, int rows, int cpl) {
+bool variant_valid(const PathDev& ph, int rows, int cpl, int passes) {
   if (ph.mode != OCSR_MODE_TILED) return false;
   for (const BuiltVariant& b : kBuilt)
-    if (b.rows == rows && b.cpl == cpl)
-      return ph.bw <= b.nx && ph.bh <= b.rows && (64 / b.rows) * b.cpl >= ph.nd;
+    if (b.rows == rows && b.cpl == cpl && b.passes == passes)
+      return ph.bw <= b.nx && ph.bh <= b.rows && (64 / b.rows) * b.cpl * b.passes >= ph.nd;
   return false;
 }
 
-int variant_candidates(const PathDev& ph, int* rows, int* cpl, int cap) {
+int variant_candidates(const PathDev& ph, int* rows, int* cpl, int* passes, int cap) {
   int n = 0;
   for (const BuiltVariant& b : kBuilt) {
-    if (!variant_valid(ph, b.rows, b.cpl)) continue;
+    if (!variant_valid(ph, b.rows, b.cpl, b.passes)) continue;
     if (n < cap) {
       rows[n] = b.rows;
       cpl[n] = b.cpl;
+      passes[n] = b.passes;
     }
     ++n;
   }
@@ -172,28 +175,35 @@ int variant_candidates(const PathDev& ph, int* rows, int* cpl, int cap) {
 
 MatchVariant pick_variant(const PathDev& ph) {
   for (const BuiltVariant& b : kBuilt)
-    if (variant_valid(ph, b.rows, b.cpl)) return MatchVariant{1, b.rows, b.cpl};
-  return MatchVariant{0, 0, 0};
+    if (variant_valid(ph, b.rows, b.cpl, b.passes)) return MatchVariant{1, b.rows, b.cpl, b.passes};
+  return MatchVariant{0, 0, 0, 0};
 }
 
 static hipError_t launch_level(const MatchParamsDev& P, const FramesDev& FR, const MatchWs& ws,
                                const DebugDev& dbg, int level, int grid, hipStream_t stream) {
   const PathDev& v = P.path[level];
-#define OCSR_TILED(R, X, C)                                                              \
-  if (v.rows == R && v.cpl == C) {                                                       \
-    match_tiled_kernel<R, X, C><<<grid, 256, 0, stream>>>(P, FR, ws, dbg, level);       \
-    return hipGetLastError();                                                            \
+#define OCSR_TILED(R, X, C, PS)                                                             \
+  if (v.rows == R && v.cpl == C && v.passes == PS) {                                        \
+    match_tiled_kernel<R, X, C, PS><<<grid, 256, 0, stream>>>(P, FR, ws, dbg, level);       \
+    return hipGetLastError();                                                               \
   }
-  OCSR_TILED(4, 4, 2)
-  OCSR_TILED(4, 4, 4)
-  OCSR_TILED(4, 4, 8)
-  OCSR_TILED(4, 4, 16)
-  OCSR_TILED(8, 8, 4)
-  OCSR_TILED(8, 8, 8)
-  OCSR_TILED(8, 8, 12)
-  OCSR_TILED(8, 8, 16)
-  OCSR_TILED(8, 8, 24)
-  OCSR_TILED(8, 8, 32)
+  OCSR_TILED(4, 4, 2, 1)
+  OCSR_TILED(4, 4, 4, 1)
+  OCSR_TILED(4, 4, 8, 1)
+  OCSR_TILED(4, 4, 16, 1)
+  OCSR_TILED(8, 8, 4, 1)
+  OCSR_TILED(8, 8, 8, 1)
+  OCSR_TILED(8, 8, 12, 1)
+  OCSR_TILED(8, 8, 16, 1)
+  OCSR_TILED(8, 8, 24, 1)
+  OCSR_TILED(8, 8, 32, 1)
+  OCSR_TILED(8, 8, 4, 2)
+  OCSR_TILED(8, 8, 4, 3)
+  OCSR_TILED(8, 8, 4, 4)
+  OCSR_TILED(8, 8, 6, 2)
+  OCSR_TILED(8, 8, 8, 2)
+  OCSR_TILED(4, 4, 2, 2)
+  OCSR_TILED(4, 4, 4, 2)
 #undef OCSR_TILED
   return hipErrorNotSupported;   // rejected by the argument checks before any launch
 }
@@ -204,6 +214,7 @@ static bool launch_pair(const MatchParamsDev& P, const FramesDev& FR, const Matc
                         const DebugDev& dbg, int grid, hipStream_t stream, bool launch) {
   const PathDev& f = P.path[0];
   const PathDev& c = P.path[1];
+  if (f.passes != 1 || c.passes != 1) return false;
 #define OCSR_PAIR(FRW, FXW, FCP, CRW, CXW, CCP)                                          \
   if (f.rows == FRW && f.cpl == FCP && c.rows == CRW && c.cpl == CCP) {                 \
     if (launch)                                                                          \

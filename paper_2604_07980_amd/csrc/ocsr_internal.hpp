@@ -49,7 +49,7 @@ struct LevelDev {
 struct PathDev {
   int32_t mode, bw, bh, n_side;
   int32_t dlo, nd;                 // level search range [dlo, dlo + nd)
-  int32_t rows, cpl;               // matching kernel variant (chosen on the host)
+  int32_t rows, cpl, passes;       // matching kernel variant (chosen on the host)
 };
 
 // Matching parameters shared by every frame of a call.
@@ -142,19 +142,20 @@ struct LaunchTimer {
 };
 
 // Kernel variant of one level's blocks: the register-blocked TILED kernel with `rows`
-// block rows per wave (4: blocks up to 4 x 4, 8: up to 8 x 8) and `cpl` consecutive
-// candidates per lane, which covers (64 / rows) * cpl level candidates. Other shapes
-// (GRID mode, wider blocks, wider ranges) have no kernel in this build.
+// block rows per wave (4: blocks up to 4 x 4, 8: up to 8 x 8), `cpl` consecutive
+// candidates per lane and `passes` passes over the candidates, which covers
+// (64 / rows) * cpl * passes level candidates. Other shapes (GRID mode, wider blocks,
+// wider ranges) have no kernel in this build.
 struct MatchVariant {
   int tiled;           // 1: a register-blocked TILED kernel exists
-  int rows, cpl;
+  int rows, cpl, passes;
 };
-// the default: the smallest cpl of the smallest rows that covers the block and range
+// the default: the first built variant (in launch order) that covers the block and range
 MatchVariant pick_variant(const PathDev& ph);
-// whether the (rows, cpl) kernel is built and covers the path's blocks and range
-bool variant_valid(const PathDev& ph, int rows, int cpl);
-// every built (rows, cpl) that covers the path, up to cap of them; returns the count
-int variant_candidates(const PathDev& ph, int* rows, int* cpl, int cap);
+// whether the (rows, cpl, passes) kernel is built and covers the path's blocks and range
+bool variant_valid(const PathDev& ph, int rows, int cpl, int passes);
+// every built variant that covers the path, up to cap of them; returns the count
+int variant_candidates(const PathDev& ph, int* rows, int* cpl, int* passes, int cap);
 
 // Census of every view and level of every frame, and the plan of every frame, in one
 // launch (frames whose images are given).

@@ -156,9 +156,10 @@ def load(path: str = LIB_PATH):
         L.ocsr_ctx_reset_timing.restype = i32
         L.ocsr_ctx_graph_stats.argtypes = [vp, C.POINTER(i64), C.POINTER(i64)]
         L.ocsr_ctx_graph_stats.restype = i32
-        L.ocsr_variant_candidates.argtypes = [i32, i32, i32, C.POINTER(i32), C.POINTER(i32), i32]
+        L.ocsr_variant_candidates.argtypes = [i32, i32, i32, C.POINTER(i32), C.POINTER(i32),
+                                              C.POINTER(i32), i32]
         L.ocsr_variant_candidates.restype = i32
-        L.ocsr_ctx_set_variant.argtypes = [vp, i32, i32, i32, i32, i32]
+        L.ocsr_ctx_set_variant.argtypes = [vp, i32, i32, i32, i32, i32, i32]
         L.ocsr_ctx_set_variant.restype = i32
         L.ocsr_dense_workspace_bytes.argtypes = [i32, i32]
         L.ocsr_dense_workspace_bytes.restype = C.c_size_t
@@ -461,22 +462,22 @@ def set_graph(enable: bool, device: int | None = None):
     set_option(OPTION_GRAPH, 1 if enable else 0, device)
 
 
-def variant_candidates(bw: int, bh: int, n_candidates: int) -> list[tuple[int, int]]:
-    """Every (rows, cpl) matching kernel that covers bw x bh blocks and n_candidates
-    level candidates (host query, no device needed)."""
+def variant_candidates(bw: int, bh: int, n_candidates: int) -> list[tuple[int, int, int]]:
+    """Every (rows, cpl, passes) matching kernel that covers bw x bh blocks and
+    n_candidates level candidates (host query, no device needed)."""
     L = load()
-    rows, cpl = (C.c_int32 * 32)(), (C.c_int32 * 32)()
-    n = L.ocsr_variant_candidates(bw, bh, n_candidates, rows, cpl, 32)
+    rows, cpl, passes = (C.c_int32 * 64)(), (C.c_int32 * 64)(), (C.c_int32 * 64)()
+    n = L.ocsr_variant_candidates(bw, bh, n_candidates, rows, cpl, passes, 64)
     if n < 0:
         raise OcsrError(n, L.ocsr_last_error().decode())
-    return [(rows[i], cpl[i]) for i in range(min(n, 32))]
+    return [(rows[i], cpl[i], passes[i]) for i in range(min(n, 64))]
 
 
-def set_variant(bw: int, bh: int, n_candidates: int, rows: int, cpl: int,
+def set_variant(bw: int, bh: int, n_candidates: int, rows: int, cpl: int, passes: int = 1,
                 device: int | None = None):
-    """Use the (rows, cpl) kernel for paths of bw x bh blocks and n_candidates level
-    candidates (rows = 0 restores the default)."""
-    _check(load().ocsr_ctx_set_variant(context(device), bw, bh, n_candidates, rows, cpl))
+    """Use the (rows, cpl, passes) kernel for paths of bw x bh blocks and n_candidates
+    level candidates (rows = 0 restores the default)."""
+    _check(load().ocsr_ctx_set_variant(context(device), bw, bh, n_candidates, rows, cpl, passes))
 
 
 def level_candidates(path: dict, scale: int) -> int:

@@ -27,26 +27,29 @@ def test_variant_candidates_cover_the_shape(built):
     for bw, bh, nd in [(4, 4, 32), (8, 8, 96), (8, 8, 64), (8, 8, 128), (5, 5, 40), (4, 4, 1)]:
         cands = ocsr.variant_candidates(bw, bh, nd)
         assert cands, (bw, bh, nd)
-        for rows, cpl in cands:
+        for rows, cpl, passes in cands:
             assert rows in (4, 8) and bh <= rows and bw <= rows
-            assert (64 // rows) * cpl >= nd
+            assert (64 // rows) * cpl * passes >= nd
     # nothing covers blocks wider than 8 or more than 256 candidates
     assert ocsr.variant_candidates(9, 8, 32) == []
     assert ocsr.variant_candidates(8, 8, 257) == []
     # 4x4 blocks can also run in the 8-row kernels
-    assert (8, 4) in ocsr.variant_candidates(4, 4, 32)
+    assert (8, 4, 1) in ocsr.variant_candidates(4, 4, 32)
+    # fewer candidates per lane in several passes
+    assert (8, 4, 3) in ocsr.variant_candidates(8, 8, 96)
 
 
 def test_table_round_trip(built):
-    t = autotune.Table(arch="gfx950", variants={"4x4/32": [4, 2], "8x8/96": [8, 16]},
+    t = autotune.Table(arch="gfx950", variants={"4x4/32": [4, 2, 1], "8x8/96": [8, 4, 3]},
                        blocks_per_wave=2, match_wgs_per_cu=8, timings_ms={"a": 1.5})
     back = autotune.from_json(autotune.to_json(t))
     assert back == t
 
 
 @pytest.mark.parametrize("bad", [
-    '{"arch": "gfx950", "variants": {"8x8/96": [8, 8]}, "blocks_per_wave": 1, "match_wgs_per_cu": 16}',
-    '{"arch": "gfx950", "variants": {"8x8/96": [4, 16]}, "blocks_per_wave": 1, "match_wgs_per_cu": 16}',
+    '{"arch": "gfx950", "variants": {"8x8/96": [8, 8, 1]}, "blocks_per_wave": 1, "match_wgs_per_cu": 16}',
+    '{"arch": "gfx950", "variants": {"8x8/96": [4, 16, 1]}, "blocks_per_wave": 1, "match_wgs_per_cu": 16}',
+    '{"arch": "gfx950", "variants": {"8x8/96": [8, 12]}, "blocks_per_wave": 1, "match_wgs_per_cu": 16}',
     '{"arch": "gfx950", "variants": {}, "blocks_per_wave": 9, "match_wgs_per_cu": 16}',
     '{"arch": "gfx950", "variants": {}, "blocks_per_wave": 1, "match_wgs_per_cu": 0}',
 ])

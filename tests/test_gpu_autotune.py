@@ -32,12 +32,12 @@ def test_every_setting_same_results(lib, orc):
     want = np.concatenate([orc.run_scene(sc.left, sc.right, p, sc.boxes)[1][0] for sc in scenes])
     try:
         for bw, bh, nd in autotune.path_shapes(p):
-            for rows, cpl in lib.variant_candidates(bw, bh, nd):
-                lib.set_variant(bw, bh, nd, rows, cpl)
+            for rows, cpl, passes in lib.variant_candidates(bw, bh, nd):
+                lib.set_variant(bw, bh, nd, rows, cpl, passes)
                 for bpw in (1, 3):
                     lib.set_option(lib.OPTION_BLOCKS_PER_WAVE, bpw)
                     assert_results_match(lib.results_to_numpy(run()), want)
-                lib.set_variant(bw, bh, nd, 0, 0)
+                lib.set_variant(bw, bh, nd, 0, 0, 0)
         for g in (1, 4, 32):
             lib.set_option(lib.OPTION_MATCH_WGS_PER_CU, g)
             assert_results_match(lib.results_to_numpy(run()), want)
