@@ -236,8 +236,18 @@ size_t ocsr_frame_workspace_bytes(int32_t width, int32_t height,
                                   const ocsr_frame_params* fp, int32_t n_boxes,
                                   int32_t cap_blocks);
 
-/* imgL, imgR (dev): uint8 [height][pitch_bytes]. The four descriptor images live in
- * the workspace. Same outputs as ocsr_match_boxes. */
+/* imgL, imgR (dev): uint8 [height][pitch_bytes]. Same outputs as ocsr_match_boxes.
+ *
+ * The workspace starts with the frame's four descriptor images, each 256-byte aligned
+ * and row-contiguous at its level width: L and R at scale 1, then L and R at the close
+ * scale (level size = floor(size / close_scale)). Per level, a ranged box of that level's
+ * type (Sec. 4.3.4) lies on the level rectangle [x0, x1) x [y0, y1) of its eligible
+ * pixels, and for candidates dlo..dhi its searches read the right view on
+ * [x0 - dhi, x1 - dlo) and the left view on [x0 - (dhi - dlo), x1 + (dhi - dlo)), rows
+ * [y0, y1). By default (OCSR_OPTION_FULL_CENSUS 0) the call makes the descriptors of
+ * every 64 x 32 tile (tiles start at multiples of 64 and 32) that meets such a range
+ * of some box, and leaves the rest of the images undefined; with the option on, of
+ * every tile. */
 int32_t ocsr_range_frame(ocsr_ctx* ctx, const uint8_t* imgL, const uint8_t* imgR,
                          int32_t width, int32_t height, int32_t pitch_bytes,
                          const ocsr_frame_params* fp, const ocsr_box* boxes,
@@ -324,6 +334,12 @@ int32_t ocsr_dense_match(ocsr_ctx* ctx, const ocsr_level* lv, int32_t dmin, int3
  * so new image or box contents at the same addresses are picked up; a change of any
  * address or size captures a new graph. Results are identical to 0 (default). */
 #define OCSR_OPTION_GRAPH 3
+/* OCSR_OPTION_FULL_CENSUS: whole-frame and batch calls make the descriptors of a view
+ * and level only on the 64 x 32 level-pixel tiles that some ranged box's search reads
+ * (0, default), or on every tile (1). Box results are identical either way; the
+ * option only decides which workspace descriptors are defined after the call (see
+ * ocsr_range_frame). */
+#define OCSR_OPTION_FULL_CENSUS 6
 int32_t ocsr_ctx_set_option(ocsr_ctx* ctx, int32_t option, int32_t value);
 
 /* ------------------------------------------------------------------------------ */

@@ -37,6 +37,7 @@ struct ocsr_ctx {
   std::map<std::array<int, 3>, std::array<int, 3>> variants;
   int match_wgs_per_cu = 16;
   int blocks_per_wave = 1;
+  int full_census = 0;
   struct Graph {
     std::string key;
     hipGraphExec_t exec;
@@ -272,6 +273,7 @@ int32_t build_params(const ocsr_ctx* ctx, const ocsr_match_params* p, int close_
   d->d_eps = p->d_eps;
   d->cap_blocks = cap_blocks;
   d->item_blocks = kItemWaves * ctx->blocks_per_wave;
+  d->full_census = ctx->full_census;
   return OCSR_OK;
 }
 
@@ -589,6 +591,9 @@ int32_t ocsr_ctx_set_option(ocsr_ctx* ctx, int32_t option, int32_t value) {
       if (value < 1 || value > kMaxBlocksPerWave)
         return fail(OCSR_E_INVALID, "blocks per wave outside 1..%d", kMaxBlocksPerWave);
       ctx->blocks_per_wave = value;
+      return OCSR_OK;
+    case OCSR_OPTION_FULL_CENSUS:
+      ctx->full_census = value != 0;
       return OCSR_OK;
     case OCSR_OPTION_WAVES_PER_CU:
       if (value < 0 || value > 32) return fail(OCSR_E_INVALID, "workgroups per CU outside 0..32");

@@ -190,12 +190,51 @@ __device__ __forceinline__ void census_tile_generic(const uint8_t* __restrict__ 
   }
 }
 
+// Whether a box's search reads some pixel of the census tile [X0, X0 + 64) x
+// [Y0, Y0 + 32) of one view at one level. A ranged box belongs to the level of its
+// far/close type (Sec. 4.3.4); its blocks lie in the level rectangle [x0, x1) x [y0, y1)
+// of its eligible pixels (the same clipping as the plan). With candidates dlo..dhi, the
+// forward search reads the right view on [x0 - dhi, x1 - dlo); the template and the
+// backward search read the left view on [x0 - (dhi - dlo), x1 + (dhi - dlo)); all on
+// rows [y0, y1). The loop and the result are uniform over the wave.
+__device__ __forceinline__ bool census_tile_needed(const MatchParamsDev& MP, const FrameDev& fr,
+                                                   const ocsr_box* __restrict__ boxes, int level,
+                                                   int view, int X0, int Y0) {
+  const int lane = threadIdx.x & 63;
+  const LevelDev& lv = fr.lv[level];
+  const int s = lv.scale;
+  const int dlo = MP.path[level].dlo, dhi = dlo + MP.path[level].nd - 1;
+  const int ext_lo = view ? dhi : dhi - dlo;   // the read range starts this far left of x0
+  const int ext_hi = view ? -dlo : dhi - dlo;  // and ends this far right of x1
+  for (int base = 0; base < fr.n_boxes; base += 64) {
+    const int i = base + lane;
+    bool hit = false;
+    if (i < fr.n_boxes) {
+      const ocsr_box b = boxes[fr.box_off + i];
+      const int cx0 = max(b.x0, 0), cy0 = max(b.y0, 0);
+      const int cx1 = min(b.x1, fr.W), cy1 = min(b.y1, fr.H);
+      if ((b.flags & OCSR_BOX_RANGE) && cx0 < cx1 && cy0 < cy1 &&
+          (max(cx1 - cx0, cy1 - cy0) < MP.tau_s ? 0 : 1) == level) {
+        const int x0 = max(cdiv_nonneg(cx0, s), lv.sx), x1 = min(cdiv_nonneg(cx1, s), lv.W - lv.sx);
+        const int y0 = max(cdiv_nonneg(cy0, s), lv.sy), y1 = min(cdiv_nonneg(cy1, s), lv.H - lv.sy);
+        hit = x0 < x1 && y0 < y1 && y0 < Y0 + kCensusTileY && Y0 < y1 &&
+              x0 - ext_lo < X0 + kCensusTileX && X0 < x1 + ext_hi;
+      }
+    }
+    if (__ballot(hit)) return true;
+  }
+  return false;
+}
+
 // Census tile c of a whole-frame call: the tiles of frame f start at
 // FR.f[f].tile_begin and run over view L then R at level 0, then L and R at level 1.
-// Window (SX, SY) > (-1, -1) takes the LDS code; (-1, -1) the generic code with (sx, sy).
+// Unless MP.full_census is set, a tile no box's search reads is skipped (every wave of
+// the workgroup takes the same decision). Window (SX, SY) > (-1, -1) takes the LDS code;
+// (-1, -1) the generic code with (sx, sy).
 template <int SX, int SY>
-__device__ __forceinline__ void frame_census_tile(const FramesDev& FR, int c, int sx, int sy,
-                                                  int sentinel, uint32_t* P) {
+__device__ __forceinline__ void frame_census_tile(const MatchParamsDev& MP, const FramesDev& FR,
+                                                  const ocsr_box* __restrict__ boxes, int c,
+                                                  int sx, int sy, int sentinel, uint32_t* P) {
   int f = 0;
   for (int k = 1; k < FR.n; ++k)
     if (c >= FR.f[k].tile_begin) f = k;
@@ -213,6 +252,7 @@ __device__ __forceinline__ void frame_census_tile(const FramesDev& FR, int c, in
   const uint8_t* img = view ? fr.imgR : fr.imgL;
   uint64_t* out = (uint64_t*)(view ? lv.R : lv.L);
   const int X0 = (t % tiles_x) * kCensusTileX, Y0 = (t / tiles_x) * kCensusTileY;
+  if (!MP.full_census && !census_tile_needed(MP, fr, boxes, level, view, X0, Y0)) return;
   if constexpr (SX >= 0) {
     census_tile<SX, SY>(img, fr.W, fr.H, fr.pitch, lv.scale, out, lv.pitch, X0, Y0, sentinel, P);
   } else {

@@ -51,7 +51,7 @@ __global__ __launch_bounds__(256) void fused_kernel(MatchParamsDev P, FramesDev 
     if (a < F) {
       if (wave == 0) dev::plan_frame(P, FR.f[a], a, FR.n_boxes_total, boxes, ws, lane);
     } else {
-      dev::frame_census_tile<CSX, CSY>(FR, a - F, CSX, CSY, sentinel, (uint32_t*)lds);
+      dev::frame_census_tile<CSX, CSY>(P, FR, boxes, a - F, CSX, CSY, sentinel, (uint32_t*)lds);
     }
     __syncthreads();   // the next item reuses the LDS
   }

@@ -30,7 +30,7 @@ __global__ __launch_bounds__(256) void frame_census_kernel(MatchParamsDev P, Fra
       dev::plan_frame(P, FR.f[blockIdx.x], blockIdx.x, FR.n_boxes_total, boxes, ws, threadIdx.x);
     return;
   }
-  dev::frame_census_tile<SX, SY>(FR, blockIdx.x - FR.n, sx, sy, sentinel, lds);
+  dev::frame_census_tile<SX, SY>(P, FR, boxes, blockIdx.x - FR.n, sx, sy, sentinel, lds);
 }
 
 // Waves per SIMD a single-level kernel is compiled for (as many as its registers allow

@@ -63,6 +63,8 @@ struct MatchParamsDev {
   float d_eps;
   int32_t cap_blocks;              // block capacity of one frame
   int32_t item_blocks;             // blocks per work item: kItemWaves x blocks per wave
+  int32_t full_census;             // whole-frame calls: 1 = census of every tile, 0 = only
+                                   // of the tiles some box's search reads
 };
 
 // One frame of a call: descriptor levels, its boxes and (whole-frame calls) its images.
