@@ -38,6 +38,7 @@ struct ocsr_ctx {
   int match_wgs_per_cu = 16;
   int blocks_per_wave = 1;
   int full_census = 0;
+  int census_list = 1;
   struct Graph {
     std::string key;
     hipGraphExec_t exec;
@@ -388,7 +389,8 @@ int32_t range_frames(ocsr_ctx* ctx, const ocsr_frame* frames, int n_frames,
                                   ctx->n_cu, ctx->wgs_per_cu, s, tp);
       return e == hipSuccess ? OCSR_OK : hip_fail(e, "fused launch");
     }
-    hipError_t e = launch_frame_census(P, FR, boxes, mws, fp->sx, fp->sy, sentinel, tiles, s, tp);
+    hipError_t e = launch_frame_census(P, FR, boxes, mws, fp->sx, fp->sy, sentinel, tiles, ctx->n_cu,
+                                       ctx->census_list != 0, s, tp);
     if (e != hipSuccess) return hip_fail(e, "census launch");
     e = launch_match(P, FR, boxes, mws, out, make_debug(nullptr), true,
                      std::max(1, ctx->n_cu * ctx->match_wgs_per_cu), s, tp);
@@ -407,7 +409,8 @@ int32_t range_frames(ocsr_ctx* ctx, const ocsr_frame* frames, int n_frames,
     put(&ws, sizeof(ws));
     put(&out, sizeof(out));
     put(&P, sizeof(P));
-    const int opts[4] = {fused ? 1 : 0, ctx->wgs_per_cu, ctx->n_cu, ctx->match_wgs_per_cu};
+    const int opts[5] = {fused ? 1 : 0, ctx->wgs_per_cu, ctx->n_cu, ctx->match_wgs_per_cu,
+                         ctx->census_list};
     put(opts, sizeof(opts));
     return graph_launch(ctx, key, enqueue, stream);
   }
@@ -594,6 +597,9 @@ int32_t ocsr_ctx_set_option(ocsr_ctx* ctx, int32_t option, int32_t value) {
       return OCSR_OK;
     case OCSR_OPTION_FULL_CENSUS:
       ctx->full_census = value != 0;
+      return OCSR_OK;
+    case OCSR_OPTION_CENSUS_TILE_LIST:
+      ctx->census_list = value != 0;
       return OCSR_OK;
     case OCSR_OPTION_WAVES_PER_CU:
       if (value < 0 || value > 32) return fail(OCSR_E_INVALID, "workgroups per CU outside 0..32");

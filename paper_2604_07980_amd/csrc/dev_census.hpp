@@ -228,13 +228,14 @@ __device__ __forceinline__ bool census_tile_needed(const MatchParamsDev& MP, con
 
 // Census tile c of a whole-frame call: the tiles of frame f start at
 // FR.f[f].tile_begin and run over view L then R at level 0, then L and R at level 1.
-// Unless MP.full_census is set, a tile no box's search reads is skipped (every wave of
-// the workgroup takes the same decision). Window (SX, SY) > (-1, -1) takes the LDS code;
-// (-1, -1) the generic code with (sx, sy).
+// With `check` set and MP.full_census clear, a tile no box's search reads is skipped
+// (every wave of the workgroup takes the same decision). Window (SX, SY) > (-1, -1)
+// takes the LDS code; (-1, -1) the generic code with (sx, sy).
 template <int SX, int SY>
 __device__ __forceinline__ void frame_census_tile(const MatchParamsDev& MP, const FramesDev& FR,
                                                   const ocsr_box* __restrict__ boxes, int c,
-                                                  int sx, int sy, int sentinel, uint32_t* P) {
+                                                  int sx, int sy, int sentinel, uint32_t* P,
+                                                  bool check = true) {
   int f = 0;
   for (int k = 1; k < FR.n; ++k)
     if (c >= FR.f[k].tile_begin) f = k;
@@ -252,11 +253,118 @@ __device__ __forceinline__ void frame_census_tile(const MatchParamsDev& MP, cons
   const uint8_t* img = view ? fr.imgR : fr.imgL;
   uint64_t* out = (uint64_t*)(view ? lv.R : lv.L);
   const int X0 = (t % tiles_x) * kCensusTileX, Y0 = (t / tiles_x) * kCensusTileY;
-  if (!MP.full_census && !census_tile_needed(MP, fr, boxes, level, view, X0, Y0)) return;
+  if (check && !MP.full_census && !census_tile_needed(MP, fr, boxes, level, view, X0, Y0)) return;
   if constexpr (SX >= 0) {
     census_tile<SX, SY>(img, fr.W, fr.H, fr.pitch, lv.scale, out, lv.pitch, X0, Y0, sentinel, P);
   } else {
     census_tile_generic(img, fr.W, fr.H, fr.pitch, lv.scale, out, lv.pitch, X0, Y0, sx, sy, sentinel);
+  }
+}
+
+// Sets bit c of `bits` for every tile c of the call that some box's search reads (the
+// ranges of census_tile_needed), or for every tile when MP.full_census is set. One
+// thread per box; a box sets, per view and tile row, one run of consecutive tile bits.
+__device__ __forceinline__ void mark_census_tiles(const MatchParamsDev& MP, const FramesDev& FR,
+                                                  const ocsr_box* __restrict__ boxes, int n_tiles,
+                                                  uint32_t* bits) {
+  const int tid = threadIdx.x;
+  const int n_words = (n_tiles + 31) >> 5;
+  if (MP.full_census) {
+    for (int i = tid; i < n_words; i += 256) {
+      const int rem = n_tiles - 32 * i;
+      bits[i] = rem >= 32 ? 0xFFFFFFFFu : ((1u << rem) - 1u);
+    }
+    return;
+  }
+  for (int f = 0; f < FR.n; ++f) {
+    const FrameDev& fr = FR.f[f];
+    for (int i = tid; i < fr.n_boxes; i += 256) {
+      const ocsr_box b = boxes[fr.box_off + i];
+      const int cx0 = max(b.x0, 0), cy0 = max(b.y0, 0);
+      const int cx1 = min(b.x1, fr.W), cy1 = min(b.y1, fr.H);
+      if (!(b.flags & OCSR_BOX_RANGE) || !(cx0 < cx1 && cy0 < cy1)) continue;
+      const int level = max(cx1 - cx0, cy1 - cy0) < MP.tau_s ? 0 : 1;
+      const LevelDev& lv = fr.lv[level];
+      const int s = lv.scale;
+      const int x0 = max(cdiv_nonneg(cx0, s), lv.sx), x1 = min(cdiv_nonneg(cx1, s), lv.W - lv.sx);
+      const int y0 = max(cdiv_nonneg(cy0, s), lv.sy), y1 = min(cdiv_nonneg(cy1, s), lv.H - lv.sy);
+      if (!(x0 < x1 && y0 < y1)) continue;
+      const int dlo = MP.path[level].dlo, dhi = dlo + MP.path[level].nd - 1;
+      const int tiles_x = level ? fr.tiles1_x : fr.tiles0_x;
+      const int tiles = level ? fr.tiles1 : fr.tiles0;
+      const int lbase = fr.tile_begin + (level ? 2 * fr.tiles0 : 0);
+      for (int view = 0; view < 2; ++view) {
+        const int a = max(x0 - (view ? dhi : dhi - dlo), 0);
+        const int e = min(x1 + (view ? -dlo : dhi - dlo), tiles_x * kCensusTileX);
+        if (a >= e) continue;
+        const int ta = a / kCensusTileX, tb = (e - 1) / kCensusTileX;
+        for (int ty = y0 / kCensusTileY; ty <= (y1 - 1) / kCensusTileY; ++ty) {
+          const int first = lbase + view * tiles + ty * tiles_x + ta;
+          const int last = first + (tb - ta);
+          for (int wd = first >> 5; wd <= (last >> 5); ++wd) {
+            const int lo = max(first - 32 * wd, 0), hi = min(last - 32 * wd, 31);
+            const uint32_t upto = hi == 31 ? 0xFFFFFFFFu : ((1u << (hi + 1)) - 1u);
+            atomicOr(&bits[wd], upto & ~((1u << lo) - 1u));
+          }
+        }
+      }
+    }
+  }
+}
+
+// Census of a whole-frame call by G persistent workgroups (this is workgroup w): each
+// builds the same bitmap of needed tiles in LDS, counts them, and makes the tiles of
+// ranks [N w / G, N (w + 1) / G) in tile order, where N is their number. Workgroups agree
+// on the list without communicating. bits: kCensusListWords words; list: kCensusListCap.
+template <int SX, int SY>
+__device__ __forceinline__ void frame_census_listed(const MatchParamsDev& MP, const FramesDev& FR,
+                                                    const ocsr_box* __restrict__ boxes,
+                                                    int n_tiles, int w, int G, int sx, int sy,
+                                                    int sentinel, uint32_t* P, uint32_t* bits,
+                                                    int* list, int* sc) {
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int n_words = (n_tiles + 31) >> 5;
+  for (int i = tid; i < n_words; i += 256) bits[i] = 0;
+  __syncthreads();
+  mark_census_tiles(MP, FR, boxes, n_tiles, bits);
+  __syncthreads();
+  // thread t owns words [t * wpt, (t + 1) * wpt); ranks run in word order
+  const int wpt = (n_words + 255) >> 8;
+  const int w0 = tid * wpt;
+  int cnt = 0;
+  for (int k = 0; k < wpt; ++k)
+    if (w0 + k < n_words) cnt += __popc(bits[w0 + k]);
+  const int incl = wave_incl_scan(cnt, lane);
+  if (lane == 63) sc[wave] = incl;
+  __syncthreads();
+  int before = 0, N = 0;
+  for (int v = 0; v < 4; ++v) {
+    before += v < wave ? sc[v] : 0;
+    N += sc[v];
+  }
+  const int excl = before + incl - cnt;
+  const int lo = (int)((long long)N * w / G), hi = (int)((long long)N * (w + 1) / G);
+  for (int base = lo; base < hi; base += kCensusListCap) {
+    const int end = min(hi, base + kCensusListCap);
+    if (excl < end && excl + cnt > base) {
+      int r = excl;
+      for (int k = 0; k < wpt && r < end; ++k) {
+        uint32_t m = w0 + k < n_words ? bits[w0 + k] : 0u;
+        while (m) {
+          const int bit = __ffs(m) - 1;
+          m &= m - 1;
+          if (r >= base && r < end) list[r - base] = 32 * (w0 + k) + bit;
+          ++r;
+        }
+      }
+    }
+    __syncthreads();
+    for (int q = 0; q < end - base; ++q) {
+      const int c = __builtin_amdgcn_readfirstlane(list[q]);
+      frame_census_tile<SX, SY>(MP, FR, boxes, c, sx, sy, sentinel, P, false);
+      __syncthreads();   // the next tile reuses P; the next chunk rewrites the list
+    }
   }
 }
 

@@ -477,7 +477,13 @@ __device__ __forceinline__ void level_items(const FramesDev& FR, const MatchWs& 
 // ---------------------------------------------------------------------------------
 struct AggLds {
   float vals[kAggMax];
-  int32_t scratch[272];
+  int32_t hist[1024];     // value histogram of the trimmed median
+  float list[2][64];      // values of the bins holding the two middle ranks
+  int32_t scratch[272];   // radix bins [0, 256), then scalars
+  int32_t n_valid, n_eligible, seg_start, seg_len;
+  uint32_t vmin, vmax;    // bit patterns of the smallest and largest valid value
+  int32_t bin[2], rank[2], count[2];
+  uint32_t pick[2];
 };
 
 __device__ __forceinline__ float median_sorted(const float* v, int m) {
@@ -522,6 +528,90 @@ __device__ __forceinline__ uint32_t radix_select(const float* vals, int n, int k
   return prefix;
 }
 
+
+// Bin of v among 1024 equal-width bins over [vmin, vmin + 1024 / scale]: a monotone map,
+// so every value of a lower bin is smaller than every value of a higher one.
+__device__ __forceinline__ int value_bin(float v, float vmin, float scale) {
+  return min((int)((v - vmin) * scale), 1023);
+}
+
+// The k-th and (k + 1)-th smallest (0-based) of the n non-negative floats in sm.vals
+// (the second only when want2), as bit patterns. The values are binned by value
+// (value_bin); a scan of the bin counts finds the bins of the two ranks and their ranks
+// within them; one wave then ranks the few values of each such bin against each other.
+// A radix selection over all values handles equal bounds, a bin of more than 64 values
+// or a range too narrow to scale. vmin, vmax: the smallest and largest value.
+__device__ __forceinline__ void select_middle(AggLds& sm, int n, int k, bool want2, float vmin,
+                                              float vmax, uint32_t* u1, uint32_t* u2) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (vmin == vmax) {
+    *u1 = *u2 = __float_as_uint(vmin);
+    return;
+  }
+  const float scale = 1024.0f / (vmax - vmin);
+  bool fallback = !(scale < 1e30f);
+  if (!fallback) {
+    for (int i = tid; i < n; i += 256) atomicAdd(&sm.hist[value_bin(sm.vals[i], vmin, scale)], 1);
+    if (tid == 0) { sm.count[0] = 0; sm.count[1] = 0; }
+    __syncthreads();
+    // thread t owns bins 4t .. 4t + 3
+    const int c0 = sm.hist[4 * tid], c1 = sm.hist[4 * tid + 1], c2 = sm.hist[4 * tid + 2],
+              c3 = sm.hist[4 * tid + 3];
+    const int sum = c0 + c1 + c2 + c3;
+    const int incl = wave_incl_scan(sum, lane);
+    if (lane == 63) sm.scratch[256 + wave] = incl;
+    __syncthreads();
+    int excl = incl - sum;
+    for (int v = 0; v < wave; ++v) excl += sm.scratch[256 + v];
+    for (int j = 0; j < (want2 ? 2 : 1); ++j) {
+      const int kj = k + j;
+      if (kj >= excl && kj < excl + sum) {   // exactly one thread
+        int b = 4 * tid, kk = kj - excl;
+        if (kk >= c0) { kk -= c0; ++b;
+          if (kk >= c1) { kk -= c1; ++b;
+            if (kk >= c2) { kk -= c2; ++b; } } }
+        sm.bin[j] = b;
+        sm.rank[j] = kk;
+      }
+    }
+    __syncthreads();
+    const int b1 = sm.bin[0], b2 = want2 ? sm.bin[1] : b1;
+    fallback = sm.hist[b1] > 64 || sm.hist[b2] > 64;
+    if (!fallback) {
+      // the values of bins b1 and b2 (list 1 only when the bins differ)
+      for (int i = tid; i < n; i += 256) {
+        const float v = sm.vals[i];
+        const int b = value_bin(v, vmin, scale);
+        if (b == b1) sm.list[0][atomicAdd(&sm.count[0], 1)] = v;
+        else if (b == b2) sm.list[1][atomicAdd(&sm.count[1], 1)] = v;
+      }
+      __syncthreads();
+      if (wave == 0) {
+        for (int j = 0; j < (want2 ? 2 : 1); ++j) {
+          const int li = (j == 1 && b2 != b1) ? 1 : 0;
+          const int c = sm.count[li];
+          const float* lst = sm.list[li];
+          const float x = lane < c ? lst[lane] : 0.0f;
+          int less = 0, eq = 0;
+          for (int i = 0; i < c; ++i) {
+            const float y = lst[i];
+            less += y < x;
+            eq += y == x;
+          }
+          // lanes holding equal values agree, so any of them may store
+          if (lane < c && sm.rank[j] >= less && sm.rank[j] < less + eq) sm.pick[j] = __float_as_uint(x);
+        }
+      }
+      __syncthreads();
+      *u1 = sm.pick[0];
+      *u2 = want2 ? sm.pick[1] : sm.pick[0];
+      return;
+    }
+  }
+  *u1 = radix_select(sm.vals, n, k, sm.scratch);
+  *u2 = want2 ? radix_select(sm.vals, n, k + 1, sm.scratch) : *u1;
+}
+
 __device__ __forceinline__ void aggregate_box(const MatchParamsDev& P, const MatchWs& ws, int kg,
                                               ocsr_box_result* out, bool timed_out, AggLds& sm) {
   const int tid = threadIdx.x;
@@ -536,8 +626,15 @@ __device__ __forceinline__ void aggregate_box(const MatchParamsDev& P, const Mat
     return;
   }
   const int base = pl.frame * P.cap_blocks + pl.off;
-  if (tid == 0) { sm.scratch[258] = 0; sm.scratch[259] = 0; }
+  if (tid == 0) {
+    sm.n_valid = 0;
+    sm.n_eligible = 0;
+    sm.vmin = 0x7FFFFFFFu;
+    sm.vmax = 0;
+  }
+  for (int i = tid; i < 1024; i += 256) sm.hist[i] = 0;
   __syncthreads();
+  uint32_t vlo = 0x7FFFFFFFu, vhi = 0;   // bit patterns of non-negative floats
   // gather the valid values: one LDS atomic per wave, positions from the ballot. Flags
   // and values of up to kGather blocks per thread are loaded before any is used.
   constexpr int kGather = 4;
@@ -559,15 +656,25 @@ __device__ __forceinline__ void aggregate_box(const MatchParamsDev& P, const Mat
       const uint64_t me = __ballot((fl[u] & 1) != 0);
       int wbase = 0;
       if (lane == 0 && (mv | me)) {
-        wbase = atomicAdd(&sm.scratch[258], (int)__popcll(mv));
-        atomicAdd(&sm.scratch[259], (int)__popcll(me));
+        wbase = atomicAdd(&sm.n_valid, (int)__popcll(mv));
+        atomicAdd(&sm.n_eligible, (int)__popcll(me));
       }
       wbase = __shfl(wbase, 0, 64);
-      if (fl[u] & 2) sm.vals[wbase + __popcll(mv & below)] = v[u];
+      if (fl[u] & 2) {
+        sm.vals[wbase + __popcll(mv & below)] = v[u];
+        vlo = min(vlo, __float_as_uint(v[u]));
+        vhi = max(vhi, __float_as_uint(v[u]));
+      }
     }
   }
+  vlo = wave_min_u32(vlo);
+  vhi = (uint32_t)wave_max((int)vhi);
+  if (lane == 0) {
+    atomicMin(&sm.vmin, vlo);
+    atomicMax(&sm.vmax, vhi);
+  }
   __syncthreads();
-  const int nv = sm.scratch[258], ne = sm.scratch[259];
+  const int nv = sm.n_valid, ne = sm.n_eligible;
   r.n_blocks = pl.nblk;
   r.n_eligible = ne;
   r.n_valid = nv;
@@ -593,26 +700,10 @@ __device__ __forceinline__ void aggregate_box(const MatchParamsDev& P, const Mat
       ok = false;
     } else {
       const int k1 = t + (m - 1) / 2;
-      const uint32_t u1 = radix_select(sm.vals, nv, k1, sm.scratch);
-      if (m & 1) {
-        d_box = __uint_as_float(u1);
-      } else {
-        // the next order statistic: u1 again if it repeats, else the least value above u1
-        if (tid == 0) { sm.scratch[260] = 0; sm.scratch[261] = 0x7F800000; }
-        __syncthreads();
-        int le = 0;
-        uint32_t above = 0x7F800000u;
-        for (int i = tid; i < nv; i += 256) {
-          const uint32_t u = __float_as_uint(sm.vals[i]);
-          le += u <= u1;
-          if (u > u1) above = min(above, u);
-        }
-        atomicAdd(&sm.scratch[260], le);
-        atomicMin((uint32_t*)&sm.scratch[261], above);
-        __syncthreads();
-        const uint32_t u2 = sm.scratch[260] >= k1 + 2 ? u1 : (uint32_t)sm.scratch[261];
-        d_box = (__uint_as_float(u1) + __uint_as_float(u2)) * 0.5f;
-      }
+      uint32_t u1, u2;
+      select_middle(sm, nv, k1, (m & 1) == 0, __uint_as_float(sm.vmin), __uint_as_float(sm.vmax),
+                    &u1, &u2);
+      d_box = (m & 1) ? __uint_as_float(u1) : (__uint_as_float(u1) + __uint_as_float(u2)) * 0.5f;
     }
   } else {
     // bitonic sort of the valid values, padded with +inf to a power of two
@@ -650,10 +741,10 @@ __device__ __forceinline__ void aggregate_box(const MatchParamsDev& P, const Mat
       }
       const int len = nv - start;
       if (len > best_len) { best_len = len; best_start = start; }
-      if (tid == 0) { sm.scratch[262] = best_start; sm.scratch[263] = best_len; }
+      if (tid == 0) { sm.seg_start = best_start; sm.seg_len = best_len; }
     }
     __syncthreads();
-    const int seg_start = sm.scratch[262], seg_len = sm.scratch[263];
+    const int seg_start = sm.seg_start, seg_len = sm.seg_len;
     r.n_used = seg_len;
     if (seg_len < P.n_min) ok = false;
     else d_box = median_sorted(sm.vals + seg_start, seg_len);

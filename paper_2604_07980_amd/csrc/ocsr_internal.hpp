@@ -31,6 +31,10 @@ struct CensusJobsDev {
 // census tile: 64 columns x 32 rows of level pixels per workgroup of 256 threads
 constexpr int kCensusTileX = 64;
 constexpr int kCensusTileY = 32;
+// persistent census of whole-frame calls: tiles a call may have (bitmap words in LDS)
+// and tiles a workgroup lists at a time
+constexpr int kCensusListWords = 2048;
+constexpr int kCensusListCap = 256;
 
 hipError_t launch_census(const CensusJobsDev& jobs, int total_tiles, int sx, int sy,
                          int sentinel, hipStream_t stream);
@@ -161,10 +165,13 @@ int variant_candidates(const PathDev& ph, int* rows, int* cpl, int* passes, int 
 
 // Census of every view and level of every frame, and the plan of every frame, in one
 // launch (frames whose images are given).
+// Census (and plan) launch of a whole-frame call. With use_list set and the call's tiles
+// within the LDS bitmap, up to n_cu x (resident workgroups per CU) persistent workgroups
+// make the listed tiles; otherwise one workgroup per tile tests and makes its own.
 hipError_t launch_frame_census(const MatchParamsDev& p, const FramesDev& fr,
                                const ocsr_box* boxes, const MatchWs& ws, int sx, int sy,
-                               int sentinel, int n_census_tiles, hipStream_t stream,
-                               const LaunchTimer* timer);
+                               int sentinel, int n_census_tiles, int n_cu, bool use_list,
+                               hipStream_t stream, const LaunchTimer* timer);
 
 // Multi-launch matching: the plan (unless plan_done), one launch per level that matches
 // the level's blocks, then one aggregation workgroup per box.

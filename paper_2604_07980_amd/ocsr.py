@@ -31,7 +31,7 @@ MAX_CENSUS_JOBS = 64
 DEFAULT_CAP_BLOCKS = 1 << 20
 
 OPTION_FUSED, OPTION_WAVES_PER_CU, OPTION_GRAPH, OPTION_MATCH_WGS_PER_CU, OPTION_BLOCKS_PER_WAVE = 1, 2, 3, 4, 5
-OPTION_FULL_CENSUS = 6
+OPTION_FULL_CENSUS, OPTION_CENSUS_TILE_LIST = 6, 7
 
 EXPORTS = ["ocsr_abi_version", "ocsr_last_error", "ocsr_ctx_create", "ocsr_ctx_destroy",
            "ocsr_census", "ocsr_census_many", "ocsr_match_workspace_bytes", "ocsr_match_boxes",

@@ -78,7 +78,7 @@ def _edge_boxes(H, W, tau):
     ], np.int32)
 
 
-def _frame(lib, orc, left, right, boxes, p, full=False):
+def _frame(lib, orc, left, right, boxes, p, full=False, listed=True):
     H, W = left.shape
     ws = lib.Workspace()
     # a one-frame batch workspace has the whole-frame layout and size
@@ -86,11 +86,13 @@ def _frame(lib, orc, left, right, boxes, p, full=False):
     buf = ws.get(nbytes, torch.device("cuda:0"))
     buf.fill_(PATTERN)
     lib.set_option(lib.OPTION_FULL_CENSUS, 1 if full else 0)
+    lib.set_option(lib.OPTION_CENSUS_TILE_LIST, 1 if listed else 0)
     try:
         got = lib.results_to_numpy(lib.range_frame(_cuda(left), _cuda(right), _cuda(boxes), p,
                                                    workspace=ws))
     finally:
         lib.set_option(lib.OPTION_FULL_CENSUS, 0)
+        lib.set_option(lib.OPTION_CENSUS_TILE_LIST, 1)
     torch.cuda.synchronize()
     want = orc.run_scene(left, right, p, boxes)[1][0]
     assert_results_match(got, want)
@@ -101,21 +103,23 @@ def _frame(lib, orc, left, right, boxes, p, full=False):
     return made
 
 
+@pytest.mark.parametrize("listed", [True, False], ids=["listed", "per_tile"])
 @pytest.mark.parametrize("variant", ["tiled_trim", "tiled_seg_lr0", "win5x5"])
 @pytest.mark.parametrize("seed", [1, 2])
-def test_frame_makes_the_tiles_boxes_read(lib, orc, variant, seed):
+def test_frame_makes_the_tiles_boxes_read(lib, orc, variant, seed, listed):
     p = _params(variant)
     sc = synth.scene_small(500 + 10 * seed + len(variant), H=200, W=360, n_planes=6)
-    made = _frame(lib, orc, sc.left, sc.right, sc.boxes, p)
+    made = _frame(lib, orc, sc.left, sc.right, sc.boxes, p, listed=listed)
     assert made, "the scene's boxes read some tile"
 
 
+@pytest.mark.parametrize("listed", [True, False], ids=["listed", "per_tile"])
 @pytest.mark.parametrize("variant", ["tiled_trim", "wide_range"])
-def test_frame_tiles_at_image_edges(lib, orc, variant):
+def test_frame_tiles_at_image_edges(lib, orc, variant, listed):
     p = _params(variant)
     sc = synth.scene_small(811, H=160, W=300, n_planes=3)
     boxes = _edge_boxes(160, 300, p["tau_s"])
-    _frame(lib, orc, sc.left, sc.right, boxes, p)
+    _frame(lib, orc, sc.left, sc.right, boxes, p, listed=listed)
 
 
 def test_frame_without_ranged_boxes_makes_no_tile(lib, orc):
@@ -126,17 +130,20 @@ def test_frame_without_ranged_boxes_makes_no_tile(lib, orc):
     assert _frame(lib, orc, sc.left, sc.right, boxes, p) == set()
 
 
-def test_full_census_option_makes_every_tile(lib, orc):
+@pytest.mark.parametrize("listed", [True, False], ids=["listed", "per_tile"])
+def test_full_census_option_makes_every_tile(lib, orc, listed):
     p = _params("tiled_trim")
     sc = synth.scene_small(813, H=150, W=260, n_planes=4)
-    _frame(lib, orc, sc.left, sc.right, sc.boxes, p, full=True)
+    _frame(lib, orc, sc.left, sc.right, sc.boxes, p, full=True, listed=listed)
 
 
-def test_realistic_frame_tiles(lib, orc):
-    """The 1920x1080 frame the benchmark times: about a fifth of the tiles are made."""
+@pytest.mark.parametrize("listed", [True, False], ids=["listed", "per_tile"])
+def test_realistic_frame_tiles(lib, orc, listed):
+    """The 1920x1080 frame the benchmark times: about a fifth of the tiles are made (2550
+    tiles, more than the persistent grid, so the listed form shares them out)."""
     p = synth.params_for(2)
     sc = synth.scene_realistic()
-    made = _frame(lib, orc, sc.left, sc.right, sc.boxes, p)
+    made = _frame(lib, orc, sc.left, sc.right, sc.boxes, p, listed=listed)
     H, W = sc.left.shape
     n_all = len(accounting.census_tiles(W, H, sc.boxes, p, full=True))
     assert 0 < len(made) < n_all
