@@ -357,7 +357,7 @@ int32_t ocsr_ctx_set_option(ocsr_ctx* ctx, int32_t option, int32_t value);
  * level candidates. Fewer candidates per lane need fewer registers, so more waves fit
  * on a compute unit, at the price of more passes. Any variant that covers a path gives
  * identical results; they differ in speed only. By default the first covering variant
- * in the library's order is used (the fewest candidates per lane in one pass).
+ * in the library's order of preference is used.
  *
  * ocsr_variant_candidates: writes up to `cap` (rows, cpl, passes) triples (host arrays)
  * that cover bw x bh blocks and n_candidates level candidates; returns how many exist

@@ -67,18 +67,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(tiled_waves
 
 // Waves per SIMD the paired kernel is compiled for: three where both variants fit in a
 // third of the register file without spilling (checked in the built code), else two.
-template <int FR_, int FC, int CC>
+template <int FR_, int FC, int CC, int CP>
 constexpr int pair_waves() {
-  return ((FR_ == 4 && FC <= 2 && CC <= 12) || (FC <= 8 && CC <= 8)) ? 3 : 2;
+  return CP > 1 ? (CC <= 6 ? 4 : 3)
+                : ((FR_ == 4 && FC <= 2 && CC <= 12) || (FC <= 8 && CC <= 8)) ? 3 : 2;
 }
 
 // Both levels in one launch: work items of every frame's close level first, then of
 // every far level (FV / CV: the far and close kernel variants).
-template <int FR_, int FX, int FC, int CR_, int CX, int CC>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(pair_waves<FR_, FC, CC>()))) void match_pair_kernel(MatchParamsDev P, FramesDev FR,
+template <int FR_, int FX, int FC, int CR_, int CX, int CC, int CP>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(pair_waves<FR_, FC, CC, CP>()))) void match_pair_kernel(MatchParamsDev P, FramesDev FR,
                                                          MatchWs ws, DebugDev dbg) {
   constexpr size_t kF = (dev::Tiled<FR_, FX, FC>::kLdsBytes + 15) & ~(size_t)15;
-  constexpr size_t kC = (dev::Tiled<CR_, CX, CC>::kLdsBytes + 15) & ~(size_t)15;
+  constexpr size_t kC = (dev::Tiled<CR_, CX, CC, CP>::kLdsBytes + 15) & ~(size_t)15;
   constexpr size_t kWave = kF > kC ? kF : kC;
   __shared__ uint64_t lds[(kItemWaves * kWave + 7) / 8];
   __shared__ int prefix[2 * kMaxFrames + 1];
@@ -106,7 +107,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(pair_waves<
     const int q = m - prefix[slot];
     if (slot < F) {
       dev::run_item(P, fr, f, FR.n_boxes_total, ws, 1, q, wave, lane, [&](const dev::BlockCtx& c) {
-        dev::match_block_tiled<CR_, CX, CC>(P, fr, ws, dbg, c, lane, wl);
+        dev::match_block_tiled<CR_, CX, CC, CP>(P, fr, ws, dbg, c, lane, wl);
       });
     } else {
       dev::run_item(P, fr, f, FR.n_boxes_total, ws, 0, q, wave, lane, [&](const dev::BlockCtx& c) {
@@ -155,8 +156,8 @@ namespace {
 struct BuiltVariant { int rows, nx, cpl, passes; };
 constexpr BuiltVariant kBuilt[] = {
     {4, 4, 2, 1},  {4, 4, 4, 1},  {4, 4, 8, 1},  {4, 4, 16, 1}, {8, 8, 4, 1},  {8, 8, 8, 1},
-    {8, 8, 12, 1}, {8, 8, 16, 1}, {8, 8, 24, 1}, {8, 8, 32, 1}, {8, 8, 4, 2},  {8, 8, 4, 3},
-    {8, 8, 4, 4},  {8, 8, 6, 2},  {8, 8, 8, 2},  {4, 4, 2, 2},  {4, 4, 4, 2}};
+    {8, 8, 6, 2},  {8, 8, 12, 1}, {8, 8, 16, 1}, {8, 8, 24, 1}, {8, 8, 32, 1}, {8, 8, 4, 2},
+    {8, 8, 4, 3},  {8, 8, 4, 4},  {8, 8, 8, 2},  {4, 4, 2, 2},  {4, 4, 4, 2}};
 }  // namespace
 
 bool variant_valid(const PathDev& ph, int rows, int cpl, int passes) {
@@ -222,21 +223,24 @@ static bool launch_pair(const MatchParamsDev& P, const FramesDev& FR, const Matc
                         const DebugDev& dbg, int grid, hipStream_t stream, bool launch) {
   const PathDev& f = P.path[0];
   const PathDev& c = P.path[1];
-  if (f.passes != 1 || c.passes != 1) return false;
-#define OCSR_PAIR(FRW, FXW, FCP, CRW, CXW, CCP)                                          \
-  if (f.rows == FRW && f.cpl == FCP && c.rows == CRW && c.cpl == CCP) {                 \
+  if (f.passes != 1) return false;
+#define OCSR_PAIR(FRW, FXW, FCP, CRW, CXW, CCP, CPS)                                     \
+  if (f.rows == FRW && f.cpl == FCP && c.rows == CRW && c.cpl == CCP && c.passes == CPS) { \
     if (launch)                                                                          \
-      match_pair_kernel<FRW, FXW, FCP, CRW, CXW, CCP><<<grid, 256, 0, stream>>>(P, FR, ws, dbg); \
+      match_pair_kernel<FRW, FXW, FCP, CRW, CXW, CCP, CPS><<<grid, 256, 0, stream>>>(P, FR, ws, dbg); \
     return true;                                                                         \
   }
-  OCSR_PAIR(4, 4, 2, 8, 8, 8)
-  OCSR_PAIR(4, 4, 2, 8, 8, 12)
-  OCSR_PAIR(4, 4, 2, 8, 8, 16)
-  OCSR_PAIR(4, 4, 4, 8, 8, 8)
-  OCSR_PAIR(4, 4, 4, 8, 8, 12)
-  OCSR_PAIR(8, 8, 8, 8, 8, 8)
-  OCSR_PAIR(8, 8, 8, 8, 8, 12)
-  OCSR_PAIR(8, 8, 8, 8, 8, 16)
+  OCSR_PAIR(4, 4, 2, 8, 8, 8, 1)
+  OCSR_PAIR(4, 4, 2, 8, 8, 12, 1)
+  OCSR_PAIR(4, 4, 2, 8, 8, 16, 1)
+  OCSR_PAIR(4, 4, 4, 8, 8, 8, 1)
+  OCSR_PAIR(4, 4, 4, 8, 8, 12, 1)
+  OCSR_PAIR(8, 8, 8, 8, 8, 8, 1)
+  OCSR_PAIR(8, 8, 8, 8, 8, 12, 1)
+  OCSR_PAIR(8, 8, 8, 8, 8, 16, 1)
+  OCSR_PAIR(4, 4, 2, 8, 8, 4, 3)
+  OCSR_PAIR(4, 4, 2, 8, 8, 6, 2)
+  OCSR_PAIR(4, 4, 2, 8, 8, 4, 2)
 #undef OCSR_PAIR
   return false;
 }

@@ -26,6 +26,17 @@ def test_graph_frame_replays(lib, orc, fused):
     boxes = torch.zeros((nb, 5), dtype=torch.int32, device="cuda:0")
     ws = lib.Workspace()
     out = torch.empty((nb, 8), dtype=torch.int32, device="cuda:0")
+    # the persistent kernel is built for single-pass close variants: pick one for the
+    # 8x8 / 96-candidate close path, so that the fused option does run it
+    if fused:
+        lib.set_variant(8, 8, 96, 8, 12, 1)
+    try:
+        _replays(lib, orc, fused, p, scenes, nb, L, R, boxes, ws, out)
+    finally:
+        lib.set_variant(8, 8, 96, 0, 0, 0)
+
+
+def _replays(lib, orc, fused, p, scenes, nb, L, R, boxes, ws, out):
     with lib_options(lib, fused=fused, graph=True):
         hits0, builds0 = lib.graph_stats()
         for rep in range(6):
