@@ -340,11 +340,12 @@ int32_t ocsr_dense_match(ocsr_ctx* ctx, const ocsr_level* lv, int32_t dmin, int3
  * option only decides which workspace descriptors are defined after the call (see
  * ocsr_range_frame). */
 #define OCSR_OPTION_FULL_CENSUS 6
-/* OCSR_OPTION_CENSUS_TILE_LIST: 1 (default) makes the census of whole-frame and batch
- * calls with persistent workgroups, one per resident slot of the GPU, that each list the
- * tiles to make from the boxes and take an equal share of them (calls of up to 65536
- * tiles of 64 x 32 level pixels); 0 launches one workgroup per tile, which makes its
- * tile or leaves. Results and the tiles made are the same either way. */
+/* OCSR_OPTION_CENSUS_TILE_LIST: 1 (default) lets whole-frame and batch calls with at
+ * least 8 tiles of 64 x 32 level pixels per resident workgroup slot of the GPU (and at
+ * most 65536 tiles) make the census with persistent workgroups, one per slot, that each
+ * list the tiles to make from the boxes and take an equal share of them; other calls,
+ * and every call with 0, launch one workgroup per tile, which makes its tile or leaves.
+ * Results and the tiles made are the same either way. */
 #define OCSR_OPTION_CENSUS_TILE_LIST 7
 int32_t ocsr_ctx_set_option(ocsr_ctx* ctx, int32_t option, int32_t value);
 

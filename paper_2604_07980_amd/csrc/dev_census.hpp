@@ -276,10 +276,14 @@ __device__ __forceinline__ void mark_census_tiles(const MatchParamsDev& MP, cons
     }
     return;
   }
-  for (int f = 0; f < FR.n; ++f) {
+  // threads over the boxes of every frame at once (frames hold consecutive box ranges)
+  for (int g = tid; g < FR.n_boxes_total; g += 256) {
+    int f = 0;
+    for (int k = 1; k < FR.n; ++k)
+      if (g >= FR.f[k].box_off) f = k;
     const FrameDev& fr = FR.f[f];
-    for (int i = tid; i < fr.n_boxes; i += 256) {
-      const ocsr_box b = boxes[fr.box_off + i];
+    {
+      const ocsr_box b = boxes[g];
       const int cx0 = max(b.x0, 0), cy0 = max(b.y0, 0);
       const int cx1 = min(b.x1, fr.W), cy1 = min(b.y1, fr.H);
       if (!(b.flags & OCSR_BOX_RANGE) || !(cx0 < cx1 && cy0 < cy1)) continue;

@@ -103,7 +103,7 @@ def _frame(lib, orc, left, right, boxes, p, full=False, listed=True):
     return made
 
 
-@pytest.mark.parametrize("listed", [True, False], ids=["listed", "per_tile"])
+@pytest.mark.parametrize("listed", [True, False], ids=["list_allowed", "per_tile"])
 @pytest.mark.parametrize("variant", ["tiled_trim", "tiled_seg_lr0", "win5x5"])
 @pytest.mark.parametrize("seed", [1, 2])
 def test_frame_makes_the_tiles_boxes_read(lib, orc, variant, seed, listed):
@@ -149,10 +149,26 @@ def test_realistic_frame_tiles(lib, orc, listed):
     assert 0 < len(made) < n_all
 
 
-def test_batch_makes_each_frames_tiles(lib, orc):
+@pytest.mark.parametrize("large", [False, True], ids=["small_per_tile", "large_listed"])
+@pytest.mark.parametrize("listed", [True, False], ids=["list_allowed", "per_tile"])
+def test_batch_makes_each_frames_tiles(lib, orc, large, listed):
+    """Small frames take the per-tile launch; four 1920x1200 frames (11400 tiles, at
+    least 8 per resident workgroup) the persistent workgroups over tile lists, unless
+    lists are switched off."""
     p = synth.params_for(3)
-    scenes = [synth.scene_small(900 + k, H=h, W=w, n_planes=5)
-              for k, (h, w) in enumerate([(160, 256), (120, 200), (200, 330)])]
+    if large:
+        scenes = [synth.scene_batch_frame(f) for f in range(4)]
+    else:
+        scenes = [synth.scene_small(900 + k, H=h, W=w, n_planes=5)
+                  for k, (h, w) in enumerate([(160, 256), (120, 200), (200, 330)])]
+    lib.set_option(lib.OPTION_CENSUS_TILE_LIST, 1 if listed else 0)
+    try:
+        _batch_tiles(lib, orc, p, scenes)
+    finally:
+        lib.set_option(lib.OPTION_CENSUS_TILE_LIST, 1)
+
+
+def _batch_tiles(lib, orc, p, scenes):
     frames = [(_cuda(s.left), _cuda(s.right), s.boxes.shape[0]) for s in scenes]
     boxes = _cuda(np.concatenate([s.boxes for s in scenes]))
     ws = lib.Workspace()
