@@ -227,7 +227,7 @@ __device__ __forceinline__ bool census_tile_needed(const MatchParamsDev& MP, con
 }
 
 // Census tile c of a whole-frame call: the tiles of frame f start at
-// FR.f[f].tile_begin and run over view L then R at level 0, then L and R at level 1.
+// FR.f[f].tile_begin and run over view L then R at level 1, then L and R at level 0.
 // With `check` set and MP.full_census clear, a tile no box's search reads is skipped
 // (every wave of the workgroup takes the same decision). Window (SX, SY) > (-1, -1)
 // takes the LDS code; (-1, -1) the generic code with (sx, sy).
@@ -240,12 +240,14 @@ __device__ __forceinline__ void frame_census_tile(const MatchParamsDev& MP, cons
   for (int k = 1; k < FR.n; ++k)
     if (c >= FR.f[k].tile_begin) f = k;
   const FrameDev& fr = FR.f[f];
-  int t = c - fr.tile_begin, level = 0, tiles = fr.tiles0, tiles_x = fr.tiles0_x;
-  if (t >= 2 * fr.tiles0) {
-    t -= 2 * fr.tiles0;
-    level = 1;
-    tiles = fr.tiles1;
-    tiles_x = fr.tiles1_x;
+  // level 1 first: its tiles are few and mostly read by the close boxes, so they are
+  // dispatched ahead of the many, mostly skipped, tiles of level 0
+  int t = c - fr.tile_begin, level = 1, tiles = fr.tiles1, tiles_x = fr.tiles1_x;
+  if (t >= 2 * fr.tiles1) {
+    t -= 2 * fr.tiles1;
+    level = 0;
+    tiles = fr.tiles0;
+    tiles_x = fr.tiles0_x;
   }
   const int view = t / tiles;
   t -= view * tiles;
@@ -296,7 +298,7 @@ __device__ __forceinline__ void mark_census_tiles(const MatchParamsDev& MP, cons
       const int dlo = MP.path[level].dlo, dhi = dlo + MP.path[level].nd - 1;
       const int tiles_x = level ? fr.tiles1_x : fr.tiles0_x;
       const int tiles = level ? fr.tiles1 : fr.tiles0;
-      const int lbase = fr.tile_begin + (level ? 2 * fr.tiles0 : 0);
+      const int lbase = fr.tile_begin + (level ? 0 : 2 * fr.tiles1);
       for (int view = 0; view < 2; ++view) {
         const int a = max(x0 - (view ? dhi : dhi - dlo), 0);
         const int e = min(x1 + (view ? -dlo : dhi - dlo), tiles_x * kCensusTileX);
