@@ -317,20 +317,44 @@ __device__ __forceinline__ uint32_t row_sum(uint32_t v) {
 template <int ROWS, int SW>
 __device__ __forceinline__ void stage_strip(uint64_t* __restrict__ S, const uint64_t* __restrict__ rows,
                                             int pitch, int x_first, int ny, int sw, int W, int lane) {
-  constexpr int N = ROWS * SW, IT = (N + 63) / 64;
-  uint64_t w[IT];
+  if constexpr ((SW & (SW - 1)) == 0) {
+    // power-of-two rows: word idx = lane + 64 k of the ROWS x SW strip, row and column
+    // by shift and mask
+    constexpr int N = ROWS * SW, IT = (N + 63) / 64;
+    uint64_t w[IT];
 #pragma unroll
-  for (int k = 0; k < IT; ++k) {
-    const int idx = lane + 64 * k;
-    const int jj = idx / SW, m = idx - jj * SW, x = x_first + m;
-    const bool ok = idx < N && jj < ny && m < sw && x >= 0 && x < W;
-    w[k] = rows[ok ? (size_t)jj * pitch + x : 0];
-    w[k] = ok ? w[k] : 0ull;
-  }
+    for (int k = 0; k < IT; ++k) {
+      const int idx = lane + 64 * k;
+      const int jj = idx / SW, m = idx % SW, x = x_first + m;
+      const bool ok = idx < N && jj < ny && m < sw && x >= 0 && x < W;
+      w[k] = rows[ok ? (size_t)jj * pitch + x : 0];
+      w[k] = ok ? w[k] : 0ull;
+    }
 #pragma unroll
-  for (int k = 0; k < IT; ++k) {
-    const int idx = lane + 64 * k;
-    if (idx < N) S[idx] = w[k];
+    for (int k = 0; k < IT; ++k) {
+      const int idx = lane + 64 * k;
+      if (idx < N) S[idx] = w[k];
+    }
+  } else {
+    // row by row in chunks of 64 words: the row is a constant and the column the lane,
+    // so no per-lane division (whose results the compiler would keep live in registers
+    // across the whole work-item loop)
+    constexpr int CH = (SW + 63) / 64;
+    uint64_t w[ROWS][CH];
+#pragma unroll
+    for (int jj = 0; jj < ROWS; ++jj)
+#pragma unroll
+      for (int c = 0; c < CH; ++c) {
+        const int m = 64 * c + lane, x = x_first + m;
+        const bool ok = jj < ny && m < sw && x >= 0 && x < W;
+        w[jj][c] = rows[ok ? (size_t)jj * pitch + x : 0];
+        w[jj][c] = ok ? w[jj][c] : 0ull;
+      }
+#pragma unroll
+    for (int jj = 0; jj < ROWS; ++jj)
+#pragma unroll
+      for (int c = 0; c < CH; ++c)
+        if (64 * c + lane < SW) S[jj * SW + 64 * c + lane] = w[jj][c];
   }
 }
 

@@ -43,13 +43,16 @@ __global__ __launch_bounds__(256) void frame_census_kernel(MatchParamsDev P, Fra
 
 // Waves per SIMD a single-level kernel is compiled for (as many as its registers allow
 // without spilling, checked in the built code).
-template <int ROWS, int CPL>
+template <int ROWS, int CPL, int PASSES>
 constexpr int tiled_waves() {
-  return ROWS == 4 ? (CPL <= 4 ? 6 : CPL <= 8 ? 4 : 2) : (CPL <= 4 ? 5 : CPL <= 12 ? 3 : CPL <= 16 ? 2 : 1);
+  return ROWS == 4 ? ((CPL <= 2 || (CPL <= 4 && PASSES == 1)) ? 6 : CPL <= 8 ? 4 : 2)
+                   : (CPL <= 4 && PASSES == 1) ? 5
+                   : ((CPL <= 4 && PASSES <= 3) || (CPL <= 6 && PASSES <= 2)) ? 4
+                   : CPL <= 12 ? 3 : CPL <= 16 ? 2 : 1;
 }
 
 template <int ROWS, int NX, int CPL, int PASSES>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(tiled_waves<ROWS, CPL>()))) void match_tiled_kernel(MatchParamsDev P, FramesDev FR,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(tiled_waves<ROWS, CPL, PASSES>()))) void match_tiled_kernel(MatchParamsDev P, FramesDev FR,
                                                           MatchWs ws, DebugDev dbg, int level) {
   constexpr size_t kWave = (dev::Tiled<ROWS, NX, CPL, PASSES>::kLdsBytes + 15) & ~(size_t)15;
   __shared__ uint64_t lds[(kItemWaves * kWave + 7) / 8];
@@ -70,7 +73,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(tiled_waves
 template <int FR_, int FC, int CC, int CP>
 constexpr int pair_waves() {
   return CP > 1 ? (CC <= 6 ? 4 : 3)
-                : ((FR_ == 4 && FC <= 2 && CC <= 12) || (FC <= 8 && CC <= 8)) ? 3 : 2;
+         : ((FR_ == 4 && FC <= 2 && CC <= 12) || (FC <= 8 && CC <= 8)) ? 3 : 2;
 }
 
 // Both levels in one launch: work items of every frame's close level first, then of
