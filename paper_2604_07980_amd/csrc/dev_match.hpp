@@ -118,6 +118,28 @@ __device__ __forceinline__ void plan_frame(const MatchParamsDev& P, const FrameD
     fc[FC_FAR_ITEMS] = carry0;
     fc[FC_CLOSE_ITEMS] = carry1;
   }
+  // item records: the frame's close items from 0, its far items after them; each lane
+  // writes those of its box (re-reading the plan it stored above)
+  ItemRec* rec = ws.items + (size_t)f * ws.items_cap;
+  for (int base = 0; base < n; base += 64) {
+    const int i = base + lane;
+    if (i >= n) continue;
+    const BoxPlan pl = ws.plan[fr.box_off + i];
+    if (pl.status != -1 || pl.nblk <= 0) continue;
+    const int nitem = (pl.nblk + P.item_blocks - 1) / P.item_blocks;
+    const int at = (pl.level == 1 ? 0 : carry1) + pl.ioff;
+    for (int t = 0; t < nitem; ++t) {
+      ItemRec r;
+      r.k = i;
+      r.first = t * P.item_blocks;
+      r.nblk = pl.nblk;
+      r.off = pl.off;
+      r.nbx = pl.nbx; r.bw = pl.bw; r.bh = pl.bh; r.ox = pl.ox; r.oy = pl.oy;
+      r.lx0 = pl.lx0; r.ly0 = pl.ly0; r.lw = pl.lw; r.lh = pl.lh;
+      r.pad[0] = r.pad[1] = r.pad[2] = 0;
+      rec[at + t] = r;
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------------
@@ -475,6 +497,23 @@ __device__ __forceinline__ void match_block_tiled(const MatchParamsDev& P, const
   }
   write_block(ws, dbg, c, ph, mask, true, d_f, d_b, lr_ok, d_sub, lr_ok, lane);
   wave_sync();
+}
+
+// Work item of frame f at `level` from its record: wave w of the workgroup runs blocks
+// r.first + w + 4 j of the box that exist.
+template <class RunBlock>
+__device__ __forceinline__ void run_item_rec(const MatchParamsDev& P, const FrameDev& fr, int f,
+                                             int level, const ItemRec& r, int wave, RunBlock run) {
+  BoxPlan pl = {};
+  pl.status = -1;
+  pl.level = level;
+  pl.lx0 = r.lx0; pl.ly0 = r.ly0; pl.lw = r.lw; pl.lh = r.lh;
+  pl.nbx = r.nbx; pl.bw = r.bw; pl.bh = r.bh; pl.ox = r.ox; pl.oy = r.oy;
+  pl.off = r.off; pl.nblk = r.nblk; pl.frame = f;
+  for (int j = wave; j < P.item_blocks; j += kItemWaves) {
+    const int local = r.first + j;
+    if (local < r.nblk) run(block_ctx(P, fr, f, r.k, pl, local, level));
+  }
 }
 
 // Grid-stride loop of a workgroup over the work items of one level of every frame:

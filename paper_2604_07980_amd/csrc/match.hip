@@ -61,8 +61,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(tiled_waves
   void* wl = (char*)lds + wave * kWave;
   dev::level_items(FR, ws, level, [&](int f, int q) {
     const FrameDev& fr = FR.f[f];
-    dev::run_item(P, fr, f, FR.n_boxes_total, ws, level, q, wave, lane,
-                  [&](const dev::BlockCtx& c) {
+    // the frame's far items follow its close items in the records
+    const int at = q + (level ? 0 : ws.fcount[f * FC_N + FC_CLOSE_ITEMS]);
+    const ItemRec r = ws.items[(size_t)f * ws.items_cap + at];
+    dev::run_item_rec(P, fr, f, level, r, wave, [&](const dev::BlockCtx& c) {
       dev::match_block_tiled<ROWS, NX, CPL, PASSES>(P, fr, ws, dbg, c, lane, wl);
     });
   });
@@ -108,12 +110,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(pair_waves<
     const int f = slot < F ? slot : slot - F;
     const FrameDev& fr = FR.f[f];
     const int q = m - prefix[slot];
+    // the frame's far items follow its close items (slot f) in the records
+    const int at = q + (slot < F ? 0 : prefix[f + 1] - prefix[f]);
+    const ItemRec r = ws.items[(size_t)f * ws.items_cap + at];
     if (slot < F) {
-      dev::run_item(P, fr, f, FR.n_boxes_total, ws, 1, q, wave, lane, [&](const dev::BlockCtx& c) {
+      dev::run_item_rec(P, fr, f, 1, r, wave, [&](const dev::BlockCtx& c) {
         dev::match_block_tiled<CR_, CX, CC, CP>(P, fr, ws, dbg, c, lane, wl);
       });
     } else {
-      dev::run_item(P, fr, f, FR.n_boxes_total, ws, 0, q, wave, lane, [&](const dev::BlockCtx& c) {
+      dev::run_item_rec(P, fr, f, 0, r, wave, [&](const dev::BlockCtx& c) {
         dev::match_block_tiled<FR_, FX, FC>(P, fr, ws, dbg, c, lane, wl);
       });
     }
@@ -136,7 +141,8 @@ size_t match_ws_bytes(int n_frames, int n_boxes_total, int cap_blocks) {
   return align256(n * sizeof(BoxPlan)) + align256(n * sizeof(BoxClip)) +
          align256(2 * n * sizeof(int32_t)) +
          align256((size_t)kMaxFrames * FC_N * sizeof(int32_t)) + align256(GC_N * sizeof(int32_t)) +
-         align256(c * sizeof(float)) + align256(c * sizeof(uint8_t));
+         align256(c * sizeof(float)) + align256(c * sizeof(uint8_t)) +
+         (size_t)(n_frames > 0 ? n_frames : 1) * items_capacity(n_boxes_total, cap_blocks) * sizeof(ItemRec);
 }
 
 MatchWs match_ws_carve(void* base, int n_frames, int n_boxes_total, int cap_blocks) {
@@ -150,7 +156,9 @@ MatchWs match_ws_carve(void* base, int n_frames, int n_boxes_total, int cap_bloc
   ws.fcount = (int32_t*)b;      b += align256((size_t)kMaxFrames * FC_N * sizeof(int32_t));
   ws.gcount = (int32_t*)b;      b += align256(GC_N * sizeof(int32_t));
   ws.blk_val = (float*)b;       b += align256(c * sizeof(float));
-  ws.blk_flag = (uint8_t*)b;
+  ws.blk_flag = (uint8_t*)b;    b += align256(c * sizeof(uint8_t));
+  ws.items = (ItemRec*)b;
+  ws.items_cap = items_capacity(n_boxes_total, cap_blocks);
   return ws;
 }
 

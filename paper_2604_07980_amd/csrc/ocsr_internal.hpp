@@ -119,6 +119,19 @@ enum { FC_NUMBERED = 0, FC_MATCHED = 1, FC_FAR_ITEMS = 2, FC_CLOSE_ITEMS = 3, FC
 constexpr int kBarSlots = 8;
 enum { GC_TIMEOUT = 0, GC_BAR0 = 8, GC_BAR1 = 16, GC_N = 24 };
 
+// A work item as the plan writes it: the box, the item's first block and the box's
+// block geometry, so that a matching workgroup reads one record (one cache line) and
+// can stage its blocks' strips at once.
+struct ItemRec {
+  int32_t k;                       // box within the frame
+  int32_t first;                   // the item's first block (0-based within the box)
+  int32_t nblk, off;               // the box's blocks and its first block number
+  int32_t nbx, bw, bh, ox, oy;     // block grid
+  int32_t lx0, ly0, lw, lh;        // level box
+  int32_t pad[3];
+};
+static_assert(sizeof(ItemRec) == 64, "one cache line per record");
+
 struct MatchWs {
   BoxPlan* plan;       // [n_boxes_total]
   BoxClip* clip;       // [n_boxes_total]
@@ -127,7 +140,15 @@ struct MatchWs {
   int32_t* gcount;     // [GC_N]
   float* blk_val;      // [n_frames][cap_blocks] full-res disparity of a valid block
   uint8_t* blk_flag;   // [n_frames][cap_blocks] bit 0 eligible, bit 1 valid
+  ItemRec* items;      // [n_frames][items_cap]: a frame's close items, then its far items
+  int32_t items_cap;   // records per frame
 };
+
+// Work items of a frame of at most cap_blocks blocks: items hold at least kItemWaves
+// blocks of one box, so there are at most cap_blocks / kItemWaves + one per box.
+inline int32_t items_capacity(int n_boxes_total, int cap_blocks) {
+  return (cap_blocks > 0 ? cap_blocks : 1) / kItemWaves + (n_boxes_total > 0 ? n_boxes_total : 1);
+}
 
 size_t match_ws_bytes(int n_frames, int n_boxes_total, int cap_blocks);
 MatchWs match_ws_carve(void* base, int n_frames, int n_boxes_total, int cap_blocks);
