@@ -397,6 +397,20 @@ def main():
     ocsr.set_graph(False)
     glat = np.array(glat)
 
+    # per-box 3D point and covariance from the frame's results (a step after the timed
+    # path): kernel time from HIP events, outside the timed steps
+    geom = synth.point_geometry(W, H, p)
+    pts = ocsr.box_points(boxes, out, geom)
+    ocsr.reset_timing()
+    ocsr.set_timing(True)
+    for _ in range(args.steps):
+        ocsr.box_points(boxes, out, geom, out=pts)
+    torch.cuda.synchronize()
+    ocsr.set_timing(False)
+    pcnt, ptot = ocsr.kernel_time("points")
+    points = {"boxes": int(n), "valid": int(ocsr.points_to_numpy(pts)["valid"].sum()),
+              "us_per_call": round(1e3 * ptot / max(pcnt, 1), 3)}
+
     # algorithmic work per launch: census = informative comparisons (the centre term
     # is constant); match = 4 int32 ops per 64-bit Hamming cost
     census_ops = census_px * (census_bits - 1) * CENSUS_OPS_PER_CMP
@@ -447,6 +461,7 @@ def main():
         "kernels": {k: {kk: (round(vv, 3) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                     for k, v in kern.items()},
         "roofline": roofline,
+        "points": points,
     }
     if args.batch_steps > 0:
         res["batch"] = batch_section(ocsr, synth, args.batch_steps, max(3, args.warmup // 10))

@@ -224,6 +224,43 @@ int32_t ocsr_match_boxes(ocsr_ctx* ctx, const ocsr_level* lv0, const ocsr_level*
                          const ocsr_debug* dbg, void* stream);
 
 /* ------------------------------------------------------------------------------ */
+/* Per-box 3D point and covariance (Sec. 4.3.6 Q-matrix equation; Sec. 4.3.7 depth  */
+/* variance and covariance rotation equations)                                      */
+/* ------------------------------------------------------------------------------ */
+/* Camera geometry of the point step. The box's image point (u, v) is the centre of
+ * its box clipped to the width x height image, in pixel-index coordinates:
+ * u = (cx0 + cx1 - 1) / 2, v = (cy0 + cy1 - 1) / 2. */
+typedef struct {
+  int32_t width, height;   /* full-resolution image size */
+  double Q[16];            /* 4x4 reprojection matrix of the rectified pair, row-major */
+  double R[9];             /* rotation of T_cam->imu, row-major */
+  double t[3];             /* translation of T_cam->imu */
+  double focal_px;         /* f of the depth variance */
+  double baseline_m;       /* b of the depth variance */
+  double var_d;            /* sigma_d^2: the configured disparity variance, px^2 */
+  double var_x, var_y;     /* sigma_x^2, sigma_y^2: lateral variances in the camera frame */
+} ocsr_point_params;
+
+typedef struct {
+  float p_cam[3];          /* (X, Y, Z) / W with (X, Y, Z, W) = Q (u, v, d, 1) */
+  float p_imu[3];          /* R p_cam + t */
+  float cov_imu[6];        /* R diag(var_x, var_y, var_z) R^T: xx, xy, xz, yy, yz, zz */
+  float var_z;             /* Z^4 var_d / (f^2 b^2), Z = p_cam[2] */
+  int32_t valid;           /* 1 iff the box result is valid, its clipped box is not
+                            * empty and W != 0; otherwise every field is 0 */
+  int32_t reserved[2];
+} ocsr_box_point;
+
+/* One 3D point per box from its aggregated disparity d = results[i].disparity
+ * (full-resolution px). boxes, results (dev): [n_boxes], as given to or returned by a
+ * ranging call. pp (host). out (dev): [n_boxes]. Computed in fp32 from the parameters
+ * rounded to fp32. OCSR_E_INVALID for n_boxes < 0, null pointers with n_boxes > 0, a
+ * non-positive image size, f or b, or a negative variance. */
+int32_t ocsr_box_points(ocsr_ctx* ctx, const ocsr_box* boxes, const ocsr_box_result* results,
+                        int32_t n_boxes, const ocsr_point_params* pp, ocsr_box_point* out,
+                        void* stream);
+
+/* ------------------------------------------------------------------------------ */
 /* Whole frame: census of both views at both levels, then matching (Alg. 2)         */
 /* ------------------------------------------------------------------------------ */
 /* Census window and the close level's scale of a frame. */
@@ -383,7 +420,7 @@ int32_t ocsr_ctx_graph_stats(ocsr_ctx* ctx, int64_t* hits, int64_t* builds);
  * match_close and match_far (one launch per level, when no kernel for the pair of
  * variants is built), aggregate, reset and fused (the persistent launch), graph (one
  * replay of a whole-frame or batch call with OCSR_OPTION_GRAPH on), dense and
- * dense_check (the dense counterpart). */
+ * dense_check (the dense counterpart), points (ocsr_box_points). */
 int32_t ocsr_ctx_set_timing(ocsr_ctx* ctx, int32_t enable);
 int32_t ocsr_ctx_kernel_time(ocsr_ctx* ctx, const char* kernel, int64_t* launches,
                              double* total_ms);

@@ -16,6 +16,8 @@
  *   aggregation ....... Sec. 4.3.4, four aggregation steps
  *   occluders ......... Sec. 4.3.5
  *   depth ............. Eq. 1 (Z = f b / d), and d_full = s d_down (Sec. 4.1)
+ *   3D point .......... Sec. 4.3.6, Q-matrix equation, then T_cam->imu
+ *   covariance ........ Sec. 4.3.7, depth-variance and rotation equations
  */
 #include "ocsr_oracle.h"
 
@@ -492,4 +494,50 @@ int32_t orc_dense_at(const uint64_t* CL, const uint64_t* CR, int32_t W, int32_t 
     out[k] = (int16_t)(ok ? d : -1);
   }
   return 0;
+}
+
+/* ------------------------------------------------------------------------------ */
+/* Per-box 3D point (Sec. 4.3.6) and covariance (Sec. 4.3.7), fp64.               */
+/* ------------------------------------------------------------------------------ */
+void orc_box_points(const int32_t* boxes, const orc_box_result* res, int32_t n, int32_t W,
+                    int32_t H, const double* Q, const double* R, const double* t, double f,
+                    double b, double var_d, double var_x, double var_y, orc_point* out) {
+  for (int i = 0; i < n; ++i) {
+    orc_point o;
+    memset(&o, 0, sizeof(o));
+    const int32_t* bx = boxes + 5 * i;
+    const int cx0 = imax(bx[0], 0), cy0 = imax(bx[1], 0);
+    const int cx1 = imin(bx[2], W), cy1 = imin(bx[3], H);
+    if (res[i].valid && cx0 < cx1 && cy0 < cy1) {
+      /* the box's image point: mean of its clipped pixel indices */
+      const double uvd1[4] = {0.5 * (cx0 + cx1 - 1), 0.5 * (cy0 + cy1 - 1), (double)res[i].disparity, 1.0};
+      double h[4];
+      for (int r = 0; r < 4; ++r) {
+        h[r] = 0.0;
+        for (int c = 0; c < 4; ++c) h[r] += Q[4 * r + c] * uvd1[c];
+      }
+      if (h[3] != 0.0) {
+        for (int k = 0; k < 3; ++k) o.p_cam[k] = h[k] / h[3];
+        /* T_cam->imu: rotate, then translate */
+        for (int r = 0; r < 3; ++r) {
+          o.p_imu[r] = t[r];
+          for (int c = 0; c < 3; ++c) o.p_imu[r] += R[3 * r + c] * o.p_cam[c];
+        }
+        /* sigma_Z^2 = (dZ/dd)^2 sigma_d^2 = Z^4 sigma_d^2 / (f^2 b^2) */
+        const double Z = o.p_cam[2];
+        o.var_z = Z * Z * Z * Z * var_d / (f * f * b * b);
+        /* R diag(sigma_x^2, sigma_y^2, sigma_Z^2) R^T */
+        const double dg[3] = {var_x, var_y, o.var_z};
+        int q = 0;
+        for (int r = 0; r < 3; ++r)
+          for (int c = r; c < 3; ++c) {
+            double acc = 0.0;
+            for (int k = 0; k < 3; ++k) acc += R[3 * r + k] * dg[k] * R[3 * c + k];
+            o.cov_imu[q++] = acc;
+          }
+        o.valid = 1;
+      }
+    }
+    out[i] = o;
+  }
 }

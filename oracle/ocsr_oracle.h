@@ -93,6 +93,23 @@ int32_t orc_dense_at(const uint64_t* CL, const uint64_t* CR, int32_t W, int32_t 
                      int32_t dmin, int32_t dmax, int32_t radius, int32_t lr_tol,
                      const int32_t* xy, int32_t n, int16_t* out, int32_t n_threads);
 
+/* Per-box 3D point and covariance (Sec. 4.3.6 Q-matrix equation; Sec. 4.3.7 depth
+ * variance and covariance rotation), in fp64. The box's image point is the centre of
+ * its box clipped to the W x H image in pixel-index coordinates, ((cx0 + cx1 - 1) / 2,
+ * (cy0 + cy1 - 1) / 2); d is the box result's disparity. (X, Y, Z, W') = Q (u, v, d, 1),
+ * p_cam = (X, Y, Z) / W', p_imu = R p_cam + t, var_z = Z^4 var_d / (f^2 b^2),
+ * cov_imu = R diag(var_x, var_y, var_z) R^T (upper triangle xx, xy, xz, yy, yz, zz).
+ * A box whose result is not valid, whose clipped box is empty or whose W' is 0 gets
+ * valid = 0 and zeros. Q, R row-major. */
+typedef struct {
+  double p_cam[3], p_imu[3], cov_imu[6], var_z;
+  int32_t valid;
+} orc_point;
+
+void orc_box_points(const int32_t* boxes, const orc_box_result* res, int32_t n, int32_t W,
+                    int32_t H, const double* Q, const double* R, const double* t, double f,
+                    double b, double var_d, double var_x, double var_y, orc_point* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -74,6 +74,9 @@ def lib():
         L.orc_dense.restype = i32
         L.orc_dense_at.argtypes = [vp, vp, i32, i32, i32, i32, i32, i32, vp, i32, vp, i32]
         L.orc_dense_at.restype = i32
+        d = C.c_double
+        L.orc_box_points.argtypes = [vp, vp, i32, i32, i32, vp, vp, vp, d, d, d, d, d, vp]
+        L.orc_box_points.restype = None
         _lib = L
     return _lib
 
@@ -163,6 +166,32 @@ def run_scene(left, right, params: dict, boxes, debug=False, threads=0, cap_bloc
     res = match_boxes(L0, R0, L1, R1, W, H, boxes, params, debug=debug, threads=threads,
                       cap_blocks=cap_blocks)
     return (L0, R0, L1, R1), res
+
+
+class _Point(C.Structure):
+    _fields_ = [("p_cam", C.c_double * 3), ("p_imu", C.c_double * 3), ("cov_imu", C.c_double * 6),
+                ("var_z", C.c_double), ("valid", C.c_int32)]
+
+
+POINT_DT = np.dtype({"names": ["p_cam", "p_imu", "cov_imu", "var_z", "valid"],
+                     "formats": [("<f8", (3,)), ("<f8", (3,)), ("<f8", (6,)), "<f8", "<i4"],
+                     "offsets": [0, 24, 48, 96, 104], "itemsize": C.sizeof(_Point)})
+
+
+def box_points(boxes, results, geom: dict) -> np.ndarray:
+    """Per-box 3D point and covariance (Sec. 4.3.6, 4.3.7), fp64: one POINT_DT record per
+    box. results: BOX_RESULT_DT records (the disparity and validity of each box)."""
+    L = lib()
+    b = np.ascontiguousarray(boxes, dtype=np.int32).reshape(-1, 5)
+    r = np.ascontiguousarray(results).view(BOX_RESULT_DT)
+    n = b.shape[0]
+    out = np.zeros(n, dtype=POINT_DT)
+    dbl = lambda a, k: np.ascontiguousarray(np.asarray(a, dtype=np.float64).reshape(k))
+    Q, R, t = dbl(geom["Q"], 16), dbl(geom["R"], 9), dbl(geom["t"], 3)
+    L.orc_box_points(_ptr(b), _ptr(r), n, int(geom["width"]), int(geom["height"]), _ptr(Q),
+                     _ptr(R), _ptr(t), float(geom["focal_px"]), float(geom["baseline_m"]),
+                     float(geom["var_d"]), float(geom["var_x"]), float(geom["var_y"]), _ptr(out))
+    return out
 
 
 def dense(CL, CR, dmin=0, dmax=191, radius=2, lr_tol=1, threads=0):

@@ -478,6 +478,34 @@ int32_t ocsr_census(ocsr_ctx* ctx, const uint8_t* img, int32_t width, int32_t he
                         (hipStream_t)stream, ctx->timing ? &t : nullptr);
 }
 
+int32_t ocsr_box_points(ocsr_ctx* ctx, const ocsr_box* boxes, const ocsr_box_result* results,
+                        int32_t n_boxes, const ocsr_point_params* pp, ocsr_box_point* out,
+                        void* stream) {
+  g_last_error.clear();
+  if (!ctx || !pp) return fail(OCSR_E_INVALID, "null context or point params");
+  if (n_boxes < 0) return fail(OCSR_E_INVALID, "n_boxes %d < 0", n_boxes);
+  if (n_boxes > 0 && (!boxes || !results || !out)) return fail(OCSR_E_INVALID, "null boxes, results or output");
+  if (pp->width <= 0 || pp->height <= 0) return fail(OCSR_E_INVALID, "image size %dx%d", pp->width, pp->height);
+  if (!(pp->focal_px > 0) || !(pp->baseline_m > 0))
+    return fail(OCSR_E_INVALID, "focal length and baseline must be positive");
+  if (!(pp->var_d >= 0) || !(pp->var_x >= 0) || !(pp->var_y >= 0))
+    return fail(OCSR_E_INVALID, "variances must be non-negative");
+  PointParamsDev d;
+  d.width = pp->width;
+  d.height = pp->height;
+  for (int k = 0; k < 16; ++k) d.Q[k] = (float)pp->Q[k];
+  for (int k = 0; k < 9; ++k) d.R[k] = (float)pp->R[k];
+  for (int k = 0; k < 3; ++k) d.t[k] = (float)pp->t[k];
+  d.fb = (float)pp->focal_px * (float)pp->baseline_m;
+  d.var_d = (float)pp->var_d;
+  d.var_x = (float)pp->var_x;
+  d.var_y = (float)pp->var_y;
+  LaunchTimer t = make_timer(ctx);
+  const hipError_t e = launch_box_points(boxes, results, n_boxes, d, out, (hipStream_t)stream,
+                                         ctx->timing ? &t : nullptr);
+  return e == hipSuccess ? OCSR_OK : hip_fail(e, "point launch");
+}
+
 int32_t ocsr_census_many(ocsr_ctx* ctx, const ocsr_census_job* jobs, int32_t n_jobs,
                          int32_t sx, int32_t sy, int32_t sentinel, void* stream) {
   g_last_error.clear();

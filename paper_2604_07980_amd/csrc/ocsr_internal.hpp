@@ -214,6 +214,19 @@ bool fused_available(const MatchParamsDev& p, int sx, int sy);
 // Dense counterpart: left-view and right-view winner-take-all over [dmin, dmax] of the
 // (2 radius + 1)^2 window sums of Hamming costs, then the left/right check. d_left and
 // d_right: int16 [H][W] scratch (d_right also an output when the caller asks for it).
+static_assert(sizeof(ocsr_box_point) == 64, "box point layout");
+
+// fp32 copy of ocsr_point_params for the point kernel
+struct PointParamsDev {
+  int32_t width, height;
+  float Q[16], R[9], t[3];
+  float fb;                        // f * b, one fp32 multiply
+  float var_d, var_x, var_y;
+};
+hipError_t launch_box_points(const ocsr_box* boxes, const ocsr_box_result* res, int n,
+                             const PointParamsDev& pp, ocsr_box_point* out, hipStream_t stream,
+                             const LaunchTimer* timer);
+
 bool dense_radius_supported(int radius);
 hipError_t launch_dense(const uint64_t* CL, const uint64_t* CR, int W, int H, int pitch, int dmin,
                         int dmax, int radius, int lr_tol, int16_t* disp, int16_t* d_left,

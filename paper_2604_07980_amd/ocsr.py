@@ -39,7 +39,7 @@ EXPORTS = ["ocsr_abi_version", "ocsr_last_error", "ocsr_ctx_create", "ocsr_ctx_d
            "ocsr_range_batch", "ocsr_ctx_set_option", "ocsr_ctx_set_timing",
            "ocsr_ctx_kernel_time", "ocsr_ctx_reset_timing", "ocsr_ctx_graph_stats",
            "ocsr_variant_candidates", "ocsr_ctx_set_variant", "ocsr_dense_workspace_bytes",
-           "ocsr_dense_match"]
+           "ocsr_dense_match", "ocsr_box_points"]
 
 
 class OcsrError(RuntimeError):
@@ -94,6 +94,17 @@ class Debug(C.Structure):
     _fields_ = [("cap_blocks", C.c_int32), ("cap_nd", C.c_int32), ("n_blocks", C.c_void_p),
                 ("blocks", C.c_void_p), ("cost_fwd", C.c_void_p), ("cost_bwd", C.c_void_p)]
 
+
+class PointParams(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("Q", C.c_double * 16),
+                ("R", C.c_double * 9), ("t", C.c_double * 3), ("focal_px", C.c_double),
+                ("baseline_m", C.c_double), ("var_d", C.c_double), ("var_x", C.c_double),
+                ("var_y", C.c_double)]
+
+
+BOX_POINT_DTYPE = np.dtype([("p_cam", "<f4", (3,)), ("p_imu", "<f4", (3,)), ("cov_imu", "<f4", (6,)),
+                            ("var_z", "<f4"), ("valid", "<i4"), ("reserved", "<i4", (2,))])
+assert BOX_POINT_DTYPE.itemsize == 64
 
 BOX_RESULT_DTYPE = np.dtype([("disparity", "<f4"), ("depth", "<f4"), ("valid", "<i4"),
                              ("reason", "<i4"), ("n_blocks", "<i4"), ("n_eligible", "<i4"),
@@ -167,6 +178,8 @@ def load(path: str = LIB_PATH):
         L.ocsr_dense_match.argtypes = [vp, C.POINTER(Level), i32, i32, i32, i32, vp, vp, vp,
                                        C.c_size_t, vp]
         L.ocsr_dense_match.restype = i32
+        L.ocsr_box_points.argtypes = [vp, vp, vp, i32, C.POINTER(PointParams), vp, vp]
+        L.ocsr_box_points.restype = i32
         _lib = L
         return L
 
@@ -447,6 +460,44 @@ def dense(L: torch.Tensor, R: torch.Tensor, dmin: int = 0, dmax: int = 191, radi
                                _dptr(disp), _dptr(disp_r) if right else None, _dptr(ws),
                                ws.numel(), _stream(dev)))
     return (disp, disp_r) if right else disp
+
+
+def point_params(geom: dict) -> PointParams:
+    """ocsr_point_params from a dict: width, height, Q (4x4), R (3x3), t (3), focal_px,
+    baseline_m, var_d, var_x, var_y."""
+    pp = PointParams()
+    pp.width, pp.height = int(geom["width"]), int(geom["height"])
+    for name, n in (("Q", 16), ("R", 9), ("t", 3)):
+        vals = np.asarray(geom[name], dtype=np.float64).reshape(-1)
+        if vals.size != n:
+            raise ValueError(f"{name} must have {n} entries")
+        getattr(pp, name)[:] = vals.tolist()
+    for name in ("focal_px", "baseline_m", "var_d", "var_x", "var_y"):
+        setattr(pp, name, float(geom[name]))
+    return pp
+
+
+def box_points(boxes: torch.Tensor, results: torch.Tensor, geom: dict,
+               out: torch.Tensor | None = None) -> torch.Tensor:
+    """Per-box 3D point and covariance from ranging results (int32 [N, 8] cuda, as
+    returned by range_frame / range_batch / match_boxes) and their boxes (int32 [N, 5]).
+    Returns an int32 [N, 16] cuda tensor; points_to_numpy views it as BOX_POINT_DTYPE."""
+    _need_cuda(boxes, results)
+    n = boxes.shape[0]
+    if boxes.dtype != torch.int32 or boxes.dim() != 2 or boxes.shape[1] != 5 or not boxes.is_contiguous():
+        raise ValueError("boxes must be a contiguous int32 [N, 5] tensor")
+    if results.dtype != torch.int32 or tuple(results.shape) != (n, 8) or not results.is_contiguous():
+        raise ValueError("results must be a contiguous int32 [N, 8] tensor")
+    if out is None:
+        out = torch.empty((n, 16), dtype=torch.int32, device=boxes.device)
+    pp = point_params(geom)
+    _check(load().ocsr_box_points(context(boxes.device.index), _dptr(boxes), _dptr(results), n,
+                                  C.byref(pp), _dptr(out), _stream(boxes.device)))
+    return out
+
+
+def points_to_numpy(pts: torch.Tensor) -> np.ndarray:
+    return pts.cpu().numpy().view(BOX_POINT_DTYPE).reshape(-1)
 
 
 def set_option(option: int, value: int, device: int | None = None):

@@ -139,6 +139,19 @@ def base_params() -> dict:
     )
 
 
+def point_geometry(width: int, height: int, params: dict) -> dict:
+    """Camera geometry of the point step for a rectified pair with the preset's f and b:
+    principal point at the image centre, camera x/y/z mapped to vehicle z-up axes
+    (x forward = camera z, y left = -camera x, z up = -camera y), camera 1.5 m above
+    and 1.2 m ahead of the vehicle origin."""
+    f, b = float(params["focal_px"]), float(params["baseline_m"])
+    cx, cy = (width - 1) / 2.0, (height - 1) / 2.0
+    Q = [[1, 0, 0, -cx], [0, 1, 0, -cy], [0, 0, 0, f], [0, 0, 1 / b, 0]]
+    R = [[0, 0, 1], [-1, 0, 0], [0, -1, 0]]
+    return dict(width=width, height=height, Q=Q, R=R, t=[1.2, 0.0, 1.5], focal_px=f,
+                baseline_m=b, var_d=0.25, var_x=0.01, var_y=0.01)
+
+
 def params_for(config: int, width: int = 1920) -> dict:
     p = base_params()
     if config == 1:
