@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define OCSR_ABI_VERSION 1
+#define OCSR_ABI_VERSION 2
 
 /* status codes */
 #define OCSR_OK 0
@@ -73,6 +73,10 @@ extern "C" {
 #define OCSR_MAX_BATCH_FRAMES 16
 /* Largest search range (level candidates) of one path. */
 #define OCSR_MAX_CANDIDATES 256
+/* Largest vertical offset (full-res px) and most (d, dy) candidates of a path with a
+ * vertical range (ocsr_match_params.dy_min, dy_max). */
+#define OCSR_MAX_DY 32
+#define OCSR_MAX_DY_CANDIDATES 2048
 
 typedef struct ocsr_ctx ocsr_ctx;
 
@@ -170,6 +174,18 @@ typedef struct {
   float focal_px;          /* f */
   float baseline_m;        /* b */
   float d_eps;             /* disparity <= d_eps: NONPOSITIVE_DISPARITY */
+  /* Vertical offsets searched together with the disparity, full-res px (the census
+   * cost of Sec. 4.3.2 over (dx, dy)); dy_min = dy_max = 0 searches dy = 0 only.
+   * -OCSR_MAX_DY <= dy_min <= dy_max <= OCSR_MAX_DY. A path on level s searches the
+   * level offsets floor(dy_min/s) .. ceil(dy_max/s) (its ndy values); the forward
+   * winner is the least cost over (d, dy), ties to the smaller d, then the smaller dy.
+   * The backward search starts at the forward match (x - d_f, y + dy_f) and visits
+   * (d, dy) at (x - d_f + d, y + dy_f - dy); the L/R check compares d_b with d_f only.
+   * Limits with a vertical range: nd * ndy <= OCSR_MAX_DY_CANDIDATES per path, and
+   * the path's working set must fit a workgroup's LDS (a 96-candidate 8 x 8 path takes
+   * up to 16 dy values); beyond them the call returns OCSR_E_UNSUPPORTED. Rows outside
+   * the level image read as all-zero descriptors, as columns do. */
+  int32_t dy_min, dy_max;
 } ocsr_match_params;
 
 typedef struct {
@@ -193,6 +209,7 @@ typedef struct {
   float d_sub;                /* sub-pixel forward disparity, level px */
   int32_t valid;
   int32_t dlo, nd;            /* level search range [dlo, dlo + nd) */
+  int32_t dy_f, dy_b;         /* level vertical offsets of the forward and backward winners */
 } ocsr_block_record;
 
 /* Optional debug outputs of ocsr_match_boxes (any pointer may be NULL). Blocks
@@ -201,8 +218,8 @@ typedef struct {
   int32_t cap_blocks, cap_nd;
   int32_t* n_blocks;              /* dev, 1 int: blocks numbered (incl. overflowed boxes) */
   ocsr_block_record* blocks;      /* dev, [cap_blocks] */
-  uint16_t* cost_fwd;             /* dev, [cap_blocks][cap_nd]: S_f(dlo + k) */
-  uint16_t* cost_bwd;             /* dev, [cap_blocks][cap_nd]: S_b(dlo + k) */
+  uint16_t* cost_fwd;             /* dev, [cap_blocks][cap_nd]: S_f(dlo + k) at dy_f */
+  uint16_t* cost_bwd;             /* dev, [cap_blocks][cap_nd]: S_b(dlo + k) at dy_b */
 } ocsr_debug;
 
 /* Workspace of ocsr_match_boxes for up to n_boxes boxes and cap_blocks blocks in
@@ -281,7 +298,9 @@ size_t ocsr_frame_workspace_bytes(int32_t width, int32_t height,
  * type (Sec. 4.3.4) lies on the level rectangle [x0, x1) x [y0, y1) of its eligible
  * pixels, and for candidates dlo..dhi its searches read the right view on
  * [x0 - dhi, x1 - dlo) and the left view on [x0 - (dhi - dlo), x1 + (dhi - dlo)), rows
- * [y0, y1). By default (OCSR_OPTION_FULL_CENSUS 0) the call makes the descriptors of
+ * [y0, y1); with level vertical offsets eylo..eyhi (a vertical range) the right view's
+ * rows are [y0 + eylo, y1 + eyhi) and the left view's [y0 - (eyhi - eylo),
+ * y1 + (eyhi - eylo)). By default (OCSR_OPTION_FULL_CENSUS 0) the call makes the descriptors of
  * every 64 x 32 tile (tiles start at multiples of 64 and 32) that meets such a range
  * of some box, and leaves the rest of the images undefined; with the option on, of
  * every tile. */

@@ -87,6 +87,8 @@ def match_boxes(levels: dict, W: int, H: int, boxes, p: dict):
         Hs, Ws = Lv.shape
         dlo = path["dmin"] // s
         nd = _cdiv(path["dmax"] - path["dmin"] + 1, s)
+        # level vertical offsets: the fewest whose s-multiples cover [dy_min, dy_max]
+        dylo, dyhi = p.get("dy_min", 0) // s, _cdiv(p.get("dy_max", 0), s)
         # level box
         xs_all = [x for x in range(Ws) if c[0] <= s * x < c[2] and p["sx"] <= x < Ws - p["sx"]]
         ys_all = [y for y in range(Hs) if c[1] <= s * y < c[3] and p["sy"] <= y < Hs - p["sy"]]
@@ -134,20 +136,28 @@ def match_boxes(levels: dict, W: int, H: int, boxes, p: dict):
             if not elig:
                 continue
             r["n_eligible"] += 1
-            fwd = [sum(_ham(_get(Lv, x, y), _get(Rv, x - d, y)) for (x, y) in used)
-                   for d in range(dlo, dlo + nd)]
-            kf = int(np.argmin(fwd))  # first minimum = smallest disparity
-            d_f = dlo + kf
+            # every (d, e) candidate; min over (cost, d, e) puts ties on the smallest d,
+            # then the smallest e
+            es = range(dylo, dyhi + 1)
+            fall = {(d, e): sum(_ham(_get(Lv, x, y), _get(Rv, x - d, y + e)) for (x, y) in used)
+                    for d in range(dlo, dlo + nd) for e in es}
+            _, d_f, e_f = min((c, d, e) for (d, e), c in fall.items())
+            kf = d_f - dlo
+            fwd = [fall[(d, e_f)] for d in range(dlo, dlo + nd)]
             if 0 < kf < nd - 1:
                 a, cc, bb = fwd[kf - 1], fwd[kf], fwd[kf + 1]
                 dsub = np.float32(d_f) + np.float32(np.float32(a - bb) / np.float32(2 * (a + bb - 2 * cc)))
             else:
                 dsub = np.float32(d_f)
-            bwd = [sum(_ham(_get(Rv, x - d_f, y), _get(Lv, x - d_f + d, y)) for (x, y) in used)
-                   for d in range(dlo, dlo + nd)]
-            d_b = dlo + int(np.argmin(bwd))
+            # backward from the matched right point (x - d_f, y + e_f): left at (+d, -e)
+            ball = {(d, e): sum(_ham(_get(Rv, x - d_f, y + e_f), _get(Lv, x - d_f + d, y + e_f - e))
+                                for (x, y) in used)
+                    for d in range(dlo, dlo + nd) for e in es}
+            _, d_b, e_b = min((c, d, e) for (d, e), c in ball.items())
+            bwd = [ball[(d, e_b)] for d in range(dlo, dlo + nd)]
             ok = abs(d_b - d_f) <= p["lr_tol"]
-            blk.update(d_f=d_f, d_b=d_b, lr_ok=int(ok), d_sub=float(dsub), cost_f=fwd, cost_b=bwd)
+            blk.update(d_f=d_f, d_b=d_b, dy_f=e_f, dy_b=e_b, lr_ok=int(ok), d_sub=float(dsub),
+                       cost_f=fwd, cost_b=bwd)
             if ok:
                 vals.append(np.float32(s) * np.float32(dsub))
         r["n_valid"] = len(vals)

@@ -9,7 +9,7 @@
  *
  * Paper map:
  *   census ............ Sec. 4.3.1, census equation and Alg. 1
- *   block cost ........ Sec. 4.3.2, census cost equation
+ *   block cost ........ Sec. 4.3.2, census cost equation, over (dx, dy) offsets
  *   sub-pixel ......... Sec. 4.3.2, parabola equation
  *   forward-backward .. Sec. 4.3.3
  *   far / close ....... Sec. 4.3.4, type equation, Alg. 2
@@ -94,11 +94,12 @@ static int boxes_overlap(const clip_t* a, const clip_t* b) {
          a->cy0 < b->cy1 && b->cy0 < a->cy1;
 }
 
-/* S(P, d) of the census-cost equation with dx = -d, dy = 0, over the masked points.
- * dir = +1: forward, template CL at p, search CR at p.x - d.
- * dir = -1: backward, template CR at q = p.x - d_f, search CL at q.x + d. */
+/* S(P, dx, dy) of the census-cost equation with dx = -d, over the masked points.
+ * dir = +1: forward, template CL at p, search CR at (p.x - d, p.y + e).
+ * dir = -1: backward, template CR at the forward match q = (p.x - d_f, p.y + e_f),
+ *           search CL at (q.x + d, q.y - e), so that (d, e) = (d_f, e_f) returns to p. */
 static int block_cost(const level_t* lv, const int* xs, const int* ys, int nx, int ny,
-                      uint64_t mask, int dir, int d, int d_f) {
+                      uint64_t mask, int dir, int d, int e, int d_f, int e_f) {
   int sum = 0;
   for (int j = 0; j < ny; ++j) {
     for (int i = 0; i < nx; ++i) {
@@ -107,10 +108,10 @@ static int block_cost(const level_t* lv, const int* xs, const int* ys, int nx, i
       uint64_t a, b;
       if (dir > 0) {
         a = rd(lv, lv->L, xs[i], ys[j]);
-        b = rd(lv, lv->R, xs[i] - d, ys[j]);
+        b = rd(lv, lv->R, xs[i] - d, ys[j] + e);
       } else {
-        a = rd(lv, lv->R, xs[i] - d_f, ys[j]);
-        b = rd(lv, lv->L, xs[i] - d_f + d, ys[j]);
+        a = rd(lv, lv->R, xs[i] - d_f, ys[j] + e_f);
+        b = rd(lv, lv->L, xs[i] - d_f + d, ys[j] + e_f - e);
       }
       sum += popcount64(a ^ b);
     }
@@ -185,6 +186,7 @@ typedef struct {
   int lx0, ly0, lw, lh; /* level box */
   int nbx, nby, bw, bh, ox, oy;
   int dlo, nd;
+  int dylo, ndy;        /* level vertical offsets [dylo, dylo + ndy) */
   int n_blocks;
 } plan_t;
 
@@ -202,6 +204,10 @@ static void plan_box(const orc_params* p, const clip_t* c, const level_t* lv0,
   int dmin = pl->path->dmin, dmax = pl->path->dmax;
   pl->dlo = floor_div(dmin, s);
   pl->nd = ceil_div_nonneg(dmax - dmin + 1, s);
+  /* level vertical range: the smallest level range whose full-res offsets s*e cover
+   * [dy_min, dy_max] (a 2D offset search, Sec. 4.3.2); 0, 0 gives the single e = 0 */
+  pl->dylo = floor_div(p->dy_min, s);
+  pl->ndy = ceil_div(p->dy_max, s) - pl->dylo + 1;
   /* level pixels whose full-res position s*x lies in the box and whose census is defined */
   int x0 = imax(ceil_div(c->cx0, s), p->sx), x1 = imin(ceil_div(c->cx1, s), lv->W - p->sx);
   int y0 = imax(ceil_div(c->cy0, s), p->sy), y1 = imin(ceil_div(c->cy1, s), lv->H - p->sy);
@@ -244,6 +250,7 @@ int32_t orc_match_boxes(const uint64_t* L0, const uint64_t* R0,
                         int32_t cap_dbg, int32_t cap_nd, int32_t n_threads) {
   if (!L0 || !R0 || !p || !out || n < 0 || (n > 0 && !boxes) || W <= 0 || H <= 0) return -1;
   if (p->close_scale <= 0 || p->sx < 0 || p->sy < 0) return -1;
+  if (p->dy_min > p->dy_max) return -1;
   {
     const orc_path* ps[2] = {&p->far_path, &p->close_path};
     for (int k = 0; k < 2; ++k) {
@@ -312,6 +319,7 @@ int32_t orc_match_boxes(const uint64_t* L0, const uint64_t* R0,
     float* vals = (float*)malloc(sizeof(float) * (size_t)pl->n_blocks);
     int* fcost = (int*)malloc(sizeof(int) * (size_t)pl->nd);
     int* bcost = (int*)malloc(sizeof(int) * (size_t)pl->nd);
+    int* fall = (int*)malloc(sizeof(int) * (size_t)pl->nd * (size_t)pl->ndy);  /* S at (k, e) */
     int n_valid = 0, n_elig = 0;
     for (int v = 0; v < pl->nby; ++v) {
       for (int u = 0; u < pl->nbx; ++u) {
@@ -337,18 +345,24 @@ int32_t orc_match_boxes(const uint64_t* L0, const uint64_t* R0,
         }
         int npts = popcount64(mask);
         int eligible = npts > 0 && 100 * npts >= p->min_point_pct * nx * ny;
-        int d_f = pl->dlo, d_b = pl->dlo, lr_ok = 0, valid = 0;
+        int d_f = pl->dlo, d_b = pl->dlo, e_f = 0, e_b = 0, lr_ok = 0, valid = 0;
         float d_sub = (float)pl->dlo;
         if (eligible) {
           ++n_elig;
-          /* forward: exhaustive search, winner-take-all, smallest d on ties */
-          int best = -1;
+          /* forward: exhaustive search over (d, e), winner-take-all; ties go to the
+           * smallest d, then the smallest e */
+          int best = -1, ebest = 0, bestc = 0;
           for (int k = 0; k < pl->nd; ++k) {
-            int d = pl->dlo + k;
-            fcost[k] = block_cost(lv, xs, ys, nx, ny, mask, +1, d, 0);
-            if (best < 0 || fcost[k] < fcost[best]) best = k;
+            for (int ei = 0; ei < pl->ndy; ++ei) {
+              int c = block_cost(lv, xs, ys, nx, ny, mask, +1, pl->dlo + k, pl->dylo + ei, 0, 0);
+              fall[k * pl->ndy + ei] = c;
+              if (best < 0 || c < bestc) { best = k; ebest = ei; bestc = c; }
+            }
           }
           d_f = pl->dlo + best;
+          e_f = pl->dylo + ebest;
+          /* costs along d at the winning e (parabola and debug output) */
+          for (int k = 0; k < pl->nd; ++k) fcost[k] = fall[k * pl->ndy + ebest];
           /* parabola through the forward costs at d_f - 1, d_f, d_f + 1 */
           if (best > 0 && best < pl->nd - 1) {
             int a = fcost[best - 1], c = fcost[best], b = fcost[best + 1];
@@ -360,13 +374,18 @@ int32_t orc_match_boxes(const uint64_t* L0, const uint64_t* R0,
             d_sub = (float)d_f;
           }
           /* backward: templates at the matched right positions, search the left */
-          int bbest = -1;
+          int bbest = -1, bebest = 0, bbestc = 0;
           for (int k = 0; k < pl->nd; ++k) {
-            int d = pl->dlo + k;
-            bcost[k] = block_cost(lv, xs, ys, nx, ny, mask, -1, d, d_f);
-            if (bbest < 0 || bcost[k] < bcost[bbest]) bbest = k;
+            for (int ei = 0; ei < pl->ndy; ++ei) {
+              int c = block_cost(lv, xs, ys, nx, ny, mask, -1, pl->dlo + k, pl->dylo + ei, d_f, e_f);
+              fall[k * pl->ndy + ei] = c;
+              if (bbest < 0 || c < bbestc) { bbest = k; bebest = ei; bbestc = c; }
+            }
           }
           d_b = pl->dlo + bbest;
+          e_b = pl->dylo + bebest;
+          for (int k = 0; k < pl->nd; ++k) bcost[k] = fall[k * pl->ndy + bebest];
+          /* consistency on the horizontal offset only (Sec. 4.3.3) */
           lr_ok = abs(d_b - d_f) <= p->lr_tol;
           valid = lr_ok;
           if (valid) vals[n_valid++] = (float)s * d_sub;
@@ -382,12 +401,13 @@ int32_t orc_match_boxes(const uint64_t* L0, const uint64_t* R0,
           bk->mask = mask; bk->eligible = eligible; bk->d_f = d_f; bk->d_b = d_b;
           bk->lr_ok = lr_ok; bk->d_sub = d_sub; bk->valid = valid;
           bk->dlo = pl->dlo; bk->nd = pl->nd;
+          bk->dy_f = e_f; bk->dy_b = e_b;
         }
       }
     }
     r->n_eligible = n_elig;
     orc_aggregate(vals, n_valid, pl->n_blocks, p, r);
-    free(vals); free(fcost); free(bcost);
+    free(vals); free(fcost); free(bcost); free(fall);
   }
   free(clip); free(plan); free(off); free(status);
   return (int32_t)total;

@@ -40,6 +40,7 @@ typedef struct {
   float   focal_px, baseline_m, d_eps;
   int32_t max_blocks_per_box; /* boxes tiling into more blocks: CAPACITY_OVERFLOW */
   int32_t cap_blocks;         /* total block capacity (prefix rule), <= 0: unlimited */
+  int32_t dy_min, dy_max;     /* vertical offsets searched, full-res px; 0, 0: none */
 } orc_params;
 
 typedef struct {
@@ -55,6 +56,7 @@ typedef struct {
   float   d_sub;                   /* level px */
   int32_t valid;
   int32_t dlo, nd;                 /* level search range [dlo, dlo + nd) */
+  int32_t dy_f, dy_b;              /* level vertical offsets of the two winners */
 } orc_block;
 
 /* Census of one level: out is [H/s][W/s] row-major, pitch W/s. Returns 0, or -1

@@ -40,7 +40,8 @@ class _Params(C.Structure):
                 ("lr_tol", C.c_int32), ("min_point_pct", C.c_int32), ("agg_mode", C.c_int32),
                 ("tau_d", C.c_float), ("n_min", C.c_int32), ("trim_pct", C.c_int32),
                 ("focal_px", C.c_float), ("baseline_m", C.c_float), ("d_eps", C.c_float),
-                ("max_blocks_per_box", C.c_int32), ("cap_blocks", C.c_int32)]
+                ("max_blocks_per_box", C.c_int32), ("cap_blocks", C.c_int32),
+                ("dy_min", C.c_int32), ("dy_max", C.c_int32)]
 
 
 BOX_RESULT_DT = np.dtype([("disparity", "<f4"), ("depth", "<f4"), ("valid", "<i4"),
@@ -50,7 +51,7 @@ BLOCK_DT = np.dtype([("box", "<i4"), ("level_scale", "<i4"), ("u", "<i4"), ("v",
                      ("px0", "<i4"), ("py0", "<i4"), ("nx", "<i4"), ("ny", "<i4"),
                      ("mask", "<u8"), ("eligible", "<i4"), ("d_f", "<i4"), ("d_b", "<i4"),
                      ("lr_ok", "<i4"), ("d_sub", "<f4"), ("valid", "<i4"),
-                     ("dlo", "<i4"), ("nd", "<i4")])
+                     ("dlo", "<i4"), ("nd", "<i4"), ("dy_f", "<i4"), ("dy_b", "<i4")])
 
 _lib = None
 
@@ -107,6 +108,7 @@ def make_params(p: dict, cap_blocks: int = 0) -> _Params:
     q.focal_px, q.baseline_m, q.d_eps = p["focal_px"], p["baseline_m"], p["d_eps"]
     q.max_blocks_per_box = p.get("max_blocks_per_box", MAX_BLOCKS_PER_BOX)
     q.cap_blocks = cap_blocks
+    q.dy_min, q.dy_max = p.get("dy_min", 0), p.get("dy_max", 0)
     return q
 
 

@@ -35,6 +35,9 @@ def census_tiles(W: int, H: int, boxes, params: dict, full: bool = False) -> set
             continue
         dlo = ph["dmin"] // s
         dhi = dlo + _cdiv(ph["dmax"] - ph["dmin"] + 1, s) - 1
+        # level vertical offsets (0, 0 without a vertical range)
+        eylo, eyhi = params.get("dy_min", 0) // s, _cdiv(params.get("dy_max", 0), s)
+        ey = eyhi - eylo
         for x0, y0, x1, y1, flags in boxes.tolist():
             cx0, cy0, cx1, cy1 = max(x0, 0), max(y0, 0), min(x1, W), min(y1, H)
             if not (flags & BOX_RANGE) or cx0 >= cx1 or cy0 >= cy1:
@@ -45,12 +48,14 @@ def census_tiles(W: int, H: int, boxes, params: dict, full: bool = False) -> set
             ly0, ly1 = max(_cdiv(cy0, s), sy), min(_cdiv(cy1, s), Hl - sy)
             if lx0 >= lx1 or ly0 >= ly1:
                 continue
-            for view, (a, b) in enumerate(((lx0 - (dhi - dlo), lx1 + (dhi - dlo)),
-                                           (lx0 - dhi, lx1 - dlo))):
+            for view, (a, b, ya, yb) in enumerate(
+                    ((lx0 - (dhi - dlo), lx1 + (dhi - dlo), ly0 - ey, ly1 + ey),
+                     (lx0 - dhi, lx1 - dlo, ly0 + eylo, ly1 + eyhi))):
                 a, b = max(a, 0), min(b, ntx * TILE_X)
-                if a >= b:
+                ya, yb = max(ya, 0), min(yb, nty * TILE_Y)
+                if a >= b or ya >= yb:
                     continue
-                for ty in range(ly0 // TILE_Y, (ly1 - 1) // TILE_Y + 1):
+                for ty in range(ya // TILE_Y, (yb - 1) // TILE_Y + 1):
                     for tx in range(a // TILE_X, (b - 1) // TILE_X + 1):
                         out.add((level, view, tx, ty))
     return out

@@ -253,6 +253,27 @@ int32_t build_params(const ocsr_ctx* ctx, const ocsr_match_params* p, int close_
       ph.passes = it->second[2];
     }
   }
+  // vertical range (a 2D offset search, Sec. 4.3.2): level offsets floor(dy_min / s) ..
+  // ceil(dy_max / s) on a level of scale s
+  if (p->dy_min < -OCSR_MAX_DY || p->dy_max > OCSR_MAX_DY || p->dy_min > p->dy_max)
+    return fail(OCSR_E_INVALID, "vertical range [%d, %d] outside -%d <= dy_min <= dy_max <= %d",
+                p->dy_min, p->dy_max, OCSR_MAX_DY, OCSR_MAX_DY);
+  d->vertical = p->dy_min != 0 || p->dy_max != 0;
+  for (int l = 0; l < 2; ++l) {
+    PathDev& ph = d->path[l];
+    const int s = l == 0 ? 1 : close_scale;
+    auto fdiv = [](int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); };
+    ph.dylo = fdiv(p->dy_min, s);
+    ph.ndy = -fdiv(-p->dy_max, s) - ph.dylo + 1;
+    if (!d->vertical) continue;
+    if (ph.nd * ph.ndy > OCSR_MAX_DY_CANDIDATES)
+      return fail(OCSR_E_UNSUPPORTED, "%s path: %d x %d (d, dy) candidates > %d", l == 0 ? "far" : "close",
+                  ph.nd, ph.ndy, OCSR_MAX_DY_CANDIDATES);
+    const size_t lds = kItemWaves * dy_wave_lds_bytes(dy_rows(ph.bw, ph.bh), ph.nd, ph.ndy);
+    if (lds > kDyMaxWgLds)
+      return fail(OCSR_E_UNSUPPORTED, "%s path: %d disparities x %d vertical offsets need %zu bytes of "
+                  "LDS per workgroup > %zu", l == 0 ? "far" : "close", ph.nd, ph.ndy, lds, kDyMaxWgLds);
+  }
   if (p->lr_tol < 0) return fail(OCSR_E_INVALID, "lr_tol < 0");
   if (p->min_point_pct < 0 || p->min_point_pct > 100) return fail(OCSR_E_INVALID, "min_point_pct outside 0..100");
   if (p->agg_mode != OCSR_AGG_SEGMENT_MEDIAN && p->agg_mode != OCSR_AGG_TRIMMED_MEDIAN)

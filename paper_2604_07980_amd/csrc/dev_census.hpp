@@ -206,6 +206,10 @@ __device__ __forceinline__ bool census_tile_needed(const MatchParamsDev& MP, con
   const int dlo = MP.path[level].dlo, dhi = dlo + MP.path[level].nd - 1;
   const int ext_lo = view ? dhi : dhi - dlo;   // the read range starts this far left of x0
   const int ext_hi = view ? -dlo : dhi - dlo;  // and ends this far right of x1
+  // rows: the right view is read at y + dy, the left view (backward) at y + dy_f - dy
+  const int eylo = MP.path[level].dylo, eyhi = eylo + MP.path[level].ndy - 1;
+  const int ey_lo = view ? -eylo : eyhi - eylo;  // rows start this far above y0
+  const int ey_hi = view ? eyhi : eyhi - eylo;   // and end this far below y1
   for (int base = 0; base < fr.n_boxes; base += 64) {
     const int i = base + lane;
     bool hit = false;
@@ -217,7 +221,7 @@ __device__ __forceinline__ bool census_tile_needed(const MatchParamsDev& MP, con
           (max(cx1 - cx0, cy1 - cy0) < MP.tau_s ? 0 : 1) == level) {
         const int x0 = max(cdiv_nonneg(cx0, s), lv.sx), x1 = min(cdiv_nonneg(cx1, s), lv.W - lv.sx);
         const int y0 = max(cdiv_nonneg(cy0, s), lv.sy), y1 = min(cdiv_nonneg(cy1, s), lv.H - lv.sy);
-        hit = x0 < x1 && y0 < y1 && y0 < Y0 + kCensusTileY && Y0 < y1 &&
+        hit = x0 < x1 && y0 < y1 && y0 - ey_lo < Y0 + kCensusTileY && Y0 < y1 + ey_hi &&
               x0 - ext_lo < X0 + kCensusTileX && X0 < x1 + ext_hi;
       }
     }
@@ -296,15 +300,20 @@ __device__ __forceinline__ void mark_census_tiles(const MatchParamsDev& MP, cons
       const int y0 = max(cdiv_nonneg(cy0, s), lv.sy), y1 = min(cdiv_nonneg(cy1, s), lv.H - lv.sy);
       if (!(x0 < x1 && y0 < y1)) continue;
       const int dlo = MP.path[level].dlo, dhi = dlo + MP.path[level].nd - 1;
+      const int eylo = MP.path[level].dylo, eyhi = eylo + MP.path[level].ndy - 1;
       const int tiles_x = level ? fr.tiles1_x : fr.tiles0_x;
       const int tiles = level ? fr.tiles1 : fr.tiles0;
+      const int tiles_y = tiles / tiles_x;
       const int lbase = fr.tile_begin + (level ? 0 : 2 * fr.tiles1);
       for (int view = 0; view < 2; ++view) {
         const int a = max(x0 - (view ? dhi : dhi - dlo), 0);
         const int e = min(x1 + (view ? -dlo : dhi - dlo), tiles_x * kCensusTileX);
         if (a >= e) continue;
         const int ta = a / kCensusTileX, tb = (e - 1) / kCensusTileX;
-        for (int ty = y0 / kCensusTileY; ty <= (y1 - 1) / kCensusTileY; ++ty) {
+        const int ya = max(y0 + (view ? eylo : eylo - eyhi), 0);
+        const int yb = min(y1 + (view ? eyhi : eyhi - eylo), tiles_y * kCensusTileY);
+        if (ya >= yb) continue;
+        for (int ty = ya / kCensusTileY; ty <= (yb - 1) / kCensusTileY; ++ty) {
           const int first = lbase + view * tiles + ty * tiles_x + ta;
           const int last = first + (tb - ta);
           for (int wd = first >> 5; wd <= (last >> 5); ++wd) {

@@ -256,7 +256,8 @@ __device__ __forceinline__ BlockCtx block_ctx(const MatchParamsDev& P, const Fra
 __device__ __forceinline__ void write_block(const MatchWs& ws, const DebugDev& dbg,
                                             const BlockCtx& c, const PathDev& ph, uint64_t mask,
                                             bool eligible, int d_f, int d_b, int lr_ok,
-                                            float d_sub, int valid, int lane) {
+                                            float d_sub, int valid, int lane, int dy_f = 0,
+                                            int dy_b = 0) {
   if (lane == 0) {
     ws.blk_val[c.slot] = (float)c.g.s * d_sub;   // d_full = s * d (Sec. 4.1)
     ws.blk_flag[c.slot] = (uint8_t)((eligible ? 1 : 0) | (valid ? 2 : 0));
@@ -267,6 +268,7 @@ __device__ __forceinline__ void write_block(const MatchWs& ws, const DebugDev& d
       rec.mask = mask; rec.eligible = eligible; rec.d_f = d_f; rec.d_b = d_b;
       rec.lr_ok = lr_ok; rec.d_sub = d_sub; rec.valid = valid;
       rec.dlo = ph.dlo; rec.nd = ph.nd;
+      rec.dy_f = dy_f; rec.dy_b = dy_b;
       dbg.blocks[c.b] = rec;
     }
   }
@@ -496,6 +498,162 @@ __device__ __forceinline__ void match_block_tiled(const MatchParamsDev& P, const
     }
   }
   write_block(ws, dbg, c, ph, mask, true, d_f, d_b, lr_ok, d_sub, lr_ok, lane);
+  wave_sync();
+}
+
+// ---------------------------------------------------------------------------------
+// TILED block with a vertical range (the census cost over (dx, dy), Sec. 4.3.2). The
+// register-blocked row costs of match_block_tiled, repeated for every vertical offset:
+// for offset e the strip holds the searched view's rows moved by e, staged with row
+// and column bounds (rows outside the level image read as zero). Candidates run in
+// runtime passes of PC; every (d, e) cost is kept in LDS (uint16) for the parabola,
+// which runs along d at the winning e. Keys order ties by d, then e.
+// LDS per wave: dy_wave_lds_bytes(ROWS, nd, ndy).
+// ---------------------------------------------------------------------------------
+// S[jj * SWr + m] = word (x_first + m, y_first + jj) of the level image for m < SWr,
+// zero outside the image, for m >= sw or for jj >= ny
+template <int ROWS>
+__device__ __forceinline__ void stage_rows_dy(uint64_t* __restrict__ S, int SWr,
+                                              const uint64_t* __restrict__ img, int pitch, int W,
+                                              int H, int x_first, int y_first, int ny, int sw,
+                                              int lane) {
+#pragma unroll
+  for (int jj = 0; jj < ROWS; ++jj) {
+    const int y = y_first + jj;
+    const bool row_ok = jj < ny && y >= 0 && y < H;
+    for (int m = lane; m < SWr; m += 64) {
+      const int x = x_first + m;
+      const bool ok = row_ok && m < sw && x >= 0 && x < W;
+      S[jj * SWr + m] = ok ? img[(size_t)y * pitch + x] : 0ull;
+    }
+  }
+}
+
+template <int ROWS, int NX>
+__device__ __forceinline__ void match_block_dy(const MatchParamsDev& P, const FrameDev& fr,
+                                               const MatchWs& ws, const DebugDev& dbg,
+                                               const BlockCtx& c, int lane, void* lds) {
+  constexpr int CPL = kDyCpl;
+  constexpr int G = 64 / ROWS;
+  constexpr int PC = G * CPL;   // candidates of one pass
+  const LevelDev& lv = fr.lv[c.level];
+  const PathDev& ph = P.path[c.level];
+  const int nd = ph.nd, dlo = ph.dlo, dhi = dlo + nd - 1;
+  const int ndy = ph.ndy, dylo = ph.dylo;
+  const int passes = (nd + PC - 1) / PC;
+  const int SWr = passes * PC + NX - 1;        // strip row stride (words)
+  const int sw = nd + NX - 1;                  // words a row's candidates read
+  auto r16 = [](size_t v) { return (v + 15) & ~(size_t)15; };
+  uint64_t* S = (uint64_t*)lds;
+  uint64_t* T = (uint64_t*)((char*)lds + r16(sizeof(uint64_t) * ROWS * SWr));
+  uint16_t* costf = (uint16_t*)((char*)T + r16(sizeof(uint64_t) * ROWS * NX));
+  uint16_t* costb = (uint16_t*)((char*)costf + r16(sizeof(uint16_t) * (size_t)nd * ndy));
+  const int j = lane % ROWS, grp = lane / ROWS;
+  const int nx = c.g.nx, ny = c.g.ny;
+  const int X0 = c.g.cx, Y0 = c.g.cy;
+
+  // forward template CL(X0 + i, Y0 + j): the block lies inside the level image
+  for (int idx = lane; idx < ROWS * NX; idx += 64) {
+    const int jj = idx / NX, i = idx % NX;
+    T[idx] = jj < ny && i < nx ? lv.L[(size_t)(Y0 + jj) * lv.pitch + X0 + i] : 0ull;
+  }
+  const uint64_t mask = block_mask(ws, fr.box_off, fr.n_boxes, c.k, c.g, lane);
+  const bool eligible = block_eligible(P, mask, nx * ny);
+  wave_sync();
+  if (!eligible) {
+    write_block(ws, dbg, c, ph, mask, false, dlo, dlo, 0, (float)dlo, 0, lane);
+    wave_sync();
+    return;
+  }
+  const uint32_t rowmask = j < ny ? (uint32_t)((mask >> (j * nx)) & ((1u << nx) - 1u)) : 0u;
+  uint32_t col_all = (1u << nx) - 1u, col_any = 0;
+  for (int jj = 0; jj < ny; ++jj) {
+    const uint32_t r = (uint32_t)((mask >> (jj * nx)) & ((1u << nx) - 1u));
+    col_all &= r;
+    col_any |= r;
+  }
+  uint64_t t[NX];
+#pragma unroll
+  for (int i = 0; i < NX; ++i) t[i] = T[j * NX + i];
+  uint32_t acc[CPL];
+  // forward: for offset e the strip row jj holds CR(X0 - dhi + m, Y0 + e + jj); entry
+  // q + i of candidate position q holds CR(X0 + i - d) for d = dhi - q
+  uint32_t key = 0xFFFFFFFFu;
+  for (int ey = 0; ey < ndy; ++ey) {
+    stage_rows_dy<ROWS>(S, SWr, lv.R, lv.pitch, lv.W, lv.H, X0 - dhi, Y0 + dylo + ey, ny, sw, lane);
+    wave_sync();
+    for (int ps = 0; ps < passes; ++ps) {
+      if (j < ny) row_costs<NX, CPL>(t, S + j * SWr + ps * PC + grp * CPL, rowmask, col_all, col_any, acc);
+#pragma unroll
+      for (int cc = 0; cc < CPL; ++cc)
+        if (j >= ny) acc[cc] = 0;
+#pragma unroll
+      for (int cc = 0; cc < CPL; ++cc) {
+        const uint32_t tot = row_sum<ROWS>(acc[cc]);
+        const int q = ps * PC + grp * CPL + cc;
+        if (q < nd) {
+          const int id = (nd - 1 - q) * ndy + ey;   // (d index, e index), d major
+          key = min(key, (tot << 16) | (uint32_t)id);
+          if (j == 0) costf[id] = (uint16_t)tot;
+        }
+      }
+    }
+    wave_sync();
+  }
+  key = wave_min_u32(key, ROWS);
+  const int best_id = (int)(key & 0xFFFFu);
+  const int kf = best_id / ndy, ef = best_id - kf * ndy;
+  const int d_f = dlo + kf, dy_f = dylo + ef;
+  const int ca = (int)costf[max(kf - 1, 0) * ndy + ef];
+  const int cb = (int)costf[min(kf + 1, nd - 1) * ndy + ef];
+  const float d_sub = subpixel(d_f, kf, nd, ca, (int)(key >> 16), cb);
+  // backward template CR(X0 - d_f + i, Y0 + dy_f + j), zero outside the image
+  {
+    const int y = Y0 + dy_f + j;
+    const bool row_ok = j < ny && y >= 0 && y < lv.H;
+#pragma unroll
+    for (int i = 0; i < NX; ++i) {
+      const int x = X0 - d_f + i;
+      const bool ok = row_ok && i < nx && x >= 0 && x < lv.W;
+      t[i] = ok ? lv.R[(size_t)y * lv.pitch + x] : 0ull;
+    }
+  }
+  // backward: for offset e the strip row jj holds CL(X0 - d_f + dlo + m, Y0 + dy_f - e + jj)
+  uint32_t bkey = 0xFFFFFFFFu;
+  for (int ey = 0; ey < ndy; ++ey) {
+    stage_rows_dy<ROWS>(S, SWr, lv.L, lv.pitch, lv.W, lv.H, X0 - d_f + dlo, Y0 + dy_f - (dylo + ey),
+                        ny, sw, lane);
+    wave_sync();
+    for (int ps = 0; ps < passes; ++ps) {
+      if (j < ny) row_costs<NX, CPL>(t, S + j * SWr + ps * PC + grp * CPL, rowmask, col_all, col_any, acc);
+#pragma unroll
+      for (int cc = 0; cc < CPL; ++cc)
+        if (j >= ny) acc[cc] = 0;
+#pragma unroll
+      for (int cc = 0; cc < CPL; ++cc) {
+        const uint32_t tot = row_sum<ROWS>(acc[cc]);
+        const int q = ps * PC + grp * CPL + cc;   // candidate dlo + q
+        if (q < nd) {
+          const int id = q * ndy + ey;
+          bkey = min(bkey, (tot << 16) | (uint32_t)id);
+          if (j == 0) costb[id] = (uint16_t)tot;
+        }
+      }
+    }
+    wave_sync();
+  }
+  bkey = wave_min_u32(bkey, ROWS);
+  const int bid = (int)(bkey & 0xFFFFu);
+  const int kb = bid / ndy, eb = bid - kb * ndy;
+  const int d_b = dlo + kb, dy_b = dylo + eb;
+  const int lr_ok = abs(d_b - d_f) <= P.lr_tol;   // consistency on d only (Sec. 4.3.3)
+  if (c.b < dbg.cap_blocks && (dbg.cost_fwd || dbg.cost_bwd)) {
+    for (int q = lane; q < nd && q < dbg.cap_nd; q += 64) {
+      if (dbg.cost_fwd) dbg.cost_fwd[(size_t)c.b * dbg.cap_nd + q] = costf[q * ndy + ef];
+      if (dbg.cost_bwd) dbg.cost_bwd[(size_t)c.b * dbg.cap_nd + q] = costb[q * ndy + eb];
+    }
+  }
+  write_block(ws, dbg, c, ph, mask, true, d_f, d_b, lr_ok, d_sub, lr_ok, lane, dy_f, dy_b);
   wave_sync();
 }
 

@@ -101,7 +101,8 @@ __global__ __launch_bounds__(256) void fused_kernel(MatchParamsDev P, FramesDev 
 enum class FusedPair { kNone, k4_2__8_12, k4_2__8_8, k4_2__8_16, k8_8__8_12 };
 
 FusedPair fused_pair(const MatchParamsDev& P, int sx, int sy) {
-  if (sx != 3 || sy != 4) return FusedPair::kNone;
+  // the persistent kernel has no vertical search: such calls take the multi-launch path
+  if (sx != 3 || sy != 4 || P.vertical) return FusedPair::kNone;
   const PathDev& f = P.path[0];
   const PathDev& c = P.path[1];
   if (c.rows != 8 || f.passes != 1 || c.passes != 1) return FusedPair::kNone;

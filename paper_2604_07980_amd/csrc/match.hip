@@ -125,6 +125,25 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(pair_waves<
   }
 }
 
+// A level's work items with a vertical range: as match_tiled_kernel, with the dy block
+// matcher and an LDS share of wave_bytes per wave (dynamic, sized on the host)
+template <int ROWS, int NX>
+__global__ __launch_bounds__(256) void match_dy_kernel(MatchParamsDev P, FramesDev FR, MatchWs ws,
+                                                       DebugDev dbg, int level, int wave_bytes) {
+  extern __shared__ uint64_t dy_lds[];
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int lane = threadIdx.x & 63;
+  void* wl = (char*)dy_lds + (size_t)wave * wave_bytes;
+  dev::level_items(FR, ws, level, [&](int f, int q) {
+    const FrameDev& fr = FR.f[f];
+    const int at = q + (level ? 0 : ws.fcount[f * FC_N + FC_CLOSE_ITEMS]);
+    const ItemRec r = ws.items[(size_t)f * ws.items_cap + at];
+    dev::run_item_rec(P, fr, f, level, r, wave, [&](const dev::BlockCtx& c) {
+      dev::match_block_dy<ROWS, NX>(P, fr, ws, dbg, c, lane, wl);
+    });
+  });
+}
+
 __global__ __launch_bounds__(256) void aggregate_kernel(MatchParamsDev P, MatchWs ws,
                                                         ocsr_box_result* out) {
   __shared__ dev::AggLds sm;
@@ -228,6 +247,20 @@ static hipError_t launch_level(const MatchParamsDev& P, const FramesDev& FR, con
   return hipErrorNotSupported;   // rejected by the argument checks before any launch
 }
 
+static hipError_t launch_dy_level(const MatchParamsDev& P, const FramesDev& FR, const MatchWs& ws,
+                                  const DebugDev& dbg, int level, int grid, hipStream_t stream) {
+  const PathDev& v = P.path[level];
+  const int rows = dy_rows(v.bw, v.bh);
+  const size_t wave_bytes = dy_wave_lds_bytes(rows, v.nd, v.ndy);
+  const size_t bytes = kItemWaves * wave_bytes;
+  if (bytes > kDyMaxWgLds) return hipErrorInvalidValue;   // rejected by the argument checks
+  if (rows == 4)
+    match_dy_kernel<4, 4><<<grid, 256, bytes, stream>>>(P, FR, ws, dbg, level, (int)wave_bytes);
+  else
+    match_dy_kernel<8, 8><<<grid, 256, bytes, stream>>>(P, FR, ws, dbg, level, (int)wave_bytes);
+  return hipGetLastError();
+}
+
 // One launch for both levels when a kernel for the pair of variants is built (with
 // launch == false: only whether it is built).
 static bool launch_pair(const MatchParamsDev& P, const FramesDev& FR, const MatchWs& ws,
@@ -308,7 +341,15 @@ hipError_t launch_match(const MatchParamsDev& P, const FramesDev& FR, const ocsr
     if (timer) timer->after(timer->ctx, "plan", stream);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  if (launch_pair(P, FR, ws, dbg, n_match_wgs, stream, false)) {
+  if (P.vertical) {
+    for (int level = 1; level >= 0; --level) {
+      const char* name = level == 0 ? "match_far" : "match_close";
+      if (timer) timer->before(timer->ctx, name, stream);
+      e = launch_dy_level(P, FR, ws, dbg, level, n_match_wgs, stream);
+      if (timer) timer->after(timer->ctx, name, stream);
+      if (e != hipSuccess) return e;
+    }
+  } else if (launch_pair(P, FR, ws, dbg, n_match_wgs, stream, false)) {
     if (timer) timer->before(timer->ctx, "match", stream);
     launch_pair(P, FR, ws, dbg, n_match_wgs, stream, true);
     if (timer) timer->after(timer->ctx, "match", stream);

@@ -54,6 +54,7 @@ struct PathDev {
   int32_t mode, bw, bh, n_side;
   int32_t dlo, nd;                 // level search range [dlo, dlo + nd)
   int32_t rows, cpl, passes;       // matching kernel variant (chosen on the host)
+  int32_t dylo, ndy;               // level vertical offsets [dylo, dylo + ndy)
 };
 
 // Matching parameters shared by every frame of a call.
@@ -69,7 +70,26 @@ struct MatchParamsDev {
   int32_t item_blocks;             // blocks per work item: kItemWaves x blocks per wave
   int32_t full_census;             // whole-frame calls: 1 = census of every tile, 0 = only
                                    // of the tiles some box's search reads
+  int32_t vertical;                // 1: a vertical range is searched (the dy kernels run)
 };
+
+// Kernel of a path with a vertical range: one wave per block, NX x ROWS points, lanes
+// (row, group of kDyCpl consecutive candidates), the candidates in runtime passes of
+// (64 / ROWS) * kDyCpl; per wave an LDS strip of ROWS rows x dy_strip_words words, the
+// template, and the forward and backward costs of every (d, dy) as uint16.
+constexpr int kDyCpl = 4;
+inline int dy_rows(int bw, int bh) { return bw <= 4 && bh <= 4 ? 4 : 8; }
+inline int dy_passes(int rows, int nd) {
+  const int pc = (64 / rows) * kDyCpl;
+  return (nd + pc - 1) / pc;
+}
+inline int dy_strip_words(int rows, int nd) { return dy_passes(rows, nd) * (64 / rows) * kDyCpl + rows - 1; }
+inline size_t dy_wave_lds_bytes(int rows, int nd, int ndy) {
+  auto r16 = [](size_t v) { return (v + 15) & ~(size_t)15; };
+  return r16(sizeof(uint64_t) * rows * dy_strip_words(rows, nd)) + r16(sizeof(uint64_t) * rows * rows) +
+         2 * r16(sizeof(uint16_t) * (size_t)nd * ndy);
+}
+constexpr size_t kDyMaxWgLds = 65536;   // LDS of one dy workgroup (kItemWaves waves)
 
 // One frame of a call: descriptor levels, its boxes and (whole-frame calls) its images.
 struct FrameDev {
@@ -215,6 +235,7 @@ bool fused_available(const MatchParamsDev& p, int sx, int sy);
 // (2 radius + 1)^2 window sums of Hamming costs, then the left/right check. d_left and
 // d_right: int16 [H][W] scratch (d_right also an output when the caller asks for it).
 static_assert(sizeof(ocsr_box_point) == 64, "box point layout");
+static_assert(sizeof(ocsr_block_record) == 80, "block record layout");
 
 // fp32 copy of ocsr_point_params for the point kernel
 struct PointParamsDev {

@@ -27,6 +27,8 @@ BOX_RANGE = 1
 MAX_BLOCKS_PER_BOX = 4096
 MAX_BATCH_FRAMES = 16
 MAX_CANDIDATES = 256
+MAX_DY = 32
+MAX_DY_CANDIDATES = 2048
 MAX_CENSUS_JOBS = 64
 DEFAULT_CAP_BLOCKS = 1 << 20
 
@@ -76,7 +78,7 @@ class MatchParams(C.Structure):
                 ("close_path", Path), ("lr_tol", C.c_int32), ("min_point_pct", C.c_int32),
                 ("agg_mode", C.c_int32), ("tau_d", C.c_float), ("n_min", C.c_int32),
                 ("trim_pct", C.c_int32), ("focal_px", C.c_float), ("baseline_m", C.c_float),
-                ("d_eps", C.c_float)]
+                ("d_eps", C.c_float), ("dy_min", C.c_int32), ("dy_max", C.c_int32)]
 
 
 class FrameParams(C.Structure):
@@ -113,8 +115,9 @@ BLOCK_RECORD_DTYPE = np.dtype([("box", "<i4"), ("level_scale", "<i4"), ("u", "<i
                                ("px0", "<i4"), ("py0", "<i4"), ("nx", "<i4"), ("ny", "<i4"),
                                ("mask", "<u8"), ("eligible", "<i4"), ("d_f", "<i4"),
                                ("d_b", "<i4"), ("lr_ok", "<i4"), ("d_sub", "<f4"),
-                               ("valid", "<i4"), ("dlo", "<i4"), ("nd", "<i4")])
-assert BOX_RESULT_DTYPE.itemsize == 32 and BLOCK_RECORD_DTYPE.itemsize == 72
+                               ("valid", "<i4"), ("dlo", "<i4"), ("nd", "<i4"),
+                               ("dy_f", "<i4"), ("dy_b", "<i4")])
+assert BOX_RESULT_DTYPE.itemsize == 32 and BLOCK_RECORD_DTYPE.itemsize == 80
 
 _lib = None
 _lock = threading.Lock()
@@ -269,6 +272,7 @@ def make_params(p: dict) -> MatchParams:
     q.lr_tol, q.min_point_pct, q.agg_mode = p["lr_tol"], p["min_point_pct"], p["agg_mode"]
     q.tau_d, q.n_min, q.trim_pct = p["tau_d"], p["n_min"], p["trim_pct"]
     q.focal_px, q.baseline_m, q.d_eps = p["focal_px"], p["baseline_m"], p["d_eps"]
+    q.dy_min, q.dy_max = int(p.get("dy_min", 0)), int(p.get("dy_max", 0))
     return q
 
 

@@ -114,6 +114,36 @@ def render_pair(rng: np.random.Generator, H: int, W: int, planes) -> tuple[np.nd
     return left, right
 
 
+def drift_rows(img: np.ndarray, dy: int) -> np.ndarray:
+    """The image moved down by dy rows (up for dy < 0), the vacated rows repeating the
+    nearest edge row: out[y] = img[clamp(y - dy)]. Applied to the right view it stands
+    for a residual vertical misalignment of the rectified pair, so that the match of
+    left row y sits on right row y + dy."""
+    H = img.shape[0]
+    rows = np.clip(np.arange(H) - int(dy), 0, H - 1)
+    return np.ascontiguousarray(img[rows])
+
+
+def shifted_texture(seed: int, H: int, W: int, dx: int, dy: int,
+                    mode: str = "2d") -> tuple[np.ndarray, np.ndarray]:
+    """Left texture and a right view that is the same texture moved by (-dx, +dy), cut
+    from one larger field: right(x - dx, y + dy) = left(x, y) wherever both exist.
+    mode "2d": blurred noise; "cols": every row the same (varies along x only);
+    "rows": every column the same (varies along y only)."""
+    rng = np.random.default_rng(seed)
+    pad = 8 + abs(dx) + abs(dy)
+    if mode == "2d":
+        big = blurred_noise(rng, H + 2 * pad, W + 2 * pad)
+    elif mode == "cols":
+        big = np.repeat(rng.integers(0, 256, (1, W + 2 * pad)).astype(np.float64), H + 2 * pad, 0)
+    else:
+        big = np.repeat(rng.integers(0, 256, (H + 2 * pad, 1)).astype(np.float64), W + 2 * pad, 1)
+    big = np.rint(big).astype(np.uint8)
+    left = big[pad:pad + H, pad:pad + W]
+    right = big[pad - dy:pad - dy + H, pad + dx:pad + dx + W]
+    return np.ascontiguousarray(left), np.ascontiguousarray(right)
+
+
 def _overlap(a, b) -> bool:
     return a[0] < b[2] and b[0] < a[2] and a[1] < b[3] and b[1] < a[3]
 

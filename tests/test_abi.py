@@ -40,7 +40,7 @@ def test_exports_every_declared_symbol(built):
 
 
 def test_abi_version_and_host_only_calls(built):
-    assert built.ocsr_abi_version() == 1
+    assert built.ocsr_abi_version() == 2
     assert built.ocsr_last_error() == b""
     # workspace sizing is pure host arithmetic
     a = built.ocsr_match_workspace_bytes(32, 1 << 16)
@@ -53,11 +53,11 @@ def test_abi_version_and_host_only_calls(built):
 
 
 def test_struct_sizes_match_header():
-    assert C.sizeof(ocsr.MatchParams) == 4 + 4 + 2 * 24 + 3 * 4 + 4 + 2 * 4 + 3 * 4
+    assert C.sizeof(ocsr.MatchParams) == 4 + 4 + 2 * 24 + 3 * 4 + 4 + 2 * 4 + 3 * 4 + 2 * 4
     assert C.sizeof(ocsr.Level) == 2 * 8 + 6 * 4
     assert C.sizeof(ocsr.CensusJob) == 2 * 8 + 6 * 4
     assert C.sizeof(ocsr.Debug) == 2 * 4 + 4 * 8
-    assert ocsr.BLOCK_RECORD_DTYPE.itemsize == 72
+    assert ocsr.BLOCK_RECORD_DTYPE.itemsize == 80
 
 
 def test_header_constants_match_binding():
@@ -66,6 +66,8 @@ def test_header_constants_match_binding():
         return int(re.search(rf"#define {name} \(?(-?\d+)", src).group(1))
     assert const("OCSR_MAX_BLOCKS_PER_BOX") == ocsr.MAX_BLOCKS_PER_BOX
     assert const("OCSR_MAX_CANDIDATES") == ocsr.MAX_CANDIDATES
+    assert const("OCSR_MAX_DY") == ocsr.MAX_DY
+    assert const("OCSR_MAX_DY_CANDIDATES") == ocsr.MAX_DY_CANDIDATES
     assert const("OCSR_MAX_CENSUS_JOBS") == ocsr.MAX_CENSUS_JOBS
     for k, name in enumerate(ocsr.REASONS):
         assert const(f"OCSR_REASON_{name}") == k

@@ -12,22 +12,31 @@ TX, TY = accounting.TILE_X, accounting.TILE_Y
 
 def _read_tiles(blk, W, H, p):
     """Tiles holding a descriptor some eligible block's searches read (forward: template
-    CL(x, y) and CR(x - d, y); backward: CR(x - d_f, y) and CL(x - d_f + d, y); d over the
-    level candidates; reads outside the level image are not reads)."""
+    CL(x, y) and CR(x - d, y + e); backward: CR(x - d_f, y + e_f) and
+    CL(x - d_f + d, y + e_f - e); d and e over the level candidates; reads outside the
+    level image are not reads)."""
     s = p["close_scale"]
     out = set()
     for b in blk[blk["eligible"] == 1]:
         level = 0 if b["level_scale"] == 1 else 1
-        Wl = W if level == 0 else W // s
+        sl = 1 if level == 0 else s
+        Wl, Hl = (W, H) if level == 0 else (W // s, H // s)
         dlo, nd = int(b["dlo"]), int(b["nd"])
         dhi = dlo + nd - 1
+        eylo, eyhi = p.get("dy_min", 0) // sl, -(-p.get("dy_max", 0) // sl)
         x0, nx, y0, ny, d_f = int(b["px0"]), int(b["nx"]), int(b["py0"]), int(b["ny"]), int(b["d_f"])
-        ranges = [(0, x0, x0 + nx), (1, x0 - dhi, x0 - dlo + nx), (1, x0 - d_f, x0 - d_f + nx),
-                  (0, x0 - d_f + dlo, x0 - d_f + dhi + nx)]
-        for view, a, e in ranges:
-            a, e = max(a, 0), min(e, Wl)
-            for ty in range(y0 // TY, (y0 + ny - 1) // TY + 1):
-                for tx in range(a // TX, (e - 1) // TX + 1) if a < e else ():
+        e_f = int(b["dy_f"])
+        # (view, x range, y range) of each read
+        ranges = [(0, x0, x0 + nx, y0, y0 + ny),
+                  (1, x0 - dhi, x0 - dlo + nx, y0 + eylo, y0 + ny + eyhi),
+                  (1, x0 - d_f, x0 - d_f + nx, y0 + e_f, y0 + e_f + ny),
+                  (0, x0 - d_f + dlo, x0 - d_f + dhi + nx, y0 + e_f - eyhi, y0 + e_f - eylo + ny)]
+        for view, a, e, ya, yb in ranges:
+            a, e, ya, yb = max(a, 0), min(e, Wl), max(ya, 0), min(yb, Hl)
+            if a >= e or ya >= yb:
+                continue
+            for ty in range(ya // TY, (yb - 1) // TY + 1):
+                for tx in range(a // TX, (e - 1) // TX + 1):
                     out.add((level, view, tx, ty))
     return out
 
@@ -70,6 +79,30 @@ def test_rule_covers_reads_of_the_realistic_frame(orc):
     rule = accounting.census_tiles(1920, 1080, sc.boxes, p)
     read = _read_tiles(blk[:n], 1920, 1080, p)
     assert read <= rule, sorted(read - rule)[:5]
+
+
+@pytest.mark.parametrize("dy", [(-3, 3), (-6, -2), (1, 5)])
+def test_rule_covers_vertical_reads(orc, dy):
+    """With a vertical range the searches read rows above and below the box: boxes along
+    tile rows and the image's top and bottom edges, right view drifted."""
+    rng = np.random.default_rng(40 + dy[0])
+    H, W = 200, 400
+    left = rng.integers(0, 256, size=(H, W), dtype=np.uint8)
+    right = synth.drift_rows(np.roll(left, -9, axis=1), dy[1] - 1)
+    p = synth.params_for(2)
+    p["far"]["dmax"], p["close"]["dmax"] = 31, 63
+    p["dy_min"], p["dy_max"] = dy
+    boxes = np.array([[40, 0, 70, 28, 1], [100, 26, 130, 40, 1], [150, 60, 260, 130, 1],
+                      [300, 150, 340, 200, 1], [20, 120, 120, 200, 1], [330, 30, 390, 62, 1]],
+                     np.int32)
+    _, (res, blk, _, _, n) = orc.run_scene(left, right, p, boxes, debug=True)
+    rule = accounting.census_tiles(W, H, boxes, p)
+    read = _read_tiles(blk[:n], W, H, p)
+    assert read <= rule, sorted(read - rule)[:5]
+    # the vertical range moves the rows read (a range of one sign moves the right view's
+    # rows away from the box's own)
+    p0 = dict(p, dy_min=0, dy_max=0)
+    assert accounting.census_tiles(W, H, boxes, p0) != rule
 
 
 def test_rule_without_ranged_boxes_is_empty():

@@ -140,7 +140,7 @@ def _check_debug(lib, extra, blk, cf, cb, n):
         bad = np.nonzero(rec[f] != blk[f])[0]
         assert bad.size == 0, (f, bad[:10], rec[f][bad[:5]], blk[f][bad[:5]])
     el = blk["eligible"] == 1
-    for f in ("d_f", "d_b", "lr_ok", "valid"):
+    for f in ("d_f", "d_b", "dy_f", "dy_b", "lr_ok", "valid"):
         assert (rec[f][el] == blk[f][el]).all(), f
     assert np.all(np.abs(rec["d_sub"][el] - blk["d_sub"][el]) <= TOL_D)
     for k in np.nonzero(el)[0]:
