@@ -43,6 +43,8 @@ def parse():
                     help="requests of the serving section at 120/s (0 skips it)")
     ap.add_argument("--serve-pool", type=int, default=2,
                     help="pre-rendered image pairs per serving resolution")
+    ap.add_argument("--vertical-steps", type=int, default=100,
+                    help="frames of the vertical-range workload (0: skip)")
     ap.add_argument("--dense-steps", type=int, default=20,
                     help="timed repetitions of the dense counterpart (0 skips it)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
@@ -99,10 +101,65 @@ def frame_costs(ocsr, L, R, boxes, p):
     el = rec["eligible"] == 1
     pts = np.array([bin(int(m)).count("1") for m in rec["mask"]], dtype=np.int64)
     far = rec["level_scale"] == 1
-    return {"costs": int((pts * rec["nd"] * el).sum()) * 2,
-            "costs_far": int((pts * rec["nd"] * (el & far)).sum()) * 2,
-            "evals": int((rec["nd"] * el).sum()) * 2,
+    # vertical offsets per block: floor(dy_min / s) .. ceil(dy_max / s) on its level
+    s = rec["level_scale"].astype(np.int64)
+    ndy = -(-p.get("dy_max", 0) // s) - p.get("dy_min", 0) // s + 1
+    cand = rec["nd"] * ndy
+    return {"costs": int((pts * cand * el).sum()) * 2,
+            "costs_far": int((pts * cand * (el & far)).sum()) * 2,
+            "evals": int((cand * el).sum()) * 2,
             "blocks": int(nb)}
+
+
+def vertical_section(ocsr, synth, steps, warmup):
+    """The 1080p frame with its right view 2 rows low, searched over dy in [-3, 3] (7
+    offsets on the far level, 5 on the close level): whole-frame time and the dy matching
+    kernels' rates (same op count per Hamming cost as the horizontal kernels)."""
+    import numpy as np
+    import torch
+    dev = torch.device("cuda:0")
+    sc = synth.scene_realistic()
+    p = dict(synth.params_for(2), dy_min=-3, dy_max=3)
+    L = torch.from_numpy(sc.left).to(dev)
+    R = torch.from_numpy(synth.drift_rows(sc.right, 2)).to(dev)
+    boxes = torch.from_numpy(sc.boxes).to(dev)
+    fw = frame_costs(ocsr, L, R, boxes, p)
+    ws = ocsr.Workspace()
+    out = torch.empty((boxes.shape[0], 8), dtype=torch.int32, device=dev)
+
+    def step():
+        ocsr.range_frame(L, R, boxes, p, workspace=ws, out=out)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / steps
+    ocsr.reset_timing()
+    ocsr.set_timing(True)
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    ocsr.set_timing(False)
+    kern = {}
+    work = {"match_far": fw["costs_far"] * MATCH_OPS_PER_COST,
+            "match_close": (fw["costs"] - fw["costs_far"]) * MATCH_OPS_PER_COST}
+    for name in ("census", "match_far", "match_close", "aggregate"):
+        cnt, tot = ocsr.kernel_time(name)
+        if cnt:
+            kern[name] = {"avg_us": round(1e3 * tot / cnt, 3)}
+            if name in work:
+                tops = work[name] / (1e-3 * tot / cnt) / 1e12
+                kern[name].update(tops=round(tops, 3), frac=round(tops / INT_PEAK_TOPS, 4))
+    res = ocsr.results_to_numpy(out)
+    return {"workload": "realistic_1080p, right view 2 rows low, dy -3..3 (far 7, close 5 "
+                        "level offsets)",
+            "ms_per_step": round(ms, 4), "costs_per_frame": fw["costs"],
+            "gcost_per_s": round(fw["costs"] / (ms * 1e-3) / 1e9, 3),
+            "valid_boxes": int(res["valid"].sum()), "kernels": kern}
 
 
 def batch_section(ocsr, synth, steps, warmup):
@@ -463,6 +520,8 @@ def main():
         "roofline": roofline,
         "points": points,
     }
+    if args.vertical_steps > 0:
+        res["vertical"] = vertical_section(ocsr, synth, args.vertical_steps, max(3, args.warmup // 10))
     if args.batch_steps > 0:
         res["batch"] = batch_section(ocsr, synth, args.batch_steps, max(3, args.warmup // 10))
     if args.dense_steps > 0:

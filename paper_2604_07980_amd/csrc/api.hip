@@ -269,7 +269,11 @@ int32_t build_params(const ocsr_ctx* ctx, const ocsr_match_params* p, int close_
     if (ph.nd * ph.ndy > OCSR_MAX_DY_CANDIDATES)
       return fail(OCSR_E_UNSUPPORTED, "%s path: %d x %d (d, dy) candidates > %d", l == 0 ? "far" : "close",
                   ph.nd, ph.ndy, OCSR_MAX_DY_CANDIDATES);
-    const size_t lds = kItemWaves * dy_wave_lds_bytes(dy_rows(ph.bw, ph.bh), ph.nd, ph.ndy);
+    const int rows = dy_rows(ph.bw, ph.bh);
+    if (dy_strip_words(rows, ph.nd) > 64 * dy_chunks(rows))
+      return fail(OCSR_E_UNSUPPORTED, "%s path: %d level disparities are more than a vertical search "
+                  "with %dx%d blocks takes", l == 0 ? "far" : "close", ph.nd, ph.bw, ph.bh);
+    const size_t lds = kItemWaves * dy_wave_lds_bytes(rows, ph.nd, ph.ndy);
     if (lds > kDyMaxWgLds)
       return fail(OCSR_E_UNSUPPORTED, "%s path: %d disparities x %d vertical offsets need %zu bytes of "
                   "LDS per workgroup > %zu", l == 0 ? "far" : "close", ph.nd, ph.ndy, lds, kDyMaxWgLds);

@@ -503,52 +503,114 @@ __device__ __forceinline__ void match_block_tiled(const MatchParamsDev& P, const
 
 // ---------------------------------------------------------------------------------
 // TILED block with a vertical range (the census cost over (dx, dy), Sec. 4.3.2). The
-// register-blocked row costs of match_block_tiled, repeated for every vertical offset:
-// for offset e the strip holds the searched view's rows moved by e, staged with row
-// and column bounds (rows outside the level image read as zero). Candidates run in
-// runtime passes of PC; every (d, e) cost is kept in LDS (uint16) for the parabola,
-// which runs along d at the winning e. Keys order ties by d, then e.
+// register-blocked row costs of match_block_tiled, repeated for every vertical offset.
+// Consecutive offsets read strip rows moved by one, so the strip lives in an LDS ring of
+// ROWS + 1 rows: step t reads rows t .. t + ROWS - 1 (lane row j from ring slot
+// (t + j) mod (ROWS + 1)) while row t + ROWS, which step t + 1 needs, is loaded into the
+// one slot step t does not read. Each row is loaded once per direction, its latency
+// hidden behind the previous step. Rows and columns outside the level image read as
+// zero. Every (d, e) cost is kept in LDS (uint16) for the parabola, which runs along d at
+// the winning e; keys order ties by d, then e.
 // LDS per wave: dy_wave_lds_bytes(ROWS, nd, ndy).
 // ---------------------------------------------------------------------------------
-// S[jj * SWr + m] = word (x_first + m, y_first + jj) of the level image for m < SWr,
-// zero outside the image, for m >= sw or for jj >= ny
-template <int ROWS>
-__device__ __forceinline__ void stage_rows_dy(uint64_t* __restrict__ S, int SWr,
-                                              const uint64_t* __restrict__ img, int pitch, int W,
-                                              int H, int x_first, int y_first, int ny, int sw,
-                                              int lane) {
+// the CH chunks of strip row y (words x_first + 64 c + lane, zero outside the image or
+// at and past sw)
+template <int CH>
+__device__ __forceinline__ void load_row_dy(uint64_t (&w)[CH], const uint64_t* __restrict__ img,
+                                            int pitch, int W, int H, int x_first, int y, int sw,
+                                            int lane) {
+  const bool row_ok = y >= 0 && y < H;
 #pragma unroll
-  for (int jj = 0; jj < ROWS; ++jj) {
-    const int y = y_first + jj;
-    const bool row_ok = jj < ny && y >= 0 && y < H;
-    for (int m = lane; m < SWr; m += 64) {
-      const int x = x_first + m;
-      const bool ok = row_ok && m < sw && x >= 0 && x < W;
-      S[jj * SWr + m] = ok ? img[(size_t)y * pitch + x] : 0ull;
-    }
+  for (int c = 0; c < CH; ++c) {
+    const int m = 64 * c + lane, x = x_first + m;
+    const bool ok = row_ok && m < sw && x >= 0 && x < W;
+    w[c] = img[ok ? (size_t)y * pitch + x : 0];
+    w[c] = ok ? w[c] : 0ull;
   }
+}
+
+template <int CH>
+__device__ __forceinline__ void store_row_dy(uint64_t* __restrict__ slot, const uint64_t (&w)[CH],
+                                             int SWr, int lane) {
+#pragma unroll
+  for (int c = 0; c < CH; ++c)
+    if (64 * c + lane < SWr) slot[64 * c + lane] = w[c];
+}
+
+// One direction's search over every (d, e): rows y_top + t + jj for steps t = 0 .. ndy-1,
+// strip columns from x_first. Step t is vertical index e = (fwd ? t : ndy - 1 - t); strip
+// position q is candidate index (fwd ? nd - 1 - q : q). Returns the lane's least key
+// (cost << 16 | (d index * ndy + e)); costs go to cost[d index * ndy + e].
+template <int ROWS, int NX, int CPL, int CH>
+__device__ __forceinline__ uint32_t search_dy(const uint64_t (&t)[NX], uint64_t* __restrict__ S,
+                                              int SWr, int passes, const uint64_t* __restrict__ img,
+                                              int pitch, int W, int H, int x_first, int y_top,
+                                              int ny, int sw, int nd, int ndy, bool fwd,
+                                              uint32_t rowmask, uint32_t col_all, uint32_t col_any,
+                                              uint16_t* __restrict__ cost, int lane) {
+  constexpr int NR = ROWS + 1;
+  constexpr int PC = (64 / ROWS) * CPL;
+  static_assert(PC == kDyPass, "a pass covers kDyPass candidates");
+  const int j = lane % ROWS, grp = lane / ROWS;
+  {
+    // rows 0 .. ROWS - 1, every load issued before the first store
+    uint64_t w[ROWS][CH];
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) load_row_dy<CH>(w[r], img, pitch, W, H, x_first, y_top + r, sw, lane);
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) store_row_dy<CH>(S + r * SWr, w[r], SWr, lane);
+  }
+  wave_sync();
+  uint32_t key = 0xFFFFFFFFu;
+  uint32_t acc[CPL];
+  for (int st = 0; st < ndy; ++st) {
+    const bool more = st + 1 < ndy;
+    uint64_t pre[CH];
+    if (more) load_row_dy<CH>(pre, img, pitch, W, H, x_first, y_top + st + ROWS, sw, lane);
+    const int e = fwd ? st : ndy - 1 - st;
+    const uint64_t* srow = S + ((st + j) % NR) * SWr;
+    for (int ps = 0; ps < passes; ++ps) {
+      if (j < ny) row_costs<NX, CPL>(t, srow + ps * PC + grp * CPL, rowmask, col_all, col_any, acc);
+#pragma unroll
+      for (int cc = 0; cc < CPL; ++cc)
+        if (j >= ny) acc[cc] = 0;
+#pragma unroll
+      for (int cc = 0; cc < CPL; ++cc) {
+        const uint32_t tot = row_sum<ROWS>(acc[cc]);
+        const int q = ps * PC + grp * CPL + cc;
+        if (q < nd) {
+          const int id = (fwd ? nd - 1 - q : q) * ndy + e;
+          key = min(key, (tot << 16) | (uint32_t)id);
+          if (j == 0) cost[id] = (uint16_t)tot;
+        }
+      }
+    }
+    // the slot of row st - 1, which step st does not read
+    if (more) store_row_dy<CH>(S + ((st + ROWS) % NR) * SWr, pre, SWr, lane);
+    wave_sync();
+  }
+  return key;
 }
 
 template <int ROWS, int NX>
 __device__ __forceinline__ void match_block_dy(const MatchParamsDev& P, const FrameDev& fr,
                                                const MatchWs& ws, const DebugDev& dbg,
                                                const BlockCtx& c, int lane, void* lds) {
-  constexpr int CPL = kDyCpl;
-  constexpr int G = 64 / ROWS;
-  constexpr int PC = G * CPL;   // candidates of one pass
+  constexpr int CPL = dy_cpl(ROWS);
+  constexpr int CH = dy_chunks(ROWS);
   const LevelDev& lv = fr.lv[c.level];
   const PathDev& ph = P.path[c.level];
   const int nd = ph.nd, dlo = ph.dlo, dhi = dlo + nd - 1;
   const int ndy = ph.ndy, dylo = ph.dylo;
-  const int passes = (nd + PC - 1) / PC;
-  const int SWr = passes * PC + NX - 1;        // strip row stride (words)
+  const int passes = (nd + kDyPass - 1) / kDyPass;
+  const int SWr = passes * kDyPass + NX - 1;   // strip row stride (words)
   const int sw = nd + NX - 1;                  // words a row's candidates read
   auto r16 = [](size_t v) { return (v + 15) & ~(size_t)15; };
   uint64_t* S = (uint64_t*)lds;
-  uint64_t* T = (uint64_t*)((char*)lds + r16(sizeof(uint64_t) * ROWS * SWr));
+  uint64_t* T = (uint64_t*)((char*)lds + r16(sizeof(uint64_t) * (ROWS + 1) * SWr));
   uint16_t* costf = (uint16_t*)((char*)T + r16(sizeof(uint64_t) * ROWS * NX));
   uint16_t* costb = (uint16_t*)((char*)costf + r16(sizeof(uint16_t) * (size_t)nd * ndy));
-  const int j = lane % ROWS, grp = lane / ROWS;
+  const int j = lane % ROWS;
   const int nx = c.g.nx, ny = c.g.ny;
   const int X0 = c.g.cx, Y0 = c.g.cy;
 
@@ -575,31 +637,11 @@ __device__ __forceinline__ void match_block_dy(const MatchParamsDev& P, const Fr
   uint64_t t[NX];
 #pragma unroll
   for (int i = 0; i < NX; ++i) t[i] = T[j * NX + i];
-  uint32_t acc[CPL];
-  // forward: for offset e the strip row jj holds CR(X0 - dhi + m, Y0 + e + jj); entry
-  // q + i of candidate position q holds CR(X0 + i - d) for d = dhi - q
-  uint32_t key = 0xFFFFFFFFu;
-  for (int ey = 0; ey < ndy; ++ey) {
-    stage_rows_dy<ROWS>(S, SWr, lv.R, lv.pitch, lv.W, lv.H, X0 - dhi, Y0 + dylo + ey, ny, sw, lane);
-    wave_sync();
-    for (int ps = 0; ps < passes; ++ps) {
-      if (j < ny) row_costs<NX, CPL>(t, S + j * SWr + ps * PC + grp * CPL, rowmask, col_all, col_any, acc);
-#pragma unroll
-      for (int cc = 0; cc < CPL; ++cc)
-        if (j >= ny) acc[cc] = 0;
-#pragma unroll
-      for (int cc = 0; cc < CPL; ++cc) {
-        const uint32_t tot = row_sum<ROWS>(acc[cc]);
-        const int q = ps * PC + grp * CPL + cc;
-        if (q < nd) {
-          const int id = (nd - 1 - q) * ndy + ey;   // (d index, e index), d major
-          key = min(key, (tot << 16) | (uint32_t)id);
-          if (j == 0) costf[id] = (uint16_t)tot;
-        }
-      }
-    }
-    wave_sync();
-  }
+  // forward: strip row of step e holds CR(X0 - dhi + m, Y0 + dylo + e + jj); entry q + i
+  // holds CR(X0 + i - d) for d = dhi - q
+  uint32_t key = search_dy<ROWS, NX, CPL, CH>(t, S, SWr, passes, lv.R, lv.pitch, lv.W, lv.H,
+                                               X0 - dhi, Y0 + dylo, ny, sw, nd, ndy, true,
+                                               rowmask, col_all, col_any, costf, lane);
   key = wave_min_u32(key, ROWS);
   const int best_id = (int)(key & 0xFFFFu);
   const int kf = best_id / ndy, ef = best_id - kf * ndy;
@@ -615,33 +657,16 @@ __device__ __forceinline__ void match_block_dy(const MatchParamsDev& P, const Fr
     for (int i = 0; i < NX; ++i) {
       const int x = X0 - d_f + i;
       const bool ok = row_ok && i < nx && x >= 0 && x < lv.W;
-      t[i] = ok ? lv.R[(size_t)y * lv.pitch + x] : 0ull;
+      t[i] = lv.R[ok ? (size_t)y * lv.pitch + x : 0];
+      t[i] = ok ? t[i] : 0ull;
     }
   }
-  // backward: for offset e the strip row jj holds CL(X0 - d_f + dlo + m, Y0 + dy_f - e + jj)
-  uint32_t bkey = 0xFFFFFFFFu;
-  for (int ey = 0; ey < ndy; ++ey) {
-    stage_rows_dy<ROWS>(S, SWr, lv.L, lv.pitch, lv.W, lv.H, X0 - d_f + dlo, Y0 + dy_f - (dylo + ey),
-                        ny, sw, lane);
-    wave_sync();
-    for (int ps = 0; ps < passes; ++ps) {
-      if (j < ny) row_costs<NX, CPL>(t, S + j * SWr + ps * PC + grp * CPL, rowmask, col_all, col_any, acc);
-#pragma unroll
-      for (int cc = 0; cc < CPL; ++cc)
-        if (j >= ny) acc[cc] = 0;
-#pragma unroll
-      for (int cc = 0; cc < CPL; ++cc) {
-        const uint32_t tot = row_sum<ROWS>(acc[cc]);
-        const int q = ps * PC + grp * CPL + cc;   // candidate dlo + q
-        if (q < nd) {
-          const int id = q * ndy + ey;
-          bkey = min(bkey, (tot << 16) | (uint32_t)id);
-          if (j == 0) costb[id] = (uint16_t)tot;
-        }
-      }
-    }
-    wave_sync();
-  }
+  // backward: offset e reads CL(X0 - d_f + dlo + m, Y0 + dy_f - dylo - e + jj); the steps
+  // run e from the last offset down, so that the rows move down by one per step
+  uint32_t bkey = search_dy<ROWS, NX, CPL, CH>(t, S, SWr, passes, lv.L, lv.pitch, lv.W, lv.H,
+                                                X0 - d_f + dlo, Y0 + dy_f - dylo - (ndy - 1), ny,
+                                                sw, nd, ndy, false, rowmask, col_all, col_any,
+                                                costb, lane);
   bkey = wave_min_u32(bkey, ROWS);
   const int bid = (int)(bkey & 0xFFFFu);
   const int kb = bid / ndy, eb = bid - kb * ndy;

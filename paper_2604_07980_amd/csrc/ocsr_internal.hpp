@@ -74,20 +74,20 @@ struct MatchParamsDev {
 };
 
 // Kernel of a path with a vertical range: one wave per block, NX x ROWS points, lanes
-// (row, group of kDyCpl consecutive candidates), the candidates in runtime passes of
-// (64 / ROWS) * kDyCpl; per wave an LDS strip of ROWS rows x dy_strip_words words, the
-// template, and the forward and backward costs of every (d, dy) as uint16.
-constexpr int kDyCpl = 4;
+// (row, group of dy_cpl(ROWS) consecutive candidates), the candidates in runtime passes
+// of kDyPass; per wave an LDS ring of ROWS + 1 strip rows of dy_strip_words words (each
+// vertical step loads one new row), the template, and the forward and backward costs of
+// every (d, dy) as uint16. A strip row is loaded in at most dy_chunks(ROWS) 64-word
+// chunks per lane.
+constexpr int kDyPass = 32;
 inline int dy_rows(int bw, int bh) { return bw <= 4 && bh <= 4 ? 4 : 8; }
-inline int dy_passes(int rows, int nd) {
-  const int pc = (64 / rows) * kDyCpl;
-  return (nd + pc - 1) / pc;
-}
-inline int dy_strip_words(int rows, int nd) { return dy_passes(rows, nd) * (64 / rows) * kDyCpl + rows - 1; }
+constexpr int dy_cpl(int rows) { return rows == 4 ? 2 : 4; }
+constexpr int dy_chunks(int rows) { return rows == 4 ? 5 : 3; }
+inline int dy_strip_words(int rows, int nd) { return (nd + kDyPass - 1) / kDyPass * kDyPass + rows - 1; }
 inline size_t dy_wave_lds_bytes(int rows, int nd, int ndy) {
   auto r16 = [](size_t v) { return (v + 15) & ~(size_t)15; };
-  return r16(sizeof(uint64_t) * rows * dy_strip_words(rows, nd)) + r16(sizeof(uint64_t) * rows * rows) +
-         2 * r16(sizeof(uint16_t) * (size_t)nd * ndy);
+  return r16(sizeof(uint64_t) * (rows + 1) * dy_strip_words(rows, nd)) +
+         r16(sizeof(uint64_t) * rows * rows) + 2 * r16(sizeof(uint16_t) * (size_t)nd * ndy);
 }
 constexpr size_t kDyMaxWgLds = 65536;   // LDS of one dy workgroup (kItemWaves waves)
 
