@@ -468,6 +468,30 @@ def main():
     points = {"boxes": int(n), "valid": int(ocsr.points_to_numpy(pts)["valid"].sum()),
               "us_per_call": round(1e3 * ptot / max(pcnt, 1), 3)}
 
+    # priority selection under a budget of 20 objects (a step before ranging): kernel time
+    # on the frame's 64 boxes and on a 16-frame call of 1000 boxes each
+    sel_out, sel_rank = ocsr.select_boxes([(W, H, n)], boxes, 20)
+    rng = np.random.default_rng(77)
+    bx0 = rng.integers(-80, W, 16000)
+    by0 = rng.integers(-80, H, 16000)
+    many = torch.from_numpy(np.stack([bx0, by0, bx0 + rng.integers(1, 400, 16000),
+                                      by0 + rng.integers(1, 300, 16000), np.ones(16000, int)],
+                                     1).astype(np.int32)).to(dev)
+    many_out, many_rank = ocsr.select_boxes([(W, H, 1000)] * 16, many, 20)
+    select = {"budget": 20}
+    for key, frames_, bx, o, r in (("frame_64_boxes", [(W, H, n)], boxes, sel_out, sel_rank),
+                                   ("16_frames_1000_boxes", [(W, H, 1000)] * 16, many, many_out,
+                                    many_rank)):
+        ocsr.reset_timing()
+        ocsr.set_timing(True)
+        for _ in range(args.steps):
+            ocsr.select_boxes(frames_, bx, 20, out=o, rank=r)
+        torch.cuda.synchronize()
+        ocsr.set_timing(False)
+        scnt, stot = ocsr.kernel_time("select")
+        select[key] = {"us_per_call": round(1e3 * stot / max(scnt, 1), 3)}
+    select["frame_64_boxes"]["kept"] = int(((sel_out[:, 4] & 1) == 1).sum().item())
+
     # algorithmic work per launch: census = informative comparisons (the centre term
     # is constant); match = 4 int32 ops per 64-bit Hamming cost
     census_ops = census_px * (census_bits - 1) * CENSUS_OPS_PER_CMP
@@ -519,6 +543,7 @@ def main():
                     for k, v in kern.items()},
         "roofline": roofline,
         "points": points,
+        "select": select,
     }
     if args.vertical_steps > 0:
         res["vertical"] = vertical_section(ocsr, synth, args.vertical_steps, max(3, args.warmup // 10))

@@ -342,6 +342,36 @@ int32_t ocsr_range_batch(ocsr_ctx* ctx, const ocsr_frame* frames, int32_t n_fram
                          size_t ws_bytes, ocsr_box_result* out, void* stream);
 
 /* ------------------------------------------------------------------------------ */
+/* Priority object selection under a budget (Sec. 4.3.5, last sentence)           */
+/* ------------------------------------------------------------------------------ */
+/* When a frame has more candidate objects than the budget, the frontal ones (in a
+ * central crop) are ranged first and the remaining slots go to the others by
+ * proximity. A candidate is a box with OCSR_BOX_RANGE whose clipped area is not empty.
+ * Candidates are ordered by the key (not frontal, larger clipped bottom y first, lower
+ * box index first): a larger bottom y is nearer the camera, the cue the occlusion rule
+ * uses. Frontal: the centre of the clipped box, ((cx0 + cx1 - 1)/2, (cy0 + cy1 - 1)/2),
+ * lies in the crop [floor(W x0/1000), floor(W x1/1000)) x [floor(H y0/1000),
+ * floor(H y1/1000)), given in permille of the frame size. */
+typedef struct {
+  int32_t max_objects;        /* budget per frame: candidates kept ranged, >= 0 */
+  int32_t crop_permille[4];   /* x0, y0, x1, y1; 0 <= x0 <= x1 <= 1000, same for y */
+} ocsr_select_params;
+
+/* Most boxes of one frame ocsr_select_boxes takes. */
+#define OCSR_MAX_SELECT_BOXES 16384
+
+/* frames (host): n_frames descriptions; only width, height, box_offset and n_boxes are
+ * read (images may be NULL). in (dev): the frames' boxes. out (dev): the same boxes,
+ * each candidate whose rank is >= max_objects with OCSR_BOX_RANGE cleared (it still
+ * occludes); every other field and box as in `in`. out must not overlap in. rank (dev,
+ * nullable): int32 per box, the candidate's rank in its frame (0 first), -1 for boxes
+ * that are not candidates. n_boxes per frame <= OCSR_MAX_SELECT_BOXES, else
+ * OCSR_E_CAPACITY. */
+int32_t ocsr_select_boxes(ocsr_ctx* ctx, const ocsr_frame* frames, int32_t n_frames,
+                          const ocsr_box* in, const ocsr_select_params* params, ocsr_box* out,
+                          int32_t* rank, void* stream);
+
+/* ------------------------------------------------------------------------------ */
 /* Dense counterpart                                                                */
 /* ------------------------------------------------------------------------------ */
 /* Not part of the paper's method: the dense matcher the object-centric path is
@@ -439,7 +469,8 @@ int32_t ocsr_ctx_graph_stats(ocsr_ctx* ctx, int64_t* hits, int64_t* builds);
  * match_close and match_far (one launch per level, when no kernel for the pair of
  * variants is built), aggregate, reset and fused (the persistent launch), graph (one
  * replay of a whole-frame or batch call with OCSR_OPTION_GRAPH on), dense and
- * dense_check (the dense counterpart), points (ocsr_box_points). */
+ * dense_check (the dense counterpart), points (ocsr_box_points), select
+ * (ocsr_select_boxes). */
 int32_t ocsr_ctx_set_timing(ocsr_ctx* ctx, int32_t enable);
 int32_t ocsr_ctx_kernel_time(ocsr_ctx* ctx, const char* kernel, int64_t* launches,
                              double* total_ms);

@@ -18,6 +18,7 @@
  *   depth ............. Eq. 1 (Z = f b / d), and d_full = s d_down (Sec. 4.1)
  *   3D point .......... Sec. 4.3.6, Q-matrix equation, then T_cam->imu
  *   covariance ........ Sec. 4.3.7, depth-variance and rotation equations
+ *   object budget ..... Sec. 4.3.5, last sentence (frontal first, then proximity)
  */
 #include "ocsr_oracle.h"
 
@@ -560,4 +561,50 @@ void orc_box_points(const int32_t* boxes, const orc_box_result* res, int32_t n, 
     }
     out[i] = o;
   }
+}
+
+/* ------------------------------------------------------------------------------ */
+/* Priority object selection (Sec. 4.3.5, last sentence): sort the candidates and   */
+/* keep the first max_objects.                                                      */
+/* ------------------------------------------------------------------------------ */
+typedef struct {
+  int frontal;   /* 1: clipped centre inside the central crop */
+  int bottom;    /* clipped bottom y: larger is nearer */
+  int index;
+} sel_t;
+
+static int cmp_sel(const void* a, const void* b) {
+  const sel_t* p = (const sel_t*)a;
+  const sel_t* q = (const sel_t*)b;
+  if (p->frontal != q->frontal) return q->frontal - p->frontal;   /* frontal first */
+  if (p->bottom != q->bottom) return q->bottom - p->bottom;       /* nearer first */
+  return p->index - q->index;
+}
+
+void orc_select_boxes(const int32_t* boxes, int32_t n, int32_t W, int32_t H, int32_t max_objects,
+                      const int32_t* crop_permille, int32_t* flags_out, int32_t* rank) {
+  /* the crop in px: floor of the permille fractions of the frame size */
+  long cx0 = (long)W * crop_permille[0] / 1000, cy0 = (long)H * crop_permille[1] / 1000;
+  long cx1 = (long)W * crop_permille[2] / 1000, cy1 = (long)H * crop_permille[3] / 1000;
+  sel_t* c = (sel_t*)malloc(sizeof(sel_t) * (size_t)(n > 0 ? n : 1));
+  int m = 0;
+  for (int i = 0; i < n; ++i) {
+    const int32_t* b = boxes + 5 * i;
+    flags_out[i] = b[4];
+    rank[i] = -1;
+    int x0 = imax(b[0], 0), y0 = imax(b[1], 0), x1 = imin(b[2], W), y1 = imin(b[3], H);
+    if (!(b[4] & 1) || !(x0 < x1 && y0 < y1)) continue;
+    /* centre of the clipped box in pixel-index coordinates */
+    double u = (x0 + x1 - 1) / 2.0, v = (y0 + y1 - 1) / 2.0;
+    c[m].frontal = u >= cx0 && u < cx1 && v >= cy0 && v < cy1;
+    c[m].bottom = y1;
+    c[m].index = i;
+    ++m;
+  }
+  qsort(c, (size_t)m, sizeof(sel_t), cmp_sel);
+  for (int k = 0; k < m; ++k) {
+    rank[c[k].index] = k;
+    if (k >= max_objects) flags_out[c[k].index] &= ~1;
+  }
+  free(c);
 }

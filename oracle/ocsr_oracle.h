@@ -59,6 +59,14 @@ typedef struct {
   int32_t dy_f, dy_b;              /* level vertical offsets of the two winners */
 } orc_block;
 
+/* Priority object selection under a budget (Sec. 4.3.5, last sentence). boxes: int32
+ * [n][5] of one W x H frame. A candidate has flag bit 0 and a non-empty clipped box.
+ * Candidates are sorted frontal first (clipped centre in the crop, given in permille of
+ * W and H), then by larger clipped bottom y, then by index; the first max_objects keep
+ * bit 0. flags_out: [n] new flags; rank: [n] position in that order, -1 if no candidate. */
+void orc_select_boxes(const int32_t* boxes, int32_t n, int32_t W, int32_t H, int32_t max_objects,
+                      const int32_t* crop_permille, int32_t* flags_out, int32_t* rank);
+
 /* Census of one level: out is [H/s][W/s] row-major, pitch W/s. Returns 0, or -1
  * when the window does not fit in 64 bits or an argument is out of range. */
 int32_t orc_census(const uint8_t* img, int32_t W, int32_t H, int32_t pitch,

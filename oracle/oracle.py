@@ -78,6 +78,8 @@ def lib():
         d = C.c_double
         L.orc_box_points.argtypes = [vp, vp, i32, i32, i32, vp, vp, vp, d, d, d, d, d, vp]
         L.orc_box_points.restype = None
+        L.orc_select_boxes.argtypes = [vp, i32, i32, i32, i32, vp, vp, vp]
+        L.orc_select_boxes.restype = None
         _lib = L
     return _lib
 
@@ -220,3 +222,17 @@ def dense_at(CL, CR, xy, dmin=0, dmax=191, radius=2, lr_tol=1, threads=0):
     if rc != 0:
         raise ValueError("orc_dense_at rejected its arguments")
     return out
+
+
+def select_boxes(boxes, W: int, H: int, max_objects: int, crop_permille=(333, 0, 667, 1000)):
+    """Priority selection of one frame's boxes (Sec. 4.3.5, last sentence). Returns (boxes
+    with the new flags, rank per box, -1 for non-candidates)."""
+    boxes = np.ascontiguousarray(boxes, dtype=np.int32).reshape(-1, 5)
+    n = boxes.shape[0]
+    flags = np.zeros(n, np.int32)
+    rank = np.zeros(n, np.int32)
+    crop = np.ascontiguousarray(crop_permille, dtype=np.int32)
+    lib().orc_select_boxes(_ptr(boxes), n, W, H, max_objects, _ptr(crop), _ptr(flags), _ptr(rank))
+    out = boxes.copy()
+    out[:, 4] = flags
+    return out, rank

@@ -503,6 +503,55 @@ int32_t ocsr_census(ocsr_ctx* ctx, const uint8_t* img, int32_t width, int32_t he
                         (hipStream_t)stream, ctx->timing ? &t : nullptr);
 }
 
+int32_t ocsr_select_boxes(ocsr_ctx* ctx, const ocsr_frame* frames, int32_t n_frames,
+                          const ocsr_box* in, const ocsr_select_params* params, ocsr_box* out,
+                          int32_t* rank, void* stream) {
+  g_last_error.clear();
+  if (!ctx || !params) return fail(OCSR_E_INVALID, "null context or select params");
+  if (!frames || n_frames < 1 || n_frames > OCSR_MAX_BATCH_FRAMES)
+    return fail(OCSR_E_INVALID, "n_frames %d outside 1..%d", n_frames, OCSR_MAX_BATCH_FRAMES);
+  if (params->max_objects < 0) return fail(OCSR_E_INVALID, "max_objects %d < 0", params->max_objects);
+  const int32_t* c = params->crop_permille;
+  if (c[0] < 0 || c[1] < 0 || c[0] > c[2] || c[1] > c[3] || c[2] > 1000 || c[3] > 1000)
+    return fail(OCSR_E_INVALID, "crop [%d, %d) x [%d, %d) permille outside 0..1000", c[0], c[2], c[1], c[3]);
+  SelectDev S;
+  memset(&S, 0, sizeof(S));
+  S.n = n_frames;
+  S.max_objects = params->max_objects;
+  long long total = 0;
+  int max_boxes = 0;
+  for (int f = 0; f < n_frames; ++f) {
+    const ocsr_frame& fr = frames[f];
+    if (fr.width <= 0 || fr.height <= 0 || fr.width > (1 << 15) || fr.height > (1 << 15))
+      return fail(OCSR_E_INVALID, "frame %d: size %dx%d outside 1..32768", f, fr.width, fr.height);
+    if (fr.n_boxes < 0 || fr.box_offset != total)
+      return fail(OCSR_E_INVALID, "frame %d: boxes must follow the previous frame's (offset %d, expected %lld)",
+                  f, fr.box_offset, total);
+    if (fr.n_boxes > OCSR_MAX_SELECT_BOXES)
+      return fail(OCSR_E_CAPACITY, "frame %d: %d boxes > %d", f, fr.n_boxes, OCSR_MAX_SELECT_BOXES);
+    SelectFrameDev& d = S.f[f];
+    d.W = fr.width;
+    d.H = fr.height;
+    d.X0 = (int)((long long)fr.width * c[0] / 1000);
+    d.Y0 = (int)((long long)fr.height * c[1] / 1000);
+    d.X1 = (int)((long long)fr.width * c[2] / 1000);
+    d.Y1 = (int)((long long)fr.height * c[3] / 1000);
+    d.box_off = fr.box_offset;
+    d.n_boxes = fr.n_boxes;
+    total += fr.n_boxes;
+    max_boxes = std::max(max_boxes, fr.n_boxes);
+  }
+  if (total == 0) return OCSR_OK;
+  if (!in || !out) return fail(OCSR_E_INVALID, "null boxes");
+  const uintptr_t a0 = (uintptr_t)in, a1 = a0 + (size_t)total * sizeof(ocsr_box);
+  const uintptr_t b0 = (uintptr_t)out, b1 = b0 + (size_t)total * sizeof(ocsr_box);
+  if (a0 < b1 && b0 < a1) return fail(OCSR_E_INVALID, "out overlaps in");
+  LaunchTimer t = make_timer(ctx);
+  const hipError_t e = launch_select(S, in, out, rank, max_boxes, (hipStream_t)stream,
+                                     ctx->timing ? &t : nullptr);
+  return e == hipSuccess ? OCSR_OK : hip_fail(e, "select launch");
+}
+
 int32_t ocsr_box_points(ocsr_ctx* ctx, const ocsr_box* boxes, const ocsr_box_result* results,
                         int32_t n_boxes, const ocsr_point_params* pp, ocsr_box_point* out,
                         void* stream) {

@@ -244,6 +244,19 @@ struct PointParamsDev {
   float fb;                        // f * b, one fp32 multiply
   float var_d, var_x, var_y;
 };
+// Priority object selection: per frame its size, crop in px and box range.
+struct SelectFrameDev {
+  int32_t W, H, X0, Y0, X1, Y1;
+  int32_t box_off, n_boxes;
+};
+struct SelectDev {
+  int32_t n;
+  int32_t max_objects;
+  SelectFrameDev f[OCSR_MAX_BATCH_FRAMES];
+};
+hipError_t launch_select(const SelectDev& S, const ocsr_box* in, ocsr_box* out, int32_t* rank,
+                         int max_boxes, hipStream_t stream, const LaunchTimer* timer);
+
 hipError_t launch_box_points(const ocsr_box* boxes, const ocsr_box_result* res, int n,
                              const PointParamsDev& pp, ocsr_box_point* out, hipStream_t stream,
                              const LaunchTimer* timer);

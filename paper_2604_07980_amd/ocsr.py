@@ -28,6 +28,7 @@ MAX_BLOCKS_PER_BOX = 4096
 MAX_BATCH_FRAMES = 16
 MAX_CANDIDATES = 256
 MAX_DY = 32
+MAX_SELECT_BOXES = 16384
 MAX_DY_CANDIDATES = 2048
 MAX_CENSUS_JOBS = 64
 DEFAULT_CAP_BLOCKS = 1 << 20
@@ -41,7 +42,7 @@ EXPORTS = ["ocsr_abi_version", "ocsr_last_error", "ocsr_ctx_create", "ocsr_ctx_d
            "ocsr_range_batch", "ocsr_ctx_set_option", "ocsr_ctx_set_timing",
            "ocsr_ctx_kernel_time", "ocsr_ctx_reset_timing", "ocsr_ctx_graph_stats",
            "ocsr_variant_candidates", "ocsr_ctx_set_variant", "ocsr_dense_workspace_bytes",
-           "ocsr_dense_match", "ocsr_box_points"]
+           "ocsr_dense_match", "ocsr_box_points", "ocsr_select_boxes"]
 
 
 class OcsrError(RuntimeError):
@@ -84,6 +85,10 @@ class MatchParams(C.Structure):
 class FrameParams(C.Structure):
     _fields_ = [("sx", C.c_int32), ("sy", C.c_int32), ("sentinel", C.c_int32),
                 ("close_scale", C.c_int32)]
+
+
+class SelectParams(C.Structure):
+    _fields_ = [("max_objects", C.c_int32), ("crop_permille", C.c_int32 * 4)]
 
 
 class Frame(C.Structure):
@@ -183,6 +188,8 @@ def load(path: str = LIB_PATH):
         L.ocsr_dense_match.restype = i32
         L.ocsr_box_points.argtypes = [vp, vp, vp, i32, C.POINTER(PointParams), vp, vp]
         L.ocsr_box_points.restype = i32
+        L.ocsr_select_boxes.argtypes = [vp, vp, i32, vp, C.POINTER(SelectParams), vp, vp, vp]
+        L.ocsr_select_boxes.restype = i32
         _lib = L
         return L
 
@@ -498,6 +505,40 @@ def box_points(boxes: torch.Tensor, results: torch.Tensor, geom: dict,
     _check(load().ocsr_box_points(context(boxes.device.index), _dptr(boxes), _dptr(results), n,
                                   C.byref(pp), _dptr(out), _stream(boxes.device)))
     return out
+
+
+# Central crop of the selection when none is given: the middle third of the width over
+# the full height (the paper leaves the crop's size open).
+DEFAULT_CROP_PERMILLE = (333, 0, 667, 1000)
+
+
+def select_boxes(frames, boxes: torch.Tensor, max_objects: int,
+                 crop_permille=DEFAULT_CROP_PERMILLE, out: torch.Tensor | None = None,
+                 rank: torch.Tensor | None = None):
+    """Priority selection under a per-frame budget. frames: list of (width, height,
+    n_boxes), boxes int32 [sum n_boxes, 5] cuda, frame by frame. Returns (boxes with the
+    range flag cleared on the candidates past the budget, int32 [N] rank per box, -1 for
+    non-candidates)."""
+    if not frames or len(frames) > MAX_BATCH_FRAMES:
+        raise ValueError(f"1..{MAX_BATCH_FRAMES} frames per call")
+    _need_cuda(boxes)
+    if boxes.dtype != torch.int32 or boxes.dim() != 2 or boxes.shape[1] != 5 or not boxes.is_contiguous():
+        raise ValueError("boxes must be a contiguous int32 [N, 5] tensor")
+    arr = (Frame * len(frames))()
+    off = 0
+    for k, (W, H, nb) in enumerate(frames):
+        arr[k] = Frame(None, None, int(W), int(H), int(W), off, int(nb), 0)
+        off += int(nb)
+    if off != boxes.shape[0]:
+        raise ValueError("box counts of the frames do not add up to the box array")
+    if out is None:
+        out = torch.empty_like(boxes)
+    if rank is None:
+        rank = torch.empty(boxes.shape[0], dtype=torch.int32, device=boxes.device)
+    sp = SelectParams(int(max_objects), (C.c_int32 * 4)(*[int(v) for v in crop_permille]))
+    _check(load().ocsr_select_boxes(context(boxes.device.index), arr, len(frames), _dptr(boxes),
+                                    C.byref(sp), _dptr(out), _dptr(rank), _stream(boxes.device)))
+    return out, rank
 
 
 def points_to_numpy(pts: torch.Tensor) -> np.ndarray:
