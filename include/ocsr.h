@@ -393,6 +393,50 @@ int32_t ocsr_dense_match(ocsr_ctx* ctx, const ocsr_level* lv, int32_t dmin, int3
                          void* ws, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------------ */
+/* Auto-rectification offset (Sec. 5.1)                                             */
+/* ------------------------------------------------------------------------------ */
+/* For every integer vertical offset delta in [delta_min, delta_max] the dense matcher
+ * above runs on a region of interest whose left descriptors are moved down by delta:
+ * the pair (CL(roi_x0 + x, roi_y0 + y - delta), CR(roi_x0 + x, roi_y0 + y)) for
+ * 0 <= x < roi_w, 0 <= y < roi_h, its windows clipped to the ROI. counts[k] is the
+ * number of ROI pixels whose checked disparity is > d_min at delta = delta_min + k: the
+ * quantity the offset search maximises (Sec. 5.1, offset equation). The paper's
+ * matcher there is block matching; this library's dense census matcher stands in for
+ * it. The paper runs one stream per offset; here every offset is one slice of the same
+ * launches. */
+typedef struct {
+  int32_t roi_x0, roi_y0, roi_w, roi_h;   /* level px; rows roi_y0 - delta must stay inside */
+  int32_t delta_min, delta_max;           /* level px, delta_max - delta_min < OCSR_MAX_RECT_OFFSETS */
+  int32_t dmin, dmax, radius, lr_tol;     /* the dense matcher's range, window, L/R tolerance */
+  int32_t d_min;                          /* >= 0: pixels with disparity > d_min count */
+} ocsr_rect_params;
+#define OCSR_MAX_RECT_OFFSETS 64
+
+/* Bytes of the workspace of ocsr_rect_offset_counts (0 if p is invalid). */
+size_t ocsr_rect_workspace_bytes(const ocsr_rect_params* p);
+/* lv (host struct, dev descriptors): one level; the ROI moved by every offset lies inside
+ * it (else OCSR_E_INVALID). counts (dev): int32 [n_offsets]. disp (dev, nullable): int16
+ * [n_offsets][roi_h][roi_w], the checked disparity maps (-1: invalid). */
+int32_t ocsr_rect_offset_counts(ocsr_ctx* ctx, const ocsr_level* lv, const ocsr_rect_params* p,
+                                int32_t* counts, int16_t* disp, void* ws, size_t ws_bytes,
+                                void* stream);
+
+/* The per-frame estimate and its temporal filter (Sec. 5.1, filter equations), on the
+ * host. The estimate delta* is the offset of the largest count; ties go to the smallest
+ * |delta|, then to the smaller delta. The filter keeps the last `window` estimates; its
+ * output moves from the previous output towards their median (the lower middle value
+ * of an even count) by at most max_step per frame. The first previous output is
+ * `initial`. */
+typedef struct ocsr_rect_filter ocsr_rect_filter;
+int32_t ocsr_rect_filter_create(int32_t window, int32_t max_step, int32_t initial,
+                                ocsr_rect_filter** out);
+void ocsr_rect_filter_destroy(ocsr_rect_filter* f);
+/* counts (host): n_offsets counts of one frame for offsets delta_min, delta_min + 1, ...
+ * Writes the frame's estimate to *raw and the filtered offset to *filtered. */
+int32_t ocsr_rect_filter_update(ocsr_rect_filter* f, const int32_t* counts, int32_t n_offsets,
+                                int32_t delta_min, int32_t* raw, int32_t* filtered);
+
+/* ------------------------------------------------------------------------------ */
 /* Options and timing                                                               */
 /* ------------------------------------------------------------------------------ */
 /* OCSR_OPTION_FUSED: 0 (default) runs whole frames and batches as the multi-launch
@@ -470,7 +514,7 @@ int32_t ocsr_ctx_graph_stats(ocsr_ctx* ctx, int64_t* hits, int64_t* builds);
  * variants is built), aggregate, reset and fused (the persistent launch), graph (one
  * replay of a whole-frame or batch call with OCSR_OPTION_GRAPH on), dense and
  * dense_check (the dense counterpart), points (ocsr_box_points), select
- * (ocsr_select_boxes). */
+ * (ocsr_select_boxes), rect_dense and rect_count (ocsr_rect_offset_counts). */
 int32_t ocsr_ctx_set_timing(ocsr_ctx* ctx, int32_t enable);
 int32_t ocsr_ctx_kernel_time(ocsr_ctx* ctx, const char* kernel, int64_t* launches,
                              double* total_ms);

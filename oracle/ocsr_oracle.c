@@ -19,6 +19,7 @@
  *   3D point .......... Sec. 4.3.6, Q-matrix equation, then T_cam->imu
  *   covariance ........ Sec. 4.3.7, depth-variance and rotation equations
  *   object budget ..... Sec. 4.3.5, last sentence (frontal first, then proximity)
+ *   rectification ..... Sec. 5.1, offset equation and filter equations
  */
 #include "ocsr_oracle.h"
 
@@ -607,4 +608,80 @@ void orc_select_boxes(const int32_t* boxes, int32_t n, int32_t W, int32_t H, int
     if (k >= max_objects) flags_out[c[k].index] &= ~1;
   }
   free(c);
+}
+
+/* ------------------------------------------------------------------------------ */
+/* Auto-rectification offset (Sec. 5.1): move the left image's rows by delta, run  */
+/* the dense matcher over the ROI, count the disparities above d_min; then argmax   */
+/* over delta and the temporal median filter with a clamped step.                   */
+/* ------------------------------------------------------------------------------ */
+int32_t orc_rect_counts(const uint64_t* CL, const uint64_t* CR, int32_t W, int32_t H,
+                        int32_t roi_x0, int32_t roi_y0, int32_t roi_w, int32_t roi_h,
+                        int32_t delta_min, int32_t delta_max, int32_t dmin, int32_t dmax,
+                        int32_t radius, int32_t lr_tol, int32_t d_min, int32_t* counts,
+                        int16_t* maps, int32_t n_threads) {
+  if (roi_w <= 0 || roi_h <= 0 || delta_min > delta_max || roi_x0 < 0 || roi_x0 + roi_w > W ||
+      roi_y0 - delta_max < 0 || roi_y0 + roi_h - delta_min > H || roi_y0 < 0 || roi_y0 + roi_h > H)
+    return -1;
+  size_t px = (size_t)roi_w * roi_h;
+  uint64_t* sl = (uint64_t*)malloc(px * sizeof(uint64_t));
+  uint64_t* sr = (uint64_t*)malloc(px * sizeof(uint64_t));
+  int16_t* d = (int16_t*)malloc(px * sizeof(int16_t));
+  /* the right ROI does not move */
+  for (int y = 0; y < roi_h; ++y)
+    for (int x = 0; x < roi_w; ++x) sr[(size_t)y * roi_w + x] = CR[(size_t)(roi_y0 + y) * W + roi_x0 + x];
+  for (int delta = delta_min; delta <= delta_max; ++delta) {
+    int k = delta - delta_min;
+    /* the left image moved down by delta: row y of the moved image is row y - delta */
+    for (int y = 0; y < roi_h; ++y)
+      for (int x = 0; x < roi_w; ++x)
+        sl[(size_t)y * roi_w + x] = CL[(size_t)(roi_y0 + y - delta) * W + roi_x0 + x];
+    if (orc_dense(sl, sr, roi_w, roi_h, dmin, dmax, radius, lr_tol, d, NULL, n_threads) != 0) {
+      free(sl); free(sr); free(d);
+      return -1;
+    }
+    int c = 0;
+    for (size_t i = 0; i < px; ++i) c += d[i] > d_min;
+    counts[k] = c;
+    if (maps) memcpy(maps + (size_t)k * px, d, px * sizeof(int16_t));
+  }
+  free(sl); free(sr); free(d);
+  return 0;
+}
+
+static int cmp_int(const void* a, const void* b) {
+  int x = *(const int*)a, y = *(const int*)b;
+  return (x > y) - (x < y);
+}
+
+void orc_rect_filter(const int32_t* counts, int32_t T, int32_t n_offsets, int32_t delta_min,
+                     int32_t window, int32_t max_step, int32_t initial, int32_t* raw,
+                     int32_t* filtered) {
+  int prev = initial;
+  int* win = (int*)malloc(sizeof(int) * (size_t)(window > 0 ? window : 1));
+  for (int t = 0; t < T; ++t) {
+    const int32_t* c = counts + (size_t)t * n_offsets;
+    /* delta* = argmax of the count; among equal counts the offset nearest 0, then the
+     * lower one */
+    int best = delta_min;
+    for (int k = 1; k < n_offsets; ++k) {
+      int dk = delta_min + k, cb = c[best - delta_min];
+      if (c[k] > cb || (c[k] == cb && (abs(dk) < abs(best) || (abs(dk) == abs(best) && dk < best))))
+        best = dk;
+    }
+    raw[t] = best;
+    /* median of raw[t - window + 1 .. t] (those that exist), lower middle if even */
+    int m = 0;
+    for (int u = t - window + 1; u <= t; ++u)
+      if (u >= 0) win[m++] = raw[u];
+    qsort(win, (size_t)m, sizeof(int), cmp_int);
+    int med = win[(m - 1) / 2];
+    /* clamped change from the previous output */
+    int step = med - prev;
+    if (step > max_step) step = max_step;
+    if (step < -max_step) step = -max_step;
+    prev += step;
+    filtered[t] = prev;
+  }
+  free(win);
 }

@@ -67,6 +67,24 @@ typedef struct {
 void orc_select_boxes(const int32_t* boxes, int32_t n, int32_t W, int32_t H, int32_t max_objects,
                       const int32_t* crop_permille, int32_t* flags_out, int32_t* rank);
 
+/* Auto-rectification offset (Sec. 5.1). For each delta in [delta_min, delta_max]: the
+ * ROI pair with the left descriptors moved down by delta (left row roi_y0 + y - delta,
+ * right row roi_y0 + y), the dense counterpart orc_dense on it, and the number of pixels
+ * whose disparity is > d_min. counts: [n_offsets]; maps (nullable): [n_offsets][roi_h][roi_w].
+ * Returns 0, or -1 when the moved ROI leaves the image. */
+int32_t orc_rect_counts(const uint64_t* CL, const uint64_t* CR, int32_t W, int32_t H,
+                        int32_t roi_x0, int32_t roi_y0, int32_t roi_w, int32_t roi_h,
+                        int32_t delta_min, int32_t delta_max, int32_t dmin, int32_t dmax,
+                        int32_t radius, int32_t lr_tol, int32_t d_min, int32_t* counts,
+                        int16_t* maps, int32_t n_threads);
+
+/* The offset estimate of each of T frames (counts: [T][n_offsets]) and its temporal
+ * filter: the median of the last `window` estimates, approached from the previous
+ * output by at most max_step per frame (Sec. 5.1, filter equations). */
+void orc_rect_filter(const int32_t* counts, int32_t T, int32_t n_offsets, int32_t delta_min,
+                     int32_t window, int32_t max_step, int32_t initial, int32_t* raw,
+                     int32_t* filtered);
+
 /* Census of one level: out is [H/s][W/s] row-major, pitch W/s. Returns 0, or -1
  * when the window does not fit in 64 bits or an argument is out of range. */
 int32_t orc_census(const uint8_t* img, int32_t W, int32_t H, int32_t pitch,

@@ -80,6 +80,10 @@ def lib():
         L.orc_box_points.restype = None
         L.orc_select_boxes.argtypes = [vp, i32, i32, i32, i32, vp, vp, vp]
         L.orc_select_boxes.restype = None
+        L.orc_rect_counts.argtypes = [vp, vp, i32, i32] + [i32] * 11 + [vp, vp, i32]
+        L.orc_rect_counts.restype = i32
+        L.orc_rect_filter.argtypes = [vp, i32, i32, i32, i32, i32, i32, vp, vp]
+        L.orc_rect_filter.restype = None
         _lib = L
     return _lib
 
@@ -236,3 +240,29 @@ def select_boxes(boxes, W: int, H: int, max_objects: int, crop_permille=(333, 0,
     out = boxes.copy()
     out[:, 4] = flags
     return out, rank
+
+
+def rect_counts(CL, CR, p: dict, maps: bool = False, threads: int = 0):
+    """Per vertical offset, the ROI pixels with dense disparity > d_min (Sec. 5.1)."""
+    CL = np.ascontiguousarray(CL, dtype=np.uint64)
+    CR = np.ascontiguousarray(CR, dtype=np.uint64)
+    H, W = CL.shape
+    nz = p["delta_max"] - p["delta_min"] + 1
+    counts = np.zeros(nz, np.int32)
+    m = np.zeros((nz, p["roi_h"], p["roi_w"]), np.int16) if maps else None
+    rc = lib().orc_rect_counts(_ptr(CL), _ptr(CR), W, H, p["roi_x0"], p["roi_y0"], p["roi_w"],
+                               p["roi_h"], p["delta_min"], p["delta_max"], p["dmin"], p["dmax"],
+                               p["radius"], p["lr_tol"], p["d_min"], _ptr(counts), _ptr(m), threads)
+    if rc != 0:
+        raise ValueError("orc_rect_counts rejected its arguments")
+    return (counts, m) if maps else counts
+
+
+def rect_filter(counts_seq, delta_min: int, window: int, max_step: int, initial: int = 0):
+    """Offset estimates and filtered offsets of a sequence of frames' counts."""
+    c = np.ascontiguousarray(np.asarray(counts_seq, dtype=np.int32))
+    T, n = c.shape
+    raw = np.zeros(T, np.int32)
+    filt = np.zeros(T, np.int32)
+    lib().orc_rect_filter(_ptr(c), T, n, delta_min, window, max_step, initial, _ptr(raw), _ptr(filt))
+    return raw, filt

@@ -5,6 +5,8 @@
 #include <cstring>
 #include <algorithm>
 #include <array>
+#include <cstdlib>
+#include <deque>
 #include <functional>
 #include <list>
 #include <map>
@@ -15,6 +17,13 @@
 #include "ocsr_internal.hpp"
 
 using namespace ocsr;
+
+// Temporal filter of the auto-rectification offset: the last `window` estimates and the
+// previous output.
+struct ocsr_rect_filter {
+  int window = 1, max_step = 0, prev = 0;
+  std::deque<int> hist;
+};
 
 struct ocsr_ctx {
   int device = 0;
@@ -501,6 +510,100 @@ int32_t ocsr_census(ocsr_ctx* ctx, const uint8_t* img, int32_t width, int32_t he
   LaunchTimer t = make_timer(ctx);
   return enqueue_census(&j, 1, params->sx, params->sy, params->sentinel ? 1 : 0,
                         (hipStream_t)stream, ctx->timing ? &t : nullptr);
+}
+
+size_t ocsr_rect_workspace_bytes(const ocsr_rect_params* p) {
+  if (!p || p->roi_w <= 0 || p->roi_h <= 0 || (int64_t)p->roi_w * p->roi_h > (1 << 26)) return 0;
+  const int64_t nz = (int64_t)p->delta_max - p->delta_min + 1;
+  if (nz < 1 || nz > OCSR_MAX_RECT_OFFSETS) return 0;
+  // per offset: the left and right winner maps and the checked map
+  return 3 * (size_t)nz * a256((size_t)p->roi_w * p->roi_h * sizeof(int16_t));
+}
+
+int32_t ocsr_rect_offset_counts(ocsr_ctx* ctx, const ocsr_level* lv, const ocsr_rect_params* p,
+                                int32_t* counts, int16_t* disp, void* ws, size_t ws_bytes,
+                                void* stream) {
+  g_last_error.clear();
+  if (!ctx || !p) return fail(OCSR_E_INVALID, "null context or rectification params");
+  int32_t rc;
+  LevelDev L;
+  if ((rc = check_level(lv, "lv", &L)) != OCSR_OK) return rc;
+  if (!counts) return fail(OCSR_E_INVALID, "null counts");
+  if (p->delta_min > p->delta_max || p->delta_max - p->delta_min + 1 > OCSR_MAX_RECT_OFFSETS)
+    return fail(OCSR_E_INVALID, "offsets [%d, %d]: 1..%d of them", p->delta_min, p->delta_max,
+                OCSR_MAX_RECT_OFFSETS);
+  if (p->roi_w <= 0 || p->roi_h <= 0 || (int64_t)p->roi_w * p->roi_h > (1 << 26))
+    return fail(OCSR_E_INVALID, "ROI %dx%d: 1..2^26 pixels", p->roi_w, p->roi_h);
+  if (p->roi_x0 < 0 || (int64_t)p->roi_x0 + p->roi_w > L.W || (int64_t)p->roi_y0 - p->delta_max < 0 ||
+      (int64_t)p->roi_y0 + p->roi_h - p->delta_min > L.H || p->roi_y0 + p->roi_h > L.H || p->roi_y0 < 0)
+    return fail(OCSR_E_INVALID, "ROI [%d, %d) x [%d, %d) moved by %d..%d leaves the %dx%d level",
+                p->roi_x0, p->roi_x0 + p->roi_w, p->roi_y0, p->roi_y0 + p->roi_h, p->delta_min,
+                p->delta_max, L.W, L.H);
+  if (p->dmin < 0 || p->dmax < p->dmin) return fail(OCSR_E_INVALID, "disparity range [%d, %d] invalid", p->dmin, p->dmax);
+  if (p->dmax - p->dmin + 1 > OCSR_MAX_CANDIDATES)
+    return fail(OCSR_E_CAPACITY, "%d candidates > %d", p->dmax - p->dmin + 1, OCSR_MAX_CANDIDATES);
+  if (!dense_radius_supported(p->radius))
+    return fail(OCSR_E_UNSUPPORTED, "window radius %d: only 1..3 are built", p->radius);
+  if (p->lr_tol < 0 || p->d_min < 0) return fail(OCSR_E_INVALID, "lr_tol and d_min must be >= 0");
+  if ((rc = check_ws(ws, ws_bytes, ocsr_rect_workspace_bytes(p))) != OCSR_OK) return rc;
+  const int nz = p->delta_max - p->delta_min + 1;
+  // the maps of one kind are consecutive planes of roi_w * roi_h (within the workspace's
+  // three padded blocks)
+  int16_t* d_left = (int16_t*)ws;
+  int16_t* d_right = d_left + (size_t)nz * p->roi_w * p->roi_h;
+  int16_t* d_chk = disp ? disp : d_right + (size_t)nz * p->roi_w * p->roi_h;
+  const uint64_t* CL0 = L.L + ((int64_t)p->roi_y0 - p->delta_min) * L.pitch + p->roi_x0;
+  const uint64_t* CR = L.R + (int64_t)p->roi_y0 * L.pitch + p->roi_x0;
+  LaunchTimer t = make_timer(ctx);
+  const hipError_t e = launch_dense_offsets(CL0, CR, p->roi_w, p->roi_h, L.pitch, nz, p->dmin, p->dmax,
+                                            p->radius, p->lr_tol, p->d_min, d_chk, d_left, d_right,
+                                            counts, (hipStream_t)stream, ctx->timing ? &t : nullptr);
+  return e == hipSuccess ? OCSR_OK : hip_fail(e, "rectification launch");
+}
+
+int32_t ocsr_rect_filter_create(int32_t window, int32_t max_step, int32_t initial,
+                                ocsr_rect_filter** out) {
+  g_last_error.clear();
+  if (!out) return fail(OCSR_E_INVALID, "null output pointer");
+  *out = nullptr;
+  if (window < 1 || window > 1024) return fail(OCSR_E_INVALID, "window %d outside 1..1024", window);
+  if (max_step < 0) return fail(OCSR_E_INVALID, "max_step %d < 0", max_step);
+  ocsr_rect_filter* f = new (std::nothrow) ocsr_rect_filter();
+  if (!f) return fail(OCSR_E_INVALID, "out of host memory");
+  f->window = window;
+  f->max_step = max_step;
+  f->prev = initial;
+  *out = f;
+  return OCSR_OK;
+}
+
+void ocsr_rect_filter_destroy(ocsr_rect_filter* f) { delete f; }
+
+int32_t ocsr_rect_filter_update(ocsr_rect_filter* f, const int32_t* counts, int32_t n_offsets,
+                                int32_t delta_min, int32_t* raw, int32_t* filtered) {
+  g_last_error.clear();
+  if (!f || !counts || !raw || !filtered) return fail(OCSR_E_INVALID, "null argument");
+  if (n_offsets < 1 || n_offsets > OCSR_MAX_RECT_OFFSETS)
+    return fail(OCSR_E_INVALID, "n_offsets %d outside 1..%d", n_offsets, OCSR_MAX_RECT_OFFSETS);
+  // estimate: the largest count; ties to the smallest |delta|, then the smaller delta
+  int best = 0;
+  for (int k = 1; k < n_offsets; ++k) {
+    const int dk = delta_min + k, db = delta_min + best;
+    if (counts[k] > counts[best] ||
+        (counts[k] == counts[best] && (std::abs(dk) < std::abs(db) || (std::abs(dk) == std::abs(db) && dk < db))))
+      best = k;
+  }
+  const int est = delta_min + best;
+  f->hist.push_back(est);
+  if ((int)f->hist.size() > f->window) f->hist.pop_front();
+  std::vector<int> v(f->hist.begin(), f->hist.end());
+  std::sort(v.begin(), v.end());
+  const int med = v[(v.size() - 1) / 2];
+  const int step = std::max(-f->max_step, std::min(f->max_step, med - f->prev));
+  f->prev += step;
+  *raw = est;
+  *filtered = f->prev;
+  return OCSR_OK;
 }
 
 int32_t ocsr_select_boxes(ocsr_ctx* ctx, const ocsr_frame* frames, int32_t n_frames,

@@ -37,6 +37,9 @@ struct DenseArgs {
   int32_t W, H, pitch;        // descriptor image size and row pitch (words)
   int32_t dlo, nd;            // disparities dlo .. dlo + nd - 1
   int16_t* out;               // [H][W] winning disparity (-1: no candidate)
+  // several pairs in one launch (grid z): pair z reads CL + z * cl_zstride (words; the
+  // right image is shared) and writes out + z * out_zstride
+  int64_t cl_zstride, out_zstride;
 };
 
 __device__ __forceinline__ uint32_t popc64(uint64_t v) {
@@ -161,6 +164,8 @@ __device__ __forceinline__ void dense_pass(const DenseArgs& a, int x, int y0, in
 
 template <int R, int RIGHT>
 __global__ __launch_bounds__(256) void dense_kernel(DenseArgs a) {
+  a.CL += (int64_t)blockIdx.z * a.cl_zstride;
+  a.out += (int64_t)blockIdx.z * a.out_zstride;
   const int lane = threadIdx.x & 63;
   const int band = blockIdx.y * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int y0 = band * kBand;
@@ -192,6 +197,10 @@ __global__ __launch_bounds__(256) void dense_kernel(DenseArgs a) {
 __global__ __launch_bounds__(256) void dense_check_kernel(const int16_t* __restrict__ dl,
                                                           const int16_t* __restrict__ dr, int W,
                                                           int H, int lr_tol, int16_t* disp) {
+  const size_t plane = (size_t)blockIdx.z * W * H;   // pair z of a multi-pair launch
+  dl += plane;
+  dr += plane;
+  disp += plane;
   const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y;
   if (x >= W) return;
   const int d = dl[(size_t)y * W + x];
@@ -204,9 +213,24 @@ __global__ __launch_bounds__(256) void dense_check_kernel(const int16_t* __restr
   disp[(size_t)y * W + x] = ok ? (int16_t)d : (int16_t)-1;
 }
 
+// counts[z] = number of pixels of map z (W x H) whose disparity is > d_min: one
+// workgroup per map, no atomics
+__global__ __launch_bounds__(256) void count_above_kernel(const int16_t* __restrict__ disp, int W,
+                                                          int H, int d_min, int32_t* counts) {
+  __shared__ int part[4];
+  const int16_t* m = disp + (size_t)blockIdx.x * W * H;
+  const int n = W * H;
+  int c = 0;
+  for (int i = threadIdx.x; i < n; i += 256) c += m[i] > d_min ? 1 : 0;
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) counts[blockIdx.x] = part[0] + part[1] + part[2] + part[3];
+}
+
 template <int R>
-hipError_t launch_dense_r(const DenseArgs& left, const DenseArgs& right, hipStream_t s) {
-  const dim3 grid((left.W + strip<R>() - 1) / strip<R>(), (left.H + 4 * kBand - 1) / (4 * kBand));
+hipError_t launch_dense_r(const DenseArgs& left, const DenseArgs& right, hipStream_t s, int nz = 1) {
+  const dim3 grid((left.W + strip<R>() - 1) / strip<R>(), (left.H + 4 * kBand - 1) / (4 * kBand), nz);
   dense_kernel<R, 0><<<grid, 256, 0, s>>>(left);
   dense_kernel<R, 1><<<grid, 256, 0, s>>>(right);
   return hipGetLastError();
@@ -219,8 +243,8 @@ bool dense_radius_supported(int radius) { return radius >= 1 && radius <= 3; }
 hipError_t launch_dense(const uint64_t* CL, const uint64_t* CR, int W, int H, int pitch, int dmin,
                         int dmax, int radius, int lr_tol, int16_t* disp, int16_t* d_left,
                         int16_t* d_right, hipStream_t stream, const LaunchTimer* timer) {
-  const DenseArgs left = {CL, CR, W, H, pitch, dmin, dmax - dmin + 1, d_left};
-  const DenseArgs right = {CL, CR, W, H, pitch, dmin, dmax - dmin + 1, d_right};
+  const DenseArgs left = {CL, CR, W, H, pitch, dmin, dmax - dmin + 1, d_left, 0, 0};
+  const DenseArgs right = {CL, CR, W, H, pitch, dmin, dmax - dmin + 1, d_right, 0, 0};
   if (timer) timer->before(timer->ctx, "dense", stream);
   hipError_t e = hipErrorNotSupported;
   if (radius == 1) e = launch_dense_r<1>(left, right, stream);
@@ -232,6 +256,30 @@ hipError_t launch_dense(const uint64_t* CL, const uint64_t* CR, int W, int H, in
   dense_check_kernel<<<dim3((W + 255) / 256, H), 256, 0, stream>>>(d_left, d_right, W, H, lr_tol,
                                                                    disp);
   if (timer) timer->after(timer->ctx, "dense_check", stream);
+  return hipGetLastError();
+}
+
+// Dense counterpart of nz pairs at once: pair z is (CL0 - z rows, CR), i.e. the left
+// descriptors moved down by z more rows; then the pixels above d_min of each map.
+hipError_t launch_dense_offsets(const uint64_t* CL0, const uint64_t* CR, int W, int H, int pitch,
+                                int nz, int dmin, int dmax, int radius, int lr_tol, int d_min,
+                                int16_t* disp, int16_t* d_left, int16_t* d_right, int32_t* counts,
+                                hipStream_t stream, const LaunchTimer* timer) {
+  const int64_t plane = (int64_t)W * H;
+  const DenseArgs left = {CL0, CR, W, H, pitch, dmin, dmax - dmin + 1, d_left, -(int64_t)pitch, plane};
+  const DenseArgs right = {CL0, CR, W, H, pitch, dmin, dmax - dmin + 1, d_right, -(int64_t)pitch, plane};
+  if (timer) timer->before(timer->ctx, "rect_dense", stream);
+  hipError_t e = hipErrorNotSupported;
+  if (radius == 1) e = launch_dense_r<1>(left, right, stream, nz);
+  if (radius == 2) e = launch_dense_r<2>(left, right, stream, nz);
+  if (radius == 3) e = launch_dense_r<3>(left, right, stream, nz);
+  if (timer) timer->after(timer->ctx, "rect_dense", stream);
+  if (e != hipSuccess) return e;
+  if (timer) timer->before(timer->ctx, "rect_count", stream);
+  dense_check_kernel<<<dim3((W + 255) / 256, H, nz), 256, 0, stream>>>(d_left, d_right, W, H, lr_tol,
+                                                                       disp);
+  count_above_kernel<<<nz, 256, 0, stream>>>(disp, W, H, d_min, counts);
+  if (timer) timer->after(timer->ctx, "rect_count", stream);
   return hipGetLastError();
 }
 

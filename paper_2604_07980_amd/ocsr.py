@@ -29,6 +29,7 @@ MAX_BATCH_FRAMES = 16
 MAX_CANDIDATES = 256
 MAX_DY = 32
 MAX_SELECT_BOXES = 16384
+MAX_RECT_OFFSETS = 64
 MAX_DY_CANDIDATES = 2048
 MAX_CENSUS_JOBS = 64
 DEFAULT_CAP_BLOCKS = 1 << 20
@@ -42,7 +43,9 @@ EXPORTS = ["ocsr_abi_version", "ocsr_last_error", "ocsr_ctx_create", "ocsr_ctx_d
            "ocsr_range_batch", "ocsr_ctx_set_option", "ocsr_ctx_set_timing",
            "ocsr_ctx_kernel_time", "ocsr_ctx_reset_timing", "ocsr_ctx_graph_stats",
            "ocsr_variant_candidates", "ocsr_ctx_set_variant", "ocsr_dense_workspace_bytes",
-           "ocsr_dense_match", "ocsr_box_points", "ocsr_select_boxes"]
+           "ocsr_dense_match", "ocsr_box_points", "ocsr_select_boxes",
+           "ocsr_rect_workspace_bytes", "ocsr_rect_offset_counts", "ocsr_rect_filter_create",
+           "ocsr_rect_filter_destroy", "ocsr_rect_filter_update"]
 
 
 class OcsrError(RuntimeError):
@@ -85,6 +88,11 @@ class MatchParams(C.Structure):
 class FrameParams(C.Structure):
     _fields_ = [("sx", C.c_int32), ("sy", C.c_int32), ("sentinel", C.c_int32),
                 ("close_scale", C.c_int32)]
+
+
+class RectParams(C.Structure):
+    _fields_ = [(n, C.c_int32) for n in ("roi_x0", "roi_y0", "roi_w", "roi_h", "delta_min",
+                                         "delta_max", "dmin", "dmax", "radius", "lr_tol", "d_min")]
 
 
 class SelectParams(C.Structure):
@@ -190,6 +198,17 @@ def load(path: str = LIB_PATH):
         L.ocsr_box_points.restype = i32
         L.ocsr_select_boxes.argtypes = [vp, vp, i32, vp, C.POINTER(SelectParams), vp, vp, vp]
         L.ocsr_select_boxes.restype = i32
+        L.ocsr_rect_workspace_bytes.argtypes = [C.POINTER(RectParams)]
+        L.ocsr_rect_workspace_bytes.restype = C.c_size_t
+        L.ocsr_rect_offset_counts.argtypes = [vp, C.POINTER(Level), C.POINTER(RectParams), vp, vp, vp,
+                                              C.c_size_t, vp]
+        L.ocsr_rect_offset_counts.restype = i32
+        L.ocsr_rect_filter_create.argtypes = [i32, i32, i32, C.POINTER(vp)]
+        L.ocsr_rect_filter_create.restype = i32
+        L.ocsr_rect_filter_destroy.argtypes = [vp]
+        L.ocsr_rect_filter_destroy.restype = None
+        L.ocsr_rect_filter_update.argtypes = [vp, vp, i32, i32, C.POINTER(i32), C.POINTER(i32)]
+        L.ocsr_rect_filter_update.restype = i32
         _lib = L
         return L
 
@@ -505,6 +524,62 @@ def box_points(boxes: torch.Tensor, results: torch.Tensor, geom: dict,
     _check(load().ocsr_box_points(context(boxes.device.index), _dptr(boxes), _dptr(results), n,
                                   C.byref(pp), _dptr(out), _stream(boxes.device)))
     return out
+
+
+# ---------------------------------------------------------------------------------
+# auto-rectification offset
+# ---------------------------------------------------------------------------------
+def rect_params(p: dict) -> RectParams:
+    return RectParams(*[int(p[k]) for k in ("roi_x0", "roi_y0", "roi_w", "roi_h", "delta_min",
+                                            "delta_max", "dmin", "dmax", "radius", "lr_tol",
+                                            "d_min")])
+
+
+def rect_offset_counts(L: torch.Tensor, R: torch.Tensor, p: dict, sx: int = 3, sy: int = 4,
+                       with_maps: bool = False, workspace: Workspace | None = None,
+                       counts: torch.Tensor | None = None):
+    """Counts of ROI pixels with disparity > d_min for every vertical offset of the left
+    descriptors (L, R: one level's uint64-as-int64 [H, W] cuda descriptors). Returns the
+    int32 [n_offsets] counts, and with with_maps the int16 [n_offsets, roi_h, roi_w] maps."""
+    _need_cuda(L, R)
+    if L.shape != R.shape or L.dtype != torch.int64 or L.stride() != R.stride() or L.stride(1) != 1:
+        raise ValueError("descriptors must be row-contiguous int64 tensors of equal shape")
+    rp = rect_params(p)
+    Lb = load()
+    nbytes = Lb.ocsr_rect_workspace_bytes(C.byref(rp))
+    if nbytes == 0:
+        raise ValueError("invalid rectification parameters")
+    dev = L.device
+    ws = (workspace or Workspace()).get(nbytes, dev)
+    nz = rp.delta_max - rp.delta_min + 1
+    if counts is None:
+        counts = torch.empty(nz, dtype=torch.int32, device=dev)
+    maps = torch.empty((nz, rp.roi_h, rp.roi_w), dtype=torch.int16, device=dev) if with_maps else None
+    lv = _level(L, R, 1, sx, sy)
+    _check(Lb.ocsr_rect_offset_counts(context(dev.index), C.byref(lv), C.byref(rp), _dptr(counts),
+                                      _dptr(maps) if with_maps else None, _dptr(ws), ws.numel(),
+                                      _stream(dev)))
+    return (counts, maps) if with_maps else counts
+
+
+class RectFilter:
+    """The library's temporal filter of the per-frame offset estimate (host only)."""
+
+    def __init__(self, window: int, max_step: int, initial: int = 0):
+        self._h = C.c_void_p()
+        _check(load().ocsr_rect_filter_create(window, max_step, initial, C.byref(self._h)))
+
+    def update(self, counts, delta_min: int) -> tuple[int, int]:
+        c = np.ascontiguousarray(np.asarray(counts, dtype=np.int32))
+        raw, filt = C.c_int32(), C.c_int32()
+        _check(load().ocsr_rect_filter_update(self._h, c.ctypes.data_as(C.c_void_p), len(c),
+                                              int(delta_min), C.byref(raw), C.byref(filt)))
+        return raw.value, filt.value
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.ocsr_rect_filter_destroy(self._h)
+            self._h = None
 
 
 # Central crop of the selection when none is given: the middle third of the width over

@@ -144,6 +144,20 @@ def shifted_texture(seed: int, H: int, W: int, dx: int, dy: int,
     return np.ascontiguousarray(left), np.ascontiguousarray(right)
 
 
+def road_pair(seed: int = 4000, H: int = 1080, W: int = 1920, drift: int = 0):
+    """A ground-like pair for the rectification-offset search: below the horizon
+    (H / 2) 12 horizontal bands, each a fronto-parallel plane whose disparity grows
+    toward the bottom (4, 12, ..., 92 px at 1080 rows), over a far background; the right
+    view then moved down by `drift` rows (drift_rows)."""
+    rng = np.random.default_rng(seed)
+    h0 = H // 2
+    band = max(1, (H - h0) // 12)
+    planes = [(-100, h0 + k * band, W + 100, h0 + (k + 1) * band if k < 11 else H,
+               (4.0 + 8.0 * k) * H / 1080.0) for k in range(12)]
+    left, right = render_pair(rng, H, W, planes)
+    return left, drift_rows(right, drift)
+
+
 def _overlap(a, b) -> bool:
     return a[0] < b[2] and b[0] < a[2] and a[1] < b[3] and b[1] < a[3]
 
