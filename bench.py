@@ -45,6 +45,8 @@ def parse():
                     help="pre-rendered image pairs per serving resolution")
     ap.add_argument("--vertical-steps", type=int, default=100,
                     help="frames of the vertical-range workload (0: skip)")
+    ap.add_argument("--rect-steps", type=int, default=50,
+                    help="frames of the rectification-offset workload (0: skip)")
     ap.add_argument("--dense-steps", type=int, default=20,
                     help="timed repetitions of the dense counterpart (0 skips it)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
@@ -290,6 +292,58 @@ def dense_section(ocsr, L, R, steps, sparse_ms):
             "valid_fraction": round(float((disp >= 0).float().mean()), 4),
             "ms_sparse_frame": round(sparse_ms, 4),
             "dense_over_sparse_time": round(ms / sparse_ms, 2), "kernels": kern}
+
+
+def rect_section(ocsr, synth, steps):
+    """Auto-rectification offset search on the ground-like 1080p pair with its right view
+    6 rows low: census of both views at s = 2, then the dense matcher (d 0..63, 5x5, L/R
+    <= 1) on a 960 x 128 band of road rows for the 9 offsets -4..4, counts of d > 2, and
+    the host filter. Kernel times from HIP events."""
+    import torch
+    dev = torch.device("cuda:0")
+    left, right = synth.road_pair(drift=6)
+    L = torch.from_numpy(left).to(dev)
+    R = torch.from_numpy(right).to(dev)
+    p = dict(roi_x0=0, roi_y0=300, roi_w=960, roi_h=128, delta_min=-4, delta_max=4, dmin=0,
+             dmax=63, radius=2, lr_tol=1, d_min=2)
+    ws = ocsr.Workspace()
+    counts = torch.empty(9, dtype=torch.int32, device=dev)
+
+    def run():
+        CL, CR = ocsr.census_many([L, R], [2, 2])
+        ocsr.rect_offset_counts(CL, CR, p, workspace=ws, counts=counts)
+
+    for _ in range(3):
+        run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        run()
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / steps
+    ocsr.reset_timing()
+    ocsr.set_timing(True)
+    for _ in range(steps):
+        run()
+    torch.cuda.synchronize()
+    ocsr.set_timing(False)
+    kern = {}
+    costs = 9 * p["roi_w"] * p["roi_h"] * (p["dmax"] - p["dmin"] + 1)
+    for name in ("census", "rect_dense", "rect_count"):
+        cnt, tot = ocsr.kernel_time(name)
+        if cnt:
+            kern[name] = {"avg_us": round(1e3 * tot / cnt, 3)}
+    if "rect_dense" in kern:
+        # 4 int32 ops per cost in each of the two views
+        tops = 2 * MATCH_OPS_PER_COST * costs / (kern["rect_dense"]["avg_us"] * 1e-6) / 1e12
+        kern["rect_dense"].update(tops=round(tops, 3), frac=round(tops / INT_PEAK_TOPS, 4))
+    f = ocsr.RectFilter(5, 1)
+    raw, filt = f.update(counts.cpu().numpy(), p["delta_min"])
+    return {"workload": "road_1080p: ground-like 1920x1080 pair, right view 6 rows low; s=2, "
+                        "ROI 960x128, offsets -4..4, dense d 0..63 5x5, count d > 2",
+            "ms_per_frame": round(ms, 4), "costs_per_frame": costs,
+            "gcost_per_s": round(costs / (ms * 1e-3) / 1e9, 3),
+            "estimate_level_rows": raw, "first_filtered": filt, "kernels": kern}
 
 
 def serving_section(ocsr, synth, n_requests, pool_size):
@@ -549,6 +603,8 @@ def main():
         res["vertical"] = vertical_section(ocsr, synth, args.vertical_steps, max(3, args.warmup // 10))
     if args.batch_steps > 0:
         res["batch"] = batch_section(ocsr, synth, args.batch_steps, max(3, args.warmup // 10))
+    if args.rect_steps > 0:
+        res["rect"] = rect_section(ocsr, synth, args.rect_steps)
     if args.dense_steps > 0:
         res["dense"] = dense_section(ocsr, L, R, args.dense_steps, ms_per_step)
     if args.serve_requests > 0:

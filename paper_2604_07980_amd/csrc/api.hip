@@ -516,8 +516,11 @@ size_t ocsr_rect_workspace_bytes(const ocsr_rect_params* p) {
   if (!p || p->roi_w <= 0 || p->roi_h <= 0 || (int64_t)p->roi_w * p->roi_h > (1 << 26)) return 0;
   const int64_t nz = (int64_t)p->delta_max - p->delta_min + 1;
   if (nz < 1 || nz > OCSR_MAX_RECT_OFFSETS) return 0;
-  // per offset: the left and right winner maps and the checked map
-  return 3 * (size_t)nz * a256((size_t)p->roi_w * p->roi_h * sizeof(int16_t));
+  // per offset: the left and right winner maps and the checked map, then one partial
+  // count per 256-pixel row segment
+  const size_t maps = 3 * (size_t)nz * p->roi_w * p->roi_h * sizeof(int16_t);
+  const size_t parts = (size_t)nz * p->roi_h * ((p->roi_w + 255) / 256) * sizeof(int32_t);
+  return a256(maps) + a256(parts);
 }
 
 int32_t ocsr_rect_offset_counts(ocsr_ctx* ctx, const ocsr_level* lv, const ocsr_rect_params* p,
@@ -547,17 +550,19 @@ int32_t ocsr_rect_offset_counts(ocsr_ctx* ctx, const ocsr_level* lv, const ocsr_
   if (p->lr_tol < 0 || p->d_min < 0) return fail(OCSR_E_INVALID, "lr_tol and d_min must be >= 0");
   if ((rc = check_ws(ws, ws_bytes, ocsr_rect_workspace_bytes(p))) != OCSR_OK) return rc;
   const int nz = p->delta_max - p->delta_min + 1;
-  // the maps of one kind are consecutive planes of roi_w * roi_h (within the workspace's
-  // three padded blocks)
+  // the maps of one kind are consecutive planes of roi_w * roi_h; the partial counts
+  // follow the three kinds
   int16_t* d_left = (int16_t*)ws;
   int16_t* d_right = d_left + (size_t)nz * p->roi_w * p->roi_h;
   int16_t* d_chk = disp ? disp : d_right + (size_t)nz * p->roi_w * p->roi_h;
+  int32_t* partial = (int32_t*)((char*)ws + a256(3 * (size_t)nz * p->roi_w * p->roi_h * sizeof(int16_t)));
   const uint64_t* CL0 = L.L + ((int64_t)p->roi_y0 - p->delta_min) * L.pitch + p->roi_x0;
   const uint64_t* CR = L.R + (int64_t)p->roi_y0 * L.pitch + p->roi_x0;
   LaunchTimer t = make_timer(ctx);
   const hipError_t e = launch_dense_offsets(CL0, CR, p->roi_w, p->roi_h, L.pitch, nz, p->dmin, p->dmax,
                                             p->radius, p->lr_tol, p->d_min, d_chk, d_left, d_right,
-                                            counts, (hipStream_t)stream, ctx->timing ? &t : nullptr);
+                                            partial, counts, (hipStream_t)stream,
+                                            ctx->timing ? &t : nullptr);
   return e == hipSuccess ? OCSR_OK : hip_fail(e, "rectification launch");
 }
 

@@ -194,34 +194,46 @@ __global__ __launch_bounds__(256) void dense_kernel(DenseArgs a) {
   }
 }
 
+// The L/R check of one row segment of 256 pixels. With `partial` set, the workgroup also
+// stores how many of its checked disparities are > d_min at
+// partial[(z * H + y) * gridDim.x + blockIdx.x].
 __global__ __launch_bounds__(256) void dense_check_kernel(const int16_t* __restrict__ dl,
                                                           const int16_t* __restrict__ dr, int W,
-                                                          int H, int lr_tol, int16_t* disp) {
+                                                          int H, int lr_tol, int16_t* disp,
+                                                          int d_min, int32_t* partial) {
+  __shared__ int part[4];
   const size_t plane = (size_t)blockIdx.z * W * H;   // pair z of a multi-pair launch
   dl += plane;
   dr += plane;
   disp += plane;
   const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y;
-  if (x >= W) return;
-  const int d = dl[(size_t)y * W + x];
-  const int xr = x - d;
-  int ok = 0;
-  if (d >= 0 && xr >= 0) {
-    const int db = dr[(size_t)y * W + xr];
-    ok = db >= 0 && abs(d - db) <= lr_tol;
+  int above = 0;
+  if (x < W) {
+    const int d = dl[(size_t)y * W + x];
+    const int xr = x - d;
+    int ok = 0;
+    if (d >= 0 && xr >= 0) {
+      const int db = dr[(size_t)y * W + xr];
+      ok = db >= 0 && abs(d - db) <= lr_tol;
+    }
+    disp[(size_t)y * W + x] = ok ? (int16_t)d : (int16_t)-1;
+    above = ok && d > d_min ? 1 : 0;
   }
-  disp[(size_t)y * W + x] = ok ? (int16_t)d : (int16_t)-1;
+  if (!partial) return;   // uniform over the launch
+  for (int o = 32; o > 0; o >>= 1) above += __shfl_xor(above, o, 64);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = above;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    partial[((size_t)blockIdx.z * H + y) * gridDim.x + blockIdx.x] = part[0] + part[1] + part[2] + part[3];
 }
 
-// counts[z] = number of pixels of map z (W x H) whose disparity is > d_min: one
-// workgroup per map, no atomics
-__global__ __launch_bounds__(256) void count_above_kernel(const int16_t* __restrict__ disp, int W,
-                                                          int H, int d_min, int32_t* counts) {
+// counts[z] = the sum of map z's n partial counts: one workgroup per map, no atomics
+__global__ __launch_bounds__(256) void count_above_kernel(const int32_t* __restrict__ partial, int n,
+                                                          int32_t* counts) {
   __shared__ int part[4];
-  const int16_t* m = disp + (size_t)blockIdx.x * W * H;
-  const int n = W * H;
+  const int32_t* p = partial + (size_t)blockIdx.x * n;
   int c = 0;
-  for (int i = threadIdx.x; i < n; i += 256) c += m[i] > d_min ? 1 : 0;
+  for (int i = threadIdx.x; i < n; i += 256) c += p[i];
   for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
   if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = c;
   __syncthreads();
@@ -254,7 +266,7 @@ hipError_t launch_dense(const uint64_t* CL, const uint64_t* CR, int W, int H, in
   if (e != hipSuccess) return e;
   if (timer) timer->before(timer->ctx, "dense_check", stream);
   dense_check_kernel<<<dim3((W + 255) / 256, H), 256, 0, stream>>>(d_left, d_right, W, H, lr_tol,
-                                                                   disp);
+                                                                   disp, 0, nullptr);
   if (timer) timer->after(timer->ctx, "dense_check", stream);
   return hipGetLastError();
 }
@@ -263,8 +275,8 @@ hipError_t launch_dense(const uint64_t* CL, const uint64_t* CR, int W, int H, in
 // descriptors moved down by z more rows; then the pixels above d_min of each map.
 hipError_t launch_dense_offsets(const uint64_t* CL0, const uint64_t* CR, int W, int H, int pitch,
                                 int nz, int dmin, int dmax, int radius, int lr_tol, int d_min,
-                                int16_t* disp, int16_t* d_left, int16_t* d_right, int32_t* counts,
-                                hipStream_t stream, const LaunchTimer* timer) {
+                                int16_t* disp, int16_t* d_left, int16_t* d_right, int32_t* partial,
+                                int32_t* counts, hipStream_t stream, const LaunchTimer* timer) {
   const int64_t plane = (int64_t)W * H;
   const DenseArgs left = {CL0, CR, W, H, pitch, dmin, dmax - dmin + 1, d_left, -(int64_t)pitch, plane};
   const DenseArgs right = {CL0, CR, W, H, pitch, dmin, dmax - dmin + 1, d_right, -(int64_t)pitch, plane};
@@ -276,9 +288,10 @@ hipError_t launch_dense_offsets(const uint64_t* CL0, const uint64_t* CR, int W, 
   if (timer) timer->after(timer->ctx, "rect_dense", stream);
   if (e != hipSuccess) return e;
   if (timer) timer->before(timer->ctx, "rect_count", stream);
-  dense_check_kernel<<<dim3((W + 255) / 256, H, nz), 256, 0, stream>>>(d_left, d_right, W, H, lr_tol,
-                                                                       disp);
-  count_above_kernel<<<nz, 256, 0, stream>>>(disp, W, H, d_min, counts);
+  const int bx = (W + 255) / 256;
+  dense_check_kernel<<<dim3(bx, H, nz), 256, 0, stream>>>(d_left, d_right, W, H, lr_tol, disp, d_min,
+                                                          partial);
+  count_above_kernel<<<nz, 256, 0, stream>>>(partial, H * bx, counts);
   if (timer) timer->after(timer->ctx, "rect_count", stream);
   return hipGetLastError();
 }

@@ -264,8 +264,8 @@ hipError_t launch_box_points(const ocsr_box* boxes, const ocsr_box_result* res, 
 bool dense_radius_supported(int radius);
 hipError_t launch_dense_offsets(const uint64_t* CL0, const uint64_t* CR, int W, int H, int pitch,
                                 int nz, int dmin, int dmax, int radius, int lr_tol, int d_min,
-                                int16_t* disp, int16_t* d_left, int16_t* d_right, int32_t* counts,
-                                hipStream_t stream, const LaunchTimer* timer);
+                                int16_t* disp, int16_t* d_left, int16_t* d_right, int32_t* partial,
+                                int32_t* counts, hipStream_t stream, const LaunchTimer* timer);
 hipError_t launch_dense(const uint64_t* CL, const uint64_t* CR, int W, int H, int pitch, int dmin,
                         int dmax, int radius, int lr_tol, int16_t* disp, int16_t* d_left,
                         int16_t* d_right, hipStream_t stream, const LaunchTimer* timer);
