@@ -504,8 +504,9 @@ __device__ __forceinline__ void match_block_tiled(const MatchParamsDev& P, const
 // ---------------------------------------------------------------------------------
 // TILED block with a vertical range (the census cost over (dx, dy), Sec. 4.3.2). The
 // register-blocked row costs of match_block_tiled, repeated for every vertical offset.
-// Consecutive offsets read strip rows moved by one, so the strip lives in an LDS ring of
-// ROWS + 1 rows: step t reads rows t .. t + ROWS - 1 (lane row j from ring slot
+// Consecutive offsets read strip rows moved by one. When all ROWS + ndy - 1 rows fit
+// kDyFullLoads loads per lane (short strips) they are staged at once; otherwise the
+// strip lives in an LDS ring of ROWS + 1 rows: step t reads rows t .. t + ROWS - 1 (lane row j from ring slot
 // (t + j) mod (ROWS + 1)) while row t + ROWS, which step t + 1 needs, is loaded into the
 // one slot step t does not read. Each row is loaded once per direction, its latency
 // hidden behind the previous step. Rows and columns outside the level image read as
@@ -552,7 +553,24 @@ __device__ __forceinline__ uint32_t search_dy(const uint64_t (&t)[NX], uint64_t*
   constexpr int PC = (64 / ROWS) * CPL;
   static_assert(PC == kDyPass, "a pass covers kDyPass candidates");
   const int j = lane % ROWS, grp = lane / ROWS;
-  {
+  // all ROWS + ndy - 1 rows at once when they fit (wave-uniform), else the ring
+  const bool full = dy_full(ROWS, nd, ndy);
+  if (full) {
+    // word idx = lane + 64 k of the rows x SWr block, every load issued before a store
+    const int n = (ROWS + ndy - 1) * SWr;
+    uint64_t w[kDyFullLoads];
+#pragma unroll
+    for (int k = 0; k < kDyFullLoads; ++k) {
+      const int idx = lane + 64 * k;
+      const int r = idx / SWr, m = idx - r * SWr, x = x_first + m, y = y_top + r;
+      const bool ok = idx < n && m < sw && x >= 0 && x < W && y >= 0 && y < H;
+      w[k] = img[ok ? (size_t)y * pitch + x : 0];
+      w[k] = ok ? w[k] : 0ull;
+    }
+#pragma unroll
+    for (int k = 0; k < kDyFullLoads; ++k)
+      if (lane + 64 * k < n) S[lane + 64 * k] = w[k];
+  } else {
     // rows 0 .. ROWS - 1, every load issued before the first store
     uint64_t w[ROWS][CH];
 #pragma unroll
@@ -564,11 +582,11 @@ __device__ __forceinline__ uint32_t search_dy(const uint64_t (&t)[NX], uint64_t*
   uint32_t key = 0xFFFFFFFFu;
   uint32_t acc[CPL];
   for (int st = 0; st < ndy; ++st) {
-    const bool more = st + 1 < ndy;
+    const bool more = !full && st + 1 < ndy;
     uint64_t pre[CH];
     if (more) load_row_dy<CH>(pre, img, pitch, W, H, x_first, y_top + st + ROWS, sw, lane);
     const int e = fwd ? st : ndy - 1 - st;
-    const uint64_t* srow = S + ((st + j) % NR) * SWr;
+    const uint64_t* srow = S + (full ? st + j : (st + j) % NR) * SWr;
     for (int ps = 0; ps < passes; ++ps) {
       if (j < ny) row_costs<NX, CPL>(t, srow + ps * PC + grp * CPL, rowmask, col_all, col_any, acc);
 #pragma unroll
@@ -586,9 +604,12 @@ __device__ __forceinline__ uint32_t search_dy(const uint64_t (&t)[NX], uint64_t*
       }
     }
     // the slot of row st - 1, which step st does not read
-    if (more) store_row_dy<CH>(S + ((st + ROWS) % NR) * SWr, pre, SWr, lane);
-    wave_sync();
+    if (more) {
+      store_row_dy<CH>(S + ((st + ROWS) % NR) * SWr, pre, SWr, lane);
+      wave_sync();
+    }
   }
+  wave_sync();   // every read of S and write of cost done before the caller goes on
   return key;
 }
 
@@ -607,7 +628,7 @@ __device__ __forceinline__ void match_block_dy(const MatchParamsDev& P, const Fr
   const int sw = nd + NX - 1;                  // words a row's candidates read
   auto r16 = [](size_t v) { return (v + 15) & ~(size_t)15; };
   uint64_t* S = (uint64_t*)lds;
-  uint64_t* T = (uint64_t*)((char*)lds + r16(sizeof(uint64_t) * (ROWS + 1) * SWr));
+  uint64_t* T = (uint64_t*)((char*)lds + r16(sizeof(uint64_t) * dy_lds_rows(ROWS, nd, ndy) * SWr));
   uint16_t* costf = (uint16_t*)((char*)T + r16(sizeof(uint64_t) * ROWS * NX));
   uint16_t* costb = (uint16_t*)((char*)costf + r16(sizeof(uint16_t) * (size_t)nd * ndy));
   const int j = lane % ROWS;

@@ -125,23 +125,51 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(pair_waves<
   }
 }
 
-// A level's work items with a vertical range: as match_tiled_kernel, with the dy block
-// matcher and an LDS share of wave_bytes per wave (dynamic, sized on the host)
-template <int ROWS, int NX>
-__global__ __launch_bounds__(256) void match_dy_kernel(MatchParamsDev P, FramesDev FR, MatchWs ws,
-                                                       DebugDev dbg, int level, int wave_bytes) {
+// Both levels with a vertical range in one launch: work items of every frame's close
+// level first, then of every far level (as match_pair_kernel), each wave with an LDS
+// share of wave_bytes (the larger of the two levels' needs). The two levels' blocks
+// overlap on the GPU, which outweighs the registers the combined kernel takes (measured
+// against one launch per level).
+template <int FROWS, int CROWS>
+__global__ __launch_bounds__(256) void match_dy_pair_kernel(MatchParamsDev P, FramesDev FR, MatchWs ws,
+                                                            DebugDev dbg, int wave_bytes) {
   extern __shared__ uint64_t dy_lds[];
+  __shared__ int prefix[2 * kMaxFrames + 1];
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int lane = threadIdx.x & 63;
+  const int F = FR.n;
+  if (threadIdx.x < 64) {
+    // prefix[j]: items before slot j; slot j < F is frame j's close level, else frame
+    // j - F's far level
+    const int j = lane < F ? lane : lane - F;
+    const int cnt = lane < 2 * F ? ws.fcount[j * FC_N + (lane < F ? FC_CLOSE_ITEMS : FC_FAR_ITEMS)] : 0;
+    const int incl = dev::wave_incl_scan(cnt, lane);
+    if (lane < 2 * F) prefix[lane + 1] = incl;
+    if (lane == 0) prefix[0] = 0;
+  }
+  __syncthreads();
   void* wl = (char*)dy_lds + (size_t)wave * wave_bytes;
-  dev::level_items(FR, ws, level, [&](int f, int q) {
+  const int total = prefix[2 * F];
+  for (int m = blockIdx.x; m < total; m += gridDim.x) {
+    int slot = 0;
+    for (int k = 1; k < 2 * F; ++k)
+      if (m >= prefix[k]) slot = k;
+    const int f = slot < F ? slot : slot - F;
     const FrameDev& fr = FR.f[f];
-    const int at = q + (level ? 0 : ws.fcount[f * FC_N + FC_CLOSE_ITEMS]);
+    const int q = m - prefix[slot];
+    // the frame's far items follow its close items in the records
+    const int at = q + (slot < F ? 0 : prefix[f + 1] - prefix[f]);
     const ItemRec r = ws.items[(size_t)f * ws.items_cap + at];
-    dev::run_item_rec(P, fr, f, level, r, wave, [&](const dev::BlockCtx& c) {
-      dev::match_block_dy<ROWS, NX>(P, fr, ws, dbg, c, lane, wl);
-    });
-  });
+    if (slot < F) {
+      dev::run_item_rec(P, fr, f, 1, r, wave, [&](const dev::BlockCtx& c) {
+        dev::match_block_dy<CROWS, CROWS>(P, fr, ws, dbg, c, lane, wl);
+      });
+    } else {
+      dev::run_item_rec(P, fr, f, 0, r, wave, [&](const dev::BlockCtx& c) {
+        dev::match_block_dy<FROWS, FROWS>(P, fr, ws, dbg, c, lane, wl);
+      });
+    }
+  }
 }
 
 __global__ __launch_bounds__(256) void aggregate_kernel(MatchParamsDev P, MatchWs ws,
@@ -247,20 +275,6 @@ static hipError_t launch_level(const MatchParamsDev& P, const FramesDev& FR, con
   return hipErrorNotSupported;   // rejected by the argument checks before any launch
 }
 
-static hipError_t launch_dy_level(const MatchParamsDev& P, const FramesDev& FR, const MatchWs& ws,
-                                  const DebugDev& dbg, int level, int grid, hipStream_t stream) {
-  const PathDev& v = P.path[level];
-  const int rows = dy_rows(v.bw, v.bh);
-  const size_t wave_bytes = dy_wave_lds_bytes(rows, v.nd, v.ndy);
-  const size_t bytes = kItemWaves * wave_bytes;
-  if (bytes > kDyMaxWgLds) return hipErrorInvalidValue;   // rejected by the argument checks
-  if (rows == 4)
-    match_dy_kernel<4, 4><<<grid, 256, bytes, stream>>>(P, FR, ws, dbg, level, (int)wave_bytes);
-  else
-    match_dy_kernel<8, 8><<<grid, 256, bytes, stream>>>(P, FR, ws, dbg, level, (int)wave_bytes);
-  return hipGetLastError();
-}
-
 // One launch for both levels when a kernel for the pair of variants is built (with
 // launch == false: only whether it is built).
 static bool launch_pair(const MatchParamsDev& P, const FramesDev& FR, const MatchWs& ws,
@@ -342,13 +356,24 @@ hipError_t launch_match(const MatchParamsDev& P, const FramesDev& FR, const ocsr
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if (P.vertical) {
-    for (int level = 1; level >= 0; --level) {
-      const char* name = level == 0 ? "match_far" : "match_close";
-      if (timer) timer->before(timer->ctx, name, stream);
-      e = launch_dy_level(P, FR, ws, dbg, level, n_match_wgs, stream);
-      if (timer) timer->after(timer->ctx, name, stream);
-      if (e != hipSuccess) return e;
-    }
+    // both levels in one launch
+    const int fr_rows = dy_rows(P.path[0].bw, P.path[0].bh), cr_rows = dy_rows(P.path[1].bw, P.path[1].bh);
+    const size_t wave_bytes = std::max(dy_wave_lds_bytes(fr_rows, P.path[0].nd, P.path[0].ndy),
+                                       dy_wave_lds_bytes(cr_rows, P.path[1].nd, P.path[1].ndy));
+    const size_t bytes = kItemWaves * wave_bytes;
+    if (bytes > kDyMaxWgLds) return hipErrorInvalidValue;   // rejected by the argument checks
+    const int wb = (int)wave_bytes;
+    if (timer) timer->before(timer->ctx, "match", stream);
+    if (fr_rows == 4 && cr_rows == 8)
+      match_dy_pair_kernel<4, 8><<<n_match_wgs, 256, bytes, stream>>>(P, FR, ws, dbg, wb);
+    else if (fr_rows == 8 && cr_rows == 8)
+      match_dy_pair_kernel<8, 8><<<n_match_wgs, 256, bytes, stream>>>(P, FR, ws, dbg, wb);
+    else if (fr_rows == 4 && cr_rows == 4)
+      match_dy_pair_kernel<4, 4><<<n_match_wgs, 256, bytes, stream>>>(P, FR, ws, dbg, wb);
+    else
+      match_dy_pair_kernel<8, 4><<<n_match_wgs, 256, bytes, stream>>>(P, FR, ws, dbg, wb);
+    if (timer) timer->after(timer->ctx, "match", stream);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
   } else if (launch_pair(P, FR, ws, dbg, n_match_wgs, stream, false)) {
     if (timer) timer->before(timer->ctx, "match", stream);
     launch_pair(P, FR, ws, dbg, n_match_wgs, stream, true);

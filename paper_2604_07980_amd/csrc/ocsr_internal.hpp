@@ -83,10 +83,17 @@ constexpr int kDyPass = 32;
 inline int dy_rows(int bw, int bh) { return bw <= 4 && bh <= 4 ? 4 : 8; }
 constexpr int dy_cpl(int rows) { return rows == 4 ? 2 : 4; }
 constexpr int dy_chunks(int rows) { return rows == 4 ? 5 : 3; }
-inline int dy_strip_words(int rows, int nd) { return (nd + kDyPass - 1) / kDyPass * kDyPass + rows - 1; }
+constexpr int dy_strip_words(int rows, int nd) { return (nd + kDyPass - 1) / kDyPass * kDyPass + rows - 1; }
+// When all ROWS + ndy - 1 strip rows of a direction fit kDyFullLoads loads per lane they
+// are staged at once (one round trip), else the ring of ROWS + 1 rows is used.
+constexpr int kDyFullLoads = 16;
+constexpr bool dy_full(int rows, int nd, int ndy) {
+  return (rows + ndy - 1) * dy_strip_words(rows, nd) <= 64 * kDyFullLoads;
+}
+constexpr int dy_lds_rows(int rows, int nd, int ndy) { return dy_full(rows, nd, ndy) ? rows + ndy - 1 : rows + 1; }
 inline size_t dy_wave_lds_bytes(int rows, int nd, int ndy) {
   auto r16 = [](size_t v) { return (v + 15) & ~(size_t)15; };
-  return r16(sizeof(uint64_t) * (rows + 1) * dy_strip_words(rows, nd)) +
+  return r16(sizeof(uint64_t) * dy_lds_rows(rows, nd, ndy) * dy_strip_words(rows, nd)) +
          r16(sizeof(uint64_t) * rows * rows) + 2 * r16(sizeof(uint16_t) * (size_t)nd * ndy);
 }
 constexpr size_t kDyMaxWgLds = 65536;   // LDS of one dy workgroup (kItemWaves waves)
