@@ -147,3 +147,19 @@ def test_vertical_rejected_arguments(lib):
         with pytest.raises(lib.OcsrError) as e:
             lib.match_boxes(*g, boxes, _with_dy(p, lo, hi))
         assert e.value.code == code, (lo, hi)
+
+
+@pytest.mark.parametrize("dy", [(-3, 3), (0, 4)])
+def test_vertical_ring_path_records(lib, orc, dy):
+    """Long strips (96 close candidates at s = 2) take the ring of strip rows rather than
+    staging every row at once: block records and cost rows against the oracle."""
+    p = _with_dy(synth.params_for(2), *dy)
+    p["tau_s"] = 40
+    sc = _drifted(2200 + dy[0], 200, 320, 6, dy[0] + 2)
+    (L0, R0, L1, R1), (res, blk, cf, cb, n) = orc.run_scene(sc.left, sc.right, p, sc.boxes,
+                                                            debug=True)
+    assert (blk["nd"][blk["level_scale"] == 2] == 96).all() and (blk["level_scale"] == 2).any()
+    g = _gpu_levels(lib, sc.left, sc.right, p)
+    out, extra = lib.match_boxes(*g, _cuda(sc.boxes), p, debug=True, cap_blocks=max(n, 1))
+    assert_results_match(lib.results_to_numpy(out), res)
+    _check_debug(lib, extra, blk, cf, cb, n)
