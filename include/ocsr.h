@@ -344,9 +344,9 @@ int32_t ocsr_range_batch(ocsr_ctx* ctx, const ocsr_frame* frames, int32_t n_fram
 /* ------------------------------------------------------------------------------ */
 /* Priority object selection under a budget (Sec. 4.3.5, last sentence)           */
 /* ------------------------------------------------------------------------------ */
-/* When a frame has more candidate objects than the budget, the frontal ones (in a
- * central crop) are ranged first and the remaining slots go to the others by
- * proximity. A candidate is a box with OCSR_BOX_RANGE whose clipped area is not empty.
+/* When a frame has more candidate objects than the budget, those in a central crop
+ * (frontal) take precedence and what is left of the budget goes to the others, nearest
+ * first. A candidate is a box with OCSR_BOX_RANGE whose clipped area is not empty.
  * Candidates are ordered by the key (not frontal, larger clipped bottom y first, lower
  * box index first): a larger bottom y is nearer the camera, the cue the occlusion rule
  * uses. Frontal: the centre of the clipped box, ((cx0 + cx1 - 1)/2, (cy0 + cy1 - 1)/2),

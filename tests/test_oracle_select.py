@@ -1,5 +1,5 @@
 """Pins of the oracle's priority object selection (Sec. 4.3.5, last sentence: over the
-budget, frontal objects in a central crop first, remaining slots by proximity). The
+budget, the objects in a central crop take precedence, then the nearest others). The
 paper gives no example, so the pins are a hand-worked frame, the special cases that fix
 the order by a library sort or make the selection the identity, and invariants of the
 rule."""
