@@ -160,7 +160,13 @@ __global__ __launch_bounds__(256) void match_dy_pair_kernel(MatchParamsDev P, Fr
     // the frame's far items follow its close items in the records
     const int at = q + (slot < F ? 0 : prefix[f + 1] - prefix[f]);
     const ItemRec r = ws.items[(size_t)f * ws.items_cap + at];
-    if (slot < F) {
+    if constexpr (FROWS == CROWS) {
+      // one matcher for both levels: a single inlined copy keeps the register count of
+      // the one-level kernel
+      dev::run_item_rec(P, fr, f, slot < F ? 1 : 0, r, wave, [&](const dev::BlockCtx& c) {
+        dev::match_block_dy<CROWS, CROWS>(P, fr, ws, dbg, c, lane, wl);
+      });
+    } else if (slot < F) {
       dev::run_item_rec(P, fr, f, 1, r, wave, [&](const dev::BlockCtx& c) {
         dev::match_block_dy<CROWS, CROWS>(P, fr, ws, dbg, c, lane, wl);
       });
@@ -356,8 +362,14 @@ hipError_t launch_match(const MatchParamsDev& P, const FramesDev& FR, const ocsr
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if (P.vertical) {
-    // both levels in one launch
-    const int fr_rows = dy_rows(P.path[0].bw, P.path[0].bh), cr_rows = dy_rows(P.path[1].bw, P.path[1].bh);
+    // both levels in one launch; when both fit the wider matcher (ROWS = 8, which also
+    // takes 4 x 4 blocks, half its lanes idle) it serves both levels
+    int fr_rows = dy_rows(P.path[0].bw, P.path[0].bh), cr_rows = dy_rows(P.path[1].bw, P.path[1].bh);
+    auto fits8 = [](const PathDev& ph) {
+      return dy_strip_words(8, ph.nd) <= 64 * dy_chunks(8) &&
+             kItemWaves * dy_wave_lds_bytes(8, ph.nd, ph.ndy) <= kDyMaxWgLds;
+    };
+    if (fr_rows != cr_rows && fits8(P.path[0]) && fits8(P.path[1])) fr_rows = cr_rows = 8;
     const size_t wave_bytes = std::max(dy_wave_lds_bytes(fr_rows, P.path[0].nd, P.path[0].ndy),
                                        dy_wave_lds_bytes(cr_rows, P.path[1].nd, P.path[1].ndy));
     const size_t bytes = kItemWaves * wave_bytes;
