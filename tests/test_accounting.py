@@ -81,8 +81,9 @@ def test_rule_covers_reads_of_the_realistic_frame(orc):
     assert read <= rule, sorted(read - rule)[:5]
 
 
+@pytest.mark.parametrize("scale", [2, 3])
 @pytest.mark.parametrize("dy", [(-3, 3), (-6, -2), (1, 5)])
-def test_rule_covers_vertical_reads(orc, dy):
+def test_rule_covers_vertical_reads(orc, dy, scale):
     """With a vertical range the searches read rows above and below the box: boxes along
     tile rows and the image's top and bottom edges, right view drifted."""
     rng = np.random.default_rng(40 + dy[0])
@@ -92,6 +93,7 @@ def test_rule_covers_vertical_reads(orc, dy):
     p = synth.params_for(2)
     p["far"]["dmax"], p["close"]["dmax"] = 31, 63
     p["dy_min"], p["dy_max"] = dy
+    p["close_scale"] = scale
     boxes = np.array([[40, 0, 70, 28, 1], [100, 26, 130, 40, 1], [150, 60, 260, 130, 1],
                       [300, 150, 340, 200, 1], [20, 120, 120, 200, 1], [330, 30, 390, 62, 1]],
                      np.int32)

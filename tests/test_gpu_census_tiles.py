@@ -114,12 +114,13 @@ def test_frame_makes_the_tiles_boxes_read(lib, orc, variant, seed, listed):
 
 
 @pytest.mark.parametrize("listed", [True, False], ids=["listed", "per_tile"])
-@pytest.mark.parametrize("dy", [(-3, 2), (1, 4)])
-def test_frame_tiles_with_vertical_range(lib, orc, dy, listed):
+@pytest.mark.parametrize("dy,scale", [((-3, 2), 2), ((1, 4), 2), ((-5, 4), 3)])
+def test_frame_tiles_with_vertical_range(lib, orc, dy, scale, listed):
     """A vertical range widens the rows the searches read: the tiles made follow the
     widened rule, edge boxes included, and the results still equal the oracle's."""
     p = _params("tiled_trim")
     p["dy_min"], p["dy_max"] = dy
+    p["close_scale"] = scale
     sc = synth.scene_small(830 + dy[0], H=160, W=300, n_planes=4)
     boxes = np.concatenate([sc.boxes.reshape(-1, 5), _edge_boxes(160, 300, p["tau_s"])]).astype(np.int32)
     right = synth.drift_rows(sc.right, dy[0])

@@ -163,3 +163,22 @@ def test_vertical_ring_path_records(lib, orc, dy):
     out, extra = lib.match_boxes(*g, _cuda(sc.boxes), p, debug=True, cap_blocks=max(n, 1))
     assert_results_match(lib.results_to_numpy(out), res)
     _check_debug(lib, extra, blk, cf, cb, n)
+
+
+@pytest.mark.parametrize("dy", [(-4, 2), (1, 5)])
+def test_vertical_close_scale_3(lib, orc, dy):
+    """Close level at scale 3: level offsets floor(dy_min / 3) .. ceil(dy_max / 3)."""
+    p = _with_dy(_params("tiled_trim"), *dy)
+    p.update(close_scale=3, tau_s=40)
+    sc = _drifted(2300 + dy[0], 150, 240, 6, dy[1])
+    (L0, R0, L1, R1), (res, blk, cf, cb, n) = orc.run_scene(sc.left, sc.right, p, sc.boxes,
+                                                            debug=True)
+    assert (blk["level_scale"] == 3).any()
+    s = 3
+    g = lib.census_many([_cuda(sc.left), _cuda(sc.right), _cuda(sc.left), _cuda(sc.right)],
+                        [1, 1, s, s], p["sx"], p["sy"], p["sentinel"])
+    out, extra = lib.match_boxes(*g, _cuda(sc.boxes), p, debug=True, cap_blocks=max(n, 1))
+    assert_results_match(lib.results_to_numpy(out), res)
+    _check_debug(lib, extra, blk, cf, cb, n)
+    got = lib.results_to_numpy(lib.range_frame(_cuda(sc.left), _cuda(sc.right), _cuda(sc.boxes), p))
+    assert_results_match(got, res)
