@@ -532,7 +532,7 @@ int32_t ocsr_rect_offset_counts(ocsr_ctx* ctx, const ocsr_level* lv, const ocsr_
   LevelDev L;
   if ((rc = check_level(lv, "lv", &L)) != OCSR_OK) return rc;
   if (!counts) return fail(OCSR_E_INVALID, "null counts");
-  if (p->delta_min > p->delta_max || p->delta_max - p->delta_min + 1 > OCSR_MAX_RECT_OFFSETS)
+  if (p->delta_min > p->delta_max || (int64_t)p->delta_max - p->delta_min + 1 > OCSR_MAX_RECT_OFFSETS)
     return fail(OCSR_E_INVALID, "offsets [%d, %d]: 1..%d of them", p->delta_min, p->delta_max,
                 OCSR_MAX_RECT_OFFSETS);
   if (p->roi_w <= 0 || p->roi_h <= 0 || (int64_t)p->roi_w * p->roi_h > (1 << 26))
@@ -543,8 +543,8 @@ int32_t ocsr_rect_offset_counts(ocsr_ctx* ctx, const ocsr_level* lv, const ocsr_
                 p->roi_x0, p->roi_x0 + p->roi_w, p->roi_y0, p->roi_y0 + p->roi_h, p->delta_min,
                 p->delta_max, L.W, L.H);
   if (p->dmin < 0 || p->dmax < p->dmin) return fail(OCSR_E_INVALID, "disparity range [%d, %d] invalid", p->dmin, p->dmax);
-  if (p->dmax - p->dmin + 1 > OCSR_MAX_CANDIDATES)
-    return fail(OCSR_E_CAPACITY, "%d candidates > %d", p->dmax - p->dmin + 1, OCSR_MAX_CANDIDATES);
+  if ((int64_t)p->dmax - p->dmin + 1 > OCSR_MAX_CANDIDATES)
+    return fail(OCSR_E_CAPACITY, "[%d, %d]: more than %d candidates", p->dmin, p->dmax, OCSR_MAX_CANDIDATES);
   if (!dense_radius_supported(p->radius))
     return fail(OCSR_E_UNSUPPORTED, "window radius %d: only 1..3 are built", p->radius);
   if (p->lr_tol < 0 || p->d_min < 0) return fail(OCSR_E_INVALID, "lr_tol and d_min must be >= 0");
