@@ -52,12 +52,29 @@ def test_abi_version_and_host_only_calls(built):
     assert built.ocsr_frame_workspace_bytes(0, 1080, C.byref(fp), 32, 1 << 16) == 0
 
 
+def test_rect_workspace_sizing(built):
+    """Host arithmetic: three int16 maps per offset plus the partial counts, each block
+    256-byte aligned; 0 for an invalid description."""
+    rp = ocsr.RectParams(0, 10, 100, 20, -2, 2, 0, 31, 2, 1, 0)
+    maps = 3 * 5 * 100 * 20 * 2
+    parts = 5 * 20 * 1 * 4
+    a256 = lambda v: (v + 255) // 256 * 256
+    assert built.ocsr_rect_workspace_bytes(C.byref(rp)) == a256(maps) + a256(parts)
+    for bad in (dict(roi_w=0), dict(delta_min=3), dict(delta_min=-40, delta_max=40)):
+        q = ocsr.RectParams(0, 10, 100, 20, -2, 2, 0, 31, 2, 1, 0)
+        for k, v in bad.items():
+            setattr(q, k, v)
+        assert built.ocsr_rect_workspace_bytes(C.byref(q)) == 0
+
+
 def test_struct_sizes_match_header():
     assert C.sizeof(ocsr.MatchParams) == 4 + 4 + 2 * 24 + 3 * 4 + 4 + 2 * 4 + 3 * 4 + 2 * 4
     assert C.sizeof(ocsr.Level) == 2 * 8 + 6 * 4
     assert C.sizeof(ocsr.CensusJob) == 2 * 8 + 6 * 4
     assert C.sizeof(ocsr.Debug) == 2 * 4 + 4 * 8
     assert ocsr.BLOCK_RECORD_DTYPE.itemsize == 80
+    assert C.sizeof(ocsr.SelectParams) == 5 * 4
+    assert C.sizeof(ocsr.RectParams) == 11 * 4
 
 
 def test_header_constants_match_binding():
@@ -68,6 +85,8 @@ def test_header_constants_match_binding():
     assert const("OCSR_MAX_CANDIDATES") == ocsr.MAX_CANDIDATES
     assert const("OCSR_MAX_DY") == ocsr.MAX_DY
     assert const("OCSR_MAX_DY_CANDIDATES") == ocsr.MAX_DY_CANDIDATES
+    assert const("OCSR_MAX_SELECT_BOXES") == ocsr.MAX_SELECT_BOXES
+    assert const("OCSR_MAX_RECT_OFFSETS") == ocsr.MAX_RECT_OFFSETS
     assert const("OCSR_MAX_CENSUS_JOBS") == ocsr.MAX_CENSUS_JOBS
     for k, name in enumerate(ocsr.REASONS):
         assert const(f"OCSR_REASON_{name}") == k
