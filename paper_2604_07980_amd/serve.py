@@ -182,15 +182,20 @@ class GpuExecutor:
     A batch's workspace, boxes and results are allocated when it is submitted and
     released when it is collected, so the memory the server accounts for is what the
     batches in flight hold (allocations come from the framework's caching allocator).
-    Box lists are staged through pinned host memory."""
+    Box lists are staged through pinned host memory. With max_objects set, each frame's
+    boxes first go through the priority selection (ocsr_select_boxes): candidates past
+    the budget keep occluding but are not ranged (reason NOT_RANGED)."""
 
-    def __init__(self, n_slots: int = 3, device: str = "cuda:0", cap_blocks: int = 1 << 18):
+    def __init__(self, n_slots: int = 3, device: str = "cuda:0", cap_blocks: int = 1 << 18,
+                 max_objects: int | None = None, crop_permille=None):
         import torch
         from . import ocsr
         self.torch, self.ocsr = torch, ocsr
         self.dev = torch.device(device)
         self.n_slots = n_slots
         self.cap_blocks = cap_blocks
+        self.max_objects = max_objects
+        self.crop = tuple(crop_permille) if crop_permille is not None else ocsr.DEFAULT_CROP_PERMILLE
         self.streams = [torch.cuda.Stream(self.dev) for _ in range(n_slots)]
         self.events = [None] * n_slots
         self.outs = [None] * n_slots
@@ -200,8 +205,9 @@ class GpuExecutor:
     def bytes_needed(self, reqs) -> int:
         shapes = [(r.shape[0], r.shape[1], len(r.boxes)) for r in reqs]
         nb = sum(len(r.boxes) for r in reqs)
+        sel = nb * (5 * 4 + 4) if self.max_objects is not None else 0   # selected boxes, ranks
         return (self.ocsr.batch_workspace_bytes(shapes, reqs[0].params, self.cap_blocks)
-                + nb * (5 * 4 + 8 * 4))
+                + nb * (5 * 4 + 8 * 4) + sel)
 
     def submit(self, slot: int, reqs) -> None:
         torch, ocsr = self.torch, self.ocsr
@@ -213,13 +219,17 @@ class GpuExecutor:
             out = torch.empty((boxes.shape[0], 8), dtype=torch.int32, device=self.dev)
             frames = [(r.left, r.right, len(r.boxes)) for r in reqs]
             ws = ocsr.Workspace()
+            boxes_in = boxes
+            if boxes.shape[0] > 0 and self.max_objects is not None:
+                boxes, _ = ocsr.select_boxes([(r.shape[1], r.shape[0], len(r.boxes)) for r in reqs],
+                                             boxes_in, self.max_objects, self.crop)
             if boxes.shape[0] > 0:
                 ocsr.range_batch(frames, boxes, reqs[0].params, cap_blocks=self.cap_blocks,
                                  workspace=ws, out=out)
             ev = torch.cuda.Event()
             ev.record(s)
         self.events[slot], self.outs[slot], self.reqs[slot] = ev, out, reqs
-        self.keep[slot] = (boxes_h, boxes, ws)   # held until the batch is collected
+        self.keep[slot] = (boxes_h, boxes_in, boxes, ws)   # held until the batch is collected
 
     def poll(self, slot: int) -> bool:
         return self.events[slot].query()

@@ -61,3 +61,21 @@ def test_budget_refuses_oversized_request(lib):
     res = srv.run(reqs)
     assert res[0].error is not None
     assert all(r.error is None for r in res[1:])
+
+
+def test_served_with_object_budget(lib, orc):
+    """With a per-frame budget the executor selects before ranging: every served result
+    equals the oracle's on the oracle's own selection of that request's boxes."""
+    reqs, host = _stream(30, seed=91)
+    ex = serve.GpuExecutor(n_slots=2, max_objects=6)
+    srv = serve.Server(ex, mem_budget=4 << 30)
+    res = srv.run(reqs)
+    n_dropped = 0
+    for q in reqs[::3]:
+        Lh, Rh = host[q.rid]
+        H, W = Lh.shape
+        sel, rank = orc.select_boxes(q.boxes, W, H, 6, lib.DEFAULT_CROP_PERMILLE)
+        want = orc.run_scene(Lh, Rh, q.params, sel)[1][0]
+        assert_results_match(res[q.rid].boxes, want)
+        n_dropped += int((rank >= 6).sum())
+    assert n_dropped > 0                                   # the budget did bind
