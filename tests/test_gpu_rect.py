@@ -83,3 +83,29 @@ def test_rect_rejects_bad_arguments(lib):
     with pytest.raises(lib.OcsrError) as e:
         lib.rect_offset_counts(CL, CR, dict(base, radius=4))
     assert e.value.code == lib.E_UNSUPPORTED
+
+
+def test_rect_estimate_drives_the_vertical_offset(lib, orc):
+    """The estimate feeds the matcher: the road pair's right view is 6 rows low; the
+    offset search at s = 2 finds 3 level rows, i.e. 6 px, and ranging with dy fixed at
+    6 px equals the oracle and validates nearly every block, where dy = 0 does not."""
+    left, right = synth.road_pair(drift=6)
+    p = dict(roi_x0=0, roi_y0=300, roi_w=960, roi_h=128, delta_min=-4, delta_max=4, dmin=0,
+             dmax=63, radius=2, lr_tol=1, d_min=2)
+    CLg, CRg = _desc(lib, left, right, 2)
+    counts = lib.rect_offset_counts(CLg, CRg, p).cpu().numpy()
+    raw, _ = lib.RectFilter(1, 100).update(counts, p["delta_min"])
+    dy = 2 * raw
+    assert dy == 6
+    boxes = np.array([[100, 620, 260, 700, 1], [500, 700, 760, 820, 1], [900, 560, 960, 600, 1],
+                      [1300, 800, 1700, 1000, 1], [1600, 600, 1650, 640, 1],
+                      [300, 900, 700, 1060, 1]], np.int32)
+    mp = synth.params_for(2)
+    mp["dy_min"] = mp["dy_max"] = dy
+    got = lib.results_to_numpy(lib.range_frame(_cuda(left), _cuda(right), _cuda(boxes), mp))
+    want = orc.run_scene(left, right, mp, boxes)[1][0]
+    from test_gpu_parity import assert_results_match
+    assert_results_match(got, want)
+    assert (got["n_valid"] >= 0.9 * got["n_blocks"]).all()
+    plain = orc.run_scene(left, right, synth.params_for(2), boxes)[1][0]
+    assert plain["n_valid"].sum() < 0.6 * got["n_valid"].sum()
