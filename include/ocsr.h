@@ -182,8 +182,9 @@ typedef struct {
    * The backward search starts at the forward match (x - d_f, y + dy_f) and visits
    * (d, dy) at (x - d_f + d, y + dy_f - dy); the L/R check compares d_b with d_f only.
    * Limits with a vertical range: nd * ndy <= OCSR_MAX_DY_CANDIDATES per path, and
-   * the path's working set must fit a workgroup's LDS (a 96-candidate 8 x 8 path takes
-   * up to 16 dy values); beyond them the call returns OCSR_E_UNSUPPORTED. Rows outside
+   * the path's working set must fit a workgroup's LDS (an 8 x 8 path takes up to 21
+   * level offsets with 96 candidates, 12 with 128, and at most 160 candidates); beyond
+   * them the call returns OCSR_E_UNSUPPORTED. Rows outside
    * the level image read as all-zero descriptors, as columns do. */
   int32_t dy_min, dy_max;
 } ocsr_match_params;

@@ -90,3 +90,25 @@ def test_header_constants_match_binding():
     assert const("OCSR_MAX_CENSUS_JOBS") == ocsr.MAX_CENSUS_JOBS
     for k, name in enumerate(ocsr.REASONS):
         assert const(f"OCSR_REASON_{name}") == k
+
+
+def test_vertical_limits_stated_in_the_header():
+    """The header's vertical-range limits for 8 x 8 paths, restated from the per-wave LDS
+    rule: a 1/4 workgroup share of 64 KB holds the strip rows (all ROWS + ndy - 1 when they
+    fit 16 loads per lane, else a ring of ROWS + 1), the template and two uint16 cost
+    tables; and nd * ndy <= OCSR_MAX_DY_CANDIDATES."""
+    def r16(v):
+        return (v + 15) // 16 * 16
+
+    def strip(rows, nd):
+        return -(-nd // 32) * 32 + rows - 1
+
+    def lds(rows, nd, ndy):
+        full = (rows + ndy - 1) * strip(rows, nd) <= 64 * 16
+        lr = rows + ndy - 1 if full else rows + 1
+        return r16(8 * lr * strip(rows, nd)) + r16(8 * rows * rows) + 2 * r16(2 * nd * ndy)
+
+    def most(nd):
+        return max(n for n in range(1, 200) if nd * n <= ocsr.MAX_DY_CANDIDATES and 4 * lds(8, nd, n) <= 65536)
+    assert most(96) == 21 and most(128) == 12
+    assert strip(8, 160) <= 3 * 64 < strip(8, 161)

@@ -147,6 +147,13 @@ def test_vertical_rejected_arguments(lib):
         with pytest.raises(lib.OcsrError) as e:
             lib.match_boxes(*g, boxes, _with_dy(p, lo, hi))
         assert e.value.code == code, (lo, hi)
+    # the stated limit of an 8 x 8 path with 96 candidates: 21 level offsets run (dy +-20
+    # at s = 2), 23 do not
+    out = lib.match_boxes(*g, boxes, _with_dy(synth.base_params(), -20, 20))
+    assert out.shape == (1, 8)
+    with pytest.raises(lib.OcsrError) as e:
+        lib.match_boxes(*g, boxes, _with_dy(synth.base_params(), -22, 22))
+    assert e.value.code == lib.E_UNSUPPORTED
 
 
 @pytest.mark.parametrize("dy", [(-3, 3), (0, 4)])
