@@ -104,7 +104,22 @@ void timer_after(void* ctx, const char* name, hipStream_t s) {
   c->open_start = nullptr;
 }
 
-LaunchTimer make_timer(ocsr_ctx* c) { return LaunchTimer{c, timer_before, timer_after}; }
+bool timer_pair(void* ctx, const char* name, hipEvent_t* start, hipEvent_t* stop) {
+  ocsr_ctx* c = (ocsr_ctx*)ctx;
+  hipEvent_t a = take_event(c);
+  if (!a) return false;
+  hipEvent_t b = take_event(c);
+  if (!b) {
+    c->free_events.push_back(a);
+    return false;
+  }
+  c->pending.push_back({name, a, b});
+  *start = a;
+  *stop = b;
+  return true;
+}
+
+LaunchTimer make_timer(ocsr_ctx* c) { return LaunchTimer{c, timer_before, timer_after, timer_pair}; }
 
 int64_t cdiv64(int64_t a, int64_t b) { return (a + b - 1) / b; }
 

@@ -253,13 +253,13 @@ MatchVariant pick_variant(const PathDev& ph) {
 }
 
 static hipError_t launch_level(const MatchParamsDev& P, const FramesDev& FR, const MatchWs& ws,
-                               const DebugDev& dbg, int level, int grid, hipStream_t stream) {
+                               const DebugDev& dbg, int level, int grid, hipStream_t stream,
+                               const LaunchTimer* timer, const char* name) {
   const PathDev& v = P.path[level];
 #define OCSR_TILED(R, X, C, PS)                                                             \
-  if (v.rows == R && v.cpl == C && v.passes == PS) {                                        \
-    match_tiled_kernel<R, X, C, PS><<<grid, 256, 0, stream>>>(P, FR, ws, dbg, level);       \
-    return hipGetLastError();                                                               \
-  }
+  if (v.rows == R && v.cpl == C && v.passes == PS)                                          \
+    return timed_launch(timer, name, match_tiled_kernel<R, X, C, PS>, dim3(grid), dim3(256), 0, \
+                        stream, P, FR, ws, dbg, level);
   OCSR_TILED(4, 4, 2, 1)
   OCSR_TILED(4, 4, 4, 1)
   OCSR_TILED(4, 4, 8, 1)
@@ -284,14 +284,16 @@ static hipError_t launch_level(const MatchParamsDev& P, const FramesDev& FR, con
 // One launch for both levels when a kernel for the pair of variants is built (with
 // launch == false: only whether it is built).
 static bool launch_pair(const MatchParamsDev& P, const FramesDev& FR, const MatchWs& ws,
-                        const DebugDev& dbg, int grid, hipStream_t stream, bool launch) {
+                        const DebugDev& dbg, int grid, hipStream_t stream, const LaunchTimer* timer,
+                        bool launch) {
   const PathDev& f = P.path[0];
   const PathDev& c = P.path[1];
   if (f.passes != 1) return false;
 #define OCSR_PAIR(FRW, FXW, FCP, CRW, CXW, CCP, CPS)                                     \
   if (f.rows == FRW && f.cpl == FCP && c.rows == CRW && c.cpl == CCP && c.passes == CPS) { \
     if (launch)                                                                          \
-      match_pair_kernel<FRW, FXW, FCP, CRW, CXW, CCP, CPS><<<grid, 256, 0, stream>>>(P, FR, ws, dbg); \
+      timed_launch(timer, "match", match_pair_kernel<FRW, FXW, FCP, CRW, CXW, CCP, CPS>,    \
+                   dim3(grid), dim3(256), 0, stream, P, FR, ws, dbg);                     \
     return true;                                                                         \
   }
   OCSR_PAIR(4, 4, 2, 8, 8, 8, 1)
@@ -335,18 +337,12 @@ hipError_t launch_frame_census(const MatchParamsDev& P, const FramesDev& FR,
   // 16-frame batch faster listed)
   const int listed = use_list && n_census_tiles <= 32 * kCensusListWords && 8 * G <= n_census_tiles;
   const dim3 grid(FR.n + (listed ? G : n_census_tiles)), block(256);
-  if (timer) timer->before(timer->ctx, "census", stream);
-  if (sx == 3 && sy == 4) {
-    frame_census_kernel<3, 4><<<grid, block, 0, stream>>>(P, FR, boxes, ws, sx, sy, sentinel, n_census_tiles, listed);
-  } else if (sx == 2 && sy == 2) {
-    frame_census_kernel<2, 2><<<grid, block, 0, stream>>>(P, FR, boxes, ws, sx, sy, sentinel, n_census_tiles, listed);
-  } else if (sx == 4 && sy == 3) {
-    frame_census_kernel<4, 3><<<grid, block, 0, stream>>>(P, FR, boxes, ws, sx, sy, sentinel, n_census_tiles, listed);
-  } else {
-    frame_census_kernel<-1, -1><<<grid, block, 0, stream>>>(P, FR, boxes, ws, sx, sy, sentinel, n_census_tiles, listed);
-  }
-  if (timer) timer->after(timer->ctx, "census", stream);
-  return hipGetLastError();
+  auto kernel = sx == 3 && sy == 4   ? frame_census_kernel<3, 4>
+                : sx == 2 && sy == 2 ? frame_census_kernel<2, 2>
+                : sx == 4 && sy == 3 ? frame_census_kernel<4, 3>
+                                     : frame_census_kernel<-1, -1>;
+  return timed_launch(timer, "census", kernel, grid, block, 0, stream, P, FR, boxes, ws, sx, sy,
+                      sentinel, n_census_tiles, listed);
 }
 
 hipError_t launch_match(const MatchParamsDev& P, const FramesDev& FR, const ocsr_box* boxes,
@@ -375,36 +371,26 @@ hipError_t launch_match(const MatchParamsDev& P, const FramesDev& FR, const ocsr
     const size_t bytes = kItemWaves * wave_bytes;
     if (bytes > kDyMaxWgLds) return hipErrorInvalidValue;   // rejected by the argument checks
     const int wb = (int)wave_bytes;
-    if (timer) timer->before(timer->ctx, "match", stream);
-    if (fr_rows == 4 && cr_rows == 8)
-      match_dy_pair_kernel<4, 8><<<n_match_wgs, 256, bytes, stream>>>(P, FR, ws, dbg, wb);
-    else if (fr_rows == 8 && cr_rows == 8)
-      match_dy_pair_kernel<8, 8><<<n_match_wgs, 256, bytes, stream>>>(P, FR, ws, dbg, wb);
-    else if (fr_rows == 4 && cr_rows == 4)
-      match_dy_pair_kernel<4, 4><<<n_match_wgs, 256, bytes, stream>>>(P, FR, ws, dbg, wb);
-    else
-      match_dy_pair_kernel<8, 4><<<n_match_wgs, 256, bytes, stream>>>(P, FR, ws, dbg, wb);
-    if (timer) timer->after(timer->ctx, "match", stream);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-  } else if (launch_pair(P, FR, ws, dbg, n_match_wgs, stream, false)) {
-    if (timer) timer->before(timer->ctx, "match", stream);
-    launch_pair(P, FR, ws, dbg, n_match_wgs, stream, true);
-    if (timer) timer->after(timer->ctx, "match", stream);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    auto kernel = fr_rows == 4 && cr_rows == 8   ? match_dy_pair_kernel<4, 8>
+                  : fr_rows == 8 && cr_rows == 8 ? match_dy_pair_kernel<8, 8>
+                  : fr_rows == 4 && cr_rows == 4 ? match_dy_pair_kernel<4, 4>
+                                                 : match_dy_pair_kernel<8, 4>;
+    e = timed_launch(timer, "match", kernel, dim3(n_match_wgs), dim3(256), bytes, stream, P, FR, ws,
+                     dbg, wb);
+    if (e != hipSuccess) return e;
+  } else if (launch_pair(P, FR, ws, dbg, n_match_wgs, stream, nullptr, false)) {
+    e = launch_pair(P, FR, ws, dbg, n_match_wgs, stream, timer, true) ? hipGetLastError() : hipErrorNotSupported;
+    if (e != hipSuccess) return e;
   } else {
     // close blocks first: they carry most of the work
     for (int level = 1; level >= 0; --level) {
-      const char* name = level == 0 ? "match_far" : "match_close";
-      if (timer) timer->before(timer->ctx, name, stream);
-      e = launch_level(P, FR, ws, dbg, level, n_match_wgs, stream);
-      if (timer) timer->after(timer->ctx, name, stream);
+      e = launch_level(P, FR, ws, dbg, level, n_match_wgs, stream, timer,
+                       level == 0 ? "match_far" : "match_close");
       if (e != hipSuccess) return e;
     }
   }
-  if (timer) timer->before(timer->ctx, "aggregate", stream);
-  aggregate_kernel<<<FR.n_boxes_total, 256, 0, stream>>>(P, ws, out);
-  if (timer) timer->after(timer->ctx, "aggregate", stream);
-  return hipGetLastError();
+  return timed_launch(timer, "aggregate", aggregate_kernel, dim3(FR.n_boxes_total), dim3(256), 0,
+                      stream, P, ws, out);
 }
 
 }  // namespace ocsr

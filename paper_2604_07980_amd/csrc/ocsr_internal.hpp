@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <cstddef>
 #include <cstdint>
@@ -193,7 +194,24 @@ struct LaunchTimer {
   void* ctx;
   void (*before)(void* ctx, const char* name, hipStream_t s);
   void (*after)(void* ctx, const char* name, hipStream_t s);
+  // two events for one launch to carry, registered under `name` (false: none left)
+  bool (*pair)(void* ctx, const char* name, hipEvent_t* start, hipEvent_t* stop);
 };
+
+// kernel<<<grid, block, shmem, s>>>(args...). With a timer the launch carries its own
+// start and stop events, which the GPU stamps when the kernel starts and ends, so the
+// time is the kernel's own, not the dispatch gap around it as with events recorded on the
+// stream before and after.
+template <typename... KArgs, typename... Args>
+hipError_t timed_launch(const LaunchTimer* timer, const char* name, void (*kernel)(KArgs...),
+                        dim3 grid, dim3 block, size_t shmem, hipStream_t s, Args... args) {
+  hipEvent_t a = nullptr, b = nullptr;
+  if (timer && timer->pair && timer->pair(timer->ctx, name, &a, &b))
+    hipExtLaunchKernelGGL(kernel, grid, block, (uint32_t)shmem, s, a, b, 0, static_cast<KArgs>(args)...);
+  else
+    hipLaunchKernelGGL(kernel, grid, block, shmem, s, static_cast<KArgs>(args)...);
+  return hipGetLastError();
+}
 
 // Kernel variant of one level's blocks: the register-blocked TILED kernel with `rows`
 // block rows per wave (4: blocks up to 4 x 4, 8: up to 8 x 8), `cpl` consecutive
