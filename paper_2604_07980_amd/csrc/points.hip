@@ -53,10 +53,8 @@ hipError_t launch_box_points(const ocsr_box* boxes, const ocsr_box_result* res, 
                              const PointParamsDev& pp, ocsr_box_point* out, hipStream_t stream,
                              const LaunchTimer* timer) {
   if (n <= 0) return hipSuccess;
-  if (timer) timer->before(timer->ctx, "points", stream);
-  box_points_kernel<<<(n + 255) / 256, 256, 0, stream>>>(boxes, res, n, pp, out);
-  if (timer) timer->after(timer->ctx, "points", stream);
-  return hipGetLastError();
+  return timed_launch(timer, "points", box_points_kernel, dim3((n + 255) / 256), dim3(256), 0, stream,
+                      boxes, res, n, pp, out);
 }
 
 }  // namespace ocsr

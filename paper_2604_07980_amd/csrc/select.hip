@@ -55,10 +55,8 @@ __global__ __launch_bounds__(256) void select_kernel(SelectDev S, const ocsr_box
 hipError_t launch_select(const SelectDev& S, const ocsr_box* in, ocsr_box* out, int32_t* rank,
                          int max_boxes, hipStream_t stream, const LaunchTimer* timer) {
   if (max_boxes <= 0) return hipSuccess;
-  if (timer) timer->before(timer->ctx, "select", stream);
-  select_kernel<<<dim3((max_boxes + 255) / 256, S.n), 256, 0, stream>>>(S, in, out, rank);
-  if (timer) timer->after(timer->ctx, "select", stream);
-  return hipGetLastError();
+  return timed_launch(timer, "select", select_kernel, dim3((max_boxes + 255) / 256, S.n), dim3(256),
+                      0, stream, S, in, out, rank);
 }
 
 }  // namespace ocsr
