@@ -189,3 +189,28 @@ def test_vertical_close_scale_3(lib, orc, dy):
     _check_debug(lib, extra, blk, cf, cb, n)
     got = lib.results_to_numpy(lib.range_frame(_cuda(sc.left), _cuda(sc.right), _cuda(sc.boxes), p))
     assert_results_match(got, res)
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_vertical_random_cases(lib, orc, seed):
+    """Seeded random path shapes, ranges, drifts and scales, block records included."""
+    rng = np.random.default_rng(4000 + seed)
+    variant = TILED[seed % len(TILED)]
+    lo = int(rng.integers(-6, 4))
+    hi = lo + int(rng.integers(0, 7))
+    p = _with_dy(_params(variant), lo, hi)
+    p["tau_s"] = int(rng.integers(24, 64))
+    p["close_scale"] = int(rng.choice([2, 3]))
+    p["close"] = dict(p["close"], dmax=int(rng.integers(p["close"]["dmin"] + 4, 120)))
+    H, W = int(rng.integers(96, 200)), int(rng.integers(128, 320))
+    sc = _drifted(4100 + seed, H, W, int(rng.integers(2, 9)), int(rng.integers(-4, 5)))
+    (L0, R0, L1, R1), (res, blk, cf, cb, n) = orc.run_scene(sc.left, sc.right, p, sc.boxes,
+                                                            debug=True)
+    s = p["close_scale"]
+    g = lib.census_many([_cuda(sc.left), _cuda(sc.right), _cuda(sc.left), _cuda(sc.right)],
+                        [1, 1, s, s], p["sx"], p["sy"], p["sentinel"])
+    out, extra = lib.match_boxes(*g, _cuda(sc.boxes), p, debug=True, cap_blocks=max(n, 1))
+    assert_results_match(lib.results_to_numpy(out), res)
+    _check_debug(lib, extra, blk, cf, cb, n)
+    got = lib.results_to_numpy(lib.range_frame(_cuda(sc.left), _cuda(sc.right), _cuda(sc.boxes), p))
+    assert_results_match(got, res)
