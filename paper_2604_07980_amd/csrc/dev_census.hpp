@@ -239,7 +239,7 @@ template <int SX, int SY>
 __device__ __forceinline__ void frame_census_tile(const MatchParamsDev& MP, const FramesDev& FR,
                                                   const ocsr_box* __restrict__ boxes, int c,
                                                   int sx, int sy, int sentinel, uint32_t* P,
-                                                  bool check = true) {
+                                                  bool check = true, int* verdict = nullptr) {
   int f = 0;
   for (int k = 1; k < FR.n; ++k)
     if (c >= FR.f[k].tile_begin) f = k;
@@ -259,7 +259,21 @@ __device__ __forceinline__ void frame_census_tile(const MatchParamsDev& MP, cons
   const uint8_t* img = view ? fr.imgR : fr.imgL;
   uint64_t* out = (uint64_t*)(view ? lv.R : lv.L);
   const int X0 = (t % tiles_x) * kCensusTileX, Y0 = (t / tiles_x) * kCensusTileY;
-  if (check && !MP.full_census && !census_tile_needed(MP, fr, boxes, level, view, X0, Y0)) return;
+  if (check && !MP.full_census) {
+    bool needed;
+    if (verdict) {
+      // wave 0 tests the tile and shares the verdict through LDS (verdict must not alias P)
+      if (threadIdx.x < 64) {
+        const bool v = census_tile_needed(MP, fr, boxes, level, view, X0, Y0);
+        if (threadIdx.x == 0) *verdict = v ? 1 : 0;
+      }
+      __syncthreads();
+      needed = *verdict != 0;
+    } else {
+      needed = census_tile_needed(MP, fr, boxes, level, view, X0, Y0);
+    }
+    if (!needed) return;
+  }
   if constexpr (SX >= 0) {
     census_tile<SX, SY>(img, fr.W, fr.H, fr.pitch, lv.scale, out, lv.pitch, X0, Y0, sentinel, P);
   } else {

@@ -38,7 +38,8 @@ __global__ __launch_bounds__(256) void frame_census_kernel(MatchParamsDev P, Fra
     dev::frame_census_listed<SX, SY>(P, FR, boxes, n_tiles, blockIdx.x - FR.n, gridDim.x - FR.n,
                                      sx, sy, sentinel, lds, tbits, tlist, tsc);
   else
-    dev::frame_census_tile<SX, SY>(P, FR, boxes, blockIdx.x - FR.n, sx, sy, sentinel, lds);
+    dev::frame_census_tile<SX, SY>(P, FR, boxes, blockIdx.x - FR.n, sx, sy, sentinel, lds, true,
+                                   &tsc[0]);
 }
 
 // Waves per SIMD a single-level kernel is compiled for (as many as its registers allow
