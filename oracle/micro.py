@@ -112,7 +112,8 @@ def match_boxes(levels: dict, W: int, H: int, boxes, p: dict):
             xs = [lx0 + int(np.floor((k + 0.5) * lw / nx)) for k in range(nx)]
             ys = [ly0 + int(np.floor((k + 0.5) * lh / ny)) for k in range(ny)]
             tiles.append((0, 0, xs, ys))
-        if len(tiles) > p.get("max_blocks_per_box", 4096):
+        # the method sets no per-box limit; a caller may impose one
+        if p.get("max_blocks_per_box", 0) > 0 and len(tiles) > p["max_blocks_per_box"]:
             r["reason"] = 7
             continue
         total += len(tiles)
@@ -168,7 +169,8 @@ def match_boxes(levels: dict, W: int, H: int, boxes, p: dict):
             r["reason"] = 4
             continue
         vals = sorted(vals)
-        if len(tiles) == 1:
+        if far and len(tiles) == 1:
+            # Alg. 2: a FAR object matched as one block takes that block's result
             dbox = vals[0]
             r["n_used"] = 1
         elif p["agg_mode"] == AGG_SEGMENT:

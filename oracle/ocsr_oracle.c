@@ -134,17 +134,19 @@ static float median_sorted(const float* v, int m) {
 
 /* Per-box aggregation (Sec. 4.3.4) and depth (Eq. 1). vals: the full-res
  * disparities of the valid blocks (sorted in place). n_blocks: blocks the box was
- * tiled into; r->n_eligible must be set by the caller. */
-void orc_aggregate(float* vals, int32_t n_valid, int32_t n_blocks, const orc_params* p,
-                   orc_box_result* r) {
+ * tiled into; far_object: the box is of type FAR; r->n_eligible must be set by the
+ * caller. */
+void orc_aggregate(float* vals, int32_t n_valid, int32_t n_blocks, int32_t far_object,
+                   const orc_params* p, orc_box_result* r) {
   r->n_valid = n_valid;
   r->n_blocks = n_blocks;
   r->disparity = 0.0f; r->depth = 0.0f; r->valid = 0; r->n_used = 0;
   if (r->n_eligible == 0) { r->reason = ORC_NO_ELIGIBLE_BLOCKS; return; }
   if (n_valid == 0) { r->reason = ORC_NO_VALID_BLOCKS; return; }
   float d_box;
-  if (n_blocks == 1) {
-    /* a single-block (far) object takes its block result directly (Alg. 2) */
+  if (far_object && n_blocks == 1) {
+    /* Alg. 2: a FAR object matched as a single block takes that block's result;
+     * CLOSE objects always go through the robust aggregation below */
     d_box = vals[0];
     r->n_used = 1;
   } else {
@@ -292,7 +294,8 @@ int32_t orc_match_boxes(const uint64_t* L0, const uint64_t* R0,
     plan_box(p, &clip[i], &lv0, &lv1, &plan[i]);
     if (plan[i].level == 1 && (!L1 || !R1)) { free(clip); free(plan); free(off); free(status); return -1; }
     if (plan[i].n_blocks == 0) { status[i] = ORC_NO_ELIGIBLE_BLOCKS; continue; }
-    if (plan[i].n_blocks > p->max_blocks_per_box) {
+    /* the method sets no limit on a box's blocks; a caller may impose one */
+    if (p->max_blocks_per_box > 0 && plan[i].n_blocks > p->max_blocks_per_box) {
       status[i] = ORC_CAPACITY_OVERFLOW;
       plan[i].n_blocks = 0;
       continue;
@@ -408,7 +411,7 @@ int32_t orc_match_boxes(const uint64_t* L0, const uint64_t* R0,
       }
     }
     r->n_eligible = n_elig;
-    orc_aggregate(vals, n_valid, pl->n_blocks, p, r);
+    orc_aggregate(vals, n_valid, pl->n_blocks, pl->level == 0, p, r);
     free(vals); free(fcost); free(bcost); free(fall);
   }
   free(clip); free(plan); free(off); free(status);

@@ -38,7 +38,8 @@ typedef struct {
   float   tau_d;
   int32_t n_min, trim_pct;
   float   focal_px, baseline_m, d_eps;
-  int32_t max_blocks_per_box; /* boxes tiling into more blocks: CAPACITY_OVERFLOW */
+  int32_t max_blocks_per_box; /* > 0: boxes tiling into more blocks report
+                               * CAPACITY_OVERFLOW; 0: no limit (the method sets none) */
   int32_t cap_blocks;         /* total block capacity (prefix rule), <= 0: unlimited */
   int32_t dy_min, dy_max;     /* vertical offsets searched, full-res px; 0, 0: none */
 } orc_params;
@@ -105,9 +106,10 @@ int32_t orc_match_boxes(const uint64_t* L0, const uint64_t* R0,
 
 /* Aggregation of one box and its depth. vals (n_valid values, sorted in place)
  * are the full-res disparities of its valid blocks; n_blocks the blocks it was
- * tiled into; r->n_eligible must be set by the caller. */
-void orc_aggregate(float* vals, int32_t n_valid, int32_t n_blocks, const orc_params* p,
-                   orc_box_result* r);
+ * tiled into; far_object: 1 for a box of type FAR (a FAR box of one block takes
+ * that block's result, Alg. 2); r->n_eligible must be set by the caller. */
+void orc_aggregate(float* vals, int32_t n_valid, int32_t n_blocks, int32_t far_object,
+                   const orc_params* p, orc_box_result* r);
 
 /* Dense counterpart: per-pixel WTA over [dmin, dmax] of the (2r+1)^2 box sum
  * of Hamming costs (clipped window), with a left/right check. disp: int16 [H][W],

@@ -16,8 +16,6 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "ocsr_oracle.c")
 LIB = os.path.join(HERE, "liborc.so")
 
-MAX_BLOCKS_PER_BOX = 4096
-
 REASONS = ["OK", "NOT_RANGED", "CLIPPED_EMPTY", "NO_ELIGIBLE_BLOCKS", "NO_VALID_BLOCKS",
            "TOO_FEW_CONSISTENT", "NONPOSITIVE_DISPARITY", "CAPACITY_OVERFLOW"]
 
@@ -69,7 +67,7 @@ def lib():
         L.orc_match_boxes.argtypes = [vp, vp, vp, vp, i32, i32, vp, i32, C.POINTER(_Params), vp,
                                       vp, vp, vp, i32, i32, i32]
         L.orc_match_boxes.restype = i32
-        L.orc_aggregate.argtypes = [vp, i32, i32, C.POINTER(_Params), vp]
+        L.orc_aggregate.argtypes = [vp, i32, i32, i32, C.POINTER(_Params), vp]
         L.orc_aggregate.restype = None
         L.orc_dense.argtypes = [vp, vp, i32, i32, i32, i32, i32, i32, vp, vp, i32]
         L.orc_dense.restype = i32
@@ -112,7 +110,8 @@ def make_params(p: dict, cap_blocks: int = 0) -> _Params:
     q.lr_tol, q.min_point_pct, q.agg_mode = p["lr_tol"], p["min_point_pct"], p["agg_mode"]
     q.tau_d, q.n_min, q.trim_pct = p["tau_d"], p["n_min"], p["trim_pct"]
     q.focal_px, q.baseline_m, q.d_eps = p["focal_px"], p["baseline_m"], p["d_eps"]
-    q.max_blocks_per_box = p.get("max_blocks_per_box", MAX_BLOCKS_PER_BOX)
+    # the method sets no per-box limit: 0 (the default) means none
+    q.max_blocks_per_box = p.get("max_blocks_per_box", 0)
     q.cap_blocks = cap_blocks
     q.dy_min, q.dy_max = p.get("dy_min", 0), p.get("dy_max", 0)
     return q
@@ -153,13 +152,16 @@ def match_boxes(L0, R0, L1, R1, W: int, H: int, boxes: np.ndarray, params: dict,
     return out, blocks, cf, cb, total
 
 
-def aggregate(vals, n_blocks: int, params: dict, n_eligible: int | None = None):
-    """Aggregation + depth of one box from the full-res disparities of its valid blocks."""
+def aggregate(vals, n_blocks: int, params: dict, n_eligible: int | None = None,
+              far: bool = True):
+    """Aggregation + depth of one box from the full-res disparities of its valid blocks.
+    far: the box is of type FAR (a FAR box of a single block takes its block result)."""
     v = np.ascontiguousarray(np.asarray(vals, dtype=np.float32).copy())
     out = np.zeros(1, dtype=BOX_RESULT_DT)
     out["n_eligible"] = len(v) if n_eligible is None else n_eligible
     q = make_params(params)
-    lib().orc_aggregate(_ptr(v) if len(v) else None, len(v), n_blocks, C.byref(q), _ptr(out))
+    lib().orc_aggregate(_ptr(v) if len(v) else None, len(v), n_blocks, int(bool(far)), C.byref(q),
+                        _ptr(out))
     return out[0]
 
 

@@ -343,3 +343,80 @@ def test_depth_paper_examples(orc):
     assert r["depth"] == np.float32(200.0)
     r = orc.aggregate([0.0], 1, _params())
     assert r["valid"] == 0 and r["reason"] == 6
+
+
+# ------------------------------------------------------------------------------------
+# single-block objects, boxes with many blocks, L/R units (Alg. 2, Sec. 4.3.3-4.3.4)
+# ------------------------------------------------------------------------------------
+
+def test_single_block_result_is_for_far_objects_only(orc):
+    """Alg. 2 hands the single block result to FAR objects; CLOSE objects go through the
+    robust aggregation, whose N_min test a single block cannot pass when N_min > 1."""
+    p = _params(agg_mode=synth.AGG_SEGMENT_MEDIAN, tau_d=1.0, n_min=3)
+    far = orc.aggregate([4.5], 1, p, far=True)
+    assert far["valid"] == 1 and far["disparity"] == np.float32(4.5) and far["n_used"] == 1
+    close = orc.aggregate([4.5], 1, p, far=False)
+    assert close["valid"] == 0 and close["reason"] == 5 and close["n_used"] == 1
+    # the same for the trimmed median; with N_min = 1 the close block is its own median
+    pt = _params(agg_mode=synth.AGG_TRIMMED_MEDIAN, trim_pct=20, n_min=3)
+    assert orc.aggregate([4.5], 1, pt, far=False)["reason"] == 5
+    one = orc.aggregate([4.5], 1, dict(pt, n_min=1), far=False)
+    assert one["valid"] == 1 and one["disparity"] == np.float32(4.5)
+    # a FAR object of several blocks is aggregated like any other
+    assert orc.aggregate([4.5, 30.0], 2, p, far=True)["reason"] == 5
+
+
+def test_single_block_close_box_scene(orc):
+    """Through the whole path: a CLOSE box that tiles into one block is aggregated (and
+    fails N_min = 3), while a FAR box of one block is ranged by that block (Alg. 2)."""
+    left, right = _shift_pair(6, H=120, W=200)
+    p = _params(agg_mode=synth.AGG_SEGMENT_MEDIAN, n_min=3, tau_s=16)
+    p["far"] = dict(mode=synth.MODE_TILED, bw=8, bh=8, n_side=8, dmin=0, dmax=31)
+    p["close"] = dict(mode=synth.MODE_TILED, bw=8, bh=8, n_side=8, dmin=0, dmax=31)
+    # 16 x 18 px: CLOSE (18 >= 16); its level box at s = 2 is 8 x 9 px, one 8 x 8 block.
+    # 8 x 8 px: FAR; one 8 x 8 block at s = 1.
+    boxes = np.array([[80, 40, 96, 58, 1], [140, 40, 148, 48, 1]], np.int32)
+    _, (res, blk, *_r) = orc.run_scene(left, right, p, boxes, debug=True)
+    assert (res["n_blocks"] == 1).all()
+    assert blk["level_scale"].tolist() == [2, 1]
+    assert res["n_valid"].tolist() == [1, 1]
+    assert res["reason"].tolist() == [5, 0]
+    assert res["disparity"][1] == np.float32(blk["d_sub"][1])
+
+
+def test_box_beyond_4096_blocks_is_ranged(orc):
+    """The aggregation of Sec. 4.3.4 sorts every valid block of a box and sets no limit on
+    their number. A close box of 1400 x 1100 px at s = 2 tiles into 87 x 68 = 5916 blocks
+    of 8 x 8; on a texture moved by an integer 12 px every interior block matches at level
+    disparity 6 exactly (zero cost), so the box is ranged within one level px of 12 / 2."""
+    k = 12
+    left, right = synth.shifted_texture(21, 1160, 1460, k, 0)
+    p = _params(agg_mode=synth.AGG_TRIMMED_MEDIAN)
+    p["close"] = dict(mode=synth.MODE_TILED, bw=8, bh=8, n_side=8, dmin=0, dmax=63)
+    box = np.array([[30, 30, 1430, 1130, 1]], np.int32)
+    _, (res, blk, *_r) = orc.run_scene(left, right, p, box, debug=True)
+    assert res["n_blocks"][0] == 87 * 68 == 5916
+    assert res["reason"][0] == 0 and res["valid"][0] == 1
+    assert (blk["d_f"] == k // 2).all() and (blk["d_b"] == k // 2).all()
+    assert abs(float(res["disparity"][0]) - k) <= 1.0
+    # a caller-imposed limit still reports the box as CAPACITY_OVERFLOW
+    _, (capped, *_r) = orc.run_scene(left, right, dict(p, max_blocks_per_box=4096), box)
+    assert capped["reason"][0] == 7
+
+
+def test_lr_tolerance_counts_level_pixels(orc):
+    """The L/R test compares d_b with d_f in level px of the block's path: on the close
+    level (s = 2) a residual of exactly one level px (two full-res px) passes lr_tol = 1
+    and fails lr_tol = 0, the paper's strict |dx_v| < 1 on integers (Sec. 4.3.3)."""
+    sc = synth.scene_realistic()
+    p = synth.params_for(2)
+    _, (res, blk, *_r) = orc.run_scene(sc.left, sc.right, p, sc.boxes, debug=True)
+    close = (blk["level_scale"] == 2) & (blk["eligible"] == 1)
+    one = close & (np.abs(blk["d_b"] - blk["d_f"]) == 1)
+    two = close & (np.abs(blk["d_b"] - blk["d_f"]) >= 2)
+    assert one.sum() > 0 and two.sum() > 0
+    assert (blk["lr_ok"][one] == 1).all() and (blk["valid"][one] == 1).all()
+    assert (blk["lr_ok"][two] == 0).all()
+    _, (res0, blk0, *_r) = orc.run_scene(sc.left, sc.right, dict(p, lr_tol=0), sc.boxes, debug=True)
+    assert (blk0["lr_ok"][one] == 0).all()
+    assert (blk0["lr_ok"][close & (blk["d_b"] == blk["d_f"])] == 1).all()
