@@ -19,7 +19,9 @@
  *   - Every call is asynchronous on `stream` (a hipStream_t; NULL = the default
  *     stream). Outputs are valid once the caller synchronizes that stream.
  *   - Disparity d >= 0 is the left-to-right shift: the right-image match of left
- *     pixel (x, y) is (x - d, y). Images are rectified, so the vertical offset is 0.
+ *     pixel (x, y) is (x - d, y + dy). The vertical offset dy is 0 unless the caller
+ *     asks for a vertical range (ocsr_match_params.dy_min, dy_max) for pairs whose
+ *     rectification has drifted.
  *   - Return value: OCSR_OK (0) or a negative status. Arguments are validated before
  *     anything is enqueued; on a negative status nothing was enqueued (except
  *     OCSR_E_HIP, reported when a launch fails). ocsr_last_error() then returns a
@@ -37,7 +39,7 @@
 extern "C" {
 #endif
 
-#define OCSR_ABI_VERSION 2
+#define OCSR_ABI_VERSION 3
 
 /* status codes */
 #define OCSR_OK 0
@@ -67,8 +69,6 @@ extern "C" {
 
 #define OCSR_BOX_RANGE 1u   /* ocsr_box.flags: produce a range (else the box only occludes) */
 
-/* A box that tiles into more blocks than this is reported CAPACITY_OVERFLOW. */
-#define OCSR_MAX_BLOCKS_PER_BOX 4096
 /* Most frames one ocsr_range_batch call takes. */
 #define OCSR_MAX_BATCH_FRAMES 16
 /* Largest search range (level candidates) of one path. */
@@ -165,7 +165,11 @@ typedef struct {
   int32_t tau_s;           /* FAR iff max(clipped width, height) < tau_s (Sec. 4.3.4) */
   ocsr_path far_path;      /* FAR boxes: level 0 (scale 1) */
   ocsr_path close_path;    /* CLOSE boxes: level 1 (scale s, e.g. 2) */
-  int32_t lr_tol;          /* a block passes the L/R check iff |d_b - d_f| <= lr_tol */
+  int32_t lr_tol;          /* a block passes the L/R check (Sec. 4.3.3) iff
+                            * |d_b - d_f| <= lr_tol, counted in level px of the block's
+                            * path (on a close level of scale s, lr_tol 1 allows s
+                            * full-res px). The paper's strict |dx_v| < tau_v on integer
+                            * residuals is lr_tol = tau_v - 1 (lr_tol 0 for tau_v 1). */
   int32_t min_point_pct;   /* block eligible iff points > 0 and 100 points >= pct nx ny */
   int32_t agg_mode;        /* OCSR_AGG_* */
   float tau_d;             /* segment gap threshold, full-res px */
@@ -226,7 +230,10 @@ typedef struct {
 /* Workspace of ocsr_match_boxes for up to n_boxes boxes and cap_blocks blocks in
  * total. Blocks are numbered by a prefix over the boxes in order; a box whose
  * range of numbers passes cap_blocks (and every box after it) is reported
- * CAPACITY_OVERFLOW. cap_blocks <= 2^24. */
+ * CAPACITY_OVERFLOW. That is the only limit on a box's blocks: the aggregation of
+ * Sec. 4.3.4 takes every valid block of a box, however many (boxes of more than 4096
+ * blocks are aggregated from the workspace instead of on-chip memory). cap_blocks
+ * <= 2^24. */
 size_t ocsr_match_workspace_bytes(int32_t n_boxes, int32_t cap_blocks);
 
 /* Matches every ranged box. lv0 (host struct, dev arrays): descriptors of level 0,
@@ -520,6 +527,18 @@ int32_t ocsr_ctx_set_timing(ocsr_ctx* ctx, int32_t enable);
 int32_t ocsr_ctx_kernel_time(ocsr_ctx* ctx, const char* kernel, int64_t* launches,
                              double* total_ms);
 int32_t ocsr_ctx_reset_timing(ocsr_ctx* ctx);
+
+/* ------------------------------------------------------------------------------ */
+/* Measurement                                                                      */
+/* ------------------------------------------------------------------------------ */
+/* Measures the int32 vector-ALU rate of the context's device, the peak the census and
+ * matching kernels are priced against: every lane of 16 workgroups of 256 threads per
+ * compute unit runs 8 independent chains of the matching cost arithmetic
+ * (b = a ^ b, acc = popcount(b) + acc: one v_xor_b32 and one v_bcnt_u32_b32 per step)
+ * for `iters` steps, on the null stream, after three untimed launches. Synchronizes.
+ * *ops_per_s: lane operations per second of the timed launch; *ms (nullable): its
+ * duration. OCSR_E_INVALID for a null ctx or ops_per_s or iters outside 1..2^20. */
+int32_t ocsr_measure_int_rate(ocsr_ctx* ctx, int32_t iters, double* ops_per_s, double* ms);
 
 #ifdef __cplusplus
 }

@@ -73,6 +73,13 @@ int32_t fail(int32_t code, const char* fmt, ...) {
   return code;
 }
 
+}  // namespace
+
+// a status with its message, for the other translation units
+int32_t ocsr::report_error(int32_t code, const char* msg) { return fail(code, "%s", msg); }
+
+namespace {
+
 int32_t hip_fail(hipError_t e, const char* what) {
   return fail(OCSR_E_HIP, "%s: %s", what, hipGetErrorString(e));
 }

@@ -15,7 +15,9 @@
 namespace ocsr {
 namespace dev {
 
-constexpr int kAggMax = OCSR_MAX_BLOCKS_PER_BOX;
+// valid block values of a box that the aggregation keeps in LDS; boxes with more
+// blocks aggregate from global memory (the method sets no limit on a box's blocks)
+constexpr int kAggMax = 4096;
 
 // ---------------------------------------------------------------------------------
 // plan: one wave walks the frame's boxes 64 at a time
@@ -71,13 +73,12 @@ __device__ __forceinline__ void plan_frame(const MatchParamsDev& P, const FrameD
             pl.bw = min(ph.n_side, pl.lw);
             pl.bh = min(ph.n_side, pl.lh);
           }
-          const int nb = pl.nbx * pl.nby;
-          if (nb > OCSR_MAX_BLOCKS_PER_BOX) {
-            pl.status = OCSR_REASON_CAPACITY_OVERFLOW;
-          } else {
-            pl.status = -1;
-            count = nb;
-          }
+          // the method sets no limit on a box's blocks; only the call's capacity does.
+          // A count past the capacity saturates at cap + 1 (the box, and every later box,
+          // then passes the capacity), which keeps the prefix in 32 bits.
+          const long long nb = (long long)pl.nbx * pl.nby;
+          pl.status = -1;
+          count = (int)min(nb, (long long)P.cap_blocks + 1);
         }
       }
     }
@@ -743,8 +744,9 @@ __device__ __forceinline__ void level_items(const FramesDev& FR, const MatchWs& 
 // aggregation: one workgroup (256 threads) per box
 // ---------------------------------------------------------------------------------
 struct AggLds {
-  float vals[kAggMax];
-  int32_t hist[1024];     // value histogram of the trimmed median
+  float vals[kAggMax];    // the box's valid values (boxes of at most kAggMax blocks)
+  int32_t hist[1024];     // value histogram of the trimmed median; per-wave digit counts
+                          // of the global radix sort ([kItemWaves][256])
   float list[2][64];      // values of the bins holding the two middle ranks
   int32_t scratch[272];   // radix bins [0, 256), then scalars
   int32_t n_valid, n_eligible, seg_start, seg_len;
@@ -758,8 +760,8 @@ __device__ __forceinline__ float median_sorted(const float* v, int m) {
   return (v[m / 2 - 1] + v[m / 2]) * 0.5f;
 }
 
-// k-th smallest (0-based) of the n non-negative floats in vals: radix select on their
-// bit patterns (monotone for non-negative floats), 8 bits per pass
+// k-th smallest (0-based) of the n non-negative floats in vals (LDS or global memory):
+// radix select on their bit patterns (monotone for non-negative floats), 8 bits per pass
 __device__ __forceinline__ uint32_t radix_select(const float* vals, int n, int k, int32_t* sc) {
   const int tid = threadIdx.x;
   uint32_t prefix = 0, pmask = 0;
@@ -795,6 +797,74 @@ __device__ __forceinline__ uint32_t radix_select(const float* vals, int n, int k
   return prefix;
 }
 
+// Ascending sort of the n non-negative floats at a (global memory) by their bit
+// patterns: four stable counting passes of 8 bits, least significant first, between a
+// and tmp (n floats); the sorted values end in a. One workgroup of 256 threads. A pass
+// counts the digits, scans them to the start of each digit's range, then scatters 256
+// values at a time in index order: a value's place is its digit's start, plus the
+// values of that digit in earlier waves of the round, plus those of lower lanes of its
+// own wave (found with eight ballots, one per digit bit). cnt: kItemWaves x 256 ints,
+// base: 256 ints of LDS.
+__device__ __forceinline__ void radix_sort_global(float* a, float* tmp, int n, int32_t* cnt,
+                                                  int32_t* base) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  for (int pass = 0; pass < 4; ++pass) {
+    const int shift = 8 * pass;
+    const float* src = (pass & 1) ? tmp : a;
+    float* dst = (pass & 1) ? a : tmp;
+    base[tid] = 0;
+    for (int w = 0; w < kItemWaves; ++w) cnt[w * 256 + tid] = 0;
+    __syncthreads();
+    for (int i = tid; i < n; i += 256) atomicAdd(&base[(__float_as_uint(src[i]) >> shift) & 255u], 1);
+    __syncthreads();
+    // exclusive scan of the 256 digit counts (thread t holds digit t)
+    {
+      const int c = base[tid];
+      const int incl = wave_incl_scan(c, lane);
+      __syncthreads();
+      if (lane == 63) cnt[wave] = incl;   // wave totals (cnt is all zero otherwise)
+      __syncthreads();
+      int excl = incl - c;
+      for (int w = 0; w < wave; ++w) excl += cnt[w];
+      __syncthreads();
+      base[tid] = excl;
+      if (tid < kItemWaves) cnt[tid] = 0;
+      __syncthreads();
+    }
+    for (int c0 = 0; c0 < n; c0 += 256) {
+      const int i = c0 + tid;
+      const bool ok = i < n;
+      const float v = ok ? src[i] : 0.0f;
+      const uint32_t dg = (__float_as_uint(v) >> shift) & 255u;
+      uint64_t same = __ballot(ok);
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        const uint64_t m = __ballot((dg >> b) & 1u);
+        same &= ((dg >> b) & 1u) ? m : ~m;
+      }
+      const int before = (int)__popcll(same & below);
+      if (ok && before == 0) cnt[wave * 256 + dg] = (int)__popcll(same);
+      __syncthreads();
+      if (ok) {
+        int pos = base[dg] + before;
+        for (int w = 0; w < wave; ++w) pos += cnt[w * 256 + dg];
+        dst[pos] = v;
+      }
+      __syncthreads();
+      int add = 0;
+      for (int w = 0; w < kItemWaves; ++w) {
+        add += cnt[w * 256 + tid];
+        cnt[w * 256 + tid] = 0;
+      }
+      base[tid] += add;
+      __syncthreads();
+    }
+  }
+  // the last pass wrote into a; make its stores visible to the whole workgroup
+  __threadfence_block();
+  __syncthreads();
+}
 
 // Bin of v among 1024 equal-width bins over [vmin, vmin + 1024 / scale]: a monotone map,
 // so every value of a lower bin is smaller than every value of a higher one.
@@ -802,14 +872,16 @@ __device__ __forceinline__ int value_bin(float v, float vmin, float scale) {
   return min((int)((v - vmin) * scale), 1023);
 }
 
-// The k-th and (k + 1)-th smallest (0-based) of the n non-negative floats in sm.vals
-// (the second only when want2), as bit patterns. The values are binned by value
-// (value_bin); a scan of the bin counts finds the bins of the two ranks and their ranks
-// within them; one wave then ranks the few values of each such bin against each other.
-// A radix selection over all values handles equal bounds, a bin of more than 64 values
-// or a range too narrow to scale. vmin, vmax: the smallest and largest value.
-__device__ __forceinline__ void select_middle(AggLds& sm, int n, int k, bool want2, float vmin,
-                                              float vmax, uint32_t* u1, uint32_t* u2) {
+// The k-th and (k + 1)-th smallest (0-based) of the n non-negative floats in vals (LDS
+// or global memory; the second only when want2), as bit patterns. The values are binned
+// by value (value_bin); a scan of the bin counts finds the bins of the two ranks and
+// their ranks within them; one wave then ranks the few values of each such bin against
+// each other. A radix selection over all values handles equal bounds, a bin of more
+// than 64 values or a range too narrow to scale. vmin, vmax: the smallest and largest
+// value.
+__device__ __forceinline__ void select_middle(AggLds& sm, const float* vals, int n, int k,
+                                              bool want2, float vmin, float vmax, uint32_t* u1,
+                                              uint32_t* u2) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (vmin == vmax) {
     *u1 = *u2 = __float_as_uint(vmin);
@@ -818,7 +890,7 @@ __device__ __forceinline__ void select_middle(AggLds& sm, int n, int k, bool wan
   const float scale = 1024.0f / (vmax - vmin);
   bool fallback = !(scale < 1e30f);
   if (!fallback) {
-    for (int i = tid; i < n; i += 256) atomicAdd(&sm.hist[value_bin(sm.vals[i], vmin, scale)], 1);
+    for (int i = tid; i < n; i += 256) atomicAdd(&sm.hist[value_bin(vals[i], vmin, scale)], 1);
     if (tid == 0) { sm.count[0] = 0; sm.count[1] = 0; }
     __syncthreads();
     // thread t owns bins 4t .. 4t + 3
@@ -847,7 +919,7 @@ __device__ __forceinline__ void select_middle(AggLds& sm, int n, int k, bool wan
     if (!fallback) {
       // the values of bins b1 and b2 (list 1 only when the bins differ)
       for (int i = tid; i < n; i += 256) {
-        const float v = sm.vals[i];
+        const float v = vals[i];
         const int b = value_bin(v, vmin, scale);
         if (b == b1) sm.list[0][atomicAdd(&sm.count[0], 1)] = v;
         else if (b == b2) sm.list[1][atomicAdd(&sm.count[1], 1)] = v;
@@ -875,8 +947,8 @@ __device__ __forceinline__ void select_middle(AggLds& sm, int n, int k, bool wan
       return;
     }
   }
-  *u1 = radix_select(sm.vals, n, k, sm.scratch);
-  *u2 = want2 ? radix_select(sm.vals, n, k + 1, sm.scratch) : *u1;
+  *u1 = radix_select(vals, n, k, sm.scratch);
+  *u2 = want2 ? radix_select(vals, n, k + 1, sm.scratch) : *u1;
 }
 
 __device__ __forceinline__ void aggregate_box(const MatchParamsDev& P, const MatchWs& ws, int kg,
@@ -893,6 +965,12 @@ __device__ __forceinline__ void aggregate_box(const MatchParamsDev& P, const Mat
     return;
   }
   const int base = pl.frame * P.cap_blocks + pl.off;
+  // a box of at most kAggMax blocks gathers its valid values into LDS; a larger one
+  // compacts them in place at the front of its own block values in global memory (a
+  // value moves to an index no larger than its own, and every chunk is loaded before
+  // any of it is stored)
+  const bool in_lds = pl.nblk <= kAggMax;
+  float* vals = in_lds ? sm.vals : ws.blk_val + base;
   if (tid == 0) {
     sm.n_valid = 0;
     sm.n_eligible = 0;
@@ -917,6 +995,7 @@ __device__ __forceinline__ void aggregate_box(const MatchParamsDev& P, const Mat
       v[u] = ws.blk_val[at];
       fl[u] = i < pl.nblk ? fl[u] : 0u;
     }
+    if (!in_lds) __syncthreads();   // the chunk is loaded before it is overwritten
 #pragma unroll
     for (int u = 0; u < kGather; ++u) {
       const uint64_t mv = __ballot((fl[u] & 2) != 0);
@@ -928,11 +1007,12 @@ __device__ __forceinline__ void aggregate_box(const MatchParamsDev& P, const Mat
       }
       wbase = __shfl(wbase, 0, 64);
       if (fl[u] & 2) {
-        sm.vals[wbase + __popcll(mv & below)] = v[u];
+        vals[wbase + __popcll(mv & below)] = v[u];
         vlo = min(vlo, __float_as_uint(v[u]));
         vhi = max(vhi, __float_as_uint(v[u]));
       }
     }
+    if (!in_lds) __syncthreads();
   }
   vlo = wave_min_u32(vlo);
   vhi = (uint32_t)wave_max((int)vhi);
@@ -940,6 +1020,7 @@ __device__ __forceinline__ void aggregate_box(const MatchParamsDev& P, const Mat
     atomicMin(&sm.vmin, vlo);
     atomicMax(&sm.vmax, vhi);
   }
+  if (!in_lds) __threadfence_block();   // compacted values visible to the workgroup
   __syncthreads();
   const int nv = sm.n_valid, ne = sm.n_eligible;
   r.n_blocks = pl.nblk;
@@ -954,12 +1035,14 @@ __device__ __forceinline__ void aggregate_box(const MatchParamsDev& P, const Mat
   }
   float d_box = 0.0f;
   bool ok = true;
-  if (pl.nblk == 1) {
-    d_box = sm.vals[0];   // a single-block object takes its block result (Alg. 2)
+  if (pl.level == 0 && pl.nblk == 1) {
+    // Alg. 2: a FAR object matched as one block takes that block's result; CLOSE
+    // objects always go through the robust aggregation
+    d_box = vals[0];
     r.n_used = 1;
   } else if (P.agg_mode == OCSR_AGG_TRIMMED_MEDIAN) {
     // symmetric trim of floor(pct * n / 100) values at each end, then the median: the
-    // one or two middle order statistics, found by radix selection
+    // one or two middle order statistics, found by selection
     const int t = P.trim_pct * nv / 100;
     const int m = nv - 2 * t;
     r.n_used = m > 0 ? m : 0;
@@ -968,35 +1051,41 @@ __device__ __forceinline__ void aggregate_box(const MatchParamsDev& P, const Mat
     } else {
       const int k1 = t + (m - 1) / 2;
       uint32_t u1, u2;
-      select_middle(sm, nv, k1, (m & 1) == 0, __uint_as_float(sm.vmin), __uint_as_float(sm.vmax),
-                    &u1, &u2);
+      select_middle(sm, vals, nv, k1, (m & 1) == 0, __uint_as_float(sm.vmin),
+                    __uint_as_float(sm.vmax), &u1, &u2);
       d_box = (m & 1) ? __uint_as_float(u1) : (__uint_as_float(u1) + __uint_as_float(u2)) * 0.5f;
     }
   } else {
-    // bitonic sort of the valid values, padded with +inf to a power of two
-    int n2 = 1;
-    while (n2 < nv) n2 <<= 1;
-    for (int i = nv + tid; i < n2; i += 256) sm.vals[i] = __builtin_inff();
-    __syncthreads();
-    for (int kk = 2; kk <= n2; kk <<= 1) {
-      for (int j = kk >> 1; j > 0; j >>= 1) {
-        for (int i = tid; i < n2; i += 256) {
-          const int ixj = i ^ j;
-          if (ixj > i) {
-            const float a = sm.vals[i], c = sm.vals[ixj];
-            const bool up = (i & kk) == 0;
-            if ((a > c) == up) { sm.vals[i] = c; sm.vals[ixj] = a; }
+    if (in_lds) {
+      // bitonic sort of the valid values, padded with +inf to a power of two
+      int n2 = 1;
+      while (n2 < nv) n2 <<= 1;
+      for (int i = nv + tid; i < n2; i += 256) sm.vals[i] = __builtin_inff();
+      __syncthreads();
+      for (int kk = 2; kk <= n2; kk <<= 1) {
+        for (int j = kk >> 1; j > 0; j >>= 1) {
+          for (int i = tid; i < n2; i += 256) {
+            const int ixj = i ^ j;
+            if (ixj > i) {
+              const float a = sm.vals[i], c = sm.vals[ixj];
+              const bool up = (i & kk) == 0;
+              if ((a > c) == up) { sm.vals[i] = c; sm.vals[ixj] = a; }
+            }
           }
+          __syncthreads();
         }
-        __syncthreads();
       }
+    } else {
+      // the values in global memory, ordered by a radix sort through the box's slots of
+      // the sort buffer
+      radix_sort_global(vals, ws.agg_tmp + base, nv, sm.hist, sm.scratch);
     }
     // longest run whose consecutive gaps stay below tau_d; the first run wins a tie
     if (tid < 64) {
       int best_start = 0, best_len = 1, start = 0;
       for (int b0 = 0; b0 < nv; b0 += 64) {
         const int q = b0 + tid;
-        const bool brk = q > 0 && q < nv && !(sm.vals[q] - sm.vals[q - 1] < P.tau_d);
+        const bool brk = q > 0 && q < nv && !(vals[q] - vals[q - 1] < P.tau_d);
         uint64_t m = __ballot(brk);
         while (m) {
           const int pos = b0 + __ffsll((unsigned long long)m) - 1;
@@ -1014,7 +1103,7 @@ __device__ __forceinline__ void aggregate_box(const MatchParamsDev& P, const Mat
     const int seg_start = sm.seg_start, seg_len = sm.seg_len;
     r.n_used = seg_len;
     if (seg_len < P.n_min) ok = false;
-    else d_box = median_sorted(sm.vals + seg_start, seg_len);
+    else d_box = median_sorted(vals + seg_start, seg_len);
   }
   if (tid == 0) {
     if (!ok) {

@@ -195,7 +195,7 @@ size_t match_ws_bytes(int n_frames, int n_boxes_total, int cap_blocks) {
   return align256(n * sizeof(BoxPlan)) + align256(n * sizeof(BoxClip)) +
          align256(2 * n * sizeof(int32_t)) +
          align256((size_t)kMaxFrames * FC_N * sizeof(int32_t)) + align256(GC_N * sizeof(int32_t)) +
-         align256(c * sizeof(float)) + align256(c * sizeof(uint8_t)) +
+         2 * align256(c * sizeof(float)) + align256(c * sizeof(uint8_t)) +
          (size_t)(n_frames > 0 ? n_frames : 1) * items_capacity(n_boxes_total, cap_blocks) * sizeof(ItemRec);
 }
 
@@ -210,6 +210,7 @@ MatchWs match_ws_carve(void* base, int n_frames, int n_boxes_total, int cap_bloc
   ws.fcount = (int32_t*)b;      b += align256((size_t)kMaxFrames * FC_N * sizeof(int32_t));
   ws.gcount = (int32_t*)b;      b += align256(GC_N * sizeof(int32_t));
   ws.blk_val = (float*)b;       b += align256(c * sizeof(float));
+  ws.agg_tmp = (float*)b;       b += align256(c * sizeof(float));
   ws.blk_flag = (uint8_t*)b;    b += align256(c * sizeof(uint8_t));
   ws.items = (ItemRec*)b;
   ws.items_cap = items_capacity(n_boxes_total, cap_blocks);

@@ -11,6 +11,9 @@
 
 namespace ocsr {
 
+// Records msg as the calling thread's last error message and returns code.
+int32_t report_error(int32_t code, const char* msg);
+
 // ---------------------------------------------------------------------------------
 // census
 // ---------------------------------------------------------------------------------
@@ -167,6 +170,8 @@ struct MatchWs {
   int32_t* fcount;     // [kMaxFrames][FC_N]
   int32_t* gcount;     // [GC_N]
   float* blk_val;      // [n_frames][cap_blocks] full-res disparity of a valid block
+  float* agg_tmp;      // [n_frames][cap_blocks] sort buffer of the aggregation of boxes
+                       // with more blocks than it keeps in LDS
   uint8_t* blk_flag;   // [n_frames][cap_blocks] bit 0 eligible, bit 1 valid
   ItemRec* items;      // [n_frames][items_cap]: a frame's close items, then its far items
   int32_t items_cap;   // records per frame

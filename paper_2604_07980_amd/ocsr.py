@@ -24,7 +24,6 @@ REASONS = ["OK", "NOT_RANGED", "CLIPPED_EMPTY", "NO_ELIGIBLE_BLOCKS", "NO_VALID_
 MODE_TILED, MODE_GRID = 0, 1
 AGG_SEGMENT_MEDIAN, AGG_TRIMMED_MEDIAN = 0, 1
 BOX_RANGE = 1
-MAX_BLOCKS_PER_BOX = 4096
 MAX_BATCH_FRAMES = 16
 MAX_CANDIDATES = 256
 MAX_DY = 32
@@ -45,7 +44,7 @@ EXPORTS = ["ocsr_abi_version", "ocsr_last_error", "ocsr_ctx_create", "ocsr_ctx_d
            "ocsr_variant_candidates", "ocsr_ctx_set_variant", "ocsr_dense_workspace_bytes",
            "ocsr_dense_match", "ocsr_box_points", "ocsr_select_boxes",
            "ocsr_rect_workspace_bytes", "ocsr_rect_offset_counts", "ocsr_rect_filter_create",
-           "ocsr_rect_filter_destroy", "ocsr_rect_filter_update"]
+           "ocsr_rect_filter_destroy", "ocsr_rect_filter_update", "ocsr_measure_int_rate"]
 
 
 class OcsrError(RuntimeError):
@@ -209,6 +208,8 @@ def load(path: str = LIB_PATH):
         L.ocsr_rect_filter_destroy.restype = None
         L.ocsr_rect_filter_update.argtypes = [vp, vp, i32, i32, C.POINTER(i32), C.POINTER(i32)]
         L.ocsr_rect_filter_update.restype = i32
+        L.ocsr_measure_int_rate.argtypes = [vp, i32, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.ocsr_measure_int_rate.restype = i32
         _lib = L
         return L
 
@@ -680,3 +681,11 @@ def kernel_time(name: str, device: int | None = None) -> tuple[int, float]:
 
 def reset_timing(device: int | None = None):
     _check(load().ocsr_ctx_reset_timing(context(device)))
+
+
+def measure_int_rate(iters: int = 4096, device: int | None = None) -> tuple[float, float]:
+    """The device's int32 vector-ALU rate (lane operations per second) and the timed
+    launch's duration in ms, from the library's chain kernel."""
+    ops, ms = C.c_double(0.0), C.c_double(0.0)
+    _check(load().ocsr_measure_int_rate(context(device), iters, C.byref(ops), C.byref(ms)))
+    return ops.value, ms.value
