@@ -248,6 +248,26 @@ int32_t ocsr_match_boxes(ocsr_ctx* ctx, const ocsr_level* lv0, const ocsr_level*
                          void* ws, size_t ws_bytes, ocsr_box_result* out,
                          const ocsr_debug* dbg, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): ocsr_match_boxes with its scratch in
+ * a library-owned device array of OCSR_NOALLOC_SCRATCH_BYTES per device instead of a
+ * caller workspace. The array is made when the library's code is loaded on a device and
+ * held until the process ends; its device address is resolved once per device by
+ * ocsr_ctx_create. The call allocates nothing (no hipMalloc, hipFree or allocating
+ * library routine, and no timing events: the context's timing does not cover it).
+ * Same arguments, results and errors as ocsr_match_boxes without ws and ws_bytes;
+ * OCSR_E_CAPACITY when ocsr_match_workspace_bytes(n_boxes, cap_blocks) exceeds
+ * OCSR_NOALLOC_SCRATCH_BYTES (cap_blocks above 670 656 with 64 boxes).
+ * Every call on a device shares that device's array, which keeps the last call's
+ * contents (the kernels write every counter they read, so no clearing is needed):
+ * calls that overlap on one device (two host threads, or two streams without an order
+ * between them) race and give undefined results. */
+#define OCSR_NOALLOC_SCRATCH_BYTES (16u << 20)
+int32_t ocsr_match_boxes_noalloc(ocsr_ctx* ctx, const ocsr_level* lv0, const ocsr_level* lv1,
+                                 const ocsr_box* boxes, int32_t n_boxes,
+                                 const ocsr_match_params* params, int32_t cap_blocks,
+                                 ocsr_box_result* out, const ocsr_debug* dbg, void* stream);
+
 /* ------------------------------------------------------------------------------ */
 /* Per-box 3D point and covariance (Sec. 4.3.6 Q-matrix equation; Sec. 4.3.7 depth  */
 /* variance and covariance rotation equations)                                      */

@@ -474,6 +474,71 @@ int32_t range_frames(ocsr_ctx* ctx, const ocsr_frame* frames, int n_frames,
   return enqueue(stream, ctx->timing ? &t : nullptr);
 }
 
+// Scratch of ocsr_match_boxes_noalloc: a file-scope device array, one copy on every
+// device the library runs on, held until the process ends. Host code never passes the
+// array's name to a kernel (on the host it is a stand-in, not a device address); it uses
+// the device address resolved once per device at context creation.
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[OCSR_NOALLOC_SCRATCH_BYTES];
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Resolves the device address of `scratch` on `device`, which must be current.
+int32_t resolve_scratch(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return OCSR_OK;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+  if (!ptr || ((uintptr_t)ptr & 255)) return fail(OCSR_E_HIP, "scratch address not 256-byte aligned");
+  g_scratch_ptr[device] = ptr;
+  return OCSR_OK;
+}
+
+void* scratch_ptr(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return device >= 0 && device < kMaxDevices ? g_scratch_ptr[device] : nullptr;
+}
+
+// ocsr_match_boxes on a given workspace; `timed` lets the context's timing events in
+int32_t match_boxes_impl(ocsr_ctx* ctx, const ocsr_level* lv0, const ocsr_level* lv1,
+                         const ocsr_box* boxes, int32_t n_boxes, const ocsr_match_params* params,
+                         int32_t cap_blocks, void* ws, size_t ws_bytes, ocsr_box_result* out,
+                         const ocsr_debug* dbg, void* stream, bool timed) {
+  int32_t rc;
+  FramesDev FR;
+  memset(&FR, 0, sizeof(FR));
+  if ((rc = check_level(lv0, "lv0", &FR.f[0].lv[0])) != OCSR_OK) return rc;
+  if ((rc = check_level(lv1, "lv1", &FR.f[0].lv[1])) != OCSR_OK) return rc;
+  if (lv0->scale != 1) return fail(OCSR_E_INVALID, "lv0 must have scale 1 (got %d)", lv0->scale);
+  MatchParamsDev P;
+  if ((rc = build_params(ctx, params, lv1->scale, cap_blocks, &P)) != OCSR_OK) return rc;
+  if (n_boxes < 0 || n_boxes > (1 << 20)) return fail(OCSR_E_INVALID, "n_boxes %d outside 0..2^20", n_boxes);
+  if (n_boxes == 0) return OCSR_OK;
+  if (!boxes || !out) return fail(OCSR_E_INVALID, "null boxes or output");
+  if ((rc = check_ws(ws, ws_bytes, match_ws_bytes(1, n_boxes, cap_blocks))) != OCSR_OK) return rc;
+  if (dbg && (dbg->cap_blocks < 0 || dbg->cap_nd < 0))
+    return fail(OCSR_E_INVALID, "debug capacities must be >= 0");
+  FR.n = 1;
+  FR.n_boxes_total = n_boxes;
+  FR.f[0].W = lv0->width;
+  FR.f[0].H = lv0->height;
+  FR.f[0].box_off = 0;
+  FR.f[0].n_boxes = n_boxes;
+  MatchWs mws = match_ws_carve(ws, 1, n_boxes, cap_blocks);
+  LaunchTimer t = make_timer(ctx);
+  hipError_t e = launch_match(P, FR, boxes, mws, out, make_debug(dbg), false,
+                              std::max(1, ctx->n_cu * ctx->match_wgs_per_cu), (hipStream_t)stream,
+                              timed && ctx->timing ? &t : nullptr);
+  if (e != hipSuccess) return hip_fail(e, "match launch");
+  if (dbg && dbg->n_blocks) {
+    e = hipMemcpyAsync(dbg->n_blocks, mws.fcount + FC_NUMBERED, sizeof(int32_t),
+                       hipMemcpyDeviceToDevice, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "debug block count copy");
+  }
+  return OCSR_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -498,6 +563,10 @@ int32_t ocsr_ctx_create(int32_t device, ocsr_ctx** out) {
   if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
     return fail(OCSR_E_UNSUPPORTED, "device %d is %s; this library is built for gfx950", device,
                 prop.gcnArchName);
+  if (device >= kMaxDevices) return fail(OCSR_E_INVALID, "device %d beyond %d", device, kMaxDevices - 1);
+  // the no-allocation entry point's scratch: its address on this device, once
+  int32_t rs = resolve_scratch(device);
+  if (rs != OCSR_OK) return rs;
   ocsr_ctx* c = new (std::nothrow) ocsr_ctx();
   if (!c) return fail(OCSR_E_INVALID, "out of host memory");
   c->device = device;
@@ -736,38 +805,27 @@ int32_t ocsr_match_boxes(ocsr_ctx* ctx, const ocsr_level* lv0, const ocsr_level*
                          const ocsr_debug* dbg, void* stream) {
   g_last_error.clear();
   if (!ctx) return fail(OCSR_E_INVALID, "null context");
-  int32_t rc;
-  FramesDev FR;
-  memset(&FR, 0, sizeof(FR));
-  if ((rc = check_level(lv0, "lv0", &FR.f[0].lv[0])) != OCSR_OK) return rc;
-  if ((rc = check_level(lv1, "lv1", &FR.f[0].lv[1])) != OCSR_OK) return rc;
-  if (lv0->scale != 1) return fail(OCSR_E_INVALID, "lv0 must have scale 1 (got %d)", lv0->scale);
-  MatchParamsDev P;
-  if ((rc = build_params(ctx, params, lv1->scale, cap_blocks, &P)) != OCSR_OK) return rc;
+  return match_boxes_impl(ctx, lv0, lv1, boxes, n_boxes, params, cap_blocks, ws, ws_bytes, out,
+                          dbg, stream, true);
+}
+
+int32_t ocsr_match_boxes_noalloc(ocsr_ctx* ctx, const ocsr_level* lv0, const ocsr_level* lv1,
+                                 const ocsr_box* boxes, int32_t n_boxes,
+                                 const ocsr_match_params* params, int32_t cap_blocks,
+                                 ocsr_box_result* out, const ocsr_debug* dbg, void* stream) {
+  g_last_error.clear();
+  if (!ctx) return fail(OCSR_E_INVALID, "null context");
+  void* ptr = scratch_ptr(ctx->device);
+  if (!ptr) return fail(OCSR_E_INVALID, "no scratch resolved for device %d", ctx->device);
   if (n_boxes < 0 || n_boxes > (1 << 20)) return fail(OCSR_E_INVALID, "n_boxes %d outside 0..2^20", n_boxes);
-  if (n_boxes == 0) return OCSR_OK;
-  if (!boxes || !out) return fail(OCSR_E_INVALID, "null boxes or output");
-  if ((rc = check_ws(ws, ws_bytes, match_ws_bytes(1, n_boxes, cap_blocks))) != OCSR_OK) return rc;
-  if (dbg && (dbg->cap_blocks < 0 || dbg->cap_nd < 0))
-    return fail(OCSR_E_INVALID, "debug capacities must be >= 0");
-  FR.n = 1;
-  FR.n_boxes_total = n_boxes;
-  FR.f[0].W = lv0->width;
-  FR.f[0].H = lv0->height;
-  FR.f[0].box_off = 0;
-  FR.f[0].n_boxes = n_boxes;
-  MatchWs mws = match_ws_carve(ws, 1, n_boxes, cap_blocks);
-  LaunchTimer t = make_timer(ctx);
-  hipError_t e = launch_match(P, FR, boxes, mws, out, make_debug(dbg), false,
-                              std::max(1, ctx->n_cu * ctx->match_wgs_per_cu), (hipStream_t)stream,
-                              ctx->timing ? &t : nullptr);
-  if (e != hipSuccess) return hip_fail(e, "match launch");
-  if (dbg && dbg->n_blocks) {
-    e = hipMemcpyAsync(dbg->n_blocks, mws.fcount + FC_NUMBERED, sizeof(int32_t),
-                       hipMemcpyDeviceToDevice, (hipStream_t)stream);
-    if (e != hipSuccess) return hip_fail(e, "debug block count copy");
-  }
-  return OCSR_OK;
+  if (cap_blocks < 1 || cap_blocks > (1 << 24)) return fail(OCSR_E_INVALID, "cap_blocks %d outside 1..2^24", cap_blocks);
+  const size_t need = match_ws_bytes(1, n_boxes, cap_blocks);
+  if (need > (size_t)OCSR_NOALLOC_SCRATCH_BYTES)
+    return fail(OCSR_E_CAPACITY, "%d boxes and %d block slots need %zu bytes of scratch, more than "
+                "the %u of OCSR_NOALLOC_SCRATCH_BYTES", n_boxes, cap_blocks, need,
+                (unsigned)OCSR_NOALLOC_SCRATCH_BYTES);
+  return match_boxes_impl(ctx, lv0, lv1, boxes, n_boxes, params, cap_blocks, ptr,
+                          (size_t)OCSR_NOALLOC_SCRATCH_BYTES, out, dbg, stream, false);
 }
 
 size_t ocsr_frame_workspace_bytes(int32_t width, int32_t height, const ocsr_frame_params* fp,

@@ -44,7 +44,8 @@ EXPORTS = ["ocsr_abi_version", "ocsr_last_error", "ocsr_ctx_create", "ocsr_ctx_d
            "ocsr_variant_candidates", "ocsr_ctx_set_variant", "ocsr_dense_workspace_bytes",
            "ocsr_dense_match", "ocsr_box_points", "ocsr_select_boxes",
            "ocsr_rect_workspace_bytes", "ocsr_rect_offset_counts", "ocsr_rect_filter_create",
-           "ocsr_rect_filter_destroy", "ocsr_rect_filter_update", "ocsr_measure_int_rate"]
+           "ocsr_rect_filter_destroy", "ocsr_rect_filter_update", "ocsr_measure_int_rate",
+           "ocsr_match_boxes_noalloc"]
 
 
 class OcsrError(RuntimeError):
@@ -208,6 +209,9 @@ def load(path: str = LIB_PATH):
         L.ocsr_rect_filter_destroy.restype = None
         L.ocsr_rect_filter_update.argtypes = [vp, vp, i32, i32, C.POINTER(i32), C.POINTER(i32)]
         L.ocsr_rect_filter_update.restype = i32
+        L.ocsr_match_boxes_noalloc.argtypes = [vp, C.POINTER(Level), C.POINTER(Level), vp, i32,
+                                               C.POINTER(MatchParams), i32, vp, C.POINTER(Debug), vp]
+        L.ocsr_match_boxes_noalloc.restype = i32
         L.ocsr_measure_int_rate.argtypes = [vp, i32, C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.ocsr_measure_int_rate.restype = i32
         _lib = L
@@ -375,6 +379,29 @@ def match_boxes(L0, R0, L1, R1, boxes: torch.Tensor, params: dict, close_scale: 
                               C.byref(dbg) if dbg is not None else None, _stream(dev)))
     if debug:
         return out, extra
+    return out
+
+
+def match_boxes_noalloc(L0, R0, L1, R1, boxes: torch.Tensor, params: dict,
+                        close_scale: int | None = None, cap_blocks: int = 1 << 16,
+                        out: torch.Tensor | None = None) -> torch.Tensor:
+    """match_boxes with the library's own device scratch (no workspace, nothing allocated
+    by the library). Returns the int32 [N, 8] result tensor."""
+    _need_cuda(boxes)
+    if boxes.dtype != torch.int32 or boxes.dim() != 2 or boxes.shape[1] != 5 or not boxes.is_contiguous():
+        raise ValueError("boxes must be a contiguous int32 [N, 5] tensor")
+    dev = boxes.device
+    sx, sy = params["sx"], params["sy"]
+    s = close_scale if close_scale is not None else params["close_scale"]
+    lv0 = _level(L0, R0, 1, sx, sy)
+    lv1 = _level(L1, R1, s, sx, sy) if L1 is not None else _level(L0, R0, 1, sx, sy)
+    n = boxes.shape[0]
+    if out is None:
+        out = torch.empty((n, 8), dtype=torch.int32, device=dev)
+    q = make_params(params)
+    _check(load().ocsr_match_boxes_noalloc(context(dev.index), C.byref(lv0), C.byref(lv1),
+                                           _dptr(boxes), n, C.byref(q), cap_blocks, _dptr(out),
+                                           None, _stream(dev)))
     return out
 
 
