@@ -3,20 +3,25 @@
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 
-Workload (one step = the whole path over one frame): the realistic 1920x1080 frame --
-census of both views at both levels (on the 64x32 tiles the boxes' searches read), then
-per-box planning, forward/backward Hamming
-block search with WTA and parabola, L/R check, aggregation and depth, for 32 ranged
-boxes (19 far, 13 close) plus 32 occluder boxes. Inputs are resident in HBM before
-the timed region starts.
+Headline workload (one step = the whole path over one batch): 16 uint8 stereo pairs of
+1920x1200 with min(128, Poisson(40)) boxes each (log-uniform 12..512 px, overlaps
+occlude), ranged by one ocsr_range_batch call -- census of both views at both levels (on
+the 64x32 tiles the boxes' searches read), per-box planning, forward/backward Hamming
+block search with WTA and parabola, L/R check, aggregation and depth -- with the kernel
+variants, blocks per wave and grid chosen by the autotuner beforehand. Inputs are
+resident in HBM before the timed region starts.
 
-Prints one JSON line: Gcost/s (one cost = one 64-bit Hamming term, forward or
-backward) over the timed steps, per-frame p50/p99 latency, the dominant kernel's
-roofline, and the CPU oracle's rate on a bounded sample of the same workload.
+Prints one JSON line: Gcost/s (one cost = one 64-bit Hamming term, forward or backward)
+over the timed steps, the dominant kernel's roofline, the CPU oracle's rate on a bounded
+sample of the same workload (one thread and all host threads), and sub-objects for the
+other workloads: the 640x480 and realistic 1080p frames, the dense counterpart, the
+vertical and rectification-offset searches, selection, 3D points and the serving mix,
+with per-frame p50/p99 latencies.
 """
 from __future__ import annotations
 
 import argparse
+import concurrent.futures as cf
 import json
 import os
 import sys
@@ -27,6 +32,7 @@ INT_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12      # int32 VALU lane-ops/s: CUs x lane
 HBM_PEAK_GBS = 8000.0
 CENSUS_OPS_PER_CMP = 1                        # one lane-op per informative comparison bit
 MATCH_OPS_PER_COST = 4                        # 2 x v_xor_b32 + 2 x v_bcnt_u32_b32
+BATCH_FRAMES = 16
 
 
 def parse():
@@ -34,14 +40,15 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=300)
     ap.add_argument("--warmup", type=int, default=30)
-    ap.add_argument("--latency-steps", type=int, default=1000)
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--latency-steps", type=int, default=1000,
+                    help="frames (or batches) per latency distribution")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="seconds of each CPU-oracle leg (one thread, all threads)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--batch-steps", type=int, default=40,
-                    help="timed repetitions of the 16-frame batch (0 skips the batch section)")
-    ap.add_argument("--serve-requests", type=int, default=600,
+    ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (library defaults)")
+    ap.add_argument("--serve-requests", type=int, default=10000,
                     help="requests of the serving section at 120/s (0 skips it)")
-    ap.add_argument("--serve-pool", type=int, default=2,
+    ap.add_argument("--serve-pool", type=int, default=32,
                     help="pre-rendered image pairs per serving resolution")
     ap.add_argument("--vertical-steps", type=int, default=100,
                     help="frames of the vertical-range workload (0: skip)")
@@ -49,46 +56,128 @@ def parse():
                     help="frames of the rectification-offset workload (0: skip)")
     ap.add_argument("--dense-steps", type=int, default=20,
                     help="timed repetitions of the dense counterpart (0 skips it)")
+    ap.add_argument("--frame-steps", type=int, default=300,
+                    help="timed repetitions of the single-frame workloads (0 skips them)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run a plain device-to-device copy of MB megabytes five times "
                          "(the reference kernel that scales the HBM byte counters)")
+    ap.add_argument("--int-peak", action="store_true",
+                    help="only measure the int32 vector-ALU rate with the library's chain kernel")
     ap.add_argument("--fused", action="store_true",
-                    help="run the one-launch persistent kernel instead of the multi-launch path")
+                    help="time the headline batch as the one-launch persistent kernel")
     return ap.parse_args()
 
 
-def cpu_baseline(sc, params, costs_per_frame, seconds):
-    """The oracle as it stands, on the host cores, repeated on the same frame."""
-    from oracle import oracle as orc
-    if not os.path.exists(orc.LIB):
-        orc.build()
-    cores = len(os.sched_getaffinity(0))
-    reps = 0
+# ------------------------------------------------------------------------------------
+# inputs (rendered on the host before the GPU is touched, in worker processes)
+# ------------------------------------------------------------------------------------
+
+def _render_batch_frame(f):
+    from paper_2604_07980_amd import synth
+    return synth.scene_batch_frame(f)
+
+
+def _render_pool_pair(args):
+    from paper_2604_07980_amd import synth
+    res, i, seed = args
+    return synth.serving_pool_pair(res, i, seed=seed)
+
+
+def render_inputs(args):
+    """The 16 batch frames and the serving pools, rendered in parallel processes (before
+    any HIP call in this process)."""
+    from paper_2604_07980_amd import synth
+    workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    pool_jobs = []
+    if args.serve_requests > 0:
+        for k, res in enumerate(synth.SERVING_RESOLUTIONS):
+            pool_jobs += [(res, i, 5000 + k) for i in range(args.serve_pool)]
+    with cf.ProcessPoolExecutor(max_workers=workers) as ex:
+        frames = list(ex.map(_render_batch_frame, range(BATCH_FRAMES)))
+        pairs = list(ex.map(_render_pool_pair, pool_jobs))
+    pools = [[] for _ in synth.SERVING_RESOLUTIONS]
+    for (res, _, _), pair in zip(pool_jobs, pairs):
+        pools[synth.SERVING_RESOLUTIONS.index(res)].append(pair)
+    return frames, pools
+
+
+# ------------------------------------------------------------------------------------
+# helpers
+# ------------------------------------------------------------------------------------
+
+def log(msg):
+    """Progress line on stderr (the JSON result is the one line on stdout)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
+def timed(fn, steps, warmup):
+    """ms per call over `steps` back-to-back calls after `warmup` untimed ones, bracketed
+    by device synchronisation on both sides."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    while True:
-        orc.run_scene(sc.left, sc.right, params, sc.boxes, threads=cores)
-        reps += 1
-        el = time.perf_counter() - t0
-        if el >= seconds:
-            break
-    return {"value": costs_per_frame * reps / el / 1e9, "unit": "Gcost/s", "cores": cores,
-            "kind": "oracle",
-            "sample": f"{reps} repetitions of the realistic 1920x1080 frame (census of both views "
-                      f"at both levels + matching of 64 boxes), {el:.1f} s, OpenMP over rows/boxes",
-            "ms_per_frame": 1e3 * el / reps}
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return 1e3 * (time.perf_counter() - t0) / steps
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed counter measurement
-    (profiles/traffic.json), or None when there is none or the kernel's sources changed
-    since it was taken."""
+def latency(fn, n):
+    """p50/p99 (ms) of enqueue-to-result on the host, one call at a time."""
+    import numpy as np
+    import torch
+    lat = []
+    for _ in range(n):
+        a = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        lat.append(1e3 * (time.perf_counter() - a))
+    lat = np.array(lat)
+    return {"p50": round(float(np.percentile(lat, 50)), 4),
+            "p99": round(float(np.percentile(lat, 99)), 4), "n": int(len(lat))}
+
+
+def kernel_times(ocsr, fn, steps, names):
+    """Per-kernel average duration (us) from the HIP events the launches carry."""
+    import torch
+    ocsr.reset_timing()
+    ocsr.set_timing(True)
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    ocsr.set_timing(False)
+    out = {}
+    for name in names:
+        cnt, tot = ocsr.kernel_time(name)
+        if cnt:
+            out[name] = {"launches": cnt, "avg_us": round(1e3 * tot / cnt, 3)}
+    return out
+
+
+def price(kern, ops):
+    """Adds the achieved int32 rate and its fraction of the peak to each timed kernel."""
+    for k, v in ops.items():
+        if k in kern:
+            tops = v / (kern[k]["avg_us"] * 1e-6) / 1e12
+            kern[k]["ops_per_launch"] = int(v)
+            kern[k]["tops"] = round(tops, 3)
+            kern[k]["frac"] = round(tops / INT_PEAK_TOPS, 4)
+    return kern
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` on `workload` from the committed counter
+    measurement (profiles/traffic.json), or None when there is none or the kernel's
+    sources changed since it was taken."""
     from paper_2604_07980_amd import profiling
     key = {"census": "census", "match": "match", "match_close": "match",
            "match_far": "match", "aggregate": "aggregate"}.get(kernel)
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "traffic.json")
     if key is None or not os.path.exists(path):
         return None
-    entry = json.load(open(path)).get(key)
+    entry = json.load(open(path)).get(workload, {}).get(kernel)
     if not entry or entry.get("source_sha256") != profiling.source_hash(key):
         return None
     return round(entry["fetch_bytes"] + entry["write_bytes"])
@@ -100,17 +189,271 @@ def frame_costs(ocsr, L, R, boxes, p):
     g = ocsr.census_many([L, R, L, R], [1, 1, p["close_scale"], p["close_scale"]])
     _, extra = ocsr.match_boxes(*g, boxes, p, debug=True, cap_blocks=1 << 16)
     nb, rec, _, _ = ocsr.debug_to_numpy(extra)
+    return costs_of_records(rec, p) | {"blocks": int(nb)}
+
+
+def costs_of_records(rec, p):
+    """Costs (per-point Hamming terms, forward and backward) of eligible blocks."""
+    import numpy as np
     el = rec["eligible"] == 1
     pts = np.array([bin(int(m)).count("1") for m in rec["mask"]], dtype=np.int64)
     far = rec["level_scale"] == 1
     # vertical offsets per block: floor(dy_min / s) .. ceil(dy_max / s) on its level
     s = rec["level_scale"].astype(np.int64)
     ndy = -(-p.get("dy_max", 0) // s) - p.get("dy_min", 0) // s + 1
-    cand = rec["nd"] * ndy
+    cand = rec["nd"].astype(np.int64) * ndy
     return {"costs": int((pts * cand * el).sum()) * 2,
             "costs_far": int((pts * cand * (el & far)).sum()) * 2,
-            "evals": int((cand * el).sum()) * 2,
-            "blocks": int(nb)}
+            "evals": int((cand * el).sum()) * 2}
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+# ------------------------------------------------------------------------------------
+# CPU baseline: the oracle as it stands on a bounded sample of the headline workload
+# ------------------------------------------------------------------------------------
+
+def cpu_baseline(scenes, params, seconds):
+    from oracle import oracle as orc
+    if not os.path.exists(orc.LIB):
+        orc.build()
+    cores = len(os.sched_getaffinity(0))
+    # work of each frame from the oracle's own block records (outside the timing)
+    costs = []
+    for sc in scenes:
+        _, (_, blk, *_rest) = orc.run_scene(sc.left, sc.right, params, sc.boxes, debug=True,
+                                           threads=cores)
+        costs.append(costs_of_records(blk, params)["costs"])
+
+    def leg(threads):
+        done, c, t0 = 0, 0, time.perf_counter()
+        while True:
+            k = done % len(scenes)
+            sc = scenes[k]
+            orc.run_scene(sc.left, sc.right, params, sc.boxes, threads=threads)
+            done += 1
+            c += costs[k]
+            el = time.perf_counter() - t0
+            if el >= seconds:
+                return {"value": round(c / el / 1e9, 4), "frames": done, "seconds": round(el, 2),
+                        "ms_per_frame": round(1e3 * el / done, 2)}
+
+    one = leg(1)
+    many = leg(cores)
+    return {"value": many["value"], "unit": "Gcost/s", "cores": cores, "kind": "oracle",
+            "sample": f"{many['frames']} frames of the 16-frame batch taken in order, one at a "
+                      f"time ({many['seconds']} s; full census of both views at both levels, "
+                      f"then matching), OpenMP over rows and boxes on {cores} threads",
+            "ms_per_frame": many["ms_per_frame"],
+            "single_thread": dict(one, unit="Gcost/s", cores=1,
+                                  sample=f"{one['frames']} frames of the batch, one thread"),
+            "cpu_model": cpu_model(), "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
+
+
+# ------------------------------------------------------------------------------------
+# headline: the 16-frame batch
+# ------------------------------------------------------------------------------------
+
+def batch_workload(ocsr, scenes, args):
+    import numpy as np
+    import torch
+    from paper_2604_07980_amd import accounting, autotune, synth
+    dev = torch.device("cuda:0")
+    p = synth.params_for(3)
+    imgs = [(torch.from_numpy(s.left).to(dev), torch.from_numpy(s.right).to(dev)) for s in scenes]
+    fboxes = [torch.from_numpy(s.boxes).to(dev) for s in scenes]
+    boxes = torch.cat(fboxes).contiguous()
+    frames = [(L, R, b.shape[0]) for (L, R), b in zip(imgs, fboxes)]
+    work = [frame_costs(ocsr, L, R, b, p) for (L, R), b in zip(imgs, fboxes)]
+    costs = sum(w["costs"] for w in work)
+    costs_far = sum(w["costs_far"] for w in work)
+    evals = sum(w["evals"] for w in work)
+    ws_b, ws_f = ocsr.Workspace(), ocsr.Workspace()
+    out_b = torch.empty((boxes.shape[0], 8), dtype=torch.int32, device=dev)
+    outs_f = [torch.empty((b.shape[0], 8), dtype=torch.int32, device=dev) for b in fboxes]
+
+    def batch():
+        ocsr.range_batch(frames, boxes, p, workspace=ws_b, out=out_b)
+
+    def per_frame():
+        for (L, R), b, o in zip(imgs, fboxes, outs_f):
+            ocsr.range_frame(L, R, b, p, workspace=ws_f, out=o)
+
+    ms_untuned = timed(batch, max(10, args.steps // 10), 3)
+    table = None
+    if not args.no_tune:
+        def run_batch():
+            batch()
+            return out_b
+        table = autotune.tune(run_batch, p, reps=5, warmup=2)
+    ref = None
+    if args.fused:
+        batch()
+        ref = out_b.clone()
+        ocsr.set_fused(True)
+
+    # timed region: K back-to-back batches
+    ms = timed(batch, args.steps, args.warmup)
+    kern = kernel_times(ocsr, batch, args.steps,
+                        ("census", "match", "match_far", "match_close", "aggregate", "fused"))
+    lat_batch = latency(batch, max(50, args.latency_steps // 5))
+    fused_identical = None
+    if args.fused:
+        fused_identical = bool(torch.equal(out_b, ref))
+        ocsr.set_fused(False)
+
+    census_px = sum(accounting.census_pixels(s.left.shape[1], s.left.shape[0],
+                                             accounting.census_tiles(s.left.shape[1], s.left.shape[0],
+                                                                     s.boxes, p), p)
+                    for s in scenes)
+    census_px_full = sum(2 * L.numel() + 2 * (L.shape[0] // p["close_scale"]) * (L.shape[1] // p["close_scale"])
+                         for L, _ in imgs)
+    census_ops = census_px * ((2 * p["sx"] + 1) * (2 * p["sy"] + 1) - 1) * CENSUS_OPS_PER_CMP
+    ops = {"census": census_ops, "match": costs * MATCH_OPS_PER_COST,
+           "match_far": costs_far * MATCH_OPS_PER_COST,
+           "match_close": (costs - costs_far) * MATCH_OPS_PER_COST,
+           "fused": census_ops + costs * MATCH_OPS_PER_COST}
+    price(kern, ops)
+
+    # the same batch against 16 per-frame calls, the one-launch form and a replayed graph
+    ms_frames = timed(per_frame, max(10, args.steps // 10), 3)
+    identical = bool(torch.equal(out_b, torch.cat(outs_f)))
+    lat_frames = []
+    for (L, R), b, o in zip(imgs, fboxes, outs_f):
+        lat_frames.append(latency(lambda: ocsr.range_frame(L, R, b, p, workspace=ws_f, out=o),
+                                  max(20, args.latency_steps // 20)))
+    ref = out_b.clone()
+    ocsr.set_fused(True)
+    ms_fused = timed(batch, max(10, args.steps // 10), 3)
+    fused_same = bool(torch.equal(out_b, ref))
+    fkern = kernel_times(ocsr, batch, 10, ("fused",))
+    ocsr.set_fused(False)
+    ocsr.set_graph(True)
+    ms_graph = timed(batch, max(10, args.steps // 10), 3)
+    graph_same = bool(torch.equal(out_b, ref))
+    ocsr.set_graph(False)
+    if table is not None:
+        autotune.reset(p)
+    res = {
+        "workload": "batch_16x1920x1200: 16 uint8 stereo pairs, min(128, Poisson(40)) boxes per "
+                    "frame (log-uniform 12..512 px, overlaps occlude), far 4x4 blocks d 0..31 at "
+                    "s=1, close 8x8 blocks d 0..191 at s=2, census 7x9 on the tiles the searches "
+                    "read, trimmed median; one ocsr_range_batch call per step",
+        "frames": BATCH_FRAMES, "boxes": int(boxes.shape[0]), "blocks": sum(w["blocks"] for w in work),
+        "costs_per_batch": costs, "costs_far": costs_far, "block_evals_per_batch": evals,
+        "census_level_px": census_px, "census_level_px_all_tiles": census_px_full,
+    }
+    details = {
+        "ms_per_batch_untuned": round(ms_untuned, 4),
+        "autotune": None if table is None else {"variants": table.variants,
+                                                 "blocks_per_wave": table.blocks_per_wave,
+                                                 "match_wgs_per_cu": table.match_wgs_per_cu},
+        "latency_ms_per_batch": lat_batch,
+        "ms_16_frame_calls": round(ms_frames, 4),
+        "speedup_vs_16_calls": round(ms_frames / ms, 3),
+        "identical_to_16_calls": identical,
+        "per_frame_call_latency_ms": {
+            "p50_median_over_frames": round(float(np.median([x["p50"] for x in lat_frames])), 4),
+            "p99_max_over_frames": round(float(max(x["p99"] for x in lat_frames)), 4)},
+        "one_launch": {"ms_per_batch": round(ms_fused, 4), "identical": fused_same,
+                       "kernel_us": fkern.get("fused", {}).get("avg_us")},
+        "graph": {"ms_per_batch": round(ms_graph, 4), "identical": graph_same},
+    }
+    if fused_identical is not None:
+        details["headline_fused_identical"] = fused_identical
+    return p, res, details, ms, kern
+
+
+# ------------------------------------------------------------------------------------
+# single-frame workloads
+# ------------------------------------------------------------------------------------
+
+def frame_section(ocsr, sc, p, name, args, graph=False):
+    """One frame per step: ms per frame, Gcost/s, kernel times, per-frame p50/p99, and with
+    `graph` the same submitted as a replayed HIP graph."""
+    import torch
+    from paper_2604_07980_amd import accounting
+    dev = torch.device("cuda:0")
+    L = torch.from_numpy(sc.left).to(dev)
+    R = torch.from_numpy(sc.right).to(dev)
+    boxes = torch.from_numpy(sc.boxes).to(dev)
+    H, W = sc.left.shape
+    fw = frame_costs(ocsr, L, R, boxes, p)
+    ws = ocsr.Workspace()
+    out = torch.empty((boxes.shape[0], 8), dtype=torch.int32, device=dev)
+
+    def step():
+        ocsr.range_frame(L, R, boxes, p, workspace=ws, out=out)
+
+    ms = timed(step, args.frame_steps, max(3, args.warmup))
+    kern = kernel_times(ocsr, step, args.frame_steps,
+                        ("census", "match", "match_far", "match_close", "aggregate"))
+    tiles = accounting.census_tiles(W, H, sc.boxes, p)
+    census_px = accounting.census_pixels(W, H, tiles, p)
+    census_ops = census_px * ((2 * p["sx"] + 1) * (2 * p["sy"] + 1) - 1)
+    price(kern, {"census": census_ops, "match": fw["costs"] * MATCH_OPS_PER_COST,
+                 "match_far": fw["costs_far"] * MATCH_OPS_PER_COST,
+                 "match_close": (fw["costs"] - fw["costs_far"]) * MATCH_OPS_PER_COST})
+    res = {"workload": name, "ms_per_frame": round(ms, 4),
+           "value": round(fw["costs"] / (ms * 1e-3) / 1e9, 3), "unit": "Gcost/s",
+           "costs_per_frame": fw["costs"], "costs_far": fw["costs_far"], "blocks": fw["blocks"],
+           "block_evals_per_frame": fw["evals"], "census_level_px": census_px,
+           "census_tiles": len(tiles), "kernels": kern,
+           "latency_ms": latency(step, args.latency_steps)}
+    if graph:
+        ocsr.set_graph(True)
+        res["graph"] = {"ms_per_frame": round(timed(step, args.frame_steps, max(3, args.warmup)), 4),
+                        "latency_ms": latency(step, args.latency_steps)}
+        ocsr.set_graph(False)
+    return res, (L, R, boxes, out, ms)
+
+
+def points_and_select(ocsr, synth, boxes, out, W, H, p, steps):
+    import numpy as np
+    import torch
+    dev = torch.device("cuda:0")
+    n = boxes.shape[0]
+    geom = synth.point_geometry(W, H, p)
+    pts = ocsr.box_points(boxes, out, geom)
+    ocsr.reset_timing()
+    ocsr.set_timing(True)
+    for _ in range(steps):
+        ocsr.box_points(boxes, out, geom, out=pts)
+    torch.cuda.synchronize()
+    ocsr.set_timing(False)
+    pcnt, ptot = ocsr.kernel_time("points")
+    points = {"boxes": int(n), "valid": int(ocsr.points_to_numpy(pts)["valid"].sum()),
+              "us_per_call": round(1e3 * ptot / max(pcnt, 1), 3)}
+    sel_out, sel_rank = ocsr.select_boxes([(W, H, n)], boxes, 20)
+    rng = np.random.default_rng(77)
+    bx0 = rng.integers(-80, W, 16000)
+    by0 = rng.integers(-80, H, 16000)
+    many = torch.from_numpy(np.stack([bx0, by0, bx0 + rng.integers(1, 400, 16000),
+                                      by0 + rng.integers(1, 300, 16000), np.ones(16000, int)],
+                                     1).astype(np.int32)).to(dev)
+    many_out, many_rank = ocsr.select_boxes([(W, H, 1000)] * 16, many, 20)
+    select = {"budget": 20}
+    for key, frames_, bx, o, r in (("frame_64_boxes", [(W, H, n)], boxes, sel_out, sel_rank),
+                                   ("16_frames_1000_boxes", [(W, H, 1000)] * 16, many, many_out,
+                                    many_rank)):
+        ocsr.reset_timing()
+        ocsr.set_timing(True)
+        for _ in range(steps):
+            ocsr.select_boxes(frames_, bx, 20, out=o, rank=r)
+        torch.cuda.synchronize()
+        ocsr.set_timing(False)
+        scnt, stot = ocsr.kernel_time("select")
+        select[key] = {"us_per_call": round(1e3 * stot / max(scnt, 1), 3)}
+    select["frame_64_boxes"]["kept"] = int(((sel_out[:, 4] & 1) == 1).sum().item())
+    return points, select
 
 
 def vertical_section(ocsr, synth, steps, warmup):
@@ -118,7 +461,6 @@ def vertical_section(ocsr, synth, steps, warmup):
     offsets on the far level, 5 on the close level): whole-frame time and the rate of the
     dy matching kernel (both levels in one launch; the same op count per Hamming cost as
     the horizontal kernels)."""
-    import numpy as np
     import torch
     dev = torch.device("cuda:0")
     sc = synth.scene_realistic()
@@ -133,165 +475,42 @@ def vertical_section(ocsr, synth, steps, warmup):
     def step():
         ocsr.range_frame(L, R, boxes, p, workspace=ws, out=out)
 
-    for _ in range(warmup):
-        step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        step()
-    torch.cuda.synchronize()
-    ms = 1e3 * (time.perf_counter() - t0) / steps
-    ocsr.reset_timing()
-    ocsr.set_timing(True)
-    for _ in range(steps):
-        step()
-    torch.cuda.synchronize()
-    ocsr.set_timing(False)
-    kern = {}
-    work = {"match": fw["costs"] * MATCH_OPS_PER_COST}
-    for name in ("census", "match", "aggregate"):
-        cnt, tot = ocsr.kernel_time(name)
-        if cnt:
-            kern[name] = {"avg_us": round(1e3 * tot / cnt, 3)}
-            if name in work:
-                tops = work[name] / (1e-3 * tot / cnt) / 1e12
-                kern[name].update(tops=round(tops, 3), frac=round(tops / INT_PEAK_TOPS, 4))
+    ms = timed(step, steps, warmup)
+    kern = price(kernel_times(ocsr, step, steps, ("census", "match", "aggregate")),
+                 {"match": fw["costs"] * MATCH_OPS_PER_COST})
     res = ocsr.results_to_numpy(out)
     return {"workload": "realistic_1080p, right view 2 rows low, dy -3..3 (far 7, close 5 "
                         "level offsets)",
-            "ms_per_step": round(ms, 4), "costs_per_frame": fw["costs"],
-            "gcost_per_s": round(fw["costs"] / (ms * 1e-3) / 1e9, 3),
+            "ms_per_frame": round(ms, 4), "costs_per_frame": fw["costs"],
+            "value": round(fw["costs"] / (ms * 1e-3) / 1e9, 3), "unit": "Gcost/s",
             "valid_boxes": int(res["valid"].sum()), "kernels": kern}
 
 
-def batch_section(ocsr, synth, steps, warmup):
-    """16 frames of 1920x1200, min(128, Poisson(40)) boxes each: one batch call against
-    16 per-frame calls on the same inputs, with identical outputs required."""
-    import torch
-    from paper_2604_07980_amd import accounting
-    dev = torch.device("cuda:0")
-    p = synth.params_for(3)
-    scenes = [synth.scene_batch_frame(f) for f in range(16)]
-    imgs = [(torch.from_numpy(s.left).to(dev), torch.from_numpy(s.right).to(dev)) for s in scenes]
-    fboxes = [torch.from_numpy(s.boxes).to(dev) for s in scenes]
-    boxes = torch.cat(fboxes).contiguous()
-    frames = [(L, R, b.shape[0]) for (L, R), b in zip(imgs, fboxes)]
-    work = [frame_costs(ocsr, L, R, b, p) for (L, R), b in zip(imgs, fboxes)]
-    costs = sum(w["costs"] for w in work)
-    ws_b, ws_f = ocsr.Workspace(), ocsr.Workspace()
-    out_b = torch.empty((boxes.shape[0], 8), dtype=torch.int32, device=dev)
-    outs_f = [torch.empty((b.shape[0], 8), dtype=torch.int32, device=dev) for b in fboxes]
-
-    def batch():
-        ocsr.range_batch(frames, boxes, p, workspace=ws_b, out=out_b)
-
-    def per_frame():
-        for (L, R), b, o in zip(imgs, fboxes, outs_f):
-            ocsr.range_frame(L, R, b, p, workspace=ws_f, out=o)
-
-    def timed(fn):
-        for _ in range(warmup):
-            fn()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            fn()
-        torch.cuda.synchronize()
-        return 1e3 * (time.perf_counter() - t0) / steps
-
-    ms_default = timed(batch)
-    # kernel variant, blocks per wave and grid from the autotuner, on this workload
-    from paper_2604_07980_amd import autotune
-
-    def run_batch():
-        batch()
-        return out_b
-    table = autotune.tune(run_batch, p, reps=5, warmup=2)
-    ms_batch = timed(batch)
-    ocsr.reset_timing()
-    ocsr.set_timing(True)
-    for _ in range(steps):
-        batch()
-    torch.cuda.synchronize()
-    ocsr.set_timing(False)
-    kern = {}
-    for name in ("census", "match", "match_far", "match_close", "aggregate"):
-        cnt, tot = ocsr.kernel_time(name)
-        if cnt:
-            kern[name] = {"launches": cnt, "avg_us": round(1e3 * tot / cnt, 3)}
-    # level pixels of the census tiles the call makes (those some box's search reads)
-    census_px = sum(accounting.census_pixels(s.left.shape[1], s.left.shape[0],
-                                             accounting.census_tiles(s.left.shape[1], s.left.shape[0],
-                                                                     s.boxes, p), p)
-                    for s in scenes)
-    census_px_full = sum(2 * L.numel() + 2 * (L.shape[0] // p["close_scale"]) * (L.shape[1] // p["close_scale"])
-                         for L, _ in imgs)
-    costs_far = sum(w["costs_far"] for w in work)
-    ops = {"census": census_px * 62, "match": costs * 4, "match_far": costs_far * 4,
-           "match_close": (costs - costs_far) * 4}
-    for k, v in ops.items():
-        if k in kern:
-            kern[k]["tops"] = round(v / (kern[k]["avg_us"] * 1e-6) / 1e12, 3)
-            kern[k]["frac"] = round(kern[k]["tops"] / INT_PEAK_TOPS, 4)
-    ms_frames = timed(per_frame)          # per-frame calls with the same tuned settings
-    identical = bool(torch.equal(out_b, torch.cat(outs_f)))
-    autotune.reset(p)
-    return {"workload": "batch_16x1920x1200: 16 uint8 stereo pairs, min(128, Poisson(40)) boxes "
-                        "per frame (log-uniform 12..512 px, overlaps occlude), params as the "
-                        "realistic frame",
-            "boxes": int(boxes.shape[0]), "blocks": sum(w["blocks"] for w in work),
-            "census_level_px": census_px, "census_level_px_all_tiles": census_px_full,
-            "costs_per_batch": costs, "steps": steps,
-            "ms_per_batch": round(ms_batch, 4),
-            "value": round(costs / (ms_batch * 1e-3) / 1e9, 3), "unit": "Gcost/s",
-            "ms_per_batch_untuned": round(ms_default, 4),
-            "autotune": {"variants": table.variants, "blocks_per_wave": table.blocks_per_wave,
-                         "match_wgs_per_cu": table.match_wgs_per_cu},
-            "kernels": kern,
-            "ms_16_frame_calls": round(ms_frames, 4),
-            "speedup_vs_16_calls": round(ms_frames / ms_batch, 3),
-            "identical_to_16_calls": identical}
-
-
-def dense_section(ocsr, L, R, steps, sparse_ms):
-    """The dense counterpart on the same 1920x1080 pair: census of both views at full
+def dense_section(ocsr, L, R, steps, sparse_ms, lat_steps):
+    """The dense counterpart on the realistic 1920x1080 pair: census of both views at full
     resolution, then every pixel over d = 0..191 with 5x5 summed Hamming costs, WTA in
     both views and the L/R check."""
-    import torch
     W, H = L.shape[1], L.shape[0]
     ws = ocsr.Workspace()
+    holder = {}
 
     def run():
         CL, CR = ocsr.census_many([L, R], [1, 1])
-        return ocsr.dense(CL, CR, 0, 191, 2, 1, workspace=ws)
+        holder["disp"] = ocsr.dense(CL, CR, 0, 191, 2, 1, workspace=ws)
 
-    for _ in range(3):
-        run()
-    torch.cuda.synchronize()
-    ocsr.reset_timing()
-    ocsr.set_timing(True)
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        disp = run()
-    torch.cuda.synchronize()
-    ms = 1e3 * (time.perf_counter() - t0) / steps
-    ocsr.set_timing(False)
-    kern = {}
-    for name in ("census", "dense", "dense_check"):
-        cnt, tot = ocsr.kernel_time(name)
-        if cnt:
-            kern[name] = {"launches": cnt, "avg_us": round(1e3 * tot / cnt, 3)}
+    ms = timed(run, steps, 3)
     costs = W * H * 192
-    if "dense" in kern:
-        # 4 int32 ops per cost in each of the two views
-        kern["dense"]["tops"] = round(2 * 4 * costs / (kern["dense"]["avg_us"] * 1e-6) / 1e12, 3)
+    kern = price(kernel_times(ocsr, run, steps, ("census", "dense", "dense_check")),
+                 {"dense": 2 * MATCH_OPS_PER_COST * costs})   # 4 ops per cost in each view
+    disp = holder["disp"]
     return {"workload": "dense_1080p: the realistic 1920x1080 pair, census 7x9 at s=1, "
                         "d = 0..191, 5x5 window, WTA left and right, L/R <= 1",
             "costs_per_frame": costs, "ms_per_frame": round(ms, 4),
             "value": round(costs / (ms * 1e-3) / 1e9, 3), "unit": "Gcost/s",
             "valid_fraction": round(float((disp >= 0).float().mean()), 4),
             "ms_sparse_frame": round(sparse_ms, 4),
-            "dense_over_sparse_time": round(ms / sparse_ms, 2), "kernels": kern}
+            "dense_over_sparse_time": round(ms / sparse_ms, 2), "kernels": kern,
+            "latency_ms": latency(run, lat_steps)}
 
 
 def rect_section(ocsr, synth, steps):
@@ -313,68 +532,50 @@ def rect_section(ocsr, synth, steps):
         CL, CR = ocsr.census_many([L, R], [2, 2])
         ocsr.rect_offset_counts(CL, CR, p, workspace=ws, counts=counts)
 
-    for _ in range(3):
-        run()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        run()
-    torch.cuda.synchronize()
-    ms = 1e3 * (time.perf_counter() - t0) / steps
-    ocsr.reset_timing()
-    ocsr.set_timing(True)
-    for _ in range(steps):
-        run()
-    torch.cuda.synchronize()
-    ocsr.set_timing(False)
-    kern = {}
+    ms = timed(run, steps, 3)
     costs = 9 * p["roi_w"] * p["roi_h"] * (p["dmax"] - p["dmin"] + 1)
-    for name in ("census", "rect_dense", "rect_count"):
-        cnt, tot = ocsr.kernel_time(name)
-        if cnt:
-            kern[name] = {"avg_us": round(1e3 * tot / cnt, 3)}
-    if "rect_dense" in kern:
-        # 4 int32 ops per cost in each of the two views
-        tops = 2 * MATCH_OPS_PER_COST * costs / (kern["rect_dense"]["avg_us"] * 1e-6) / 1e12
-        kern["rect_dense"].update(tops=round(tops, 3), frac=round(tops / INT_PEAK_TOPS, 4))
+    kern = price(kernel_times(ocsr, run, steps, ("census", "rect_dense", "rect_count")),
+                 {"rect_dense": 2 * MATCH_OPS_PER_COST * costs})
     f = ocsr.RectFilter(5, 1)
     raw, filt = f.update(counts.cpu().numpy(), p["delta_min"])
     return {"workload": "road_1080p: ground-like 1920x1080 pair, right view 6 rows low; s=2, "
                         "ROI 960x128, offsets -4..4, dense d 0..63 5x5, count d > 2",
             "ms_per_frame": round(ms, 4), "costs_per_frame": costs,
-            "gcost_per_s": round(costs / (ms * 1e-3) / 1e9, 3),
+            "value": round(costs / (ms * 1e-3) / 1e9, 3), "unit": "Gcost/s",
             "estimate_level_rows": raw, "first_filtered": filt, "kernels": kern}
 
 
-def serving_section(ocsr, synth, n_requests, pool_size):
+def serving_section(ocsr, synth, pools_np, n_requests):
     """The serving workload: Poisson arrivals at 120/s mixing 1280x720, 1920x1080 and
-    3840x2160 frames (0.3/0.5/0.2) from resident image pools, 1..200 boxes, close
-    ranges 0..127/191/255; continuous batching under a 4 GiB budget. Also run with all
-    requests arriving at once (throughput), and as plain per-frame calls one after
+    3840x2160 frames (0.3/0.5/0.2) drawn from resident pools, 1..200 boxes, close ranges
+    0..127/191/255; continuous batching under a 4 GiB budget over 3 streams, each with a
+    resident workspace and graph-captured launches per frame-shape bucket. Also run with
+    every request arriving at once (throughput), and as plain per-frame calls one after
     another, whose outputs the served ones must equal."""
     import numpy as np
     import torch
     from paper_2604_07980_amd import serve
     dev = torch.device("cuda:0")
-    pools = [[(torch.from_numpy(L).to(dev), torch.from_numpy(R).to(dev))
-              for L, R in synth.serving_pool(res, pool_size, seed=5000 + k)]
-             for k, res in enumerate(synth.SERVING_RESOLUTIONS)]
-    spec = synth.serving_requests(n_requests, pool_sizes=(pool_size,) * 3)
+    pools = [[(torch.from_numpy(L).to(dev), torch.from_numpy(R).to(dev)) for L, R in pool]
+             for pool in pools_np]
+    spec = synth.serving_requests(n_requests, pool_sizes=tuple(len(pl) for pl in pools))
 
     def requests(at_once):
         return [serve.Request(q["rid"], *pools[q["res"]][q["pool"]], q["boxes"], q["params"],
                               0.0 if at_once else q["arrival"]) for q in spec]
 
+    ex = serve.GpuExecutor(n_slots=3)
+
     def served(at_once):
-        srv = serve.Server(serve.GpuExecutor(n_slots=3), mem_budget=4 << 30)
+        srv = serve.Server(ex, mem_budget=4 << 30)
         t0 = time.perf_counter()
         res = srv.run(requests(at_once))
         wall = time.perf_counter() - t0
         return res, serve.summarize(res, wall)
 
-    served(True)                                   # warm-up: kernels, pools, allocator
-    res_rt, rt = served(False)
+    served(True)                                   # warm-up: kernels, graphs, allocator
     res_sat, sat = served(True)
+    res_rt, rt = served(False)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     plain = []
@@ -382,35 +583,39 @@ def serving_section(ocsr, synth, n_requests, pool_size):
     for q in requests(True):
         out = ocsr.range_frame(q.left, q.right, torch.from_numpy(q.boxes).to(dev), q.params,
                                cap_blocks=1 << 18, workspace=ws)
-        plain.append(ocsr.results_to_numpy(out))
+        plain.append(out)
+    torch.cuda.synchronize()
     wall_plain = time.perf_counter() - t0
-    identical = all((a.boxes.view(np.int32) == b.view(np.int32)).all() and
+    plain = [ocsr.results_to_numpy(o) for o in plain]
+    identical = all(a.boxes is not None and c.boxes is not None and
+                    (a.boxes.view(np.int32) == b.view(np.int32)).all() and
                     (c.boxes.view(np.int32) == b.view(np.int32)).all()
                     for a, c, b in zip(res_rt, res_sat, plain))
     r4 = lambda v: None if v is None else round(v, 4)
+    summ = lambda s: {"frames_per_s": r4(s["frames_per_s"]),
+                      "latency_ms": {k: r4(v) for k, v in s["latency_ms"].items()},
+                      "mean_batch_frames": r4(s["mean_batch_frames"]), "served": s["served"],
+                      "rejected": s["rejected"]}
     return {"workload": f"serving mix: {n_requests} requests, Poisson 120/s, 1280x720 / 1920x1080 "
-                        f"/ 3840x2160 (0.3/0.5/0.2), 1..200 boxes, close 0..127/191/255, "
-                        f"{pool_size} resident pairs per resolution, 4 GiB budget, 3 streams",
-            "realtime_120_per_s": {"frames_per_s": r4(rt["frames_per_s"]),
-                                   "latency_ms": {k: r4(v) for k, v in rt["latency_ms"].items()},
-                                   "mean_batch_frames": r4(rt["mean_batch_frames"])},
-            "all_at_once": {"frames_per_s": r4(sat["frames_per_s"]),
-                            "latency_ms": {k: r4(v) for k, v in sat["latency_ms"].items()},
-                            "mean_batch_frames": r4(sat["mean_batch_frames"])},
+                        f"/ 3840x2160 (0.3/0.5/0.2) from pools of {len(pools[0])} resident pairs "
+                        f"per resolution, 1..200 boxes, close 0..127/191/255, 4 GiB budget, "
+                        f"3 streams with resident workspaces and per-shape graphs",
+            "realtime_120_per_s": summ(rt), "all_at_once": summ(sat),
             "plain_per_frame_calls": {"frames_per_s": r4(n_requests / wall_plain)},
+            "graphs": ex.graph_stats(),
             "identical_to_plain_calls": bool(identical)}
 
+
+# ------------------------------------------------------------------------------------
 
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the path is per frame "
-              "and shards by frames, see DESIGN.md", file=sys.stderr)
+              "and shards by frames across GPUs, which this build does not run", file=sys.stderr)
         sys.exit(2)
-    import numpy as np
     import torch
-
-    from paper_2604_07980_amd import accounting, ocsr, synth
+    from paper_2604_07980_amd import ocsr, synth
 
     if args.copy_calibration > 0:
         # a buffer well beyond the 256 MB last-level cache, so the copy's reads come from
@@ -424,193 +629,86 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes": n, "copies": 5}), flush=True)
         return
+    if args.int_peak:
+        torch.cuda.set_device(0)
+        rates = [ocsr.measure_int_rate(4096) for _ in range(5)]
+        best = max(r[0] for r in rates)
+        print(json.dumps({"int32_lane_ops_per_s": best, "tops": round(best / 1e12, 3),
+                          "spec_tops": round(INT_PEAK_TOPS, 2),
+                          "ms": [round(r[1], 4) for r in rates]}), flush=True)
+        return
 
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    sc = synth.scene_realistic()
-    p = synth.params_for(2)
-    H, W = sc.left.shape
-    L = torch.from_numpy(sc.left).to(dev)
-    R = torch.from_numpy(sc.right).to(dev)
-    boxes = torch.from_numpy(sc.boxes).to(dev)
-    n = boxes.shape[0]
-    ocsr.set_fused(args.fused)
-    ws = ocsr.Workspace()
-    out = torch.empty((n, 8), dtype=torch.int32, device=dev)
+    t_start = time.perf_counter()
+    scenes, pools = render_inputs(args)
+    log(f"inputs rendered ({time.perf_counter() - t_start:.1f} s)")
+    torch.cuda.set_device(torch.device("cuda:0"))
+    int_rate, _ = ocsr.measure_int_rate(4096)
 
-    # work of one frame, from the library's own block records (outside the timed region)
-    fw = frame_costs(ocsr, L, R, boxes, p)
-    costs, costs_far, evals, nb = fw["costs"], fw["costs_far"], fw["evals"], fw["blocks"]
-    census_px_full = 2 * (W * H) + 2 * (W // 2) * (H // 2)
-    tiles = accounting.census_tiles(W, H, sc.boxes, p)
-    tiles_all = accounting.census_tiles(W, H, sc.boxes, p, full=True)
-    census_px = accounting.census_pixels(W, H, tiles, p)   # pixels of the tiles made
-    census_bits = (2 * p["sx"] + 1) * (2 * p["sy"] + 1)
-
-    def step():
-        ocsr.range_frame(L, R, boxes, p, workspace=ws, out=out)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-
-    # timed region: K back-to-back frames
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_per_step = 1e3 * (t1 - t0) / args.steps
-
-    # the same K frames again with every kernel bracketed by HIP events on its stream
-    ocsr.reset_timing()
-    ocsr.set_timing(True)
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    ms_per_step_events = 1e3 * (time.perf_counter() - t2) / args.steps
-    ocsr.set_timing(False)
-    kern = {}
-    for name in ("census", "plan", "match", "match_far", "match_close", "aggregate", "reset",
-                 "fused", "graph"):
-        cnt, tot = ocsr.kernel_time(name)
-        if cnt:
-            kern[name] = {"launches": cnt, "avg_us": 1e3 * tot / cnt}
-
-    # per-frame latency: enqueue to result on the host, one frame at a time
-    lat = []
-    for _ in range(args.latency_steps):
-        a = time.perf_counter()
-        step()
-        torch.cuda.synchronize()
-        lat.append(1e3 * (time.perf_counter() - a))
-    lat = np.array(lat)
-
-    # the same frame submitted as a replayed HIP graph (one submission per frame)
-    ocsr.set_graph(True)
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    ms_graph = 1e3 * (time.perf_counter() - t0) / args.steps
-    glat = []
-    for _ in range(args.latency_steps):
-        a = time.perf_counter()
-        step()
-        torch.cuda.synchronize()
-        glat.append(1e3 * (time.perf_counter() - a))
-    ocsr.set_graph(False)
-    glat = np.array(glat)
-
-    # per-box 3D point and covariance from the frame's results (a step after the timed
-    # path): kernel time from HIP events, outside the timed steps
-    geom = synth.point_geometry(W, H, p)
-    pts = ocsr.box_points(boxes, out, geom)
-    ocsr.reset_timing()
-    ocsr.set_timing(True)
-    for _ in range(args.steps):
-        ocsr.box_points(boxes, out, geom, out=pts)
-    torch.cuda.synchronize()
-    ocsr.set_timing(False)
-    pcnt, ptot = ocsr.kernel_time("points")
-    points = {"boxes": int(n), "valid": int(ocsr.points_to_numpy(pts)["valid"].sum()),
-              "us_per_call": round(1e3 * ptot / max(pcnt, 1), 3)}
-
-    # priority selection under a budget of 20 objects (a step before ranging): kernel time
-    # on the frame's 64 boxes and on a 16-frame call of 1000 boxes each
-    sel_out, sel_rank = ocsr.select_boxes([(W, H, n)], boxes, 20)
-    rng = np.random.default_rng(77)
-    bx0 = rng.integers(-80, W, 16000)
-    by0 = rng.integers(-80, H, 16000)
-    many = torch.from_numpy(np.stack([bx0, by0, bx0 + rng.integers(1, 400, 16000),
-                                      by0 + rng.integers(1, 300, 16000), np.ones(16000, int)],
-                                     1).astype(np.int32)).to(dev)
-    many_out, many_rank = ocsr.select_boxes([(W, H, 1000)] * 16, many, 20)
-    select = {"budget": 20}
-    for key, frames_, bx, o, r in (("frame_64_boxes", [(W, H, n)], boxes, sel_out, sel_rank),
-                                   ("16_frames_1000_boxes", [(W, H, 1000)] * 16, many, many_out,
-                                    many_rank)):
-        ocsr.reset_timing()
-        ocsr.set_timing(True)
-        for _ in range(args.steps):
-            ocsr.select_boxes(frames_, bx, 20, out=o, rank=r)
-        torch.cuda.synchronize()
-        ocsr.set_timing(False)
-        scnt, stot = ocsr.kernel_time("select")
-        select[key] = {"us_per_call": round(1e3 * stot / max(scnt, 1), 3)}
-    select["frame_64_boxes"]["kept"] = int(((sel_out[:, 4] & 1) == 1).sum().item())
-
-    # algorithmic work per launch: census = informative comparisons (the centre term
-    # is constant); match = 4 int32 ops per 64-bit Hamming cost
-    census_ops = census_px * (census_bits - 1) * CENSUS_OPS_PER_CMP
-    far_ops = costs_far * MATCH_OPS_PER_COST
-    close_ops = (costs - costs_far) * MATCH_OPS_PER_COST
-    work = {"census": census_ops, "match": far_ops + close_ops, "match_far": far_ops,
-            "match_close": close_ops, "fused": census_ops + far_ops + close_ops}
-    for k, ops in work.items():
-        if k in kern:
-            kern[k]["tops"] = ops / (kern[k]["avg_us"] * 1e-6) / 1e12
-            kern[k]["frac"] = kern[k]["tops"] / INT_PEAK_TOPS
-    dom = max((k for k in work if k in kern), key=lambda k: kern[k]["avg_us"])
+    # headline: the 16-frame batch
+    p3, bres, bdetails, ms, kern = batch_workload(ocsr, scenes, args)
+    log(f"batch: {ms:.4f} ms per batch")
+    costs = bres["costs_per_batch"]
+    work = {k: v["ops_per_launch"] for k, v in kern.items() if "ops_per_launch" in v}
+    dom = max(work, key=lambda k: kern[k]["avg_us"])
     ach = kern[dom]["tops"]
-    roofline = {"kernel": dom, "bound": "alu", "achieved": round(ach, 3), "peak": round(INT_PEAK_TOPS, 2),
+    roofline = {"kernel": dom, "bound": "alu", "achieved": ach, "peak": round(INT_PEAK_TOPS, 2),
                 "unit": "TOP/s", "frac": round(ach / INT_PEAK_TOPS, 4),
-                "traffic": measured_traffic(dom), "ops_per_launch": work[dom]}
-
+                "traffic": measured_traffic(dom, "batch_16x1920x1200"),
+                "ops_per_launch": work[dom], "avg_us": kern[dom]["avg_us"],
+                "peak_measured": round(int_rate / 1e12, 3)}
     res = {
         "metric": METRIC,
-        "value": round(costs / (ms_per_step * 1e-3) / 1e9, 3),
+        "value": round(costs / (ms * 1e-3) / 1e9, 3),
         "unit": "Gcost/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 4),
+        "ms_per_step": round(ms, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "u64",
         "data": "synthetic",
-        "config": {"workload": "realistic_1080p: one 1920x1080 uint8 stereo pair, 32 ranged boxes "
-                               "(19 far 4x4 blocks d 0..31 at s=1, 13 close 8x8 blocks d 0..191 at "
-                               "s=2) + 32 occluder boxes, census 7x9 on the tiles the searches read, "
-                               "trimmed median",
-                   "costs_per_frame": costs, "costs_far": costs_far,
-                   "block_evals_per_frame": evals,
-                   "blocks": int(nb), "census_level_px": census_px,
-                   "census_tiles": len(tiles), "census_tiles_all": len(tiles_all),
-                   "census_level_px_all_tiles": census_px_full},
-        "block_evals_per_s": round(evals / (ms_per_step * 1e-3), 1),
-        "ms_per_step_with_kernel_events": round(ms_per_step_events, 4),
-        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
-                       "p99": round(float(np.percentile(lat, 99)), 4),
-                       "frames": int(len(lat))},
-        "graph": {"ms_per_step": round(ms_graph, 4),
-                  "latency_ms": {"p50": round(float(np.percentile(glat, 50)), 4),
-                                 "p99": round(float(np.percentile(glat, 99)), 4)}},
-        "kernels": {k: {kk: (round(vv, 3) if isinstance(vv, float) else vv) for kk, vv in v.items()}
-                    for k, v in kern.items()},
+        "config": bres,
+        "block_evals_per_s": round(bres["block_evals_per_batch"] / (ms * 1e-3), 1),
+        "latency_ms": {"per_batch": bdetails["latency_ms_per_batch"],
+                       "per_frame_call": bdetails["per_frame_call_latency_ms"]},
+        "kernels": kern,
         "roofline": roofline,
-        "points": points,
-        "select": select,
+        "batch": bdetails,
     }
+    if args.frame_steps > 0:
+        tiny, _ = frame_section(ocsr, synth.scene_tiny(), synth.params_for(1),
+                                "tiny_640x480: 4 boxes, 8x8 blocks d 0..63 at s=1, segment median",
+                                args)
+        res["tiny_640x480"] = tiny
+        log("tiny frame done")
+        sc2 = synth.scene_realistic()
+        p2 = synth.params_for(2)
+        real, (L, R, boxes, out, ms2) = frame_section(
+            ocsr, sc2, p2, "realistic_1080p: one 1920x1080 uint8 pair, 32 ranged boxes (19 far "
+            "4x4 blocks d 0..31 at s=1, 13 close 8x8 blocks d 0..191 at s=2) + 32 occluder boxes, "
+            "census 7x9 on the tiles the searches read, trimmed median", args, graph=True)
+        res["realistic_1080p"] = real
+        H, W = sc2.left.shape
+        res["points"], res["select"] = points_and_select(ocsr, synth, boxes, out, W, H, p2,
+                                                         args.frame_steps)
+        log("realistic frame, points, select done")
+        if args.dense_steps > 0:
+            res["dense"] = dense_section(ocsr, L, R, args.dense_steps, ms2,
+                                         max(20, args.latency_steps // 20))
+            log("dense done")
     if args.vertical_steps > 0:
-        res["vertical"] = vertical_section(ocsr, synth, args.vertical_steps, max(3, args.warmup // 10))
-    if args.batch_steps > 0:
-        res["batch"] = batch_section(ocsr, synth, args.batch_steps, max(3, args.warmup // 10))
+        res["vertical"] = vertical_section(ocsr, synth, args.vertical_steps, 3)
+        log("vertical done")
     if args.rect_steps > 0:
         res["rect"] = rect_section(ocsr, synth, args.rect_steps)
-    if args.dense_steps > 0:
-        res["dense"] = dense_section(ocsr, L, R, args.dense_steps, ms_per_step)
+        log("rect done")
     if args.serve_requests > 0:
-        res["serving"] = serving_section(ocsr, synth, args.serve_requests, args.serve_pool)
+        res["serving"] = serving_section(ocsr, synth, pools, args.serve_requests)
+        log("serving done")
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(sc, p, costs, args.cpu_seconds)
+        res["cpu_baseline"] = cpu_baseline(scenes, p3, args.cpu_seconds)
     print(json.dumps(res), flush=True)
 
 

@@ -487,7 +487,7 @@ int32_t ocsr_rect_filter_update(ocsr_rect_filter* f, const int32_t* counts, int3
  * ocsr_range_batch) as HIP graphs: the first call with a given set of arguments
  * (every frame description, device pointer, size, parameter and option) captures its
  * launches and instantiates them, and later calls with the same arguments replay the
- * instantiated graph with a single submission. Up to 32 graphs are kept per context,
+ * instantiated graph with a single submission. Up to 128 graphs are kept per context,
  * least recently used dropped first. The kernels read their inputs at replay time,
  * so new image or box contents at the same addresses are picked up; a change of any
  * address or size captures a new graph. Results are identical to 0 (default). */
@@ -510,13 +510,21 @@ int32_t ocsr_ctx_set_option(ocsr_ctx* ctx, int32_t option, int32_t value);
 /* ------------------------------------------------------------------------------ */
 /* Matching kernel variants (for tuners)                                            */
 /* ------------------------------------------------------------------------------ */
-/* A TILED path's blocks run in a register-blocked kernel: `rows` block rows per wave
- * (4 for blocks up to 4x4, 8 for blocks up to 8x8), `cpl` consecutive candidates per
- * lane and `passes` passes over the candidates, covering (64 / rows) * cpl * passes
- * level candidates. Fewer candidates per lane need fewer registers, so more waves fit
- * on a compute unit, at the price of more passes. Any variant that covers a path gives
- * identical results; they differ in speed only. By default the first covering variant
- * in the library's order of preference is used.
+/* A TILED path's blocks run in one of three kernel families, named by (rows, cpl,
+ * passes):
+ *   rows = 1: four blocks of up to 4 x 4 points per wave, 16 lanes per block, each lane
+ *             `cpl` consecutive candidates over all of its block's points (16 * cpl
+ *             candidates, passes = 1);
+ *   rows = 2: one block of up to 8 x 8 points per wave, lanes over 32 candidate groups
+ *             of `cpl` consecutive candidates and the block's two halves of 4 rows
+ *             (32 * cpl candidates, passes = 1);
+ *   rows = 4 or 8: a register-blocked kernel with `rows` block rows per wave (blocks up
+ *             to 4 x 4 or 8 x 8), `cpl` consecutive candidates per lane and `passes`
+ *             passes over the candidates, covering (64 / rows) * cpl * passes candidates.
+ * Any variant that covers a path gives identical results; they differ in speed only. By
+ * default the first covering variant in the library's order of preference is used:
+ * rows = 1 for blocks up to 4 x 4 and 32 or 64 candidates, rows = 2 for blocks up to
+ * 8 x 8 and up to 128 candidates, else the register-blocked kernels.
  *
  * ocsr_variant_candidates: writes up to `cap` (rows, cpl, passes) triples (host arrays)
  * that cover bw x bh blocks and n_candidates level candidates; returns how many exist
@@ -554,7 +562,7 @@ int32_t ocsr_ctx_reset_timing(ocsr_ctx* ctx);
 /* Measures the int32 vector-ALU rate of the context's device, the peak the census and
  * matching kernels are priced against: every lane of 16 workgroups of 256 threads per
  * compute unit runs 8 independent chains of the matching cost arithmetic
- * (b = a ^ b, acc = popcount(b) + acc: one v_xor_b32 and one v_bcnt_u32_b32 per step)
+ * (b = acc ^ b, acc = popcount(b) + acc: one v_xor_b32 and one v_bcnt_u32_b32 per step)
  * for `iters` steps, on the null stream, after three untimed launches. Synchronizes.
  * *ops_per_s: lane operations per second of the timed launch; *ms (nullable): its
  * duration. OCSR_E_INVALID for a null ctx or ops_per_s or iters outside 1..2^20. */

@@ -57,7 +57,7 @@ struct ocsr_ctx {
   int64_t graph_hits = 0, graph_builds = 0;
 };
 
-constexpr size_t kMaxGraphs = 32;
+constexpr size_t kMaxGraphs = 128;
 
 namespace {
 
@@ -329,7 +329,9 @@ int32_t build_params(const ocsr_ctx* ctx, const ocsr_match_params* p, int close_
   d->fb = f * b;
   d->d_eps = p->d_eps;
   d->cap_blocks = cap_blocks;
-  d->item_blocks = kItemWaves * ctx->blocks_per_wave;
+  // work items: four blocks per wave for the four-block kernel, else blocks per wave
+  for (int l = 0; l < 2; ++l)
+    d->item_blocks[l] = kItemWaves * (d->path[l].rows == 1 ? 4 : ctx->blocks_per_wave);
   d->full_census = ctx->full_census;
   return OCSR_OK;
 }

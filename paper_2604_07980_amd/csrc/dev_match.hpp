@@ -90,8 +90,9 @@ __device__ __forceinline__ void plan_frame(const MatchParamsDev& P, const FrameD
       if ((long long)off + count > (long long)P.cap_blocks) pl.status = OCSR_REASON_CAPACITY_OVERFLOW;
       else nblk = count;
     }
-    // work items of item_blocks blocks, per level
-    const int nitem = (nblk + P.item_blocks - 1) / P.item_blocks;
+    // work items of item_blocks blocks of the box's level
+    const int ib = P.item_blocks[pl.level];
+    const int nitem = (nblk + ib - 1) / ib;
     const int c0 = (pl.status == -1 && pl.level == 0) ? nitem : 0;
     const int c1 = (pl.status == -1 && pl.level == 1) ? nitem : 0;
     const int incl0 = wave_incl_scan(c0, lane);
@@ -127,12 +128,13 @@ __device__ __forceinline__ void plan_frame(const MatchParamsDev& P, const FrameD
     if (i >= n) continue;
     const BoxPlan pl = ws.plan[fr.box_off + i];
     if (pl.status != -1 || pl.nblk <= 0) continue;
-    const int nitem = (pl.nblk + P.item_blocks - 1) / P.item_blocks;
+    const int ib = P.item_blocks[pl.level];
+    const int nitem = (pl.nblk + ib - 1) / ib;
     const int at = (pl.level == 1 ? 0 : carry1) + pl.ioff;
     for (int t = 0; t < nitem; ++t) {
       ItemRec r;
       r.k = i;
-      r.first = t * P.item_blocks;
+      r.first = t * ib;
       r.nblk = pl.nblk;
       r.off = pl.off;
       r.nbx = pl.nbx; r.bw = pl.bw; r.bh = pl.bh; r.ox = pl.ox; r.oy = pl.oy;
@@ -284,12 +286,13 @@ __device__ __forceinline__ void write_block(const MatchWs& ws, const DebugDev& d
 // (2 x v_xor_b32 + 2 x v_bcnt_u32_b32 each). Row sums are combined with DPP.
 // ---------------------------------------------------------------------------------
 // popcount of a 64-bit word added to acc as two v_bcnt_u32_b32 (each adds its popcount
-// to its second operand). The empty asm keeps the compiler from regrouping the three
-// terms into a v_add3_u32, which would cost a fifth instruction per term.
+// to its second operand). Written as instructions so that the compiler cannot regroup a
+// chain of these sums into popcounts of zero plus v_add3_u32 adds, which costs a fifth
+// instruction per term.
 __device__ __forceinline__ uint32_t popc64_acc(uint64_t x, uint32_t acc) {
-  uint32_t t = __popc((uint32_t)x) + acc;
-  asm volatile("" : "+v"(t));
-  return __popc((uint32_t)(x >> 32)) + t;
+  asm("v_bcnt_u32_b32 %0, %1, %0" : "+v"(acc) : "v"((uint32_t)x));
+  asm("v_bcnt_u32_b32 %0, %1, %0" : "+v"(acc) : "v"((uint32_t)(x >> 32)));
+  return acc;
 }
 
 // acc[c] = sum over the row's unmasked points i of popcount(t[i] ^ srow[i + c]).
@@ -499,6 +502,474 @@ __device__ __forceinline__ void match_block_tiled(const MatchParamsDev& P, const
     }
   }
   write_block(ws, dbg, c, ph, mask, true, d_f, d_b, lr_ok, d_sub, lr_ok, lane);
+  wave_sync();
+}
+
+// ---------------------------------------------------------------------------------
+// TILED block of up to 8 x 8 points, lanes over (candidate group, row half): lane
+// l = 2 g + h takes block rows 4h .. 4h + 3 and the CPL consecutive strip positions
+// g CPL + c (c < CPL), so one wave covers 32 CPL candidates in one pass. For each of its
+// rows a lane reads the 8 template words and CPL + 7 strip words from LDS and forms
+// 8 CPL costs at 4 operations each; the two row halves of a candidate meet in one DPP
+// add, and the winner is a DPP wave minimum of packed (cost << 16 | index) keys. A strip
+// row is staged in 64-word chunks, lane l loading word l of each chunk: inside the
+// image this needs no per-lane address arithmetic (a uniform row address plus the lane's
+// fixed offset); blocks whose strip leaves the image take a checked copy.
+// ---------------------------------------------------------------------------------
+template <int CPL>
+struct Half {
+  static constexpr int NC = 32 * CPL;               // candidates one wave covers
+  static constexpr int SWP = NC + 8;                // LDS words per strip row (>= NC + 7)
+  static constexpr int CH = (NC + 7 + 63) / 64;     // 64-word chunks of a strip row
+  static constexpr size_t kLdsBytes =
+      sizeof(uint64_t) * (8 * SWP + 64) + sizeof(uint32_t) * 2 * NC;
+};
+
+// Whole-wave minimum of v (every lane gets it): DPP within rows of 16, then row
+// broadcasts (lane 15 into the next row, lane 31 into rows 2 and 3), then lane 63.
+__device__ __forceinline__ uint32_t wave_min_dpp(uint32_t v) {
+  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0xB1, 0xF, 0xF, false));
+  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x4E, 0xF, 0xF, false));
+  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x141, 0xF, 0xF, false));
+  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x140, 0xF, 0xF, false));
+  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x142, 0xA, 0xF, false));
+  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x143, 0xC, 0xF, false));
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+// Strip rows 0 .. ny - 1 of a level image from `rows` (the block's first row), words
+// [x_first, x_first + sw), into S[jj * SWP + m]. `inside`: every word lies in the image
+// (wave-uniform); otherwise words outside it are stored as 0. All loads of a lane are
+// issued before the first store.
+template <int SWP, int CH>
+__device__ __forceinline__ void stage_half_strip(uint64_t* __restrict__ S, const uint64_t* __restrict__ rows,
+                                                 int pitch, int x_first, int ny, int sw, int W,
+                                                 bool inside, int lane) {
+  uint64_t w[8][CH];
+  if (inside) {
+    const uint64_t* __restrict__ p = rows + x_first;
+#pragma unroll
+    for (int jj = 0; jj < 8; ++jj)
+#pragma unroll
+      for (int c = 0; c < CH; ++c)
+        if (jj < ny && 64 * c + lane < sw) w[jj][c] = p[(size_t)jj * pitch + 64 * c + lane];
+  } else {
+#pragma unroll
+    for (int jj = 0; jj < 8; ++jj)
+#pragma unroll
+      for (int c = 0; c < CH; ++c) {
+        const int m = 64 * c + lane, x = x_first + m;
+        const bool ok = jj < ny && m < sw && x >= 0 && x < W;
+        w[jj][c] = rows[ok ? (size_t)jj * pitch + x : 0];
+        w[jj][c] = ok ? w[jj][c] : 0ull;
+      }
+  }
+#pragma unroll
+  for (int jj = 0; jj < 8; ++jj)
+#pragma unroll
+    for (int c = 0; c < CH; ++c)
+      if (jj < ny && 64 * c + lane < sw) S[jj * SWP + 64 * c + lane] = w[jj][c];
+}
+
+// One direction of the search: acc[c] = cost of strip position g CPL + c over the lane's
+// rows, summed with the other row half. keep: the lane's point mask (bit r 8 + i for
+// row 4h + r, column i; 0 for points that do not exist). `full` (wave-uniform): every
+// point of an 8 x 8 block is kept, and a cost is 4 operations; otherwise each
+// difference is ANDed with its point's mask bit (6 operations), with no branch per row
+// or column.
+template <int CPL>
+__device__ __forceinline__ void half_costs(const uint64_t* __restrict__ T, const uint64_t* __restrict__ S,
+                                           int g, int h, bool full, uint32_t keep,
+                                           uint32_t (&acc)[CPL]) {
+  constexpr int SWP = Half<CPL>::SWP;
+#pragma unroll
+  for (int c = 0; c < CPL; ++c) acc[c] = 0;
+  const uint64_t* __restrict__ trow = T + 32 * h;
+  const uint64_t* __restrict__ srow = S + 4 * h * SWP + g * CPL;
+  if (full) {
+#pragma unroll 1
+    for (int r = 0; r < 4; ++r) {
+      uint64_t t[8], w[CPL + 7];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) t[i] = trow[8 * r + i];
+#pragma unroll
+      for (int m = 0; m < CPL + 7; ++m) w[m] = srow[r * SWP + m];
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) acc[c] = popc64_acc(t[i] ^ w[i + c], acc[c]);
+    }
+  } else {
+#pragma unroll 1
+    for (int r = 0; r < 4; ++r) {
+      uint64_t t[8], w[CPL + 7];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) t[i] = trow[8 * r + i];
+#pragma unroll
+      for (int m = 0; m < CPL + 7; ++m) w[m] = srow[r * SWP + m];
+      const uint32_t kr = keep >> (8 * r);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const uint64_t k = ((kr >> i) & 1u) ? ~0ull : 0ull;
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) acc[c] = popc64_acc((t[i] ^ w[i + c]) & k, acc[c]);
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < CPL; ++c)
+    acc[c] += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)acc[c], 0xB1, 0xF, 0xF, false);
+}
+
+// Occlusion mask of a TILED block (Sec. 4.3.5) in the 8-column layout: bit j*8 + i is
+// set iff point (i, j) exists (i < nx, j < ny) and lies in no box of the frame that
+// overlaps box k and has a larger bottom y. Lane l tests point (l & 7, l >> 3).
+__device__ __forceinline__ uint64_t tiled_mask8(const MatchWs& ws, int box_off, int n, int k,
+                                                int s, int cx, int cy, int nx, int ny, int lane) {
+  const BoxClip ck = ws.clip[box_off + k];
+  const int pi = lane & 7, pj = lane >> 3;
+  const bool exists = pi < nx && pj < ny;
+  const int fx = s * (cx + pi), fy = s * (cy + pj);
+  const int bx0 = s * cx, bx1 = s * (cx + nx - 1);
+  const int by0 = s * cy, by1 = s * (cy + ny - 1);
+  bool hidden = false;
+  for (int jb = 0; jb < n; jb += 64) {
+    const int o = jb + lane;
+    const BoxClip co = o < n ? ws.clip[box_off + o] : BoxClip{0, 0, 0, 0};
+    const bool occ = o < n && o != k && ck.cx0 < co.cx1 && co.cx0 < ck.cx1 && ck.cy0 < co.cy1 &&
+                     co.cy0 < ck.cy1 && co.cy1 > ck.cy1 && co.cx0 <= bx1 && co.cx1 > bx0 &&
+                     co.cy0 <= by1 && co.cy1 > by0;
+    uint64_t m = __ballot(occ);
+    while (m) {
+      const int src = __ffsll((unsigned long long)m) - 1;
+      m &= m - 1;
+      const int x0 = __builtin_amdgcn_readlane(co.cx0, src), x1 = __builtin_amdgcn_readlane(co.cx1, src);
+      const int y0 = __builtin_amdgcn_readlane(co.cy0, src), y1 = __builtin_amdgcn_readlane(co.cy1, src);
+      hidden |= fx >= x0 && fx < x1 && fy >= y0 && fy < y1;
+    }
+  }
+  return __ballot(exists && !hidden);
+}
+
+// The 8-column mask in the record's layout (bit j * nx + i).
+__device__ __forceinline__ uint64_t pack_mask8(uint64_t m8, int nx, int ny, int lane) {
+  const int j = lane / nx, i = lane - j * nx;
+  return __ballot(lane < nx * ny && ((m8 >> (8 * j + i)) & 1ull));
+}
+
+template <int CPL>
+__device__ __forceinline__ void match_block_half(const MatchParamsDev& P, const FrameDev& fr,
+                                                 const MatchWs& ws, const DebugDev& dbg,
+                                                 const BlockCtx& c, int lane, void* lds) {
+  using HH = Half<CPL>;
+  constexpr int SWP = HH::SWP, CH = HH::CH, NC = HH::NC;
+  uint64_t* S = (uint64_t*)lds;
+  uint64_t* T = S + 8 * SWP;
+  uint32_t* costf = (uint32_t*)(T + 64);
+  uint32_t* costb = costf + NC;
+  const int g = lane >> 1, h = lane & 1;
+  const LevelDev& lv = fr.lv[c.level];
+  const PathDev& ph = P.path[c.level];
+  const int nd = ph.nd, dlo = ph.dlo, dhi = dlo + nd - 1;
+  const int nx = c.g.nx, ny = c.g.ny;
+  const int X0 = c.g.cx, Y0 = c.g.cy;
+  const int W = lv.W;
+  const uint64_t* __restrict__ Lb = uniform(lv.L + (size_t)Y0 * lv.pitch);
+  const uint64_t* __restrict__ Rb = uniform(lv.R + (size_t)Y0 * lv.pitch);
+  const int sw = nd + nx - 1;
+  // forward strip CR(X0 - dhi + m, Y0 + j) and template CL(X0 + i, Y0 + j), loads issued
+  // before the occluder scan so both are in flight together
+  const int xf = X0 - dhi;
+  stage_half_strip<SWP, CH>(S, Rb, lv.pitch, xf, ny, sw, W, xf >= 0 && xf + sw <= W, lane);
+  {
+    const int i = lane & 7, jj = lane >> 3;
+    const bool ok = i < nx && jj < ny;
+    uint64_t t = Lb[ok ? (size_t)jj * lv.pitch + X0 + i : 0];
+    T[lane] = ok ? t : 0ull;
+  }
+  const uint64_t m8 = tiled_mask8(ws, fr.box_off, fr.n_boxes, c.k, c.g.s, X0, Y0, nx, ny, lane);
+  const int npts = __popcll(m8);
+  const bool eligible = npts > 0 && 100 * npts >= P.min_point_pct * nx * ny;
+  wave_sync();
+  if (!eligible) {
+    const uint64_t mask = dbg.blocks ? pack_mask8(m8, nx, ny, lane) : 0ull;
+    write_block(ws, dbg, c, ph, mask, false, dlo, dlo, 0, (float)dlo, 0, lane);
+    wave_sync();
+    return;
+  }
+  const bool full = m8 == ~0ull;   // an 8 x 8 block with every point kept
+  const uint32_t keep = (uint32_t)(m8 >> (32 * h));
+  uint32_t acc[CPL];
+  half_costs<CPL>(T, S, g, h, full, keep, acc);
+  uint32_t key = 0xFFFFFFFFu;
+#pragma unroll
+  for (int cc = 0; cc < CPL; ++cc) {
+    const int e = g * CPL + cc;            // strip position: candidate d = dhi - e
+    if (e < nd) {
+      const int kc = nd - 1 - e;
+      key = min(key, (acc[cc] << 16) | (uint32_t)kc);
+      if (h == 0) costf[kc] = acc[cc];
+    }
+  }
+  key = wave_min_dpp(key);
+  const int best = (int)(key & 0xFFFFu);
+  const int d_f = dlo + best;
+  // backward template CR(X0 - d_f + i, Y0 + j): strip position dhi - d_f + i
+  {
+    const int i = lane & 7, jj = lane >> 3;
+    const uint64_t t = S[jj * SWP + (dhi - d_f) + i];
+    wave_sync();
+    T[lane] = t;
+  }
+  const int ca = (int)costf[max(best - 1, 0)];
+  const int cb = (int)costf[min(best + 1, nd - 1)];
+  const float d_sub = subpixel(d_f, best, nd, ca, (int)(key >> 16), cb);
+  // backward strip CL(X0 - d_f + dlo + m, Y0 + j)
+  const int xb = X0 - d_f + dlo;
+  wave_sync();
+  stage_half_strip<SWP, CH>(S, Lb, lv.pitch, xb, ny, sw, W, xb >= 0 && xb + sw <= W, lane);
+  wave_sync();
+  half_costs<CPL>(T, S, g, h, full, keep, acc);
+  uint32_t bkey = 0xFFFFFFFFu;
+#pragma unroll
+  for (int cc = 0; cc < CPL; ++cc) {
+    const int kc = g * CPL + cc;           // candidate d' = dlo + kc
+    if (kc < nd) {
+      bkey = min(bkey, (acc[cc] << 16) | (uint32_t)kc);
+      if (h == 0) costb[kc] = acc[cc];
+    }
+  }
+  bkey = wave_min_dpp(bkey);
+  const int d_b = dlo + (int)(bkey & 0xFFFFu);
+  const int lr_ok = abs(d_b - d_f) <= P.lr_tol;
+  uint64_t mask = 0;
+  if (dbg.blocks || dbg.cost_fwd || dbg.cost_bwd) {
+    mask = pack_mask8(m8, nx, ny, lane);
+    if (c.b < dbg.cap_blocks && (dbg.cost_fwd || dbg.cost_bwd)) {
+      wave_sync();
+      for (int kc = lane; kc < nd && kc < dbg.cap_nd; kc += 64) {
+        if (dbg.cost_fwd) dbg.cost_fwd[(size_t)c.b * dbg.cap_nd + kc] = (uint16_t)costf[kc];
+        if (dbg.cost_bwd) dbg.cost_bwd[(size_t)c.b * dbg.cap_nd + kc] = (uint16_t)costb[kc];
+      }
+    }
+  }
+  write_block(ws, dbg, c, ph, mask, true, d_f, d_b, lr_ok, d_sub, lr_ok, lane);
+  wave_sync();
+}
+
+// ---------------------------------------------------------------------------------
+// TILED blocks of up to 4 x 4 points, four blocks per wave: lane l = 16 q + g takes
+// block q of the four (its 16 lanes a DPP row) and the CPL consecutive strip positions
+// g CPL + c, so a row of lanes covers 16 CPL candidates and each lane forms the whole
+// cost of its candidates over the block's points (no reduction across lanes). The
+// winner of a block is a DPP minimum within its row of lanes. Each block has its own
+// strip and template in LDS, staged by its 16 lanes.
+// ---------------------------------------------------------------------------------
+template <int CPL>
+struct Quad {
+  static constexpr int NC = 16 * CPL;               // candidates per block
+  static constexpr int SWP = NC + 4;                // LDS words per strip row (>= NC + 3)
+  static constexpr int BLK = 4 * SWP + 16;          // LDS words per block: strip, template
+  static constexpr int CH = (NC + 3 + 15) / 16;     // 16-word chunks of a strip row
+  static constexpr size_t kLdsBytes = sizeof(uint64_t) * 4 * BLK + sizeof(uint32_t) * 2 * 4 * NC;
+};
+
+// Minimum over each row of 16 lanes (every lane of the row gets it).
+__device__ __forceinline__ uint32_t row16_min_dpp(uint32_t v) {
+  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0xB1, 0xF, 0xF, false));
+  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x4E, 0xF, 0xF, false));
+  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x141, 0xF, 0xF, false));
+  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x140, 0xF, 0xF, false));
+  return v;
+}
+
+// One quarter's strip: rows 0 .. ny - 1 from `rows` (its block's first row), words
+// [x_first, x_first + sw) into S[jj * SWP + m], 0 outside the image; g: the lane's
+// index in its quarter. All loads are issued before the first store.
+template <int CPL>
+__device__ __forceinline__ void stage_quad_strip(uint64_t* __restrict__ S, const uint64_t* __restrict__ rows,
+                                                 int pitch, int x_first, int ny, int sw, int W,
+                                                 bool live, int g) {
+  constexpr int SWP = Quad<CPL>::SWP, CH = Quad<CPL>::CH;
+  uint64_t w[4][CH];
+#pragma unroll
+  for (int jj = 0; jj < 4; ++jj)
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      const int m = 16 * c + g, x = x_first + m;
+      const bool ok = live && jj < ny && m < sw && x >= 0 && x < W;
+      w[jj][c] = rows[ok ? (size_t)jj * pitch + x : 0];
+      w[jj][c] = ok ? w[jj][c] : 0ull;
+    }
+#pragma unroll
+  for (int jj = 0; jj < 4; ++jj)
+#pragma unroll
+    for (int c = 0; c < CH; ++c)
+      if (16 * c + g < SWP) S[jj * SWP + 16 * c + g] = w[jj][c];
+}
+
+// acc[c] = cost of strip position g CPL + c over the block's points; keep: the block's
+// point mask in the 4-column layout (bit j * 4 + i); `full`: every point of four 4 x 4
+// blocks is kept (wave-uniform).
+template <int CPL>
+__device__ __forceinline__ void quad_costs(const uint64_t* __restrict__ T, const uint64_t* __restrict__ S,
+                                           int g, bool full, uint32_t keep, uint32_t (&acc)[CPL]) {
+  constexpr int SWP = Quad<CPL>::SWP;
+#pragma unroll
+  for (int c = 0; c < CPL; ++c) acc[c] = 0;
+  const uint64_t* __restrict__ srow = S + g * CPL;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    uint64_t t[4], w[CPL + 3];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) t[i] = T[4 * r + i];
+#pragma unroll
+    for (int m = 0; m < CPL + 3; ++m) w[m] = srow[r * SWP + m];
+    if (full) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) acc[c] = popc64_acc(t[i] ^ w[i + c], acc[c]);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const uint64_t k = ((keep >> (4 * r + i)) & 1u) ? ~0ull : 0ull;
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) acc[c] = popc64_acc((t[i] ^ w[i + c]) & k, acc[c]);
+      }
+    }
+  }
+}
+
+// Blocks first .. first + 3 (those below nblk) of one box, one per row of 16 lanes.
+template <int CPL>
+__device__ __forceinline__ void match_blocks_quad(const MatchParamsDev& P, const FrameDev& fr,
+                                                  const MatchWs& ws, const DebugDev& dbg, int f,
+                                                  int level, const ItemRec& r, int first, int lane,
+                                                  void* lds) {
+  using QQ = Quad<CPL>;
+  constexpr int SWP = QQ::SWP, NC = QQ::NC;
+  const int q = lane >> 4, g = lane & 15;
+  const int local = first + q;
+  const bool live = local < r.nblk;
+  uint64_t* S = (uint64_t*)lds + q * QQ::BLK;
+  uint64_t* T = S + 4 * SWP;
+  uint32_t* costf = (uint32_t*)((uint64_t*)lds + 4 * QQ::BLK) + q * NC;
+  uint32_t* costb = costf + 4 * NC;
+  const LevelDev& lv = fr.lv[level];
+  const PathDev& ph = P.path[level];
+  const int nd = ph.nd, dlo = ph.dlo, dhi = dlo + nd - 1;
+  const int nx = r.bw, ny = r.bh, W = lv.W, s = lv.scale;
+  const int vv = live ? local / r.nbx : 0;
+  const int uu = live ? local - vv * r.nbx : 0;
+  const int X0 = r.ox + uu * nx, Y0 = r.oy + vv * ny;
+  const uint64_t* __restrict__ Lb = lv.L + (size_t)Y0 * lv.pitch;
+  const uint64_t* __restrict__ Rb = lv.R + (size_t)Y0 * lv.pitch;
+  const int sw = nd + nx - 1;
+  // forward strip CR(X0 - dhi + m, Y0 + j) and template CL(X0 + i, Y0 + j) of this
+  // lane's block, issued before the occluder scan
+  stage_quad_strip<CPL>(S, Rb, lv.pitch, X0 - dhi, ny, sw, W, live, g);
+  const int pi = g & 3, pj = g >> 2;
+  const bool exists = live && pi < nx && pj < ny;
+  {
+    uint64_t t = Lb[exists ? (size_t)pj * lv.pitch + X0 + pi : 0];
+    T[g] = exists ? t : 0ull;
+  }
+  // occlusion (Sec. 4.3.5): every block of the wave belongs to box k, so the boxes that
+  // occlude it are found once; each lane tests its own point against them
+  const BoxClip ck = ws.clip[fr.box_off + r.k];
+  const int fx = s * (X0 + pi), fy = s * (Y0 + pj);
+  bool hidden = false;
+  for (int jb = 0; jb < fr.n_boxes; jb += 64) {
+    const int o = jb + lane;
+    const BoxClip co = o < fr.n_boxes ? ws.clip[fr.box_off + o] : BoxClip{0, 0, 0, 0};
+    const bool occ = o < fr.n_boxes && o != r.k && ck.cx0 < co.cx1 && co.cx0 < ck.cx1 &&
+                     ck.cy0 < co.cy1 && co.cy0 < ck.cy1 && co.cy1 > ck.cy1;
+    uint64_t m = __ballot(occ);
+    while (m) {
+      const int src = __ffsll((unsigned long long)m) - 1;
+      m &= m - 1;
+      const int x0 = __builtin_amdgcn_readlane(co.cx0, src), x1 = __builtin_amdgcn_readlane(co.cx1, src);
+      const int y0 = __builtin_amdgcn_readlane(co.cy0, src), y1 = __builtin_amdgcn_readlane(co.cy1, src);
+      hidden |= fx >= x0 && fx < x1 && fy >= y0 && fy < y1;
+    }
+  }
+  const uint64_t m64 = __ballot(exists && !hidden);
+  const uint32_t keep = (uint32_t)(m64 >> (16 * q)) & 0xFFFFu;
+  const int npts = __popc(keep);
+  const bool eligible = live && npts > 0 && 100 * npts >= P.min_point_pct * nx * ny;
+  const bool full = m64 == ~0ull;
+  const bool writer = live && g == 0;
+  wave_sync();
+  uint32_t acc[CPL];
+  quad_costs<CPL>(T, S, g, full, keep, acc);
+  uint32_t key = 0xFFFFFFFFu;
+#pragma unroll
+  for (int cc = 0; cc < CPL; ++cc) {
+    const int e = g * CPL + cc;            // strip position: candidate d = dhi - e
+    if (e < nd) {
+      const int kc = nd - 1 - e;
+      key = min(key, (acc[cc] << 16) | (uint32_t)kc);
+      costf[kc] = acc[cc];
+    }
+  }
+  key = row16_min_dpp(key);
+  const int best = (int)(key & 0xFFFFu);
+  const int d_f = dlo + best;
+  // backward template CR(X0 - d_f + i, Y0 + j): strip position dhi - d_f + i
+  const uint64_t tb = S[pj * SWP + (dhi - d_f) + pi];
+  wave_sync();
+  T[g] = exists ? tb : 0ull;
+  const int ca = (int)costf[max(best - 1, 0)];
+  const int cb = (int)costf[min(best + 1, nd - 1)];
+  const float d_sub = subpixel(d_f, best, nd, ca, (int)(key >> 16), cb);
+  wave_sync();
+  stage_quad_strip<CPL>(S, Lb, lv.pitch, X0 - d_f + dlo, ny, sw, W, live, g);
+  wave_sync();
+  quad_costs<CPL>(T, S, g, full, keep, acc);
+  uint32_t bkey = 0xFFFFFFFFu;
+#pragma unroll
+  for (int cc = 0; cc < CPL; ++cc) {
+    const int kc = g * CPL + cc;           // candidate d' = dlo + kc
+    if (kc < nd) {
+      bkey = min(bkey, (acc[cc] << 16) | (uint32_t)kc);
+      costb[kc] = acc[cc];
+    }
+  }
+  bkey = row16_min_dpp(bkey);
+  const int d_b = dlo + (int)(bkey & 0xFFFFu);
+  const int lr_ok = abs(d_b - d_f) <= P.lr_tol;
+  const int slot = f * P.cap_blocks + r.off + local;
+  if (writer) {
+    ws.blk_val[slot] = (float)s * (eligible ? d_sub : (float)dlo);   // d_full = s * d (Sec. 4.1)
+    ws.blk_flag[slot] = (uint8_t)((eligible ? 1 : 0) | (eligible && lr_ok ? 2 : 0));
+  }
+  if (dbg.blocks || dbg.cost_fwd || dbg.cost_bwd) {
+    // record mask in the record's layout (bit j * nx + i) from the 4-column layout
+    const int jr = g / nx, ir = g - jr * nx;
+    const uint64_t pm = __ballot(live && g < nx * ny && ((keep >> (4 * jr + ir)) & 1u));
+    const uint64_t mask = (pm >> (16 * q)) & 0xFFFFull;
+    const int b = r.off + local;
+    if (writer && dbg.blocks && b < dbg.cap_blocks) {
+      ocsr_block_record rec;
+      rec.box = r.k; rec.level_scale = s; rec.u = uu; rec.v = vv;
+      rec.px0 = X0; rec.py0 = Y0; rec.nx = nx; rec.ny = ny;
+      rec.mask = mask; rec.eligible = eligible;
+      rec.d_f = eligible ? d_f : dlo; rec.d_b = eligible ? d_b : dlo;
+      rec.lr_ok = eligible ? lr_ok : 0; rec.d_sub = eligible ? d_sub : (float)dlo;
+      rec.valid = eligible && lr_ok;
+      rec.dlo = dlo; rec.nd = nd;
+      rec.dy_f = 0; rec.dy_b = 0;
+      dbg.blocks[b] = rec;
+    }
+    if (live && eligible && b < dbg.cap_blocks && (dbg.cost_fwd || dbg.cost_bwd)) {
+      wave_sync();
+      for (int kc = g; kc < nd && kc < dbg.cap_nd; kc += 16) {
+        if (dbg.cost_fwd) dbg.cost_fwd[(size_t)b * dbg.cap_nd + kc] = (uint16_t)costf[kc];
+        if (dbg.cost_bwd) dbg.cost_bwd[(size_t)b * dbg.cap_nd + kc] = (uint16_t)costb[kc];
+      }
+    }
+  }
   wave_sync();
 }
 
@@ -715,7 +1186,7 @@ __device__ __forceinline__ void run_item_rec(const MatchParamsDev& P, const Fram
   pl.lx0 = r.lx0; pl.ly0 = r.ly0; pl.lw = r.lw; pl.lh = r.lh;
   pl.nbx = r.nbx; pl.bw = r.bw; pl.bh = r.bh; pl.ox = r.ox; pl.oy = r.oy;
   pl.off = r.off; pl.nblk = r.nblk; pl.frame = f;
-  for (int j = wave; j < P.item_blocks; j += kItemWaves) {
+  for (int j = wave; j < P.item_blocks[level]; j += kItemWaves) {
     const int local = r.first + j;
     if (local < r.nblk) run(block_ctx(P, fr, f, r.k, pl, local, level));
   }
@@ -1133,8 +1604,8 @@ __device__ __forceinline__ void run_item(const MatchParamsDev& P, const FrameDev
                                          int wave, int lane, RunBlock run) {
   const int k = find_box(ws.litem_end + (size_t)level * n_total + fr.box_off, fr.n_boxes, q, lane);
   const BoxPlan pl = ws.plan[fr.box_off + k];
-  const int first = P.item_blocks * (q - pl.ioff);
-  for (int j = wave; j < P.item_blocks; j += kItemWaves) {
+  const int first = P.item_blocks[level] * (q - pl.ioff);
+  for (int j = wave; j < P.item_blocks[level]; j += kItemWaves) {
     const int local = first + j;
     if (local < pl.nblk) run(block_ctx(P, fr, f, k, pl, local, level));
   }

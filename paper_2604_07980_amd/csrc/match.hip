@@ -126,6 +126,100 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(pair_waves<
   }
 }
 
+// Matchers of one level's TILED blocks, for the generic pair kernel: the register-blocked
+// kernel (ROWS block rows per wave, CPL candidates per lane, PASSES passes) and the
+// row-half kernel (32 CPL candidates per wave).
+// run_item: wave `wave`'s share of work item r (frame f, level `level`).
+template <int ROWS, int NX, int CPL, int PASSES>
+struct TiledMatcher {
+  static constexpr size_t kLds = (dev::Tiled<ROWS, NX, CPL, PASSES>::kLdsBytes + 15) & ~(size_t)15;
+  static __device__ __forceinline__ void run_item(const MatchParamsDev& P, const FrameDev& fr,
+                                                  const MatchWs& ws, const DebugDev& dbg, int f,
+                                                  int level, const ItemRec& r, int wave, int lane,
+                                                  void* lds) {
+    dev::run_item_rec(P, fr, f, level, r, wave, [&](const dev::BlockCtx& c) {
+      dev::match_block_tiled<ROWS, NX, CPL, PASSES>(P, fr, ws, dbg, c, lane, lds);
+    });
+  }
+};
+template <int CPL>
+struct HalfMatcher {
+  static constexpr size_t kLds = (dev::Half<CPL>::kLdsBytes + 15) & ~(size_t)15;
+  static __device__ __forceinline__ void run_item(const MatchParamsDev& P, const FrameDev& fr,
+                                                  const MatchWs& ws, const DebugDev& dbg, int f,
+                                                  int level, const ItemRec& r, int wave, int lane,
+                                                  void* lds) {
+    dev::run_item_rec(P, fr, f, level, r, wave, [&](const dev::BlockCtx& c) {
+      dev::match_block_half<CPL>(P, fr, ws, dbg, c, lane, lds);
+    });
+  }
+};
+// four blocks per wave: wave w takes blocks r.first + 4 w .. + 3 of a 16-block item
+template <int CPL>
+struct QuadMatcher {
+  static constexpr size_t kLds = (dev::Quad<CPL>::kLdsBytes + 15) & ~(size_t)15;
+  static __device__ __forceinline__ void run_item(const MatchParamsDev& P, const FrameDev& fr,
+                                                  const MatchWs& ws, const DebugDev& dbg, int f,
+                                                  int level, const ItemRec& r, int wave, int lane,
+                                                  void* lds) {
+    const int first = r.first + 4 * wave;
+    if (first < r.nblk && first < r.first + P.item_blocks[level])
+      dev::match_blocks_quad<CPL>(P, fr, ws, dbg, f, level, r, first, lane, lds);
+  }
+};
+
+// Both levels in one launch with any pair of matchers (FM far, CM close): work items of
+// every frame's close level first, then of every far level. Compiled for WAVES waves per
+// SIMD.
+template <class FM, class CM, int WAVES>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES))) void match_pair2_kernel(
+    MatchParamsDev P, FramesDev FR, MatchWs ws, DebugDev dbg) {
+  constexpr size_t kWave = FM::kLds > CM::kLds ? FM::kLds : CM::kLds;
+  __shared__ uint64_t lds[(kItemWaves * kWave + 7) / 8];
+  __shared__ int prefix[2 * kMaxFrames + 1];
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int lane = threadIdx.x & 63;
+  const int F = FR.n;
+  if (threadIdx.x < 64) {
+    const int j = lane < F ? lane : lane - F;
+    const int cnt = lane < 2 * F ? ws.fcount[j * FC_N + (lane < F ? FC_CLOSE_ITEMS : FC_FAR_ITEMS)] : 0;
+    const int incl = dev::wave_incl_scan(cnt, lane);
+    if (lane < 2 * F) prefix[lane + 1] = incl;
+    if (lane == 0) prefix[0] = 0;
+  }
+  __syncthreads();
+  void* wl = (char*)lds + wave * kWave;
+  const int total = prefix[2 * F];
+  for (int m = blockIdx.x; m < total; m += gridDim.x) {
+    int slot = 0;
+    for (int k = 1; k < 2 * F; ++k)
+      if (m >= prefix[k]) slot = k;
+    const int f = slot < F ? slot : slot - F;
+    const FrameDev& fr = FR.f[f];
+    const int q = m - prefix[slot];
+    const int at = q + (slot < F ? 0 : prefix[f + 1] - prefix[f]);
+    const ItemRec r = ws.items[(size_t)f * ws.items_cap + at];
+    if (slot < F) CM::run_item(P, fr, ws, dbg, f, 1, r, wave, lane, wl);
+    else FM::run_item(P, fr, ws, dbg, f, 0, r, wave, lane, wl);
+  }
+}
+
+// One level with any matcher.
+template <class M, int WAVES>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES))) void match_level_kernel(
+    MatchParamsDev P, FramesDev FR, MatchWs ws, DebugDev dbg, int level) {
+  __shared__ uint64_t lds[(kItemWaves * M::kLds + 7) / 8];
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int lane = threadIdx.x & 63;
+  void* wl = (char*)lds + wave * M::kLds;
+  dev::level_items(FR, ws, level, [&](int f, int q) {
+    const FrameDev& fr = FR.f[f];
+    const int at = q + (level ? 0 : ws.fcount[f * FC_N + FC_CLOSE_ITEMS]);
+    const ItemRec r = ws.items[(size_t)f * ws.items_cap + at];
+    M::run_item(P, fr, ws, dbg, f, level, r, wave, lane, wl);
+  });
+}
+
 // Both levels with a vertical range in one launch: work items of every frame's close
 // level first, then of every far level (as match_pair_kernel), each wave with an LDS
 // share of wave_bytes (the larger of the two levels' needs). The two levels' blocks
@@ -220,8 +314,14 @@ MatchWs match_ws_carve(void* base, int n_frames, int n_boxes_total, int cap_bloc
 namespace {
 // the built kernels, as in launch_level, in order of preference for the default
 struct BuiltVariant { int rows, nx, cpl, passes; };
+// rows = 2: the row-half kernel (lanes over 32 candidate groups x 2 row halves of an
+// up to 8 x 8 block, cpl candidates per group)
+// rows = 1: the four-block kernel (lanes over 4 blocks of up to 4 x 4 points x 16
+// candidate groups, cpl candidates per group)
 constexpr BuiltVariant kBuilt[] = {
-    {4, 4, 2, 1},  {4, 4, 4, 1},  {4, 4, 8, 1},  {4, 4, 16, 1}, {8, 8, 4, 1},  {8, 8, 8, 1},
+    {1, 4, 2, 1},  {1, 4, 4, 1},
+    {4, 4, 2, 1},  {2, 8, 1, 1},  {2, 8, 2, 1},  {2, 8, 3, 1},  {2, 8, 4, 1},
+    {4, 4, 4, 1},  {4, 4, 8, 1},  {4, 4, 16, 1}, {8, 8, 4, 1},  {8, 8, 8, 1},
     {8, 8, 6, 2},  {8, 8, 12, 1}, {8, 8, 16, 1}, {8, 8, 24, 1}, {8, 8, 32, 1}, {8, 8, 4, 2},
     {8, 8, 4, 3},  {8, 8, 4, 4},  {8, 8, 8, 2},  {4, 4, 2, 2},  {4, 4, 4, 2}};
 }  // namespace
@@ -230,7 +330,9 @@ bool variant_valid(const PathDev& ph, int rows, int cpl, int passes) {
   if (ph.mode != OCSR_MODE_TILED) return false;
   for (const BuiltVariant& b : kBuilt)
     if (b.rows == rows && b.cpl == cpl && b.passes == passes)
-      return ph.bw <= b.nx && ph.bh <= b.rows && (64 / b.rows) * b.cpl * b.passes >= ph.nd;
+      return b.rows == 1   ? ph.bw <= 4 && ph.bh <= 4 && 16 * b.cpl >= ph.nd
+             : b.rows == 2 ? ph.bw <= 8 && ph.bh <= 8 && 32 * b.cpl >= ph.nd
+                           : ph.bw <= b.nx && ph.bh <= b.rows && (64 / b.rows) * b.cpl * b.passes >= ph.nd;
   return false;
 }
 
@@ -280,11 +382,27 @@ static hipError_t launch_level(const MatchParamsDev& P, const FramesDev& FR, con
   OCSR_TILED(4, 4, 2, 2)
   OCSR_TILED(4, 4, 4, 2)
 #undef OCSR_TILED
+#define OCSR_HALF(C)                                                                        \
+  if (v.rows == 2 && v.cpl == C)                                                             \
+    return timed_launch(timer, name, match_level_kernel<HalfMatcher<C>, 4>, dim3(grid), dim3(256), \
+                        0, stream, P, FR, ws, dbg, level);
+  OCSR_HALF(1)
+  OCSR_HALF(2)
+  OCSR_HALF(3)
+  OCSR_HALF(4)
+#undef OCSR_HALF
+  if (v.rows == 1 && v.cpl == 2)
+    return timed_launch(timer, name, match_level_kernel<QuadMatcher<2>, 4>, dim3(grid), dim3(256), 0,
+                        stream, P, FR, ws, dbg, level);
+  if (v.rows == 1 && v.cpl == 4)
+    return timed_launch(timer, name, match_level_kernel<QuadMatcher<4>, 4>, dim3(grid), dim3(256), 0,
+                        stream, P, FR, ws, dbg, level);
   return hipErrorNotSupported;   // rejected by the argument checks before any launch
 }
 
 // One launch for both levels when a kernel for the pair of variants is built (with
 // launch == false: only whether it is built).
+#define COMMA ,
 static bool launch_pair(const MatchParamsDev& P, const FramesDev& FR, const MatchWs& ws,
                         const DebugDev& dbg, int grid, hipStream_t stream, const LaunchTimer* timer,
                         bool launch) {
@@ -310,6 +428,26 @@ static bool launch_pair(const MatchParamsDev& P, const FramesDev& FR, const Matc
   OCSR_PAIR(4, 4, 2, 8, 8, 6, 2)
   OCSR_PAIR(4, 4, 2, 8, 8, 4, 2)
 #undef OCSR_PAIR
+#define OCSR_PAIR2(FM, FRW, FCP, FPS, CCP)                                                  \
+  if (f.rows == FRW && f.cpl == FCP && f.passes == FPS && c.rows == 2 && c.cpl == CCP) {    \
+    if (launch)                                                                          \
+      timed_launch(timer, "match", match_pair2_kernel<FM, HalfMatcher<CCP>, 4>, dim3(grid),  \
+                   dim3(256), 0, stream, P, FR, ws, dbg);                                 \
+    return true;                                                                         \
+  }
+  OCSR_PAIR2(TiledMatcher<4 COMMA 4 COMMA 2 COMMA 1>, 4, 2, 1, 2)
+  OCSR_PAIR2(TiledMatcher<4 COMMA 4 COMMA 2 COMMA 1>, 4, 2, 1, 3)
+  OCSR_PAIR2(TiledMatcher<4 COMMA 4 COMMA 2 COMMA 1>, 4, 2, 1, 4)
+  OCSR_PAIR2(HalfMatcher<1>, 2, 1, 1, 3)
+  OCSR_PAIR2(HalfMatcher<2>, 2, 2, 1, 3)
+  OCSR_PAIR2(HalfMatcher<2>, 2, 2, 1, 4)
+  OCSR_PAIR2(HalfMatcher<3>, 2, 3, 1, 3)
+  OCSR_PAIR2(QuadMatcher<2>, 1, 2, 1, 2)
+  OCSR_PAIR2(QuadMatcher<2>, 1, 2, 1, 3)
+  OCSR_PAIR2(QuadMatcher<2>, 1, 2, 1, 4)
+  OCSR_PAIR2(QuadMatcher<4>, 1, 4, 1, 3)
+  OCSR_PAIR2(QuadMatcher<4>, 1, 4, 1, 4)
+#undef OCSR_PAIR2
   return false;
 }
 

@@ -71,7 +71,8 @@ struct MatchParamsDev {
   float fb;                        // focal_px * baseline_m, one fp32 multiply
   float d_eps;
   int32_t cap_blocks;              // block capacity of one frame
-  int32_t item_blocks;             // blocks per work item: kItemWaves x blocks per wave
+  int32_t item_blocks[2];          // blocks per work item of each level: kItemWaves x
+                                   // the blocks one wave takes
   int32_t full_census;             // whole-frame calls: 1 = census of every tile, 0 = only
                                    // of the tiles some box's search reads
   int32_t vertical;                // 1: a vertical range is searched (the dy kernels run)

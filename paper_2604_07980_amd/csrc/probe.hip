@@ -1,8 +1,10 @@
 // Measurement of the device's int32 vector-ALU rate, the peak the matching and census
 // kernels are priced against. Every lane runs kChains independent chains of the
-// matching kernels' cost arithmetic, b <- a ^ b; acc <- popcount(b) + acc (one
-// v_xor_b32 and one accumulating v_bcnt_u32_b32 per step), with enough workgroups to fill
-// every SIMD. The rate is lane-operations per second over one timed launch.
+// matching kernels' cost arithmetic, b <- acc ^ b; acc <- popcount(b) + acc (one
+// v_xor_b32 and one accumulating v_bcnt_u32_b32 per step; feeding the sum back into the
+// next operand keeps the chain from having a closed form the compiler could use), with
+// enough workgroups to fill every SIMD. The rate is lane-operations per second over one
+// timed launch.
 #include "ocsr_internal.hpp"
 
 namespace ocsr {
@@ -15,18 +17,17 @@ constexpr int kChains = 8;
 __device__ uint32_t g_probe_sink[256];
 
 __global__ __launch_bounds__(256) void int_rate_kernel(int iters, uint32_t seed) {
-  uint32_t a[kChains], b[kChains], acc[kChains];
+  uint32_t b[kChains], acc[kChains];
 #pragma unroll
   for (int i = 0; i < kChains; ++i) {
-    a[i] = seed * (threadIdx.x + 13u * i + 1u);
-    b[i] = a[i] * 7u + 3u;
-    acc[i] = 0;
+    acc[i] = seed * (threadIdx.x + 13u * i + 1u);
+    b[i] = acc[i] * 7u + 3u;
   }
   for (int it = 0; it < iters; ++it) {
 #pragma unroll
     for (int i = 0; i < kChains; ++i) {
-      b[i] = a[i] ^ b[i];
-      acc[i] = __popc(b[i]) + acc[i];
+      b[i] = acc[i] ^ b[i];
+      asm("v_bcnt_u32_b32 %0, %1, %0" : "+v"(acc[i]) : "v"(b[i]));
     }
   }
   uint32_t s = 0;

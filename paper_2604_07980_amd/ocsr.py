@@ -329,12 +329,21 @@ def _workspace(nbytes: int, device) -> torch.Tensor:
 
 
 class Workspace:
-    """A reusable device workspace (grows on demand)."""
+    """A reusable device workspace: grows on demand, or (with `region`) a fixed
+    256-byte-aligned uint8 region of a caller's buffer that never grows."""
 
-    def __init__(self):
-        self.buf = None
+    def __init__(self, region: torch.Tensor | None = None):
+        if region is not None and (region.dtype != torch.uint8 or region.dim() != 1 or
+                                   region.data_ptr() % 256):
+            raise ValueError("a workspace region is a 256-byte-aligned 1-D uint8 tensor")
+        self.buf = region
+        self.fixed = region is not None
 
     def get(self, nbytes: int, device) -> torch.Tensor:
+        if self.fixed:
+            if self.buf.numel() < nbytes or self.buf.device != torch.device(device):
+                raise ValueError(f"workspace region of {self.buf.numel()} bytes < {nbytes} needed")
+            return self.buf
         if self.buf is None or self.buf.numel() < nbytes or self.buf.device != torch.device(device):
             self.buf = _workspace(nbytes, device)
         return self.buf

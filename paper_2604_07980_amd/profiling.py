@@ -2,14 +2,16 @@
 
     python -m paper_2604_07980_amd.profiling stats <kernel_stats.csv> --command "..."
     python -m paper_2604_07980_amd.profiling traffic --fetch <dir> --write <dir> \\
-        --copy-fetch <dir> --copy-write <dir> --copy-bytes N --kernel census --command "..."
+        --copy-fetch <dir> --copy-write <dir> --copy-bytes N --kernel census \\
+        --workload batch_16x1920x1200 --command "..."
 
 `stats` turns a `--kernel-trace --stats` kernel table into a short markdown table.
 `traffic` turns two `--pmc FETCH_SIZE` / `--pmc WRITE_SIZE` runs of a workload, plus the
 same two counters read for a plain device copy of known size, into HBM bytes per launch
 of one kernel: each counter's per-dispatch mean is scaled by the bytes the copy really
-moves over what the counter reported for it. The entry also records a hash of the
-kernel's source files, so a reader can tell whether the kernel changed since.
+moves over what the counter reported for it. Entries are filed by workload, then kernel;
+each records a hash of the kernel's source files, so a reader can tell whether the
+kernel changed since.
 """
 from __future__ import annotations
 
@@ -134,6 +136,7 @@ def main(argv=None):
         b.add_argument("--" + k.replace("_", "-"), required=True)
     b.add_argument("--copy-bytes", type=int, required=True)
     b.add_argument("--kernel", required=True, choices=sorted(KERNEL_SOURCES))
+    b.add_argument("--workload", required=True, help="workload name the entry is filed under")
     b.add_argument("--command", required=True)
     b.add_argument("--out", default=os.path.join(ROOT, "profiles", "traffic.json"))
     args = ap.parse_args(argv)
@@ -143,7 +146,7 @@ def main(argv=None):
     entry = traffic_entry(args.kernel, args.fetch, args.write, args.copy_fetch, args.copy_write,
                           args.copy_bytes, args.command)
     table = json.load(open(args.out)) if os.path.exists(args.out) else {}
-    table[args.kernel] = entry
+    table.setdefault(args.workload, {})[args.kernel] = entry
     with open(args.out, "w") as f:
         json.dump(table, f, indent=1, sort_keys=True)
     print(json.dumps(entry, indent=1))

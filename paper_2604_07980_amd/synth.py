@@ -338,15 +338,17 @@ def scene_small(seed: int, H: int = 96, W: int = 128, n_planes: int = 3) -> Scen
     return Scene(left, right, boxes, truth, seed)
 
 
+def serving_pool_pair(res: tuple[int, int], i: int, seed: int = 5000) -> tuple[np.ndarray, np.ndarray]:
+    """Pair i of the pre-rendered pool of one resolution."""
+    H, W = res
+    rng = np.random.default_rng(seed * 1000 + H * 7 + i)
+    planes = random_boxes(rng, H, W, 24, scale=W / 1920, tau_s=64 * W / 1920)
+    return render_pair(rng, H, W, planes)
+
+
 def serving_pool(res: tuple[int, int], n: int, seed: int = 5000) -> list[tuple[np.ndarray, np.ndarray]]:
     """Pre-rendered image pairs of one resolution for the request stream."""
-    H, W = res
-    out = []
-    for i in range(n):
-        rng = np.random.default_rng(seed * 1000 + H * 7 + i)
-        planes = random_boxes(rng, H, W, 24, scale=W / 1920, tau_s=64 * W / 1920)
-        out.append(render_pair(rng, H, W, planes))
-    return out
+    return [serving_pool_pair(res, i, seed) for i in range(n)]
 
 
 SERVING_RESOLUTIONS = ((720, 1280), (1080, 1920), (2160, 3840))

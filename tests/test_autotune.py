@@ -28,8 +28,13 @@ def test_variant_candidates_cover_the_shape(built):
         cands = ocsr.variant_candidates(bw, bh, nd)
         assert cands, (bw, bh, nd)
         for rows, cpl, passes in cands:
-            assert rows in (4, 8) and bh <= rows and bw <= rows
-            assert (64 // rows) * cpl * passes >= nd
+            if rows == 1:      # four blocks of up to 4 x 4 per wave, 16 candidate groups
+                assert bw <= 4 and bh <= 4 and 16 * cpl >= nd and passes == 1
+            elif rows == 2:    # two row halves of an up to 8 x 8 block, 32 candidate groups
+                assert bw <= 8 and bh <= 8 and 32 * cpl >= nd and passes == 1
+            else:
+                assert rows in (4, 8) and bh <= rows and bw <= rows
+                assert (64 // rows) * cpl * passes >= nd
     # nothing covers blocks wider than 8 or more than 256 candidates
     assert ocsr.variant_candidates(9, 8, 32) == []
     assert ocsr.variant_candidates(8, 8, 257) == []
@@ -37,6 +42,10 @@ def test_variant_candidates_cover_the_shape(built):
     assert (8, 4, 1) in ocsr.variant_candidates(4, 4, 32)
     # fewer candidates per lane in several passes
     assert (8, 4, 3) in ocsr.variant_candidates(8, 8, 96)
+    # the defaults: four 4x4 blocks per wave, row halves for 8x8 blocks
+    assert ocsr.variant_candidates(4, 4, 32)[0] == (1, 2, 1)
+    assert ocsr.variant_candidates(8, 8, 96)[0] == (2, 3, 1)
+    assert ocsr.variant_candidates(8, 8, 128)[0] == (2, 4, 1)
 
 
 def test_table_round_trip(built):

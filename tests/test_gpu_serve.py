@@ -79,3 +79,38 @@ def test_served_with_object_budget(lib, orc):
         assert_results_match(res[q.rid].boxes, want)
         n_dropped += int((rank >= 6).sum())
     assert n_dropped > 0                                   # the budget did bind
+
+
+def test_served_with_per_frame_graphs(lib, orc):
+    """Single-frame batches replay a graph captured per slot and per (resolution, box
+    capacity, parameters) bucket, with the frame's images copied into the slot's staging
+    images and its boxes padded with empty, not-ranged boxes: every result equals the
+    request run alone, and later frames of a bucket replay instead of capturing."""
+    reqs, host = _stream(40, seed=123, rate=300.0)
+    ex = serve.GpuExecutor(n_slots=2, graphs=True, slot_bytes=256 << 20)
+    srv = serve.Server(ex, mem_budget=512 << 20)
+    res = srv.run(reqs)
+    st = ex.graph_stats()
+    assert st["graph_frames"] > 0 and st["replays"] > 0
+    for q, r in zip(reqs, res):
+        assert r.error is None
+        alone = lib.results_to_numpy(lib.range_frame(q.left, q.right, _cuda(q.boxes), q.params))
+        assert (alone.view(np.int32) == r.boxes.view(np.int32)).all(), q.rid
+    for q in reqs[::9]:
+        Lh, Rh = host[q.rid]
+        assert_results_match(res[q.rid].boxes, orc.run_scene(Lh, Rh, q.params, q.boxes)[1][0])
+
+
+def test_deadline_and_cancellation_on_the_device(lib):
+    """A request cancelled while its batch runs comes back as cancelled; one whose
+    deadline passes while it waits for a slot times out; the rest are served."""
+    reqs, _ = _stream(12, seed=5, rate=1e6)
+    reqs[3].cancel_at = 0.0          # cancelled from the start: never submitted
+    for q in reqs[6:]:
+        q.deadline = 0.0             # all arrive at once behind one slot: most time out
+    ex = serve.GpuExecutor(n_slots=1, slot_bytes=256 << 20)
+    srv = serve.Server(ex, mem_budget=512 << 20, max_frames=1)
+    res = srv.run(reqs)
+    assert res[3].error == serve.ERR_CANCELLED and res[3].boxes is None
+    assert any(r.error == serve.ERR_DEADLINE for r in res[6:])
+    assert all(r.error is None for i, r in enumerate(res[:6]) if i != 3)

@@ -147,3 +147,52 @@ def test_summary():
     s = serve.summarize(res, wall=res[-1].done)
     assert s["served"] == 50 and s["rejected"] == 0
     assert s["latency_ms"]["p50"] <= s["latency_ms"]["p99"]
+
+
+def test_cancelled_while_queued_is_never_submitted():
+    # one slot, three requests at t = 0: the second is cancelled at 0.2 ms, while the
+    # first runs (1.5 ms), so it leaves the queue and the third runs next
+    reqs = [serve.Request(i, FakeImage(8, 8), FakeImage(8, 8), np.zeros((1, 5), np.int32),
+                          {"cls": i}, 0.0) for i in range(3)]
+    reqs[1].cancel_at = 0.2e-3
+    srv, ex, res = _run(reqs, slots=1)
+    assert res[1].error == serve.ERR_CANCELLED and res[1].boxes is None
+    submitted = [rid for _, _, rids, _ in ex.log for rid in rids]
+    assert submitted == [0, 2]
+    assert ex.log[1][0] == pytest.approx(1.5e-3)      # the third starts when the slot frees
+
+
+def test_cancelled_while_running_discards_its_result():
+    reqs = [serve.Request(0, FakeImage(8, 8), FakeImage(8, 8), np.zeros((1, 5), np.int32),
+                        {"cls": 0}, 0.0, cancel_at=1e-3)]
+    srv, ex, res = _run(reqs, slots=1)
+    assert [rid for _, _, rids, _ in ex.log for rid in rids] == [0]
+    assert res[0].error == serve.ERR_CANCELLED and res[0].boxes is None
+    assert srv.in_use == 0
+
+
+def test_deadline_times_out_queued_requests_only():
+    # one slot, batches of one frame: request 0 runs 0..1.5 ms; request 1 (deadline 1 ms)
+    # is still queued then and times out; request 2 (deadline 2 ms) starts at 1.5 ms and
+    # is served even though it completes after its deadline
+    reqs = [serve.Request(i, FakeImage(8, 8), FakeImage(8, 8), np.zeros((1, 5), np.int32),
+                          {"cls": 0}, 0.0) for i in range(3)]
+    reqs[1].deadline = 1e-3
+    reqs[2].deadline = 2e-3
+    srv, ex, res = _run(reqs, slots=1, max_frames=1)
+    assert res[1].error == serve.ERR_DEADLINE
+    assert res[0].error is None and res[2].error is None
+    assert res[2].done > 2e-3
+    assert [rid for _, _, rids, _ in ex.log for rid in rids] == [0, 2]
+
+
+def test_waiting_request_times_out_without_other_events():
+    # the only queued request cannot fit while a larger one runs; its deadline passes
+    # while the clock idles on the running batch
+    reqs = [serve.Request(0, FakeImage(8, 8), FakeImage(8, 8), np.zeros((1000, 5), np.int32),
+                          {"cls": 0}, 0.0),
+            serve.Request(1, FakeImage(8, 8), FakeImage(8, 8), np.zeros((1000, 5), np.int32),
+                          {"cls": 1}, 0.0, deadline=0.5e-3)]
+    srv, ex, res = _run(reqs, budget=3 << 20, slots=2)
+    assert res[1].error == serve.ERR_DEADLINE
+    assert res[0].error is None
