@@ -303,7 +303,8 @@ def batch_workload(ocsr, scenes, args):
     # timed region: K back-to-back batches
     ms = timed(batch, args.steps, args.warmup)
     kern = kernel_times(ocsr, batch, args.steps,
-                        ("census", "match", "match_far", "match_close", "aggregate", "fused"))
+                        ("plan", "census", "match", "match_far", "match_close", "aggregate", "reset",
+                         "fused"))
     lat_batch = latency(batch, max(50, args.latency_steps // 5))
     fused_identical = None
     if args.fused:
@@ -334,7 +335,7 @@ def batch_workload(ocsr, scenes, args):
     ocsr.set_fused(True)
     ms_fused = timed(batch, max(10, args.steps // 10), 3)
     fused_same = bool(torch.equal(out_b, ref))
-    fkern = kernel_times(ocsr, batch, 10, ("fused",))
+    fkern = kernel_times(ocsr, batch, 10, ("reset", "fused"))
     ocsr.set_fused(False)
     ocsr.set_graph(True)
     ms_graph = timed(batch, max(10, args.steps // 10), 3)
@@ -395,7 +396,7 @@ def frame_section(ocsr, sc, p, name, args, graph=False):
 
     ms = timed(step, args.frame_steps, max(3, args.warmup))
     kern = kernel_times(ocsr, step, args.frame_steps,
-                        ("census", "match", "match_far", "match_close", "aggregate"))
+                        ("plan", "census", "match", "match_far", "match_close", "aggregate"))
     tiles = accounting.census_tiles(W, H, sc.boxes, p)
     census_px = accounting.census_pixels(W, H, tiles, p)
     census_ops = census_px * ((2 * p["sx"] + 1) * (2 * p["sy"] + 1) - 1)
@@ -476,7 +477,7 @@ def vertical_section(ocsr, synth, steps, warmup):
         ocsr.range_frame(L, R, boxes, p, workspace=ws, out=out)
 
     ms = timed(step, steps, warmup)
-    kern = price(kernel_times(ocsr, step, steps, ("census", "match", "aggregate")),
+    kern = price(kernel_times(ocsr, step, steps, ("plan", "census", "match", "aggregate")),
                  {"match": fw["costs"] * MATCH_OPS_PER_COST})
     res = ocsr.results_to_numpy(out)
     return {"workload": "realistic_1080p, right view 2 rows low, dy -3..3 (far 7, close 5 "

@@ -264,15 +264,13 @@ int32_t build_params(const ocsr_ctx* ctx, const ocsr_match_params* p, int close_
   int32_t rc;
   if ((rc = check_path(p->far_path, "far", 1, &d->path[0])) != OCSR_OK) return rc;
   if ((rc = check_path(p->close_path, "close", close_scale, &d->path[1])) != OCSR_OK) return rc;
-  // Only the register-blocked TILED kernels are enabled: the per-candidate kernel that
-  // served GRID mode and blocks wider than 8 x 8 faulted on the device in its
-  // work-queue form and stays off until that is understood.
+  // the kernel variant of each path: the first built one that covers it (every TILED
+  // block of up to 64 points and every GRID block is covered up to 256 candidates)
   for (int l = 0; l < 2; ++l) {
     PathDev& ph = d->path[l];
     const MatchVariant v = pick_variant(ph);
     if (!v.tiled)
-      return fail(OCSR_E_UNSUPPORTED, "%s path: GRID mode, blocks wider or taller than 8 and "
-                  "more than 256 level candidates are not enabled in this build",
+      return fail(OCSR_E_UNSUPPORTED, "%s path: no kernel covers this block shape and range",
                   l == 0 ? "far" : "close");
     ph.rows = v.rows;
     ph.cpl = v.cpl;
@@ -297,6 +295,9 @@ int32_t build_params(const ocsr_ctx* ctx, const ocsr_match_params* p, int close_
     ph.dylo = fdiv(p->dy_min, s);
     ph.ndy = -fdiv(-p->dy_max, s) - ph.dylo + 1;
     if (!d->vertical) continue;
+    if (ph.mode != OCSR_MODE_TILED || ph.bw > 8 || ph.bh > 8)
+      return fail(OCSR_E_UNSUPPORTED, "%s path: a vertical range needs TILED blocks of at most "
+                  "8 x 8 points", l == 0 ? "far" : "close");
     if (ph.nd * ph.ndy > OCSR_MAX_DY_CANDIDATES)
       return fail(OCSR_E_UNSUPPORTED, "%s path: %d x %d (d, dy) candidates > %d", l == 0 ? "far" : "close",
                   ph.nd, ph.ndy, OCSR_MAX_DY_CANDIDATES);
@@ -359,8 +360,17 @@ int32_t check_ws(void* ws, size_t ws_bytes, size_t need) {
 size_t a256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 // descriptor images of one frame: L0, R0 at scale 1, L1, R1 at the close scale
+// census tiles of both views at both levels of a frame
+int64_t frame_tiles(int W, int H, int s) {
+  return 2 * (cdiv64(W, kCensusTileX) * cdiv64(H, kCensusTileY) +
+              cdiv64(W / s, kCensusTileX) * cdiv64(H / s, kCensusTileY));
+}
+
+// the four descriptor images of a frame, and the list of its census tiles (the lists of
+// every frame follow the images of every frame)
 size_t frame_census_bytes(int W, int H, int s) {
-  return 2 * a256((size_t)W * H * 8) + 2 * a256((size_t)(W / s) * (H / s) * 8);
+  return 2 * a256((size_t)W * H * 8) + 2 * a256((size_t)(W / s) * (H / s) * 8) +
+         a256(sizeof(int32_t) * (size_t)frame_tiles(W, H, s));
 }
 
 int32_t check_frames(const ocsr_frame* frames, int n_frames, const ocsr_frame_params* fp,
@@ -437,8 +447,13 @@ int32_t range_frames(ocsr_ctx* ctx, const ocsr_frame* frames, int n_frames,
     d.tile_begin = tiles;
     tiles += 2 * (d.tiles0 + d.tiles1);
   }
+  // the frames' census tile lists, after the images of every frame
+  for (int f = 0; f < n_frames; ++f) {
+    FR.f[f].tile_list = (int32_t*)base;
+    base += a256(sizeof(int32_t) * (size_t)frame_tiles(frames[f].width, frames[f].height, s));
+  }
   MatchWs mws = match_ws_carve(base, n_frames, n_total, cap_blocks);
-  const bool fused = ctx->use_fused && fused_available(P, fp->sx, fp->sy);
+  const bool fused = ctx->use_fused && fused_available(P, fp->sx, fp->sy, (int)tiles);
   const int sentinel = fp->sentinel ? 1 : 0;
   // the whole launch sequence of the call, on stream s
   auto enqueue = [&](hipStream_t s, const LaunchTimer* tp) -> int32_t {
@@ -447,8 +462,11 @@ int32_t range_frames(ocsr_ctx* ctx, const ocsr_frame* frames, int n_frames,
                                   ctx->n_cu, ctx->wgs_per_cu, s, tp);
       return e == hipSuccess ? OCSR_OK : hip_fail(e, "fused launch");
     }
-    hipError_t e = launch_frame_census(P, FR, boxes, mws, fp->sx, fp->sy, sentinel, tiles, ctx->n_cu,
-                                       ctx->census_list != 0, s, tp);
+    hipError_t e = ctx->census_list != 0
+                       ? launch_plan_and_census(P, FR, boxes, mws, fp->sx, fp->sy, sentinel, ctx->n_cu, s, tp)
+                       : hipErrorNotSupported;
+    if (e == hipErrorNotSupported)
+      e = launch_frame_census(P, FR, boxes, mws, fp->sx, fp->sy, sentinel, tiles, ctx->n_cu, false, s, tp);
     if (e != hipSuccess) return hip_fail(e, "census launch");
     e = launch_match(P, FR, boxes, mws, out, make_debug(nullptr), true,
                      std::max(1, ctx->n_cu * ctx->match_wgs_per_cu), s, tp);

@@ -42,6 +42,24 @@ __device__ __forceinline__ uint32_t wave_min_u32(uint32_t v, int from = 1) {
   return v;
 }
 
+// XCD-aware dealing of n work units over a launch's workgroups. The GPU hands out
+// workgroups round-robin over its 8 XCDs (workgroup b runs on XCD b mod 8), and each
+// XCD has its own L2. When the grid is a multiple of 8, XCD x takes the contiguous
+// units [n x / 8, n (x + 1) / 8), dealt over its workgroups b = x, x + 8, ..., so
+// neighbouring units, which read neighbouring data, share one L2; otherwise every
+// workgroup strides over all units. first / step: the workgroup's first unit and stride;
+// end: one past its last.
+struct Deal {
+  int first, step, end;
+};
+__device__ __forceinline__ Deal xcd_deal(int n) {
+  const int G = gridDim.x, b = blockIdx.x;
+  if ((G & 7) != 0 || G < 8) return Deal{b, G, n};
+  const int x = b & 7, per = G >> 3;
+  const int lo = (int)((long long)n * x / 8), hi = (int)((long long)n * (x + 1) / 8);
+  return Deal{lo + (b >> 3), per, hi};
+}
+
 // Orders the LDS traffic of one wave: every lane's earlier LDS writes are seen by the
 // wave's later LDS reads (a wave's LDS instructions complete in order).
 __device__ __forceinline__ void wave_sync() {

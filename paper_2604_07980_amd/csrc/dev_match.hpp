@@ -22,9 +22,10 @@ constexpr int kAggMax = 4096;
 // ---------------------------------------------------------------------------------
 // plan: one wave walks the frame's boxes 64 at a time
 // ---------------------------------------------------------------------------------
+// With items == false the item records are left to write_frame_items.
 __device__ __forceinline__ void plan_frame(const MatchParamsDev& P, const FrameDev& fr, int f,
                                            int n_total, const ocsr_box* __restrict__ boxes,
-                                           const MatchWs& ws, int lane) {
+                                           const MatchWs& ws, int lane, bool items = true) {
   const int n = fr.n_boxes;
   const int W = fr.W, H = fr.H;
   int carry = 0, carry0 = 0, carry1 = 0, matched_end = 0;
@@ -120,6 +121,7 @@ __device__ __forceinline__ void plan_frame(const MatchParamsDev& P, const FrameD
     fc[FC_FAR_ITEMS] = carry0;
     fc[FC_CLOSE_ITEMS] = carry1;
   }
+  if (!items) return;
   // item records: the frame's close items from 0, its far items after them; each lane
   // writes those of its box (re-reading the plan it stored above)
   ItemRec* rec = ws.items + (size_t)f * ws.items_cap;
@@ -142,6 +144,40 @@ __device__ __forceinline__ void plan_frame(const MatchParamsDev& P, const FrameD
       r.pad[0] = r.pad[1] = r.pad[2] = 0;
       rec[at + t] = r;
     }
+  }
+}
+
+// The item records of frame f (as plan_frame writes them) by nthr threads at once, after
+// plan_frame(..., items = false) has stored the frame's plans, running item ends and
+// counters (and the threads have synchronised with it): thread tid writes items tid,
+// tid + nthr, ...; the box of an item is found by binary search on the running item
+// ends of its level.
+__device__ __forceinline__ void write_frame_items(const MatchParamsDev& P, const FrameDev& fr, int f,
+                                                  int n_total, const MatchWs& ws, int tid, int nthr) {
+  const int n = fr.n_boxes;
+  const int32_t* fc = ws.fcount + f * FC_N;
+  const int n_close = fc[FC_CLOSE_ITEMS], n_far = fc[FC_FAR_ITEMS];
+  ItemRec* rec = ws.items + (size_t)f * ws.items_cap;
+  for (int t = tid; t < n_close + n_far; t += nthr) {
+    const int level = t < n_close ? 1 : 0;
+    const int q = level ? t : t - n_close;
+    const int32_t* end = ws.litem_end + (size_t)level * n_total + fr.box_off;
+    int lo = 0, hi = n - 1;   // first box whose running end passes q
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (end[mid] > q) hi = mid;
+      else lo = mid + 1;
+    }
+    const BoxPlan pl = ws.plan[fr.box_off + lo];
+    ItemRec r;
+    r.k = lo;
+    r.first = (q - pl.ioff) * P.item_blocks[level];
+    r.nblk = pl.nblk;
+    r.off = pl.off;
+    r.nbx = pl.nbx; r.bw = pl.bw; r.bh = pl.bh; r.ox = pl.ox; r.oy = pl.oy;
+    r.lx0 = pl.lx0; r.ly0 = pl.ly0; r.lw = pl.lw; r.lh = pl.lh;
+    r.pad[0] = r.pad[1] = r.pad[2] = 0;
+    rec[t] = r;
   }
 }
 
@@ -512,9 +548,7 @@ __device__ __forceinline__ void match_block_tiled(const MatchParamsDev& P, const
 // rows a lane reads the 8 template words and CPL + 7 strip words from LDS and forms
 // 8 CPL costs at 4 operations each; the two row halves of a candidate meet in one DPP
 // add, and the winner is a DPP wave minimum of packed (cost << 16 | index) keys. A strip
-// row is staged in 64-word chunks, lane l loading word l of each chunk: inside the
-// image this needs no per-lane address arithmetic (a uniform row address plus the lane's
-// fixed offset); blocks whose strip leaves the image take a checked copy.
+// row is staged in 64-word chunks through a buffer resource per row (stage_half_strip).
 // ---------------------------------------------------------------------------------
 template <int CPL>
 struct Half {
@@ -538,37 +572,36 @@ __device__ __forceinline__ uint32_t wave_min_dpp(uint32_t v) {
 }
 
 // Strip rows 0 .. ny - 1 of a level image from `rows` (the block's first row), words
-// [x_first, x_first + sw), into S[jj * SWP + m]. `inside`: every word lies in the image
-// (wave-uniform); otherwise words outside it are stored as 0. All loads of a lane are
-// issued before the first store.
+// [x_first, x_first + 64 CH) of each row, into S[jj * SWP + m] for m < SWP. Each row is
+// read through a buffer resource spanning exactly that row (W words), so a word outside
+// the image, left or right, reads as 0 by the hardware's range check: a column below 0
+// gives a byte offset that wraps past the range. The rows' resources and offsets are
+// wave-uniform (scalar instructions); lane l reads word l of each 64-word chunk at a byte
+// offset fixed for the whole strip, so the loads take no per-lane address arithmetic.
+// All loads of a lane are issued before the first store.
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 template <int SWP, int CH>
 __device__ __forceinline__ void stage_half_strip(uint64_t* __restrict__ S, const uint64_t* __restrict__ rows,
-                                                 int pitch, int x_first, int ny, int sw, int W,
-                                                 bool inside, int lane) {
-  uint64_t w[8][CH];
-  if (inside) {
-    const uint64_t* __restrict__ p = rows + x_first;
+                                                 int pitch, int x_first, int ny, int W, int lane) {
+  uint32_t voff[CH];
 #pragma unroll
-    for (int jj = 0; jj < 8; ++jj)
+  for (int c = 0; c < CH; ++c) voff[c] = (uint32_t)(x_first + 64 * c + lane) * 8u;
+  u32x2 w[8][CH];
 #pragma unroll
-      for (int c = 0; c < CH; ++c)
-        if (jj < ny && 64 * c + lane < sw) w[jj][c] = p[(size_t)jj * pitch + 64 * c + lane];
-  } else {
+  for (int jj = 0; jj < 8; ++jj) {
+    if (jj < ny) {
+      const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+          (void*)(rows + (size_t)jj * pitch), (short)0, W * 8, 0x00020000);
 #pragma unroll
-    for (int jj = 0; jj < 8; ++jj)
-#pragma unroll
-      for (int c = 0; c < CH; ++c) {
-        const int m = 64 * c + lane, x = x_first + m;
-        const bool ok = jj < ny && m < sw && x >= 0 && x < W;
-        w[jj][c] = rows[ok ? (size_t)jj * pitch + x : 0];
-        w[jj][c] = ok ? w[jj][c] : 0ull;
-      }
+      for (int c = 0; c < CH; ++c) w[jj][c] = __builtin_amdgcn_raw_buffer_load_b64(rs, voff[c], 0, 0);
+    }
   }
 #pragma unroll
   for (int jj = 0; jj < 8; ++jj)
 #pragma unroll
     for (int c = 0; c < CH; ++c)
-      if (jj < ny && 64 * c + lane < sw) S[jj * SWP + 64 * c + lane] = w[jj][c];
+      if (jj < ny && 64 * c + lane < SWP)
+        S[jj * SWP + 64 * c + lane] = ((uint64_t)w[jj][c].y << 32) | w[jj][c].x;
 }
 
 // One direction of the search: acc[c] = cost of strip position g CPL + c over the lane's
@@ -679,8 +712,7 @@ __device__ __forceinline__ void match_block_half(const MatchParamsDev& P, const 
   const int sw = nd + nx - 1;
   // forward strip CR(X0 - dhi + m, Y0 + j) and template CL(X0 + i, Y0 + j), loads issued
   // before the occluder scan so both are in flight together
-  const int xf = X0 - dhi;
-  stage_half_strip<SWP, CH>(S, Rb, lv.pitch, xf, ny, sw, W, xf >= 0 && xf + sw <= W, lane);
+  stage_half_strip<SWP, CH>(S, Rb, lv.pitch, X0 - dhi, ny, W, lane);
   {
     const int i = lane & 7, jj = lane >> 3;
     const bool ok = i < nx && jj < ny;
@@ -725,9 +757,8 @@ __device__ __forceinline__ void match_block_half(const MatchParamsDev& P, const 
   const int cb = (int)costf[min(best + 1, nd - 1)];
   const float d_sub = subpixel(d_f, best, nd, ca, (int)(key >> 16), cb);
   // backward strip CL(X0 - d_f + dlo + m, Y0 + j)
-  const int xb = X0 - d_f + dlo;
   wave_sync();
-  stage_half_strip<SWP, CH>(S, Lb, lv.pitch, xb, ny, sw, W, xb >= 0 && xb + sw <= W, lane);
+  stage_half_strip<SWP, CH>(S, Lb, lv.pitch, X0 - d_f + dlo, ny, W, lane);
   wave_sync();
   half_costs<CPL>(T, S, g, h, full, keep, acc);
   uint32_t bkey = 0xFFFFFFFFu;
@@ -974,6 +1005,97 @@ __device__ __forceinline__ void match_blocks_quad(const MatchParamsDev& P, const
 }
 
 // ---------------------------------------------------------------------------------
+// Any block of up to 64 points on any point grid (TILED, or the single GRID block of
+// the paper's far path, Sec. 4.3.4 "Far Objects"), up to 256 candidates: one wave per
+// block, lane l takes candidates l + 64 r (r < 4) and walks the block's unmasked points
+// one at a time. A point's template word is the same for every lane; its candidate
+// words are consecutive in the row, one per lane. Every read of the level images goes
+// through ld_word, which returns 0 outside [0, W); point rows lie inside the level box.
+// ---------------------------------------------------------------------------------
+constexpr size_t kGenericLdsBytes = sizeof(uint32_t) * 2 * 256;
+
+__device__ __forceinline__ void generic_costs(const LevelDev& lv, const BlockGeom& g, uint64_t mask,
+                                              int dlo, int nd, bool fwd, int d_f, int lane,
+                                              uint32_t (&acc)[4]) {
+  acc[0] = acc[1] = acc[2] = acc[3] = 0;
+  uint64_t m = mask;
+  while (m) {
+    const int t = __ffsll((unsigned long long)m) - 1;
+    m &= m - 1;
+    const int j = t / g.nx, i = t - j * g.nx;
+    const int x = geom_col(g, i), y = geom_row(g, j);
+    const uint64_t* __restrict__ rowL = lv.L + (size_t)y * lv.pitch;
+    const uint64_t* __restrict__ rowR = lv.R + (size_t)y * lv.pitch;
+    // forward: CL(x) against CR(x - d); backward: CR(x - d_f) against CL(x - d_f + d')
+    const uint64_t tmpl = fwd ? ld_word(rowL, x, lv.W) : ld_word(rowR, x - d_f, lv.W);
+    const uint64_t* __restrict__ other = fwd ? rowR : rowL;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int kc = lane + 64 * r;
+      const int xc = fwd ? x - (dlo + kc) : x - d_f + dlo + kc;
+      if (kc < nd) acc[r] = popc64_acc(tmpl ^ ld_word(other, xc, lv.W), acc[r]);
+    }
+  }
+}
+
+__device__ __forceinline__ void match_block_generic(const MatchParamsDev& P, const FrameDev& fr,
+                                                    const MatchWs& ws, const DebugDev& dbg,
+                                                    const BlockCtx& c, int lane, void* lds) {
+  uint32_t* costf = (uint32_t*)lds;
+  uint32_t* costb = costf + 256;
+  const LevelDev& lv = fr.lv[c.level];
+  const PathDev& ph = P.path[c.level];
+  const int nd = ph.nd, dlo = ph.dlo;
+  const uint64_t mask = block_mask(ws, fr.box_off, fr.n_boxes, c.k, c.g, lane);
+  const bool eligible = block_eligible(P, mask, c.g.nx * c.g.ny);
+  if (!eligible) {
+    write_block(ws, dbg, c, ph, mask, false, dlo, dlo, 0, (float)dlo, 0, lane);
+    wave_sync();
+    return;
+  }
+  uint32_t acc[4];
+  generic_costs(lv, c.g, mask, dlo, nd, true, 0, lane, acc);
+  uint32_t key = 0xFFFFFFFFu;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int kc = lane + 64 * r;
+    if (kc < nd) {
+      key = min(key, (acc[r] << 16) | (uint32_t)kc);
+      costf[kc] = acc[r];
+    }
+  }
+  key = wave_min_dpp(key);
+  const int best = (int)(key & 0xFFFFu);
+  const int d_f = dlo + best;
+  wave_sync();
+  const int ca = (int)costf[max(best - 1, 0)];
+  const int cb = (int)costf[min(best + 1, nd - 1)];
+  const float d_sub = subpixel(d_f, best, nd, ca, (int)(key >> 16), cb);
+  generic_costs(lv, c.g, mask, dlo, nd, false, d_f, lane, acc);
+  uint32_t bkey = 0xFFFFFFFFu;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int kc = lane + 64 * r;
+    if (kc < nd) {
+      bkey = min(bkey, (acc[r] << 16) | (uint32_t)kc);
+      costb[kc] = acc[r];
+    }
+  }
+  bkey = wave_min_dpp(bkey);
+  const int d_b = dlo + (int)(bkey & 0xFFFFu);
+  const int lr_ok = abs(d_b - d_f) <= P.lr_tol;
+  if (c.b < dbg.cap_blocks && (dbg.cost_fwd || dbg.cost_bwd)) {
+    wave_sync();
+    for (int kc = lane; kc < nd && kc < dbg.cap_nd; kc += 64) {
+      if (dbg.cost_fwd) dbg.cost_fwd[(size_t)c.b * dbg.cap_nd + kc] = (uint16_t)costf[kc];
+      if (dbg.cost_bwd) dbg.cost_bwd[(size_t)c.b * dbg.cap_nd + kc] = (uint16_t)costb[kc];
+    }
+  }
+  write_block(ws, dbg, c, ph, mask, true, d_f, d_b, lr_ok, d_sub, lr_ok, lane);
+  wave_sync();
+}
+
+// ---------------------------------------------------------------------------------
 // TILED block with a vertical range (the census cost over (dx, dy), Sec. 4.3.2). The
 // register-blocked row costs of match_block_tiled, repeated for every vertical offset.
 // Consecutive offsets read strip rows moved by one. When all ROWS + ndy - 1 rows fit
@@ -1192,10 +1314,10 @@ __device__ __forceinline__ void run_item_rec(const MatchParamsDev& P, const Fram
   }
 }
 
-// Grid-stride loop of a workgroup over the work items of one level of every frame:
-// frames in order, each frame's items in box order. Item numbers come from the
-// workgroup index, so the loop is uniform across the workgroup and needs no shared
-// counter. body(f, q) gets the frame and the item number within the frame's level.
+// Loop of a workgroup over the work items of one level of every frame (frames in
+// order, each frame's items in box order), dealt XCD by XCD (xcd_deal). Item numbers
+// come from the workgroup index, so the loop is uniform across the workgroup and needs
+// no shared counter. body(f, q) gets the frame and the item number within the frame's level.
 template <class Body>
 __device__ __forceinline__ void level_items(const FramesDev& FR, const MatchWs& ws, int level,
                                             Body body) {
@@ -1203,7 +1325,8 @@ __device__ __forceinline__ void level_items(const FramesDev& FR, const MatchWs& 
   const int cnt = lane < FR.n ? ws.fcount[lane * FC_N + (level == 0 ? FC_FAR_ITEMS : FC_CLOSE_ITEMS)] : 0;
   const int incl = wave_incl_scan(cnt, lane);
   const int total = __builtin_amdgcn_readfirstlane(__shfl(incl, 63, 64));
-  for (int q = blockIdx.x; q < total; q += gridDim.x) {
+  const Deal dl = xcd_deal(total);
+  for (int q = dl.first; q < dl.end; q += dl.step) {
     const uint64_t m = __ballot(lane < FR.n && incl > q);
     const int f = __ffsll((unsigned long long)m) - 1;
     const int excl = __builtin_amdgcn_readfirstlane(__shfl(incl - cnt, f, 64));
@@ -1592,6 +1715,61 @@ __device__ __forceinline__ void aggregate_box(const MatchParamsDev& P, const Mat
     out[kg] = r;
   }
 }
+
+// ---------------------------------------------------------------------------------
+// Matchers of one level's TILED blocks, for the generic pair kernel: the register-blocked
+// kernel (ROWS block rows per wave, CPL candidates per lane, PASSES passes) and the
+// row-half kernel (32 CPL candidates per wave).
+// run_item: wave `wave`'s share of work item r (frame f, level `level`).
+template <int ROWS, int NX, int CPL, int PASSES>
+struct TiledMatcher {
+  static constexpr size_t kLds = (Tiled<ROWS, NX, CPL, PASSES>::kLdsBytes + 15) & ~(size_t)15;
+  static __device__ __forceinline__ void run_item(const MatchParamsDev& P, const FrameDev& fr,
+                                                  const MatchWs& ws, const DebugDev& dbg, int f,
+                                                  int level, const ItemRec& r, int wave, int lane,
+                                                  void* lds) {
+    run_item_rec(P, fr, f, level, r, wave, [&](const BlockCtx& c) {
+      match_block_tiled<ROWS, NX, CPL, PASSES>(P, fr, ws, dbg, c, lane, lds);
+    });
+  }
+};
+template <int CPL>
+struct HalfMatcher {
+  static constexpr size_t kLds = (Half<CPL>::kLdsBytes + 15) & ~(size_t)15;
+  static __device__ __forceinline__ void run_item(const MatchParamsDev& P, const FrameDev& fr,
+                                                  const MatchWs& ws, const DebugDev& dbg, int f,
+                                                  int level, const ItemRec& r, int wave, int lane,
+                                                  void* lds) {
+    run_item_rec(P, fr, f, level, r, wave, [&](const BlockCtx& c) {
+      match_block_half<CPL>(P, fr, ws, dbg, c, lane, lds);
+    });
+  }
+};
+// any block of up to 64 points (GRID blocks included), lanes over candidates
+struct GenericMatcher {
+  static constexpr size_t kLds = kGenericLdsBytes;
+  static __device__ __forceinline__ void run_item(const MatchParamsDev& P, const FrameDev& fr,
+                                                  const MatchWs& ws, const DebugDev& dbg, int f,
+                                                  int level, const ItemRec& r, int wave, int lane,
+                                                  void* lds) {
+    run_item_rec(P, fr, f, level, r, wave, [&](const BlockCtx& c) {
+      match_block_generic(P, fr, ws, dbg, c, lane, lds);
+    });
+  }
+};
+// four blocks per wave: wave w takes blocks r.first + 4 w .. + 3 of a 16-block item
+template <int CPL>
+struct QuadMatcher {
+  static constexpr size_t kLds = (Quad<CPL>::kLdsBytes + 15) & ~(size_t)15;
+  static __device__ __forceinline__ void run_item(const MatchParamsDev& P, const FrameDev& fr,
+                                                  const MatchWs& ws, const DebugDev& dbg, int f,
+                                                  int level, const ItemRec& r, int wave, int lane,
+                                                  void* lds) {
+    const int first = r.first + 4 * wave;
+    if (first < r.nblk && first < r.first + P.item_blocks[level])
+      match_blocks_quad<CPL>(P, fr, ws, dbg, f, level, r, first, lane, lds);
+  }
+};
 
 // ---------------------------------------------------------------------------------
 // work items

@@ -2,11 +2,12 @@
 // kMaxFrames frames in one kernel (Alg. 2 end to end).
 //
 // The grid holds exactly as many 256-thread workgroups as fit on the device at once, so
-// all of them are resident, and the launch runs in three phases split by grid barriers:
-//   1. the plan of every frame, then every census tile (64 x 32 level pixels of one view
-//      at one level), dealt round-robin to the workgroups;
-//   2. the work items of every frame (all close items first, then all far items), up to
-//      item_blocks blocks of one box per item, spread over the four waves;
+// all of them are resident, and the launch runs in phases split by grid barriers:
+//   1. the plan of every frame with the list of the census tiles its boxes' searches
+//      read (workgroups 0 .. F - 1), then, after a grid barrier, the census of the
+//      listed tiles, the shares of one XCD's workgroups consecutive in the list;
+//   2. the work items of every frame (all close items first, then all far items), each
+//      list dealt XCD by XCD, in the same matchers as the multi-launch kernels;
 //   3. one box per workgroup: aggregation and depth.
 // Work is dealt by workgroup index, so no shared counter is touched per item; each
 // barrier costs one atomic per workgroup, spread over kBarSlots counters. Its wait is
@@ -18,25 +19,20 @@
 namespace ocsr {
 namespace {
 
-template <int ROWS, int NX, int CPL>
-struct VTiled {
-  static constexpr int rows = ROWS, nx = NX, cpl = CPL;
-  static constexpr size_t kLdsBytes = dev::Tiled<ROWS, NX, CPL>::kLdsBytes;
-};
-
 constexpr size_t cmax(size_t a, size_t b) { return a > b ? a : b; }
 
 __global__ __launch_bounds__(64) void reset_kernel(MatchWs ws) {
   if (threadIdx.x < GC_N) ws.gcount[threadIdx.x] = 0;
 }
 
-template <int CSX, int CSY, class FV, class CV>
+template <int CSX, int CSY, class FM, class CM>
 __global__ __launch_bounds__(256) void fused_kernel(MatchParamsDev P, FramesDev FR,
                                                     const ocsr_box* boxes, MatchWs ws,
                                                     ocsr_box_result* out, int sentinel,
                                                     int n_census) {
-  constexpr size_t kWave = (cmax(FV::kLdsBytes, CV::kLdsBytes) + 15) & ~(size_t)15;
-  constexpr size_t kLds = cmax(cmax(dev::CensusTile<CSX, CSY>::kLdsBytes, 4 * kWave),
+  constexpr size_t kWave = cmax(FM::kLds, CM::kLds);
+  constexpr size_t kPlan = sizeof(uint32_t) * kFrameTileWords + sizeof(int) * 8;
+  constexpr size_t kLds = cmax(cmax(cmax(dev::CensusTile<CSX, CSY>::kLdsBytes, kPlan), kItemWaves * kWave),
                                sizeof(dev::AggLds));
   __shared__ uint64_t lds[(kLds + 7) / 8];
   __shared__ int mprefix[2 * kMaxFrames + 1];
@@ -46,22 +42,46 @@ __global__ __launch_bounds__(256) void fused_kernel(MatchParamsDev P, FramesDev 
   const int F = FR.n;
   int32_t* timeout = ws.gcount + GC_TIMEOUT;
 
-  // ---- phase 1: plans, then census tiles
-  for (int a = w; a < F + n_census; a += G) {
-    if (a < F) {
-      if (wave == 0) dev::plan_frame(P, FR.f[a], a, FR.n_boxes_total, boxes, ws, lane);
-    } else {
-      dev::frame_census_tile<CSX, CSY>(P, FR, boxes, a - F, CSX, CSY, sentinel, (uint32_t*)lds);
-    }
-    __syncthreads();   // the next item reuses the LDS
+  // ---- phase 1: the plan of every frame with its list of census tiles, then the census
+  // of the listed tiles, the shares of one XCD's workgroups consecutive in the list
+  if (w < F) {
+    uint32_t* bits = (uint32_t*)lds;
+    int* sc = (int*)(bits + kFrameTileWords);
+    if (wave == 0) dev::plan_frame(P, FR.f[w], w, FR.n_boxes_total, boxes, ws, lane, false);
+    dev::list_frame_tiles(P, FR.f[w], w, boxes, ws, bits, sc);
+    dev::write_frame_items(P, FR.f[w], w, FR.n_boxes_total, ws, tid, 256);
+    __syncthreads();   // the LDS is reused below
   }
   dev::grid_barrier(ws.gcount + GC_BAR0, G, timeout);
+  {
+    int* pre = mprefix;   // the frames' list lengths, then reused for the items
+    if (tid < 64) {
+      const int cnt = lane < F ? ws.fcount[lane * FC_N + FC_TILES] : 0;
+      const int incl = dev::wave_incl_scan(cnt, lane);
+      if (lane < F) pre[lane + 1] = incl;
+      if (lane == 0) pre[0] = 0;
+    }
+    __syncthreads();
+    const int N = pre[F];
+    const int x = w & 7;
+    int r = 0;
+    for (int y = 0; y < x; ++y) r += (G - y + 7) >> 3;
+    r += w >> 3;
+    const int lo = (int)((long long)N * r / G), hi = (int)((long long)N * (r + 1) / G);
+    int f = 0;
+    for (int q = lo; q < hi; ++q) {
+      while (q >= pre[f + 1]) ++f;
+      const FrameDev& fr = FR.f[f];
+      const int c = fr.tile_begin + fr.tile_list[q - pre[f]];
+      dev::frame_census_tile<CSX, CSY>(P, FR, boxes, c, CSX, CSY, sentinel, (uint32_t*)lds, false);
+      __syncthreads();   // the next tile reuses the LDS
+    }
+  }
+  dev::grid_barrier(ws.gcount + GC_BAR2, G, timeout);
   bool timed_out = dev::load_relaxed(timeout) != 0;
 
   // ---- phase 2: work items; close items of every frame, then far items
   if (tid < 64) {
-    // mprefix[j] = items before slot j, slot j < F: close items of frame j, else far
-    // items of frame j - F
     const int j = lane < F ? lane : lane - F;
     const int cnt = lane < 2 * F ? ws.fcount[j * FC_N + (lane < F ? FC_CLOSE_ITEMS : FC_FAR_ITEMS)] : 0;
     const int incl = dev::wave_incl_scan(cnt, lane);
@@ -69,25 +89,27 @@ __global__ __launch_bounds__(256) void fused_kernel(MatchParamsDev P, FramesDev 
     if (lane == 0) mprefix[0] = 0;
   }
   __syncthreads();
-  const int n_items = timed_out ? 0 : mprefix[2 * F];
-  void* wl = (char*)lds + wave * kWave;
-  for (int m = w; m < n_items; m += G) {
-    int slot = 0;
-    for (int k = 1; k < 2 * F; ++k)
-      if (m >= mprefix[k]) slot = k;
-    const int f = slot < F ? slot : slot - F;
-    const FrameDev& fr = FR.f[f];
-    const int q = m - mprefix[slot];
-    if (slot < F) {
-      dev::run_item(P, fr, f, FR.n_boxes_total, ws, 1, q, wave, lane, [&](const dev::BlockCtx& c) {
-        dev::match_block_tiled<CV::rows, CV::nx, CV::cpl>(P, fr, ws, DebugDev{}, c, lane, wl);
-      });
-    } else {
-      dev::run_item(P, fr, f, FR.n_boxes_total, ws, 0, q, wave, lane, [&](const dev::BlockCtx& c) {
-        dev::match_block_tiled<FV::rows, FV::nx, FV::cpl>(P, fr, ws, DebugDev{}, c, lane, wl);
-      });
+  if (!timed_out) {
+    void* wl = (char*)lds + wave * kWave;
+    const int n_close = mprefix[F], n_far = mprefix[2 * F] - n_close;
+    for (int part = 0; part < 2; ++part) {
+      const dev::Deal dl = dev::xcd_deal(part ? n_far : n_close);
+      for (int i = dl.first; i < dl.end; i += dl.step) {
+        const int m = i + (part ? n_close : 0);
+        int slot = 0;
+        for (int k = 1; k < 2 * F; ++k)
+          if (m >= mprefix[k]) slot = k;
+        const int f = slot < F ? slot : slot - F;
+        const FrameDev& fr = FR.f[f];
+        const int q = m - mprefix[slot];
+        const int at = q + (slot < F ? 0 : mprefix[f + 1] - mprefix[f]);
+        const ItemRec rec = ws.items[(size_t)f * ws.items_cap + at];
+        if (slot < F) CM::run_item(P, fr, ws, DebugDev{}, f, 1, rec, wave, lane, wl);
+        else FM::run_item(P, fr, ws, DebugDev{}, f, 0, rec, wave, lane, wl);
+      }
     }
   }
+  __syncthreads();
   dev::grid_barrier(ws.gcount + GC_BAR1, G, timeout);
   timed_out = dev::load_relaxed(timeout) != 0;
 
@@ -98,20 +120,22 @@ __global__ __launch_bounds__(256) void fused_kernel(MatchParamsDev P, FramesDev 
   }
 }
 
-enum class FusedPair { kNone, k4_2__8_12, k4_2__8_8, k4_2__8_16, k8_8__8_12 };
+// matcher pairs with a fused kernel: far (rows, cpl) and close (rows, cpl)
+enum class FusedPair { kNone, kQ2H3, kQ2H4, kQ2H2, kQ4H4, kH2H3 };
 
 FusedPair fused_pair(const MatchParamsDev& P, int sx, int sy) {
   // the persistent kernel has no vertical search: such calls take the multi-launch path
   if (sx != 3 || sy != 4 || P.vertical) return FusedPair::kNone;
   const PathDev& f = P.path[0];
   const PathDev& c = P.path[1];
-  if (c.rows != 8 || f.passes != 1 || c.passes != 1) return FusedPair::kNone;
-  if (f.rows == 4 && f.cpl == 2) {
-    if (c.cpl == 12) return FusedPair::k4_2__8_12;
-    if (c.cpl == 8) return FusedPair::k4_2__8_8;
-    if (c.cpl == 16) return FusedPair::k4_2__8_16;
+  if (c.rows != 2 || f.passes != 1 || c.passes != 1) return FusedPair::kNone;
+  if (f.rows == 1 && f.cpl == 2) {
+    if (c.cpl == 3) return FusedPair::kQ2H3;
+    if (c.cpl == 4) return FusedPair::kQ2H4;
+    if (c.cpl == 2) return FusedPair::kQ2H2;
   }
-  if (f.rows == 8 && f.cpl == 8 && c.cpl == 12) return FusedPair::k8_8__8_12;
+  if (f.rows == 1 && f.cpl == 4 && c.cpl == 4) return FusedPair::kQ4H4;
+  if (f.rows == 2 && f.cpl == 2 && c.cpl == 3) return FusedPair::kH2H3;
   return FusedPair::kNone;
 }
 
@@ -130,8 +154,8 @@ hipError_t launch_one(K kernel, const MatchParamsDev& P, const FramesDev& FR, co
 
 }  // namespace
 
-bool fused_available(const MatchParamsDev& p, int sx, int sy) {
-  return fused_pair(p, sx, sy) != FusedPair::kNone;
+bool fused_available(const MatchParamsDev& p, int sx, int sy, int n_census_tiles) {
+  return fused_pair(p, sx, sy) != FusedPair::kNone && n_census_tiles <= 32 * kCensusListWords;
 }
 
 hipError_t launch_fused(const MatchParamsDev& P, const FramesDev& FR, const ocsr_box* boxes,
@@ -139,7 +163,7 @@ hipError_t launch_fused(const MatchParamsDev& P, const FramesDev& FR, const ocsr
                         int n_census_tiles, int n_cu, int wgs_per_cu, hipStream_t stream,
                         const LaunchTimer* timer) {
   const FusedPair pair = fused_pair(P, sx, sy);
-  if (pair == FusedPair::kNone) return hipErrorNotSupported;
+  if (pair == FusedPair::kNone || n_census_tiles > 32 * kCensusListWords) return hipErrorNotSupported;
   if (timer) timer->before(timer->ctx, "reset", stream);
   reset_kernel<<<1, 64, 0, stream>>>(ws);
   if (timer) timer->after(timer->ctx, "reset", stream);
@@ -147,22 +171,17 @@ hipError_t launch_fused(const MatchParamsDev& P, const FramesDev& FR, const ocsr
   if (e != hipSuccess) return e;
   if (timer) timer->before(timer->ctx, "fused", stream);
   switch (pair) {
-    case FusedPair::k4_2__8_12:
-      e = launch_one(fused_kernel<3, 4, VTiled<4, 4, 2>, VTiled<8, 8, 12>>, P, FR, boxes, ws, out,
-                     sentinel, n_census_tiles, n_cu, wgs_per_cu, stream);
+#define OCSR_FUSED(K, FMT, CMT)                                                              \
+    case FusedPair::K:                                                                       \
+      e = launch_one(fused_kernel<3, 4, dev::FMT, dev::CMT>, P, FR, boxes, ws, out, sentinel,  \
+                     n_census_tiles, n_cu, wgs_per_cu, stream);                              \
       break;
-    case FusedPair::k4_2__8_8:
-      e = launch_one(fused_kernel<3, 4, VTiled<4, 4, 2>, VTiled<8, 8, 8>>, P, FR, boxes, ws, out,
-                     sentinel, n_census_tiles, n_cu, wgs_per_cu, stream);
-      break;
-    case FusedPair::k4_2__8_16:
-      e = launch_one(fused_kernel<3, 4, VTiled<4, 4, 2>, VTiled<8, 8, 16>>, P, FR, boxes, ws, out,
-                     sentinel, n_census_tiles, n_cu, wgs_per_cu, stream);
-      break;
-    case FusedPair::k8_8__8_12:
-      e = launch_one(fused_kernel<3, 4, VTiled<8, 8, 8>, VTiled<8, 8, 12>>, P, FR, boxes, ws, out,
-                     sentinel, n_census_tiles, n_cu, wgs_per_cu, stream);
-      break;
+    OCSR_FUSED(kQ2H3, QuadMatcher<2>, HalfMatcher<3>)
+    OCSR_FUSED(kQ2H4, QuadMatcher<2>, HalfMatcher<4>)
+    OCSR_FUSED(kQ2H2, QuadMatcher<2>, HalfMatcher<2>)
+    OCSR_FUSED(kQ4H4, QuadMatcher<4>, HalfMatcher<4>)
+    OCSR_FUSED(kH2H3, HalfMatcher<2>, HalfMatcher<3>)
+#undef OCSR_FUSED
     default:
       e = hipErrorNotSupported;
   }

@@ -34,12 +34,66 @@ __global__ __launch_bounds__(256) void frame_census_kernel(MatchParamsDev P, Fra
       dev::plan_frame(P, FR.f[blockIdx.x], blockIdx.x, FR.n_boxes_total, boxes, ws, threadIdx.x);
     return;
   }
-  if (listed)
-    dev::frame_census_listed<SX, SY>(P, FR, boxes, n_tiles, blockIdx.x - FR.n, gridDim.x - FR.n,
-                                     sx, sy, sentinel, lds, tbits, tlist, tsc);
+  if (listed) {
+    // XCD-aware share: the census workgroups b in [F, F + G) are renumbered so that those
+    // of one XCD (b mod 8) take consecutive shares of the tile list, whose neighbouring
+    // tiles read overlapping source rows
+    const int A = FR.n, B = gridDim.x, b = blockIdx.x, x = b & 7;
+    int w = 0;
+    for (int y = 0; y < x; ++y) w += ((B - y + 7) >> 3) - ((A - y + 7) >> 3);
+    w += (b - (A + ((x - A) & 7))) >> 3;
+    dev::frame_census_listed<SX, SY>(P, FR, boxes, n_tiles, w, B - A, sx, sy, sentinel, lds,
+                                     tbits, tlist, tsc);
+  }
   else
     dev::frame_census_tile<SX, SY>(P, FR, boxes, blockIdx.x - FR.n, sx, sy, sentinel, lds, true,
                                    &tsc[0]);
+}
+
+// Plan of frame blockIdx.x (wave 0 plans the boxes, then all four waves write the work
+// items) and the list of its census tiles (all four waves).
+__global__ __launch_bounds__(256) void plan_tiles_kernel(MatchParamsDev P, FramesDev FR,
+                                                         const ocsr_box* boxes, MatchWs ws) {
+  __shared__ uint32_t bits[kFrameTileWords];
+  __shared__ int sc[8];
+  const int f = blockIdx.x;
+  if (threadIdx.x < 64)
+    dev::plan_frame(P, FR.f[f], f, FR.n_boxes_total, boxes, ws, threadIdx.x, false);
+  dev::list_frame_tiles(P, FR.f[f], f, boxes, ws, bits, sc);   // synchronises the workgroup
+  dev::write_frame_items(P, FR.f[f], f, FR.n_boxes_total, ws, threadIdx.x, 256);
+}
+
+// Census of the listed tiles of every frame by persistent workgroups: the frames' lists,
+// concatenated, are shared out in equal consecutive parts, the parts of one XCD's
+// workgroups adjacent (neighbouring tiles read overlapping source rows).
+template <int SX, int SY>
+__global__ __launch_bounds__(256) void census_list_kernel(MatchParamsDev P, FramesDev FR,
+                                                          const ocsr_box* boxes, MatchWs ws,
+                                                          int sx, int sy, int sentinel) {
+  __shared__ uint32_t lds[SX >= 0 ? dev::CensusTile<(SX > 0 ? SX : 0), (SY > 0 ? SY : 0)>::kLdsBytes / 4 : 1];
+  __shared__ int pre[kMaxFrames + 1];
+  const int tid = threadIdx.x, lane = tid & 63;
+  if (tid < 64) {
+    const int cnt = lane < FR.n ? ws.fcount[lane * FC_N + FC_TILES] : 0;
+    const int incl = dev::wave_incl_scan(cnt, lane);
+    if (lane < FR.n) pre[lane + 1] = incl;
+    if (lane == 0) pre[0] = 0;
+  }
+  __syncthreads();
+  const int N = pre[FR.n];
+  const int G = gridDim.x, b = blockIdx.x, x = b & 7;
+  int w = 0;   // this workgroup's rank when the workgroups of XCD 0 come first, then XCD 1, ...
+  for (int y = 0; y < x; ++y) w += (G - y + 7) >> 3;
+  w += b >> 3;
+  const int lo = (int)((long long)N * w / G), hi = (int)((long long)N * (w + 1) / G);
+  int f = 0;
+  for (int q = lo; q < hi; ++q) {
+    while (q >= pre[f + 1]) ++f;
+    const FrameDev& fr = FR.f[f];
+    const int c = fr.tile_begin + fr.tile_list[q - pre[f]];
+    dev::frame_census_tile<SX, SY>(P, FR, boxes, c, sx, sy, sentinel, lds, false);
+    __syncthreads();   // the next tile reuses the LDS
+  }
 }
 
 // Waves per SIMD a single-level kernel is compiled for (as many as its registers allow
@@ -126,48 +180,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(pair_waves<
   }
 }
 
-// Matchers of one level's TILED blocks, for the generic pair kernel: the register-blocked
-// kernel (ROWS block rows per wave, CPL candidates per lane, PASSES passes) and the
-// row-half kernel (32 CPL candidates per wave).
-// run_item: wave `wave`'s share of work item r (frame f, level `level`).
-template <int ROWS, int NX, int CPL, int PASSES>
-struct TiledMatcher {
-  static constexpr size_t kLds = (dev::Tiled<ROWS, NX, CPL, PASSES>::kLdsBytes + 15) & ~(size_t)15;
-  static __device__ __forceinline__ void run_item(const MatchParamsDev& P, const FrameDev& fr,
-                                                  const MatchWs& ws, const DebugDev& dbg, int f,
-                                                  int level, const ItemRec& r, int wave, int lane,
-                                                  void* lds) {
-    dev::run_item_rec(P, fr, f, level, r, wave, [&](const dev::BlockCtx& c) {
-      dev::match_block_tiled<ROWS, NX, CPL, PASSES>(P, fr, ws, dbg, c, lane, lds);
-    });
-  }
-};
-template <int CPL>
-struct HalfMatcher {
-  static constexpr size_t kLds = (dev::Half<CPL>::kLdsBytes + 15) & ~(size_t)15;
-  static __device__ __forceinline__ void run_item(const MatchParamsDev& P, const FrameDev& fr,
-                                                  const MatchWs& ws, const DebugDev& dbg, int f,
-                                                  int level, const ItemRec& r, int wave, int lane,
-                                                  void* lds) {
-    dev::run_item_rec(P, fr, f, level, r, wave, [&](const dev::BlockCtx& c) {
-      dev::match_block_half<CPL>(P, fr, ws, dbg, c, lane, lds);
-    });
-  }
-};
-// four blocks per wave: wave w takes blocks r.first + 4 w .. + 3 of a 16-block item
-template <int CPL>
-struct QuadMatcher {
-  static constexpr size_t kLds = (dev::Quad<CPL>::kLdsBytes + 15) & ~(size_t)15;
-  static __device__ __forceinline__ void run_item(const MatchParamsDev& P, const FrameDev& fr,
-                                                  const MatchWs& ws, const DebugDev& dbg, int f,
-                                                  int level, const ItemRec& r, int wave, int lane,
-                                                  void* lds) {
-    const int first = r.first + 4 * wave;
-    if (first < r.nblk && first < r.first + P.item_blocks[level])
-      dev::match_blocks_quad<CPL>(P, fr, ws, dbg, f, level, r, first, lane, lds);
-  }
-};
-
 // Both levels in one launch with any pair of matchers (FM far, CM close): work items of
 // every frame's close level first, then of every far level. Compiled for WAVES waves per
 // SIMD.
@@ -189,18 +201,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES))) vo
   }
   __syncthreads();
   void* wl = (char*)lds + wave * kWave;
-  const int total = prefix[2 * F];
-  for (int m = blockIdx.x; m < total; m += gridDim.x) {
-    int slot = 0;
-    for (int k = 1; k < 2 * F; ++k)
-      if (m >= prefix[k]) slot = k;
-    const int f = slot < F ? slot : slot - F;
-    const FrameDev& fr = FR.f[f];
-    const int q = m - prefix[slot];
-    const int at = q + (slot < F ? 0 : prefix[f + 1] - prefix[f]);
-    const ItemRec r = ws.items[(size_t)f * ws.items_cap + at];
-    if (slot < F) CM::run_item(P, fr, ws, dbg, f, 1, r, wave, lane, wl);
-    else FM::run_item(P, fr, ws, dbg, f, 0, r, wave, lane, wl);
+  // the close items of every frame, then the far ones, each list dealt XCD by XCD
+  const int n_close = prefix[F], n_far = prefix[2 * F] - n_close;
+  for (int part = 0; part < 2; ++part) {
+    const dev::Deal dl = dev::xcd_deal(part ? n_far : n_close);
+    for (int i = dl.first; i < dl.end; i += dl.step) {
+      const int m = i + (part ? n_close : 0);
+      int slot = 0;
+      for (int k = 1; k < 2 * F; ++k)
+        if (m >= prefix[k]) slot = k;
+      const int f = slot < F ? slot : slot - F;
+      const FrameDev& fr = FR.f[f];
+      const int q = m - prefix[slot];
+      const int at = q + (slot < F ? 0 : prefix[f + 1] - prefix[f]);
+      const ItemRec r = ws.items[(size_t)f * ws.items_cap + at];
+      if (slot < F) CM::run_item(P, fr, ws, dbg, f, 1, r, wave, lane, wl);
+      else FM::run_item(P, fr, ws, dbg, f, 0, r, wave, lane, wl);
+    }
   }
 }
 
@@ -323,14 +340,19 @@ constexpr BuiltVariant kBuilt[] = {
     {4, 4, 2, 1},  {2, 8, 1, 1},  {2, 8, 2, 1},  {2, 8, 3, 1},  {2, 8, 4, 1},
     {4, 4, 4, 1},  {4, 4, 8, 1},  {4, 4, 16, 1}, {8, 8, 4, 1},  {8, 8, 8, 1},
     {8, 8, 6, 2},  {8, 8, 12, 1}, {8, 8, 16, 1}, {8, 8, 24, 1}, {8, 8, 32, 1}, {8, 8, 4, 2},
-    {8, 8, 4, 3},  {8, 8, 4, 4},  {8, 8, 8, 2},  {4, 4, 2, 2},  {4, 4, 4, 2}};
+    {8, 8, 4, 3},  {8, 8, 4, 4},  {8, 8, 8, 2},  {4, 4, 2, 2},  {4, 4, 4, 2},
+    {0, 8, 4, 1}};
 }  // namespace
 
 bool variant_valid(const PathDev& ph, int rows, int cpl, int passes) {
+  // rows = 0: the generic kernel, any TILED block of up to 64 points or a GRID block
+  if (rows == 0 && cpl == 4 && passes == 1)
+    return ph.nd <= 256 && (ph.mode == OCSR_MODE_GRID ? ph.n_side <= 8 : ph.bw * ph.bh <= 64);
   if (ph.mode != OCSR_MODE_TILED) return false;
   for (const BuiltVariant& b : kBuilt)
     if (b.rows == rows && b.cpl == cpl && b.passes == passes)
-      return b.rows == 1   ? ph.bw <= 4 && ph.bh <= 4 && 16 * b.cpl >= ph.nd
+      return b.rows == 0   ? false
+             : b.rows == 1 ? ph.bw <= 4 && ph.bh <= 4 && 16 * b.cpl >= ph.nd
              : b.rows == 2 ? ph.bw <= 8 && ph.bh <= 8 && 32 * b.cpl >= ph.nd
                            : ph.bw <= b.nx && ph.bh <= b.rows && (64 / b.rows) * b.cpl * b.passes >= ph.nd;
   return false;
@@ -384,18 +406,21 @@ static hipError_t launch_level(const MatchParamsDev& P, const FramesDev& FR, con
 #undef OCSR_TILED
 #define OCSR_HALF(C)                                                                        \
   if (v.rows == 2 && v.cpl == C)                                                             \
-    return timed_launch(timer, name, match_level_kernel<HalfMatcher<C>, 4>, dim3(grid), dim3(256), \
+    return timed_launch(timer, name, match_level_kernel<dev::HalfMatcher<C>, 4>, dim3(grid), dim3(256), \
                         0, stream, P, FR, ws, dbg, level);
   OCSR_HALF(1)
   OCSR_HALF(2)
   OCSR_HALF(3)
   OCSR_HALF(4)
 #undef OCSR_HALF
+  if (v.rows == 0)
+    return timed_launch(timer, name, match_level_kernel<dev::GenericMatcher, 4>, dim3(grid), dim3(256), 0,
+                        stream, P, FR, ws, dbg, level);
   if (v.rows == 1 && v.cpl == 2)
-    return timed_launch(timer, name, match_level_kernel<QuadMatcher<2>, 4>, dim3(grid), dim3(256), 0,
+    return timed_launch(timer, name, match_level_kernel<dev::QuadMatcher<2>, 4>, dim3(grid), dim3(256), 0,
                         stream, P, FR, ws, dbg, level);
   if (v.rows == 1 && v.cpl == 4)
-    return timed_launch(timer, name, match_level_kernel<QuadMatcher<4>, 4>, dim3(grid), dim3(256), 0,
+    return timed_launch(timer, name, match_level_kernel<dev::QuadMatcher<4>, 4>, dim3(grid), dim3(256), 0,
                         stream, P, FR, ws, dbg, level);
   return hipErrorNotSupported;   // rejected by the argument checks before any launch
 }
@@ -431,22 +456,17 @@ static bool launch_pair(const MatchParamsDev& P, const FramesDev& FR, const Matc
 #define OCSR_PAIR2(FM, FRW, FCP, FPS, CCP)                                                  \
   if (f.rows == FRW && f.cpl == FCP && f.passes == FPS && c.rows == 2 && c.cpl == CCP) {    \
     if (launch)                                                                          \
-      timed_launch(timer, "match", match_pair2_kernel<FM, HalfMatcher<CCP>, 4>, dim3(grid),  \
+      timed_launch(timer, "match", match_pair2_kernel<FM, dev::HalfMatcher<CCP>, 4>, dim3(grid),  \
                    dim3(256), 0, stream, P, FR, ws, dbg);                                 \
     return true;                                                                         \
   }
-  OCSR_PAIR2(TiledMatcher<4 COMMA 4 COMMA 2 COMMA 1>, 4, 2, 1, 2)
-  OCSR_PAIR2(TiledMatcher<4 COMMA 4 COMMA 2 COMMA 1>, 4, 2, 1, 3)
-  OCSR_PAIR2(TiledMatcher<4 COMMA 4 COMMA 2 COMMA 1>, 4, 2, 1, 4)
-  OCSR_PAIR2(HalfMatcher<1>, 2, 1, 1, 3)
-  OCSR_PAIR2(HalfMatcher<2>, 2, 2, 1, 3)
-  OCSR_PAIR2(HalfMatcher<2>, 2, 2, 1, 4)
-  OCSR_PAIR2(HalfMatcher<3>, 2, 3, 1, 3)
-  OCSR_PAIR2(QuadMatcher<2>, 1, 2, 1, 2)
-  OCSR_PAIR2(QuadMatcher<2>, 1, 2, 1, 3)
-  OCSR_PAIR2(QuadMatcher<2>, 1, 2, 1, 4)
-  OCSR_PAIR2(QuadMatcher<4>, 1, 4, 1, 3)
-  OCSR_PAIR2(QuadMatcher<4>, 1, 4, 1, 4)
+  OCSR_PAIR2(dev::TiledMatcher<4 COMMA 4 COMMA 2 COMMA 1>, 4, 2, 1, 2)
+  OCSR_PAIR2(dev::TiledMatcher<4 COMMA 4 COMMA 2 COMMA 1>, 4, 2, 1, 3)
+  OCSR_PAIR2(dev::TiledMatcher<4 COMMA 4 COMMA 2 COMMA 1>, 4, 2, 1, 4)
+  OCSR_PAIR2(dev::HalfMatcher<1>, 2, 1, 1, 3)
+  OCSR_PAIR2(dev::HalfMatcher<2>, 2, 2, 1, 3)
+  OCSR_PAIR2(dev::HalfMatcher<2>, 2, 2, 1, 4)
+  OCSR_PAIR2(dev::HalfMatcher<3>, 2, 3, 1, 3)
 #undef OCSR_PAIR2
   return false;
 }
@@ -483,6 +503,43 @@ hipError_t launch_frame_census(const MatchParamsDev& P, const FramesDev& FR,
                                      : frame_census_kernel<-1, -1>;
   return timed_launch(timer, "census", kernel, grid, block, 0, stream, P, FR, boxes, ws, sx, sy,
                       sentinel, n_census_tiles, listed);
+}
+
+template <int SX, int SY>
+static int census_list_occupancy() {
+  static const int occ = [] {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, census_list_kernel<SX, SY>, 256, 0) != hipSuccess)
+      n = 1;
+    return n > 0 ? n : 1;
+  }();
+  return occ;
+}
+
+hipError_t launch_plan_and_census(const MatchParamsDev& P, const FramesDev& FR,
+                                  const ocsr_box* boxes, const MatchWs& ws, int sx, int sy,
+                                  int sentinel, int n_cu, hipStream_t stream,
+                                  const LaunchTimer* timer) {
+  int n_tiles = 0;
+  for (int f = 0; f < FR.n; ++f) {
+    const int t = 2 * (FR.f[f].tiles0 + FR.f[f].tiles1);
+    if (t > 32 * kFrameTileWords) return hipErrorNotSupported;
+    n_tiles += t;
+  }
+  const bool w34 = sx == 3 && sy == 4, w22 = sx == 2 && sy == 2, w43 = sx == 4 && sy == 3;
+  const int occ = w34 ? census_list_occupancy<3, 4>() : w22 ? census_list_occupancy<2, 2>()
+                  : w43 ? census_list_occupancy<4, 3>() : census_list_occupancy<-1, -1>();
+  // lists pay off once every persistent workgroup has several tiles to consider (a
+  // 1080p frame's 2550 tiles run faster one workgroup per tile, a 16-frame batch's
+  // 45600 listed)
+  if (8 * std::max(1, n_cu) * occ > n_tiles) return hipErrorNotSupported;
+  hipError_t e = timed_launch(timer, "plan", plan_tiles_kernel, dim3(FR.n), dim3(256), 0, stream, P,
+                              FR, boxes, ws);
+  if (e != hipSuccess) return e;
+  auto kernel = w34 ? census_list_kernel<3, 4> : w22 ? census_list_kernel<2, 2>
+                : w43 ? census_list_kernel<4, 3> : census_list_kernel<-1, -1>;
+  return timed_launch(timer, "census", kernel, dim3(std::max(1, n_cu) * occ), dim3(256), 0, stream,
+                      P, FR, boxes, ws, sx, sy, sentinel);
 }
 
 hipError_t launch_match(const MatchParamsDev& P, const FramesDev& FR, const ocsr_box* boxes,

@@ -39,6 +39,9 @@ constexpr int kCensusTileY = 32;
 // and tiles a workgroup lists at a time
 constexpr int kCensusListWords = 2048;
 constexpr int kCensusListCap = 256;
+// plan step of whole-frame calls: the census tiles of one frame it can list (bitmap
+// words in LDS); frames with more tiles take the per-tile census
+constexpr int kFrameTileWords = 4096;
 
 hipError_t launch_census(const CensusJobsDev& jobs, int total_tiles, int sx, int sy,
                          int sentinel, hipStream_t stream);
@@ -110,7 +113,9 @@ struct FrameDev {
   const uint8_t* imgR;
   int32_t W, H, pitch;             // full-resolution image size and pitch (bytes)
   int32_t box_off, n_boxes;        // the frame's boxes: [box_off, box_off + n_boxes)
-  int32_t tile_begin;              // fused call: first census tile item of the frame
+  int32_t tile_begin;              // first census tile of the frame in the call's numbering
+  int32_t* tile_list;              // whole-frame calls: the frame's tiles to make (frame-local
+                                   // numbers), written by the plan step
   int32_t tiles0_x, tiles0, tiles1_x, tiles1;   // census tiles per view at levels 0 / 1
 };
 
@@ -145,11 +150,11 @@ constexpr int kMaxBlocksPerWave = 8;
 
 // per-frame counters: blocks numbered, block end of the matched boxes, work items of
 // the far and close levels
-enum { FC_NUMBERED = 0, FC_MATCHED = 1, FC_FAR_ITEMS = 2, FC_CLOSE_ITEMS = 3, FC_N = 8 };
+enum { FC_NUMBERED = 0, FC_MATCHED = 1, FC_FAR_ITEMS = 2, FC_CLOSE_ITEMS = 3, FC_TILES = 4, FC_N = 8 };
 // call-wide counters: the timeout flag, and the arrival slots of the fused launch's two
 // grid barriers (arrivals spread over kBarSlots counters to keep atomics uncontended)
 constexpr int kBarSlots = 8;
-enum { GC_TIMEOUT = 0, GC_BAR0 = 8, GC_BAR1 = 16, GC_N = 24 };
+enum { GC_TIMEOUT = 0, GC_BAR0 = 8, GC_BAR1 = 16, GC_BAR2 = 24, GC_N = 32 };
 
 // A work item as the plan writes it: the box, the item's first block and the box's
 // block geometry, so that a matching workgroup reads one record (one cache line) and
@@ -245,6 +250,15 @@ hipError_t launch_frame_census(const MatchParamsDev& p, const FramesDev& fr,
                                int sentinel, int n_census_tiles, int n_cu, bool use_list,
                                hipStream_t stream, const LaunchTimer* timer);
 
+// Plan of every frame of a whole-frame call, with the list of the census tiles its boxes'
+// searches read (one workgroup per frame), then the census of the listed tiles by
+// persistent workgroups. Returns hipErrorNotSupported (nothing launched) when a frame has
+// more tiles than the plan step can list.
+hipError_t launch_plan_and_census(const MatchParamsDev& p, const FramesDev& fr,
+                                  const ocsr_box* boxes, const MatchWs& ws, int sx, int sy,
+                                  int sentinel, int n_cu, hipStream_t stream,
+                                  const LaunchTimer* timer);
+
 // Multi-launch matching: the plan (unless plan_done), one launch per level that matches
 // the level's blocks, then one aggregation workgroup per box.
 hipError_t launch_match(const MatchParamsDev& p, const FramesDev& fr, const ocsr_box* boxes,
@@ -260,7 +274,7 @@ hipError_t launch_fused(const MatchParamsDev& p, const FramesDev& fr, const ocsr
                         const MatchWs& ws, ocsr_box_result* out, int sx, int sy, int sentinel,
                         int n_census_tiles, int n_cu, int wgs_per_cu, hipStream_t stream,
                         const LaunchTimer* timer);
-bool fused_available(const MatchParamsDev& p, int sx, int sy);
+bool fused_available(const MatchParamsDev& p, int sx, int sy, int n_census_tiles);
 
 // Dense counterpart: left-view and right-view winner-take-all over [dmin, dmax] of the
 // (2 radius + 1)^2 window sums of Hamming costs, then the left/right check. d_left and

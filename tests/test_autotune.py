@@ -28,14 +28,18 @@ def test_variant_candidates_cover_the_shape(built):
         cands = ocsr.variant_candidates(bw, bh, nd)
         assert cands, (bw, bh, nd)
         for rows, cpl, passes in cands:
-            if rows == 1:      # four blocks of up to 4 x 4 per wave, 16 candidate groups
+            if rows == 0:      # the generic kernel: any block of up to 64 points
+                assert bw * bh <= 64 and 64 * cpl >= nd and passes == 1
+            elif rows == 1:    # four blocks of up to 4 x 4 per wave, 16 candidate groups
                 assert bw <= 4 and bh <= 4 and 16 * cpl >= nd and passes == 1
             elif rows == 2:    # two row halves of an up to 8 x 8 block, 32 candidate groups
                 assert bw <= 8 and bh <= 8 and 32 * cpl >= nd and passes == 1
             else:
                 assert rows in (4, 8) and bh <= rows and bw <= rows
                 assert (64 // rows) * cpl * passes >= nd
-    # nothing covers blocks wider than 8 or more than 256 candidates
+    # blocks wider than 8 (up to 64 points) run only in the generic kernel; nothing
+    # covers more than 256 candidates
+    assert ocsr.variant_candidates(16, 4, 32) == [(0, 4, 1)]
     assert ocsr.variant_candidates(9, 8, 32) == []
     assert ocsr.variant_candidates(8, 8, 257) == []
     # 4x4 blocks can also run in the 8-row kernels

@@ -111,11 +111,10 @@ VARIANTS = {
 }
 
 
-# Variants whose blocks are not TILED (GRID mode): the kernel serving them is switched off
-# after a device memory fault in its work-queue form whose cause is not yet shown; the
-# library rejects them with OCSR_E_UNSUPPORTED (checked below without launching anything).
-NOT_ENABLED = {"grid_far", "grid_both_s3"}
-SKIP_REASON = "GRID-mode kernel disabled after an unexplained device fault (see DESIGN.md)"
+# GRID-mode variants (the paper's single grid-sampled far block) run in the generic
+# per-candidate kernel.
+NOT_ENABLED: set = set()
+SKIP_REASON = ""
 
 
 def _params(v):
@@ -280,12 +279,30 @@ def test_frame_degenerate_images(lib, orc, shape):
     assert_results_match(got, want)
 
 
-def test_grid_mode_rejected(lib):
-    """GRID-mode paths are refused before anything is enqueued."""
-    p = _params("grid_far")
+def test_grid_mode_with_vertical_range_rejected(lib):
+    """A vertical range needs TILED blocks of at most 8 x 8: a GRID path with one is
+    refused before anything is enqueued."""
+    p = dict(_params("grid_far"), dy_min=-1, dy_max=1)
     img = torch.zeros((64, 96), dtype=torch.uint8, device=DEV)
     g = lib.census_many([img, img, img, img], [1, 1, 2, 2])
     boxes = torch.tensor([[10, 10, 30, 30, 1]], dtype=torch.int32, device=DEV)
     with pytest.raises(lib.OcsrError) as e:
         lib.match_boxes(*g, boxes, p)
     assert e.value.code == lib.E_UNSUPPORTED
+
+
+def test_grid_far_box_config_scene(lib, orc):
+    """The paper's far path on the realistic 1080p frame: every far box is one GRID block
+    of 8 x 8 grid-sampled points (Sec. 4.3.4), the close boxes keep 8 x 8 tiles."""
+    sc = synth.scene_realistic()
+    p = synth.params_for(2)
+    p["far"] = dict(mode=1, bw=4, bh=4, n_side=8, dmin=0, dmax=31)
+    p["agg_mode"] = 0
+    _, (res, blk, cf, cb, n) = orc.run_scene(sc.left, sc.right, p, sc.boxes, debug=True)
+    g = _gpu_levels(lib, sc.left, sc.right, p)
+    out, extra = lib.match_boxes(*g, _cuda(sc.boxes), p, debug=True, cap_blocks=max(n, 1))
+    got = lib.results_to_numpy(out)
+    assert_results_match(got, res)
+    _check_debug(lib, extra, blk, cf, cb, n)
+    far = (blk["level_scale"] == 1)
+    assert far.sum() >= 15 and (res["n_blocks"][:32][res["reason"][:32] == 0] >= 1).all()
