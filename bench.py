@@ -46,6 +46,12 @@ def parse():
                     help="seconds of each CPU-oracle leg (one thread, all threads)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (library defaults)")
+    ap.add_argument("--tune-table", default="", metavar="PATH",
+                    help="load the autotuner's table from PATH when it exists (no tuning), else "
+                         "tune and save the table there")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="time only the headline batch (no untuned, per-frame-call, one-launch or "
+                         "graph comparison and no other section): the command to profile")
     ap.add_argument("--serve-requests", type=int, default=10000,
                     help="requests of the serving section at 120/s (0 skips it)")
     ap.add_argument("--serve-pool", type=int, default=32,
@@ -172,13 +178,11 @@ def measured_traffic(kernel, workload):
     measurement (profiles/traffic.json), or None when there is none or the kernel's
     sources changed since it was taken."""
     from paper_2604_07980_amd import profiling
-    key = {"census": "census", "match": "match", "match_close": "match",
-           "match_far": "match", "aggregate": "aggregate"}.get(kernel)
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "traffic.json")
-    if key is None or not os.path.exists(path):
+    if kernel not in profiling.KERNEL_SOURCES or not os.path.exists(path):
         return None
     entry = json.load(open(path)).get(workload, {}).get(kernel)
-    if not entry or entry.get("source_sha256") != profiling.source_hash(key):
+    if not entry or entry.get("source_sha256") != profiling.source_hash(kernel):
         return None
     return round(entry["fetch_bytes"] + entry["write_bytes"])
 
@@ -287,13 +291,18 @@ def batch_workload(ocsr, scenes, args):
         for (L, R), b, o in zip(imgs, fboxes, outs_f):
             ocsr.range_frame(L, R, b, p, workspace=ws_f, out=o)
 
-    ms_untuned = timed(batch, max(10, args.steps // 10), 3)
+    ms_untuned = None if args.headline_only else timed(batch, max(10, args.steps // 10), 3)
     table = None
-    if not args.no_tune:
+    if args.tune_table and os.path.exists(args.tune_table):
+        table = autotune.load(args.tune_table)
+        autotune.apply(table)
+    elif not args.no_tune:
         def run_batch():
             batch()
             return out_b
         table = autotune.tune(run_batch, p, reps=5, warmup=2)
+        if args.tune_table:
+            autotune.save(table, args.tune_table)
     ref = None
     if args.fused:
         batch()
@@ -324,6 +333,21 @@ def batch_workload(ocsr, scenes, args):
            "fused": census_ops + costs * MATCH_OPS_PER_COST}
     price(kern, ops)
 
+    res = {
+        "workload": "batch_16x1920x1200: 16 uint8 stereo pairs, min(128, Poisson(40)) boxes per "
+                    "frame (log-uniform 12..512 px, overlaps occlude), far 4x4 blocks d 0..31 at "
+                    "s=1, close 8x8 blocks d 0..191 at s=2, census 7x9 on the tiles the searches "
+                    "read, trimmed median; one ocsr_range_batch call per step",
+        "frames": BATCH_FRAMES, "boxes": int(boxes.shape[0]), "blocks": sum(w["blocks"] for w in work),
+        "costs_per_batch": costs, "costs_far": costs_far, "block_evals_per_batch": evals,
+        "census_level_px": census_px, "census_level_px_all_tiles": census_px_full,
+    }
+    tuned = None if table is None else {"variants": table.variants,
+                                         "blocks_per_wave": table.blocks_per_wave,
+                                         "match_wgs_per_cu": table.match_wgs_per_cu}
+    if args.headline_only:
+        return p, res, {"autotune": tuned, "latency_ms_per_batch": lat_batch}, ms, kern
+
     # the same batch against 16 per-frame calls, the one-launch form and a replayed graph
     ms_frames = timed(per_frame, max(10, args.steps // 10), 3)
     identical = bool(torch.equal(out_b, torch.cat(outs_f)))
@@ -343,20 +367,9 @@ def batch_workload(ocsr, scenes, args):
     ocsr.set_graph(False)
     if table is not None:
         autotune.reset(p)
-    res = {
-        "workload": "batch_16x1920x1200: 16 uint8 stereo pairs, min(128, Poisson(40)) boxes per "
-                    "frame (log-uniform 12..512 px, overlaps occlude), far 4x4 blocks d 0..31 at "
-                    "s=1, close 8x8 blocks d 0..191 at s=2, census 7x9 on the tiles the searches "
-                    "read, trimmed median; one ocsr_range_batch call per step",
-        "frames": BATCH_FRAMES, "boxes": int(boxes.shape[0]), "blocks": sum(w["blocks"] for w in work),
-        "costs_per_batch": costs, "costs_far": costs_far, "block_evals_per_batch": evals,
-        "census_level_px": census_px, "census_level_px_all_tiles": census_px_full,
-    }
     details = {
         "ms_per_batch_untuned": round(ms_untuned, 4),
-        "autotune": None if table is None else {"variants": table.variants,
-                                                 "blocks_per_wave": table.blocks_per_wave,
-                                                 "match_wgs_per_cu": table.match_wgs_per_cu},
+        "autotune": tuned,
         "latency_ms_per_batch": lat_batch,
         "ms_16_frame_calls": round(ms_frames, 4),
         "speedup_vs_16_calls": round(ms_frames / ms, 3),
@@ -673,11 +686,14 @@ def main():
         "config": bres,
         "block_evals_per_s": round(bres["block_evals_per_batch"] / (ms * 1e-3), 1),
         "latency_ms": {"per_batch": bdetails["latency_ms_per_batch"],
-                       "per_frame_call": bdetails["per_frame_call_latency_ms"]},
+                       "per_frame_call": bdetails.get("per_frame_call_latency_ms")},
         "kernels": kern,
         "roofline": roofline,
         "batch": bdetails,
     }
+    if args.headline_only:
+        print(json.dumps(res), flush=True)
+        return
     if args.frame_steps > 0:
         tiny, _ = frame_section(ocsr, synth.scene_tiny(), synth.params_for(1),
                                 "tiny_640x480: 4 boxes, 8x8 blocks d 0..63 at s=1, segment median",
