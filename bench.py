@@ -300,7 +300,7 @@ def batch_workload(ocsr, scenes, args):
         def run_batch():
             batch()
             return out_b
-        table = autotune.tune(run_batch, p, reps=5, warmup=2)
+        table = autotune.tune(run_batch, p, reps=15, warmup=3)
         if args.tune_table:
             autotune.save(table, args.tune_table)
     ref = None
@@ -344,7 +344,9 @@ def batch_workload(ocsr, scenes, args):
     }
     tuned = None if table is None else {"variants": table.variants,
                                          "blocks_per_wave": table.blocks_per_wave,
-                                         "match_wgs_per_cu": table.match_wgs_per_cu}
+                                         "match_wgs_per_cu": table.match_wgs_per_cu,
+                                         "level_launches": table.level_launches,
+                                         "timings_ms": table.timings_ms}
     if args.headline_only:
         return p, res, {"autotune": tuned, "latency_ms_per_batch": lat_batch}, ms, kern
 

@@ -505,6 +505,12 @@ int32_t ocsr_rect_filter_update(ocsr_rect_filter* f, const int32_t* counts, int3
  * and every call with 0, launch one workgroup per tile, which makes its tile or leaves.
  * Results and the tiles made are the same either way. */
 #define OCSR_OPTION_CENSUS_TILE_LIST 7
+/* OCSR_OPTION_LEVEL_LAUNCHES: how the blocks of the two levels are matched. 0 (default):
+ * one launch for both levels in calls of one frame when a kernel for the pair of chosen
+ * variants is built, one launch per level otherwise; 1: always one launch per level;
+ * 2: one launch for both levels whenever such a kernel is built. Results are identical
+ * either way. */
+#define OCSR_OPTION_LEVEL_LAUNCHES 8
 int32_t ocsr_ctx_set_option(ocsr_ctx* ctx, int32_t option, int32_t value);
 
 /* ------------------------------------------------------------------------------ */
@@ -532,8 +538,8 @@ int32_t ocsr_ctx_set_option(ocsr_ctx* ctx, int32_t option, int32_t value);
 int32_t ocsr_variant_candidates(int32_t bw, int32_t bh, int32_t n_candidates, int32_t* rows,
                                 int32_t* cpl, int32_t* passes, int32_t cap);
 /* Chooses the variant for paths of bw x bh blocks and n_candidates level candidates in
- * this context (rows == 0 restores the default). OCSR_E_INVALID if the variant does not
- * cover such a path. */
+ * this context ((rows, cpl, passes) == (0, 0, 0) restores the default; (0, 4, 1) is the
+ * generic kernel). OCSR_E_INVALID if the variant does not cover such a path. */
 int32_t ocsr_ctx_set_variant(ocsr_ctx* ctx, int32_t bw, int32_t bh, int32_t n_candidates,
                              int32_t rows, int32_t cpl, int32_t passes);
 

@@ -1,9 +1,11 @@
 """Autotuner of the matching launches: kernel variant per path shape, blocks per wave
-and grid size, measured on the caller's own workload and kept in a JSON table.
+grid size and whether both levels share one launch, measured on the caller's own
+workload and kept in a JSON table.
 
 The register-blocked matching kernel comes in variants (rows of a block per wave,
 candidates per lane) that all compute the same costs; blocks per wave and the grid size
-only change how work items are dealt. None of them changes a result, so the tuner times
+only change how work items are dealt, and a shared launch only how they are launched.
+None of them changes a result, so the tuner times
 each choice on a real workload, requires its output to equal the default's bit for bit,
 and keeps the fastest. A table is tied to the device architecture it was measured on.
 
@@ -30,6 +32,7 @@ class Table:
     variants: dict = field(default_factory=dict)   # "bw x bh / nd" -> [rows, cpl, passes]
     blocks_per_wave: int = DEFAULT_BLOCKS_PER_WAVE
     match_wgs_per_cu: int = DEFAULT_MATCH_WGS_PER_CU
+    level_launches: int = 0                          # OPTION_LEVEL_LAUNCHES
     timings_ms: dict = field(default_factory=dict)  # choice -> measured time
 
 
@@ -83,6 +86,7 @@ def apply(table: Table, device: int | None = None) -> None:
         ocsr.set_variant(bw, bh, int(nd), rows, cpl, passes, device)
     ocsr.set_option(ocsr.OPTION_BLOCKS_PER_WAVE, table.blocks_per_wave, device)
     ocsr.set_option(ocsr.OPTION_MATCH_WGS_PER_CU, table.match_wgs_per_cu, device)
+    ocsr.set_option(ocsr.OPTION_LEVEL_LAUNCHES, table.level_launches, device)
 
 
 def reset(params: dict, device: int | None = None) -> None:
@@ -91,18 +95,21 @@ def reset(params: dict, device: int | None = None) -> None:
         ocsr.set_variant(bw, bh, nd, 0, 0, 0, device)
     ocsr.set_option(ocsr.OPTION_BLOCKS_PER_WAVE, DEFAULT_BLOCKS_PER_WAVE, device)
     ocsr.set_option(ocsr.OPTION_MATCH_WGS_PER_CU, DEFAULT_MATCH_WGS_PER_CU, device)
+    ocsr.set_option(ocsr.OPTION_LEVEL_LAUNCHES, 0, device)
 
 
 def tune(run, params: dict, reps: int = 20, warmup: int = 3,
          blocks_per_wave=BLOCKS_PER_WAVE, match_wgs_per_cu=MATCH_WGS_PER_CU,
-         device: int | None = None) -> Table:
+         device: int | None = None, rounds: int = 2) -> Table:
     """Tunes the matching launches for the workload `run` (a callable that submits one
     call and returns its result tensor) with parameters `params`.
 
     Coordinate descent: the variant of each path shape in turn (the others at their
-    current best), then blocks per wave, then the grid. Every choice's output must equal
-    the default configuration's exactly; a choice that differs raises, since it would be
-    a library defect. The chosen configuration is left installed."""
+    current best), then blocks per wave, then the grid, then one or two matching
+    launches; `rounds` passes over all of them, each starting from the last's choices.
+    Every choice's output must equal the default configuration's exactly; a choice that
+    differs raises, since it would be a library defect. The chosen configuration is left
+    installed."""
     reset(params, device)
     ref = _snapshot(run())
     table = Table(arch=_arch())
@@ -115,34 +122,44 @@ def tune(run, params: dict, reps: int = 20, warmup: int = 3,
         table.timings_ms[label] = round(ms, 5)
         return ms
 
-    for bw, bh, nd in path_shapes(params):
+    for rnd in range(rounds):
+        for bw, bh, nd in path_shapes(params):
+            best = None
+            for rows, cpl, passes in ocsr.variant_candidates(bw, bh, nd):
+                ocsr.set_variant(bw, bh, nd, rows, cpl, passes, device)
+                ms = measure(f"round {rnd} variant {shape_key(bw, bh, nd)} rows={rows} cpl={cpl} passes={passes}")
+                if best is None or ms < best[0]:
+                    best = (ms, rows, cpl, passes)
+            if best is not None:
+                ocsr.set_variant(bw, bh, nd, best[1], best[2], best[3], device)
+                table.variants[shape_key(bw, bh, nd)] = [best[1], best[2], best[3]]
+
         best = None
-        for rows, cpl, passes in ocsr.variant_candidates(bw, bh, nd):
-            ocsr.set_variant(bw, bh, nd, rows, cpl, passes, device)
-            ms = measure(f"variant {shape_key(bw, bh, nd)} rows={rows} cpl={cpl} passes={passes}")
+        for bpw in blocks_per_wave:
+            ocsr.set_option(ocsr.OPTION_BLOCKS_PER_WAVE, bpw, device)
+            ms = measure(f"round {rnd} blocks_per_wave={bpw}")
             if best is None or ms < best[0]:
-                best = (ms, rows, cpl, passes)
-        if best is not None:
-            ocsr.set_variant(bw, bh, nd, best[1], best[2], best[3], device)
-            table.variants[shape_key(bw, bh, nd)] = [best[1], best[2], best[3]]
+                best = (ms, bpw)
+        table.blocks_per_wave = best[1]
+        ocsr.set_option(ocsr.OPTION_BLOCKS_PER_WAVE, table.blocks_per_wave, device)
 
-    best = None
-    for bpw in blocks_per_wave:
-        ocsr.set_option(ocsr.OPTION_BLOCKS_PER_WAVE, bpw, device)
-        ms = measure(f"blocks_per_wave={bpw}")
-        if best is None or ms < best[0]:
-            best = (ms, bpw)
-    table.blocks_per_wave = best[1]
-    ocsr.set_option(ocsr.OPTION_BLOCKS_PER_WAVE, table.blocks_per_wave, device)
+        best = None
+        for g in match_wgs_per_cu:
+            ocsr.set_option(ocsr.OPTION_MATCH_WGS_PER_CU, g, device)
+            ms = measure(f"round {rnd} match_wgs_per_cu={g}")
+            if best is None or ms < best[0]:
+                best = (ms, g)
+        table.match_wgs_per_cu = best[1]
+        ocsr.set_option(ocsr.OPTION_MATCH_WGS_PER_CU, table.match_wgs_per_cu, device)
 
-    best = None
-    for g in match_wgs_per_cu:
-        ocsr.set_option(ocsr.OPTION_MATCH_WGS_PER_CU, g, device)
-        ms = measure(f"match_wgs_per_cu={g}")
-        if best is None or ms < best[0]:
-            best = (ms, g)
-    table.match_wgs_per_cu = best[1]
-    ocsr.set_option(ocsr.OPTION_MATCH_WGS_PER_CU, table.match_wgs_per_cu, device)
+        best = None
+        for mode in (0, 1, 2):
+            ocsr.set_option(ocsr.OPTION_LEVEL_LAUNCHES, mode, device)
+            ms = measure(f"round {rnd} level_launches={mode}")
+            if best is None or ms < best[0]:
+                best = (ms, mode)
+        table.level_launches = best[1]
+        ocsr.set_option(ocsr.OPTION_LEVEL_LAUNCHES, table.level_launches, device)
     return table
 
 
@@ -150,6 +167,7 @@ def to_json(table: Table) -> str:
     return json.dumps({"arch": table.arch, "variants": table.variants,
                        "blocks_per_wave": table.blocks_per_wave,
                        "match_wgs_per_cu": table.match_wgs_per_cu,
+                       "level_launches": table.level_launches,
                        "timings_ms": table.timings_ms}, indent=1, sort_keys=True)
 
 
@@ -158,13 +176,14 @@ def from_json(text: str) -> Table:
     t = Table(arch=d["arch"], variants={k: [int(x) for x in v] for k, v in d["variants"].items()},
               blocks_per_wave=int(d["blocks_per_wave"]),
               match_wgs_per_cu=int(d["match_wgs_per_cu"]),
+              level_launches=int(d.get("level_launches", 0)),
               timings_ms=dict(d.get("timings_ms", {})))
     for key, v in t.variants.items():
         bw_bh, nd = key.split("/")
         bw, bh = (int(x) for x in bw_bh.split("x"))
         if len(v) != 3 or tuple(v) not in ocsr.variant_candidates(bw, bh, int(nd)):
             raise ValueError(f"table entry {key}: no kernel {v} (rows, cpl, passes) covers it")
-    if not 1 <= t.blocks_per_wave <= 8 or not 1 <= t.match_wgs_per_cu <= 64:
+    if not 1 <= t.blocks_per_wave <= 8 or not 1 <= t.match_wgs_per_cu <= 64 or t.level_launches not in (0, 1, 2):
         raise ValueError("table launch settings out of range")
     return t
 

@@ -48,6 +48,7 @@ struct ocsr_ctx {
   int blocks_per_wave = 1;
   int full_census = 0;
   int census_list = 1;
+  int level_launches = 0;   // OCSR_OPTION_LEVEL_LAUNCHES
   struct Graph {
     std::string key;
     hipGraphExec_t exec;
@@ -469,7 +470,7 @@ int32_t range_frames(ocsr_ctx* ctx, const ocsr_frame* frames, int n_frames,
       e = launch_frame_census(P, FR, boxes, mws, fp->sx, fp->sy, sentinel, tiles, ctx->n_cu, false, s, tp);
     if (e != hipSuccess) return hip_fail(e, "census launch");
     e = launch_match(P, FR, boxes, mws, out, make_debug(nullptr), true,
-                     std::max(1, ctx->n_cu * ctx->match_wgs_per_cu), s, tp);
+                     std::max(1, ctx->n_cu * ctx->match_wgs_per_cu), ctx->level_launches, s, tp);
     return e == hipSuccess ? OCSR_OK : hip_fail(e, "match launch");
   };
   if (ctx->use_graph) {
@@ -485,8 +486,8 @@ int32_t range_frames(ocsr_ctx* ctx, const ocsr_frame* frames, int n_frames,
     put(&ws, sizeof(ws));
     put(&out, sizeof(out));
     put(&P, sizeof(P));
-    const int opts[5] = {fused ? 1 : 0, ctx->wgs_per_cu, ctx->n_cu, ctx->match_wgs_per_cu,
-                         ctx->census_list};
+    const int opts[6] = {fused ? 1 : 0, ctx->wgs_per_cu, ctx->n_cu, ctx->match_wgs_per_cu,
+                         ctx->census_list, ctx->level_launches};
     put(opts, sizeof(opts));
     return graph_launch(ctx, key, enqueue, stream);
   }
@@ -548,7 +549,8 @@ int32_t match_boxes_impl(ocsr_ctx* ctx, const ocsr_level* lv0, const ocsr_level*
   MatchWs mws = match_ws_carve(ws, 1, n_boxes, cap_blocks);
   LaunchTimer t = make_timer(ctx);
   hipError_t e = launch_match(P, FR, boxes, mws, out, make_debug(dbg), false,
-                              std::max(1, ctx->n_cu * ctx->match_wgs_per_cu), (hipStream_t)stream,
+                              std::max(1, ctx->n_cu * ctx->match_wgs_per_cu), ctx->level_launches,
+                              (hipStream_t)stream,
                               timed && ctx->timing ? &t : nullptr);
   if (e != hipSuccess) return hip_fail(e, "match launch");
   if (dbg && dbg->n_blocks) {
@@ -911,6 +913,10 @@ int32_t ocsr_ctx_set_option(ocsr_ctx* ctx, int32_t option, int32_t value) {
     case OCSR_OPTION_CENSUS_TILE_LIST:
       ctx->census_list = value != 0;
       return OCSR_OK;
+    case OCSR_OPTION_LEVEL_LAUNCHES:
+      if (value < 0 || value > 2) return fail(OCSR_E_INVALID, "level launches %d outside 0..2", value);
+      ctx->level_launches = value;
+      return OCSR_OK;
     case OCSR_OPTION_WAVES_PER_CU:
       if (value < 0 || value > 32) return fail(OCSR_E_INVALID, "workgroups per CU outside 0..32");
       ctx->wgs_per_cu = value;
@@ -967,7 +973,7 @@ int32_t ocsr_ctx_set_variant(ocsr_ctx* ctx, int32_t bw, int32_t bh, int32_t n_ca
                              int32_t rows, int32_t cpl, int32_t passes) {
   g_last_error.clear();
   if (!ctx) return fail(OCSR_E_INVALID, "null context");
-  if (rows == 0) {
+  if (rows == 0 && cpl == 0 && passes == 0) {   // (0, 0, 0): back to the default
     ctx->variants.erase({bw, bh, n_candidates});
     return OCSR_OK;
   }

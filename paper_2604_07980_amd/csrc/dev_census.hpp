@@ -33,35 +33,36 @@ struct CensusTile {
   static_assert(N + 1 <= 64, "window wider than a 64-bit code");
 };
 
+// One census tile: the uint8 source img (pitch bytes, W x H) at level scale s (level
+// image W/s x H/s), the level position (X0, Y0) of the tile, and the descriptor image
+// out (out_pitch words).
+struct CensusJob {
+  const uint8_t* img;
+  int W, H, pitch, s;
+  uint64_t* out;
+  int out_pitch, X0, Y0;
+};
+
 typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 
-// img: uint8 source (pitch bytes), level scale s: level image Ws x Hs = W/s x H/s.
-// (X0, Y0): level position of the tile. P: LDS of CensusTile<SX,SY>::kLdsBytes.
-// Called by all 256 threads of the workgroup.
+// P[r * LW + c] = I(c, r) | I(c, r + 1) << 16 over the tile and its halo (level
+// samples, c and r counted from the halo's corner). A position outside the level image
+// reads some valid byte of the image instead: only pixels whose window leaves the image
+// see such values, and their words are stored as 0 regardless.
+__device__ __forceinline__ int clamp_to(int v, int n) { return v < 0 ? 0 : (v < n ? v : n - 1); }
+
+// Stages tile j in P through registers. Wave w loads source rows w*RB .. w*RB + RB of
+// the tile (one more than the pair rows it writes): the row address is wave-uniform,
+// so each load is one scalar base plus the lane's unsigned column offset. All loads are
+// issued before the first is waited for. Called by all 256 threads of the workgroup.
 template <int SX, int SY>
-__device__ __forceinline__ void census_tile(const uint8_t* __restrict__ img, int W, int H,
-                                            int pitch, int s, uint64_t* __restrict__ out,
-                                            int out_pitch, int X0, int Y0, int sentinel,
-                                            uint32_t* P) {
+__device__ __forceinline__ void census_stage(const CensusJob& j, uint32_t* P) {
   using T = CensusTile<SX, SY>;
-  constexpr int LW = T::LW, PR = T::PR, WR = T::WR, N = T::N;
-  img = uniform(img);
-  out = uniform(out);
-  W = uniform(W);
-  H = uniform(H);
-  pitch = uniform(pitch);
-  s = uniform(s);
-  out_pitch = uniform(out_pitch);
-  X0 = uniform(X0);
-  Y0 = uniform(Y0);
-  const int Ws = W / s, Hs = H / s;
-  // P[r * LW + c] = I(c, r) | I(c, r + 1) << 16 over the tile and its halo. Wave w
-  // loads source rows w*RB .. w*RB + RB of the tile (one more than the pair rows it
-  // writes): the row address is wave-uniform, so each load is one scalar base plus
-  // the lane's unsigned column offset. All loads are issued before the first is waited
-  // for. A position outside the level image reads some valid byte of the image instead:
-  // only pixels whose window leaves the image see such values, and their words are
-  // stored as 0 regardless.
+  constexpr int LW = T::LW, PR = T::PR;
+  const uint8_t* img = uniform(j.img);
+  const int pitch = uniform(j.pitch), s = uniform(j.s);
+  const int X0 = uniform(j.X0), Y0 = uniform(j.Y0);
+  const int Ws = uniform(j.W) / s, Hs = uniform(j.H) / s;
   constexpr int RB = (PR + 1 + 3) / 4;
   constexpr int NPASS = (LW + 63) / 64;
   {
@@ -72,11 +73,11 @@ __device__ __forceinline__ void census_tile(const uint8_t* __restrict__ img, int
     for (int cp = 0; cp < NPASS; ++cp) {
       const int pc = lane + 64 * cp;
       const int X = X0 - SX + pc;
-      const uint32_t coff = (uint32_t)(s * (X < 0 ? 0 : (X < Ws ? X : Ws - 1)));
+      const uint32_t coff = (uint32_t)(s * clamp_to(X, Ws));
 #pragma unroll
       for (int k = 0; k <= RB; ++k) {
         const int Y = Y0 - SY + wave * RB + k;
-        const int Yc = Y < 0 ? 0 : (Y < Hs ? Y : Hs - 1);
+        const int Yc = clamp_to(Y, Hs);
         const uint8_t* rp = img + (size_t)(s * Yc) * pitch;
         px[cp][k] = rp[coff];
       }
@@ -91,16 +92,23 @@ __device__ __forceinline__ void census_tile(const uint8_t* __restrict__ img, int
       }
     }
   }
-  __syncthreads();
+}
 
+// The census words of tile j from P (staged by census_stage), after a barrier. Called
+// by all 256 threads of the workgroup.
+template <int SX, int SY>
+__device__ __forceinline__ void census_compute(const CensusJob& j, int sentinel, const uint32_t* P) {
+  using T = CensusTile<SX, SY>;
+  constexpr int LW = T::LW, WR = T::WR, N = T::N;
+  uint64_t* out = uniform(j.out);
+  const int s = uniform(j.s), out_pitch = uniform(j.out_pitch);
+  const int X0 = uniform(j.X0), Y0 = uniform(j.Y0);
+  const int Ws = uniform(j.W) / s, Hs = uniform(j.H) / s;
   const int lane = threadIdx.x & 63;
   const int r0 = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) * kCensusRowsPerLane;
-  uint32_t v[2 * SX + 1][WR];
-#pragma unroll
-  for (int i = 0; i < 2 * SX + 1; ++i)
-#pragma unroll
-    for (int rr = 0; rr < WR; ++rr) v[i][rr] = P[(r0 + rr) * LW + lane + i];
-
+  // the lane's window words are read one window column at a time, so that only one
+  // column (WR words) is held besides the accumulators
+  const uint32_t* Pl = P + r0 * LW + lane;
   const int X = X0 + lane;
   const bool x_in = X < Ws;
   const bool x_def = X >= SX && X < Ws - SX;
@@ -113,10 +121,13 @@ __device__ __forceinline__ void census_tile(const uint8_t* __restrict__ img, int
   for (int pp = 0; pp < NP; ++pp) {
 #pragma unroll
     for (int k = 0; k < 8; ++k) acc[pp][k] = 0;
-    c2[pp] = __builtin_bit_cast(u16x2, v[SX][2 * pp + SY]);
+    c2[pp] = __builtin_bit_cast(u16x2, Pl[(2 * pp + SY) * LW + SX]);
   }
 #pragma unroll
   for (int i = 0; i < 2 * SX + 1; ++i) {
+    uint32_t v[WR];
+#pragma unroll
+    for (int rr = 0; rr < WR; ++rr) v[rr] = Pl[rr * LW + i];
 #pragma unroll
     for (int jj = 0; jj < 2 * SY + 1; ++jj) {
       const int pos = N - 1 - (i * (2 * SY + 1) + jj);   // Alg. 1 order, MSB first
@@ -126,7 +137,7 @@ __device__ __forceinline__ void census_tile(const uint8_t* __restrict__ img, int
       for (int pp = 0; pp < NP; ++pp) {
         // half = centre - neighbour: in 0..255 when the neighbour is not brighter, in
         // 0xFF01..0xFFFF when it is, so bits 8..15 of each half all equal the bit
-        d[pp] = __builtin_bit_cast(uint32_t, c2[pp] - __builtin_bit_cast(u16x2, v[i][2 * pp + jj]));
+        d[pp] = __builtin_bit_cast(uint32_t, c2[pp] - __builtin_bit_cast(u16x2, v[2 * pp + jj]));
       }
 #pragma unroll
       for (int pp = 0; pp < NP; ++pp) acc[pp][q] = (d[pp] & (0x01000100u << (pos & 7))) | acc[pp][q];
@@ -165,6 +176,19 @@ __device__ __forceinline__ void census_tile(const uint8_t* __restrict__ img, int
       (out + (size_t)YB * out_pitch)[(uint32_t)X] = def ? codeB : 0ull;
     }
   }
+}
+
+
+// One tile, staged through registers.
+template <int SX, int SY>
+__device__ __forceinline__ void census_tile(const uint8_t* __restrict__ img, int W, int H,
+                                            int pitch, int s, uint64_t* __restrict__ out,
+                                            int out_pitch, int X0, int Y0, int sentinel,
+                                            uint32_t* P) {
+  const CensusJob j{img, W, H, pitch, s, out, out_pitch, X0, Y0};
+  census_stage<SX, SY>(j, P);
+  __syncthreads();
+  census_compute<SX, SY>(j, sentinel, P);
 }
 
 // Any window: one pixel per thread per row, straight from global memory (no LDS).
@@ -232,20 +256,17 @@ __device__ __forceinline__ bool census_tile_needed(const MatchParamsDev& MP, con
 
 // Census tile c of a whole-frame call: the tiles of frame f start at
 // FR.f[f].tile_begin and run over view L then R at level 1, then L and R at level 0.
-// With `check` set and MP.full_census clear, a tile no box's search reads is skipped
-// (every wave of the workgroup takes the same decision). Window (SX, SY) > (-1, -1)
-// takes the LDS code; (-1, -1) the generic code with (sx, sy).
-template <int SX, int SY>
-__device__ __forceinline__ void frame_census_tile(const MatchParamsDev& MP, const FramesDev& FR,
-                                                  const ocsr_box* __restrict__ boxes, int c,
-                                                  int sx, int sy, int sentinel, uint32_t* P,
-                                                  bool check = true, int* verdict = nullptr) {
+// Level 1 comes first: its tiles are few and mostly read by the close boxes, so they are
+// dispatched ahead of the many, mostly skipped, tiles of level 0.
+struct FrameTile {
+  int f, level, view;
+  CensusJob job;
+};
+__device__ __forceinline__ FrameTile frame_tile(const FramesDev& FR, int c) {
   int f = 0;
   for (int k = 1; k < FR.n; ++k)
     if (c >= FR.f[k].tile_begin) f = k;
   const FrameDev& fr = FR.f[f];
-  // level 1 first: its tiles are few and mostly read by the close boxes, so they are
-  // dispatched ahead of the many, mostly skipped, tiles of level 0
   int t = c - fr.tile_begin, level = 1, tiles = fr.tiles1, tiles_x = fr.tiles1_x;
   if (t >= 2 * fr.tiles1) {
     t -= 2 * fr.tiles1;
@@ -256,28 +277,49 @@ __device__ __forceinline__ void frame_census_tile(const MatchParamsDev& MP, cons
   const int view = t / tiles;
   t -= view * tiles;
   const LevelDev& lv = fr.lv[level];
-  const uint8_t* img = view ? fr.imgR : fr.imgL;
-  uint64_t* out = (uint64_t*)(view ? lv.R : lv.L);
-  const int X0 = (t % tiles_x) * kCensusTileX, Y0 = (t / tiles_x) * kCensusTileY;
+  FrameTile ft;
+  ft.f = f;
+  ft.level = level;
+  ft.view = view;
+  ft.job = CensusJob{view ? fr.imgR : fr.imgL, fr.W, fr.H, fr.pitch, lv.scale,
+                     (uint64_t*)(view ? lv.R : lv.L), lv.pitch,
+                     (t % tiles_x) * kCensusTileX, (t / tiles_x) * kCensusTileY};
+  return ft;
+}
+
+// Makes census tile c of a whole-frame call. With `check` set and MP.full_census clear,
+// a tile no box's search reads is skipped (every wave of the workgroup takes the same
+// decision). Window (SX, SY) > (-1, -1) takes the LDS code; (-1, -1) the generic code
+// with (sx, sy).
+template <int SX, int SY>
+__device__ __forceinline__ void frame_census_tile(const MatchParamsDev& MP, const FramesDev& FR,
+                                                  const ocsr_box* __restrict__ boxes, int c,
+                                                  int sx, int sy, int sentinel, uint32_t* P,
+                                                  bool check = true, int* verdict = nullptr) {
+  const FrameTile ft = frame_tile(FR, c);
+  const CensusJob& j = ft.job;
   if (check && !MP.full_census) {
+    const FrameDev& fr = FR.f[ft.f];
     bool needed;
     if (verdict) {
       // wave 0 tests the tile and shares the verdict through LDS (verdict must not alias P)
       if (threadIdx.x < 64) {
-        const bool v = census_tile_needed(MP, fr, boxes, level, view, X0, Y0);
+        const bool v = census_tile_needed(MP, fr, boxes, ft.level, ft.view, j.X0, j.Y0);
         if (threadIdx.x == 0) *verdict = v ? 1 : 0;
       }
       __syncthreads();
       needed = *verdict != 0;
     } else {
-      needed = census_tile_needed(MP, fr, boxes, level, view, X0, Y0);
+      needed = census_tile_needed(MP, fr, boxes, ft.level, ft.view, j.X0, j.Y0);
     }
     if (!needed) return;
   }
   if constexpr (SX >= 0) {
-    census_tile<SX, SY>(img, fr.W, fr.H, fr.pitch, lv.scale, out, lv.pitch, X0, Y0, sentinel, P);
+    census_stage<SX, SY>(j, P);
+    __syncthreads();
+    census_compute<SX, SY>(j, sentinel, P);
   } else {
-    census_tile_generic(img, fr.W, fr.H, fr.pitch, lv.scale, out, lv.pitch, X0, Y0, sx, sy, sentinel);
+    census_tile_generic(j.img, j.W, j.H, j.pitch, j.s, j.out, j.out_pitch, j.X0, j.Y0, sx, sy, sentinel);
   }
 }
 

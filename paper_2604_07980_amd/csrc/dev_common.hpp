@@ -60,6 +60,25 @@ __device__ __forceinline__ Deal xcd_deal(int n) {
   return Deal{lo + (b >> 3), per, hi};
 }
 
+// Two lists dealt together (the close and the far work items of a call): each XCD
+// takes its contiguous share of list A and its share of list B and deals them, A's
+// first, over its workgroups as one local list. Every XCD thus holds an equal share of
+// each list, and a workgroup that gets no A unit takes a B unit. Local position i is
+// the unit at(i) of the concatenation [A, B].
+struct Deal2 {
+  int first, step, end;   // the workgroup's positions in its XCD's local list
+  int a_lo, a_n, b_at;    // the XCD's A share [a_lo, a_lo + a_n); its B share at b_at
+  __device__ __forceinline__ int at(int i) const { return i < a_n ? a_lo + i : b_at + (i - a_n); }
+};
+__device__ __forceinline__ Deal2 xcd_deal2(int na, int nb) {
+  const int G = gridDim.x, b = blockIdx.x;
+  if ((G & 7) != 0 || G < 8) return Deal2{b, G, na + nb, 0, na, na};
+  const int x = b & 7, per = G >> 3;
+  const int alo = (int)((long long)na * x / 8), ahi = (int)((long long)na * (x + 1) / 8);
+  const int blo = (int)((long long)nb * x / 8), bhi = (int)((long long)nb * (x + 1) / 8);
+  return Deal2{b >> 3, per, (ahi - alo) + (bhi - blo), alo, ahi - alo, na + blo};
+}
+
 // Orders the LDS traffic of one wave: every lane's earlier LDS writes are seen by the
 // wave's later LDS reads (a wave's LDS instructions complete in order).
 __device__ __forceinline__ void wave_sync() {

@@ -91,22 +91,20 @@ __global__ __launch_bounds__(256) void fused_kernel(MatchParamsDev P, FramesDev 
   __syncthreads();
   if (!timed_out) {
     void* wl = (char*)lds + wave * kWave;
-    const int n_close = mprefix[F], n_far = mprefix[2 * F] - n_close;
-    for (int part = 0; part < 2; ++part) {
-      const dev::Deal dl = dev::xcd_deal(part ? n_far : n_close);
-      for (int i = dl.first; i < dl.end; i += dl.step) {
-        const int m = i + (part ? n_close : 0);
-        int slot = 0;
-        for (int k = 1; k < 2 * F; ++k)
-          if (m >= mprefix[k]) slot = k;
-        const int f = slot < F ? slot : slot - F;
-        const FrameDev& fr = FR.f[f];
-        const int q = m - mprefix[slot];
-        const int at = q + (slot < F ? 0 : mprefix[f + 1] - mprefix[f]);
-        const ItemRec rec = ws.items[(size_t)f * ws.items_cap + at];
-        if (slot < F) CM::run_item(P, fr, ws, DebugDev{}, f, 1, rec, wave, lane, wl);
-        else FM::run_item(P, fr, ws, DebugDev{}, f, 0, rec, wave, lane, wl);
-      }
+    const int n_close = mprefix[F];
+    const dev::Deal2 dl = dev::xcd_deal2(n_close, mprefix[2 * F] - n_close);
+    for (int i = dl.first; i < dl.end; i += dl.step) {
+      const int m = dl.at(i);
+      int slot = 0;
+      for (int k = 1; k < 2 * F; ++k)
+        if (m >= mprefix[k]) slot = k;
+      const int f = slot < F ? slot : slot - F;
+      const FrameDev& fr = FR.f[f];
+      const int q = m - mprefix[slot];
+      const int at = q + (slot < F ? 0 : mprefix[f + 1] - mprefix[f]);
+      const ItemRec rec = ws.items[(size_t)f * ws.items_cap + at];
+      if (slot < F) CM::run_item(P, fr, ws, DebugDev{}, f, 1, rec, wave, lane, wl);
+      else FM::run_item(P, fr, ws, DebugDev{}, f, 0, rec, wave, lane, wl);
     }
   }
   __syncthreads();

@@ -157,8 +157,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(pair_waves<
   }
   __syncthreads();
   void* wl = (char*)lds + wave * kWave;
-  const int total = prefix[2 * F];
-  for (int m = blockIdx.x; m < total; m += gridDim.x) {
+  const int n_close = prefix[F];
+  const dev::Deal2 dl = dev::xcd_deal2(n_close, prefix[2 * F] - n_close);
+  for (int i = dl.first; i < dl.end; i += dl.step) {
+    const int m = dl.at(i);
     int slot = 0;
     for (int k = 1; k < 2 * F; ++k)
       if (m >= prefix[k]) slot = k;
@@ -201,23 +203,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES))) vo
   }
   __syncthreads();
   void* wl = (char*)lds + wave * kWave;
-  // the close items of every frame, then the far ones, each list dealt XCD by XCD
-  const int n_close = prefix[F], n_far = prefix[2 * F] - n_close;
-  for (int part = 0; part < 2; ++part) {
-    const dev::Deal dl = dev::xcd_deal(part ? n_far : n_close);
-    for (int i = dl.first; i < dl.end; i += dl.step) {
-      const int m = i + (part ? n_close : 0);
-      int slot = 0;
-      for (int k = 1; k < 2 * F; ++k)
-        if (m >= prefix[k]) slot = k;
-      const int f = slot < F ? slot : slot - F;
-      const FrameDev& fr = FR.f[f];
-      const int q = m - prefix[slot];
-      const int at = q + (slot < F ? 0 : prefix[f + 1] - prefix[f]);
-      const ItemRec r = ws.items[(size_t)f * ws.items_cap + at];
-      if (slot < F) CM::run_item(P, fr, ws, dbg, f, 1, r, wave, lane, wl);
-      else FM::run_item(P, fr, ws, dbg, f, 0, r, wave, lane, wl);
-    }
+  // the close items of every frame, then the far ones, dealt XCD by XCD as two lists
+  const int n_close = prefix[F];
+  const dev::Deal2 dl = dev::xcd_deal2(n_close, prefix[2 * F] - n_close);
+  for (int i = dl.first; i < dl.end; i += dl.step) {
+    const int m = dl.at(i);
+    int slot = 0;
+    for (int k = 1; k < 2 * F; ++k)
+      if (m >= prefix[k]) slot = k;
+    const int f = slot < F ? slot : slot - F;
+    const FrameDev& fr = FR.f[f];
+    const int q = m - prefix[slot];
+    const int at = q + (slot < F ? 0 : prefix[f + 1] - prefix[f]);
+    const ItemRec r = ws.items[(size_t)f * ws.items_cap + at];
+    if (slot < F) CM::run_item(P, fr, ws, dbg, f, 1, r, wave, lane, wl);
+    else FM::run_item(P, fr, ws, dbg, f, 0, r, wave, lane, wl);
   }
 }
 
@@ -467,6 +467,9 @@ static bool launch_pair(const MatchParamsDev& P, const FramesDev& FR, const Matc
   OCSR_PAIR2(dev::HalfMatcher<2>, 2, 2, 1, 3)
   OCSR_PAIR2(dev::HalfMatcher<2>, 2, 2, 1, 4)
   OCSR_PAIR2(dev::HalfMatcher<3>, 2, 3, 1, 3)
+  OCSR_PAIR2(dev::QuadMatcher<2>, 1, 2, 1, 3)
+  OCSR_PAIR2(dev::QuadMatcher<2>, 1, 2, 1, 4)
+  OCSR_PAIR2(dev::GenericMatcher, 0, 4, 1, 3)
 #undef OCSR_PAIR2
   return false;
 }
@@ -544,7 +547,7 @@ hipError_t launch_plan_and_census(const MatchParamsDev& P, const FramesDev& FR,
 
 hipError_t launch_match(const MatchParamsDev& P, const FramesDev& FR, const ocsr_box* boxes,
                         const MatchWs& ws, ocsr_box_result* out, const DebugDev& dbg,
-                        bool plan_done, int n_match_wgs, hipStream_t stream,
+                        bool plan_done, int n_match_wgs, int level_launches, hipStream_t stream,
                         const LaunchTimer* timer) {
   if (FR.n_boxes_total <= 0) return hipSuccess;
   hipError_t e;
@@ -575,7 +578,12 @@ hipError_t launch_match(const MatchParamsDev& P, const FramesDev& FR, const ocsr
     e = timed_launch(timer, "match", kernel, dim3(n_match_wgs), dim3(256), bytes, stream, P, FR, ws,
                      dbg, wb);
     if (e != hipSuccess) return e;
-  } else if (launch_pair(P, FR, ws, dbg, n_match_wgs, stream, nullptr, false)) {
+  } else if ((level_launches == 2 || (level_launches == 0 && FR.n == 1)) &&
+             launch_pair(P, FR, ws, dbg, n_match_wgs, stream, nullptr, false)) {
+    // one launch for both levels: in a one-frame call the far level alone cannot fill
+    // the GPU, and its blocks fill the close level's tail (whole 1080p frame: 31 against
+    // 38 us per frame); each level of a batch fills the GPU by itself, and there the
+    // larger paired kernel is slower (16 frames: 159 us against 10 + 131 us)
     e = launch_pair(P, FR, ws, dbg, n_match_wgs, stream, timer, true) ? hipGetLastError() : hipErrorNotSupported;
     if (e != hipSuccess) return e;
   } else {

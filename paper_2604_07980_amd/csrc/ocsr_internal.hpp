@@ -259,11 +259,13 @@ hipError_t launch_plan_and_census(const MatchParamsDev& p, const FramesDev& fr,
                                   int sentinel, int n_cu, hipStream_t stream,
                                   const LaunchTimer* timer);
 
-// Multi-launch matching: the plan (unless plan_done), one launch per level that matches
-// the level's blocks, then one aggregation workgroup per box.
+// Multi-launch matching: the plan (unless plan_done), the matching of both levels'
+// blocks, then one aggregation workgroup per box. level_launches (OCSR_OPTION_LEVEL_LAUNCHES)
+// decides between one launch for both levels, when a kernel for the pair of variants
+// is built, and one launch per level.
 hipError_t launch_match(const MatchParamsDev& p, const FramesDev& fr, const ocsr_box* boxes,
                         const MatchWs& ws, ocsr_box_result* out, const DebugDev& dbg,
-                        bool plan_done, int n_match_wgs, hipStream_t stream,
+                        bool plan_done, int n_match_wgs, int level_launches, hipStream_t stream,
                         const LaunchTimer* timer);
 
 // Fused path: census of every frame, planning, matching and aggregation in one

@@ -34,7 +34,7 @@ MAX_CENSUS_JOBS = 64
 DEFAULT_CAP_BLOCKS = 1 << 20
 
 OPTION_FUSED, OPTION_WAVES_PER_CU, OPTION_GRAPH, OPTION_MATCH_WGS_PER_CU, OPTION_BLOCKS_PER_WAVE = 1, 2, 3, 4, 5
-OPTION_FULL_CENSUS, OPTION_CENSUS_TILE_LIST = 6, 7
+OPTION_FULL_CENSUS, OPTION_CENSUS_TILE_LIST, OPTION_LEVEL_LAUNCHES = 6, 7, 8
 
 EXPORTS = ["ocsr_abi_version", "ocsr_last_error", "ocsr_ctx_create", "ocsr_ctx_destroy",
            "ocsr_census", "ocsr_census_many", "ocsr_match_workspace_bytes", "ocsr_match_boxes",
@@ -685,7 +685,7 @@ def variant_candidates(bw: int, bh: int, n_candidates: int) -> list[tuple[int, i
 def set_variant(bw: int, bh: int, n_candidates: int, rows: int, cpl: int, passes: int = 1,
                 device: int | None = None):
     """Use the (rows, cpl, passes) kernel for paths of bw x bh blocks and n_candidates
-    level candidates (rows = 0 restores the default)."""
+    level candidates ((0, 0, 0) restores the default; (0, 4, 1) is the generic kernel)."""
     _check(load().ocsr_ctx_set_variant(context(device), bw, bh, n_candidates, rows, cpl, passes))
 
 

@@ -54,7 +54,7 @@ def test_variant_candidates_cover_the_shape(built):
 
 def test_table_round_trip(built):
     t = autotune.Table(arch="gfx950", variants={"4x4/32": [4, 2, 1], "8x8/96": [8, 4, 3]},
-                       blocks_per_wave=2, match_wgs_per_cu=8, timings_ms={"a": 1.5})
+                       blocks_per_wave=2, match_wgs_per_cu=8, level_launches=2, timings_ms={"a": 1.5})
     back = autotune.from_json(autotune.to_json(t))
     assert back == t
 
@@ -65,6 +65,7 @@ def test_table_round_trip(built):
     '{"arch": "gfx950", "variants": {"8x8/96": [8, 12]}, "blocks_per_wave": 1, "match_wgs_per_cu": 16}',
     '{"arch": "gfx950", "variants": {}, "blocks_per_wave": 9, "match_wgs_per_cu": 16}',
     '{"arch": "gfx950", "variants": {}, "blocks_per_wave": 1, "match_wgs_per_cu": 0}',
+    '{"arch": "gfx950", "variants": {}, "blocks_per_wave": 1, "match_wgs_per_cu": 16, "level_launches": 3}',
 ])
 def test_invalid_tables_rejected(built, bad):
     with pytest.raises(ValueError):

@@ -34,9 +34,12 @@ def test_every_setting_same_results(lib, orc):
         for bw, bh, nd in autotune.path_shapes(p):
             for rows, cpl, passes in lib.variant_candidates(bw, bh, nd):
                 lib.set_variant(bw, bh, nd, rows, cpl, passes)
-                for bpw in (1, 3):
+                # one launch for both levels where a pair kernel is built, and one per level
+                for bpw, mode in ((1, 0), (3, 0), (1, 1), (1, 2)):
                     lib.set_option(lib.OPTION_BLOCKS_PER_WAVE, bpw)
+                    lib.set_option(lib.OPTION_LEVEL_LAUNCHES, mode)
                     assert_results_match(lib.results_to_numpy(run()), want)
+                lib.set_option(lib.OPTION_LEVEL_LAUNCHES, 0)
                 lib.set_variant(bw, bh, nd, 0, 0, 0)
         for g in (1, 4, 32):
             lib.set_option(lib.OPTION_MATCH_WGS_PER_CU, g)
