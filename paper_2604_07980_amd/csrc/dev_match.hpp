@@ -548,7 +548,7 @@ __device__ __forceinline__ void match_block_tiled(const MatchParamsDev& P, const
 // rows a lane reads the 8 template words and CPL + 7 strip words from LDS and forms
 // 8 CPL costs at 4 operations each; the two row halves of a candidate meet in one DPP
 // add, and the winner is a DPP wave minimum of packed (cost << 16 | index) keys. A strip
-// row is staged in 64-word chunks through a buffer resource per row (stage_half_strip).
+// row is staged in 64-word chunks through a buffer resource per row (load_half_strip).
 // ---------------------------------------------------------------------------------
 template <int CPL>
 struct Half {
@@ -571,37 +571,60 @@ __device__ __forceinline__ uint32_t wave_min_dpp(uint32_t v) {
   return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
 }
 
-// Strip rows 0 .. ny - 1 of a level image from `rows` (the block's first row), words
-// [x_first, x_first + 64 CH) of each row, into S[jj * SWP + m] for m < SWP. Each row is
-// read through a buffer resource spanning exactly that row (W words), so a word outside
-// the image, left or right, reads as 0 by the hardware's range check: a column below 0
+// Strip rows 0 .. 7 of a level image from `rows` (the block's first row), words
+// [x_first, x_first + 64 CH) of each row, for S[jj * SWP + m], m < SWP; rows at or past
+// ny (which no kept point reads) are 0. load_half_strip issues the loads and
+// store_half_strip writes the words to LDS, so that a caller can put other loads in
+// flight between the two. Each row is read through a buffer resource spanning exactly
+// that row (W words; none for rows past ny), so a word outside the image, left or right,
+// reads as 0 by the hardware's range check without a memory access: a column below 0
 // gives a byte offset that wraps past the range. The rows' resources and offsets are
-// wave-uniform (scalar instructions); lane l reads word l of each 64-word chunk at a byte
-// offset fixed for the whole strip, so the loads take no per-lane address arithmetic.
-// All loads of a lane are issued before the first store.
+// wave-uniform (scalar instructions); lane l reads word l of each 64-word chunk at a
+// byte offset fixed for the whole strip, so the loads take no per-lane address
+// arithmetic.
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+template <int CH>
+struct HalfStrip {
+  u32x2 w[8][CH];
+};
 template <int SWP, int CH>
-__device__ __forceinline__ void stage_half_strip(uint64_t* __restrict__ S, const uint64_t* __restrict__ rows,
-                                                 int pitch, int x_first, int ny, int W, int lane) {
+__device__ __forceinline__ HalfStrip<CH> load_half_strip(const uint64_t* __restrict__ rows, int pitch,
+                                                         int x_first, int ny, int W, int lane) {
+  static_assert(SWP > 64 * (CH - 1) && SWP <= 64 * CH, "the strip row ends in the last chunk");
   uint32_t voff[CH];
 #pragma unroll
   for (int c = 0; c < CH; ++c) voff[c] = (uint32_t)(x_first + 64 * c + lane) * 8u;
-  u32x2 w[8][CH];
+  HalfStrip<CH> st;
 #pragma unroll
   for (int jj = 0; jj < 8; ++jj) {
-    if (jj < ny) {
-      const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-          (void*)(rows + (size_t)jj * pitch), (short)0, W * 8, 0x00020000);
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(rows + (size_t)jj * pitch), (short)0, jj < ny ? W * 8 : 0, 0x00020000);
 #pragma unroll
-      for (int c = 0; c < CH; ++c) w[jj][c] = __builtin_amdgcn_raw_buffer_load_b64(rs, voff[c], 0, 0);
-    }
+    for (int c = 0; c < CH; ++c) st.w[jj][c] = __builtin_amdgcn_raw_buffer_load_b64(rs, voff[c], 0, 0);
   }
+  return st;
+}
+// The last chunk goes first: its lanes past the row end write their chunk-0 word, which
+// the chunk-0 stores that follow overwrite (a wave's LDS writes land in order), so no
+// lane mask is needed and no load is held back behind one.
+template <int SWP, int CH>
+__device__ __forceinline__ void store_half_strip(uint64_t* __restrict__ S, const HalfStrip<CH>& st,
+                                                 int lane) {
+  auto word = [](u32x2 v) { return ((uint64_t)v.y << 32) | v.x; };
+  if constexpr (CH == 1) {
+    if (lane < SWP) {
 #pragma unroll
-  for (int jj = 0; jj < 8; ++jj)
+      for (int jj = 0; jj < 8; ++jj) S[jj * SWP + lane] = word(st.w[jj][0]);
+    }
+  } else {
+    const int mlast = 64 * (CH - 1) + lane < SWP ? 64 * (CH - 1) + lane : lane;
 #pragma unroll
-    for (int c = 0; c < CH; ++c)
-      if (jj < ny && 64 * c + lane < SWP)
-        S[jj * SWP + 64 * c + lane] = ((uint64_t)w[jj][c].y << 32) | w[jj][c].x;
+    for (int jj = 0; jj < 8; ++jj) S[jj * SWP + mlast] = word(st.w[jj][CH - 1]);
+#pragma unroll
+    for (int jj = 0; jj < 8; ++jj)
+#pragma unroll
+      for (int c = 0; c < CH - 1; ++c) S[jj * SWP + 64 * c + lane] = word(st.w[jj][c]);
+  }
 }
 
 // One direction of the search: acc[c] = cost of strip position g CPL + c over the lane's
@@ -710,16 +733,19 @@ __device__ __forceinline__ void match_block_half(const MatchParamsDev& P, const 
   const uint64_t* __restrict__ Lb = uniform(lv.L + (size_t)Y0 * lv.pitch);
   const uint64_t* __restrict__ Rb = uniform(lv.R + (size_t)Y0 * lv.pitch);
   const int sw = nd + nx - 1;
-  // forward strip CR(X0 - dhi + m, Y0 + j) and template CL(X0 + i, Y0 + j), loads issued
-  // before the occluder scan so both are in flight together
-  stage_half_strip<SWP, CH>(S, Rb, lv.pitch, X0 - dhi, ny, W, lane);
+  // forward strip CR(X0 - dhi + m, Y0 + j) and template CL(X0 + i, Y0 + j): their loads
+  // and the occluder scan's are in flight together (one wait for all of them)
+  const HalfStrip<CH> fw = load_half_strip<SWP, CH>(Rb, lv.pitch, X0 - dhi, ny, W, lane);
+  uint64_t tw;
   {
     const int i = lane & 7, jj = lane >> 3;
     const bool ok = i < nx && jj < ny;
-    uint64_t t = Lb[ok ? (size_t)jj * lv.pitch + X0 + i : 0];
-    T[lane] = ok ? t : 0ull;
+    tw = Lb[ok ? (size_t)jj * lv.pitch + X0 + i : 0];
+    tw = ok ? tw : 0ull;
   }
   const uint64_t m8 = tiled_mask8(ws, fr.box_off, fr.n_boxes, c.k, c.g.s, X0, Y0, nx, ny, lane);
+  store_half_strip<SWP, CH>(S, fw, lane);
+  T[lane] = tw;
   const int npts = __popcll(m8);
   const bool eligible = npts > 0 && 100 * npts >= P.min_point_pct * nx * ny;
   wave_sync();
@@ -758,7 +784,7 @@ __device__ __forceinline__ void match_block_half(const MatchParamsDev& P, const 
   const float d_sub = subpixel(d_f, best, nd, ca, (int)(key >> 16), cb);
   // backward strip CL(X0 - d_f + dlo + m, Y0 + j)
   wave_sync();
-  stage_half_strip<SWP, CH>(S, Lb, lv.pitch, X0 - d_f + dlo, ny, W, lane);
+  store_half_strip<SWP, CH>(S, load_half_strip<SWP, CH>(Lb, lv.pitch, X0 - d_f + dlo, ny, W, lane), lane);
   wave_sync();
   half_costs<CPL>(T, S, g, h, full, keep, acc);
   uint32_t bkey = 0xFFFFFFFFu;
