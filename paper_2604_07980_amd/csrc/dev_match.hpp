@@ -29,13 +29,17 @@ __device__ __forceinline__ void plan_frame(const MatchParamsDev& P, const FrameD
   const int n = fr.n_boxes;
   const int W = fr.W, H = fr.H;
   int carry = 0, carry0 = 0, carry1 = 0, matched_end = 0;
+  // the next 64 boxes are loaded while the current ones are planned
+  ocsr_box next = {};
+  if (lane < n) next = boxes[fr.box_off + lane];
   for (int base = 0; base < n; base += 64) {
     const int i = base + lane;
     BoxPlan pl = {};
     BoxClip cl = {0, 0, 0, 0};
     int count = 0;
+    const ocsr_box b = next;
+    if (i + 64 < n) next = boxes[fr.box_off + i + 64];
     if (i < n) {
-      const ocsr_box b = boxes[fr.box_off + i];
       const int cx0 = max(b.x0, 0), cy0 = max(b.y0, 0);
       const int cx1 = min(b.x1, W), cy1 = min(b.y1, H);
       const bool empty = !(cx0 < cx1 && cy0 < cy1);
@@ -147,21 +151,32 @@ __device__ __forceinline__ void plan_frame(const MatchParamsDev& P, const FrameD
   }
 }
 
-// The item records of frame f (as plan_frame writes them) by nthr threads at once, after
-// plan_frame(..., items = false) has stored the frame's plans, running item ends and
-// counters (and the threads have synchronised with it): thread tid writes items tid,
-// tid + nthr, ...; the box of an item is found by binary search on the running item
-// ends of its level.
+// The item records of frame f (as plan_frame writes them) by the nthr threads of one
+// workgroup, after plan_frame(..., items = false) has stored the frame's plans, running
+// item ends and counters (and the threads have synchronised with it): thread tid writes
+// items tid, tid + nthr, ...; the box of an item is found by binary search on the running
+// item ends of its level. With lds (lds_cap words the caller is done with) holding both
+// levels' ends of the frame, they are copied there first and searched in LDS.
 __device__ __forceinline__ void write_frame_items(const MatchParamsDev& P, const FrameDev& fr, int f,
-                                                  int n_total, const MatchWs& ws, int tid, int nthr) {
+                                                  int n_total, const MatchWs& ws, int tid, int nthr,
+                                                  int32_t* lds = nullptr, int lds_cap = 0) {
   const int n = fr.n_boxes;
+  const bool in_lds = lds && 2 * n <= lds_cap;
+  if (in_lds) {
+    __syncthreads();   // every thread is done with the caller's use of the LDS
+    for (int i = tid; i < n; i += nthr) {
+      lds[i] = ws.litem_end[fr.box_off + i];
+      lds[n + i] = ws.litem_end[(size_t)n_total + fr.box_off + i];
+    }
+    __syncthreads();
+  }
   const int32_t* fc = ws.fcount + f * FC_N;
   const int n_close = fc[FC_CLOSE_ITEMS], n_far = fc[FC_FAR_ITEMS];
   ItemRec* rec = ws.items + (size_t)f * ws.items_cap;
   for (int t = tid; t < n_close + n_far; t += nthr) {
     const int level = t < n_close ? 1 : 0;
     const int q = level ? t : t - n_close;
-    const int32_t* end = ws.litem_end + (size_t)level * n_total + fr.box_off;
+    const int32_t* end = in_lds ? lds + level * n : ws.litem_end + (size_t)level * n_total + fr.box_off;
     int lo = 0, hi = n - 1;   // first box whose running end passes q
     while (lo < hi) {
       const int mid = (lo + hi) >> 1;

@@ -49,7 +49,8 @@ __global__ __launch_bounds__(256) void fused_kernel(MatchParamsDev P, FramesDev 
     int* sc = (int*)(bits + kFrameTileWords);
     if (wave == 0) dev::plan_frame(P, FR.f[w], w, FR.n_boxes_total, boxes, ws, lane, false);
     dev::list_frame_tiles(P, FR.f[w], w, boxes, ws, bits, sc);
-    dev::write_frame_items(P, FR.f[w], w, FR.n_boxes_total, ws, tid, 256);
+    dev::write_frame_items(P, FR.f[w], w, FR.n_boxes_total, ws, tid, 256, (int32_t*)bits,
+                           kFrameTileWords);
     __syncthreads();   // the LDS is reused below
   }
   dev::grid_barrier(ws.gcount + GC_BAR0, G, timeout);

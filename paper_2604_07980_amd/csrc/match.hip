@@ -60,7 +60,8 @@ __global__ __launch_bounds__(256) void plan_tiles_kernel(MatchParamsDev P, Frame
   if (threadIdx.x < 64)
     dev::plan_frame(P, FR.f[f], f, FR.n_boxes_total, boxes, ws, threadIdx.x, false);
   dev::list_frame_tiles(P, FR.f[f], f, boxes, ws, bits, sc);   // synchronises the workgroup
-  dev::write_frame_items(P, FR.f[f], f, FR.n_boxes_total, ws, threadIdx.x, 256);
+  dev::write_frame_items(P, FR.f[f], f, FR.n_boxes_total, ws, threadIdx.x, 256, (int32_t*)bits,
+                         kFrameTileWords);
 }
 
 // Census of the listed tiles of every frame by persistent workgroups: the frames' lists,
