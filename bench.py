@@ -230,22 +230,28 @@ def cpu_baseline(scenes, params, seconds):
     if not os.path.exists(orc.LIB):
         orc.build()
     cores = len(os.sched_getaffinity(0))
-    # work of each frame from the oracle's own block records (outside the timing)
-    costs = []
-    for sc in scenes:
-        _, (_, blk, *_rest) = orc.run_scene(sc.left, sc.right, params, sc.boxes, debug=True,
-                                           threads=cores)
-        costs.append(costs_of_records(blk, params)["costs"])
+    # work of each frame from the oracle's own block records, found the first time the
+    # frame is used, outside the timed calls
+    costs = {}
+
+    def frame_costs_cpu(k):
+        if k not in costs:
+            sc = scenes[k]
+            _, (_, blk, *_rest) = orc.run_scene(sc.left, sc.right, params, sc.boxes, debug=True,
+                                               threads=cores)
+            costs[k] = costs_of_records(blk, params)["costs"]
+        return costs[k]
 
     def leg(threads):
-        done, c, t0 = 0, 0, time.perf_counter()
+        done, c, el = 0, 0, 0.0
         while True:
             k = done % len(scenes)
             sc = scenes[k]
+            c += frame_costs_cpu(k)
+            t0 = time.perf_counter()
             orc.run_scene(sc.left, sc.right, params, sc.boxes, threads=threads)
+            el += time.perf_counter() - t0
             done += 1
-            c += costs[k]
-            el = time.perf_counter() - t0
             if el >= seconds:
                 return {"value": round(c / el / 1e9, 4), "frames": done, "seconds": round(el, 2),
                         "ms_per_frame": round(1e3 * el / done, 2)}
@@ -580,7 +586,7 @@ def serving_section(ocsr, synth, pools_np, n_requests):
         return [serve.Request(q["rid"], *pools[q["res"]][q["pool"]], q["boxes"], q["params"],
                               0.0 if at_once else q["arrival"]) for q in spec]
 
-    ex = serve.GpuExecutor(n_slots=3)
+    ex = serve.GpuExecutor(n_slots=3, graphs=True)
 
     def served(at_once):
         srv = serve.Server(ex, mem_budget=4 << 30)
