@@ -565,13 +565,22 @@ __device__ __forceinline__ void match_block_tiled(const MatchParamsDev& P, const
 // add, and the winner is a DPP wave minimum of packed (cost << 16 | index) keys. A strip
 // row is staged in 64-word chunks through a buffer resource per row (load_half_strip).
 // ---------------------------------------------------------------------------------
+// strip row stride beyond the candidates (see Half::SWP)
+constexpr int kHalfStripPad = 10;
+
 template <int CPL>
 struct Half {
   static constexpr int NC = 32 * CPL;               // candidates one wave covers
-  static constexpr int SWP = NC + 8;                // LDS words per strip row (>= NC + 7)
+  // LDS words per strip row (>= NC + 7). The two row halves are read by the same
+  // instructions (lanes 2g and 2g + 1), so rows four apart must start in different LDS
+  // banks: 4 SWP is an odd multiple of 8 words.
+  static constexpr int SWP = NC + kHalfStripPad;
+  static constexpr int TH = 40;                     // template: rows 4..7 start here
+  static constexpr int TW = TH + 32;                // template words
   static constexpr int CH = (NC + 7 + 63) / 64;     // 64-word chunks of a strip row
   static constexpr size_t kLdsBytes =
-      sizeof(uint64_t) * (8 * SWP + 64) + sizeof(uint32_t) * 2 * NC;
+      sizeof(uint64_t) * (8 * SWP + TW) + sizeof(uint16_t) * 2 * NC;
+  static_assert(SWP >= NC + 7, "a strip row holds nd + 7 words");
 };
 
 // Whole-wave minimum of v (every lane gets it): DPP within rows of 16, then row
@@ -655,7 +664,7 @@ __device__ __forceinline__ void half_costs(const uint64_t* __restrict__ T, const
   constexpr int SWP = Half<CPL>::SWP;
 #pragma unroll
   for (int c = 0; c < CPL; ++c) acc[c] = 0;
-  const uint64_t* __restrict__ trow = T + 32 * h;
+  const uint64_t* __restrict__ trow = T + Half<CPL>::TH * h;
   const uint64_t* __restrict__ srow = S + 4 * h * SWP + g * CPL;
   if (full) {
 #pragma unroll 1
@@ -735,9 +744,10 @@ __device__ __forceinline__ void match_block_half(const MatchParamsDev& P, const 
   using HH = Half<CPL>;
   constexpr int SWP = HH::SWP, CH = HH::CH, NC = HH::NC;
   uint64_t* S = (uint64_t*)lds;
-  uint64_t* T = S + 8 * SWP;
-  uint32_t* costf = (uint32_t*)(T + 64);
-  uint32_t* costb = costf + NC;
+  uint64_t* T = S + 8 * SWP;                   // row jj at 8 jj, rows 4..7 moved by TH - 32
+  uint16_t* costf = (uint16_t*)(T + HH::TW);   // a cost is at most 64 x 64
+  uint16_t* costb = costf + NC;
+  const int tslot = lane + (lane >= 32 ? HH::TH - 32 : 0);   // lane (i, jj) = i + 8 jj
   const int g = lane >> 1, h = lane & 1;
   const LevelDev& lv = fr.lv[c.level];
   const PathDev& ph = P.path[c.level];
@@ -760,7 +770,7 @@ __device__ __forceinline__ void match_block_half(const MatchParamsDev& P, const 
   }
   const uint64_t m8 = tiled_mask8(ws, fr.box_off, fr.n_boxes, c.k, c.g.s, X0, Y0, nx, ny, lane);
   store_half_strip<SWP, CH>(S, fw, lane);
-  T[lane] = tw;
+  T[tslot] = tw;
   const int npts = __popcll(m8);
   const bool eligible = npts > 0 && 100 * npts >= P.min_point_pct * nx * ny;
   wave_sync();
@@ -792,7 +802,7 @@ __device__ __forceinline__ void match_block_half(const MatchParamsDev& P, const 
     const int i = lane & 7, jj = lane >> 3;
     const uint64_t t = S[jj * SWP + (dhi - d_f) + i];
     wave_sync();
-    T[lane] = t;
+    T[tslot] = t;
   }
   const int ca = (int)costf[max(best - 1, 0)];
   const int cb = (int)costf[min(best + 1, nd - 1)];
