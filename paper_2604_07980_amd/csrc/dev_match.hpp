@@ -285,9 +285,11 @@ struct BlockCtx {
   BlockGeom g;
 };
 
-// block `local` (0-based, row-major over the box's block grid) of box k of frame f
+// block `local` (0-based, row-major over the box's block grid) of box k of frame f, at
+// column u and row v of the grid
 __device__ __forceinline__ BlockCtx block_ctx(const MatchParamsDev& P, const FrameDev& fr, int f,
-                                              int k, const BoxPlan& pl, int local, int level) {
+                                              int k, const BoxPlan& pl, int local, int u, int v,
+                                              int level) {
   BlockCtx c;
   c.f = f;
   c.level = level;
@@ -296,14 +298,19 @@ __device__ __forceinline__ BlockCtx block_ctx(const MatchParamsDev& P, const Fra
   c.pl = pl;
   c.b = pl.off + local;
   c.slot = f * P.cap_blocks + c.b;
-  c.v = local / pl.nbx;
-  c.u = local - c.v * pl.nbx;
+  c.v = v;
+  c.u = u;
   const LevelDev& lv = fr.lv[level];
   c.g.nx = pl.bw; c.g.ny = pl.bh; c.g.s = lv.scale;
   c.g.tiled = P.path[level].mode == OCSR_MODE_TILED;
   c.g.cx = pl.ox + c.u * pl.bw; c.g.lx0 = pl.lx0; c.g.lw = pl.lw;
   c.g.cy = pl.oy + c.v * pl.bh; c.g.ly0 = pl.ly0; c.g.lh = pl.lh;
   return c;
+}
+__device__ __forceinline__ BlockCtx block_ctx(const MatchParamsDev& P, const FrameDev& fr, int f,
+                                              int k, const BoxPlan& pl, int local, int level) {
+  const int v = local / pl.nbx;
+  return block_ctx(P, fr, f, k, pl, local, local - v * pl.nbx, v, level);
 }
 
 // Stores the block's result (lane 0 of the wave).
@@ -621,8 +628,10 @@ __device__ __forceinline__ HalfStrip<CH> load_half_strip(const uint64_t* __restr
   HalfStrip<CH> st;
 #pragma unroll
   for (int jj = 0; jj < 8; ++jj) {
+    // W words for rows inside the block (jj < ny: the sign bit of jj - ny), else none
+    const int nrec = W * 8 * (int)((uint32_t)(jj - ny) >> 31);
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-        (void*)(rows + (size_t)jj * pitch), (short)0, jj < ny ? W * 8 : 0, 0x00020000);
+        (void*)(rows + (size_t)jj * pitch), (short)0, nrec, 0x00020000);
 #pragma unroll
     for (int c = 0; c < CH; ++c) st.w[jj][c] = __builtin_amdgcn_raw_buffer_load_b64(rs, voff[c], 0, 0);
   }
@@ -784,15 +793,16 @@ __device__ __forceinline__ void match_block_half(const MatchParamsDev& P, const 
   const uint32_t keep = (uint32_t)(m8 >> (32 * h));
   uint32_t acc[CPL];
   half_costs<CPL>(T, S, g, h, full, keep, acc);
+  // both lanes of a group hold the whole cost; a strip position past the range writes
+  // its (unread) slot at index e >= nd instead of a branch
   uint32_t key = 0xFFFFFFFFu;
 #pragma unroll
   for (int cc = 0; cc < CPL; ++cc) {
     const int e = g * CPL + cc;            // strip position: candidate d = dhi - e
-    if (e < nd) {
-      const int kc = nd - 1 - e;
-      key = min(key, (acc[cc] << 16) | (uint32_t)kc);
-      if (h == 0) costf[kc] = acc[cc];
-    }
+    const bool in = e < nd;
+    const int kc = nd - 1 - e;
+    key = min(key, in ? (acc[cc] << 16) | (uint32_t)kc : 0xFFFFFFFFu);
+    costf[in ? kc : e] = (uint16_t)acc[cc];
   }
   key = wave_min_dpp(key);
   const int best = (int)(key & 0xFFFFu);
@@ -815,11 +825,9 @@ __device__ __forceinline__ void match_block_half(const MatchParamsDev& P, const 
   uint32_t bkey = 0xFFFFFFFFu;
 #pragma unroll
   for (int cc = 0; cc < CPL; ++cc) {
-    const int kc = g * CPL + cc;           // candidate d' = dlo + kc
-    if (kc < nd) {
-      bkey = min(bkey, (acc[cc] << 16) | (uint32_t)kc);
-      if (h == 0) costb[kc] = acc[cc];
-    }
+    const int kc = g * CPL + cc;           // candidate d' = dlo + kc (slots past nd unread)
+    bkey = min(bkey, kc < nd ? (acc[cc] << 16) | (uint32_t)kc : 0xFFFFFFFFu);
+    costb[kc] = (uint16_t)acc[cc];
   }
   bkey = wave_min_dpp(bkey);
   const int d_b = dlo + (int)(bkey & 0xFFFFu);
@@ -1359,9 +1367,17 @@ __device__ __forceinline__ void run_item_rec(const MatchParamsDev& P, const Fram
   pl.lx0 = r.lx0; pl.ly0 = r.ly0; pl.lw = r.lw; pl.lh = r.lh;
   pl.nbx = r.nbx; pl.bw = r.bw; pl.bh = r.bh; pl.ox = r.ox; pl.oy = r.oy;
   pl.off = r.off; pl.nblk = r.nblk; pl.frame = f;
+  // the wave's blocks step by kItemWaves along the grid's rows: one division per item
+  int local = r.first + wave;
+  int v = local / pl.nbx, u = local - v * pl.nbx;
   for (int j = wave; j < P.item_blocks[level]; j += kItemWaves) {
-    const int local = r.first + j;
-    if (local < r.nblk) run(block_ctx(P, fr, f, r.k, pl, local, level));
+    if (local < r.nblk) run(block_ctx(P, fr, f, r.k, pl, local, u, v, level));
+    local += kItemWaves;
+    u += kItemWaves;
+    while (u >= pl.nbx) {
+      u -= pl.nbx;
+      ++v;
+    }
   }
 }
 
