@@ -445,6 +445,8 @@ int32_t range_frames(ocsr_ctx* ctx, const ocsr_frame* frames, int n_frames,
     d.tiles0 = d.tiles0_x * (int)cdiv64(H, kCensusTileY);
     d.tiles1_x = (int)cdiv64(W1, kCensusTileX);
     d.tiles1 = d.tiles1_x * (int)cdiv64(H1, kCensusTileY);
+    d.tx_recip[0] = ((1ull << 40) + (uint64_t)d.tiles0_x - 1) / (uint64_t)d.tiles0_x;
+    d.tx_recip[1] = ((1ull << 40) + (uint64_t)d.tiles1_x - 1) / (uint64_t)d.tiles1_x;
     d.tile_begin = tiles;
     tiles += 2 * (d.tiles0 + d.tiles1);
   }

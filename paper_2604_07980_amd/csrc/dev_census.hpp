@@ -29,16 +29,16 @@ struct CensusTile {
   static constexpr int PR = kCensusTileY + 2 * SY - 1;            // rows of pixel pairs
   static constexpr int WR = kCensusRowsPerLane - 1 + 2 * SY;      // pair rows per lane
   static constexpr int N = (2 * SX + 1) * (2 * SY + 1);           // comparisons
-  static constexpr size_t kLdsBytes = sizeof(uint32_t) * PR * LW;
+  static constexpr size_t kLdsBytes = sizeof(uint32_t) * (PR * LW + 64);   // + spare words
   static_assert(N + 1 <= 64, "window wider than a 64-bit code");
 };
 
 // One census tile: the uint8 source img (pitch bytes, W x H) at level scale s (level
-// image W/s x H/s), the level position (X0, Y0) of the tile, and the descriptor image
-// out (out_pitch words).
+// image Ws x Hs = W/s x H/s), the level position (X0, Y0) of the tile, and the
+// descriptor image out (out_pitch words).
 struct CensusJob {
   const uint8_t* img;
-  int W, H, pitch, s;
+  int W, H, pitch, s, Ws, Hs;
   uint64_t* out;
   int out_pitch, X0, Y0;
 };
@@ -62,7 +62,7 @@ __device__ __forceinline__ void census_stage(const CensusJob& j, uint32_t* P) {
   const uint8_t* img = uniform(j.img);
   const int pitch = uniform(j.pitch), s = uniform(j.s);
   const int X0 = uniform(j.X0), Y0 = uniform(j.Y0);
-  const int Ws = uniform(j.W) / s, Hs = uniform(j.H) / s;
+  const int Ws = uniform(j.Ws), Hs = uniform(j.Hs);
   constexpr int RB = (PR + 1 + 3) / 4;
   constexpr int NPASS = (LW + 63) / 64;
   {
@@ -88,7 +88,8 @@ __device__ __forceinline__ void census_stage(const CensusJob& j, uint32_t* P) {
 #pragma unroll
       for (int k = 0; k < RB; ++k) {
         const int pr = wave * RB + k;
-        if (pr < PR && pc < LW) P[pr * LW + pc] = px[cp][k] | (px[cp][k + 1] << 16);
+        // positions past the tile write the spare words after P (no lane mask)
+        P[pr < PR && pc < LW ? pr * LW + pc : PR * LW + lane] = px[cp][k] | (px[cp][k + 1] << 16);
       }
     }
   }
@@ -103,9 +104,10 @@ __device__ __forceinline__ void census_compute(const CensusJob& j, int sentinel,
   uint64_t* out = uniform(j.out);
   const int s = uniform(j.s), out_pitch = uniform(j.out_pitch);
   const int X0 = uniform(j.X0), Y0 = uniform(j.Y0);
-  const int Ws = uniform(j.W) / s, Hs = uniform(j.H) / s;
+  const int Ws = uniform(j.Ws), Hs = uniform(j.Hs);
   const int lane = threadIdx.x & 63;
   const int r0 = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) * kCensusRowsPerLane;
+  uint64_t* orow = uniform(out + (size_t)(Y0 + r0) * out_pitch);   // the wave's first row
   // the lane's window words are read one window column at a time, so that only one
   // column (WR words) is held besides the accumulators
   const uint32_t* Pl = P + r0 * LW + lane;
@@ -163,18 +165,20 @@ __device__ __forceinline__ void census_compute(const CensusJob& j, int sentinel,
                            __builtin_amdgcn_perm(x23, x01, 0x05040100u);
     const uint64_t codeB = ((uint64_t)__builtin_amdgcn_perm(x67, x45, 0x07060302u) << 32) |
                            __builtin_amdgcn_perm(x23, x01, 0x07060302u);
-    // rows are wave-uniform: one scalar row address per store, the lane's column as an
-    // unsigned offset
+    // rows are wave-uniform: the row address steps by the pitch (scalar adds), the
+    // lane's column is an unsigned offset
     const int YA = Y0 + r0 + 2 * pp;
     const int YB = YA + 1;
     if (YA < Hs && x_in) {
       const bool def = x_def && YA >= SY && YA < Hs - SY;
-      (out + (size_t)YA * out_pitch)[(uint32_t)X] = def ? codeA : 0ull;
+      orow[(uint32_t)X] = def ? codeA : 0ull;
     }
+    orow += out_pitch;
     if (YB < Hs && x_in) {
       const bool def = x_def && YB >= SY && YB < Hs - SY;
-      (out + (size_t)YB * out_pitch)[(uint32_t)X] = def ? codeB : 0ull;
+      orow[(uint32_t)X] = def ? codeB : 0ull;
     }
+    orow += out_pitch;
   }
 }
 
@@ -185,7 +189,7 @@ __device__ __forceinline__ void census_tile(const uint8_t* __restrict__ img, int
                                             int pitch, int s, uint64_t* __restrict__ out,
                                             int out_pitch, int X0, int Y0, int sentinel,
                                             uint32_t* P) {
-  const CensusJob j{img, W, H, pitch, s, out, out_pitch, X0, Y0};
+  const CensusJob j{img, W, H, pitch, s, W / s, H / s, out, out_pitch, X0, Y0};
   census_stage<SX, SY>(j, P);
   __syncthreads();
   census_compute<SX, SY>(j, sentinel, P);
@@ -262,29 +266,50 @@ struct FrameTile {
   int f, level, view;
   CensusJob job;
 };
-__device__ __forceinline__ FrameTile frame_tile(const FramesDev& FR, int c) {
-  int f = 0;
-  for (int k = 1; k < FR.n; ++k)
-    if (c >= FR.f[k].tile_begin) f = k;
-  const FrameDev& fr = FR.f[f];
-  int t = c - fr.tile_begin, level = 1, tiles = fr.tiles1, tiles_x = fr.tiles1_x;
+// Frame-local tile t of frame f (the frame's tiles number fewer than 2^30; the row of a
+// tile comes from the frame's reciprocal of its tiles per row, without a division).
+__device__ __forceinline__ FrameTile frame_tile_local(const FrameDev& fr, int f, int t) {
+  int level = 1, tiles = fr.tiles1, tiles_x = fr.tiles1_x;
+  uint64_t recip = fr.tx_recip[1];
   if (t >= 2 * fr.tiles1) {
     t -= 2 * fr.tiles1;
     level = 0;
     tiles = fr.tiles0;
     tiles_x = fr.tiles0_x;
+    recip = fr.tx_recip[0];
   }
-  const int view = t / tiles;
-  t -= view * tiles;
+  const int view = t >= tiles ? 1 : 0;
+  t -= view ? tiles : 0;
+  const int ty = (int)(((uint64_t)(uint32_t)t * recip) >> 40);
+  const int tx = t - ty * tiles_x;
   const LevelDev& lv = fr.lv[level];
   FrameTile ft;
   ft.f = f;
   ft.level = level;
   ft.view = view;
-  ft.job = CensusJob{view ? fr.imgR : fr.imgL, fr.W, fr.H, fr.pitch, lv.scale,
-                     (uint64_t*)(view ? lv.R : lv.L), lv.pitch,
-                     (t % tiles_x) * kCensusTileX, (t / tiles_x) * kCensusTileY};
+  ft.job = CensusJob{view ? fr.imgR : fr.imgL, fr.W, fr.H, fr.pitch, lv.scale, lv.W, lv.H,
+                     (uint64_t*)(view ? lv.R : lv.L), lv.pitch, tx * kCensusTileX, ty * kCensusTileY};
   return ft;
+}
+__device__ __forceinline__ FrameTile frame_tile(const FramesDev& FR, int c) {
+  int f = 0;
+  for (int k = 1; k < FR.n; ++k)
+    if (c >= FR.f[k].tile_begin) f = k;
+  return frame_tile_local(FR.f[f], f, c - FR.f[f].tile_begin);
+}
+
+// Makes tile j: window (SX, SY) > (-1, -1) through LDS, (-1, -1) the generic code with
+// (sx, sy). All 256 threads of the workgroup.
+template <int SX, int SY>
+__device__ __forceinline__ void make_census_tile(const CensusJob& j, int sx, int sy, int sentinel,
+                                                 uint32_t* P) {
+  if constexpr (SX >= 0) {
+    census_stage<SX, SY>(j, P);
+    __syncthreads();
+    census_compute<SX, SY>(j, sentinel, P);
+  } else {
+    census_tile_generic(j.img, j.W, j.H, j.pitch, j.s, j.out, j.out_pitch, j.X0, j.Y0, sx, sy, sentinel);
+  }
 }
 
 // Makes census tile c of a whole-frame call. With `check` set and MP.full_census clear,
@@ -314,13 +339,7 @@ __device__ __forceinline__ void frame_census_tile(const MatchParamsDev& MP, cons
     }
     if (!needed) return;
   }
-  if constexpr (SX >= 0) {
-    census_stage<SX, SY>(j, P);
-    __syncthreads();
-    census_compute<SX, SY>(j, sentinel, P);
-  } else {
-    census_tile_generic(j.img, j.W, j.H, j.pitch, j.s, j.out, j.out_pitch, j.X0, j.Y0, sx, sy, sentinel);
-  }
+  make_census_tile<SX, SY>(j, sx, sy, sentinel, P);
 }
 
 // Sets bit c of `bits` for every tile c of the call that some box's search reads (the

@@ -60,6 +60,12 @@ __device__ __forceinline__ Deal xcd_deal(int n) {
   return Deal{lo + (b >> 3), per, hi};
 }
 
+// First unit of share w of n units cut into G equal consecutive shares, floor(n w / G),
+// in 32-bit arithmetic (n < 2^31, G < 46341).
+__device__ __forceinline__ int share_start(int n, int w, int G) {
+  return (n / G) * w + (n % G) * w / G;
+}
+
 // Two lists dealt together (the close and the far work items of a call): each XCD
 // takes its contiguous share of list A and its share of list B and deals them, A's
 // first, over its workgroups as one local list. Every XCD thus holds an equal share of

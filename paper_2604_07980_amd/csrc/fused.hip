@@ -68,13 +68,13 @@ __global__ __launch_bounds__(256) void fused_kernel(MatchParamsDev P, FramesDev 
     int r = 0;
     for (int y = 0; y < x; ++y) r += (G - y + 7) >> 3;
     r += w >> 3;
-    const int lo = (int)((long long)N * r / G), hi = (int)((long long)N * (r + 1) / G);
+    const int lo = dev::share_start(N, r, G), hi = dev::share_start(N, r + 1, G);
     int f = 0;
     for (int q = lo; q < hi; ++q) {
       while (q >= pre[f + 1]) ++f;
       const FrameDev& fr = FR.f[f];
-      const int c = fr.tile_begin + fr.tile_list[q - pre[f]];
-      dev::frame_census_tile<CSX, CSY>(P, FR, boxes, c, CSX, CSY, sentinel, (uint32_t*)lds, false);
+      const dev::FrameTile ft = dev::frame_tile_local(fr, f, fr.tile_list[q - pre[f]]);
+      dev::make_census_tile<CSX, CSY>(ft.job, CSX, CSY, sentinel, (uint32_t*)lds);
       __syncthreads();   // the next tile reuses the LDS
     }
   }

@@ -86,13 +86,13 @@ __global__ __launch_bounds__(256) void census_list_kernel(MatchParamsDev P, Fram
   int w = 0;   // this workgroup's rank when the workgroups of XCD 0 come first, then XCD 1, ...
   for (int y = 0; y < x; ++y) w += (G - y + 7) >> 3;
   w += b >> 3;
-  const int lo = (int)((long long)N * w / G), hi = (int)((long long)N * (w + 1) / G);
+  const int lo = dev::share_start(N, w, G), hi = dev::share_start(N, w + 1, G);
   int f = 0;
   for (int q = lo; q < hi; ++q) {
     while (q >= pre[f + 1]) ++f;
     const FrameDev& fr = FR.f[f];
-    const int c = fr.tile_begin + fr.tile_list[q - pre[f]];
-    dev::frame_census_tile<SX, SY>(P, FR, boxes, c, sx, sy, sentinel, lds, false);
+    const dev::FrameTile ft = dev::frame_tile_local(fr, f, fr.tile_list[q - pre[f]]);
+    dev::make_census_tile<SX, SY>(ft.job, sx, sy, sentinel, lds);
     __syncthreads();   // the next tile reuses the LDS
   }
 }
@@ -542,7 +542,8 @@ hipError_t launch_plan_and_census(const MatchParamsDev& P, const FramesDev& FR,
   if (e != hipSuccess) return e;
   auto kernel = w34 ? census_list_kernel<3, 4> : w22 ? census_list_kernel<2, 2>
                 : w43 ? census_list_kernel<4, 3> : census_list_kernel<-1, -1>;
-  return timed_launch(timer, "census", kernel, dim3(std::max(1, n_cu) * occ), dim3(256), 0, stream,
+  // (shares are cut in 32-bit arithmetic, which takes grids below 46341)
+  return timed_launch(timer, "census", kernel, dim3(std::min(std::max(1, n_cu) * occ, 46340)), dim3(256), 0, stream,
                       P, FR, boxes, ws, sx, sy, sentinel);
 }
 

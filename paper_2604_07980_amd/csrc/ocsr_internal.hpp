@@ -117,6 +117,8 @@ struct FrameDev {
   int32_t* tile_list;              // whole-frame calls: the frame's tiles to make (frame-local
                                    // numbers), written by the plan step
   int32_t tiles0_x, tiles0, tiles1_x, tiles1;   // census tiles per view at levels 0 / 1
+  uint64_t tx_recip[2];            // ceil(2^40 / tiles_x) of levels 0 / 1: t / tiles_x is
+                                   // (t * tx_recip) >> 40, exactly, for t < 2^30
 };
 
 struct FramesDev {
