@@ -475,7 +475,7 @@ int32_t ocsr_rect_filter_update(ocsr_rect_filter* f, const int32_t* counts, int3
  * to the multi-launch sequence. Both give identical results. */
 #define OCSR_OPTION_FUSED 1
 /* OCSR_OPTION_WAVES_PER_CU: cap on the workgroups per compute unit of the persistent
- * launch (0 = as many as fit, 1..32 = cap). */
+ * launch (0 = the library's default, 2; 1..32 = cap; never more than fit). */
 #define OCSR_OPTION_WAVES_PER_CU 2
 /* OCSR_OPTION_MATCH_WGS_PER_CU: workgroups per compute unit of the grid of each matching
  * launch (1..64, default 16). The launch deals its work items over this grid. */

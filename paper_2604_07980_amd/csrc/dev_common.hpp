@@ -109,16 +109,19 @@ __device__ __forceinline__ int load_relaxed(const int32_t* p) {
 // the wait ends; the bound only guards against a defect.
 constexpr int kSpinLimit = 1 << 22;
 
-// Publishes a workgroup's global writes before one thread signals a counter: every
-// wave waits for its own stores, then the workgroup meets at a barrier.
+// Readies a workgroup's global writes for one thread's device-scope release: every wave
+// waits until its own stores are complete in the L2 (vmcnt 0: the vector L1 writes
+// through), then the workgroup meets at a barrier. The one release that follows (an L2
+// write-back on this multi-XCD GPU) then covers every wave's writes, where a release
+// fence in each wave would cost one write-back per wave.
 __device__ __forceinline__ void publish_workgroup() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
 }
 
 // Grid-wide barrier of a launch whose workgroups are all resident: every workgroup
-// publishes its writes, counts itself in one of kBarSlots counters and waits (bounded)
-// until the slots add up to the grid size.
+// publishes its writes, counts itself in one of kBarSlots counters (one device-scope
+// release per workgroup) and waits (bounded) until the slots add up to the grid size.
 __device__ __forceinline__ void grid_barrier(int32_t* slots, int n_groups, int32_t* timeout_flag) {
   publish_workgroup();
   if (threadIdx.x == 0) {

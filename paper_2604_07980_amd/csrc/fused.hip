@@ -138,6 +138,8 @@ FusedPair fused_pair(const MatchParamsDev& P, int sx, int sy) {
   return FusedPair::kNone;
 }
 
+constexpr int kFusedDefaultWgsPerCu = 2;
+
 template <class K>
 hipError_t launch_one(K kernel, const MatchParamsDev& P, const FramesDev& FR, const ocsr_box* boxes,
                       const MatchWs& ws, ocsr_box_result* out, int sentinel, int n_census,
@@ -146,7 +148,11 @@ hipError_t launch_one(K kernel, const MatchParamsDev& P, const FramesDev& FR, co
   hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)kernel, 256, 0);
   if (e != hipSuccess) return e;
   if (per_cu < 1) return hipErrorNotSupported;
-  if (wgs_per_cu > 0) per_cu = per_cu < wgs_per_cu ? per_cu : wgs_per_cu;
+  // default 2 per CU: every workgroup pays an L2 write-back and an invalidation at each
+  // grid barrier, which outweighs the waves more workgroups add (16-frame batch: 0.42 ms
+  // at 2 per CU, 0.57 ms at the 4 that fit)
+  const int cap = wgs_per_cu > 0 ? wgs_per_cu : kFusedDefaultWgsPerCu;
+  per_cu = per_cu < cap ? per_cu : cap;
   kernel<<<per_cu * n_cu, 256, 0, stream>>>(P, FR, boxes, ws, out, sentinel, n_census);
   return hipGetLastError();
 }
