@@ -49,6 +49,9 @@ def parse():
     ap.add_argument("--tune-table", default="", metavar="PATH",
                     help="load the autotuner's table from PATH when it exists (no tuning), else "
                          "tune and save the table there")
+    ap.add_argument("--only", default="", choices=["", "tiny", "realistic", "dense", "vertical", "rect"],
+                    help="run only this single-frame section and print its JSON object (the "
+                         "command to profile it)")
     ap.add_argument("--headline-only", action="store_true",
                     help="time only the headline batch (no untuned, per-frame-call, one-launch or "
                          "graph comparison and no other section): the command to profile")
@@ -630,6 +633,23 @@ def serving_section(ocsr, synth, pools_np, n_requests):
 
 # ------------------------------------------------------------------------------------
 
+def only_section(ocsr, synth, args):
+    """One single-frame section alone, as the full run measures it."""
+    if args.only == "tiny":
+        return frame_section(ocsr, synth.scene_tiny(), synth.params_for(1),
+                             "tiny_640x480: 4 boxes, 8x8 blocks d 0..63 at s=1, segment median", args)[0]
+    if args.only == "vertical":
+        return vertical_section(ocsr, synth, args.vertical_steps, 3)
+    if args.only == "rect":
+        return rect_section(ocsr, synth, args.rect_steps)
+    real, (L, R, boxes, out, ms2) = frame_section(
+        ocsr, synth.scene_realistic(), synth.params_for(2), "realistic_1080p", args,
+        graph=args.only == "realistic")
+    if args.only == "dense":
+        return dense_section(ocsr, L, R, args.dense_steps, ms2, max(20, args.latency_steps // 20))
+    return real
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -660,6 +680,10 @@ def main():
                           "ms": [round(r[1], 4) for r in rates]}), flush=True)
         return
 
+    if args.only:
+        torch.cuda.set_device(torch.device("cuda:0"))
+        print(json.dumps({args.only: only_section(ocsr, synth, args)}), flush=True)
+        return
     t_start = time.perf_counter()
     scenes, pools = render_inputs(args)
     log(f"inputs rendered ({time.perf_counter() - t_start:.1f} s)")
