@@ -68,19 +68,20 @@ __device__ __forceinline__ void census_stage(const CensusJob& j, uint32_t* P) {
   {
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
+    // each row through a buffer resource over that row (scalar setup), the lane's
+    // clamped column a byte offset fixed for the tile: no per-load address arithmetic
+    uint32_t coff[NPASS];
+#pragma unroll
+    for (int cp = 0; cp < NPASS; ++cp) coff[cp] = (uint32_t)(s * clamp_to(X0 - SX + lane + 64 * cp, Ws));
+    const int wbytes = uniform(j.W);
     uint32_t px[NPASS][RB + 1];
 #pragma unroll
-    for (int cp = 0; cp < NPASS; ++cp) {
-      const int pc = lane + 64 * cp;
-      const int X = X0 - SX + pc;
-      const uint32_t coff = (uint32_t)(s * clamp_to(X, Ws));
+    for (int k = 0; k <= RB; ++k) {
+      const int Yc = clamp_to(Y0 - SY + wave * RB + k, Hs);
+      const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+          (void*)(img + (size_t)(s * Yc) * pitch), (short)0, wbytes, 0x00020000);
 #pragma unroll
-      for (int k = 0; k <= RB; ++k) {
-        const int Y = Y0 - SY + wave * RB + k;
-        const int Yc = clamp_to(Y, Hs);
-        const uint8_t* rp = img + (size_t)(s * Yc) * pitch;
-        px[cp][k] = rp[coff];
-      }
+      for (int cp = 0; cp < NPASS; ++cp) px[cp][k] = __builtin_amdgcn_raw_buffer_load_b8(rs, coff[cp], 0, 0);
     }
 #pragma unroll
     for (int cp = 0; cp < NPASS; ++cp) {
