@@ -456,20 +456,20 @@ int32_t range_frames(ocsr_ctx* ctx, const ocsr_frame* frames, int n_frames,
     base += a256(sizeof(int32_t) * (size_t)frame_tiles(frames[f].width, frames[f].height, s));
   }
   MatchWs mws = match_ws_carve(base, n_frames, n_total, cap_blocks);
-  const bool fused = ctx->use_fused && fused_available(P, fp->sx, fp->sy, (int)tiles);
+  const bool fused = ctx->use_fused && fused_available(P, FR, fp->sx, fp->sy);
   const int sentinel = fp->sentinel ? 1 : 0;
   // the whole launch sequence of the call, on stream s
   auto enqueue = [&](hipStream_t s, const LaunchTimer* tp) -> int32_t {
     if (fused) {
-      hipError_t e = launch_fused(P, FR, boxes, mws, out, fp->sx, fp->sy, sentinel, tiles,
-                                  ctx->n_cu, ctx->wgs_per_cu, s, tp);
+      hipError_t e = launch_fused(P, FR, boxes, mws, out, fp->sx, fp->sy, sentinel, ctx->n_cu,
+                                  ctx->wgs_per_cu, s, tp);
       return e == hipSuccess ? OCSR_OK : hip_fail(e, "fused launch");
     }
     hipError_t e = ctx->census_list != 0
                        ? launch_plan_and_census(P, FR, boxes, mws, fp->sx, fp->sy, sentinel, ctx->n_cu, s, tp)
                        : hipErrorNotSupported;
     if (e == hipErrorNotSupported)
-      e = launch_frame_census(P, FR, boxes, mws, fp->sx, fp->sy, sentinel, tiles, ctx->n_cu, false, s, tp);
+      e = launch_frame_census(P, FR, boxes, mws, fp->sx, fp->sy, sentinel, tiles, s, tp);
     if (e != hipSuccess) return hip_fail(e, "census launch");
     e = launch_match(P, FR, boxes, mws, out, make_debug(nullptr), true,
                      std::max(1, ctx->n_cu * ctx->match_wgs_per_cu), ctx->level_launches, s, tp);

@@ -343,66 +343,6 @@ __device__ __forceinline__ void frame_census_tile(const MatchParamsDev& MP, cons
   make_census_tile<SX, SY>(j, sx, sy, sentinel, P);
 }
 
-// Sets bit c of `bits` for every tile c of the call that some box's search reads (the
-// ranges of census_tile_needed), or for every tile when MP.full_census is set. One
-// thread per box; a box sets, per view and tile row, one run of consecutive tile bits.
-__device__ __forceinline__ void mark_census_tiles(const MatchParamsDev& MP, const FramesDev& FR,
-                                                  const ocsr_box* __restrict__ boxes, int n_tiles,
-                                                  uint32_t* bits) {
-  const int tid = threadIdx.x;
-  const int n_words = (n_tiles + 31) >> 5;
-  if (MP.full_census) {
-    for (int i = tid; i < n_words; i += 256) {
-      const int rem = n_tiles - 32 * i;
-      bits[i] = rem >= 32 ? 0xFFFFFFFFu : ((1u << rem) - 1u);
-    }
-    return;
-  }
-  // threads over the boxes of every frame at once (frames hold consecutive box ranges)
-  for (int g = tid; g < FR.n_boxes_total; g += 256) {
-    int f = 0;
-    for (int k = 1; k < FR.n; ++k)
-      if (g >= FR.f[k].box_off) f = k;
-    const FrameDev& fr = FR.f[f];
-    {
-      const ocsr_box b = boxes[g];
-      const int cx0 = max(b.x0, 0), cy0 = max(b.y0, 0);
-      const int cx1 = min(b.x1, fr.W), cy1 = min(b.y1, fr.H);
-      if (!(b.flags & OCSR_BOX_RANGE) || !(cx0 < cx1 && cy0 < cy1)) continue;
-      const int level = max(cx1 - cx0, cy1 - cy0) < MP.tau_s ? 0 : 1;
-      const LevelDev& lv = fr.lv[level];
-      const int s = lv.scale;
-      const int x0 = max(cdiv_nonneg(cx0, s), lv.sx), x1 = min(cdiv_nonneg(cx1, s), lv.W - lv.sx);
-      const int y0 = max(cdiv_nonneg(cy0, s), lv.sy), y1 = min(cdiv_nonneg(cy1, s), lv.H - lv.sy);
-      if (!(x0 < x1 && y0 < y1)) continue;
-      const int dlo = MP.path[level].dlo, dhi = dlo + MP.path[level].nd - 1;
-      const int eylo = MP.path[level].dylo, eyhi = eylo + MP.path[level].ndy - 1;
-      const int tiles_x = level ? fr.tiles1_x : fr.tiles0_x;
-      const int tiles = level ? fr.tiles1 : fr.tiles0;
-      const int tiles_y = tiles / tiles_x;
-      const int lbase = fr.tile_begin + (level ? 0 : 2 * fr.tiles1);
-      for (int view = 0; view < 2; ++view) {
-        const int a = max(x0 - (view ? dhi : dhi - dlo), 0);
-        const int e = min(x1 + (view ? -dlo : dhi - dlo), tiles_x * kCensusTileX);
-        if (a >= e) continue;
-        const int ta = a / kCensusTileX, tb = (e - 1) / kCensusTileX;
-        const int ya = max(y0 + (view ? eylo : eylo - eyhi), 0);
-        const int yb = min(y1 + (view ? eyhi : eyhi - eylo), tiles_y * kCensusTileY);
-        if (ya >= yb) continue;
-        for (int ty = ya / kCensusTileY; ty <= (yb - 1) / kCensusTileY; ++ty) {
-          const int first = lbase + view * tiles + ty * tiles_x + ta;
-          const int last = first + (tb - ta);
-          for (int wd = first >> 5; wd <= (last >> 5); ++wd) {
-            const int lo = max(first - 32 * wd, 0), hi = min(last - 32 * wd, 31);
-            const uint32_t upto = hi == 31 ? 0xFFFFFFFFu : ((1u << (hi + 1)) - 1u);
-            atomicOr(&bits[wd], upto & ~((1u << lo) - 1u));
-          }
-        }
-      }
-    }
-  }
-}
-
 // The plan step's list of the census tiles of frame f: every tile some ranged box's
 // search reads (the ranges of census_tile_needed), or every tile with MP.full_census,
 // in increasing frame-local tile number (the order frame_census_tile decodes: level 1,
@@ -480,62 +420,6 @@ __device__ __forceinline__ void list_frame_tiles(const MatchParamsDev& MP, const
     }
   }
   if (tid == 255) ws.fcount[f * FC_N + FC_TILES] = r;
-}
-
-// Census of a whole-frame call by G persistent workgroups (this is workgroup w): each
-// builds the same bitmap of needed tiles in LDS, counts them, and makes the tiles of
-// ranks [N w / G, N (w + 1) / G) in tile order, where N is their number. Workgroups agree
-// on the list without communicating. bits: kCensusListWords words; list: kCensusListCap.
-template <int SX, int SY>
-__device__ __forceinline__ void frame_census_listed(const MatchParamsDev& MP, const FramesDev& FR,
-                                                    const ocsr_box* __restrict__ boxes,
-                                                    int n_tiles, int w, int G, int sx, int sy,
-                                                    int sentinel, uint32_t* P, uint32_t* bits,
-                                                    int* list, int* sc) {
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int n_words = (n_tiles + 31) >> 5;
-  for (int i = tid; i < n_words; i += 256) bits[i] = 0;
-  __syncthreads();
-  mark_census_tiles(MP, FR, boxes, n_tiles, bits);
-  __syncthreads();
-  // thread t owns words [t * wpt, (t + 1) * wpt); ranks run in word order
-  const int wpt = (n_words + 255) >> 8;
-  const int w0 = tid * wpt;
-  int cnt = 0;
-  for (int k = 0; k < wpt; ++k)
-    if (w0 + k < n_words) cnt += __popc(bits[w0 + k]);
-  const int incl = wave_incl_scan(cnt, lane);
-  if (lane == 63) sc[wave] = incl;
-  __syncthreads();
-  int before = 0, N = 0;
-  for (int v = 0; v < 4; ++v) {
-    before += v < wave ? sc[v] : 0;
-    N += sc[v];
-  }
-  const int excl = before + incl - cnt;
-  const int lo = (int)((long long)N * w / G), hi = (int)((long long)N * (w + 1) / G);
-  for (int base = lo; base < hi; base += kCensusListCap) {
-    const int end = min(hi, base + kCensusListCap);
-    if (excl < end && excl + cnt > base) {
-      int r = excl;
-      for (int k = 0; k < wpt && r < end; ++k) {
-        uint32_t m = w0 + k < n_words ? bits[w0 + k] : 0u;
-        while (m) {
-          const int bit = __ffs(m) - 1;
-          m &= m - 1;
-          if (r >= base && r < end) list[r - base] = 32 * (w0 + k) + bit;
-          ++r;
-        }
-      }
-    }
-    __syncthreads();
-    for (int q = 0; q < end - base; ++q) {
-      const int c = __builtin_amdgcn_readfirstlane(list[q]);
-      frame_census_tile<SX, SY>(MP, FR, boxes, c, sx, sy, sentinel, P, false);
-      __syncthreads();   // the next tile reuses P; the next chunk rewrites the list
-    }
-  }
 }
 
 }  // namespace dev

@@ -28,8 +28,7 @@ __global__ __launch_bounds__(64) void reset_kernel(MatchWs ws) {
 template <int CSX, int CSY, class FM, class CM>
 __global__ __launch_bounds__(256) void fused_kernel(MatchParamsDev P, FramesDev FR,
                                                     const ocsr_box* boxes, MatchWs ws,
-                                                    ocsr_box_result* out, int sentinel,
-                                                    int n_census) {
+                                                    ocsr_box_result* out, int sentinel) {
   constexpr size_t kWave = cmax(FM::kLds, CM::kLds);
   constexpr size_t kPlan = sizeof(uint32_t) * kFrameTileWords + sizeof(int) * 8;
   constexpr size_t kLds = cmax(cmax(cmax(dev::CensusTile<CSX, CSY>::kLdsBytes, kPlan), kItemWaves * kWave),
@@ -142,8 +141,8 @@ constexpr int kFusedDefaultWgsPerCu = 2;
 
 template <class K>
 hipError_t launch_one(K kernel, const MatchParamsDev& P, const FramesDev& FR, const ocsr_box* boxes,
-                      const MatchWs& ws, ocsr_box_result* out, int sentinel, int n_census,
-                      int n_cu, int wgs_per_cu, hipStream_t stream) {
+                      const MatchWs& ws, ocsr_box_result* out, int sentinel, int n_cu,
+                      int wgs_per_cu, hipStream_t stream) {
   int per_cu = 0;
   hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)kernel, 256, 0);
   if (e != hipSuccess) return e;
@@ -153,22 +152,28 @@ hipError_t launch_one(K kernel, const MatchParamsDev& P, const FramesDev& FR, co
   // at 2 per CU, 0.57 ms at the 4 that fit)
   const int cap = wgs_per_cu > 0 ? wgs_per_cu : kFusedDefaultWgsPerCu;
   per_cu = per_cu < cap ? per_cu : cap;
-  kernel<<<per_cu * n_cu, 256, 0, stream>>>(P, FR, boxes, ws, out, sentinel, n_census);
+  kernel<<<per_cu * n_cu, 256, 0, stream>>>(P, FR, boxes, ws, out, sentinel);
   return hipGetLastError();
+}
+
+// the plan step lists a frame's census tiles in an LDS bitmap of kFrameTileWords words
+bool frames_listable(const FramesDev& FR) {
+  for (int f = 0; f < FR.n; ++f)
+    if (2 * (FR.f[f].tiles0 + FR.f[f].tiles1) > 32 * kFrameTileWords) return false;
+  return true;
 }
 
 }  // namespace
 
-bool fused_available(const MatchParamsDev& p, int sx, int sy, int n_census_tiles) {
-  return fused_pair(p, sx, sy) != FusedPair::kNone && n_census_tiles <= 32 * kCensusListWords;
+bool fused_available(const MatchParamsDev& p, const FramesDev& FR, int sx, int sy) {
+  return fused_pair(p, sx, sy) != FusedPair::kNone && frames_listable(FR);
 }
 
 hipError_t launch_fused(const MatchParamsDev& P, const FramesDev& FR, const ocsr_box* boxes,
                         const MatchWs& ws, ocsr_box_result* out, int sx, int sy, int sentinel,
-                        int n_census_tiles, int n_cu, int wgs_per_cu, hipStream_t stream,
-                        const LaunchTimer* timer) {
+                        int n_cu, int wgs_per_cu, hipStream_t stream, const LaunchTimer* timer) {
   const FusedPair pair = fused_pair(P, sx, sy);
-  if (pair == FusedPair::kNone || n_census_tiles > 32 * kCensusListWords) return hipErrorNotSupported;
+  if (pair == FusedPair::kNone || !frames_listable(FR)) return hipErrorNotSupported;
   if (timer) timer->before(timer->ctx, "reset", stream);
   reset_kernel<<<1, 64, 0, stream>>>(ws);
   if (timer) timer->after(timer->ctx, "reset", stream);
@@ -179,7 +184,7 @@ hipError_t launch_fused(const MatchParamsDev& P, const FramesDev& FR, const ocsr
 #define OCSR_FUSED(K, FMT, CMT)                                                              \
     case FusedPair::K:                                                                       \
       e = launch_one(fused_kernel<3, 4, dev::FMT, dev::CMT>, P, FR, boxes, ws, out, sentinel,  \
-                     n_census_tiles, n_cu, wgs_per_cu, stream);                              \
+                     n_cu, wgs_per_cu, stream);                                              \
       break;
     OCSR_FUSED(kQ2H3, QuadMatcher<2>, HalfMatcher<3>)
     OCSR_FUSED(kQ2H4, QuadMatcher<2>, HalfMatcher<4>)

@@ -18,36 +18,21 @@ __global__ __launch_bounds__(64) void plan_kernel(MatchParamsDev P, FramesDev FR
   dev::plan_frame(P, FR.f[f], f, FR.n_boxes_total, boxes, ws, threadIdx.x);
 }
 
-// workgroups 0 .. n_frames - 1 plan a frame each (one wave); the rest make the census:
-// persistent workgroups over the list of needed tiles (`listed`), else one tile each
+// workgroups 0 .. n_frames - 1 plan a frame each (one wave); the rest make the census, one
+// tile each (a workgroup tests whether some box's search reads its tile)
 template <int SX, int SY>
 __global__ __launch_bounds__(256) void frame_census_kernel(MatchParamsDev P, FramesDev FR,
                                                            const ocsr_box* boxes, MatchWs ws,
-                                                           int sx, int sy, int sentinel,
-                                                           int n_tiles, int listed) {
+                                                           int sx, int sy, int sentinel) {
   __shared__ uint32_t lds[SX >= 0 ? dev::CensusTile<(SX > 0 ? SX : 0), (SY > 0 ? SY : 0)>::kLdsBytes / 4 : 1];
-  __shared__ uint32_t tbits[kCensusListWords];
-  __shared__ int tlist[kCensusListCap];
   __shared__ int tsc[4];
   if ((int)blockIdx.x < FR.n) {
     if (threadIdx.x < 64)
       dev::plan_frame(P, FR.f[blockIdx.x], blockIdx.x, FR.n_boxes_total, boxes, ws, threadIdx.x);
     return;
   }
-  if (listed) {
-    // XCD-aware share: the census workgroups b in [F, F + G) are renumbered so that those
-    // of one XCD (b mod 8) take consecutive shares of the tile list, whose neighbouring
-    // tiles read overlapping source rows
-    const int A = FR.n, B = gridDim.x, b = blockIdx.x, x = b & 7;
-    int w = 0;
-    for (int y = 0; y < x; ++y) w += ((B - y + 7) >> 3) - ((A - y + 7) >> 3);
-    w += (b - (A + ((x - A) & 7))) >> 3;
-    dev::frame_census_listed<SX, SY>(P, FR, boxes, n_tiles, w, B - A, sx, sy, sentinel, lds,
-                                     tbits, tlist, tsc);
-  }
-  else
-    dev::frame_census_tile<SX, SY>(P, FR, boxes, blockIdx.x - FR.n, sx, sy, sentinel, lds, true,
-                                   &tsc[0]);
+  dev::frame_census_tile<SX, SY>(P, FR, boxes, blockIdx.x - FR.n, sx, sy, sentinel, lds, true,
+                                 &tsc[0]);
 }
 
 // Plan of frame blockIdx.x (wave 0 plans the boxes, then all four waves write the work
@@ -475,38 +460,17 @@ static bool launch_pair(const MatchParamsDev& P, const FramesDev& FR, const Matc
   return false;
 }
 
-// resident workgroups per compute unit of a census kernel (occupancy API, once)
-template <int SX, int SY>
-static int census_occupancy() {
-  static const int occ = [] {
-    int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, frame_census_kernel<SX, SY>, 256, 0) != hipSuccess)
-      n = 1;
-    return n > 0 ? n : 1;
-  }();
-  return occ;
-}
-
 hipError_t launch_frame_census(const MatchParamsDev& P, const FramesDev& FR,
                                const ocsr_box* boxes, const MatchWs& ws, int sx, int sy,
-                               int sentinel, int n_census_tiles, int n_cu, bool use_list,
-                               hipStream_t stream, const LaunchTimer* timer) {
-  const int occ = sx == 3 && sy == 4   ? census_occupancy<3, 4>()
-                  : sx == 2 && sy == 2 ? census_occupancy<2, 2>()
-                  : sx == 4 && sy == 3 ? census_occupancy<4, 3>()
-                                       : census_occupancy<-1, -1>();
-  const int G = std::max(1, n_cu) * occ;
-  // lists pay off once every persistent workgroup has several tiles to make (measured:
-  // the 2550 tiles of a 1080p frame run faster one workgroup per tile, the 45600 of a
-  // 16-frame batch faster listed)
-  const int listed = use_list && n_census_tiles <= 32 * kCensusListWords && 8 * G <= n_census_tiles;
-  const dim3 grid(FR.n + (listed ? G : n_census_tiles)), block(256);
+                               int sentinel, int n_census_tiles, hipStream_t stream,
+                               const LaunchTimer* timer) {
+  const dim3 grid(FR.n + n_census_tiles), block(256);
   auto kernel = sx == 3 && sy == 4   ? frame_census_kernel<3, 4>
                 : sx == 2 && sy == 2 ? frame_census_kernel<2, 2>
                 : sx == 4 && sy == 3 ? frame_census_kernel<4, 3>
                                      : frame_census_kernel<-1, -1>;
   return timed_launch(timer, "census", kernel, grid, block, 0, stream, P, FR, boxes, ws, sx, sy,
-                      sentinel, n_census_tiles, listed);
+                      sentinel);
 }
 
 template <int SX, int SY>

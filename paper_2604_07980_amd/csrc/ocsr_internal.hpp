@@ -35,10 +35,6 @@ struct CensusJobsDev {
 // census tile: 64 columns x 32 rows of level pixels per workgroup of 256 threads
 constexpr int kCensusTileX = 64;
 constexpr int kCensusTileY = 32;
-// persistent census of whole-frame calls: tiles a call may have (bitmap words in LDS)
-// and tiles a workgroup lists at a time
-constexpr int kCensusListWords = 2048;
-constexpr int kCensusListCap = 256;
 // plan step of whole-frame calls: the census tiles of one frame it can list (bitmap
 // words in LDS); frames with more tiles take the per-tile census
 constexpr int kFrameTileWords = 4096;
@@ -244,13 +240,12 @@ int variant_candidates(const PathDev& ph, int* rows, int* cpl, int* passes, int 
 
 // Census of every view and level of every frame, and the plan of every frame, in one
 // launch (frames whose images are given).
-// Census (and plan) launch of a whole-frame call. With use_list set and the call's tiles
-// within the LDS bitmap, up to n_cu x (resident workgroups per CU) persistent workgroups
-// make the listed tiles; otherwise one workgroup per tile tests and makes its own.
+// Census (and plan) launch of a whole-frame call: one workgroup per census tile tests
+// whether some box's search reads its tile and makes it if so; one more per frame plans it.
 hipError_t launch_frame_census(const MatchParamsDev& p, const FramesDev& fr,
                                const ocsr_box* boxes, const MatchWs& ws, int sx, int sy,
-                               int sentinel, int n_census_tiles, int n_cu, bool use_list,
-                               hipStream_t stream, const LaunchTimer* timer);
+                               int sentinel, int n_census_tiles, hipStream_t stream,
+                               const LaunchTimer* timer);
 
 // Plan of every frame of a whole-frame call, with the list of the census tiles its boxes'
 // searches read (one workgroup per frame), then the census of the listed tiles by
@@ -273,12 +268,12 @@ hipError_t launch_match(const MatchParamsDev& p, const FramesDev& fr, const ocsr
 // Fused path: census of every frame, planning, matching and aggregation in one
 // persistent launch of co-resident workgroups (after a counter reset). Returns
 // hipErrorNotSupported when no fused kernel is built for this census window and pair of
-// path variants. wgs_per_cu caps the workgroups per compute unit (0: as many as fit).
+// path variants, or when a frame has more census tiles than the plan step can list.
+// wgs_per_cu caps the workgroups per compute unit (0: the library default, 2).
 hipError_t launch_fused(const MatchParamsDev& p, const FramesDev& fr, const ocsr_box* boxes,
                         const MatchWs& ws, ocsr_box_result* out, int sx, int sy, int sentinel,
-                        int n_census_tiles, int n_cu, int wgs_per_cu, hipStream_t stream,
-                        const LaunchTimer* timer);
-bool fused_available(const MatchParamsDev& p, int sx, int sy, int n_census_tiles);
+                        int n_cu, int wgs_per_cu, hipStream_t stream, const LaunchTimer* timer);
+bool fused_available(const MatchParamsDev& p, const FramesDev& fr, int sx, int sy);
 
 // Dense counterpart: left-view and right-view winner-take-all over [dmin, dmax] of the
 // (2 radius + 1)^2 window sums of Hamming costs, then the left/right check. d_left and
