@@ -710,6 +710,20 @@ __device__ __forceinline__ void half_costs(const uint64_t* __restrict__ T, const
     acc[c] += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)acc[c], 0xB1, 0xF, 0xF, false);
 }
 
+// Whether point (fx, fy) lies in one of the rectangles held by the lanes of m (each lane
+// o holds the clipped box co).
+__device__ __forceinline__ bool in_lane_rects(uint64_t m, const BoxClip& co, int fx, int fy) {
+  bool hidden = false;
+  while (m) {
+    const int src = __ffsll((unsigned long long)m) - 1;
+    m &= m - 1;
+    const int x0 = __builtin_amdgcn_readlane(co.cx0, src), x1 = __builtin_amdgcn_readlane(co.cx1, src);
+    const int y0 = __builtin_amdgcn_readlane(co.cy0, src), y1 = __builtin_amdgcn_readlane(co.cy1, src);
+    hidden |= fx >= x0 && fx < x1 && fy >= y0 && fy < y1;
+  }
+  return hidden;
+}
+
 // Occlusion mask of a TILED block (Sec. 4.3.5) in the 8-column layout: bit j*8 + i is
 // set iff point (i, j) exists (i < nx, j < ny) and lies in no box of the frame that
 // overlaps box k and has a larger bottom y. Lane l tests point (l & 7, l >> 3).
@@ -728,15 +742,46 @@ __device__ __forceinline__ uint64_t tiled_mask8(const MatchWs& ws, int box_off, 
     const bool occ = o < n && o != k && ck.cx0 < co.cx1 && co.cx0 < ck.cx1 && ck.cy0 < co.cy1 &&
                      co.cy0 < ck.cy1 && co.cy1 > ck.cy1 && co.cx0 <= bx1 && co.cx1 > bx0 &&
                      co.cy0 <= by1 && co.cy1 > by0;
-    uint64_t m = __ballot(occ);
-    while (m) {
-      const int src = __ffsll((unsigned long long)m) - 1;
-      m &= m - 1;
-      const int x0 = __builtin_amdgcn_readlane(co.cx0, src), x1 = __builtin_amdgcn_readlane(co.cx1, src);
-      const int y0 = __builtin_amdgcn_readlane(co.cy0, src), y1 = __builtin_amdgcn_readlane(co.cy1, src);
-      hidden |= fx >= x0 && fx < x1 && fy >= y0 && fy < y1;
-    }
+    hidden |= in_lane_rects(__ballot(occ), co, fx, fy);
   }
+  return __ballot(exists && !hidden);
+}
+
+// The boxes that may hide points of box k, for all blocks of one work item of a frame of
+// at most 64 boxes (in_lanes; otherwise each block scans the frame's boxes itself):
+// lane o holds box o's clipped rectangle, and bit o of `cand` is set iff box o overlaps
+// box k and has the larger bottom y, the part of tiled_mask8's test that does not depend
+// on the block.
+struct OccLanes {
+  BoxClip co;
+  uint64_t cand;
+  bool in_lanes;
+};
+__device__ __forceinline__ OccLanes box_occluders(const MatchWs& ws, int box_off, int n, int k,
+                                                  int lane) {
+  OccLanes oc{BoxClip{0, 0, 0, 0}, 0ull, n <= 64};
+  if (oc.in_lanes) {
+    const BoxClip ck = ws.clip[box_off + k];
+    const BoxClip co = lane < n ? ws.clip[box_off + lane] : BoxClip{0, 0, 0, 0};
+    oc.co = co;
+    oc.cand = __ballot(lane < n && lane != k && ck.cx0 < co.cx1 && co.cx0 < ck.cx1 &&
+                       ck.cy0 < co.cy1 && co.cy0 < ck.cy1 && co.cy1 > ck.cy1);
+  }
+  return oc;
+}
+// tiled_mask8 from the rectangles of box_occluders
+__device__ __forceinline__ uint64_t tiled_mask8_lanes(const OccLanes& oc, int s, int cx, int cy,
+                                                      int nx, int ny, int lane) {
+  const int pi = lane & 7, pj = lane >> 3;
+  const bool exists = pi < nx && pj < ny;
+  const int fx = s * (cx + pi), fy = s * (cy + pj);
+  const int bx0 = s * cx, bx1 = s * (cx + nx - 1);
+  const int by0 = s * cy, by1 = s * (cy + ny - 1);
+  const BoxClip co = oc.co;
+  const bool occ = ((oc.cand >> lane) & 1ull) && co.cx0 <= bx1 && co.cx1 > bx0 && co.cy0 <= by1 &&
+                   co.cy1 > by0;
+  // the ballot of candidates is taken by the whole wave (lanes past the block hold boxes too)
+  const bool hidden = in_lane_rects(__ballot(occ), co, fx, fy);
   return __ballot(exists && !hidden);
 }
 
@@ -746,10 +791,14 @@ __device__ __forceinline__ uint64_t pack_mask8(uint64_t m8, int nx, int ny, int 
   return __ballot(lane < nx * ny && ((m8 >> (8 * j + i)) & 1ull));
 }
 
+// oc: the box's occluders when the frame's boxes fit the lanes (box_occluders). The
+// occlusion mask comes first (from registers in that case), so that a block that is not
+// eligible loads no strip.
 template <int CPL>
 __device__ __forceinline__ void match_block_half(const MatchParamsDev& P, const FrameDev& fr,
                                                  const MatchWs& ws, const DebugDev& dbg,
-                                                 const BlockCtx& c, int lane, void* lds) {
+                                                 const BlockCtx& c, const OccLanes& oc, int lane,
+                                                 void* lds) {
   using HH = Half<CPL>;
   constexpr int SWP = HH::SWP, CH = HH::CH, NC = HH::NC;
   uint64_t* S = (uint64_t*)lds;
@@ -766,9 +815,16 @@ __device__ __forceinline__ void match_block_half(const MatchParamsDev& P, const 
   const int W = lv.W;
   const uint64_t* __restrict__ Lb = uniform(lv.L + (size_t)Y0 * lv.pitch);
   const uint64_t* __restrict__ Rb = uniform(lv.R + (size_t)Y0 * lv.pitch);
-  const int sw = nd + nx - 1;
-  // forward strip CR(X0 - dhi + m, Y0 + j) and template CL(X0 + i, Y0 + j): their loads
-  // and the occluder scan's are in flight together (one wait for all of them)
+  const uint64_t m8 = oc.in_lanes ? tiled_mask8_lanes(oc, c.g.s, X0, Y0, nx, ny, lane)
+                                  : tiled_mask8(ws, fr.box_off, fr.n_boxes, c.k, c.g.s, X0, Y0, nx, ny, lane);
+  const int npts = __popcll(m8);
+  const bool eligible = npts > 0 && 100 * npts >= P.min_point_pct * nx * ny;
+  if (!eligible) {
+    const uint64_t mask = dbg.blocks ? pack_mask8(m8, nx, ny, lane) : 0ull;
+    write_block(ws, dbg, c, ph, mask, false, dlo, dlo, 0, (float)dlo, 0, lane);
+    return;
+  }
+  // forward strip CR(X0 - dhi + m, Y0 + j) and template CL(X0 + i, Y0 + j), loaded together
   const HalfStrip<CH> fw = load_half_strip<SWP, CH>(Rb, lv.pitch, X0 - dhi, ny, W, lane);
   uint64_t tw;
   {
@@ -777,18 +833,9 @@ __device__ __forceinline__ void match_block_half(const MatchParamsDev& P, const 
     tw = Lb[ok ? (size_t)jj * lv.pitch + X0 + i : 0];
     tw = ok ? tw : 0ull;
   }
-  const uint64_t m8 = tiled_mask8(ws, fr.box_off, fr.n_boxes, c.k, c.g.s, X0, Y0, nx, ny, lane);
   store_half_strip<SWP, CH>(S, fw, lane);
   T[tslot] = tw;
-  const int npts = __popcll(m8);
-  const bool eligible = npts > 0 && 100 * npts >= P.min_point_pct * nx * ny;
   wave_sync();
-  if (!eligible) {
-    const uint64_t mask = dbg.blocks ? pack_mask8(m8, nx, ny, lane) : 0ull;
-    write_block(ws, dbg, c, ph, mask, false, dlo, dlo, 0, (float)dlo, 0, lane);
-    wave_sync();
-    return;
-  }
   const bool full = m8 == ~0ull;   // an 8 x 8 block with every point kept
   const uint32_t keep = (uint32_t)(m8 >> (32 * h));
   uint32_t acc[CPL];
@@ -1358,15 +1405,19 @@ __device__ __forceinline__ void match_block_dy(const MatchParamsDev& P, const Fr
 
 // Work item of frame f at `level` from its record: wave w of the workgroup runs blocks
 // r.first + w + 4 j of the box that exist.
-template <class RunBlock>
-__device__ __forceinline__ void run_item_rec(const MatchParamsDev& P, const FrameDev& fr, int f,
-                                             int level, const ItemRec& r, int wave, RunBlock run) {
+__device__ __forceinline__ BoxPlan item_plan(const ItemRec& r, int f, int level) {
   BoxPlan pl = {};
   pl.status = -1;
   pl.level = level;
   pl.lx0 = r.lx0; pl.ly0 = r.ly0; pl.lw = r.lw; pl.lh = r.lh;
   pl.nbx = r.nbx; pl.bw = r.bw; pl.bh = r.bh; pl.ox = r.ox; pl.oy = r.oy;
   pl.off = r.off; pl.nblk = r.nblk; pl.frame = f;
+  return pl;
+}
+template <class RunBlock>
+__device__ __forceinline__ void run_item_rec(const MatchParamsDev& P, const FrameDev& fr, int f,
+                                             int level, const ItemRec& r, int wave, RunBlock run) {
+  const BoxPlan pl = item_plan(r, f, level);
   // the wave's blocks step by kItemWaves along the grid's rows: one division per item
   int local = r.first + wave;
   int v = local / pl.nbx, u = local - v * pl.nbx;
@@ -1807,8 +1858,9 @@ struct HalfMatcher {
                                                   const MatchWs& ws, const DebugDev& dbg, int f,
                                                   int level, const ItemRec& r, int wave, int lane,
                                                   void* lds) {
+    const OccLanes oc = box_occluders(ws, fr.box_off, fr.n_boxes, r.k, lane);
     run_item_rec(P, fr, f, level, r, wave, [&](const BlockCtx& c) {
-      match_block_half<CPL>(P, fr, ws, dbg, c, lane, lds);
+      match_block_half<CPL>(P, fr, ws, dbg, c, oc, lane, lds);
     });
   }
 };
