@@ -500,10 +500,10 @@ int32_t ocsr_rect_filter_update(ocsr_rect_filter* f, const int32_t* counts, int3
 #define OCSR_OPTION_FULL_CENSUS 6
 /* OCSR_OPTION_CENSUS_TILE_LIST: 1 (default) lets whole-frame and batch calls with at
  * least 8 tiles of 64 x 32 level pixels per resident workgroup slot of the GPU (and at
- * most 65536 tiles) make the census with persistent workgroups, one per slot, that each
- * list the tiles to make from the boxes and take an equal share of them; other calls,
- * and every call with 0, launch one workgroup per tile, which makes its tile or leaves.
- * Results and the tiles made are the same either way. */
+ * most 131072 tiles in any frame) make the census with persistent workgroups, one per
+ * slot, that each list the tiles to make from the boxes and take an equal share of
+ * them; other calls, and every call with 0, launch one workgroup per tile, which makes
+ * its tile or leaves. Results and the tiles made are the same either way. */
 #define OCSR_OPTION_CENSUS_TILE_LIST 7
 /* OCSR_OPTION_LEVEL_LAUNCHES: how the blocks of the two levels are matched. 0 (default):
  * one launch for both levels in calls of one frame when a kernel for the pair of chosen

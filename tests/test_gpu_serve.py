@@ -33,7 +33,9 @@ def _stream(n, seed=77, rate=4000.0):
 
 
 def test_served_equals_alone_and_oracle(lib, orc):
-    reqs, host = _stream(60)
+    # arrivals 1 us apart: requests queue behind the first batches whatever the GPU's
+    # speed, so batches of several frames must form
+    reqs, host = _stream(60, rate=1e6)
     ex = serve.GpuExecutor(n_slots=3)
     budget = 3 * ex.bytes_needed(reqs[:8])
     srv = serve.Server(ex, mem_budget=budget)
