@@ -100,16 +100,18 @@ def reset(params: dict, device: int | None = None) -> None:
 
 def tune(run, params: dict, reps: int = 20, warmup: int = 3,
          blocks_per_wave=BLOCKS_PER_WAVE, match_wgs_per_cu=MATCH_WGS_PER_CU,
-         device: int | None = None, rounds: int = 2) -> Table:
+         device: int | None = None, rounds: int = 2, margin: float = 0.01) -> Table:
     """Tunes the matching launches for the workload `run` (a callable that submits one
     call and returns its result tensor) with parameters `params`.
 
     Coordinate descent: the variant of each path shape in turn (the others at their
     current best), then blocks per wave, then the grid, then one or two matching
     launches; `rounds` passes over all of them, each starting from the last's choices.
-    Every choice's output must equal the default configuration's exactly; a choice that
-    differs raises, since it would be a library defect. The chosen configuration is left
-    installed."""
+    Each coordinate keeps its current setting (the library default in the first round)
+    unless another is faster by more than `margin` (a fraction of its time), so that
+    timing noise does not move it. Every choice's output must equal the default
+    configuration's exactly; a choice that differs raises, since it would be a library
+    defect. The chosen configuration is left installed."""
     reset(params, device)
     ref = _snapshot(run())
     table = Table(arch=_arch())
@@ -122,44 +124,48 @@ def tune(run, params: dict, reps: int = 20, warmup: int = 3,
         table.timings_ms[label] = round(ms, 5)
         return ms
 
+    def pick(current, candidates, apply, label):
+        """The fastest of `candidates`, measured after `current`; another replaces
+        `current` only when faster by more than the margin. Leaves the pick applied."""
+        apply(current)
+        best_ms, best = measure(label(current)), current
+        for c in candidates:
+            if c == current:
+                continue
+            apply(c)
+            ms = measure(label(c))
+            if ms < best_ms * (1.0 - margin):
+                best_ms, best = ms, c
+        apply(best)
+        return best
+
+    bpw_now, wgs_now, mode_now = DEFAULT_BLOCKS_PER_WAVE, DEFAULT_MATCH_WGS_PER_CU, 0
     for rnd in range(rounds):
         for bw, bh, nd in path_shapes(params):
-            best = None
-            for rows, cpl, passes in ocsr.variant_candidates(bw, bh, nd):
-                ocsr.set_variant(bw, bh, nd, rows, cpl, passes, device)
-                ms = measure(f"round {rnd} variant {shape_key(bw, bh, nd)} rows={rows} cpl={cpl} passes={passes}")
-                if best is None or ms < best[0]:
-                    best = (ms, rows, cpl, passes)
-            if best is not None:
-                ocsr.set_variant(bw, bh, nd, best[1], best[2], best[3], device)
-                table.variants[shape_key(bw, bh, nd)] = [best[1], best[2], best[3]]
+            cands = [tuple(v) for v in ocsr.variant_candidates(bw, bh, nd)]
+            if not cands:
+                continue
+            key = shape_key(bw, bh, nd)
+            # the library's default for the shape is the first candidate
+            now = tuple(table.variants.get(key, cands[0]))
+            best = pick(now, cands, lambda v: ocsr.set_variant(bw, bh, nd, *v, device),
+                        lambda v: f"round {rnd} variant {key} rows={v[0]} cpl={v[1]} passes={v[2]}")
+            table.variants[key] = list(best)
 
-        best = None
-        for bpw in blocks_per_wave:
-            ocsr.set_option(ocsr.OPTION_BLOCKS_PER_WAVE, bpw, device)
-            ms = measure(f"round {rnd} blocks_per_wave={bpw}")
-            if best is None or ms < best[0]:
-                best = (ms, bpw)
-        table.blocks_per_wave = best[1]
-        ocsr.set_option(ocsr.OPTION_BLOCKS_PER_WAVE, table.blocks_per_wave, device)
+        bpw_now = pick(bpw_now, list(blocks_per_wave),
+                       lambda v: ocsr.set_option(ocsr.OPTION_BLOCKS_PER_WAVE, v, device),
+                       lambda v: f"round {rnd} blocks_per_wave={v}")
+        table.blocks_per_wave = bpw_now
 
-        best = None
-        for g in match_wgs_per_cu:
-            ocsr.set_option(ocsr.OPTION_MATCH_WGS_PER_CU, g, device)
-            ms = measure(f"round {rnd} match_wgs_per_cu={g}")
-            if best is None or ms < best[0]:
-                best = (ms, g)
-        table.match_wgs_per_cu = best[1]
-        ocsr.set_option(ocsr.OPTION_MATCH_WGS_PER_CU, table.match_wgs_per_cu, device)
+        wgs_now = pick(wgs_now, list(match_wgs_per_cu),
+                       lambda v: ocsr.set_option(ocsr.OPTION_MATCH_WGS_PER_CU, v, device),
+                       lambda v: f"round {rnd} match_wgs_per_cu={v}")
+        table.match_wgs_per_cu = wgs_now
 
-        best = None
-        for mode in (0, 1, 2):
-            ocsr.set_option(ocsr.OPTION_LEVEL_LAUNCHES, mode, device)
-            ms = measure(f"round {rnd} level_launches={mode}")
-            if best is None or ms < best[0]:
-                best = (ms, mode)
-        table.level_launches = best[1]
-        ocsr.set_option(ocsr.OPTION_LEVEL_LAUNCHES, table.level_launches, device)
+        mode_now = pick(mode_now, [0, 1, 2],
+                        lambda v: ocsr.set_option(ocsr.OPTION_LEVEL_LAUNCHES, v, device),
+                        lambda v: f"round {rnd} level_launches={v}")
+        table.level_launches = mode_now
     return table
 
 

@@ -70,3 +70,45 @@ def test_table_round_trip(built):
 def test_invalid_tables_rejected(built, bad):
     with pytest.raises(ValueError):
         autotune.from_json(bad)
+
+
+def test_tune_keeps_the_current_setting_within_the_margin(monkeypatch):
+    """The search over a simulated library: a setting replaces the current one only when
+    it is faster by more than the margin, so noise-level differences keep the defaults."""
+    state = {"variant": {}, "opts": {}}
+    cands = {(4, 4, 32): [(1, 2, 1), (1, 4, 1)], (8, 8, 96): [(2, 3, 1), (2, 4, 1), (8, 12, 1)]}
+    monkeypatch.setattr(autotune.ocsr, "variant_candidates", lambda bw, bh, nd, device=None: cands[(bw, bh, nd)])
+    monkeypatch.setattr(autotune.ocsr, "set_variant",
+                        lambda bw, bh, nd, r, c, p, device=None: state["variant"].__setitem__((bw, bh, nd), (r, c, p)))
+    monkeypatch.setattr(autotune.ocsr, "set_option",
+                        lambda o, v, device=None: state["opts"].__setitem__(o, v))
+    monkeypatch.setattr(autotune, "_arch", lambda: "gfx950")
+    monkeypatch.setattr(autotune, "path_shapes", lambda params: [(4, 4, 32), (8, 8, 96)])
+    monkeypatch.setattr(autotune, "_snapshot", lambda r: r)
+
+    import numpy as np
+
+    def run():
+        return np.zeros(4)
+
+    def cost():
+        v = state["variant"]
+        o = state["opts"]
+        ms = 1.0
+        ms -= 0.005 if v.get((4, 4, 32)) == (1, 4, 1) else 0.0     # within the margin: kept out
+        ms -= 0.10 if v.get((8, 8, 96)) == (8, 12, 1) else 0.0     # a clear win: taken
+        ms -= 0.05 if o.get(ocsr.OPTION_BLOCKS_PER_WAVE) == 4 else 0.0
+        ms -= 0.004 if o.get(ocsr.OPTION_LEVEL_LAUNCHES) == 2 else 0.0
+        return ms
+
+    monkeypatch.setattr(autotune, "_time_ms", lambda run, reps, warmup: cost())
+    table = autotune.tune(run, {}, reps=1, warmup=0)
+    assert table.variants == {"4x4/32": [1, 2, 1], "8x8/96": [8, 12, 1]}
+    assert table.blocks_per_wave == 4
+    assert table.match_wgs_per_cu == autotune.DEFAULT_MATCH_WGS_PER_CU
+    assert table.level_launches == 0
+    # the installed configuration is the table's
+    assert state["variant"][(8, 8, 96)] == (8, 12, 1) and state["opts"][ocsr.OPTION_LEVEL_LAUNCHES] == 0
+    # with no margin the small gains are taken too
+    table0 = autotune.tune(run, {}, reps=1, warmup=0, margin=0.0)
+    assert table0.variants["4x4/32"] == [1, 4, 1] and table0.level_launches == 2
