@@ -72,6 +72,9 @@ def parse():
                          "(the reference kernel that scales the HBM byte counters)")
     ap.add_argument("--int-peak", action="store_true",
                     help="only measure the int32 vector-ALU rate with the library's chain kernel")
+    ap.add_argument("--batch-frames", type=int, default=BATCH_FRAMES, choices=range(1, BATCH_FRAMES + 1),
+                    metavar="N", help="time a batch of the first N of the 16 frames (16, the default, "
+                    "is the headline workload; fewer give the launches' cost against the work)")
     ap.add_argument("--fused", action="store_true",
                     help="time the headline batch as the one-launch persistent kernel")
     return ap.parse_args()
@@ -102,7 +105,7 @@ def render_inputs(args):
         for k, res in enumerate(synth.SERVING_RESOLUTIONS):
             pool_jobs += [(res, i, 5000 + k) for i in range(args.serve_pool)]
     with cf.ProcessPoolExecutor(max_workers=workers) as ex:
-        frames = list(ex.map(_render_batch_frame, range(BATCH_FRAMES)))
+        frames = list(ex.map(_render_batch_frame, range(args.batch_frames)))
         pairs = list(ex.map(_render_pool_pair, pool_jobs))
     pools = [[] for _ in synth.SERVING_RESOLUTIONS]
     for (res, _, _), pair in zip(pool_jobs, pairs):
@@ -343,11 +346,11 @@ def batch_workload(ocsr, scenes, args):
     price(kern, ops)
 
     res = {
-        "workload": "batch_16x1920x1200: 16 uint8 stereo pairs, min(128, Poisson(40)) boxes per "
+        "workload": f"batch_{len(frames)}x1920x1200: {len(frames)} uint8 stereo pairs, min(128, Poisson(40)) boxes per "
                     "frame (log-uniform 12..512 px, overlaps occlude), far 4x4 blocks d 0..31 at "
                     "s=1, close 8x8 blocks d 0..191 at s=2, census 7x9 on the tiles the searches "
                     "read, trimmed median; one ocsr_range_batch call per step",
-        "frames": BATCH_FRAMES, "boxes": int(boxes.shape[0]), "blocks": sum(w["blocks"] for w in work),
+        "frames": len(frames), "boxes": int(boxes.shape[0]), "blocks": sum(w["blocks"] for w in work),
         "costs_per_batch": costs, "costs_far": costs_far, "block_evals_per_batch": evals,
         "census_level_px": census_px, "census_level_px_all_tiles": census_px_full,
     }
@@ -690,7 +693,7 @@ def main():
     torch.cuda.set_device(torch.device("cuda:0"))
     int_rate, _ = ocsr.measure_int_rate(4096)
 
-    # headline: the 16-frame batch
+    # headline: the 16-frame batch (or its first --batch-frames frames)
     p3, bres, bdetails, ms, kern = batch_workload(ocsr, scenes, args)
     log(f"batch: {ms:.4f} ms per batch")
     costs = bres["costs_per_batch"]
@@ -699,7 +702,7 @@ def main():
     ach = kern[dom]["tops"]
     roofline = {"kernel": dom, "bound": "alu", "achieved": ach, "peak": round(INT_PEAK_TOPS, 2),
                 "unit": "TOP/s", "frac": round(ach / INT_PEAK_TOPS, 4),
-                "traffic": measured_traffic(dom, "batch_16x1920x1200"),
+                "traffic": measured_traffic(dom, f"batch_{args.batch_frames}x1920x1200"),
                 "ops_per_launch": work[dom], "avg_us": kern[dom]["avg_us"],
                 "peak_measured": round(int_rate / 1e12, 3)}
     res = {
