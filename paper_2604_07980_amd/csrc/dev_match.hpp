@@ -757,19 +757,23 @@ struct OccLanes {
   uint64_t cand;
   bool in_lanes;
 };
-__device__ __forceinline__ OccLanes box_occluders(const MatchWs& ws, int box_off, int n, int k,
-                                                  int lane) {
+// The frame's part, which does not depend on k (so its load need not wait for an item
+// record): lane o holds box o's clipped rectangle.
+__device__ __forceinline__ OccLanes frame_lanes(const MatchWs& ws, int box_off, int n, int lane) {
   OccLanes oc{BoxClip{0, 0, 0, 0}, 0ull, n <= 64};
-  if (oc.in_lanes) {
-    const BoxClip ck = ws.clip[box_off + k];
-    const BoxClip co = lane < n ? ws.clip[box_off + lane] : BoxClip{0, 0, 0, 0};
-    oc.co = co;
-    oc.cand = __ballot(lane < n && lane != k && ck.cx0 < co.cx1 && co.cx0 < ck.cx1 &&
-                       ck.cy0 < co.cy1 && co.cy0 < ck.cy1 && co.cy1 > ck.cy1);
-  }
+  if (oc.in_lanes && lane < n) oc.co = ws.clip[box_off + lane];
   return oc;
 }
-// tiled_mask8 from the rectangles of box_occluders
+// Box k's candidates (box k's own rectangle from lane k).
+__device__ __forceinline__ void box_candidates(OccLanes& oc, int n, int k, int lane) {
+  if (!oc.in_lanes) return;
+  const BoxClip co = oc.co;
+  const BoxClip ck{__builtin_amdgcn_readlane(co.cx0, k), __builtin_amdgcn_readlane(co.cy0, k),
+                   __builtin_amdgcn_readlane(co.cx1, k), __builtin_amdgcn_readlane(co.cy1, k)};
+  oc.cand = __ballot(lane < n && lane != k && ck.cx0 < co.cx1 && co.cx0 < ck.cx1 &&
+                     ck.cy0 < co.cy1 && co.cy0 < ck.cy1 && co.cy1 > ck.cy1);
+}
+// tiled_mask8 from the rectangles of frame_lanes and box_candidates
 __device__ __forceinline__ uint64_t tiled_mask8_lanes(const OccLanes& oc, int s, int cx, int cy,
                                                       int nx, int ny, int lane) {
   const int pi = lane & 7, pj = lane >> 3;
@@ -791,9 +795,9 @@ __device__ __forceinline__ uint64_t pack_mask8(uint64_t m8, int nx, int ny, int 
   return __ballot(lane < nx * ny && ((m8 >> (8 * j + i)) & 1ull));
 }
 
-// oc: the box's occluders when the frame's boxes fit the lanes (box_occluders). The
-// occlusion mask comes first (from registers in that case), so that a block that is not
-// eligible loads no strip.
+// oc: the box's occluders when the frame's boxes fit the lanes (frame_lanes,
+// box_candidates). The occlusion mask comes first (from registers in that case), so that
+// a block that is not eligible loads no strip.
 template <int CPL>
 __device__ __forceinline__ void match_block_half(const MatchParamsDev& P, const FrameDev& fr,
                                                  const MatchWs& ws, const DebugDev& dbg,
@@ -1435,12 +1439,15 @@ __device__ __forceinline__ void run_item_rec(const MatchParamsDev& P, const Fram
 // Loop of a workgroup over the work items of one level of every frame (frames in
 // order, each frame's items in box order), dealt XCD by XCD (xcd_deal). Item numbers
 // come from the workgroup index, so the loop is uniform across the workgroup and needs
-// no shared counter. body(f, q) gets the frame and the item number within the frame's level.
+// no shared counter. body(f, q, at) gets the frame, the item number within the frame's
+// level and the item's record within the frame's records (close items first, then far).
 template <class Body>
 __device__ __forceinline__ void level_items(const FramesDev& FR, const MatchWs& ws, int level,
                                             Body body) {
   const int lane = threadIdx.x & 63;
-  const int cnt = lane < FR.n ? ws.fcount[lane * FC_N + (level == 0 ? FC_FAR_ITEMS : FC_CLOSE_ITEMS)] : 0;
+  const int n_close = lane < FR.n ? ws.fcount[lane * FC_N + FC_CLOSE_ITEMS] : 0;
+  const int n_far = lane < FR.n ? ws.fcount[lane * FC_N + FC_FAR_ITEMS] : 0;
+  const int cnt = level == 0 ? n_far : n_close;
   const int incl = wave_incl_scan(cnt, lane);
   const int total = __builtin_amdgcn_readfirstlane(__shfl(incl, 63, 64));
   const Deal dl = xcd_deal(total);
@@ -1448,7 +1455,8 @@ __device__ __forceinline__ void level_items(const FramesDev& FR, const MatchWs& 
     const uint64_t m = __ballot(lane < FR.n && incl > q);
     const int f = __ffsll((unsigned long long)m) - 1;
     const int excl = __builtin_amdgcn_readfirstlane(__shfl(incl - cnt, f, 64));
-    body(f, q - excl);
+    const int skip = level == 0 ? __builtin_amdgcn_readlane(n_close, f) : 0;
+    body(f, q - excl, q - excl + skip);
   }
 }
 
@@ -1839,26 +1847,37 @@ __device__ __forceinline__ void aggregate_box(const MatchParamsDev& P, const Mat
 // kernel (ROWS block rows per wave, CPL candidates per lane, PASSES passes) and the
 // row-half kernel (32 CPL candidates per wave).
 // run_item: wave `wave`'s share of work item r (frame f, level `level`).
+// frame_state: what a matcher reads per frame before an item's record arrives (issued
+// first, so that its loads and the record's are in flight together).
+struct NoFrameState {};
 template <int ROWS, int NX, int CPL, int PASSES>
 struct TiledMatcher {
   static constexpr size_t kLds = (Tiled<ROWS, NX, CPL, PASSES>::kLdsBytes + 15) & ~(size_t)15;
+  using State = NoFrameState;
+  static __device__ __forceinline__ State frame_state(const MatchWs&, const FrameDev&, int) { return {}; }
   static __device__ __forceinline__ void run_item(const MatchParamsDev& P, const FrameDev& fr,
                                                   const MatchWs& ws, const DebugDev& dbg, int f,
                                                   int level, const ItemRec& r, int wave, int lane,
-                                                  void* lds) {
+                                                  void* lds, const State& = State()) {
     run_item_rec(P, fr, f, level, r, wave, [&](const BlockCtx& c) {
       match_block_tiled<ROWS, NX, CPL, PASSES>(P, fr, ws, dbg, c, lane, lds);
     });
   }
 };
+// (its frame state: the frame's box rectangles in lanes, when they fit)
 template <int CPL>
 struct HalfMatcher {
   static constexpr size_t kLds = (Half<CPL>::kLdsBytes + 15) & ~(size_t)15;
+  using State = OccLanes;
+  static __device__ __forceinline__ State frame_state(const MatchWs& ws, const FrameDev& fr, int lane) {
+    return frame_lanes(ws, fr.box_off, fr.n_boxes, lane);
+  }
   static __device__ __forceinline__ void run_item(const MatchParamsDev& P, const FrameDev& fr,
                                                   const MatchWs& ws, const DebugDev& dbg, int f,
                                                   int level, const ItemRec& r, int wave, int lane,
-                                                  void* lds) {
-    const OccLanes oc = box_occluders(ws, fr.box_off, fr.n_boxes, r.k, lane);
+                                                  void* lds, const State& st) {
+    OccLanes oc = st;
+    box_candidates(oc, fr.n_boxes, r.k, lane);
     run_item_rec(P, fr, f, level, r, wave, [&](const BlockCtx& c) {
       match_block_half<CPL>(P, fr, ws, dbg, c, oc, lane, lds);
     });
@@ -1867,10 +1886,12 @@ struct HalfMatcher {
 // any block of up to 64 points (GRID blocks included), lanes over candidates
 struct GenericMatcher {
   static constexpr size_t kLds = kGenericLdsBytes;
+  using State = NoFrameState;
+  static __device__ __forceinline__ State frame_state(const MatchWs&, const FrameDev&, int) { return {}; }
   static __device__ __forceinline__ void run_item(const MatchParamsDev& P, const FrameDev& fr,
                                                   const MatchWs& ws, const DebugDev& dbg, int f,
                                                   int level, const ItemRec& r, int wave, int lane,
-                                                  void* lds) {
+                                                  void* lds, const State& = State()) {
     run_item_rec(P, fr, f, level, r, wave, [&](const BlockCtx& c) {
       match_block_generic(P, fr, ws, dbg, c, lane, lds);
     });
@@ -1880,10 +1901,12 @@ struct GenericMatcher {
 template <int CPL>
 struct QuadMatcher {
   static constexpr size_t kLds = (Quad<CPL>::kLdsBytes + 15) & ~(size_t)15;
+  using State = NoFrameState;
+  static __device__ __forceinline__ State frame_state(const MatchWs&, const FrameDev&, int) { return {}; }
   static __device__ __forceinline__ void run_item(const MatchParamsDev& P, const FrameDev& fr,
                                                   const MatchWs& ws, const DebugDev& dbg, int f,
                                                   int level, const ItemRec& r, int wave, int lane,
-                                                  void* lds) {
+                                                  void* lds, const State& = State()) {
     const int first = r.first + 4 * wave;
     if (first < r.nblk && first < r.first + P.item_blocks[level])
       match_blocks_quad<CPL>(P, fr, ws, dbg, f, level, r, first, lane, lds);

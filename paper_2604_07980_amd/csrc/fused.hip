@@ -102,9 +102,16 @@ __global__ __launch_bounds__(256) void fused_kernel(MatchParamsDev P, FramesDev 
       const FrameDev& fr = FR.f[f];
       const int q = m - mprefix[slot];
       const int at = q + (slot < F ? 0 : mprefix[f + 1] - mprefix[f]);
-      const ItemRec rec = ws.items[(size_t)f * ws.items_cap + at];
-      if (slot < F) CM::run_item(P, fr, ws, DebugDev{}, f, 1, rec, wave, lane, wl);
-      else FM::run_item(P, fr, ws, DebugDev{}, f, 0, rec, wave, lane, wl);
+      const ItemRec* rp = ws.items + (size_t)f * ws.items_cap + at;
+      if (slot < F) {
+        const typename CM::State st = CM::frame_state(ws, fr, lane);
+        const ItemRec rec = *rp;
+        CM::run_item(P, fr, ws, DebugDev{}, f, 1, rec, wave, lane, wl, st);
+      } else {
+        const typename FM::State st = FM::frame_state(ws, fr, lane);
+        const ItemRec rec = *rp;
+        FM::run_item(P, fr, ws, DebugDev{}, f, 0, rec, wave, lane, wl, st);
+      }
     }
   }
   __syncthreads();

@@ -100,10 +100,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(tiled_waves
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int lane = threadIdx.x & 63;
   void* wl = (char*)lds + wave * kWave;
-  dev::level_items(FR, ws, level, [&](int f, int q) {
+  dev::level_items(FR, ws, level, [&](int f, int, int at) {
     const FrameDev& fr = FR.f[f];
-    // the frame's far items follow its close items in the records
-    const int at = q + (level ? 0 : ws.fcount[f * FC_N + FC_CLOSE_ITEMS]);
     const ItemRec r = ws.items[(size_t)f * ws.items_cap + at];
     dev::run_item_rec(P, fr, f, level, r, wave, [&](const dev::BlockCtx& c) {
       dev::match_block_tiled<ROWS, NX, CPL, PASSES>(P, fr, ws, dbg, c, lane, wl);
@@ -201,9 +199,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES))) vo
     const FrameDev& fr = FR.f[f];
     const int q = m - prefix[slot];
     const int at = q + (slot < F ? 0 : prefix[f + 1] - prefix[f]);
-    const ItemRec r = ws.items[(size_t)f * ws.items_cap + at];
-    if (slot < F) CM::run_item(P, fr, ws, dbg, f, 1, r, wave, lane, wl);
-    else FM::run_item(P, fr, ws, dbg, f, 0, r, wave, lane, wl);
+    const ItemRec* rp = ws.items + (size_t)f * ws.items_cap + at;
+    if (slot < F) {
+      const typename CM::State st = CM::frame_state(ws, fr, lane);
+      const ItemRec r = *rp;
+      CM::run_item(P, fr, ws, dbg, f, 1, r, wave, lane, wl, st);
+    } else {
+      const typename FM::State st = FM::frame_state(ws, fr, lane);
+      const ItemRec r = *rp;
+      FM::run_item(P, fr, ws, dbg, f, 0, r, wave, lane, wl, st);
+    }
   }
 }
 
@@ -215,11 +220,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES))) vo
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int lane = threadIdx.x & 63;
   void* wl = (char*)lds + wave * M::kLds;
-  dev::level_items(FR, ws, level, [&](int f, int q) {
+  dev::level_items(FR, ws, level, [&](int f, int, int at) {
     const FrameDev& fr = FR.f[f];
-    const int at = q + (level ? 0 : ws.fcount[f * FC_N + FC_CLOSE_ITEMS]);
+    const typename M::State st = M::frame_state(ws, fr, lane);
     const ItemRec r = ws.items[(size_t)f * ws.items_cap + at];
-    M::run_item(P, fr, ws, dbg, f, level, r, wave, lane, wl);
+    M::run_item(P, fr, ws, dbg, f, level, r, wave, lane, wl, st);
   });
 }
 
