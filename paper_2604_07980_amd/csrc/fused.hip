@@ -103,14 +103,17 @@ __global__ __launch_bounds__(256) void fused_kernel(MatchParamsDev P, FramesDev 
       const int q = m - mprefix[slot];
       const int at = q + (slot < F ? 0 : mprefix[f + 1] - mprefix[f]);
       const ItemRec* rp = ws.items + (size_t)f * ws.items_cap + at;
+      // per-lane indexing formed afresh per item (as in match_pair2_kernel)
+      int il = lane;
+      asm volatile("" : "+v"(il));
       if (slot < F) {
-        const typename CM::State st = CM::frame_state(ws, fr, lane);
+        const typename CM::State st = CM::frame_state(ws, fr, il);
         const ItemRec rec = *rp;
-        CM::run_item(P, fr, ws, DebugDev{}, f, 1, rec, wave, lane, wl, st);
+        CM::run_item(P, fr, ws, DebugDev{}, f, 1, rec, wave, il, wl, st);
       } else {
-        const typename FM::State st = FM::frame_state(ws, fr, lane);
+        const typename FM::State st = FM::frame_state(ws, fr, il);
         const ItemRec rec = *rp;
-        FM::run_item(P, fr, ws, DebugDev{}, f, 0, rec, wave, lane, wl, st);
+        FM::run_item(P, fr, ws, DebugDev{}, f, 0, rec, wave, il, wl, st);
       }
     }
   }

@@ -200,14 +200,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES))) vo
     const int q = m - prefix[slot];
     const int at = q + (slot < F ? 0 : prefix[f + 1] - prefix[f]);
     const ItemRec* rp = ws.items + (size_t)f * ws.items_cap + at;
+    // the lane index passes through an empty asm statement per item, so that neither
+    // matcher's per-lane indexing is held in registers across the loop (both would be)
+    int il = lane;
+    asm volatile("" : "+v"(il));
     if (slot < F) {
-      const typename CM::State st = CM::frame_state(ws, fr, lane);
+      const typename CM::State st = CM::frame_state(ws, fr, il);
       const ItemRec r = *rp;
-      CM::run_item(P, fr, ws, dbg, f, 1, r, wave, lane, wl, st);
+      CM::run_item(P, fr, ws, dbg, f, 1, r, wave, il, wl, st);
     } else {
-      const typename FM::State st = FM::frame_state(ws, fr, lane);
+      const typename FM::State st = FM::frame_state(ws, fr, il);
       const ItemRec r = *rp;
-      FM::run_item(P, fr, ws, dbg, f, 0, r, wave, lane, wl, st);
+      FM::run_item(P, fr, ws, dbg, f, 0, r, wave, il, wl, st);
     }
   }
 }
