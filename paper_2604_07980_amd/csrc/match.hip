@@ -557,8 +557,8 @@ hipError_t launch_match(const MatchParamsDev& P, const FramesDev& FR, const ocsr
              launch_pair(P, FR, ws, dbg, n_match_wgs, stream, nullptr, false)) {
     // one launch for both levels: in a one-frame call the far level alone cannot fill
     // the GPU, and its blocks fill the close level's tail (whole 1080p frame: 31 against
-    // 38 us per frame); each level of a batch fills the GPU by itself, and there the
-    // larger paired kernel is slower (16 frames: 159 us against 10 + 131 us)
+    // 38 us per frame); each level of a batch fills the GPU by itself, and there the two
+    // forms are about even (16 frames: 117.5 against 10.3 + 109.2 us)
     e = launch_pair(P, FR, ws, dbg, n_match_wgs, stream, timer, true) ? hipGetLastError() : hipErrorNotSupported;
     if (e != hipSuccess) return e;
   } else {
