@@ -343,6 +343,92 @@ __device__ __forceinline__ void frame_census_tile(const MatchParamsDev& MP, cons
   make_census_tile<SX, SY>(j, sx, sy, sentinel, P);
 }
 
+// Sets, in bits, the tile bits of the frame's boxes i = t0, t0 + nt, ... (thread t0 of nt
+// threads; atomic ORs, so threads may share a map).
+__device__ __forceinline__ void mark_frame_tiles(const MatchParamsDev& MP, const FrameDev& fr,
+                                                 const ocsr_box* __restrict__ boxes,
+                                                 uint32_t* bits, int t0, int nt) {
+  for (int i = t0; i < fr.n_boxes; i += nt) {
+    const ocsr_box b = boxes[fr.box_off + i];
+    const int cx0 = max(b.x0, 0), cy0 = max(b.y0, 0);
+    const int cx1 = min(b.x1, fr.W), cy1 = min(b.y1, fr.H);
+    if (!(b.flags & OCSR_BOX_RANGE) || !(cx0 < cx1 && cy0 < cy1)) continue;
+    const int level = max(cx1 - cx0, cy1 - cy0) < MP.tau_s ? 0 : 1;
+    const LevelDev& lv = fr.lv[level];
+    const int s = lv.scale;
+    const int x0 = max(cdiv_nonneg(cx0, s), lv.sx), x1 = min(cdiv_nonneg(cx1, s), lv.W - lv.sx);
+    const int y0 = max(cdiv_nonneg(cy0, s), lv.sy), y1 = min(cdiv_nonneg(cy1, s), lv.H - lv.sy);
+    if (!(x0 < x1 && y0 < y1)) continue;
+    const int dlo = MP.path[level].dlo, dhi = dlo + MP.path[level].nd - 1;
+    const int eylo = MP.path[level].dylo, eyhi = eylo + MP.path[level].ndy - 1;
+    const int tiles_x = level ? fr.tiles1_x : fr.tiles0_x;
+    const int tiles = level ? fr.tiles1 : fr.tiles0;
+    const int tiles_y = tiles / tiles_x;
+    const int lbase = level ? 0 : 2 * fr.tiles1;
+    for (int view = 0; view < 2; ++view) {
+      const int a = max(x0 - (view ? dhi : dhi - dlo), 0);
+      const int e = min(x1 + (view ? -dlo : dhi - dlo), tiles_x * kCensusTileX);
+      if (a >= e) continue;
+      const int ta = a / kCensusTileX, tb = (e - 1) / kCensusTileX;
+      const int ya = max(y0 + (view ? eylo : eylo - eyhi), 0);
+      const int yb = min(y1 + (view ? eyhi : eyhi - eylo), tiles_y * kCensusTileY);
+      if (ya >= yb) continue;
+      for (int ty = ya / kCensusTileY; ty <= (yb - 1) / kCensusTileY; ++ty) {
+        const int first = lbase + view * tiles + ty * tiles_x + ta;
+        const int last = first + (tb - ta);
+        for (int wd = first >> 5; wd <= (last >> 5); ++wd) {
+          const int lo = max(first - 32 * wd, 0), hi = min(last - 32 * wd, 31);
+          const uint32_t upto = hi == 31 ? 0xFFFFFFFFu : ((1u << (hi + 1)) - 1u);
+          atomicOr(&bits[wd], upto & ~((1u << lo) - 1u));
+        }
+      }
+    }
+  }
+}
+
+// Word i of an empty tile map of n_tiles tiles, or of a full one with MP.full_census.
+__device__ __forceinline__ uint32_t tile_map_init(const MatchParamsDev& MP, int n_tiles, int i) {
+  const int rem = n_tiles - 32 * i;
+  return !MP.full_census ? 0u : rem >= 32 ? 0xFFFFFFFFu : ((1u << rem) - 1u);
+}
+
+// Writes the tiles set in the OR of n_maps maps (map m at bits + m * stride words) to
+// fr.tile_list in increasing tile number and their number to the frame's FC_TILES
+// counter. All 256 threads of the workgroup, after the maps are complete; sc: 8 ints.
+__device__ __forceinline__ void compact_frame_tiles(const FrameDev& fr, int f, const MatchWs& ws,
+                                                    const uint32_t* bits, int n_maps, int stride,
+                                                    int* sc) {
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int n_tiles = 2 * (fr.tiles0 + fr.tiles1);
+  const int n_words = (n_tiles + 31) >> 5;
+  auto word = [&](int i) {
+    uint32_t m = 0;
+    for (int k = 0; k < n_maps; ++k) m |= bits[k * stride + i];
+    return m;
+  };
+  // thread t owns words [t wpt, (t + 1) wpt); ranks run in word order
+  const int wpt = (n_words + 255) >> 8;
+  const int w0 = tid * wpt;
+  int cnt = 0;
+  for (int k = 0; k < wpt; ++k)
+    if (w0 + k < n_words) cnt += __popc(word(w0 + k));
+  const int incl = wave_incl_scan(cnt, lane);
+  if (lane == 63) sc[wave] = incl;
+  __syncthreads();
+  int r = incl - cnt;
+  for (int v = 0; v < wave; ++v) r += sc[v];
+  for (int k = 0; k < wpt; ++k) {
+    uint32_t m = w0 + k < n_words ? word(w0 + k) : 0u;
+    while (m) {
+      const int bit = __ffs(m) - 1;
+      m &= m - 1;
+      fr.tile_list[r++] = 32 * (w0 + k) + bit;
+    }
+  }
+  if (tid == 255) ws.fcount[f * FC_N + FC_TILES] = r;
+}
+
 // The plan step's list of the census tiles of frame f: every tile some ranged box's
 // search reads (the ranges of census_tile_needed), or every tile with MP.full_census,
 // in increasing frame-local tile number (the order frame_census_tile decodes: level 1,
@@ -352,74 +438,16 @@ __device__ __forceinline__ void frame_census_tile(const MatchParamsDev& MP, cons
 __device__ __forceinline__ void list_frame_tiles(const MatchParamsDev& MP, const FrameDev& fr, int f,
                                                  const ocsr_box* __restrict__ boxes,
                                                  const MatchWs& ws, uint32_t* bits, int* sc) {
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int tid = threadIdx.x;
   const int n_tiles = 2 * (fr.tiles0 + fr.tiles1);
   const int n_words = (n_tiles + 31) >> 5;
-  for (int i = tid; i < n_words; i += 256) {
-    const int rem = n_tiles - 32 * i;
-    bits[i] = !MP.full_census ? 0u : rem >= 32 ? 0xFFFFFFFFu : ((1u << rem) - 1u);
-  }
+  for (int i = tid; i < n_words; i += 256) bits[i] = tile_map_init(MP, n_tiles, i);
   __syncthreads();
   if (!MP.full_census) {
-    for (int i = tid; i < fr.n_boxes; i += 256) {
-      const ocsr_box b = boxes[fr.box_off + i];
-      const int cx0 = max(b.x0, 0), cy0 = max(b.y0, 0);
-      const int cx1 = min(b.x1, fr.W), cy1 = min(b.y1, fr.H);
-      if (!(b.flags & OCSR_BOX_RANGE) || !(cx0 < cx1 && cy0 < cy1)) continue;
-      const int level = max(cx1 - cx0, cy1 - cy0) < MP.tau_s ? 0 : 1;
-      const LevelDev& lv = fr.lv[level];
-      const int s = lv.scale;
-      const int x0 = max(cdiv_nonneg(cx0, s), lv.sx), x1 = min(cdiv_nonneg(cx1, s), lv.W - lv.sx);
-      const int y0 = max(cdiv_nonneg(cy0, s), lv.sy), y1 = min(cdiv_nonneg(cy1, s), lv.H - lv.sy);
-      if (!(x0 < x1 && y0 < y1)) continue;
-      const int dlo = MP.path[level].dlo, dhi = dlo + MP.path[level].nd - 1;
-      const int eylo = MP.path[level].dylo, eyhi = eylo + MP.path[level].ndy - 1;
-      const int tiles_x = level ? fr.tiles1_x : fr.tiles0_x;
-      const int tiles = level ? fr.tiles1 : fr.tiles0;
-      const int tiles_y = tiles / tiles_x;
-      const int lbase = level ? 0 : 2 * fr.tiles1;
-      for (int view = 0; view < 2; ++view) {
-        const int a = max(x0 - (view ? dhi : dhi - dlo), 0);
-        const int e = min(x1 + (view ? -dlo : dhi - dlo), tiles_x * kCensusTileX);
-        if (a >= e) continue;
-        const int ta = a / kCensusTileX, tb = (e - 1) / kCensusTileX;
-        const int ya = max(y0 + (view ? eylo : eylo - eyhi), 0);
-        const int yb = min(y1 + (view ? eyhi : eyhi - eylo), tiles_y * kCensusTileY);
-        if (ya >= yb) continue;
-        for (int ty = ya / kCensusTileY; ty <= (yb - 1) / kCensusTileY; ++ty) {
-          const int first = lbase + view * tiles + ty * tiles_x + ta;
-          const int last = first + (tb - ta);
-          for (int wd = first >> 5; wd <= (last >> 5); ++wd) {
-            const int lo = max(first - 32 * wd, 0), hi = min(last - 32 * wd, 31);
-            const uint32_t upto = hi == 31 ? 0xFFFFFFFFu : ((1u << (hi + 1)) - 1u);
-            atomicOr(&bits[wd], upto & ~((1u << lo) - 1u));
-          }
-        }
-      }
-    }
+    mark_frame_tiles(MP, fr, boxes, bits, tid, 256);
     __syncthreads();
   }
-  // compaction: thread t owns words [t wpt, (t + 1) wpt); ranks run in word order
-  const int wpt = (n_words + 255) >> 8;
-  const int w0 = tid * wpt;
-  int cnt = 0;
-  for (int k = 0; k < wpt; ++k)
-    if (w0 + k < n_words) cnt += __popc(bits[w0 + k]);
-  const int incl = wave_incl_scan(cnt, lane);
-  if (lane == 63) sc[wave] = incl;
-  __syncthreads();
-  int r = incl - cnt;
-  for (int v = 0; v < wave; ++v) r += sc[v];
-  for (int k = 0; k < wpt; ++k) {
-    uint32_t m = w0 + k < n_words ? bits[w0 + k] : 0u;
-    while (m) {
-      const int bit = __ffs(m) - 1;
-      m &= m - 1;
-      fr.tile_list[r++] = 32 * (w0 + k) + bit;
-    }
-  }
-  if (tid == 255) ws.fcount[f * FC_N + FC_TILES] = r;
+  compact_frame_tiles(fr, f, ws, bits, 1, 0, sc);
 }
 
 }  // namespace dev

@@ -22,10 +22,15 @@ constexpr int kAggMax = 4096;
 // ---------------------------------------------------------------------------------
 // plan: one wave walks the frame's boxes 64 at a time
 // ---------------------------------------------------------------------------------
-// With items == false the item records are left to write_frame_items.
+// With items == false the item records are left to write_frame_items. With lplan and a
+// frame of at most lcap boxes, the plans also go to lplan[i] and the running item ends of
+// the two levels to lend[i] (far) and lend[n + i] (close), and the two item counts to
+// lend[2 n] (far) and lend[2 n + 1] (close), in LDS, for write_frame_items.
 __device__ __forceinline__ void plan_frame(const MatchParamsDev& P, const FrameDev& fr, int f,
                                            int n_total, const ocsr_box* __restrict__ boxes,
-                                           const MatchWs& ws, int lane, bool items = true) {
+                                           const MatchWs& ws, int lane, bool items = true,
+                                           BoxPlan* lplan = nullptr, int32_t* lend = nullptr,
+                                           int lcap = 0) {
   const int n = fr.n_boxes;
   const int W = fr.W, H = fr.H;
   int carry = 0, carry0 = 0, carry1 = 0, matched_end = 0;
@@ -112,6 +117,11 @@ __device__ __forceinline__ void plan_frame(const MatchParamsDev& P, const FrameD
       ws.clip[g] = cl;
       ws.litem_end[g] = carry0 + incl0;
       ws.litem_end[n_total + g] = carry1 + incl1;
+      if (lplan && n <= lcap) {
+        lplan[i] = pl;
+        lend[i] = carry0 + incl0;
+        lend[n + i] = carry1 + incl1;
+      }
     }
     matched_end = max(matched_end, wave_max(nblk > 0 ? off + nblk : 0));
     carry += __shfl(incl, 63, 64);
@@ -124,6 +134,10 @@ __device__ __forceinline__ void plan_frame(const MatchParamsDev& P, const FrameD
     fc[FC_MATCHED] = matched_end;
     fc[FC_FAR_ITEMS] = carry0;
     fc[FC_CLOSE_ITEMS] = carry1;
+    if (lplan && n <= lcap) {
+      lend[2 * n] = carry0;
+      lend[2 * n + 1] = carry1;
+    }
   }
   if (!items) return;
   // item records: the frame's close items from 0, its far items after them; each lane
@@ -156,13 +170,20 @@ __device__ __forceinline__ void plan_frame(const MatchParamsDev& P, const FrameD
 // item ends and counters (and the threads have synchronised with it): thread tid writes
 // items tid, tid + nthr, ...; the box of an item is found by binary search on the running
 // item ends of its level. With lds (lds_cap words the caller is done with) holding both
-// levels' ends of the frame, they are copied there first and searched in LDS.
+// levels' ends of the frame, they are copied there first and searched in LDS. With
+// lplan (a frame of at most lcap boxes), plan_frame's LDS copies of the plans and ends
+// are used instead.
 __device__ __forceinline__ void write_frame_items(const MatchParamsDev& P, const FrameDev& fr, int f,
                                                   int n_total, const MatchWs& ws, int tid, int nthr,
-                                                  int32_t* lds = nullptr, int lds_cap = 0) {
+                                                  int32_t* lds = nullptr, int lds_cap = 0,
+                                                  const BoxPlan* lplan = nullptr,
+                                                  const int32_t* lend = nullptr, int lcap = 0) {
   const int n = fr.n_boxes;
-  const bool in_lds = lds && 2 * n <= lds_cap;
-  if (in_lds) {
+  const bool from_plan = lplan && n <= lcap;
+  const bool in_lds = !from_plan && lds && 2 * n <= lds_cap;
+  if (from_plan) {
+    lds = (int32_t*)lend;
+  } else if (in_lds) {
     __syncthreads();   // every thread is done with the caller's use of the LDS
     for (int i = tid; i < n; i += nthr) {
       lds[i] = ws.litem_end[fr.box_off + i];
@@ -171,19 +192,21 @@ __device__ __forceinline__ void write_frame_items(const MatchParamsDev& P, const
     __syncthreads();
   }
   const int32_t* fc = ws.fcount + f * FC_N;
-  const int n_close = fc[FC_CLOSE_ITEMS], n_far = fc[FC_FAR_ITEMS];
+  const int n_close = from_plan ? lend[2 * n + 1] : fc[FC_CLOSE_ITEMS];
+  const int n_far = from_plan ? lend[2 * n] : fc[FC_FAR_ITEMS];
   ItemRec* rec = ws.items + (size_t)f * ws.items_cap;
   for (int t = tid; t < n_close + n_far; t += nthr) {
     const int level = t < n_close ? 1 : 0;
     const int q = level ? t : t - n_close;
-    const int32_t* end = in_lds ? lds + level * n : ws.litem_end + (size_t)level * n_total + fr.box_off;
+    const int32_t* end = in_lds || from_plan ? lds + level * n
+                                             : ws.litem_end + (size_t)level * n_total + fr.box_off;
     int lo = 0, hi = n - 1;   // first box whose running end passes q
     while (lo < hi) {
       const int mid = (lo + hi) >> 1;
       if (end[mid] > q) hi = mid;
       else lo = mid + 1;
     }
-    const BoxPlan pl = ws.plan[fr.box_off + lo];
+    const BoxPlan pl = from_plan ? lplan[lo] : ws.plan[fr.box_off + lo];
     ItemRec r;
     r.k = lo;
     r.first = (q - pl.ioff) * P.item_blocks[level];

@@ -35,18 +35,37 @@ __global__ __launch_bounds__(256) void frame_census_kernel(MatchParamsDev P, Fra
                                  &tsc[0]);
 }
 
-// Plan of frame blockIdx.x (wave 0 plans the boxes, then all four waves write the work
-// items) and the list of its census tiles (all four waves).
+// Plan of frame blockIdx.x and the list of its census tiles. Wave 0 plans the boxes while
+// waves 1-3 mark the tiles their searches read, each wave in a tile map of its own (so
+// the marking waits for no workgroup barrier, and the plan and the marking overlap);
+// then all four waves list the tiles of the three maps and write the work items, from
+// the plans wave 0 also left in LDS.
 __global__ __launch_bounds__(256) void plan_tiles_kernel(MatchParamsDev P, FramesDev FR,
                                                          const ocsr_box* boxes, MatchWs ws) {
-  __shared__ uint32_t bits[kFrameTileWords];
+  constexpr int kMaps = kItemWaves - 1;
+  constexpr int kPlanCap = 128;   // frames of at most this many boxes keep their plans in LDS
+  __shared__ uint32_t bits[kMaps * kFrameTileWords];
+  __shared__ BoxPlan lplan[kPlanCap];
+  __shared__ int32_t lend[2 * kPlanCap + 2];
   __shared__ int sc[8];
   const int f = blockIdx.x;
-  if (threadIdx.x < 64)
-    dev::plan_frame(P, FR.f[f], f, FR.n_boxes_total, boxes, ws, threadIdx.x, false);
-  dev::list_frame_tiles(P, FR.f[f], f, boxes, ws, bits, sc);   // synchronises the workgroup
-  dev::write_frame_items(P, FR.f[f], f, FR.n_boxes_total, ws, threadIdx.x, 256, (int32_t*)bits,
-                         kFrameTileWords);
+  const FrameDev& fr = FR.f[f];
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int lane = threadIdx.x & 63;
+  if (wave == 0) {
+    dev::plan_frame(P, fr, f, FR.n_boxes_total, boxes, ws, lane, false, lplan, lend, kPlanCap);
+  } else {
+    uint32_t* map = bits + (wave - 1) * kFrameTileWords;
+    const int n_tiles = 2 * (fr.tiles0 + fr.tiles1);
+    const int n_words = (n_tiles + 31) >> 5;
+    for (int i = lane; i < n_words; i += 64) map[i] = dev::tile_map_init(P, n_tiles, i);
+    dev::wave_sync();
+    if (!P.full_census) dev::mark_frame_tiles(P, fr, boxes, map, (int)threadIdx.x - 64, 192);
+  }
+  __syncthreads();
+  dev::compact_frame_tiles(fr, f, ws, bits, kMaps, kFrameTileWords, sc);
+  dev::write_frame_items(P, fr, f, FR.n_boxes_total, ws, threadIdx.x, 256, (int32_t*)bits,
+                         kMaps * kFrameTileWords, lplan, lend, kPlanCap);
 }
 
 // Census of the listed tiles of every frame by persistent workgroups: the frames' lists,
