@@ -51,10 +51,11 @@ typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 // see such values, and their words are stored as 0 regardless.
 __device__ __forceinline__ int clamp_to(int v, int n) { return v < 0 ? 0 : (v < n ? v : n - 1); }
 
-// Stages tile j in P through registers. Wave w loads source rows w*RB .. w*RB + RB of
-// the tile (one more than the pair rows it writes): the row address is wave-uniform,
-// so each load is one scalar base plus the lane's unsigned column offset. All loads are
-// issued before the first is waited for. Called by all 256 threads of the workgroup.
+// Stages tile j in P through registers. For the first 64 columns wave w loads source rows
+// w*RB .. w*RB + RB of the tile (one more than the pair rows it writes): the row address
+// is wave-uniform, so each load is one scalar base plus the lane's unsigned column
+// offset. The 2 SX halo columns to their right take one pair word per thread. All loads
+// are issued before the first is waited for. Called by all 256 threads of the workgroup.
 template <int SX, int SY>
 __device__ __forceinline__ void census_stage(const CensusJob& j, uint32_t* P) {
   using T = CensusTile<SX, SY>;
@@ -64,34 +65,47 @@ __device__ __forceinline__ void census_stage(const CensusJob& j, uint32_t* P) {
   const int X0 = uniform(j.X0), Y0 = uniform(j.Y0);
   const int Ws = uniform(j.Ws), Hs = uniform(j.Hs);
   constexpr int RB = (PR + 1 + 3) / 4;
-  constexpr int NPASS = (LW + 63) / 64;
+  // the halo columns right of the first 64: one pair word per thread (NH per thread)
+  constexpr int NX = LW - 64, NH = (NX * PR + 255) / 256;
+  static_assert(NX > 0 && NX <= 64, "one pass of 64 columns, then the halo columns");
   {
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
     // each row through a buffer resource over that row (scalar setup), the lane's
     // clamped column a byte offset fixed for the tile: no per-load address arithmetic
-    uint32_t coff[NPASS];
-#pragma unroll
-    for (int cp = 0; cp < NPASS; ++cp) coff[cp] = (uint32_t)(s * clamp_to(X0 - SX + lane + 64 * cp, Ws));
+    const uint32_t coff = (uint32_t)(s * clamp_to(X0 - SX + lane, Ws));
     const int wbytes = uniform(j.W);
-    uint32_t px[NPASS][RB + 1];
+    uint32_t px[RB + 1];
 #pragma unroll
     for (int k = 0; k <= RB; ++k) {
       const int Yc = clamp_to(Y0 - SY + wave * RB + k, Hs);
       const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
           (void*)(img + (size_t)(s * Yc) * pitch), (short)0, wbytes, 0x00020000);
+      px[k] = __builtin_amdgcn_raw_buffer_load_b8(rs, coff, 0, 0);
+    }
+    // halo word t = pr NX + (pc - 64): its two source bytes through per-thread addresses
+    // (threads past the halo load the last row's word again and store it to the spare
+    // words)
+    uint32_t hlo[NH], hhi[NH];
 #pragma unroll
-      for (int cp = 0; cp < NPASS; ++cp) px[cp][k] = __builtin_amdgcn_raw_buffer_load_b8(rs, coff[cp], 0, 0);
+    for (int i = 0; i < NH; ++i) {
+      const int t = (int)threadIdx.x + 256 * i;
+      const int pr = min(t / NX, PR - 1);
+      const int pc = 64 + t % NX;
+      const size_t col = (size_t)(s * clamp_to(X0 - SX + pc, Ws));
+      hlo[i] = img[(size_t)(s * clamp_to(Y0 - SY + pr, Hs)) * pitch + col];
+      hhi[i] = img[(size_t)(s * clamp_to(Y0 - SY + pr + 1, Hs)) * pitch + col];
     }
 #pragma unroll
-    for (int cp = 0; cp < NPASS; ++cp) {
-      const int pc = lane + 64 * cp;
+    for (int k = 0; k < RB; ++k) {
+      const int pr = wave * RB + k;
+      // rows past the tile write the spare words after P (no lane mask)
+      P[pr < PR ? pr * LW + lane : PR * LW + lane] = px[k] | (px[k + 1] << 16);
+    }
 #pragma unroll
-      for (int k = 0; k < RB; ++k) {
-        const int pr = wave * RB + k;
-        // positions past the tile write the spare words after P (no lane mask)
-        P[pr < PR && pc < LW ? pr * LW + pc : PR * LW + lane] = px[cp][k] | (px[cp][k + 1] << 16);
-      }
+    for (int i = 0; i < NH; ++i) {
+      const int t = (int)threadIdx.x + 256 * i;
+      P[t < NX * PR ? (t / NX) * LW + 64 + t % NX : PR * LW + lane] = hlo[i] | (hhi[i] << 16);
     }
   }
 }
