@@ -98,9 +98,8 @@ __device__ __forceinline__ void census_stage(const CensusJob& j, uint32_t* P) {
     }
 #pragma unroll
     for (int k = 0; k < RB; ++k) {
-      const int pr = wave * RB + k;
-      // rows past the tile write the spare words after P (no lane mask)
-      P[pr < PR ? pr * LW + lane : PR * LW + lane] = px[k] | (px[k + 1] << 16);
+      const int pr = wave * RB + k;   // wave-uniform: the test is a scalar branch
+      if (pr < PR) P[pr * LW + lane] = px[k] | (px[k + 1] << 16);
     }
 #pragma unroll
     for (int i = 0; i < NH; ++i) {
@@ -147,6 +146,8 @@ __device__ __forceinline__ void census_compute(const CensusJob& j, int sentinel,
     for (int rr = 0; rr < WR; ++rr) v[rr] = Pl[rr * LW + i];
 #pragma unroll
     for (int jj = 0; jj < 2 * SY + 1; ++jj) {
+      // the centre against itself: its bit is 0, nothing to file
+      if (i == SX && jj == SY) continue;
       const int pos = N - 1 - (i * (2 * SY + 1) + jj);   // Alg. 1 order, MSB first
       const int q = pos >> 3;
       uint32_t d[NP];
