@@ -656,8 +656,9 @@ def only_section(ocsr, synth, args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the path is per frame "
-              "and shards by frames across GPUs, which this build does not run", file=sys.stderr)
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}): the path is per frame "
+              "and would shard by frames across GPUs, but no multi-GPU run is implemented",
+              file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2604_07980_amd import ocsr, synth

@@ -226,7 +226,7 @@ hipError_t timed_launch(const LaunchTimer* timer, const char* name, void (*kerne
 // block rows per wave (4: blocks up to 4 x 4, 8: up to 8 x 8), `cpl` consecutive
 // candidates per lane and `passes` passes over the candidates, which covers
 // (64 / rows) * cpl * passes level candidates. Other shapes (GRID mode, wider blocks,
-// wider ranges) have no kernel in this build.
+// wider ranges) have no register-blocked kernel; the generic kernel takes those it covers.
 struct MatchVariant {
   int tiled;           // 1: a register-blocked TILED kernel exists
   int rows, cpl, passes;

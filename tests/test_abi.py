@@ -111,3 +111,13 @@ def test_vertical_limits_stated_in_the_header():
         return max(n for n in range(1, 200) if nd * n <= ocsr.MAX_DY_CANDIDATES and 4 * lds(8, nd, n) <= 65536)
     assert most(96) == 21 and most(128) == 12
     assert strip(8, 160) <= 3 * 64 < strip(8, 161)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: --gpus N > 1 exits with a message before touching a GPU."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU only" in r.stderr and r.stdout == ""
