@@ -901,7 +901,11 @@ __device__ __forceinline__ void match_block_half(const MatchParamsDev& P, const 
   for (int cc = 0; cc < CPL; ++cc) {
     const int kc = g * CPL + cc;           // candidate d' = dlo + kc (slots past nd unread)
     bkey = min(bkey, kc < nd ? (acc[cc] << 16) | (uint32_t)kc : 0xFFFFFFFFu);
-    costb[kc] = (uint16_t)acc[cc];
+  }
+  // the backward costs are read only for the debug output
+  if (dbg.cost_bwd) {
+#pragma unroll
+    for (int cc = 0; cc < CPL; ++cc) costb[g * CPL + cc] = (uint16_t)acc[cc];
   }
   bkey = wave_min_dpp(bkey);
   const int d_b = dlo + (int)(bkey & 0xFFFFu);
