@@ -312,7 +312,7 @@ def batch_workload(ocsr, scenes, args):
         def run_batch():
             batch()
             return out_b
-        table = autotune.tune(run_batch, p, reps=15, warmup=3)
+        table = autotune.tune(run_batch, p, reps=20, warmup=3)
         if args.tune_table:
             autotune.save(table, args.tune_table)
     ref = None

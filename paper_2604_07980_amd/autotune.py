@@ -56,18 +56,21 @@ def _arch() -> str:
     return torch.cuda.get_device_properties(torch.cuda.current_device()).gcnArchName.split(":")[0]
 
 
-def _time_ms(run, reps: int, warmup: int) -> float:
+def _time_ms(run, reps: int, warmup: int, trials: int = 3) -> float:
+    """Milliseconds per call of `run` submitted back to back (the throughput a caller that
+    keeps the stream busy sees): the median over `trials` runs of `reps` calls."""
     import torch
     for _ in range(warmup):
         run()
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     times = []
-    for _ in range(reps):
+    for _ in range(trials):
         a.record()
-        run()
+        for _ in range(reps):
+            run()
         b.record()
         b.synchronize()
-        times.append(a.elapsed_time(b))
+        times.append(a.elapsed_time(b) / reps)
     times.sort()
     return times[len(times) // 2]
 
