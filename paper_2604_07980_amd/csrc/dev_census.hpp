@@ -55,58 +55,78 @@ __device__ __forceinline__ int clamp_to(int v, int n) { return v < 0 ? 0 : (v < 
 // w*RB .. w*RB + RB of the tile (one more than the pair rows it writes): the row address
 // is wave-uniform, so each load is one scalar base plus the lane's unsigned column
 // offset. The 2 SX halo columns to their right take one pair word per thread. All loads
-// are issued before the first is waited for. Called by all 256 threads of the workgroup.
+// are issued before the first is waited for. census_load issues them into registers and
+// census_put writes those to P, so that a caller can keep one tile's loads in flight
+// while it works on another; census_stage does both. Called by all 256 threads of the
+// workgroup.
 template <int SX, int SY>
-__device__ __forceinline__ void census_stage(const CensusJob& j, uint32_t* P) {
+struct CensusRegs {
   using T = CensusTile<SX, SY>;
-  constexpr int LW = T::LW, PR = T::PR;
+  static constexpr int RB = (T::PR + 1 + 3) / 4;
+  static constexpr int NX = T::LW - 64, NH = (NX * T::PR + 255) / 256;
+  static_assert(NX > 0 && NX <= 64, "one pass of 64 columns, then the halo columns");
+  uint32_t px[RB + 1];
+  uint32_t hlo[NH], hhi[NH];
+};
+
+template <int SX, int SY>
+__device__ __forceinline__ void census_load(const CensusJob& j, CensusRegs<SX, SY>& g) {
+  using G = CensusRegs<SX, SY>;
+  constexpr int PR = G::T::PR, RB = G::RB, NX = G::NX, NH = G::NH;
   const uint8_t* img = uniform(j.img);
   const int pitch = uniform(j.pitch), s = uniform(j.s);
   const int X0 = uniform(j.X0), Y0 = uniform(j.Y0);
   const int Ws = uniform(j.Ws), Hs = uniform(j.Hs);
-  constexpr int RB = (PR + 1 + 3) / 4;
-  // the halo columns right of the first 64: one pair word per thread (NH per thread)
-  constexpr int NX = LW - 64, NH = (NX * PR + 255) / 256;
-  static_assert(NX > 0 && NX <= 64, "one pass of 64 columns, then the halo columns");
-  {
-    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int lane = threadIdx.x & 63;
-    // each row through a buffer resource over that row (scalar setup), the lane's
-    // clamped column a byte offset fixed for the tile: no per-load address arithmetic
-    const uint32_t coff = (uint32_t)(s * clamp_to(X0 - SX + lane, Ws));
-    const int wbytes = uniform(j.W);
-    uint32_t px[RB + 1];
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int lane = threadIdx.x & 63;
+  // each row through a buffer resource over that row (scalar setup), the lane's clamped
+  // column a byte offset fixed for the tile: no per-load address arithmetic
+  const uint32_t coff = (uint32_t)(s * clamp_to(X0 - SX + lane, Ws));
+  const int wbytes = uniform(j.W);
 #pragma unroll
-    for (int k = 0; k <= RB; ++k) {
-      const int Yc = clamp_to(Y0 - SY + wave * RB + k, Hs);
-      const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-          (void*)(img + (size_t)(s * Yc) * pitch), (short)0, wbytes, 0x00020000);
-      px[k] = __builtin_amdgcn_raw_buffer_load_b8(rs, coff, 0, 0);
-    }
-    // halo word t = pr NX + (pc - 64): its two source bytes through per-thread addresses
-    // (threads past the halo load the last row's word again and store it to the spare
-    // words)
-    uint32_t hlo[NH], hhi[NH];
-#pragma unroll
-    for (int i = 0; i < NH; ++i) {
-      const int t = (int)threadIdx.x + 256 * i;
-      const int pr = min(t / NX, PR - 1);
-      const int pc = 64 + t % NX;
-      const size_t col = (size_t)(s * clamp_to(X0 - SX + pc, Ws));
-      hlo[i] = img[(size_t)(s * clamp_to(Y0 - SY + pr, Hs)) * pitch + col];
-      hhi[i] = img[(size_t)(s * clamp_to(Y0 - SY + pr + 1, Hs)) * pitch + col];
-    }
-#pragma unroll
-    for (int k = 0; k < RB; ++k) {
-      const int pr = wave * RB + k;   // wave-uniform: the test is a scalar branch
-      if (pr < PR) P[pr * LW + lane] = px[k] | (px[k + 1] << 16);
-    }
-#pragma unroll
-    for (int i = 0; i < NH; ++i) {
-      const int t = (int)threadIdx.x + 256 * i;
-      P[t < NX * PR ? (t / NX) * LW + 64 + t % NX : PR * LW + lane] = hlo[i] | (hhi[i] << 16);
-    }
+  for (int k = 0; k <= RB; ++k) {
+    const int Yc = clamp_to(Y0 - SY + wave * RB + k, Hs);
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(img + (size_t)(s * Yc) * pitch), (short)0, wbytes, 0x00020000);
+    g.px[k] = __builtin_amdgcn_raw_buffer_load_b8(rs, coff, 0, 0);
   }
+  // halo word t = pr NX + (pc - 64): its two source bytes through per-thread addresses
+  // (threads past the halo load the last row's word again and store it to the spare
+  // words)
+#pragma unroll
+  for (int i = 0; i < NH; ++i) {
+    const int t = (int)threadIdx.x + 256 * i;
+    const int pr = min(t / NX, PR - 1);
+    const int pc = 64 + t % NX;
+    const size_t col = (size_t)(s * clamp_to(X0 - SX + pc, Ws));
+    g.hlo[i] = img[(size_t)(s * clamp_to(Y0 - SY + pr, Hs)) * pitch + col];
+    g.hhi[i] = img[(size_t)(s * clamp_to(Y0 - SY + pr + 1, Hs)) * pitch + col];
+  }
+}
+
+template <int SX, int SY>
+__device__ __forceinline__ void census_put(const CensusRegs<SX, SY>& g, uint32_t* P) {
+  using G = CensusRegs<SX, SY>;
+  constexpr int LW = G::T::LW, PR = G::T::PR, RB = G::RB, NX = G::NX, NH = G::NH;
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int k = 0; k < RB; ++k) {
+    const int pr = wave * RB + k;   // wave-uniform: the test is a scalar branch
+    if (pr < PR) P[pr * LW + lane] = g.px[k] | (g.px[k + 1] << 16);
+  }
+#pragma unroll
+  for (int i = 0; i < NH; ++i) {
+    const int t = (int)threadIdx.x + 256 * i;
+    P[t < NX * PR ? (t / NX) * LW + 64 + t % NX : PR * LW + lane] = g.hlo[i] | (g.hhi[i] << 16);
+  }
+}
+
+template <int SX, int SY>
+__device__ __forceinline__ void census_stage(const CensusJob& j, uint32_t* P) {
+  CensusRegs<SX, SY> g;
+  census_load<SX, SY>(j, g);
+  census_put<SX, SY>(g, P);
 }
 
 // The census words of tile j from P (staged by census_stage), after a barrier. Called

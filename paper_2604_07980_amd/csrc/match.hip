@@ -92,12 +92,35 @@ __global__ __launch_bounds__(256) void census_list_kernel(MatchParamsDev P, Fram
   w += b >> 3;
   const int lo = dev::share_start(N, w, G), hi = dev::share_start(N, w + 1, G);
   int f = 0;
-  for (int q = lo; q < hi; ++q) {
+  auto job = [&](int q) {
     while (q >= pre[f + 1]) ++f;
     const FrameDev& fr = FR.f[f];
-    const dev::FrameTile ft = dev::frame_tile_local(fr, f, fr.tile_list[q - pre[f]]);
-    dev::make_census_tile<SX, SY>(ft.job, sx, sy, sentinel, lds);
-    __syncthreads();   // the next tile reuses the LDS
+    return dev::frame_tile_local(fr, f, fr.tile_list[q - pre[f]]).job;
+  };
+  if constexpr (SX >= 0) {
+    // software-pipelined: the next tile's source bytes are loaded into registers while
+    // the current tile's comparisons run from LDS
+    if (lo >= hi) return;
+    dev::CensusRegs<SX, SY> g;
+    dev::CensusJob jq = job(lo);
+    dev::census_load<SX, SY>(jq, g);
+    for (int q = lo; q < hi; ++q) {
+      dev::census_put<SX, SY>(g, lds);
+      __syncthreads();
+      dev::CensusJob jn = jq;
+      if (q + 1 < hi) {
+        jn = job(q + 1);
+        dev::census_load<SX, SY>(jn, g);
+      }
+      dev::census_compute<SX, SY>(jq, sentinel, lds);
+      __syncthreads();   // the next tile reuses the LDS
+      jq = jn;
+    }
+  } else {
+    for (int q = lo; q < hi; ++q) {
+      dev::make_census_tile<SX, SY>(job(q), sx, sy, sentinel, lds);
+      __syncthreads();
+    }
   }
 }
 
