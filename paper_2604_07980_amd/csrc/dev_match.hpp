@@ -1619,80 +1619,126 @@ __device__ __forceinline__ int value_bin(float v, float vmin, float scale) {
   return min((int)((v - vmin) * scale), 1023);
 }
 
+// Over the counts in sm.hist (1024 bins), the bins of ranks r1 and r2 (0-based; r2 only
+// when want2) and the ranks within them, into sm.bin and sm.rank. All 256 threads; ends
+// with a barrier.
+__device__ __forceinline__ void find_rank_bins(AggLds& sm, int r1, int r2, bool want2) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // thread t owns bins 4t .. 4t + 3
+  const int c0 = sm.hist[4 * tid], c1 = sm.hist[4 * tid + 1], c2 = sm.hist[4 * tid + 2],
+            c3 = sm.hist[4 * tid + 3];
+  const int sum = c0 + c1 + c2 + c3;
+  const int incl = wave_incl_scan(sum, lane);
+  if (lane == 63) sm.scratch[256 + wave] = incl;
+  __syncthreads();
+  int excl = incl - sum;
+  for (int v = 0; v < wave; ++v) excl += sm.scratch[256 + v];
+  for (int j = 0; j < (want2 ? 2 : 1); ++j) {
+    const int kj = j ? r2 : r1;
+    if (kj >= excl && kj < excl + sum) {   // exactly one thread
+      int b = 4 * tid, kk = kj - excl;
+      if (kk >= c0) { kk -= c0; ++b;
+        if (kk >= c1) { kk -= c1; ++b;
+          if (kk >= c2) { kk -= c2; ++b; } } }
+      sm.bin[j] = b;
+      sm.rank[j] = kk;
+    }
+  }
+  __syncthreads();
+}
+
+// The values whose key (key(v) < 1024, or -1 for none) is kb1 or kb2 gathered into the
+// two lists (list 1 only when the keys differ), and the values of ranks sm.rank[0] and
+// sm.rank[1] within their key picked by one wave into sm.pick. Every key count is at most
+// 64. All 256 threads; ends with a barrier.
+template <typename Key>
+__device__ __forceinline__ void pick_in_lists(AggLds& sm, const float* vals, int n, Key key,
+                                              int kb1, int kb2, bool want2) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int i = tid; i < n; i += 256) {
+    const float v = vals[i];
+    const int b = key(v);
+    if (b == kb1) sm.list[0][atomicAdd(&sm.count[0], 1)] = v;
+    else if (b == kb2) sm.list[1][atomicAdd(&sm.count[1], 1)] = v;
+  }
+  __syncthreads();
+  if (wave == 0) {
+    for (int j = 0; j < (want2 ? 2 : 1); ++j) {
+      const int li = (j == 1 && kb2 != kb1) ? 1 : 0;
+      const int c = sm.count[li];
+      const float* lst = sm.list[li];
+      const float x = lane < c ? lst[lane] : 0.0f;
+      int less = 0, eq = 0;
+      for (int i = 0; i < c; ++i) {
+        const float y = lst[i];
+        less += y < x;
+        eq += y == x;
+      }
+      // lanes holding equal values agree, so any of them may store
+      if (lane < c && sm.rank[j] >= less && sm.rank[j] < less + eq) sm.pick[j] = __float_as_uint(x);
+    }
+  }
+  __syncthreads();
+}
+
 // The k-th and (k + 1)-th smallest (0-based) of the n non-negative floats in vals (LDS
 // or global memory; the second only when want2), as bit patterns. The values are binned
 // by value (value_bin); a scan of the bin counts finds the bins of the two ranks and
 // their ranks within them; one wave then ranks the few values of each such bin against
-// each other. A radix selection over all values handles equal bounds, a bin of more
-// than 64 values or a range too narrow to scale. vmin, vmax: the smallest and largest
-// value.
+// each other. When a bin holds more than 64 values (a box's values crowd a few bins when
+// a few outliers stretch the range), the values of the one or two bins are binned again
+// over each bin's own span, 512 sub-bins each, and the same steps run on the sub-bins.
+// A radix selection over all values handles a sub-bin of more than 64 values or a range
+// too narrow to scale. vmin, vmax: the smallest and largest value. Every step is a
+// monotone map of the value, so the order statistics are exact.
 __device__ __forceinline__ void select_middle(AggLds& sm, const float* vals, int n, int k,
                                               bool want2, float vmin, float vmax, uint32_t* u1,
                                               uint32_t* u2) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x;
   if (vmin == vmax) {
     *u1 = *u2 = __float_as_uint(vmin);
     return;
   }
   const float scale = 1024.0f / (vmax - vmin);
-  bool fallback = !(scale < 1e30f);
-  if (!fallback) {
+  if (scale < 1e30f) {
     for (int i = tid; i < n; i += 256) atomicAdd(&sm.hist[value_bin(vals[i], vmin, scale)], 1);
     if (tid == 0) { sm.count[0] = 0; sm.count[1] = 0; }
     __syncthreads();
-    // thread t owns bins 4t .. 4t + 3
-    const int c0 = sm.hist[4 * tid], c1 = sm.hist[4 * tid + 1], c2 = sm.hist[4 * tid + 2],
-              c3 = sm.hist[4 * tid + 3];
-    const int sum = c0 + c1 + c2 + c3;
-    const int incl = wave_incl_scan(sum, lane);
-    if (lane == 63) sm.scratch[256 + wave] = incl;
-    __syncthreads();
-    int excl = incl - sum;
-    for (int v = 0; v < wave; ++v) excl += sm.scratch[256 + v];
-    for (int j = 0; j < (want2 ? 2 : 1); ++j) {
-      const int kj = k + j;
-      if (kj >= excl && kj < excl + sum) {   // exactly one thread
-        int b = 4 * tid, kk = kj - excl;
-        if (kk >= c0) { kk -= c0; ++b;
-          if (kk >= c1) { kk -= c1; ++b;
-            if (kk >= c2) { kk -= c2; ++b; } } }
-        sm.bin[j] = b;
-        sm.rank[j] = kk;
-      }
-    }
-    __syncthreads();
+    find_rank_bins(sm, k, k + 1, want2);
     const int b1 = sm.bin[0], b2 = want2 ? sm.bin[1] : b1;
-    fallback = sm.hist[b1] > 64 || sm.hist[b2] > 64;
-    if (!fallback) {
-      // the values of bins b1 and b2 (list 1 only when the bins differ)
-      for (int i = tid; i < n; i += 256) {
-        const float v = vals[i];
-        const int b = value_bin(v, vmin, scale);
-        if (b == b1) sm.list[0][atomicAdd(&sm.count[0], 1)] = v;
-        else if (b == b2) sm.list[1][atomicAdd(&sm.count[1], 1)] = v;
-      }
-      __syncthreads();
-      if (wave == 0) {
-        for (int j = 0; j < (want2 ? 2 : 1); ++j) {
-          const int li = (j == 1 && b2 != b1) ? 1 : 0;
-          const int c = sm.count[li];
-          const float* lst = sm.list[li];
-          const float x = lane < c ? lst[lane] : 0.0f;
-          int less = 0, eq = 0;
-          for (int i = 0; i < c; ++i) {
-            const float y = lst[i];
-            less += y < x;
-            eq += y == x;
-          }
-          // lanes holding equal values agree, so any of them may store
-          if (lane < c && sm.rank[j] >= less && sm.rank[j] < less + eq) sm.pick[j] = __float_as_uint(x);
-        }
-      }
-      __syncthreads();
+    const int n1 = sm.hist[b1], n2 = sm.hist[b2];
+    if (n1 <= 64 && n2 <= 64) {
+      pick_in_lists(sm, vals, n, [&](float v) { return value_bin(v, vmin, scale); }, b1, b2, want2);
       *u1 = sm.pick[0];
       *u2 = want2 ? sm.pick[1] : sm.pick[0];
       return;
     }
+    // second level: bin b1's values into sub-bins 0..511 and, when the second rank lies
+    // in a later bin b2, bin b2's into 512..1023; ranks counted over the two bins together
+    const int r1 = sm.rank[0], r2 = want2 ? (b2 == b1 ? sm.rank[1] : n1 + sm.rank[1]) : r1;
+    auto sub = [&](float v) {
+      const int b = value_bin(v, vmin, scale);
+      if (b != b1 && b != b2) return -1;
+      const int q = min(max((int)(((v - vmin) * scale - (float)b) * 512.0f), 0), 511);
+      return b == b1 ? q : 512 + q;
+    };
+    __syncthreads();   // every thread has read the first level's counts
+    for (int i = tid; i < 1024; i += 256) sm.hist[i] = 0;
+    __syncthreads();
+    for (int i = tid; i < n; i += 256) {
+      const int q = sub(vals[i]);
+      if (q >= 0) atomicAdd(&sm.hist[q], 1);
+    }
+    __syncthreads();
+    find_rank_bins(sm, r1, r2, want2);
+    const int s1 = sm.bin[0], s2 = want2 ? sm.bin[1] : s1;
+    if (sm.hist[s1] <= 64 && sm.hist[s2] <= 64) {
+      pick_in_lists(sm, vals, n, sub, s1, s2, want2);
+      *u1 = sm.pick[0];
+      *u2 = want2 ? sm.pick[1] : sm.pick[0];
+      return;
+    }
+    __syncthreads();   // every thread has read the second level's counts
   }
   *u1 = radix_select(vals, n, k, sm.scratch);
   *u2 = want2 ? radix_select(vals, n, k + 1, sm.scratch) : *u1;
@@ -1717,156 +1763,162 @@ __device__ __forceinline__ void aggregate_box(const MatchParamsDev& P, const Mat
   // value moves to an index no larger than its own, and every chunk is loaded before
   // any of it is stored)
   const bool in_lds = pl.nblk <= kAggMax;
-  float* vals = in_lds ? sm.vals : ws.blk_val + base;
-  if (tid == 0) {
-    sm.n_valid = 0;
-    sm.n_eligible = 0;
-    sm.vmin = 0x7FFFFFFFu;
-    sm.vmax = 0;
-  }
-  for (int i = tid; i < 1024; i += 256) sm.hist[i] = 0;
-  __syncthreads();
-  uint32_t vlo = 0x7FFFFFFFu, vhi = 0;   // bit patterns of non-negative floats
-  // gather the valid values: one LDS atomic per wave, positions from the ballot. Flags
-  // and values of up to kGather blocks per thread are loaded before any is used.
-  constexpr int kGather = 4;
-  const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-  for (int b0 = 0; b0 < pl.nblk; b0 += 256 * kGather) {
-    uint32_t fl[kGather];
-    float v[kGather];
-#pragma unroll
-    for (int u = 0; u < kGather; ++u) {
-      const int i = b0 + 256 * u + tid;
-      const int at = base + (i < pl.nblk ? i : 0);
-      fl[u] = ws.blk_flag[at];
-      v[u] = ws.blk_val[at];
-      fl[u] = i < pl.nblk ? fl[u] : 0u;
-    }
-    if (!in_lds) __syncthreads();   // the chunk is loaded before it is overwritten
-#pragma unroll
-    for (int u = 0; u < kGather; ++u) {
-      const uint64_t mv = __ballot((fl[u] & 2) != 0);
-      const uint64_t me = __ballot((fl[u] & 1) != 0);
-      int wbase = 0;
-      if (lane == 0 && (mv | me)) {
-        wbase = atomicAdd(&sm.n_valid, (int)__popcll(mv));
-        atomicAdd(&sm.n_eligible, (int)__popcll(me));
-      }
-      wbase = __shfl(wbase, 0, 64);
-      if (fl[u] & 2) {
-        vals[wbase + __popcll(mv & below)] = v[u];
-        vlo = min(vlo, __float_as_uint(v[u]));
-        vhi = max(vhi, __float_as_uint(v[u]));
-      }
-    }
-    if (!in_lds) __syncthreads();
-  }
-  vlo = wave_min_u32(vlo);
-  vhi = (uint32_t)wave_max((int)vhi);
-  if (lane == 0) {
-    atomicMin(&sm.vmin, vlo);
-    atomicMax(&sm.vmax, vhi);
-  }
-  if (!in_lds) __threadfence_block();   // compacted values visible to the workgroup
-  __syncthreads();
-  const int nv = sm.n_valid, ne = sm.n_eligible;
-  r.n_blocks = pl.nblk;
-  r.n_eligible = ne;
-  r.n_valid = nv;
-  if (ne == 0 || nv == 0) {
+  // the rest runs with vals in LDS or in global memory, each instance with its pointer's
+  // memory space known to the compiler (LDS reads rather than generic ones, whose
+  // latency is that of a memory access)
+  auto rest = [&](float* vals) {
     if (tid == 0) {
-      r.reason = ne == 0 ? OCSR_REASON_NO_ELIGIBLE_BLOCKS : OCSR_REASON_NO_VALID_BLOCKS;
+      sm.n_valid = 0;
+      sm.n_eligible = 0;
+      sm.vmin = 0x7FFFFFFFu;
+      sm.vmax = 0;
+    }
+    for (int i = tid; i < 1024; i += 256) sm.hist[i] = 0;
+    __syncthreads();
+    uint32_t vlo = 0x7FFFFFFFu, vhi = 0;   // bit patterns of non-negative floats
+    // gather the valid values: one LDS atomic per wave, positions from the ballot. Flags
+    // and values of up to kGather blocks per thread are loaded before any is used.
+    constexpr int kGather = 4;
+    const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    for (int b0 = 0; b0 < pl.nblk; b0 += 256 * kGather) {
+      uint32_t fl[kGather];
+      float v[kGather];
+  #pragma unroll
+      for (int u = 0; u < kGather; ++u) {
+        const int i = b0 + 256 * u + tid;
+        const int at = base + (i < pl.nblk ? i : 0);
+        fl[u] = ws.blk_flag[at];
+        v[u] = ws.blk_val[at];
+        fl[u] = i < pl.nblk ? fl[u] : 0u;
+      }
+      if (!in_lds) __syncthreads();   // the chunk is loaded before it is overwritten
+  #pragma unroll
+      for (int u = 0; u < kGather; ++u) {
+        const uint64_t mv = __ballot((fl[u] & 2) != 0);
+        const uint64_t me = __ballot((fl[u] & 1) != 0);
+        int wbase = 0;
+        if (lane == 0 && (mv | me)) {
+          wbase = atomicAdd(&sm.n_valid, (int)__popcll(mv));
+          atomicAdd(&sm.n_eligible, (int)__popcll(me));
+        }
+        wbase = __shfl(wbase, 0, 64);
+        if (fl[u] & 2) {
+          vals[wbase + __popcll(mv & below)] = v[u];
+          vlo = min(vlo, __float_as_uint(v[u]));
+          vhi = max(vhi, __float_as_uint(v[u]));
+        }
+      }
+      if (!in_lds) __syncthreads();
+    }
+    vlo = wave_min_u32(vlo);
+    vhi = (uint32_t)wave_max((int)vhi);
+    if (lane == 0) {
+      atomicMin(&sm.vmin, vlo);
+      atomicMax(&sm.vmax, vhi);
+    }
+    if (!in_lds) __threadfence_block();   // compacted values visible to the workgroup
+    __syncthreads();
+    const int nv = sm.n_valid, ne = sm.n_eligible;
+    r.n_blocks = pl.nblk;
+    r.n_eligible = ne;
+    r.n_valid = nv;
+    if (ne == 0 || nv == 0) {
+      if (tid == 0) {
+        r.reason = ne == 0 ? OCSR_REASON_NO_ELIGIBLE_BLOCKS : OCSR_REASON_NO_VALID_BLOCKS;
+        out[kg] = r;
+      }
+      return;
+    }
+    float d_box = 0.0f;
+    bool ok = true;
+    if (pl.level == 0 && pl.nblk == 1) {
+      // Alg. 2: a FAR object matched as one block takes that block's result; CLOSE
+      // objects always go through the robust aggregation
+      d_box = vals[0];
+      r.n_used = 1;
+    } else if (P.agg_mode == OCSR_AGG_TRIMMED_MEDIAN) {
+      // symmetric trim of floor(pct * n / 100) values at each end, then the median: the
+      // one or two middle order statistics, found by selection
+      const int t = P.trim_pct * nv / 100;
+      const int m = nv - 2 * t;
+      r.n_used = m > 0 ? m : 0;
+      if (m <= 0 || m < P.n_min) {
+        ok = false;
+      } else {
+        const int k1 = t + (m - 1) / 2;
+        uint32_t u1, u2;
+        select_middle(sm, vals, nv, k1, (m & 1) == 0, __uint_as_float(sm.vmin),
+                      __uint_as_float(sm.vmax), &u1, &u2);
+        d_box = (m & 1) ? __uint_as_float(u1) : (__uint_as_float(u1) + __uint_as_float(u2)) * 0.5f;
+      }
+    } else {
+      if (in_lds) {
+        // bitonic sort of the valid values, padded with +inf to a power of two
+        int n2 = 1;
+        while (n2 < nv) n2 <<= 1;
+        for (int i = nv + tid; i < n2; i += 256) sm.vals[i] = __builtin_inff();
+        __syncthreads();
+        for (int kk = 2; kk <= n2; kk <<= 1) {
+          for (int j = kk >> 1; j > 0; j >>= 1) {
+            for (int i = tid; i < n2; i += 256) {
+              const int ixj = i ^ j;
+              if (ixj > i) {
+                const float a = sm.vals[i], c = sm.vals[ixj];
+                const bool up = (i & kk) == 0;
+                if ((a > c) == up) { sm.vals[i] = c; sm.vals[ixj] = a; }
+              }
+            }
+            __syncthreads();
+          }
+        }
+      } else {
+        // the values in global memory, ordered by a radix sort through the box's slots of
+        // the sort buffer
+        radix_sort_global(vals, ws.agg_tmp + base, nv, sm.hist, sm.scratch);
+      }
+      // longest run whose consecutive gaps stay below tau_d; the first run wins a tie
+      if (tid < 64) {
+        int best_start = 0, best_len = 1, start = 0;
+        for (int b0 = 0; b0 < nv; b0 += 64) {
+          const int q = b0 + tid;
+          const bool brk = q > 0 && q < nv && !(vals[q] - vals[q - 1] < P.tau_d);
+          uint64_t m = __ballot(brk);
+          while (m) {
+            const int pos = b0 + __ffsll((unsigned long long)m) - 1;
+            m &= m - 1;
+            const int len = pos - start;
+            if (len > best_len) { best_len = len; best_start = start; }
+            start = pos;
+          }
+        }
+        const int len = nv - start;
+        if (len > best_len) { best_len = len; best_start = start; }
+        if (tid == 0) { sm.seg_start = best_start; sm.seg_len = best_len; }
+      }
+      __syncthreads();
+      const int seg_start = sm.seg_start, seg_len = sm.seg_len;
+      r.n_used = seg_len;
+      if (seg_len < P.n_min) ok = false;
+      else d_box = median_sorted(vals + seg_start, seg_len);
+    }
+    if (tid == 0) {
+      if (!ok) {
+        r.reason = OCSR_REASON_TOO_FEW_CONSISTENT;
+      } else {
+        r.disparity = d_box;
+        if (!(d_box > P.d_eps)) {
+          r.reason = OCSR_REASON_NONPOSITIVE_DISPARITY;
+        } else {
+          r.depth = P.fb / d_box;   // Eq. 1, IEEE fp32 division
+          r.valid = 1;
+          r.reason = OCSR_REASON_OK;
+        }
+      }
       out[kg] = r;
     }
-    return;
-  }
-  float d_box = 0.0f;
-  bool ok = true;
-  if (pl.level == 0 && pl.nblk == 1) {
-    // Alg. 2: a FAR object matched as one block takes that block's result; CLOSE
-    // objects always go through the robust aggregation
-    d_box = vals[0];
-    r.n_used = 1;
-  } else if (P.agg_mode == OCSR_AGG_TRIMMED_MEDIAN) {
-    // symmetric trim of floor(pct * n / 100) values at each end, then the median: the
-    // one or two middle order statistics, found by selection
-    const int t = P.trim_pct * nv / 100;
-    const int m = nv - 2 * t;
-    r.n_used = m > 0 ? m : 0;
-    if (m <= 0 || m < P.n_min) {
-      ok = false;
-    } else {
-      const int k1 = t + (m - 1) / 2;
-      uint32_t u1, u2;
-      select_middle(sm, vals, nv, k1, (m & 1) == 0, __uint_as_float(sm.vmin),
-                    __uint_as_float(sm.vmax), &u1, &u2);
-      d_box = (m & 1) ? __uint_as_float(u1) : (__uint_as_float(u1) + __uint_as_float(u2)) * 0.5f;
-    }
-  } else {
-    if (in_lds) {
-      // bitonic sort of the valid values, padded with +inf to a power of two
-      int n2 = 1;
-      while (n2 < nv) n2 <<= 1;
-      for (int i = nv + tid; i < n2; i += 256) sm.vals[i] = __builtin_inff();
-      __syncthreads();
-      for (int kk = 2; kk <= n2; kk <<= 1) {
-        for (int j = kk >> 1; j > 0; j >>= 1) {
-          for (int i = tid; i < n2; i += 256) {
-            const int ixj = i ^ j;
-            if (ixj > i) {
-              const float a = sm.vals[i], c = sm.vals[ixj];
-              const bool up = (i & kk) == 0;
-              if ((a > c) == up) { sm.vals[i] = c; sm.vals[ixj] = a; }
-            }
-          }
-          __syncthreads();
-        }
-      }
-    } else {
-      // the values in global memory, ordered by a radix sort through the box's slots of
-      // the sort buffer
-      radix_sort_global(vals, ws.agg_tmp + base, nv, sm.hist, sm.scratch);
-    }
-    // longest run whose consecutive gaps stay below tau_d; the first run wins a tie
-    if (tid < 64) {
-      int best_start = 0, best_len = 1, start = 0;
-      for (int b0 = 0; b0 < nv; b0 += 64) {
-        const int q = b0 + tid;
-        const bool brk = q > 0 && q < nv && !(vals[q] - vals[q - 1] < P.tau_d);
-        uint64_t m = __ballot(brk);
-        while (m) {
-          const int pos = b0 + __ffsll((unsigned long long)m) - 1;
-          m &= m - 1;
-          const int len = pos - start;
-          if (len > best_len) { best_len = len; best_start = start; }
-          start = pos;
-        }
-      }
-      const int len = nv - start;
-      if (len > best_len) { best_len = len; best_start = start; }
-      if (tid == 0) { sm.seg_start = best_start; sm.seg_len = best_len; }
-    }
-    __syncthreads();
-    const int seg_start = sm.seg_start, seg_len = sm.seg_len;
-    r.n_used = seg_len;
-    if (seg_len < P.n_min) ok = false;
-    else d_box = median_sorted(vals + seg_start, seg_len);
-  }
-  if (tid == 0) {
-    if (!ok) {
-      r.reason = OCSR_REASON_TOO_FEW_CONSISTENT;
-    } else {
-      r.disparity = d_box;
-      if (!(d_box > P.d_eps)) {
-        r.reason = OCSR_REASON_NONPOSITIVE_DISPARITY;
-      } else {
-        r.depth = P.fb / d_box;   // Eq. 1, IEEE fp32 division
-        r.valid = 1;
-        r.reason = OCSR_REASON_OK;
-      }
-    }
-    out[kg] = r;
-  }
+  };
+  if (in_lds) rest(sm.vals);
+  else rest(ws.blk_val + base);
 }
 
 // ---------------------------------------------------------------------------------
