@@ -378,12 +378,17 @@ __device__ __forceinline__ void frame_census_tile(const MatchParamsDev& MP, cons
   make_census_tile<SX, SY>(j, sx, sy, sentinel, P);
 }
 
-// Sets, in bits, the tile bits of the frame's boxes i = t0, t0 + nt, ... (thread t0 of nt
-// threads; atomic ORs, so threads may share a map).
+// Sets, in bits, the tile bits of the frame's boxes (thread t0 of nt threads; atomic ORs,
+// so threads may share a map). With fewer boxes than threads, tpb threads share a box and
+// take every tpb-th of its tile rows: thread t0 takes boxes t0 / tpb, t0 / tpb + nt / tpb,
+// ... and rows sub, sub + tpb, ... of each.
 __device__ __forceinline__ void mark_frame_tiles(const MatchParamsDev& MP, const FrameDev& fr,
                                                  const ocsr_box* __restrict__ boxes,
                                                  uint32_t* bits, int t0, int nt) {
-  for (int i = t0; i < fr.n_boxes; i += nt) {
+  const int tpb = max(1, min(8, nt / max(fr.n_boxes, 1)));
+  const int sub = t0 % tpb, groups = nt / tpb;
+  if (t0 >= groups * tpb) return;
+  for (int i = t0 / tpb; i < fr.n_boxes; i += groups) {
     const ocsr_box b = boxes[fr.box_off + i];
     const int cx0 = max(b.x0, 0), cy0 = max(b.y0, 0);
     const int cx1 = min(b.x1, fr.W), cy1 = min(b.y1, fr.H);
@@ -408,7 +413,7 @@ __device__ __forceinline__ void mark_frame_tiles(const MatchParamsDev& MP, const
       const int ya = max(y0 + (view ? eylo : eylo - eyhi), 0);
       const int yb = min(y1 + (view ? eyhi : eyhi - eylo), tiles_y * kCensusTileY);
       if (ya >= yb) continue;
-      for (int ty = ya / kCensusTileY; ty <= (yb - 1) / kCensusTileY; ++ty) {
+      for (int ty = ya / kCensusTileY + sub; ty <= (yb - 1) / kCensusTileY; ty += tpb) {
         const int first = lbase + view * tiles + ty * tiles_x + ta;
         const int last = first + (tb - ta);
         for (int wd = first >> 5; wd <= (last >> 5); ++wd) {
